@@ -1,0 +1,427 @@
+"""Plain float64 CPU reference of the binary-TTN energy-minimisation sweep.
+
+TEST INFRASTRUCTURE (see the package docstring): slow, obviously correct,
+numpy/scipy only, no blocking or fusion beyond the definitions below.
+
+What the paper fixes, and the readings taken where it is silent
+---------------------------------------------------------------
+* Ansatz (Sec. II.C, Eqs. (constraint), (normalization)): a binary tree over
+  L = 2**n effective sites.  Layer tau = 1..n-1 holds one isometry w_tau that
+  is shared by every position (translation invariance, Sec. III), shape
+  (a, b, b) with a = chi_tau, b = chi_{tau-1}, and rows orthonormal:
+  sum_{l,r} w[a;l,r] w[a';l,r] = delta.  The top tensor v (chi_{n-1} x
+  chi_{n-1}) joins the two sites of level n-1 and has unit Frobenius norm.
+  Reading: chi_0 = d, chi_tau = min(chi_{tau-1}**2, chi) (a bond cannot
+  exceed the Hilbert-space dimension of the block below it).
+* Hamiltonian (Eqs. (H1D), (1)-(5)): an effective chain
+  H = sum_j [h1_j + sum_k A_{k,j} B_{k,j+1}], periodic; the product form of
+  the bond term is the "bond index of dimension L_y" of Fig. 2(b).
+* Environment (Sec. III.A, Figs. 2(b), 3): the sum over Hamiltonian terms of
+  the network with one copy of w removed, w w^T pairs outside the causal cone
+  removed by the isometric constraint, evaluated as a sequence of matrix
+  products of cost at most O(chi**4) (Fig. 4(b)).  Reading: for a layer whose
+  copies are all equal, Env = (1 / (2 L_tau)) dE/dw summed over all copies at
+  the current tensors, with the one-site reduced density matrices averaged
+  over positions.
+* Update (Sec. III.B, Fig. 4(c-d), Fig. 10(a)): SVD of the flattened
+  environment and w = V U^dagger.  Reading: with the Hamiltonian shifted so
+  that every bond term is negative semidefinite (shift c = largest eigenvalue
+  of the bond term), w = -U V^T for Env = U S V^T written with w's index
+  shape (a x b*b); this is the same polar factor and it minimises the energy
+  linearised in w.
+* Top tensor: "updated similarly" (Sec. III.B).  Reading: v is the lowest
+  eigenvector of the top Hamiltonian (the fixed point of repeating the update
+  on v), sign fixed so that its entry of largest magnitude is positive.
+* Sweep (Sec. IV, Sec. V): one update of every isometry; bottom-up
+  (tau = 1..n-1), then v.  Convergence: the energy per site changes by less
+  than 1e-10 over a sweep (Sec. IV).
+
+Notation
+--------
+Operators are one-site matrices O[x, x'] (ket index first); the pairing is
+<X, Y> = sum X[x, x'] Y[x, x'].  Building blocks, each one matrix product:
+  apply_r(O, w)[a;l,r] = sum_r' O[r,r'] w[a;l,r']
+  apply_l(O, w)[a;l,r] = sum_l' O[l,l'] w[a;l',r]
+  left_mul(X, P)[a;l,r] = sum_a' X[a,a'] P[a';l,r]
+  close(P, Q)[a,a']   = sum_{l,r} P[a;l,r] Q[a';l,r]
+  close_l(P, Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r]
+  close_r(P, Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']
+
+Pins (tests/test_oracle_*.py): full-chi equality with exact diagonalisation
+(ascend + top + shift), brute-force state-vector energies and one-site RDMs
+(ascend, descend), brute-force bond energies and level independence
+(dressed chains), finite differences of a brute-force quartic energy and the
+Euler identity (environment), the polar characterisation (update), residual
+and dense eigensolver agreement (top), closed-form shifts, free-fermion and
+Bethe energies (whole sweep).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse.linalg as spla
+
+
+# --------------------------------------------------------------------------
+# shapes and the shift
+# --------------------------------------------------------------------------
+def num_levels(L: int) -> int:
+    """n with L = 2**n; the tree has levels 0..n-1 and isometry layers 1..n-1."""
+    n = int(round(math.log2(L)))
+    if 2 ** n != L or n < 2:
+        raise ValueError("L must be a power of two >= 4")
+    return n
+
+
+def bond_dims(L: int, d: int, chi: int):
+    """[chi_0, ..., chi_{n-1}] with chi_0 = d, chi_tau = min(chi_{tau-1}^2, chi)."""
+    n = num_levels(L)
+    dims = [d]
+    for _ in range(1, n):
+        dims.append(min(dims[-1] ** 2, chi))
+    return dims
+
+
+def layer_shapes(L: int, d: int, chi: int):
+    """[(a, b)] for layers tau = 1..n-1 (a = chi_tau, b = chi_{tau-1})."""
+    dims = bond_dims(L, d, chi)
+    return [(dims[t], dims[t - 1]) for t in range(1, len(dims))]
+
+
+def bond_term(h1, A, B):
+    """Two-site term b = 1/2 (h1 x I + I x h1) + sum_k A_k x B_k (d^2 x d^2).
+
+    The one-site term is split evenly between the two bonds that touch a
+    site, as in Eqs. (2)-(5) of the paper (factor 1/2 against double
+    counting in Eq. (H1D)).
+    """
+    d = h1.shape[0]
+    I = np.eye(d)
+    b = 0.5 * (np.kron(h1, I) + np.kron(I, h1))
+    for a_k, b_k in zip(A, B):
+        b = b + np.kron(a_k, b_k)
+    return b
+
+
+def shift_constant(h1, A, B) -> float:
+    """c = largest eigenvalue of the bond term, so that every b - c <= 0."""
+    return float(np.linalg.eigvalsh(bond_term(h1, A, B))[-1])
+
+
+# --------------------------------------------------------------------------
+# building blocks (Fig. 4(b): each is one matrix product after flattening)
+# --------------------------------------------------------------------------
+def apply_r(O, w):
+    return np.einsum("xy,aly->alx", O, w, optimize=True)
+
+
+def apply_l(O, w):
+    return np.einsum("xy,ayr->axr", O, w, optimize=True)
+
+
+def left_mul(X, P):
+    return np.einsum("ab,blr->alr", X, P, optimize=True)
+
+
+def close(P, Q):
+    return np.einsum("alr,blr->ab", P, Q, optimize=True)
+
+
+def close_l(P, Q):
+    return np.einsum("alr,amr->lm", P, Q, optimize=True)
+
+
+def close_r(P, Q):
+    return np.einsum("alr,als->rs", P, Q, optimize=True)
+
+
+def pair(X, Y) -> float:
+    return float(np.sum(X * Y))
+
+
+# --------------------------------------------------------------------------
+# ascending the Hamiltonian (Fig. 3: w w^T pairs outside the cone drop out)
+# --------------------------------------------------------------------------
+def s_apply(w, h, A, B):
+    """(h x I + I x h + sum_k A_k x B_k) applied to the two input legs of w.
+
+    The left child carries A_k and the right child B_k of the internal bond
+    (site j+1 of A_{k,j} B_{k,j+1} is the right one).
+    """
+    out = apply_l(h, w) + apply_r(h, w)
+    for a_k, b_k in zip(A, B):
+        out = out + apply_l(a_k, apply_r(b_k, w))
+    return out
+
+
+def ascend(w, h, A, B):
+    """Level-tau operators from level tau-1 through the layer isometry w.
+
+    One-site term: internal bond plus both one-site terms, h' = w S w^T.
+    Product terms across the boundary between two parents: A acts on the
+    right child of parent j, B on the left child of parent j+1, so
+    A'_k = w (I x A_k) w^T and B'_k = w (B_k x I) w^T.
+    """
+    h_new = close(w, s_apply(w, h, A, B))
+    A_new = [close(w, apply_r(a_k, w)) for a_k in A]
+    B_new = [close(w, apply_l(b_k, w)) for b_k in B]
+    return h_new, A_new, B_new
+
+
+def ascend_all(ws, h0, A0, B0):
+    """Operators at every level 0..n-1 (ws[tau-1] is the isometry of layer tau)."""
+    hs, As, Bs = [h0], [list(A0)], [list(B0)]
+    for w in ws:
+        h, A, B = ascend(w, hs[-1], As[-1], Bs[-1])
+        hs.append(h)
+        As.append(A)
+        Bs.append(B)
+    return hs, As, Bs
+
+
+# --------------------------------------------------------------------------
+# the top tensor
+# --------------------------------------------------------------------------
+def top_matvec(v, h, A, B):
+    """H_top v for the two sites of level n-1 with both periodic bonds.
+
+    Sites: v[alpha, beta], alpha the left half.  H_top = h x I + I x h
+    + sum_k (A_k x B_k + B_k x A_k).
+    """
+    out = h @ v + v @ h.T
+    for a_k, b_k in zip(A, B):
+        out = out + a_k @ v @ b_k.T + b_k @ v @ a_k.T
+    return out
+
+
+def top_matrix(h, A, B):
+    """Dense H_top acting on v flattened row-major (only for small chi)."""
+    x = h.shape[0]
+    I = np.eye(x)
+    H = np.kron(h, I) + np.kron(I, h)
+    for a_k, b_k in zip(A, B):
+        H = H + np.kron(a_k, b_k) + np.kron(b_k, a_k)
+    return H
+
+
+def fix_sign(vec):
+    """Sign such that the entry of largest magnitude is positive (first on ties)."""
+    flat = vec.reshape(-1)
+    i = int(np.argmax(np.abs(flat)))
+    return vec if flat[i] >= 0 else -vec
+
+
+def top_eigen(h, A, B, v0=None, dense_limit=1024, tol=1e-14):
+    """Lowest eigenpair (lambda, v) of H_top, v of unit norm and sign-fixed."""
+    x = h.shape[0]
+    dim = x * x
+    if dim <= dense_limit:
+        evals, evecs = np.linalg.eigh(top_matrix(h, A, B))
+        lam = float(evals[0])
+        v = evecs[:, 0].reshape(x, x)
+    else:
+        op = spla.LinearOperator(
+            (dim, dim), dtype=np.float64,
+            matvec=lambda y: top_matvec(y.reshape(x, x), h, A, B).reshape(-1))
+        start = None if v0 is None else v0.reshape(-1)
+        evals, evecs = spla.eigsh(op, k=1, which="SA", v0=start, tol=tol,
+                                  ncv=min(dim, 64), maxiter=100000)
+        lam = float(evals[0])
+        v = evecs[:, 0].reshape(x, x)
+    v = v / np.linalg.norm(v)
+    return lam, fix_sign(v)
+
+
+# --------------------------------------------------------------------------
+# descending reduced density matrices
+# --------------------------------------------------------------------------
+def rho_top(v):
+    """Position-averaged one-site RDM of level n-1: 1/2 (v v^T + v^T v)."""
+    return 0.5 * (v @ v.T + v.T @ v)
+
+
+def descend_rho(w, rho):
+    """Position-averaged one-site RDM one level down through w.
+
+    Each site of the lower level is either the left or the right child of
+    exactly one parent, hence the average of the two partial traces.
+    """
+    P = left_mul(rho, w)
+    return 0.5 * (close_l(w, P) + close_r(w, P))
+
+
+def descend_rho_all(ws, v):
+    """rhos[tau] for tau = 0..n-1 from the top down."""
+    n = len(ws) + 1
+    rhos = [None] * n
+    rhos[n - 1] = rho_top(v)
+    for tau in range(n - 1, 0, -1):
+        rhos[tau - 1] = descend_rho(ws[tau - 1], rhos[tau])
+    return rhos
+
+
+def dressed_top(v, A_top, B_top):
+    """Two-site information at level n-1 for every product term k.
+
+    Rbar_k is the A_k-dressed RDM seen from the B site, so that the bond
+    energy sum_j <A_{k,j} B_{k,j+1}> = L_tau <Rbar_k, B_k>; Lbar_k is the
+    B_k-dressed RDM seen from the A site (<Lbar_k, A_k> gives the same sum).
+    The two bonds of the top pair are (1,2) and (2,1).
+    """
+    R = [0.5 * (v.T @ a @ v + v @ a @ v.T) for a in A_top]
+    Lb = [0.5 * (v @ b @ v.T + v.T @ b @ v) for b in B_top]
+    return R, Lb
+
+
+def descend_dressed(w, rho, R, Lb, A_low, B_low):
+    """Rbar, Lbar one level down through w (level sigma -> sigma-1).
+
+    Half of the bonds of the lower level lie inside a parent (A on the left
+    child, B on the right child, weighted by rho of the parent level); the
+    other half cross from the right child of one parent to the left child of
+    the next (carried by Rbar/Lbar of the parent level).
+    """
+    R_new, L_new = [], []
+    for a_k, b_k, r_k, l_k in zip(A_low, B_low, R, Lb):
+        inside_R = close_r(w, left_mul(rho, apply_l(a_k, w)))
+        cross_R = close_l(w, left_mul(r_k, w))
+        R_new.append(0.5 * (inside_R + cross_R))
+        inside_L = close_l(w, left_mul(rho, apply_r(b_k, w)))
+        cross_L = close_r(w, left_mul(l_k, w))
+        L_new.append(0.5 * (inside_L + cross_L))
+    return R_new, L_new
+
+
+def dressed_chain(ws, v, rhos, tau, A_low, B_low):
+    """Rbar^(tau), Lbar^(tau) for the current tensors.
+
+    A_low, B_low are the product terms at level tau-1 (ascended with the
+    current layers below).  They are carried up through layers tau..n-1
+    with the current isometries, the top dressing is formed from v and the
+    result is descended back to level tau.
+    """
+    n = len(ws) + 1
+    At = {tau - 1: list(A_low)}
+    Bt = {tau - 1: list(B_low)}
+    for sigma in range(tau, n):
+        w = ws[sigma - 1]
+        At[sigma] = [close(w, apply_r(a, w)) for a in At[sigma - 1]]
+        Bt[sigma] = [close(w, apply_l(b, w)) for b in Bt[sigma - 1]]
+    R, Lb = dressed_top(v, At[n - 1], Bt[n - 1])
+    for sigma in range(n - 1, tau, -1):
+        R, Lb = descend_dressed(ws[sigma - 1], rhos[sigma], R, Lb,
+                                At[sigma - 1], Bt[sigma - 1])
+    return R, Lb
+
+
+# --------------------------------------------------------------------------
+# environment, update, energy
+# --------------------------------------------------------------------------
+def environment(w, h, A, B, rho, R, Lb):
+    """Env of the layer isometry w (same index shape as w).
+
+    Env = rho o (S w) + sum_k Rbar_k o (B_k .l w) + sum_k Lbar_k o (A_k .r w)
+    with h, A, B at the level below w and rho, Rbar, Lbar at w's level.
+    """
+    E = left_mul(rho, s_apply(w, h, A, B))
+    for a_k, b_k, r_k, l_k in zip(A, B, R, Lb):
+        E = E + left_mul(r_k, apply_l(b_k, w)) + left_mul(l_k, apply_r(a_k, w))
+    return E
+
+
+def polar_update(env):
+    """w = -U V^T from the thin SVD of Env (a x b*b), LAPACK gesdd."""
+    a = env.shape[0]
+    U, s, Vt = np.linalg.svd(env.reshape(a, -1), full_matrices=False)
+    return -(U @ Vt).reshape(env.shape), s
+
+
+def level_energy(L, tau, h, B, rho, R, c):
+    """E = L_tau [<rho, h> + sum_k <Rbar_k, B_k>] + c L at level tau."""
+    L_tau = L >> tau
+    e = pair(rho, h) + sum(pair(r, b) for r, b in zip(R, B))
+    return L_tau * e + c * L
+
+
+def ortho_error(w):
+    W = w.reshape(w.shape[0], -1)
+    return float(np.linalg.norm(W @ W.T - np.eye(W.shape[0])))
+
+
+# --------------------------------------------------------------------------
+# the sweep
+# --------------------------------------------------------------------------
+class TTNRef:
+    """State of a uniform binary TTN and the bottom-up sweep of Sec. III."""
+
+    def __init__(self, L, chi, h1, A, B, ly=1, ws=None, shift=None):
+        self.L = int(L)
+        self.n = num_levels(L)
+        self.h1 = np.asarray(h1, dtype=np.float64)
+        self.A0 = [np.asarray(a, dtype=np.float64) for a in A]
+        self.B0 = [np.asarray(b, dtype=np.float64) for b in B]
+        self.d = self.h1.shape[0]
+        self.D = len(self.A0)
+        self.ly = ly
+        self.dims = bond_dims(L, self.d, chi)
+        self.c = shift_constant(self.h1, self.A0, self.B0) if shift is None else float(shift)
+        self.h0 = self.h1 - self.c * np.eye(self.d)
+        if ws is None:
+            raise ValueError("initial isometries are an input (see inputs.random_isometries)")
+        self.ws = [np.array(w, dtype=np.float64) for w in ws]
+        for t, w in enumerate(self.ws, start=1):
+            if w.shape != (self.dims[t], self.dims[t - 1], self.dims[t - 1]):
+                raise ValueError(f"layer {t}: shape {w.shape}")
+        self.v = None
+        self.lam = None
+        self.history = []
+        self.diag = []
+
+    # energies -------------------------------------------------------------
+    def energy_total(self):
+        return self.lam + self.c * self.L
+
+    def energy_per_site(self):
+        return self.energy_total() / (self.L * self.ly)
+
+    # initial state (ascend everything, solve the top) -----------------------
+    def initialise(self):
+        self.hs, self.As, self.Bs = ascend_all(self.ws, self.h0, self.A0, self.B0)
+        top = self.n - 1
+        self.lam, self.v = top_eigen(self.hs[top], self.As[top], self.Bs[top])
+        self.history.append(self.energy_per_site())
+        return self.energy_per_site()
+
+    def sweep(self):
+        """One bottom-up sweep; returns the energy per site after it."""
+        n = self.n
+        rhos = descend_rho_all(self.ws, self.v)
+        info = {"ortho": [], "sigma_ratio": []}
+        for tau in range(1, n):
+            w = self.ws[tau - 1]
+            h, A, B = self.hs[tau - 1], self.As[tau - 1], self.Bs[tau - 1]
+            R, Lb = dressed_chain(self.ws, self.v, rhos, tau, A, B)
+            env = environment(w, h, A, B, rhos[tau], R, Lb)
+            w_new, s = polar_update(env)
+            self.ws[tau - 1] = w_new
+            info["ortho"].append(ortho_error(w_new))
+            info["sigma_ratio"].append(float(s[-1] / s[0]) if s[0] > 0 else 0.0)
+            self.hs[tau], self.As[tau], self.Bs[tau] = ascend(w_new, h, A, B)
+        top = n - 1
+        self.lam, self.v = top_eigen(self.hs[top], self.As[top], self.Bs[top], v0=self.v)
+        self.history.append(self.energy_per_site())
+        self.diag.append(info)
+        return self.energy_per_site()
+
+    def run(self, sweeps, tol=None):
+        """Sweep up to ``sweeps`` times; with ``tol`` stop when |de| < tol."""
+        if self.v is None:
+            self.initialise()
+        for _ in range(sweeps):
+            before = self.history[-1]
+            after = self.sweep()
+            if tol is not None and abs(after - before) < tol:
+                break
+        return list(self.history)

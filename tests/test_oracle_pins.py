@@ -1,0 +1,290 @@
+"""Pins of the CPU reference (oracle/) against mathematics other than itself.
+
+Each test names the part of the sweep it pins and the kind of pin: exact
+diagonalisation of the physical Hamiltonian, closed forms, brute-force
+state vectors on tiny systems, finite differences, invariants.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import physics_ref as P
+from oracle import ttn_ref as T
+from paper_1905_01331_amd import inputs as I
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ed_energies.json")))
+
+
+def make(model, L, chi, seed=0):
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), seed)
+    return T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
+
+
+# ---------------------------------------------------------------- shift ----
+@pytest.mark.parametrize("h", [0.5, 1.0, 2.9])
+def test_shift_tfim_closed_form(h):
+    # bond term -ZZ - h/2 (X I + I X): spectrum {-1, 1, +-sqrt(1+h^2)}
+    m = I.tfim_chain(h)
+    assert T.shift_constant(m.h1, m.A, m.B) == pytest.approx(np.sqrt(1 + h * h), abs=1e-14)
+
+
+def test_shift_xxx_closed_form():
+    # S.S has triplet eigenvalue 1/4 and singlet -3/4
+    m = I.xxx_chain()
+    assert T.shift_constant(m.h1, m.A, m.B) == pytest.approx(0.25, abs=1e-15)
+
+
+# ------------------------------------------------- closed forms and ED ----
+@pytest.mark.parametrize("L", [6, 8, 10])
+@pytest.mark.parametrize("h", [0.5, 1.0, 1.5])
+def test_free_fermion_closed_form_equals_ed(L, h):
+    e_ed = P.ground_energy(P.tfim_chain_hamiltonian(L, h))
+    assert P.tfim_free_fermion_energy(L, h) == pytest.approx(e_ed, abs=1e-11)
+
+
+def test_critical_closed_form():
+    for L in (8, 16, 1024):
+        assert P.tfim_free_fermion_energy(L, 1.0) == pytest.approx(P.tfim_critical_energy(L), rel=1e-13)
+    assert P.tfim_critical_energy(1024) / 1024 == pytest.approx(-1.273240044078004, abs=1e-14)
+
+
+def test_golden_ed_values():
+    assert GOLD["tfim_chain_L16_h1"] == pytest.approx(P.tfim_critical_energy(16), abs=1e-10)
+    # Heisenberg rings (standard exact-diagonalisation tables)
+    assert GOLD["xxx_chain_L8"] == pytest.approx(-3.651093408937, abs=1e-11)
+    assert GOLD["xxx_chain_L16"] == pytest.approx(-7.142296360617, abs=1e-11)
+
+
+# ------------------------------------------- full chi == exact (ascend+top) ----
+@pytest.mark.parametrize("name,model,L,chi,key", [
+    ("tfim8", I.tfim_chain(1.0), 8, 16, "tfim_chain_L8_h1"),
+    ("xxx8", I.xxx_chain(), 8, 16, "xxx_chain_L8"),
+    ("torus4x3", I.torus_tfim_column(3, 3.0), 4, 64, "torus_tfim_4x3_h3"),
+])
+def test_full_chi_equals_ed(name, model, L, chi, key):
+    r = make(model, L, chi, seed=7)
+    r.initialise()
+    assert r.energy_total() == pytest.approx(GOLD[key], abs=1e-10 * abs(GOLD[key]))
+
+
+@pytest.mark.slow
+def test_full_chi_equals_ed_large():
+    r = make(I.tfim_chain(1.0), 16, 256, seed=1)
+    r.initialise()
+    assert r.energy_total() == pytest.approx(GOLD["tfim_chain_L16_h1"], rel=1e-10)
+    r = make(I.torus_tfim_column(4, 3.0), 4, 256, seed=1)
+    r.initialise()
+    assert r.energy_total() == pytest.approx(GOLD["torus_tfim_4x4_h3"], rel=1e-10)
+
+
+# ------------------------------------------- brute force at truncated chi ----
+def _physical(model_name, L):
+    if model_name == "tfim":
+        return P.tfim_chain_hamiltonian(L, 0.8)
+    return P.heisenberg_chain_hamiltonian(L)
+
+
+@pytest.mark.parametrize("model_name", ["tfim", "xxx"])
+def test_ascend_energy_bruteforce(model_name):
+    model = I.tfim_chain(0.8) if model_name == "tfim" else I.xxx_chain()
+    L, chi = 16, 6
+    r = make(model, L, chi, seed=3)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 11)
+    top = r.n - 1
+    e_ttn = T.pair(v, T.top_matvec(v, r.hs[top], r.As[top], r.Bs[top])) + r.c * L
+    psi = P.full_state(r.ws, v)
+    e_bf = float(psi @ (_physical(model_name, L) @ psi))
+    assert np.linalg.norm(psi) == pytest.approx(1.0, abs=1e-13)
+    assert e_ttn == pytest.approx(e_bf, abs=1e-12 * max(1, abs(e_bf)))
+
+
+def test_ascend_energy_bruteforce_torus():
+    model = I.torus_tfim_column(3, 2.0)
+    r = make(model, 4, 12, seed=5)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 2)
+    top = r.n - 1
+    e_ttn = T.pair(v, T.top_matvec(v, r.hs[top], r.As[top], r.Bs[top])) + r.c * 4
+    psi = P.full_state(r.ws, v)
+    e_bf = float(psi @ (P.torus_tfim_hamiltonian(4, 3, 2.0) @ psi))
+    assert e_ttn == pytest.approx(e_bf, abs=1e-11)
+
+
+def test_ascend_identity_and_adjointness():
+    rng = np.random.default_rng(0)
+    w = I.random_isometries([(5, 3)], 1)[0]
+    # identity ascends to identity (isometric constraint, Fig. 4(a))
+    h, A, B = T.ascend(w, np.eye(3), [], [])
+    assert np.allclose(h, 2 * np.eye(5), atol=1e-14)  # h x I + I x h with h = I
+    O = rng.standard_normal((3, 3))
+    X = rng.standard_normal((5, 5))
+    # <X, C(w, O .r w)> = <C_R(w, X o w), O>  and the l-version
+    lhs = T.pair(X, T.close(w, T.apply_r(O, w)))
+    rhs = T.pair(T.close_r(w, T.left_mul(X, w)), O)
+    assert lhs == pytest.approx(rhs, abs=1e-13)
+    lhs = T.pair(X, T.close(w, T.apply_l(O, w)))
+    rhs = T.pair(T.close_l(w, T.left_mul(X, w)), O)
+    assert lhs == pytest.approx(rhs, abs=1e-13)
+
+
+# ------------------------------------------------------------- descend ----
+@pytest.mark.parametrize("model", [I.tfim_chain(0.8), I.xxx_chain()])
+def test_rho_descend_bruteforce(model):
+    L, chi = 16, 6
+    r = make(model, L, chi, seed=4)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 3)
+    rhos = T.descend_rho_all(r.ws, v)
+    for tau in range(r.n):
+        bf = P.one_site_rdm_average(P.level_state(r.ws, v, tau))
+        assert np.abs(rhos[tau] - bf).max() < 1e-14
+        assert np.trace(rhos[tau]) == pytest.approx(1.0, abs=1e-14)
+        assert np.linalg.eigvalsh(rhos[tau]).min() > -1e-14
+
+
+# ------------------------------------------------------ dressed chains ----
+@pytest.mark.parametrize("model", [I.tfim_chain(0.8), I.xxx_chain(), I.torus_tfim_column(3, 2.0)])
+def test_dressed_chain_bruteforce_and_level_independence(model):
+    L = 16 if model.d == 2 else 8
+    chi = 6 if model.d == 2 else 10
+    r = make(model, L, chi, seed=2)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 9)
+    rhos = T.descend_rho_all(r.ws, v)
+    energies = []
+    for tau in range(1, r.n):
+        R, Lb = T.dressed_chain(r.ws, v, rhos, tau, r.As[tau - 1], r.Bs[tau - 1])
+        psi = P.level_state(r.ws, v, tau)
+        L_tau = L >> tau
+        for k in range(model.D):
+            bf = P.bond_expectation_sum(psi, r.As[tau][k], r.Bs[tau][k])
+            assert L_tau * T.pair(R[k], r.Bs[tau][k]) == pytest.approx(bf, abs=1e-12)
+            assert L_tau * T.pair(Lb[k], r.As[tau][k]) == pytest.approx(bf, abs=1e-12)
+        energies.append(T.level_energy(L, tau, r.hs[tau], r.Bs[tau], rhos[tau], R, r.c))
+    top = r.n - 1
+    e_top = T.pair(v, T.top_matvec(v, r.hs[top], r.As[top], r.Bs[top])) + r.c * L
+    assert np.allclose(energies, e_top, atol=1e-12 * abs(e_top) + 1e-12)
+
+
+# ---------------------------------------------------------- environment ----
+def _quartic_energy(w, psi_tau, h, A, B):
+    """Energy of the level-tau state with layer-tau operators built from w by
+    explicit Kronecker products (no use of the reference building blocks)."""
+    a, b, _ = w.shape
+    W = w.reshape(a, b * b)
+    Ib = np.eye(b)
+    S = np.kron(h, Ib) + np.kron(Ib, h) + sum((np.kron(x, y) for x, y in zip(A, B)), np.zeros((b * b, b * b)))
+    hn = W @ S @ W.T
+    An = [W @ np.kron(Ib, x) @ W.T for x in A]
+    Bn = [W @ np.kron(y, Ib) @ W.T for y in B]
+    return P.chain_operator_expectation(psi_tau, hn, An, Bn)
+
+
+@pytest.mark.parametrize("model", [I.tfim_chain(0.7), I.xxx_chain()])
+def test_environment_finite_differences_and_euler(model):
+    L, chi = 16, 6
+    r = make(model, L, chi, seed=3)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 5)
+    rhos = T.descend_rho_all(r.ws, v)
+    rng = np.random.default_rng(0)
+    for tau in range(1, r.n):
+        w = r.ws[tau - 1]
+        h, A, B = r.hs[tau - 1], r.As[tau - 1], r.Bs[tau - 1]
+        R, Lb = T.dressed_chain(r.ws, v, rhos, tau, A, B)
+        env = T.environment(w, h, A, B, rhos[tau], R, Lb)
+        psi_tau = P.level_state(r.ws, v, tau)
+        L_tau = L >> tau
+        Dw = rng.standard_normal(w.shape)
+        eps = 1e-4
+        fd = (_quartic_energy(w + eps * Dw, psi_tau, h, A, B)
+              - _quartic_energy(w - eps * Dw, psi_tau, h, A, B)) / (2 * eps)
+        assert 2 * L_tau * T.pair(env, Dw) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+        # Euler identity for a quadratic-plus-quartic function of w
+        e_shift = _quartic_energy(w, psi_tau, h, A, B)
+        e_bond = L_tau * sum(T.pair(x, y) for x, y in zip(R, r.Bs[tau]))
+        assert L_tau * T.pair(w, env) == pytest.approx(e_shift + e_bond, abs=1e-11)
+
+
+# --------------------------------------------------------------- update ----
+def test_polar_update_characterisation():
+    rng = np.random.default_rng(3)
+    env = rng.standard_normal((6, 4, 4))
+    w, s = T.polar_update(env)
+    W = w.reshape(6, -1)
+    E = env.reshape(6, -1)
+    assert np.abs(W @ W.T - np.eye(6)).max() < 1e-14
+    M = -E @ W.T  # must be symmetric positive definite for the polar factor
+    assert np.abs(M - M.T).max() < 1e-13
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    assert -T.pair(w, env) == pytest.approx(float(np.sum(s)), rel=1e-13)
+    # it maximises <w, -Env> among isometries
+    for seed in range(20):
+        x = I.random_isometries([(6, 4)], 100 + seed)[0]
+        assert -T.pair(x, env) <= -T.pair(w, env) + 1e-12
+
+
+def test_polar_zero_hamiltonian_fixed_point():
+    # h1 = 0, no product terms, explicit shift c > 0: H - cL = -cL I.  The
+    # environment is -2c rho o w and the update returns w unchanged when rho
+    # has full rank.
+    d, L, chi = 2, 16, 4
+    ws = I.random_isometries(T.layer_shapes(L, d, chi), 8)
+    r = T.TTNRef(L, chi, np.zeros((d, d)), [], [], ws=ws, shift=0.5)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 1)
+    rhos = T.descend_rho_all(r.ws, v)
+    for tau in range(1, r.n):
+        w = r.ws[tau - 1]
+        env = T.environment(w, r.hs[tau - 1], [], [], rhos[tau], [], [])
+        w_new, s = T.polar_update(env)
+        assert np.abs(w_new - w).max() < 1e-12
+
+
+# ------------------------------------------------------------------ top ----
+def test_top_eigen_residual_and_dense_agreement():
+    r = make(I.xxx_chain(), 32, 40, seed=1)
+    r.initialise()
+    top = r.n - 1
+    h, A, B = r.hs[top], r.As[top], r.Bs[top]
+    lam_it, v_it = T.top_eigen(h, A, B, dense_limit=0)
+    lam_dn, v_dn = T.top_eigen(h, A, B, dense_limit=10 ** 9)
+    res = T.top_matvec(v_it, h, A, B) - lam_it * v_it
+    assert np.linalg.norm(res) < 1e-10 * abs(lam_it)
+    assert lam_it == pytest.approx(lam_dn, rel=1e-13)
+    assert abs(float(np.sum(v_it * v_dn))) == pytest.approx(1.0, abs=1e-10)
+
+
+# ---------------------------------------------------------------- sweep ----
+def test_sweep_monotone_and_variational_cfg1():
+    # L = 16 TFIM at criticality, chi = 8, 30 sweeps
+    r = make(I.tfim_chain(1.0), 16, 8, seed=0)
+    hist = r.run(30)
+    e_ed = GOLD["tfim_chain_L16_h1"] / 16
+    assert all(b <= a + 1e-13 * abs(a) for a, b in zip(hist, hist[1:]))
+    assert hist[-1] >= e_ed - 1e-12
+    assert hist[-1] - e_ed < 5e-3
+    for info in r.diag:
+        assert max(info["ortho"]) < 1e-13
+
+
+def test_sweep_free_fermion_bound():
+    L = 64
+    r = make(I.tfim_chain(1.0), L, 12, seed=0)
+    hist = r.run(12)
+    e0 = P.tfim_free_fermion_energy(L, 1.0) / L
+    assert hist[-1] >= e0 - 1e-12
+    assert all(b <= a + 1e-12 for a, b in zip(hist, hist[1:]))
+
+
+def test_sweep_xxx_bethe_bound():
+    r = make(I.xxx_chain(), 32, 12, seed=0)
+    hist = r.run(10)
+    e_ed16 = GOLD["xxx_chain_L16"] / 16
+    # finite periodic rings lie below the Bethe density; the TTN lies above the ring ground state
+    assert hist[-1] > P.BETHE_XXX_ENERGY_DENSITY - 0.01
+    assert hist[-1] > e_ed16 - 0.01
+    assert all(b <= a + 1e-12 for a, b in zip(hist, hist[1:]))
