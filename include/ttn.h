@@ -1,0 +1,199 @@
+/*
+ * ttn.h - C ABI of the MI355X (gfx950) binary tree tensor network sweep.
+ *
+ * The library runs the energy-minimisation sweep of a uniform binary tree
+ * tensor network (TTN) for a periodic effective chain
+ *     H = sum_j [ h1_j + sum_k A_{k,j} B_{k,j+1} ],
+ * following Milsted, Ganahl, Leichenauer, Hidary, Vidal, "TensorNetwork on
+ * TensorFlow: A Spin Chain Application Using Tree Tensor Networks"
+ * (arXiv:1905.01331): the ansatz of Sec. II.C (isometries w of
+ * Eq. (constraint), one per layer by translation invariance, Sec. III; top
+ * tensor v of Eq. (normalization)), the environment of Sec. III.A
+ * (Figs. 2(b), 3, 4(b)), the SVD/polar update of Sec. III.B (Fig. 4(c-d),
+ * Fig. 10(a)) and the sweep of Secs. IV-V.
+ *
+ * Levels tau = 0..n-1 (L = 2^n effective sites, level tau has L/2^tau
+ * sites, level n-1 has 2).  Bond dimensions chi_0 = d,
+ * chi_tau = min(chi_{tau-1}^2, chi).  Layer tau = 1..n-1 holds one isometry
+ * w_tau[a; l, r] of shape (chi_tau, chi_{tau-1}, chi_{tau-1}), row-major with
+ * r fastest, rows orthonormal.  The top tensor v is chi_{n-1} x chi_{n-1},
+ * row-major, unit Frobenius norm.  All matrices are real, row-major, ket
+ * index first.
+ *
+ * Memory and streams.  The caller allocates ONE device workspace of at least
+ * ttn_workspace_bytes() bytes and passes it to ttn_init(); the library never
+ * allocates device memory itself and lays out all tensors inside it.  Host
+ * arrays passed in are copied before the call returns.  Every stage call is
+ * enqueued asynchronously on the caller's HIP stream (hipStream_t passed as
+ * void*); ttn_energy, ttn_get_tensor, ttn_get_operator and ttn_stats
+ * synchronise that stream.
+ *
+ * Errors.  Every call returns a ttn_status: 0 = success, < 0 = error (the
+ * handle is left unchanged and ttn_last_error() describes it), > 0 = a
+ * warning (the call completed).  No exception crosses the ABI.  A handle is
+ * not thread-safe; distinct handles on distinct streams are independent.
+ */
+#ifndef TTN_H
+#define TTN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ttn_ctx* ttn_handle;
+typedef int ttn_status;
+
+enum {
+  TTN_OK = 0,
+  TTN_WRANK = 1,        /* an environment was numerically rank deficient
+                           (sigma_min/sigma_max < 1e-14): the polar factor is
+                           not unique there and was completed deterministically */
+  TTN_WNOCONV = 2,      /* the top eigensolver stopped at its iteration budget
+                           above its residual target                          */
+  TTN_EINVAL = -1,      /* invalid argument or configuration                  */
+  TTN_ENOMEM = -2,      /* workspace smaller than ttn_workspace_bytes()        */
+  TTN_EHIP = -3,        /* a HIP runtime call failed                          */
+  TTN_ENONFINITE = -4,  /* NaN or Inf in a host input                         */
+  TTN_ENOCONV = -5,     /* reserved                                            */
+  TTN_EORTHO = -6,      /* an updated isometry failed ||W W^T - I||_F <= 1e-10 */
+  TTN_ESTATE = -7       /* stage called out of the order of the sweep         */
+};
+
+/* Arithmetic of the bulk contractions (ascend, descend, environment).  The
+ * polar update, the orthonormality check, the top eigensolver and the
+ * energy always run in float64. */
+enum {
+  TTN_FP64 = 0,        /* float64 everywhere                                  */
+  TTN_FP32 = 1,        /* float32 operands, float32 MFMA accumulation          */
+  TTN_SPLIT_BF16 = 2   /* each float32 operand x = hi + lo with bf16 hi, lo;
+                          hi*hi + hi*lo + lo*hi on bf16 MFMA, float32 accumulate */
+};
+
+enum { TTN_DESCEND_RHO = 0, TTN_DESCEND_DRESSED = 1 };
+#define TTN_TOP (-1)
+
+/* Kinds for ttn_get_operator (level-tau one-site matrices, chi_tau^2). */
+enum {
+  TTN_OP_H = 0,     /* one-site term h^(tau), shift included (level 0: h1 - c I) */
+  TTN_OP_A = 1,     /* product term A_k^(tau)                                  */
+  TTN_OP_B = 2,     /* product term B_k^(tau)                                  */
+  TTN_OP_RHO = 3,   /* position-averaged one-site RDM rho^(tau) (descend cache) */
+  TTN_OP_RBAR = 4,  /* A_k-dressed two-site RDM seen from the B site, level tau  */
+  TTN_OP_LBAR = 5,  /* B_k-dressed two-site RDM seen from the A site, level tau  */
+  TTN_OP_ENV = 6    /* environment of w_tau (chi_tau x chi_{tau-1}^2), last ttn_env */
+};
+
+typedef struct ttn_config {
+  int L;              /* effective sites: power of two, >= 4                  */
+  int d;              /* effective site dimension (2, or 2^L_y for a torus)   */
+  int chi;            /* bond-dimension cap, >= 1                             */
+  int D;              /* number of product terms, >= 0                        */
+  const double* h1;   /* host, d*d, symmetric one-site term                   */
+  const double* A;    /* host, D*d*d: A_k acts on site j                      */
+  const double* B;    /* host, D*d*d: B_k acts on site j+1; each pair (A_k,B_k)
+                         is both symmetric or both antisymmetric              */
+  double shift;       /* c with every bond term minus c negative semidefinite;
+                         NaN selects the largest eigenvalue of the bond term
+                         1/2(h1 x I + I x h1) + sum_k A_k x B_k              */
+  int ly;             /* physical spins per effective site (energy per spin
+                         divides by L*ly), >= 1                               */
+  int precision;      /* TTN_FP64, TTN_FP32 or TTN_SPLIT_BF16                 */
+  unsigned long long seed; /* isometries when w0 == NULL: Gaussian entries
+                         from a counter-based generator (SplitMix64 +
+                         Box-Muller) made orthonormal by the polar update     */
+  const double* const* w0; /* optional host array of n-1 pointers, layer tau
+                         at w0[tau-1] with shape (chi_tau, chi_{tau-1}^2)     */
+  const double* v0;   /* optional host chi_{n-1}^2 start vector of the top
+                         eigensolver (else a fixed deterministic vector)      */
+  int krylov;         /* Lanczos basis size per restart (0: 40)               */
+  int restarts;       /* Lanczos restarts per top update (0: 6)               */
+  double lanczos_tol; /* target ||H v - lambda v|| / ||H||_est (0: 1e-13)     */
+} ttn_config;
+
+/* Bytes of device workspace needed by ttn_init for these configs. */
+ttn_status ttn_workspace_bytes(const ttn_config* cfgs, int batch, size_t* bytes);
+
+/* Validates the configs, lays out the caller-owned device workspace
+ * (`workspace`, `bytes`, 256-byte aligned), copies the host inputs, builds
+ * or loads the isometries, ascends every level, solves the top tensor and
+ * computes the energy (Sec. III; initial state of the sweep).  `stream` is a
+ * hipStream_t (NULL = default stream).  On success *out owns no device memory;
+ * the workspace must outlive the handle. */
+ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t bytes,
+                    void* stream, ttn_handle* out);
+
+/* Ascends the one-site term and the product terms through layers
+ * tau_from..tau_to (1 <= tau_from <= tau_to <= n-1), Fig. 3 / Fig. 4(b):
+ *   h' = w S w^T,  A'_k = w (I x A_k) w^T,  B'_k = w (B_k x I) w^T
+ * with S = h x I + I x h + sum_k A_k x B_k applied to the legs of w. */
+ttn_status ttn_ascend(ttn_handle h, int tau_from, int tau_to);
+
+/* what = TTN_DESCEND_RHO: position-averaged one-site RDMs rho^(tau) for
+ *   tau = n-1..1 from v (cache for the whole sweep; `tau` is ignored).
+ * what = TTN_DESCEND_DRESSED: the two-site information Rbar_k^(tau),
+ *   Lbar_k^(tau) for the update of layer tau (1 <= tau <= n-1): A_k, B_k of
+ *   level tau-1 are carried up to the top with the current layers, dressed by
+ *   v and descended back to level tau (Sec. III.A, Fig. 3). */
+ttn_status ttn_descend(ttn_handle h, int what, int tau);
+
+/* Environment of w_tau (Sec. III.A), same index shape as w_tau:
+ *   Env = rho o (S w) + sum_k Rbar_k o (B_k .l w) + sum_k Lbar_k o (A_k .r w).
+ * Requires ttn_descend(DRESSED, tau) since the last change of layer tau. */
+ttn_status ttn_env(ttn_handle h, int tau);
+
+/* tau in 1..n-1: w_tau <- -polar(Env) = -U V^T for the thin SVD
+ *   Env = U S V^T (Sec. III.B, Fig. 10(a)), in float64, followed by the check
+ *   ||W W^T - I||_F <= 1e-10 (TTN_EORTHO otherwise).  Does not re-ascend.
+ * tau == TTN_TOP: v <- lowest eigenvector of the top Hamiltonian (Lanczos,
+ *   float64, warm-started from the current v) and the energy. */
+ttn_status ttn_update(ttn_handle h, int tau);
+
+/* Synchronises the stream and writes the energy per physical spin
+ * (E + c L) / (L ly) of each batch member to e_per_site[batch] (host). */
+ttn_status ttn_energy(ttn_handle h, double* e_per_site);
+
+/* nsweeps full sweeps: descend(RHO); for tau = 1..n-1 { descend(DRESSED,
+ * tau); env(tau); update(tau); ascend(tau, tau) }; update(TOP). */
+ttn_status ttn_sweep(ttn_handle h, int nsweeps);
+
+/* Checkpoint / parity access to the float64 master tensors of member b:
+ * tau in 1..n-1 selects w_tau (chi_tau*chi_{tau-1}^2 doubles), tau == TTN_TOP
+ * selects v (chi_{n-1}^2 doubles).  set_tensor invalidates every cached
+ * operator above the layer; call ttn_ascend before the next stage. */
+ttn_status ttn_get_tensor(ttn_handle h, int b, int tau, double* host);
+ttn_status ttn_set_tensor(ttn_handle h, int b, int tau, const double* host);
+
+/* Copies a level-tau one-site matrix (kind TTN_OP_*, product term k) of
+ * member b to host float64 (chi_tau^2 doubles; TTN_OP_ENV: the last
+ * environment of layer tau, chi_tau*chi_{tau-1}^2 doubles). */
+ttn_status ttn_get_operator(ttn_handle h, int b, int level, int kind, int k, double* host);
+
+typedef struct ttn_stats_t {
+  double energy;          /* energy per physical spin after the last update    */
+  double lambda;          /* lowest eigenvalue of the shifted top Hamiltonian */
+  double lanczos_resid;   /* ||H v - lambda v|| of the last top update        */
+  double ortho_err_max;   /* max ||W W^T - I||_F of the updates since init    */
+  double sigma_ratio_min; /* min sigma_min/sigma_max of the environments       */
+  double shift;           /* c                                                 */
+  double flops_bulk;      /* algorithmic bulk flops of one sweep              */
+  double flops_fp64;      /* algorithmic float64 flops of one sweep           */
+  int n_levels;           /* n                                                 */
+  int lanczos_iters;      /* Krylov steps of the last top update              */
+} ttn_stats_t;
+
+ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
+
+/* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
+int ttn_bond_dim(ttn_handle h, int b, int tau);
+
+/* Thread-local description of the last error. */
+const char* ttn_last_error(void);
+
+ttn_status ttn_free(ttn_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTN_H */

@@ -1,0 +1,239 @@
+"""ctypes binding of libttn.so (include/ttn.h): the same entry points, argument
+marshalling only.  PyTorch provides the device workspace and the stream.
+
+The library is loaded from this package directory; if it is missing the
+import of any entry point raises (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttn.so")
+
+TTN_OK, TTN_WRANK, TTN_WNOCONV = 0, 1, 2
+TTN_EINVAL, TTN_ENOMEM, TTN_EHIP, TTN_ENONFINITE, TTN_ENOCONV, TTN_EORTHO, TTN_ESTATE = -1, -2, -3, -4, -5, -6, -7
+TTN_FP64, TTN_FP32, TTN_SPLIT_BF16 = 0, 1, 2
+TTN_DESCEND_RHO, TTN_DESCEND_DRESSED = 0, 1
+TTN_TOP = -1
+TTN_OP_H, TTN_OP_A, TTN_OP_B, TTN_OP_RHO, TTN_OP_RBAR, TTN_OP_LBAR, TTN_OP_ENV = range(7)
+PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
+
+# Every symbol declared in include/ttn.h.
+EXPORTS = [
+    "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
+    "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator",
+    "ttn_stats", "ttn_bond_dim", "ttn_last_error", "ttn_free",
+]
+
+
+class TTNConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int), ("d", ctypes.c_int), ("chi", ctypes.c_int), ("D", ctypes.c_int),
+        ("h1", ctypes.POINTER(ctypes.c_double)), ("A", ctypes.POINTER(ctypes.c_double)),
+        ("B", ctypes.POINTER(ctypes.c_double)), ("shift", ctypes.c_double), ("ly", ctypes.c_int),
+        ("precision", ctypes.c_int), ("seed", ctypes.c_ulonglong),
+        ("w0", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+        ("v0", ctypes.POINTER(ctypes.c_double)), ("krylov", ctypes.c_int), ("restarts", ctypes.c_int),
+        ("lanczos_tol", ctypes.c_double),
+    ]
+
+
+class TTNStats(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("lanczos_resid", ctypes.c_double),
+        ("ortho_err_max", ctypes.c_double), ("sigma_ratio_min", ctypes.c_double), ("shift", ctypes.c_double),
+        ("flops_bulk", ctypes.c_double), ("flops_fp64", ctypes.c_double), ("n_levels", ctypes.c_int),
+        ("lanczos_iters", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libttn.so and declares the argument types of every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1905_01331_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ttn_workspace_bytes": ([ctypes.POINTER(TTNConfig), I, ctypes.POINTER(ctypes.c_size_t)], I),
+        "ttn_init": ([ctypes.POINTER(TTNConfig), I, P, ctypes.c_size_t, P, ctypes.POINTER(P)], I),
+        "ttn_ascend": ([P, I, I], I),
+        "ttn_descend": ([P, I, I], I),
+        "ttn_env": ([P, I], I),
+        "ttn_update": ([P, I], I),
+        "ttn_energy": ([P, DP], I),
+        "ttn_sweep": ([P, I], I),
+        "ttn_get_tensor": ([P, I, I, DP], I),
+        "ttn_set_tensor": ([P, I, I, DP], I),
+        "ttn_get_operator": ([P, I, I, I, I, DP], I),
+        "ttn_stats": ([P, I, ctypes.POINTER(TTNStats)], I),
+        "ttn_bond_dim": ([P, I, I], I),
+        "ttn_last_error": ([], ctypes.c_char_p),
+        "ttn_free": ([P], I),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class TTNError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _check(status, allow_warn=True):
+    if status < 0 or (status > 0 and not allow_warn):
+        raise TTNError(status, load_library().ttn_last_error().decode())
+    return status
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class ChainInput:
+    """Host-side arrays of one batch member, kept alive for the ctypes config."""
+
+    def __init__(self, model, L, chi, precision="fp64", seed=0, w0=None, v0=None, shift=None,
+                 krylov=0, restarts=0, lanczos_tol=0.0):
+        h1, A, B = model.packed()
+        self.h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        self.A = np.ascontiguousarray(A, dtype=np.float64)
+        self.B = np.ascontiguousarray(B, dtype=np.float64)
+        self.w0 = None if w0 is None else [np.ascontiguousarray(w, dtype=np.float64) for w in w0]
+        self.v0 = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
+        self._wptrs = None
+        cfg = TTNConfig()
+        cfg.L, cfg.d, cfg.chi, cfg.D = int(L), int(model.d), int(chi), int(model.D)
+        cfg.h1 = _dptr(self.h1)
+        cfg.A = _dptr(self.A) if model.D else None
+        cfg.B = _dptr(self.B) if model.D else None
+        cfg.shift = math.nan if shift is None else float(shift)
+        cfg.ly = int(model.ly)
+        cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cfg.seed = int(seed)
+        if self.w0 is not None:
+            arr = (ctypes.POINTER(ctypes.c_double) * len(self.w0))(*[_dptr(w) for w in self.w0])
+            self._wptrs = arr
+            cfg.w0 = ctypes.cast(arr, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
+        else:
+            cfg.w0 = None
+        cfg.v0 = _dptr(self.v0) if self.v0 is not None else None
+        cfg.krylov, cfg.restarts, cfg.lanczos_tol = int(krylov), int(restarts), float(lanczos_tol)
+        self.cfg = cfg
+
+
+def ttn_workspace_bytes(inputs):
+    lib = load_library()
+    arr = (TTNConfig * len(inputs))(*[x.cfg for x in inputs])
+    out = ctypes.c_size_t(0)
+    _check(lib.ttn_workspace_bytes(arr, len(inputs), ctypes.byref(out)))
+    return out.value
+
+
+class TTN:
+    """One handle over a batch of chains; the workspace is a torch uint8 tensor."""
+
+    def __init__(self, inputs, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        if not isinstance(inputs, (list, tuple)):
+            inputs = [inputs]
+        self.inputs = list(inputs)
+        self.batch = len(self.inputs)
+        nbytes = ttn_workspace_bytes(self.inputs)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
+        arr = (TTNConfig * self.batch)(*[x.cfg for x in self.inputs])
+        h = ctypes.c_void_p(0)
+        self.init_status = _check(lib.ttn_init(arr, self.batch, ctypes.c_void_p(aligned), nbytes,
+                                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+
+    # stage calls -------------------------------------------------------------
+    def ascend(self, tau_from, tau_to):
+        return _check(self.lib.ttn_ascend(self.h, tau_from, tau_to))
+
+    def descend(self, what, tau=0):
+        return _check(self.lib.ttn_descend(self.h, what, tau))
+
+    def env(self, tau):
+        return _check(self.lib.ttn_env(self.h, tau))
+
+    def update(self, tau):
+        return _check(self.lib.ttn_update(self.h, tau))
+
+    def energy(self):
+        out = np.zeros(self.batch)
+        _check(self.lib.ttn_energy(self.h, _dptr(out)))
+        return out
+
+    def sweep(self, nsweeps=1):
+        return _check(self.lib.ttn_sweep(self.h, nsweeps))
+
+    # access -----------------------------------------------------------------
+    def bond_dim(self, tau, b=0):
+        return self.lib.ttn_bond_dim(self.h, b, tau)
+
+    def n_levels(self, b=0):
+        return self.stats(b).n_levels
+
+    def get_tensor(self, tau, b=0):
+        n = self.n_levels(b)
+        if tau == TTN_TOP:
+            x = self.bond_dim(n - 1, b)
+            out = np.zeros((x, x))
+        else:
+            a, bb = self.bond_dim(tau, b), self.bond_dim(tau - 1, b)
+            out = np.zeros((a, bb, bb))
+        _check(self.lib.ttn_get_tensor(self.h, b, tau, _dptr(out)))
+        return out
+
+    def set_tensor(self, tau, arr, b=0):
+        arr = np.ascontiguousarray(arr, dtype=np.float64)
+        _check(self.lib.ttn_set_tensor(self.h, b, tau, _dptr(arr)))
+
+    def get_operator(self, level, kind, k=0, b=0):
+        x = self.bond_dim(level, b)
+        if kind == TTN_OP_ENV:
+            y = self.bond_dim(level - 1, b)
+            out = np.zeros((x, y, y))
+        else:
+            out = np.zeros((x, x))
+        _check(self.lib.ttn_get_operator(self.h, b, level, kind, k, _dptr(out)))
+        return out
+
+    def stats(self, b=0):
+        st = TTNStats()
+        _check(self.lib.ttn_stats(self.h, b, ctypes.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.ttn_free(self.h)
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

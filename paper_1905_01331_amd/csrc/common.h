@@ -1,0 +1,58 @@
+// Internal declarations shared by the HIP sources of libttn (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace ttn {
+
+// Strided, batched matrix product  C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n).
+// Element addresses:  A + b*sAb + m*sAm + koff_A(k),  B + b*sBb + koff_B(k) + n*sBn,
+// C + b*sCb + m*sCm + n*sCn,  with a two-level contraction index k = k1*K2 + k2:
+// koff_A(k) = k1*sAk1 + k2*sAk (likewise for B).  K2 == K means a single level.
+struct GemmDesc {
+  int M, N, K, K2;
+  int batch;
+  const void* A; long long sAm, sAk, sAk1, sAb;
+  const void* B; long long sBk, sBn, sBk1, sBb;
+  void* C;       long long sCm, sCn, sCb;
+  double alpha, beta;
+};
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
+
+// Launches one product in the given arithmetic.  F64: double operands and
+// result.  F32 / BF16X3: float operands and result (BF16X3 splits every
+// float operand into bf16 hi + lo on load).  `scratch` (float/double,
+// `scratch_elems` elements) holds split-K partial sums when the launcher
+// chooses to split the contraction; the reduction is deterministic.
+hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s);
+
+// -------- small kernels (small.hip) -------------------------------------------
+hipError_t convert_f64_to_f32(const double* x, float* y, size_t n, hipStream_t s);
+hipError_t convert_f32_to_f64(const float* x, double* y, size_t n, hipStream_t s);
+hipError_t fill_f64(double* x, double v, size_t n, hipStream_t s);
+hipError_t fill_f32(float* x, float v, size_t n, hipStream_t s);
+hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s);
+// y = alpha*x + beta*y over n elements (float or double)
+hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size_t n, hipStream_t s);
+hipError_t axpby_f32(const float* x, float* y, float alpha, float beta, size_t n, hipStream_t s);
+hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned long long stream_id, hipStream_t s);
+
+// Jacobi eigensolver of a symmetric n x n float64 matrix G (in place; on
+// return the diagonal holds the eigenvalues), eigenvectors in the columns of
+// V (n x n).  One work-group.  `info` (device int[4]): [0] sweeps used,
+// [1] rotations in the first sweep.
+hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s);
+// Z[i,:] = Y[i,:] / ||Y[i,:]||  for an m x k matrix (row norms into nrm[m]); rows
+// with a zero norm are left zero.
+hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, long long k, hipStream_t s);
+// Frobenius pairing sum X.*Y (float64 result into out[0]).
+// `part` is device scratch of at least 256 doubles.
+hipError_t pair_f64(const double* X, const double* Y, long long n, double* out, double* part, hipStream_t s);
+hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, double* part, hipStream_t s);
+// ||W W^T - I||_F from the Gram G (n x n): out[0] = sqrt(sum (G - I)^2)
+hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s);
+
+}  // namespace ttn

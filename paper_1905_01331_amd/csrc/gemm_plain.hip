@@ -1,0 +1,248 @@
+// Register-blocked, LDS-tiled strided GEMM for float64 and float32 (gfx950).
+//
+// Every contraction of the sweep (leg applications, closes, left
+// multiplications, child closes; Fig. 4(b): matrix products after
+// flattening) is one strided product; the index permutations of the
+// rank-3 tensors are folded into the operand strides of the tile loaders,
+// so no tensor is ever transposed in memory.
+//
+// This kernel is the general path: any strides, ragged edges, two-level
+// contraction index.  The float32 / split-bf16 MFMA kernels take the large
+// regular shapes.
+#include "common.h"
+#include "gemm_internal.h"
+
+namespace ttn {
+
+namespace {
+
+constexpr int PT_M = 64, PT_N = 64, PT_K = 16, PT_THREADS = 256;
+
+__device__ __forceinline__ long long koff(int k, int K2, long long s2, long long s1) {
+  if (K2 <= 0) return (long long)k * s2;
+  int k1 = k / K2;
+  int k2 = k - k1 * K2;
+  return (long long)k1 * s1 + (long long)k2 * s2;
+}
+
+// Round a float to the nearest bf16 value (ties to even), returned as float.
+__device__ __forceinline__ float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;  // inf / nan unchanged
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  u &= 0xffff0000u;
+  return __uint_as_float(u);
+}
+
+// MODE 0: plain (T = double or float).  MODE 1: split-bf16 emulation on the
+// vector units (T = float): every operand is split into hi = bf16(x),
+// lo = bf16(x - hi) and the product is hi*hi + hi*lo + lo*hi accumulated in
+// float32.
+template <typename T, int MODE>
+__global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int splits, int kchunk,
+                                                                T* __restrict__ partial) {
+  __shared__ T As[PT_K][PT_M + 1];
+  __shared__ T Bs[PT_K][PT_N + 1];
+  __shared__ T Al[MODE ? PT_K : 1][MODE ? PT_M + 1 : 1];
+  __shared__ T Bl[MODE ? PT_K : 1][MODE ? PT_N + 1 : 1];
+
+  const int bz = blockIdx.z;
+  const int b = bz / splits;
+  const int sp = bz - b * splits;
+  const int m0 = blockIdx.y * PT_M;
+  const int n0 = blockIdx.x * PT_N;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  const T* __restrict__ A = (const T*)g.A + (long long)b * g.sAb;
+  const T* __restrict__ B = (const T*)g.B + (long long)b * g.sBb;
+
+  const int tid = threadIdx.x;
+  const int tx = tid & 15;  // columns n0 + tx + 16*j
+  const int ty = tid >> 4;  // rows    m0 + ty + 16*i
+
+  T acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+
+  const bool a_kcontig = (g.sAk == 1);
+  const bool b_ncontig = (g.sBn == 1);
+
+  for (int k0 = kbeg; k0 < kend; k0 += PT_K) {
+#pragma unroll
+    for (int it = 0; it < (PT_M * PT_K) / PT_THREADS; ++it) {
+      int idx = tid + it * PT_THREADS;
+      int mm, kk;
+      if (a_kcontig) { mm = idx / PT_K; kk = idx - mm * PT_K; }
+      else           { kk = idx / PT_M; mm = idx - kk * PT_M; }
+      int m = m0 + mm, k = k0 + kk;
+      T v = T(0);
+      if (m < g.M && k < kend) v = A[(long long)m * g.sAm + koff(k, g.K2, g.sAk, g.sAk1)];
+      if constexpr (MODE == 1) {
+        float hi = bf16_round((float)v);
+        As[kk][mm] = hi;
+        Al[kk][mm] = bf16_round((float)v - hi);
+      } else {
+        As[kk][mm] = v;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < (PT_N * PT_K) / PT_THREADS; ++it) {
+      int idx = tid + it * PT_THREADS;
+      int nn, kk;
+      if (b_ncontig) { kk = idx / PT_N; nn = idx - kk * PT_N; }
+      else           { nn = idx / PT_K; kk = idx - nn * PT_K; }
+      int n = n0 + nn, k = k0 + kk;
+      T v = T(0);
+      if (n < g.N && k < kend) v = B[(long long)n * g.sBn + koff(k, g.K2, g.sBk, g.sBk1)];
+      if constexpr (MODE == 1) {
+        float hi = bf16_round((float)v);
+        Bs[kk][nn] = hi;
+        Bl[kk][nn] = bf16_round((float)v - hi);
+      } else {
+        Bs[kk][nn] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < PT_K; ++kk) {
+      T a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+      if constexpr (MODE == 1) {
+        T al[4], bl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) al[i] = Al[kk][ty + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bl[j] = Bl[kk][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            acc[i][j] = fmaf(al[i], bb[j], acc[i][j]);
+            acc[i][j] = fmaf(a[i], bl[j], acc[i][j]);
+            acc[i][j] = fmaf(a[i], bb[j], acc[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * bb[j];
+      }
+    }
+    __syncthreads();
+  }
+
+  if (splits == 1) {
+    T* C = (T*)g.C + (long long)b * g.sCb;
+    const T alpha = (T)g.alpha, beta = (T)g.beta;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int m = m0 + ty + 16 * i;
+      if (m >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int n = n0 + tx + 16 * j;
+        if (n >= g.N) continue;
+        T* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
+        T r = alpha * acc[i][j];
+        if (g.beta != 0.0) r += beta * (*c);
+        *c = r;
+      }
+    }
+  } else {
+    // partial sums, dense (M x N) per (split, batch) slice
+    T* P = partial + ((long long)sp * g.batch + b) * (long long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int m = m0 + ty + 16 * i;
+      if (m >= g.M) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int n = n0 + tx + 16 * j;
+        if (n >= g.N) continue;
+        P[(long long)m * g.N + n] = acc[i][j];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// Deterministic split-K reduction: C = alpha * sum_s P[s] + beta * C, the
+// partial slices summed in increasing split order.
+template <typename T>
+__global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict__ partial) {
+  long long total = (long long)g.batch * g.M * g.N;
+  long long MN = (long long)g.M * g.N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    int b = (int)(i / MN);
+    long long r = i - (long long)b * MN;
+    int m = (int)(r / g.N);
+    int n = (int)(r - (long long)m * g.N);
+    T s = T(0);
+    for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * g.batch + b) * MN + r];
+    T* c = (T*)g.C + (long long)b * g.sCb + (long long)m * g.sCm + (long long)n * g.sCn;
+    T out = (T)g.alpha * s;
+    if (g.beta != 0.0) out += (T)g.beta * (*c);
+    *c = out;
+  }
+}
+
+template <typename T>
+static int choose_splits(const GemmDesc& g, size_t scratch_bytes) {
+  long long tiles = (long long)((g.M + PT_M - 1) / PT_M) * ((g.N + PT_N - 1) / PT_N) * g.batch;
+  if (tiles >= 512 || g.K < 8 * PT_K) return 1;
+  long long want = (1024 + tiles - 1) / tiles;
+  long long maxk = (g.K + 4 * PT_K - 1) / (4 * PT_K);  // at least 4 k-tiles per split
+  long long s = want < maxk ? want : maxk;
+  if (s > 64) s = 64;
+  size_t slice = (size_t)g.batch * g.M * g.N * sizeof(T);
+  if (slice == 0) return 1;
+  long long fit = (long long)(scratch_bytes / slice);
+  if (s > fit) s = fit;
+  return s < 1 ? 1 : (int)s;
+}
+
+template <typename T, int MODE>
+static hipError_t launch_plain(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return hipSuccess;
+  int splits = (g.K > 0) ? choose_splits<T>(g, scratch_bytes) : 1;
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = ((kchunk + PT_K - 1) / PT_K) * PT_K;
+  if (kchunk == 0) kchunk = PT_K;
+  splits = (g.K + kchunk - 1) / kchunk;
+  if (splits < 1) splits = 1;
+  dim3 grid((g.N + PT_N - 1) / PT_N, (g.M + PT_M - 1) / PT_M, g.batch * splits);
+  hipLaunchKernelGGL((gemm_plain_kernel<T, MODE>), grid, dim3(PT_THREADS), 0, s, g, splits, kchunk,
+                     (T*)scratch);
+  if (splits > 1) {
+    long long total = (long long)g.batch * g.M * g.N;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(blocks), dim3(256), 0, s, g, splits,
+                       (const T*)scratch);
+  }
+  return hipGetLastError();
+}
+
+hipError_t gemm_plain(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  switch (prec) {
+    case P_F64: return launch_plain<double, 0>(g, scratch, scratch_bytes, s);
+    case P_F32: return launch_plain<float, 0>(g, scratch, scratch_bytes, s);
+    case P_BF16X3: return launch_plain<float, 1>(g, scratch, scratch_bytes, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  return gemm_plain(prec, g, scratch, scratch_bytes, s);
+}
+
+}  // namespace ttn

@@ -1,0 +1,23 @@
+#pragma once
+#include "common.h"
+
+namespace ttn {
+hipError_t lz_three_term(double* w, const double* qj, const double* qjm1, const double* alpha, const double* beta, int j,
+                         size_t n, const int* stop, hipStream_t s);
+hipError_t lz_set_beta(const double* ss, const double* hss, double* beta, int j, double tol, int* stop, int* m_eff,
+                       hipStream_t s);
+hipError_t lz_next_q(const double* w, double* qn, const double* beta, int j, size_t n, const int* stop, hipStream_t s);
+hipError_t lz_build_T(const double* alpha, const double* beta, int m, const int* stop, const int* m_eff, double* T,
+                      hipStream_t s);
+hipError_t lz_select_lowest(const double* T, const double* V, int m, double* y, double* theta, hipStream_t s);
+hipError_t scale_rsqrt(double* x, const double* ss, size_t n, hipStream_t s);
+hipError_t residual_vec(const double* Hv, const double* v, const double* lam, double* r, size_t n, hipStream_t s);
+hipError_t sign_fix(double* v, size_t n, hipStream_t s);
+hipError_t axpy_dev(double* y, const double* x, const double* scale, double factor, size_t n, hipStream_t s);
+hipError_t sqrt_inplace(double* x, hipStream_t s);
+hipError_t energy_store(const double* lam, double c, double L, double ly, double* out, hipStream_t s);
+hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, hipStream_t s);
+hipError_t running_max(const double* x, double* run_max, hipStream_t s);
+hipError_t identity_f64(double* X, int n, hipStream_t s);
+hipError_t zero_int(int* x, int n, hipStream_t s);
+}  // namespace ttn

@@ -1,0 +1,255 @@
+// Device kernels of the float64 Lanczos solver for the top tensor and small
+// helpers of the polar update.  All scalars of the recurrence live in device
+// memory so the host never waits inside an iteration.
+#include "common.h"
+#include "lanczos.h"
+#include <math.h>
+
+namespace ttn {
+namespace {
+
+inline int grid_for(size_t n, int threads = 256, int cap = 4096) {
+  size_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > (size_t)cap) b = cap;
+  return (int)b;
+}
+
+// w <- w - alpha[j] q_j - beta[j-1] q_{j-1}
+__global__ void k_three_term(double* __restrict__ w, const double* __restrict__ qj, const double* __restrict__ qjm1,
+                             const double* __restrict__ alpha, const double* __restrict__ beta, int j, size_t n,
+                             const int* __restrict__ stop) {
+  if (*stop) return;
+  double a = alpha[j];
+  double b = (j > 0) ? beta[j - 1] : 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    double v = w[i] - a * qj[i];
+    if (j > 0) v -= b * qjm1[i];
+    w[i] = v;
+  }
+}
+
+// beta[j] = sqrt(ss); stop when beta[j] <= tol * hnorm (invariant subspace).
+__global__ void k_set_beta(const double* __restrict__ ss, const double* __restrict__ hss, double* __restrict__ beta,
+                           int j, double tol, int* __restrict__ stop, int* __restrict__ m_eff) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (*stop) { beta[j] = 0.0; return; }
+  double b = sqrt(fmax(ss[0], 0.0));
+  double hn = sqrt(fmax(hss[0], 0.0));
+  if (!(b > tol * hn) || b == 0.0) {
+    beta[j] = 0.0;
+    *stop = 1;
+    *m_eff = j + 1;
+  } else {
+    beta[j] = b;
+  }
+}
+
+// q_{j+1} = w / beta[j] (left at zero after a stop)
+__global__ void k_next_q(const double* __restrict__ w, double* __restrict__ qn, const double* __restrict__ beta, int j,
+                         size_t n, const int* __restrict__ stop) {
+  double b = beta[j];
+  bool st = *stop;
+  double inv = (!st && b > 0.0) ? 1.0 / b : 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    qn[i] = st ? 0.0 : w[i] * inv;
+}
+
+// Dense tridiagonal T (m x m) from alpha/beta; rows past m_eff are decoupled
+// with a diagonal above every Ritz value so they never become the lowest.
+__global__ void k_build_T(const double* __restrict__ alpha, const double* __restrict__ beta, int m,
+                          const int* __restrict__ stop, const int* __restrict__ m_eff, double* __restrict__ T) {
+  int me = (*stop) ? *m_eff : m;
+  double big = 0.0;
+  for (int i = 0; i < me; ++i) big = fmax(big, fabs(alpha[i]) + 2.0 * fabs(beta[i]));
+  big = 4.0 * big + 1.0;
+  for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+    int r = idx / m, c = idx - r * m;
+    double v = 0.0;
+    if (r < me && c < me) {
+      if (r == c) v = alpha[r];
+      else if (c == r + 1) v = beta[r];
+      else if (r == c + 1) v = beta[c];
+    } else if (r == c) {
+      v = big;
+    }
+    T[idx] = v;
+  }
+}
+
+// y = eigenvector of the smallest diagonal entry of the diagonalised T
+// (columns of V), the entry of largest magnitude made positive.
+__global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* __restrict__ V, int m,
+                                double* __restrict__ y, double* __restrict__ theta) {
+  __shared__ int best;
+  if (threadIdx.x == 0) {
+    int b = 0;
+    for (int i = 1; i < m; ++i)
+      if (Tdiag[(size_t)i * m + i] < Tdiag[(size_t)b * m + b]) b = i;
+    best = b;
+    theta[0] = Tdiag[(size_t)b * m + b];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) y[i] = V[(size_t)i * m + best];
+}
+
+// x *= 1 / sqrt(ss[0])
+__global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__ ss, size_t n) {
+  double s = ss[0];
+  double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] *= inv;
+}
+
+// r = Hv - lam v, lam = lamv[0]
+__global__ void k_residual(const double* __restrict__ Hv, const double* __restrict__ v, const double* __restrict__ lamv,
+                           double* __restrict__ r, size_t n) {
+  double lam = lamv[0];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    r[i] = Hv[i] - lam * v[i];
+}
+
+// Sign convention: the entry of largest magnitude (first on ties) positive.
+__global__ void k_sign_fix(double* __restrict__ v, size_t n) {
+  __shared__ double bv[256];
+  __shared__ long long bi[256];
+  double best = -1.0;
+  long long idx = -1;
+  for (size_t i = threadIdx.x; i < n; i += blockDim.x) {
+    double a = fabs(v[i]);
+    if (a > best) { best = a; idx = (long long)i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double o = bv[threadIdx.x + s];
+      long long oi = bi[threadIdx.x + s];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi >= 0 && (bi[threadIdx.x] < 0 || oi < bi[threadIdx.x]))) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  long long im = bi[0];
+  __syncthreads();
+  if (im < 0) return;
+  bool flip = v[im] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x) v[i] = -v[i];
+}
+
+// out = a*x + b*y with a, b read from device scalars (sa, sb may be null for 1)
+__global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ scale,
+                           double factor, size_t n) {
+  double s = factor * (scale ? scale[0] : 1.0);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] += s * x[i];
+}
+
+__global__ void k_sqrt_inplace(double* x) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = sqrt(fmax(x[0], 0.0));
+}
+
+// energy bookkeeping: out[0] = lam, out[1] = (lam + c L) / (L ly)
+__global__ void k_energy(const double* __restrict__ lam, double c, double L, double ly, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    out[0] = lam[0];
+    out[1] = (lam[0] + c * L) / (L * ly);
+  }
+}
+
+// min/max of nrm[0..m) -> out[0] = min/max ratio (0 if max == 0)
+__global__ void k_ratio(const double* __restrict__ nrm, int m, double* __restrict__ out, double* __restrict__ run_min) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double mn = nrm[0], mx = nrm[0];
+    for (int i = 1; i < m; ++i) { mn = fmin(mn, nrm[i]); mx = fmax(mx, nrm[i]); }
+    double r = mx > 0.0 ? mn / mx : 0.0;
+    out[0] = r;
+    if (run_min) run_min[0] = fmin(run_min[0], r);
+  }
+}
+
+__global__ void k_running_max(const double* __restrict__ x, double* __restrict__ run_max) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) run_max[0] = fmax(run_max[0], x[0]);
+}
+
+__global__ void k_identity(double* __restrict__ X, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x)
+    X[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
+__global__ void k_zero_int(int* x, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
+}
+
+}  // namespace
+
+hipError_t lz_three_term(double* w, const double* qj, const double* qjm1, const double* alpha, const double* beta, int j,
+                         size_t n, const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_three_term, dim3(grid_for(n)), dim3(256), 0, s, w, qj, qjm1, alpha, beta, j, n, stop);
+  return hipGetLastError();
+}
+hipError_t lz_set_beta(const double* ss, const double* hss, double* beta, int j, double tol, int* stop, int* m_eff,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_set_beta, dim3(1), dim3(64), 0, s, ss, hss, beta, j, tol, stop, m_eff);
+  return hipGetLastError();
+}
+hipError_t lz_next_q(const double* w, double* qn, const double* beta, int j, size_t n, const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_next_q, dim3(grid_for(n)), dim3(256), 0, s, w, qn, beta, j, n, stop);
+  return hipGetLastError();
+}
+hipError_t lz_build_T(const double* alpha, const double* beta, int m, const int* stop, const int* m_eff, double* T,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_build_T, dim3(1), dim3(256), 0, s, alpha, beta, m, stop, m_eff, T);
+  return hipGetLastError();
+}
+hipError_t lz_select_lowest(const double* T, const double* V, int m, double* y, double* theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_lowest, dim3(1), dim3(64), 0, s, T, V, m, y, theta);
+  return hipGetLastError();
+}
+hipError_t scale_rsqrt(double* x, const double* ss, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n)), dim3(256), 0, s, x, ss, n);
+  return hipGetLastError();
+}
+hipError_t residual_vec(const double* Hv, const double* v, const double* lam, double* r, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(256), 0, s, Hv, v, lam, r, n);
+  return hipGetLastError();
+}
+hipError_t sign_fix(double* v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_sign_fix, dim3(1), dim3(256), 0, s, v, n);
+  return hipGetLastError();
+}
+hipError_t axpy_dev(double* y, const double* x, const double* scale, double factor, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(n)), dim3(256), 0, s, y, x, scale, factor, n);
+  return hipGetLastError();
+}
+hipError_t sqrt_inplace(double* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_sqrt_inplace, dim3(1), dim3(64), 0, s, x);
+  return hipGetLastError();
+}
+hipError_t energy_store(const double* lam, double c, double L, double ly, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, s, lam, c, L, ly, out);
+  return hipGetLastError();
+}
+hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, hipStream_t s) {
+  hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, nrm, m, out, run_min);
+  return hipGetLastError();
+}
+hipError_t running_max(const double* x, double* run_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_running_max, dim3(1), dim3(64), 0, s, x, run_max);
+  return hipGetLastError();
+}
+hipError_t identity_f64(double* X, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_identity, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, X, n);
+  return hipGetLastError();
+}
+hipError_t zero_int(int* x, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, x, n);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

@@ -1,0 +1,326 @@
+// Element-wise kernels, deterministic reductions, the counter-based Gaussian
+// generator and the float64 Jacobi eigensolver used by the polar update.
+#include "common.h"
+#include <math.h>
+
+namespace ttn {
+
+namespace {
+
+inline int grid_for(size_t n, int threads = 256, int cap = 8192) {
+  size_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > (size_t)cap) b = cap;
+  return (int)b;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+__global__ void k_f32_to_f64(const float* __restrict__ x, double* __restrict__ y, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
+}
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, T v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+__global__ void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_add_diag(double* X, int n, double v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) X[(size_t)i * n + i] += v;
+}
+template <typename T>
+__global__ void k_axpby(const T* __restrict__ x, T* __restrict__ y, T alpha, T beta, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    y[i] = alpha * x[i] + (beta == T(0) ? T(0) : beta * y[i]);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__global__ void k_gaussian(double* __restrict__ x, size_t n, uint64_t seed, uint64_t stream_id) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    uint64_t base = splitmix64(seed ^ splitmix64(stream_id + 0x632be59bd9b4e019ull));
+    uint64_t r1 = splitmix64(base + 2 * (uint64_t)i);
+    uint64_t r2 = splitmix64(base + 2 * (uint64_t)i + 1);
+    // uniforms in (0, 1]
+    double u1 = ((double)(r1 >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+    double u2 = (double)(r2 >> 11) * (1.0 / 9007199254740992.0);
+    x[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);  // Box-Muller
+  }
+}
+
+// Deterministic two-stage reductions: fixed grid, per-block partials, one
+// final block summing the partials in order.
+constexpr int RED_BLOCKS = 256;
+constexpr int RED_THREADS = 256;
+
+template <typename T>
+__device__ double block_sum(double v, double* sh) {
+  int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) sh[tid] += sh[tid + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_pair_partial(const T* __restrict__ X, const T* __restrict__ Y,
+                                                              long long n, double* __restrict__ part) {
+  __shared__ double sh[RED_THREADS];
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    acc += (double)X[i] * (double)Y[i];
+  double s = block_sum<T>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+__global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __restrict__ part, int np,
+                                                              double* __restrict__ out) {
+  __shared__ double sh[RED_THREADS];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
+  double s = block_sum<double>(acc, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_ortho_err(const double* __restrict__ G, int n, double* out) {
+  __shared__ double sh[RED_THREADS];
+  double acc = 0.0;
+  long long nn = (long long)n * n;
+  for (long long i = threadIdx.x; i < nn; i += blockDim.x) {
+    int r = (int)(i / n), c = (int)(i - (long long)r * n);
+    double e = G[i] - (r == c ? 1.0 : 0.0);
+    acc += e * e;
+  }
+  double s = block_sum<double>(acc, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(s);
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __restrict__ Y, double* __restrict__ Z,
+                                                               double* __restrict__ nrm, long long k) {
+  __shared__ double sh[RED_THREADS];
+  const double* y = Y + (long long)blockIdx.x * k;
+  double* z = Z + (long long)blockIdx.x * k;
+  // scaled sum of squares: first the max magnitude, then sum (y/max)^2
+  double mx = 0.0;
+  for (long long i = threadIdx.x; i < k; i += blockDim.x) mx = fmax(mx, fabs(y[i]));
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  mx = sh[0];
+  __syncthreads();
+  double acc = 0.0;
+  if (mx > 0.0) {
+    double inv = 1.0 / mx;
+    for (long long i = threadIdx.x; i < k; i += blockDim.x) {
+      double t = y[i] * inv;
+      acc += t * t;
+    }
+  }
+  double ss = block_sum<double>(acc, sh);
+  double norm = mx * sqrt(ss);
+  if (threadIdx.x == 0) nrm[blockIdx.x] = norm;
+  double inv = norm > 0.0 ? 1.0 / norm : 0.0;
+  for (long long i = threadIdx.x; i < k; i += blockDim.x) z[i] = y[i] * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi eigensolver (parallel round-robin ordering), float64.
+// Rotation of the pair (p, q) with t = tan(phi) from
+// theta = (G_qq - G_pp) / (2 G_pq), t = sign(theta) / (|theta| + sqrt(theta^2+1)),
+// c = 1/sqrt(1+t^2), s = t c;  G <- J^T G J, V <- V J, J = [[c, s], [-s, c]] on
+// (p, q).  A pair is skipped when |G_pq| <= tol * sqrt(|G_pp G_qq|) (relative
+// threshold: small eigenvalues of a graded matrix keep their relative
+// accuracy, Demmel and Veselic 1992).  All n/2 rotations of one round touch
+// disjoint index pairs, so the 2x2 blocks of J^T G J are independent.
+// ---------------------------------------------------------------------------
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_MAXN = 1024;
+
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, double* __restrict__ V, int n,
+                                                        int max_sweeps, double tol, int* info) {
+  __shared__ double cs[JAC_MAXN / 2], sn[JAC_MAXN / 2], tn[JAC_MAXN / 2];
+  __shared__ int pp[JAC_MAXN / 2], qq[JAC_MAXN / 2];
+  __shared__ int rot_count;
+  const int tid = threadIdx.x;
+  const int N = n + (n & 1);   // even number of players; index n is a dummy when n is odd
+  const int npair = N / 2;
+  for (long long i = tid; i < (long long)n * n; i += blockDim.x) {
+    int r = (int)(i / n), c = (int)(i - (long long)r * n);
+    V[i] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  int sweep = 0, first_rot = -1;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) rot_count = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      for (int k = tid; k < npair; k += blockDim.x) {
+        int p, q;
+        if (k == 0) { p = r; q = N - 1; }
+        else { p = (r + k) % (N - 1); q = (r - k + (N - 1)) % (N - 1); }
+        if (p > q) { int t = p; p = q; q = t; }
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (q < n) {
+          double gpp = G[(long long)p * n + p], gqq = G[(long long)q * n + q], gpq = G[(long long)p * n + q];
+          if (gpq != 0.0 && fabs(gpq) > tol * sqrt(fabs(gpp * gqq))) {
+            double theta = (gqq - gpp) / (2.0 * gpq);
+            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            atomicAdd(&rot_count, 1);
+          }
+        }
+        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t;
+      }
+      __syncthreads();
+      for (long long idx = tid; idx < (long long)npair * npair; idx += blockDim.x) {
+        int k1 = (int)(idx / npair), k2 = (int)(idx - (long long)k1 * npair);
+        int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        bool hq1 = q1 < n, hq2 = q2 < n;
+        double gpp = G[(long long)p1 * n + p2];
+        double gpq = hq2 ? G[(long long)p1 * n + q2] : 0.0;
+        double gqp = hq1 ? G[(long long)q1 * n + p2] : 0.0;
+        double gqq = (hq1 && hq2) ? G[(long long)q1 * n + q2] : 0.0;
+        // rows: (J1^T G)
+        double rp_p = c1 * gpp - s1 * gqp, rp_q = c1 * gpq - s1 * gqq;
+        double rq_p = s1 * gpp + c1 * gqp, rq_q = s1 * gpq + c1 * gqq;
+        // columns: (. J2)
+        double npp = c2 * rp_p - s2 * rp_q, npq = s2 * rp_p + c2 * rp_q;
+        double nqp = c2 * rq_p - s2 * rq_q, nqq = s2 * rq_p + c2 * rq_q;
+        if (k1 == k2 && s1 != 0.0) {
+          // the rotated pair itself: exact annihilation, Rutishauser's diagonal update
+          double t1 = tn[k1];
+          double g_pq = G[(long long)p1 * n + q1];
+          npp = G[(long long)p1 * n + p1] - t1 * g_pq;
+          nqq = G[(long long)q1 * n + q1] + t1 * g_pq;
+          npq = 0.0;
+          nqp = 0.0;
+        }
+        G[(long long)p1 * n + p2] = npp;
+        if (hq2) G[(long long)p1 * n + q2] = npq;
+        if (hq1) G[(long long)q1 * n + p2] = nqp;
+        if (hq1 && hq2) G[(long long)q1 * n + q2] = nqq;
+      }
+      for (long long idx = tid; idx < (long long)n * npair; idx += blockDim.x) {
+        int i = (int)(idx / npair), k = (int)(idx - (long long)i * npair);
+        double c = cs[k], s = sn[k];
+        if (s == 0.0) continue;
+        int p = pp[k], q = qq[k];
+        double vp = V[(long long)i * n + p], vq = V[(long long)i * n + q];
+        V[(long long)i * n + p] = c * vp - s * vq;
+        V[(long long)i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+    int rc = rot_count;
+    if (first_rot < 0) first_rot = rc;
+    __syncthreads();
+    if (rc == 0) break;
+  }
+  if (tid == 0 && info) {
+    info[0] = sweep;
+    info[1] = first_rot;
+  }
+}
+
+}  // namespace
+
+hipError_t convert_f64_to_f32(const double* x, float* y, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+hipError_t convert_f32_to_f64(const float* x, double* y, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+hipError_t fill_f64(double* x, double v, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+  return hipGetLastError();
+}
+hipError_t fill_f32(float* x, float v, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+  return hipGetLastError();
+}
+hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return hipSuccess;
+  if ((bytes % 8 == 0) && ((uintptr_t)dst % 8 == 0) && ((uintptr_t)src % 8 == 0)) {
+    size_t n = bytes / 8;
+    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n)), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n);
+  } else {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(bytes)), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
+  }
+  return hipGetLastError();
+}
+hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_diag, dim3(grid_for(n)), dim3(256), 0, s, X, n, v);
+  return hipGetLastError();
+}
+hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby<double>, dim3(grid_for(n)), dim3(256), 0, s, x, y, alpha, beta, n);
+  return hipGetLastError();
+}
+hipError_t axpby_f32(const float* x, float* y, float alpha, float beta, size_t n, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_axpby<float>, dim3(grid_for(n)), dim3(256), 0, s, x, y, alpha, beta, n);
+  return hipGetLastError();
+}
+hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned long long stream_id, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for(n)), dim3(256), 0, s, x, n, (uint64_t)seed, (uint64_t)stream_id);
+  return hipGetLastError();
+}
+hipError_t pair_f64(const double* X, const double* Y, long long n, double* out, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, Y, n, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out);
+  return hipGetLastError();
+}
+hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, Y, n, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out);
+  return hipGetLastError();
+}
+hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_ortho_err, dim3(1), dim3(RED_THREADS), 0, s, G, n, out);
+  return hipGetLastError();
+}
+hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, long long k, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_normalize, dim3(m), dim3(RED_THREADS), 0, s, Y, Z, nrm, k);
+  return hipGetLastError();
+}
+hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s) {
+  if (n > JAC_MAXN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
+  return hipGetLastError();
+}
+
+}  // namespace ttn

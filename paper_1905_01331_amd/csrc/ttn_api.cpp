@@ -1,0 +1,1118 @@
+// C ABI of the binary-TTN sweep: handle, workspace layout, the stages of the
+// sweep (ascend, descend, environment, update, top), and their schedule.
+//
+// The arithmetic of every stage runs in device kernels (gemm_*.hip,
+// small.hip, lanczos.hip); this file only decides shapes, strides and order.
+// Host-side arithmetic is limited to validating inputs and the one-off shift
+// constant (largest eigenvalue of the d^2 x d^2 bond term).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ttn.h"
+#include "common.h"
+#include "lanczos.h"
+
+using namespace ttn;
+
+namespace {
+
+thread_local std::string g_err;
+
+ttn_status fail(ttn_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(TTN_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// host: largest eigenvalue of a small symmetric matrix (cyclic Jacobi)
+// ---------------------------------------------------------------------------
+double host_lambda_max(std::vector<double> a, int n) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) (p == q ? diag : off) += a[p * n + q] * a[p * n + q];
+    if (off <= 1e-32 * (diag + off) || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = a[p * n + q];
+        if (apq == 0.0) continue;
+        double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          double xp = a[p * n + k], xq = a[q * n + k];
+          a[p * n + k] = c * xp - s * xq;
+          a[q * n + k] = s * xp + c * xq;
+        }
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          double xp = a[k * n + p], xq = a[k * n + q];
+          a[k * n + p] = c * xp - s * xq;
+          a[k * n + q] = s * xp + c * xq;
+        }
+      }
+  }
+  double mx = -INFINITY;
+  for (int i = 0; i < n; ++i) mx = std::max(mx, a[i * n + i]);
+  return mx;
+}
+
+// ---------------------------------------------------------------------------
+// workspace arena
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : reinterpret_cast<T*>(off + 256);
+    off += n * sizeof(T);
+    return p;
+  }
+  void* take_bytes(size_t n) { return take<char>(n); }
+};
+
+constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO_MAX = 4, SCAL_RATIO = 5,
+              SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10, SCAL_N = 16;
+constexpr int POLAR_REFRESH = 3;
+constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
+
+struct Member {
+  // configuration
+  int L = 0, n = 0, d = 0, D = 0, chi = 0, ly = 1, prec = TTN_FP64;
+  double c = 0.0;
+  unsigned long long seed = 0;
+  std::vector<int> dims;
+  std::vector<double> h1, A, B;
+  const double* const* w0 = nullptr;
+  const double* v0 = nullptr;
+  int krylov = 40, restarts = 6;
+  double ltol = 1e-13;
+  // device
+  size_t esz = 8;  // bulk element size
+  std::vector<double*> w64;
+  std::vector<void*> wT, opH, opA, opB, rho, Pc, At, Bt;
+  void *Rb[2] = {nullptr, nullptr}, *Lb[2] = {nullptr, nullptr};
+  int rb_cur = 0;
+  void *Sw = nullptr, *S2 = nullptr, *S3 = nullptr, *envT = nullptr;
+  double *env64 = nullptr, *Y = nullptr, *Y2 = nullptr, *G = nullptr, *V = nullptr, *Q = nullptr, *Q2 = nullptr,
+         *nrm = nullptr;
+  int* jinfo = nullptr;
+  double* vtop = nullptr;
+  void* vT = nullptr;
+  void* tmpT = nullptr;  // chi^2 bulk scratch for the top dressing
+  double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr;
+  double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
+  double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr;
+  int* lzint = nullptr;
+  double* scal = nullptr;
+  double* part = nullptr;
+  void* splitk = nullptr;
+  size_t splitk_bytes = 0;
+  // state of the sweep: rho^(l) is current for l >= rho_from, the cached
+  // rho^(l) o w_l for l >= pc_from
+  int rho_from = 1 << 20, pc_from = 1 << 20;
+  int dressed_tau = -1, env_tau = -1, ops_upto = 0;
+  int lz_iters = 0;
+  bool ortho_fail = false;
+
+  Prec gp() const { return prec == TTN_FP64 ? P_F64 : (prec == TTN_FP32 ? P_F32 : P_BF16X3); }
+  size_t el(size_t n_) const { return n_ * esz; }
+  void* at(void* base, size_t elems) const { return (char*)base + elems * esz; }
+  const void* at(const void* base, size_t elems) const { return (const char*)base + elems * esz; }
+};
+
+struct Ctx {
+  std::vector<Member> m;
+  hipStream_t s = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// configuration
+// ---------------------------------------------------------------------------
+ttn_status setup_member(const ttn_config& c, Member& M) {
+  if (c.L < 4 || (c.L & (c.L - 1))) return fail(TTN_EINVAL, "L=%d must be a power of two >= 4", c.L);
+  if (c.d < 2 || c.d > 64) return fail(TTN_EINVAL, "d=%d out of range [2, 64]", c.d);
+  if (c.chi < 1 || c.chi > 1024) return fail(TTN_EINVAL, "chi=%d out of range [1, 1024]", c.chi);
+  if (c.D < 0 || c.D > 64) return fail(TTN_EINVAL, "D=%d out of range [0, 64]", c.D);
+  if (!c.h1 || (c.D > 0 && (!c.A || !c.B))) return fail(TTN_EINVAL, "missing Hamiltonian arrays");
+  if (c.ly < 1) return fail(TTN_EINVAL, "ly=%d must be >= 1", c.ly);
+  if (c.precision < TTN_FP64 || c.precision > TTN_SPLIT_BF16) return fail(TTN_EINVAL, "unknown precision %d", c.precision);
+  M.L = c.L;
+  M.n = 0;
+  while ((1 << M.n) < c.L) ++M.n;
+  M.d = c.d;
+  M.D = c.D;
+  M.chi = c.chi;
+  M.ly = c.ly;
+  M.prec = c.precision;
+  M.seed = c.seed;
+  M.w0 = c.w0;
+  M.v0 = c.v0;
+  M.krylov = c.krylov > 0 ? c.krylov : 40;
+  M.restarts = c.restarts > 0 ? c.restarts : 6;
+  M.ltol = c.lanczos_tol > 0 ? c.lanczos_tol : 1e-13;
+  if (M.krylov > 256) return fail(TTN_EINVAL, "krylov=%d > 256", M.krylov);
+  const int d = c.d, D = c.D;
+  M.h1.assign(c.h1, c.h1 + d * d);
+  M.A.assign(D ? c.A : nullptr, D ? c.A + (size_t)D * d * d : nullptr);
+  M.B.assign(D ? c.B : nullptr, D ? c.B + (size_t)D * d * d : nullptr);
+  for (double x : M.h1) if (!std::isfinite(x)) return fail(TTN_ENONFINITE, "h1 has a non-finite entry");
+  for (double x : M.A) if (!std::isfinite(x)) return fail(TTN_ENONFINITE, "A has a non-finite entry");
+  for (double x : M.B) if (!std::isfinite(x)) return fail(TTN_ENONFINITE, "B has a non-finite entry");
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < i; ++j)
+      if (std::fabs(M.h1[i * d + j] - M.h1[j * d + i]) > 1e-12 * (1 + std::fabs(M.h1[i * d + j])))
+        return fail(TTN_EINVAL, "h1 is not symmetric");
+  for (int k = 0; k < D; ++k) {
+    const double* a = &M.A[(size_t)k * d * d];
+    const double* b = &M.B[(size_t)k * d * d];
+    bool a_sym = true, a_anti = true, b_sym = true, b_anti = true;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double tol = 1e-12 * (1 + std::fabs(a[i * d + j]));
+        if (std::fabs(a[i * d + j] - a[j * d + i]) > tol) a_sym = false;
+        if (std::fabs(a[i * d + j] + a[j * d + i]) > tol) a_anti = false;
+        double tolb = 1e-12 * (1 + std::fabs(b[i * d + j]));
+        if (std::fabs(b[i * d + j] - b[j * d + i]) > tolb) b_sym = false;
+        if (std::fabs(b[i * d + j] + b[j * d + i]) > tolb) b_anti = false;
+      }
+    if (!((a_sym && b_sym) || (a_anti && b_anti)))
+      return fail(TTN_EINVAL, "product term %d: A and B must be both symmetric or both antisymmetric", k);
+  }
+  M.dims.resize(M.n);
+  M.dims[0] = d;
+  for (int t = 1; t < M.n; ++t) M.dims[t] = (int)std::min<long long>((long long)M.dims[t - 1] * M.dims[t - 1], c.chi);
+  if (std::isnan(c.shift)) {
+    // bond term 1/2 (h1 x I + I x h1) + sum_k A_k x B_k
+    int dd = d * d;
+    std::vector<double> b((size_t)dd * dd, 0.0);
+    for (int i1 = 0; i1 < d; ++i1)
+      for (int i2 = 0; i2 < d; ++i2)
+        for (int j1 = 0; j1 < d; ++j1)
+          for (int j2 = 0; j2 < d; ++j2) {
+            double v = 0.0;
+            if (i2 == j2) v += 0.5 * M.h1[i1 * d + j1];
+            if (i1 == j1) v += 0.5 * M.h1[i2 * d + j2];
+            for (int k = 0; k < D; ++k) v += M.A[(size_t)k * d * d + i1 * d + j1] * M.B[(size_t)k * d * d + i2 * d + j2];
+            b[(size_t)(i1 * d + i2) * dd + (j1 * d + j2)] = v;
+          }
+    M.c = host_lambda_max(b, dd);
+  } else {
+    if (!std::isfinite(c.shift)) return fail(TTN_ENONFINITE, "shift is not finite");
+    M.c = c.shift;
+  }
+  M.esz = (M.prec == TTN_FP64) ? 8 : 4;
+  if (c.w0) {
+    for (int t = 1; t < M.n; ++t)
+      if (!c.w0[t - 1]) return fail(TTN_EINVAL, "w0[%d] is NULL", t - 1);
+  }
+  return TTN_OK;
+}
+
+void layout_member(Member& M, Arena& ar) {
+  const int n = M.n, D = M.D;
+  int cmax = 0;
+  size_t cube = 0;  // largest a*b*b
+  for (int t = 0; t < n; ++t) cmax = std::max(cmax, M.dims[t]);
+  for (int t = 1; t < n; ++t) cube = std::max(cube, (size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1]);
+  cube = std::max(cube, (size_t)(1 + 2 * D) * M.d * M.d);  // staging of the level-0 operators
+  const int x = M.dims[n - 1];
+  const size_t xx = (size_t)x * x;
+  M.w64.assign(n, nullptr);
+  M.wT.assign(n, nullptr);
+  for (int t = 1; t < n; ++t) {
+    size_t e = (size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1];
+    M.w64[t] = ar.take<double>(e);
+    M.wT[t] = (M.prec == TTN_FP64) ? (void*)M.w64[t] : ar.take_bytes(M.el(e));
+  }
+  M.opH.assign(n, nullptr);
+  M.opA.assign(n, nullptr);
+  M.opB.assign(n, nullptr);
+  M.rho.assign(n, nullptr);
+  M.Pc.assign(n, nullptr);
+  M.At.assign(n, nullptr);
+  M.Bt.assign(n, nullptr);
+  for (int t = 0; t < n; ++t) {
+    size_t q = (size_t)M.dims[t] * M.dims[t];
+    M.opH[t] = ar.take_bytes(M.el(q));
+    M.opA[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
+    M.opB[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
+    M.rho[t] = ar.take_bytes(M.el(q));
+    M.At[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
+    M.Bt[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
+    if (t >= 2) M.Pc[t] = ar.take_bytes(M.el((size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1]));
+  }
+  size_t cq = (size_t)cmax * cmax * std::max(D, 1);
+  for (int i = 0; i < 2; ++i) {
+    M.Rb[i] = ar.take_bytes(M.el(cq));
+    M.Lb[i] = ar.take_bytes(M.el(cq));
+  }
+  M.Sw = ar.take_bytes(M.el(cube));
+  M.S2 = ar.take_bytes(M.el(cube));
+  M.S3 = ar.take_bytes(M.el(cube));
+  M.envT = (M.prec == TTN_FP64) ? nullptr : ar.take_bytes(M.el(cube));
+  M.env64 = ar.take<double>(cube);
+  M.Y = ar.take<double>(cube);
+  M.Y2 = ar.take<double>(cube);
+  if (M.prec == TTN_FP64) M.envT = M.env64;
+  size_t c2 = (size_t)cmax * cmax;
+  M.G = ar.take<double>(c2);
+  M.V = ar.take<double>(c2);
+  M.Q = ar.take<double>(c2);
+  M.Q2 = ar.take<double>(c2);
+  M.nrm = ar.take<double>(cmax);
+  M.jinfo = ar.take<int>(64);
+  M.vtop = ar.take<double>(xx);
+  M.vT = (M.prec == TTN_FP64) ? (void*)M.vtop : ar.take_bytes(M.el(xx));
+  M.tmpT = ar.take_bytes(M.el(xx));
+  M.hop64 = ar.take<double>(xx);
+  M.Aop64 = ar.take<double>(xx * std::max(D, 1));
+  M.Bop64 = ar.take<double>(xx * std::max(D, 1));
+  int m = std::min<long long>(M.krylov, (long long)xx);
+  M.lzQ = ar.take<double>((size_t)(m + 1) * xx);
+  M.lzW = ar.take<double>(xx);
+  M.lzT = ar.take<double>(xx);
+  M.lzHv = ar.take<double>(xx);
+  M.lzR = ar.take<double>(xx);
+  M.alpha = ar.take<double>(m + 1);
+  M.beta = ar.take<double>(m + 1);
+  M.Tm = ar.take<double>((size_t)m * m);
+  M.Vm = ar.take<double>((size_t)m * m);
+  M.ycoef = ar.take<double>(m + 1);
+  M.coef = ar.take<double>(m + 1);
+  M.lzint = ar.take<int>(16);
+  M.scal = ar.take<double>(SCAL_N);
+  M.part = ar.take<double>(256);
+  // split-K partial sums: up to 64 slices of the largest output tile set
+  size_t out_max = std::max<size_t>(c2, xx);
+  M.splitk_bytes = 64 * out_max * 8;
+  M.splitk = ar.take_bytes(M.splitk_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// contraction helpers (element strides; bulk arithmetic of the member)
+// ---------------------------------------------------------------------------
+hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s) {
+  return gemm(p, g, M.splitk, M.splitk_bytes, s);
+}
+
+GemmDesc desc0() {
+  GemmDesc g;
+  std::memset(&g, 0, sizeof g);
+  g.batch = 1;
+  g.alpha = 1.0;
+  g.beta = 0.0;
+  return g;
+}
+
+// (O .r X)[a;l,r] = sum_r' O[r,r'] X[a;l,r']  -> Y
+hipError_t apply_r(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
+                   hipStream_t s) {
+  GemmDesc g = desc0();
+  g.M = a * b; g.N = b; g.K = b; g.K2 = 0;
+  g.A = X; g.sAm = b; g.sAk = 1;
+  g.B = O; g.sBk = 1; g.sBn = b;
+  g.C = Y; g.sCm = b; g.sCn = 1;
+  g.beta = beta;
+  return run(M, p, g, s);
+}
+// (O .l X)[a;l,r] = sum_l' O[l,l'] X[a;l',r]  -> Y   (batched over a)
+hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
+                   hipStream_t s) {
+  GemmDesc g = desc0();
+  g.batch = a;
+  g.M = b; g.N = b; g.K = b; g.K2 = 0;
+  g.A = O; g.sAm = b; g.sAk = 1; g.sAb = 0;
+  g.B = X; g.sBk = b; g.sBn = 1; g.sBb = (long long)b * b;
+  g.C = Y; g.sCm = b; g.sCn = 1; g.sCb = (long long)b * b;
+  g.beta = beta;
+  return run(M, p, g, s);
+}
+// C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b)
+hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                    double beta, hipStream_t s) {
+  GemmDesc g = desc0();
+  long long bb = (long long)b * b;
+  g.M = a; g.N = a; g.K = (int)bb; g.K2 = 0;
+  g.A = P; g.sAm = bb; g.sAk = 1;
+  g.B = Qm; g.sBk = 1; g.sBn = bb;
+  g.C = C; g.sCm = a; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s);
+}
+// (X o P)[a;l,r] = sum_a' X[a,a'] P[a';l,r]
+hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void* Y, int a, int b, double alpha,
+                    double beta, hipStream_t s) {
+  GemmDesc g = desc0();
+  long long bb = (long long)b * b;
+  g.M = a; g.N = (int)bb; g.K = a; g.K2 = 0;
+  g.A = X; g.sAm = a; g.sAk = 1;
+  g.B = P; g.sBk = bb; g.sBn = 1;
+  g.C = Y; g.sCm = bb; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s);
+}
+// C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']   (b x b, K = a*b)
+hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                   double beta, hipStream_t s) {
+  GemmDesc g = desc0();
+  g.M = b; g.N = b; g.K = a * b; g.K2 = 0;
+  g.A = P; g.sAm = 1; g.sAk = b;
+  g.B = Qm; g.sBk = b; g.sBn = 1;
+  g.C = C; g.sCm = b; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s);
+}
+// C_L(P,Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r]   (b x b, K = (a, r))
+hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                   double beta, hipStream_t s) {
+  GemmDesc g = desc0();
+  long long bb = (long long)b * b;
+  g.M = b; g.N = b; g.K = a * b; g.K2 = b;
+  g.A = P; g.sAm = b; g.sAk = 1; g.sAk1 = bb;
+  g.B = Qm; g.sBk = 1; g.sBk1 = bb; g.sBn = b;
+  g.C = C; g.sCm = b; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s);
+}
+// dense square products of order x: C = alpha op(A) op(B) + beta C
+hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, bool tb, void* C, int x, double alpha,
+              double beta, hipStream_t s) {
+  GemmDesc g = desc0();
+  g.M = x; g.N = x; g.K = x; g.K2 = 0;
+  g.A = Am; g.sAm = ta ? 1 : x; g.sAk = ta ? x : 1;
+  g.B = Bm; g.sBk = tb ? 1 : x; g.sBn = tb ? x : 1;
+  g.C = C; g.sCm = x; g.sCn = 1;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s);
+}
+
+// S w = h .l w + h .r w + sum_k A_k .l (B_k .r w)   (into M.Sw)
+hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, hipStream_t s) {
+  Prec p = M.gp();
+  size_t bb = (size_t)b * b;
+  hipError_t e;
+  if ((e = apply_l(M, p, M.opH[lvl_below], w, M.Sw, a, b, 0.0, s))) return e;
+  if ((e = apply_r(M, p, M.opH[lvl_below], w, M.Sw, a, b, 1.0, s))) return e;
+  for (int k = 0; k < M.D; ++k) {
+    if ((e = apply_r(M, p, M.at(M.opB[lvl_below], k * bb), w, M.S2, a, b, 0.0, s))) return e;
+    if ((e = apply_l(M, p, M.at(M.opA[lvl_below], k * bb), M.S2, M.Sw, a, b, 1.0, s))) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+ttn_status stage_ascend(Member& M, int tau, hipStream_t s) {
+  Prec p = M.gp();
+  const int a = M.dims[tau], b = M.dims[tau - 1];
+  const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+  const void* w = M.wT[tau];
+  HIPCHK(s_apply(M, tau - 1, w, a, b, s));
+  HIPCHK(close_aa(M, p, w, M.Sw, M.opH[tau], a, b, 1.0, 0.0, s));
+  for (int k = 0; k < M.D; ++k) {
+    HIPCHK(apply_r(M, p, M.at(M.opA[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
+    HIPCHK(close_aa(M, p, w, M.S2, M.at(M.opA[tau], k * aa), a, b, 1.0, 0.0, s));
+    HIPCHK(apply_l(M, p, M.at(M.opB[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
+    HIPCHK(close_aa(M, p, w, M.S2, M.at(M.opB[tau], k * aa), a, b, 1.0, 0.0, s));
+  }
+  return TTN_OK;
+}
+
+ttn_status stage_descend_rho(Member& M, hipStream_t s) {
+  Prec p = M.gp();
+  const int n = M.n, x = M.dims[n - 1];
+  // rho^(n-1) = 1/2 (v v^T + v^T v)
+  HIPCHK(mm(M, p, M.vT, false, M.vT, true, M.rho[n - 1], x, 0.5, 0.0, s));
+  HIPCHK(mm(M, p, M.vT, true, M.vT, false, M.rho[n - 1], x, 0.5, 1.0, s));
+  for (int lv = n - 1; lv >= 2; --lv) {
+    const int a = M.dims[lv], b = M.dims[lv - 1];
+    HIPCHK(left_mul(M, p, M.rho[lv], M.wT[lv], M.Pc[lv], a, b, 1.0, 0.0, s));
+    HIPCHK(close_l(M, p, M.wT[lv], M.Pc[lv], M.rho[lv - 1], a, b, 0.5, 0.0, s));
+    HIPCHK(close_r(M, p, M.wT[lv], M.Pc[lv], M.rho[lv - 1], a, b, 0.5, 1.0, s));
+  }
+  M.rho_from = 1;
+  M.pc_from = 2;
+  return TTN_OK;
+}
+
+ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
+  Prec p = M.gp();
+  const int n = M.n, D = M.D;
+  // carry A_k, B_k of level tau-1 up through layers tau..n-1
+  const void* prevA = M.opA[tau - 1];
+  const void* prevB = M.opB[tau - 1];
+  for (int sg = tau; sg < n; ++sg) {
+    const int a = M.dims[sg], b = M.dims[sg - 1];
+    const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+    const void* w = M.wT[sg];
+    for (int k = 0; k < D; ++k) {
+      HIPCHK(apply_r(M, p, M.at(prevA, k * bb), w, M.S2, a, b, 0.0, s));
+      HIPCHK(close_aa(M, p, w, M.S2, M.at(M.At[sg], k * aa), a, b, 1.0, 0.0, s));
+      HIPCHK(apply_l(M, p, M.at(prevB, k * bb), w, M.S2, a, b, 0.0, s));
+      HIPCHK(close_aa(M, p, w, M.S2, M.at(M.Bt[sg], k * aa), a, b, 1.0, 0.0, s));
+    }
+    prevA = M.At[sg];
+    prevB = M.Bt[sg];
+  }
+  // top dressing: Rbar = 1/2 (v^T A v + v A v^T), Lbar = 1/2 (v B v^T + v^T B v)
+  const int x = M.dims[n - 1];
+  const size_t xx = (size_t)x * x;
+  int cur = 0;
+  for (int k = 0; k < D; ++k) {
+    const void* Ak = M.at(M.At[n - 1], k * xx);
+    const void* Bk = M.at(M.Bt[n - 1], k * xx);
+    void* R = M.at(M.Rb[cur], k * xx);
+    void* Lq = M.at(M.Lb[cur], k * xx);
+    HIPCHK(mm(M, p, Ak, false, M.vT, false, M.tmpT, x, 1.0, 0.0, s));   // A v
+    HIPCHK(mm(M, p, M.vT, true, M.tmpT, false, R, x, 0.5, 0.0, s));     // v^T A v
+    HIPCHK(mm(M, p, Ak, false, M.vT, true, M.tmpT, x, 1.0, 0.0, s));    // A v^T
+    HIPCHK(mm(M, p, M.vT, false, M.tmpT, false, R, x, 0.5, 1.0, s));    // v A v^T
+    HIPCHK(mm(M, p, Bk, false, M.vT, true, M.tmpT, x, 1.0, 0.0, s));    // B v^T
+    HIPCHK(mm(M, p, M.vT, false, M.tmpT, false, Lq, x, 0.5, 0.0, s));   // v B v^T
+    HIPCHK(mm(M, p, Bk, false, M.vT, false, M.tmpT, x, 1.0, 0.0, s));   // B v
+    HIPCHK(mm(M, p, M.vT, true, M.tmpT, false, Lq, x, 0.5, 1.0, s));    // v^T B v
+  }
+  // descend through layers n-1 .. tau+1
+  for (int sg = n - 1; sg >= tau + 1; --sg) {
+    const int a = M.dims[sg], b = M.dims[sg - 1];
+    const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+    const void* w = M.wT[sg];
+    const void* P = M.Pc[sg];
+    const int nx = 1 - cur;
+    for (int k = 0; k < D; ++k) {
+      void* Rn = M.at(M.Rb[nx], k * bb);
+      void* Ln = M.at(M.Lb[nx], k * bb);
+      // inside a parent (A left child, B right child) + across parents
+      HIPCHK(apply_l(M, p, M.at(M.At[sg - 1], k * bb), w, M.S2, a, b, 0.0, s));
+      HIPCHK(close_r(M, p, P, M.S2, Rn, a, b, 0.5, 0.0, s));
+      HIPCHK(left_mul(M, p, M.at(M.Rb[cur], k * aa), w, M.S3, a, b, 1.0, 0.0, s));
+      HIPCHK(close_l(M, p, w, M.S3, Rn, a, b, 0.5, 1.0, s));
+      HIPCHK(apply_r(M, p, M.at(M.Bt[sg - 1], k * bb), w, M.S2, a, b, 0.0, s));
+      HIPCHK(close_l(M, p, P, M.S2, Ln, a, b, 0.5, 0.0, s));
+      HIPCHK(left_mul(M, p, M.at(M.Lb[cur], k * aa), w, M.S3, a, b, 1.0, 0.0, s));
+      HIPCHK(close_r(M, p, w, M.S3, Ln, a, b, 0.5, 1.0, s));
+    }
+    cur = nx;
+  }
+  M.rb_cur = cur;
+  M.dressed_tau = tau;
+  return TTN_OK;
+}
+
+ttn_status stage_env(Member& M, int tau, hipStream_t s) {
+  Prec p = M.gp();
+  const int a = M.dims[tau], b = M.dims[tau - 1];
+  const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+  const void* w = M.wT[tau];
+  HIPCHK(s_apply(M, tau - 1, w, a, b, s));
+  HIPCHK(left_mul(M, p, M.rho[tau], M.Sw, M.envT, a, b, 1.0, 0.0, s));
+  for (int k = 0; k < M.D; ++k) {
+    HIPCHK(apply_l(M, p, M.at(M.opB[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
+    HIPCHK(left_mul(M, p, M.at(M.Rb[M.rb_cur], k * aa), M.S2, M.envT, a, b, 1.0, 1.0, s));
+    HIPCHK(apply_r(M, p, M.at(M.opA[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
+    HIPCHK(left_mul(M, p, M.at(M.Lb[M.rb_cur], k * aa), M.S2, M.envT, a, b, 1.0, 1.0, s));
+  }
+  if (M.prec != TTN_FP64) HIPCHK(convert_f32_to_f64((const float*)M.envT, M.env64, (size_t)a * bb, s));
+  M.env_tau = tau;
+  return TTN_OK;
+}
+
+// out = sign * polar(src) for src (a x K), float64: Gram -> Jacobi eigenvectors
+// -> rotate, repeated; rows of the rotated matrix end up mutually orthogonal
+// with relative accuracy, then normalised and rotated back.
+ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s) {
+  const size_t aK = (size_t)a * K;
+  HIPCHK(copy_bytes(M.Y, src, aK * 8, s));
+  double* Yc = M.Y;
+  double* Yn = M.Y2;
+  double* Qc = M.Q;
+  double* Qn = M.Q2;
+  for (int it = 0; it < POLAR_REFRESH; ++it) {
+    GemmDesc g = desc0();  // G = Y Y^T
+    g.M = a; g.N = a; g.K = (int)K;
+    g.A = Yc; g.sAm = K; g.sAk = 1;
+    g.B = Yc; g.sBk = 1; g.sBn = K;
+    g.C = M.G; g.sCm = a; g.sCn = 1;
+    HIPCHK(run(M, P_F64, g, s));
+    HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, 1e-15, M.jinfo + 2 * it, s));
+    GemmDesc r = desc0();  // Yn = V^T Y
+    r.M = a; r.N = (int)K; r.K = a;
+    r.A = M.V; r.sAm = 1; r.sAk = a;
+    r.B = Yc; r.sBk = K; r.sBn = 1;
+    r.C = Yn; r.sCm = K; r.sCn = 1;
+    HIPCHK(run(M, P_F64, r, s));
+    if (it == 0) {
+      HIPCHK(copy_bytes(Qc, M.V, (size_t)a * a * 8, s));
+    } else {
+      HIPCHK(mm(M, P_F64, Qc, false, M.V, false, Qn, a, 1.0, 0.0, s));
+      std::swap(Qc, Qn);
+    }
+    std::swap(Yc, Yn);
+  }
+  HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
+  GemmDesc f = desc0();  // out = sign * Q Z
+  f.M = a; f.N = (int)K; f.K = a;
+  f.A = Qc; f.sAm = a; f.sAk = 1;
+  f.B = Yn; f.sBk = K; f.sBn = 1;
+  f.C = out; f.sCm = K; f.sCn = 1;
+  f.alpha = sign;
+  HIPCHK(run(M, P_F64, f, s));
+  return TTN_OK;
+}
+
+ttn_status refresh_shadow(Member& M, int tau, hipStream_t s) {
+  if (M.prec == TTN_FP64) return TTN_OK;
+  size_t e = (size_t)M.dims[tau] * M.dims[tau - 1] * M.dims[tau - 1];
+  HIPCHK(convert_f64_to_f32(M.w64[tau], (float*)M.wT[tau], e, s));
+  return TTN_OK;
+}
+
+ttn_status ortho_check(Member& M, int tau, hipStream_t s) {
+  const int a = M.dims[tau];
+  const long long K = (long long)M.dims[tau - 1] * M.dims[tau - 1];
+  GemmDesc g = desc0();
+  g.M = a; g.N = a; g.K = (int)K;
+  g.A = M.w64[tau]; g.sAm = K; g.sAk = 1;
+  g.B = M.w64[tau]; g.sBk = 1; g.sBn = K;
+  g.C = M.G; g.sCm = a; g.sCn = 1;
+  HIPCHK(run(M, P_F64, g, s));
+  HIPCHK(ortho_err_from_gram(M.G, a, M.scal + SCAL_ORTHO, s));
+  HIPCHK(running_max(M.scal + SCAL_ORTHO, M.scal + SCAL_ORTHO_MAX, s));
+  return TTN_OK;
+}
+
+ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
+  const int a = M.dims[tau], b = M.dims[tau - 1];
+  const long long K = (long long)b * b;
+  const size_t aK = (size_t)a * K;
+  // Env' = Env - eps ||Env|| w_old: a tie-breaker in directions where Env is
+  // numerically zero; invisible elsewhere at float64 resolution.
+  HIPCHK(pair_f64(M.env64, M.env64, (long long)aK, M.scal + SCAL_TMP0, M.part, s));
+  HIPCHK(sqrt_inplace(M.scal + SCAL_TMP0, s));
+  HIPCHK(copy_bytes(M.Y2, M.env64, aK * 8, s));
+  HIPCHK(axpy_dev(M.Y2, M.w64[tau], M.scal + SCAL_TMP0, -POLAR_REG, aK, s));
+  // polar_core copies its source into M.Y first, so passing M.Y2 is safe
+  ttn_status st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s);
+  if (st) return st;
+  HIPCHK(ratio_minmax(M.nrm, a, M.scal + SCAL_RATIO, M.scal + SCAL_RATIO_MIN, s));
+  if ((st = ortho_check(M, tau, s))) return st;
+  if ((st = refresh_shadow(M, tau, s))) return st;
+  M.env_tau = -1;
+  M.dressed_tau = -1;
+  M.ops_upto = std::min(M.ops_upto, tau - 1);
+  M.rho_from = std::max(M.rho_from, tau);
+  M.pc_from = std::max(M.pc_from, tau + 1);
+  return TTN_OK;
+}
+
+// H_top y for the two sites of level n-1 (float64 copies of the operators)
+hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s) {
+  const int x = M.dims[M.n - 1];
+  const size_t xx = (size_t)x * x;
+  hipError_t e;
+  if ((e = mm(M, P_F64, M.hop64, false, y, false, out, x, 1.0, 0.0, s))) return e;   // h v
+  if ((e = mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s))) return e;    // v h^T
+  for (int k = 0; k < M.D; ++k) {
+    const double* Ak = M.Aop64 + k * xx;
+    const double* Bk = M.Bop64 + k * xx;
+    if ((e = mm(M, P_F64, y, false, Bk, true, M.lzT, x, 1.0, 0.0, s))) return e;    // v B^T
+    if ((e = mm(M, P_F64, Ak, false, M.lzT, false, out, x, 1.0, 1.0, s))) return e;  // A v B^T
+    if ((e = mm(M, P_F64, y, false, Ak, true, M.lzT, x, 1.0, 0.0, s))) return e;    // v A^T
+    if ((e = mm(M, P_F64, Bk, false, M.lzT, false, out, x, 1.0, 1.0, s))) return e;  // B v A^T
+  }
+  return hipSuccess;
+}
+
+ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
+  const int n = M.n, x = M.dims[n - 1], D = M.D;
+  const size_t xx = (size_t)x * x;
+  if (M.prec == TTN_FP64) {
+    HIPCHK(copy_bytes(M.hop64, M.opH[n - 1], xx * 8, s));
+    if (D) {
+      HIPCHK(copy_bytes(M.Aop64, M.opA[n - 1], D * xx * 8, s));
+      HIPCHK(copy_bytes(M.Bop64, M.opB[n - 1], D * xx * 8, s));
+    }
+  } else {
+    HIPCHK(convert_f32_to_f64((const float*)M.opH[n - 1], M.hop64, xx, s));
+    if (D) {
+      HIPCHK(convert_f32_to_f64((const float*)M.opA[n - 1], M.Aop64, D * xx, s));
+      HIPCHK(convert_f32_to_f64((const float*)M.opB[n - 1], M.Bop64, D * xx, s));
+    }
+  }
+  const int m = (int)std::min<long long>(M.krylov, (long long)xx);
+  int iters = 0;
+  *converged = false;
+  for (int rs = 0; rs < M.restarts; ++rs) {
+    // q_0 = v / ||v||
+    HIPCHK(pair_f64(M.vtop, M.vtop, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
+    HIPCHK(scale_rsqrt(M.vtop, M.scal + SCAL_TMP0, xx, s));
+    HIPCHK(copy_bytes(M.lzQ, M.vtop, xx * 8, s));
+    HIPCHK(zero_int(M.lzint, 16, s));
+    for (int j = 0; j < m; ++j) {
+      double* qj = M.lzQ + (size_t)j * xx;
+      const double* qjm1 = j ? M.lzQ + (size_t)(j - 1) * xx : qj;
+      HIPCHK(top_matvec(M, qj, M.lzW, s));
+      HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP1, M.part, s));
+      HIPCHK(pair_f64(qj, M.lzW, (long long)xx, M.alpha + j, M.part, s));
+      HIPCHK(lz_three_term(M.lzW, qj, qjm1, M.alpha, M.beta, j, xx, M.lzint, s));
+      for (int pass = 0; pass < 2; ++pass) {  // full reorthogonalisation
+        GemmDesc g = desc0();  // coef = Q[0..j] w
+        g.M = j + 1; g.N = 1; g.K = (int)xx;
+        g.A = M.lzQ; g.sAm = (long long)xx; g.sAk = 1;
+        g.B = M.lzW; g.sBk = 1; g.sBn = 1;
+        g.C = M.coef; g.sCm = 1; g.sCn = 1;
+        HIPCHK(run(M, P_F64, g, s));
+        GemmDesc h = desc0();  // w -= Q[0..j]^T coef
+        h.M = 1; h.N = (int)xx; h.K = j + 1;
+        h.A = M.coef; h.sAm = 0; h.sAk = 1;
+        h.B = M.lzQ; h.sBk = (long long)xx; h.sBn = 1;
+        h.C = M.lzW; h.sCm = 0; h.sCn = 1;
+        h.alpha = -1.0; h.beta = 1.0;
+        HIPCHK(run(M, P_F64, h, s));
+      }
+      HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
+      HIPCHK(lz_set_beta(M.scal + SCAL_TMP0, M.scal + SCAL_TMP1, M.beta, j, 1e-12, M.lzint, M.lzint + 1, s));
+      HIPCHK(lz_next_q(M.lzW, M.lzQ + (size_t)(j + 1) * xx, M.beta, j, xx, M.lzint, s));
+    }
+    iters += m;
+    HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
+    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, 1e-15, M.jinfo + 16, s));
+    HIPCHK(lz_select_lowest(M.Tm, M.Vm, m, M.ycoef, M.scal + SCAL_THETA, s));
+    GemmDesc g = desc0();  // v = Q[0..m-1]^T y
+    g.M = 1; g.N = (int)xx; g.K = m;
+    g.A = M.ycoef; g.sAm = 0; g.sAk = 1;
+    g.B = M.lzQ; g.sBk = (long long)xx; g.sBn = 1;
+    g.C = M.vtop; g.sCm = 0; g.sCn = 1;
+    HIPCHK(run(M, P_F64, g, s));
+    HIPCHK(pair_f64(M.vtop, M.vtop, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
+    HIPCHK(scale_rsqrt(M.vtop, M.scal + SCAL_TMP0, xx, s));
+    HIPCHK(top_matvec(M, M.vtop, M.lzHv, s));
+    HIPCHK(pair_f64(M.vtop, M.lzHv, (long long)xx, M.scal + SCAL_LAM, M.part, s));
+    HIPCHK(residual_vec(M.lzHv, M.vtop, M.scal + SCAL_LAM, M.lzR, xx, s));
+    HIPCHK(pair_f64(M.lzR, M.lzR, (long long)xx, M.scal + SCAL_RES, M.part, s));
+    HIPCHK(sqrt_inplace(M.scal + SCAL_RES, s));
+    double hs[3];
+    HIPCHK(hipMemcpyAsync(hs, M.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hs[SCAL_RES] <= M.ltol * std::max(1.0, std::fabs(hs[SCAL_LAM]))) {
+      *converged = true;
+      break;
+    }
+  }
+  HIPCHK(sign_fix(M.vtop, xx, s));
+  HIPCHK(energy_store(M.scal + SCAL_LAM, M.c, (double)M.L, (double)M.ly, M.scal + SCAL_LAM, s));
+  if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, xx, s));
+  M.lz_iters = iters;
+  M.rho_from = M.pc_from = 1 << 20;
+  return TTN_OK;
+}
+
+ttn_status init_member(Member& M, hipStream_t s, bool* conv) {
+  const int n = M.n, d = M.d, D = M.D;
+  const size_t dd = (size_t)d * d;
+  // level-0 operators (host -> device through a float64 staging area)
+  std::vector<double> h0 = M.h1;
+  for (int i = 0; i < d; ++i) h0[i * d + i] -= M.c;
+  double* stage = M.env64;  // scratch
+  HIPCHK(hipMemcpyAsync(stage, h0.data(), dd * 8, hipMemcpyHostToDevice, s));
+  if (D) {
+    HIPCHK(hipMemcpyAsync(stage + dd, M.A.data(), D * dd * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(stage + (1 + D) * dd, M.B.data(), D * dd * 8, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  if (M.prec == TTN_FP64) {
+    HIPCHK(copy_bytes(M.opH[0], stage, dd * 8, s));
+    if (D) {
+      HIPCHK(copy_bytes(M.opA[0], stage + dd, D * dd * 8, s));
+      HIPCHK(copy_bytes(M.opB[0], stage + (1 + D) * dd, D * dd * 8, s));
+    }
+  } else {
+    HIPCHK(convert_f64_to_f32(stage, (float*)M.opH[0], dd, s));
+    if (D) {
+      HIPCHK(convert_f64_to_f32(stage + dd, (float*)M.opA[0], D * dd, s));
+      HIPCHK(convert_f64_to_f32(stage + (1 + D) * dd, (float*)M.opB[0], D * dd, s));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  // isometries
+  for (int t = 1; t < n; ++t) {
+    const int a = M.dims[t], b = M.dims[t - 1];
+    const size_t e = (size_t)a * b * b;
+    if (M.w0) {
+      HIPCHK(hipMemcpyAsync(M.w64[t], M.w0[t - 1], e * 8, hipMemcpyHostToDevice, s));
+    } else {
+      HIPCHK(gaussian_f64(M.env64, e, M.seed, (unsigned long long)t, s));
+      ttn_status st = polar_core(M, M.env64, a, (long long)b * b, 1.0, M.w64[t], s);
+      if (st) return st;
+    }
+    ttn_status st = refresh_shadow(M, t, s);
+    if (st) return st;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  // scalars
+  double init_scal[SCAL_N] = {0};
+  init_scal[SCAL_RATIO_MIN] = 1.0;
+  HIPCHK(hipMemcpyAsync(M.scal, init_scal, sizeof init_scal, hipMemcpyHostToDevice, s));
+  // top start vector
+  const int x = M.dims[n - 1];
+  const size_t xx = (size_t)x * x;
+  if (M.v0) {
+    HIPCHK(hipMemcpyAsync(M.vtop, M.v0, xx * 8, hipMemcpyHostToDevice, s));
+  } else {
+    HIPCHK(gaussian_f64(M.vtop, xx, M.seed ^ 0x5bd1e995ull, 0xfffffffull, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  for (int t = 1; t < n; ++t) {
+    ttn_status st = stage_ascend(M, t, s);
+    if (st) return st;
+  }
+  M.ops_upto = n - 1;
+  ttn_status st = stage_update_top(M, s, conv);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  return TTN_OK;
+}
+
+void layer_flops(const Member& M, double* bulk, double* f64) {
+  const int n = M.n, D = M.D;
+  auto asc = [&](int t) { double a = M.dims[t], b = M.dims[t - 1]; return 2 * a * b * b * b + 2 * a * a * b * b; };
+  double F = 0, G = 0;
+  for (int t = 1; t < n; ++t) {
+    double a = M.dims[t], b = M.dims[t - 1];
+    double env = (4 + 8.0 * D) * a * b * b * b + (2 + 4.0 * D) * a * a * b * b;
+    double reasc = (4 + 4.0 * D) * a * b * b * b + 2 * a * a * b * b + 2.0 * D * asc(t);
+    double chain = 0;
+    for (int sg = t; sg < n; ++sg) chain += 2.0 * D * asc(sg);
+    double desc = 0;
+    for (int sg = t + 1; sg < n; ++sg) {
+      double aa = M.dims[sg], bb = M.dims[sg - 1];
+      desc += D * (12 * aa * bb * bb * bb + 4 * aa * aa * bb * bb);
+    }
+    F += env + reasc + chain + desc;
+    // float64: polar (POLAR_REFRESH Gram + rotate, final product) + orthonormality Gram
+    G += (POLAR_REFRESH * 4.0 + 2.0 + 2.0) * a * a * b * b;
+  }
+  for (int sg = 2; sg < n; ++sg) {
+    double a = M.dims[sg], b = M.dims[sg - 1];
+    F += 2 * a * a * b * b + 4 * a * b * b * b;
+  }
+  *bulk = F;
+  *f64 = G;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+struct ttn_ctx {
+  Ctx c;
+};
+
+extern "C" {
+
+const char* ttn_last_error(void) { return g_err.c_str(); }
+
+ttn_status ttn_workspace_bytes(const ttn_config* cfgs, int batch, size_t* bytes) {
+  if (!cfgs || batch < 1 || !bytes) return fail(TTN_EINVAL, "bad arguments");
+  Arena ar;
+  for (int i = 0; i < batch; ++i) {
+    Member M;
+    ttn_status st = setup_member(cfgs[i], M);
+    if (st) return st;
+    layout_member(M, ar);
+  }
+  *bytes = ar.off + 256;
+  return TTN_OK;
+}
+
+ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t bytes, void* stream, ttn_handle* out) {
+  if (!cfgs || batch < 1 || !out) return fail(TTN_EINVAL, "bad arguments");
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(TTN_EINVAL, "workspace must be non-null and 256-byte aligned");
+  size_t need = 0;
+  ttn_status st = ttn_workspace_bytes(cfgs, batch, &need);
+  if (st) return st;
+  if (bytes < need) return fail(TTN_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, need);
+  ttn_ctx* h = new ttn_ctx;
+  h->c.s = (hipStream_t)stream;
+  h->c.m.resize(batch);
+  Arena ar;
+  ar.base = (char*)workspace;
+  bool any_noconv = false;
+  for (int i = 0; i < batch; ++i) {
+    Member& M = h->c.m[i];
+    setup_member(cfgs[i], M);
+    layout_member(M, ar);
+  }
+  for (int i = 0; i < batch; ++i) {
+    bool conv = false;
+    st = init_member(h->c.m[i], h->c.s, &conv);
+    if (st) {
+      delete h;
+      return st;
+    }
+    any_noconv |= !conv;
+    h->c.m[i].w0 = nullptr;
+    h->c.m[i].v0 = nullptr;
+  }
+  *out = h;
+  return any_noconv ? TTN_WNOCONV : TTN_OK;
+}
+
+ttn_status ttn_free(ttn_handle h) {
+  delete h;
+  return TTN_OK;
+}
+
+ttn_status ttn_ascend(ttn_handle h, int tau_from, int tau_to) {
+  if (!h) return fail(TTN_EINVAL, "null handle");
+  for (auto& M : h->c.m) {
+    if (tau_from < 1 || tau_to > M.n - 1 || tau_from > tau_to)
+      return fail(TTN_EINVAL, "ascend range [%d, %d] outside [1, %d]", tau_from, tau_to, M.n - 1);
+    if (M.ops_upto < tau_from - 1) return fail(TTN_ESTATE, "level %d operators are stale; ascend from a lower layer", tau_from - 1);
+  }
+  for (auto& M : h->c.m) {
+    for (int t = tau_from; t <= tau_to; ++t) {
+      ttn_status st = stage_ascend(M, t, h->c.s);
+      if (st) return st;
+    }
+    M.ops_upto = std::max(M.ops_upto, tau_to);
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_descend(ttn_handle h, int what, int tau) {
+  if (!h) return fail(TTN_EINVAL, "null handle");
+  if (what == TTN_DESCEND_RHO) {
+    for (auto& M : h->c.m) {
+      ttn_status st = stage_descend_rho(M, h->c.s);
+      if (st) return st;
+    }
+    return TTN_OK;
+  }
+  if (what != TTN_DESCEND_DRESSED) return fail(TTN_EINVAL, "unknown descend kind %d", what);
+  for (auto& M : h->c.m) {
+    if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
+    if (M.rho_from > tau || M.pc_from > tau + 1)
+      return fail(TTN_ESTATE, "descend(DRESSED, %d) needs descend(RHO) after the last change of v or of a layer above %d", tau, tau);
+    if (M.ops_upto < tau - 1) return fail(TTN_ESTATE, "level %d operators are stale", tau - 1);
+  }
+  for (auto& M : h->c.m) {
+    ttn_status st = stage_descend_dressed(M, tau, h->c.s);
+    if (st) return st;
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_env(ttn_handle h, int tau) {
+  if (!h) return fail(TTN_EINVAL, "null handle");
+  for (auto& M : h->c.m) {
+    if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
+    if (M.dressed_tau != tau) return fail(TTN_ESTATE, "env(%d) needs descend(DRESSED, %d) first", tau, tau);
+  }
+  for (auto& M : h->c.m) {
+    ttn_status st = stage_env(M, tau, h->c.s);
+    if (st) return st;
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_update(ttn_handle h, int tau) {
+  if (!h) return fail(TTN_EINVAL, "null handle");
+  if (tau == TTN_TOP) {
+    for (auto& M : h->c.m)
+      if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "top update needs every layer ascended (ops up to %d of %d)", M.ops_upto, M.n - 1);
+    bool all = true;
+    for (auto& M : h->c.m) {
+      bool conv = false;
+      ttn_status st = stage_update_top(M, h->c.s, &conv);
+      if (st) return st;
+      all &= conv;
+    }
+    return all ? TTN_OK : TTN_WNOCONV;
+  }
+  for (auto& M : h->c.m) {
+    if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
+    if (M.env_tau != tau) return fail(TTN_ESTATE, "update(%d) needs env(%d) first", tau, tau);
+  }
+  for (auto& M : h->c.m) {
+    ttn_status st = stage_update_layer(M, tau, h->c.s);
+    if (st) return st;
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_energy(ttn_handle h, double* e) {
+  if (!h || !e) return fail(TTN_EINVAL, "bad arguments");
+  HIPCHK(hipStreamSynchronize(h->c.s));
+  bool bad = false;
+  for (size_t i = 0; i < h->c.m.size(); ++i) {
+    double sc[SCAL_N];
+    HIPCHK(hipMemcpy(sc, h->c.m[i].scal, sizeof sc, hipMemcpyDeviceToHost));
+    e[i] = sc[SCAL_E];
+    if (!(sc[SCAL_ORTHO_MAX] <= 1e-10)) bad = true;
+  }
+  if (bad) return fail(TTN_EORTHO, "an updated isometry failed the orthonormality check");
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep(ttn_handle h, int nsweeps) {
+  if (!h || nsweeps < 0) return fail(TTN_EINVAL, "bad arguments");
+  ttn_status warn = TTN_OK;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (auto& M : h->c.m) {
+      hipStream_t s = h->c.s;
+      ttn_status st;
+      if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "sweep needs every layer ascended");
+      if ((st = stage_descend_rho(M, s))) return st;
+      for (int t = 1; t < M.n; ++t) {
+        if ((st = stage_descend_dressed(M, t, s))) return st;
+        if ((st = stage_env(M, t, s))) return st;
+        if ((st = stage_update_layer(M, t, s))) return st;
+        if ((st = stage_ascend(M, t, s))) return st;
+        M.ops_upto = std::max(M.ops_upto, t);
+      }
+      bool conv = false;
+      if ((st = stage_update_top(M, s, &conv))) return st;
+      if (!conv) warn = TTN_WNOCONV;
+    }
+  }
+  return warn;
+}
+
+ttn_status ttn_get_tensor(ttn_handle h, int b, int tau, double* host) {
+  if (!h || !host || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  Member& M = h->c.m[b];
+  size_t e;
+  const double* src;
+  if (tau == TTN_TOP) {
+    e = (size_t)M.dims[M.n - 1] * M.dims[M.n - 1];
+    src = M.vtop;
+  } else {
+    if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
+    e = (size_t)M.dims[tau] * M.dims[tau - 1] * M.dims[tau - 1];
+    src = M.w64[tau];
+  }
+  HIPCHK(hipStreamSynchronize(h->c.s));
+  HIPCHK(hipMemcpy(host, src, e * 8, hipMemcpyDeviceToHost));
+  return TTN_OK;
+}
+
+ttn_status ttn_set_tensor(ttn_handle h, int b, int tau, const double* host) {
+  if (!h || !host || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  Member& M = h->c.m[b];
+  hipStream_t s = h->c.s;
+  if (tau == TTN_TOP) {
+    size_t e = (size_t)M.dims[M.n - 1] * M.dims[M.n - 1];
+    for (size_t i = 0; i < e; ++i) if (!std::isfinite(host[i])) return fail(TTN_ENONFINITE, "v has a non-finite entry");
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(M.vtop, host, e * 8, hipMemcpyHostToDevice));
+    if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, e, s));
+    M.rho_from = M.pc_from = 1 << 20;
+    M.dressed_tau = -1;
+    M.env_tau = -1;
+    return TTN_OK;
+  }
+  if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
+  size_t e = (size_t)M.dims[tau] * M.dims[tau - 1] * M.dims[tau - 1];
+  for (size_t i = 0; i < e; ++i) if (!std::isfinite(host[i])) return fail(TTN_ENONFINITE, "w has a non-finite entry");
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(M.w64[tau], host, e * 8, hipMemcpyHostToDevice));
+  ttn_status st = refresh_shadow(M, tau, s);
+  if (st) return st;
+  M.ops_upto = std::min(M.ops_upto, tau - 1);
+  M.rho_from = std::max(M.rho_from, tau);
+  M.pc_from = std::max(M.pc_from, tau + 1);
+  M.dressed_tau = -1;
+  M.env_tau = -1;
+  return TTN_OK;
+}
+
+ttn_status ttn_get_operator(ttn_handle h, int b, int level, int kind, int k, double* host) {
+  if (!h || !host || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  Member& M = h->c.m[b];
+  if (level < 0 || level > M.n - 1) return fail(TTN_EINVAL, "level=%d outside [0, %d]", level, M.n - 1);
+  if ((kind == TTN_OP_A || kind == TTN_OP_B || kind == TTN_OP_RBAR || kind == TTN_OP_LBAR) && (k < 0 || k >= M.D))
+    return fail(TTN_EINVAL, "k=%d outside [0, %d)", k, M.D);
+  const size_t q = (size_t)M.dims[level] * M.dims[level];
+  const void* src = nullptr;
+  size_t e = q;
+  switch (kind) {
+    case TTN_OP_H: src = M.opH[level]; break;
+    case TTN_OP_A: src = M.at(M.opA[level], k * q); break;
+    case TTN_OP_B: src = M.at(M.opB[level], k * q); break;
+    case TTN_OP_RHO: src = M.rho[level]; break;
+    case TTN_OP_RBAR:
+      if (M.dressed_tau != level) return fail(TTN_ESTATE, "no dressed RDM at level %d", level);
+      src = M.at(M.Rb[M.rb_cur], k * q);
+      break;
+    case TTN_OP_LBAR:
+      if (M.dressed_tau != level) return fail(TTN_ESTATE, "no dressed RDM at level %d", level);
+      src = M.at(M.Lb[M.rb_cur], k * q);
+      break;
+    case TTN_OP_ENV:
+      if (M.env_tau != level || level < 1) return fail(TTN_ESTATE, "no environment of layer %d", level);
+      e = (size_t)M.dims[level] * M.dims[level - 1] * M.dims[level - 1];
+      HIPCHK(hipStreamSynchronize(h->c.s));
+      HIPCHK(hipMemcpy(host, M.env64, e * 8, hipMemcpyDeviceToHost));
+      return TTN_OK;
+    default: return fail(TTN_EINVAL, "unknown operator kind %d", kind);
+  }
+  HIPCHK(hipStreamSynchronize(h->c.s));
+  if (M.esz == 8) {
+    HIPCHK(hipMemcpy(host, src, e * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(e);
+    HIPCHK(hipMemcpy(tmp.data(), src, e * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < e; ++i) host[i] = tmp[i];
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out) {
+  if (!h || !out || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  Member& M = h->c.m[b];
+  HIPCHK(hipStreamSynchronize(h->c.s));
+  double sc[SCAL_N];
+  HIPCHK(hipMemcpy(sc, M.scal, sizeof sc, hipMemcpyDeviceToHost));
+  out->energy = sc[SCAL_E];
+  out->lambda = sc[SCAL_LAM];
+  out->lanczos_resid = sc[SCAL_RES];
+  out->ortho_err_max = sc[SCAL_ORTHO_MAX];
+  out->sigma_ratio_min = sc[SCAL_RATIO_MIN];
+  out->shift = M.c;
+  layer_flops(M, &out->flops_bulk, &out->flops_fp64);
+  out->n_levels = M.n;
+  out->lanczos_iters = M.lz_iters;
+  return TTN_OK;
+}
+
+int ttn_bond_dim(ttn_handle h, int b, int tau) {
+  if (!h || b < 0 || b >= (int)h->c.m.size()) return -1;
+  Member& M = h->c.m[b];
+  if (tau < 0 || tau >= M.n) return -1;
+  return M.dims[tau];
+}
+
+}  // extern "C"

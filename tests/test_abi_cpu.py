@@ -1,0 +1,83 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and the host-side validation rejects bad configurations
+without touching a GPU (ttn_workspace_bytes runs on the host only)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1905_01331_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "ttn.h")).read()
+    return sorted(set(re.findall(r"\b(ttn_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1905_01331_amd import build
+        build.build()
+    return binding.load_library()
+
+
+def test_header_and_binding_agree():
+    assert header_symbols() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_symbol(lib):
+    for name in header_symbols():
+        assert hasattr(lib, name), name
+
+
+def _bytes(model, L, chi, **kw):
+    return binding.ttn_workspace_bytes([binding.ChainInput(model, L, chi, **kw)])
+
+
+def test_workspace_sizes(lib):
+    small = _bytes(inputs.tfim_chain(1.0), 16, 8)
+    big = _bytes(inputs.tfim_chain(1.0), 1024, 64)
+    assert 0 < small < big
+    # the chi = 256 chain of 4096 sites keeps its tensors well inside one GPU
+    assert _bytes(inputs.xxx_chain(), 4096, 256, precision="bf16x3") < 16 * 2 ** 30
+
+
+@pytest.mark.parametrize("L", [3, 6, 2, 0])
+def test_rejects_bad_length(lib, L):
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(inputs.tfim_chain(1.0), L, 8)
+    assert e.value.status == binding.TTN_EINVAL
+
+
+def test_rejects_nonfinite_and_asymmetric(lib):
+    m = inputs.tfim_chain(1.0)
+    m.h1 = m.h1.copy()
+    m.h1[0, 0] = math.nan
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(m, 16, 8)
+    assert e.value.status == binding.TTN_ENONFINITE
+    m = inputs.tfim_chain(1.0)
+    m.h1 = np.array([[0.0, 1.0], [0.5, 0.0]])
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(m, 16, 8)
+    assert e.value.status == binding.TTN_EINVAL
+
+
+def test_rejects_mixed_parity_pair(lib):
+    m = inputs.ChainModel("bad", np.zeros((2, 2)), [inputs.PAULI_X], [inputs.PAULI_IY])
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(m, 16, 8)
+    assert e.value.status == binding.TTN_EINVAL
+
+
+def test_rejects_bad_precision_and_chi(lib):
+    with pytest.raises(binding.TTNError):
+        _bytes(inputs.tfim_chain(1.0), 16, 8, precision=7)
+    with pytest.raises(binding.TTNError):
+        _bytes(inputs.tfim_chain(1.0), 16, 0)
