@@ -1,0 +1,202 @@
+"""Benchmark of the binary-TTN sweep on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config NAME] [--precision P]
+
+A step is one full sweep (descend the RDM cache; for every layer the dressed
+two-site chains, the environment, the float64 polar update and the
+re-ascent; then the float64 top eigensolver and the energy) over a
+synthetic Hamiltonian resident in HBM.  W untimed sweeps, then K timed
+sweeps bracketed by device synchronisation.  Prints ONE JSON line.
+
+The line carries the energy per site after the timed sweeps, its difference
+from the float64 GPU path run from the same initial isometries for the same
+number of sweeps, the algorithmic contraction TFLOP/s, a roofline entry for
+the dominant contraction class (its average launch time measured with HIP
+events over a second pass of K sweeps), and the CPU reference timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_GBs": 8000.0}
+
+CONFIGS = {
+    # name: (model builder, L, chi, default precision, description)
+    "tfim16": (lambda I: I.tfim_chain(1.0), 16, 8, "fp64", "critical TFIM chain L=16 chi=8"),
+    "tfim1024": (lambda I: I.tfim_chain(1.0), 1024, 64, "fp32", "critical TFIM chain L=1024 chi=64"),
+    "torus64x4": (lambda I: I.torus_tfim_column(4, 3.0), 64, 128, "bf16x3",
+                  "2D TFIM 64x4 torus h=3 (d=16 column sites) chi=128"),
+    "xxx4096": (lambda I: I.xxx_chain(), 4096, 256, "bf16x3", "Heisenberg XXX chain L=4096 chi=256"),
+}
+DEFAULT_CONFIG = "torus64x4"
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--config", default=DEFAULT_CONFIG, choices=sorted(CONFIGS))
+    p.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"])
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--no-fp64-ref", action="store_true")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
+    return p.parse_args()
+
+
+def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
+    """Times the CPU reference (oracle/) on a bounded sample of the workload."""
+    import numpy as np
+    from oracle import ttn_ref as T
+    from paper_1905_01331_amd import inputs as I
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count() or 1])
+    except Exception:
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), seed)
+    ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
+    t0 = time.perf_counter()
+    ref.initialise()
+    t_init = time.perf_counter() - t0
+    n = ref.n
+    # whole sweeps while they fit the budget, else the top layer step only
+    est_layer = None
+    t0 = time.perf_counter()
+    rhos = T.descend_rho_all(ref.ws, ref.v)
+    tau = n - 1
+    h, A, B = ref.hs[tau - 1], ref.As[tau - 1], ref.Bs[tau - 1]
+    R, Lb = T.dressed_chain(ref.ws, ref.v, rhos, tau, A, B)
+    env = T.environment(ref.ws[tau - 1], h, A, B, rhos[tau], R, Lb)
+    w_new, _ = T.polar_update(env)
+    T.ascend(w_new, h, A, B)
+    t_step = time.perf_counter() - t0
+    a, b, D = ref.dims[tau], ref.dims[tau - 1], ref.D
+    asc = 2 * a * b ** 3 + 2 * a * a * b * b
+    step_flops = ((4 + 8 * D) * a * b ** 3 + (2 + 4 * D) * a * a * b * b          # environment
+                  + (4 + 4 * D) * a * b ** 3 + 2 * a * a * b * b + 2 * D * asc     # re-ascend
+                  + 2 * D * asc                                                    # dressed chain
+                  + sum(2 * ref.dims[s] ** 2 * ref.dims[s - 1] ** 2 + 4 * ref.dims[s] * ref.dims[s - 1] ** 3
+                        for s in range(2, n)))                                     # rho cache
+    if t_step * (n + 2) < budget_s:
+        t0 = time.perf_counter()
+        ref.sweep()
+        t_sweep = time.perf_counter() - t0
+        return {"value": 1.0 / t_sweep, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
+                "sample": f"one full sweep after initialisation ({t_sweep:.2f} s)"}
+    rate = step_flops / t_step
+    return {"value": rate / gpu_sweep_flops, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
+            "sample": (f"top-layer step (rho cache, dressed chain, environment, SVD update, re-ascent) "
+                       f"= {step_flops / 1e9:.1f} GFLOP in {t_step:.2f} s, scaled to the sweep's "
+                       f"{gpu_sweep_flops / 1e12:.2f} TFLOP by the flop model")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(the multi-GPU sharding is a design note only)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1905_01331_amd import binding as B
+    from paper_1905_01331_amd import inputs as I
+
+    build, L, chi, prec_default, desc = CONFIGS[args.config]
+    prec = args.precision or prec_default
+    model = build(I)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=args.seed))
+    for _ in range(args.warmup):
+        t.sweep(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        t.sweep(1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    st = t.stats()
+    sweeps_per_s = args.steps / elapsed
+    tflops = st.flops_bulk / (elapsed / args.steps) / 1e12
+
+    # second pass of K sweeps with per-class HIP event timing
+    t.profile(True)
+    for _ in range(args.steps):
+        t.sweep(1)
+    prof = t.profile_read()
+    t.profile(False)
+    e = float(t.energy()[0])  # after warmup + 2 K sweeps
+    bulk_classes = {k: v for k, v in prof.items() if k in
+                    ("apply_r", "apply_l", "close", "left_mul", "close_l", "close_r")}
+    dom_name, dom = max(bulk_classes.items(), key=lambda kv: kv[1]["ms"])
+    avg_s = dom["ms"] / dom["launches"] / 1e3
+    ach = dom["flops"] / dom["launches"] / avg_s / 1e12
+    peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"] / 3}[prec]
+    roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": None,
+                "kernel": dom_name, "launches": dom["launches"],
+                "avg_launch_us": round(avg_s * 1e6, 2),
+                "flops_per_launch": dom["flops"] / dom["launches"]}
+    classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / args.steps, 3),
+                   "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None}
+               for k, v in prof.items()}
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+
+    err = None
+    e64 = None
+    if prec != "fp64" and not args.no_fp64_ref:
+        r = B.TTN(B.ChainInput(model, L, chi, "fp64", seed=args.seed))
+        r.sweep(args.warmup + 2 * args.steps)
+        e64 = float(r.energy()[0])
+        r.close()
+        del r
+        err = abs(e - e64) / abs(e64)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(model, L, chi, args.seed, args.cpu_budget, st.flops_bulk)
+
+    out = {
+        "metric": "TTN sweeps/sec + contraction TFLOP/s at chi=128,256; energy err vs FP64",
+        "value": round(sweeps_per_s, 4),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": desc, "L": L, "chi": chi, "d": model.d, "D": model.D,
+                   "levels": int(st.n_levels), "precision": prec, "seed": args.seed,
+                   "parallelism": "single GPU"},
+        "contraction_tflops": round(tflops, 3),
+        "flops_bulk_per_sweep": st.flops_bulk,
+        "flops_fp64_per_sweep": st.flops_fp64,
+        "energy_per_site": e,
+        "energy_fp64_gpu": e64,
+        "energy_rel_err_vs_fp64": err,
+        "ortho_err_max": st.ortho_err_max,
+        "roofline": roofline,
+        "classes": classes,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,23 @@ typedef struct ttn_stats_t {
 
 ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
 
+/* Event timing of the contraction classes (apply_r, apply_l, close,
+ * left_mul, close_l, close_r, top_mm, polar_gemm, jacobi, lanczos_gemm).
+ * ttn_profile(h, 1) clears the record and brackets every later launch of a
+ * class with hipEventRecord on the handle's stream; ttn_profile(h, 0) stops.
+ * ttn_profile_read synchronises the stream and returns one entry per class
+ * with its launch count, summed elapsed milliseconds and algorithmic flops
+ * (2 M N K per product) and bytes (operands read once, result written). */
+typedef struct ttn_profile_entry {
+  char name[24];
+  int launches;
+  double ms;
+  double flops;
+  double bytes;
+} ttn_profile_entry;
+ttn_status ttn_profile(ttn_handle h, int enable);
+ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entries, int* n_out);
+
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);
 

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
 EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
     "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator",
-    "ttn_stats", "ttn_bond_dim", "ttn_last_error", "ttn_free",
+    "ttn_stats", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
 ]
 
 
@@ -50,6 +50,11 @@ class TTNStats(ctypes.Structure):
         ("flops_bulk", ctypes.c_double), ("flops_fp64", ctypes.c_double), ("n_levels", ctypes.c_int),
         ("lanczos_iters", ctypes.c_int),
     ]
+
+
+class TTNProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -82,6 +87,8 @@ def load_library(path: str = LIB_PATH):
         "ttn_bond_dim": ([P, I, I], I),
         "ttn_last_error": ([], ctypes.c_char_p),
         "ttn_free": ([P], I),
+        "ttn_profile": ([P, I], I),
+        "ttn_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -226,6 +233,16 @@ class TTN:
         st = TTNStats()
         _check(self.lib.ttn_stats(self.h, b, ctypes.byref(st)))
         return st
+
+    def profile(self, enable=True):
+        return _check(self.lib.ttn_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (TTNProfileEntry * 32)()
+        n = ctypes.c_int(0)
+        _check(self.lib.ttn_profile_read(self.h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                           bytes=arr[i].bytes) for i in range(n.value)}
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -1,0 +1,358 @@
+// MFMA strided GEMM for the float32 and split-bf16 bulk contractions (gfx950).
+//
+// One kernel serves every contraction shape of the sweep: the operand tile
+// loaders take either a contraction-contiguous or an output-contiguous
+// layout (the index permutations of the rank-3 tensors are folded into the
+// strides, including the two-level contraction index of the left-child
+// close), so no operand is transposed in memory.
+//
+// Tile 128 x 128 per 256-thread work-group, 2 x 2 waves, 64 x 64 per wave as
+// 2 x 2 blocks of 32 x 32 MFMA accumulators.
+//   float32:     v_mfma_f32_32x32x2_f32, BK = 16.
+//   split-bf16:  every float32 operand x is split on load into hi = bf16(x),
+//                lo = bf16(x - hi) (round to nearest even); each 32x32x16
+//                step issues lo*hi, hi*lo, hi*hi with v_mfma_f32_32x32x16_bf16
+//                into the same float32 accumulator, BK = 32.
+// Operand tiles live in LDS as [k][mn] (float32) or [k/8][mn][8] (bf16 hi and
+// lo planes), so that the 32 lanes of a half-wave read 32 consecutive
+// entries (float32) or 32 consecutive 16-byte chunks (bf16).
+// Long contractions are split over the grid's z dimension into partial
+// float32 slices reduced in a fixed order (deterministic).
+#include "common.h"
+#include "gemm_internal.h"
+
+namespace ttn {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, NT = 256;
+
+template <int MODE> struct Cfg;
+template <> struct Cfg<P_F32> { static constexpr int BK = 16; };
+template <> struct Cfg<P_BF16X3> { static constexpr int BK = 32; };
+
+// Operand view: element (mn, k) at base + mn*s_mn + koff(k), koff(k) =
+// (k / K2)*s_k1 + (k % K2)*s_k.  KC: contraction-contiguous (s_k == 1),
+// else output-contiguous (s_mn == 1).
+struct OpView {
+  const float* base;
+  long long s_mn, s_k, s_k1;
+  int MN, K2;
+};
+
+__device__ __forceinline__ long long k_offset(const OpView& v, int k) {
+  if (v.K2 <= 0) return (long long)k * v.s_k;
+  int k1 = k / v.K2;
+  return (long long)k1 * v.s_k1 + (long long)(k - k1 * v.K2) * v.s_k;
+}
+
+__device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+
+// Per-thread register staging of one operand tile (BMN x BK floats).
+template <int MODE, bool KC>
+struct Stage {
+  static constexpr int BK = Cfg<MODE>::BK;
+  static constexpr int NV = (BM * BK) / (4 * NT);  // float4 per thread
+  f32x4 r[NV];
+
+  // KC: float4 along k; index f -> (mn = f / (BK/4), kq = f % (BK/4)).
+  // !KC (float32): float4 along mn; f -> (k = f / (BM/4), mq = f % (BM/4)).
+  // !KC (bf16): a 4(mn) x 4(k) block per thread: t -> (mb = t % 32, kb = t / 32).
+  __device__ __forceinline__ void load(const OpView& v, int mn0, int k0, int kend, int tid) {
+    if constexpr (KC) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        int f = tid + i * NT;
+        int mn = f / (BK / 4), k = (f % (BK / 4)) * 4;
+        int gm = mn0 + mn, gk = k0 + k;
+        if (gm < v.MN && gk < kend) r[i] = ld4(v.base + (long long)gm * v.s_mn + k_offset(v, gk));
+        else r[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    } else if constexpr (MODE == P_F32) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        int f = tid + i * NT;
+        int k = f / (BM / 4), mn = (f % (BM / 4)) * 4;
+        int gm = mn0 + mn, gk = k0 + k;
+        if (gm < v.MN && gk < kend) r[i] = ld4(v.base + gm + k_offset(v, gk));
+        else r[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    } else {
+      static_assert(NV == 4, "bf16 output-contiguous staging is a 4x4 block");
+      int mn = (tid % 32) * 4, kb = (tid / 32) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int gm = mn0 + mn, gk = k0 + kb + i;
+        if (gm < v.MN && gk < kend) r[i] = ld4(v.base + gm + k_offset(v, gk));
+        else r[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+};
+
+// LDS planes
+template <int MODE> struct Smem;
+template <> struct Smem<P_F32> {
+  float a[16][BM + 4];
+  float b[16][BN + 4];
+};
+template <> struct Smem<P_BF16X3> {
+  __bf16 ahi[4][BM][8], alo[4][BM][8];
+  __bf16 bhi[4][BN][8], blo[4][BN][8];
+};
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <bool KC>
+__device__ __forceinline__ void store_f32(const Stage<P_F32, KC>& st, float (*pl)[BM + 4], int tid) {
+  constexpr int BK = 16;
+  if constexpr (KC) {
+#pragma unroll
+    for (int i = 0; i < Stage<P_F32, KC>::NV; ++i) {
+      int f = tid + i * NT;
+      int mn = f / (BK / 4), k = (f % (BK / 4)) * 4;
+      pl[k + 0][mn] = st.r[i][0];
+      pl[k + 1][mn] = st.r[i][1];
+      pl[k + 2][mn] = st.r[i][2];
+      pl[k + 3][mn] = st.r[i][3];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Stage<P_F32, KC>::NV; ++i) {
+      int f = tid + i * NT;
+      int k = f / (BM / 4), mn = (f % (BM / 4)) * 4;
+      *reinterpret_cast<f32x4*>(&pl[k][mn]) = st.r[i];
+    }
+  }
+}
+
+template <bool KC>
+__device__ __forceinline__ void store_bf16(const Stage<P_BF16X3, KC>& st, __bf16 (*hi)[BM][8], __bf16 (*lo)[BM][8],
+                                           int tid) {
+  constexpr int BK = 32;
+  if constexpr (KC) {
+#pragma unroll
+    for (int i = 0; i < Stage<P_BF16X3, KC>::NV; ++i) {
+      int f = tid + i * NT;
+      int mn = f / (BK / 4), k = (f % (BK / 4)) * 4;
+      bf16x4 h, l;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        __bf16 a, b;
+        split_bf16(st.r[i][e], a, b);
+        h[e] = a;
+        l[e] = b;
+      }
+      *reinterpret_cast<bf16x4*>(&hi[k >> 3][mn][k & 7]) = h;
+      *reinterpret_cast<bf16x4*>(&lo[k >> 3][mn][k & 7]) = l;
+    }
+  } else {
+    int mn = (tid % 32) * 4, kb = (tid / 32) * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {  // row mn + e, k = kb .. kb+3
+      bf16x4 h, l;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        __bf16 a, b;
+        split_bf16(st.r[i][e], a, b);
+        h[i] = a;
+        l[i] = b;
+      }
+      *reinterpret_cast<bf16x4*>(&hi[kb >> 3][mn + e][kb & 7]) = h;
+      *reinterpret_cast<bf16x4*>(&lo[kb >> 3][mn + e][kb & 7]) = l;
+    }
+  }
+}
+
+template <int MODE, bool AKC, bool BKC>
+__global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, int kchunk, float* __restrict__ partial) {
+  constexpr int BK = Cfg<MODE>::BK;
+  __shared__ Smem<MODE> sm;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int bz = blockIdx.z;
+  const int b = bz / splits, sp = bz - b * splits;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  OpView va{(const float*)g.A + (long long)b * g.sAb, g.sAm, g.sAk, g.sAk1, g.M, g.K2};
+  OpView vb{(const float*)g.B + (long long)b * g.sBb, g.sBn, g.sBk, g.sBk1, g.N, g.K2};
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  Stage<MODE, AKC> sa;
+  Stage<MODE, BKC> sb;
+  if (kbeg < kend) {
+    sa.load(va, m0, kbeg, kend, tid);
+    sb.load(vb, n0, kbeg, kend, tid);
+  }
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    if constexpr (MODE == P_F32) {
+      store_f32<AKC>(sa, sm.a, tid);
+      store_f32<BKC>(sb, sm.b, tid);
+    } else {
+      store_bf16<AKC>(sa, sm.ahi, sm.alo, tid);
+      store_bf16<BKC>(sb, sm.bhi, sm.blo, tid);
+    }
+    __syncthreads();
+    if (k0 + BK < kend) {
+      sa.load(va, m0, k0 + BK, kend, tid);
+      sb.load(vb, n0, k0 + BK, kend, tid);
+    }
+    if constexpr (MODE == P_F32) {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 2) {
+        float a0 = sm.a[kk + (lane >> 5)][wm + (lane & 31)];
+        float a1 = sm.a[kk + (lane >> 5)][wm + 32 + (lane & 31)];
+        float b0 = sm.b[kk + (lane >> 5)][wn + (lane & 31)];
+        float b1 = sm.b[kk + (lane >> 5)][wn + 32 + (lane & 31)];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int kc = 0; kc < BK / 8; kc += 2) {
+        const int c = kc + (lane >> 5);
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          ah[i] = *reinterpret_cast<const bf16x8*>(&sm.ahi[c][wm + 32 * i + (lane & 31)][0]);
+          al[i] = *reinterpret_cast<const bf16x8*>(&sm.alo[c][wm + 32 * i + (lane & 31)][0]);
+          bh[i] = *reinterpret_cast<const bf16x8*>(&sm.bhi[c][wn + 32 * i + (lane & 31)][0]);
+          bl[i] = *reinterpret_cast<const bf16x8*>(&sm.blo[c][wn + 32 * i + (lane & 31)][0]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: lane l, register r of block (i, j) holds
+  // row wm + 32 i + 8 (r / 4) + 4 (l / 32) + r % 4, column wn + 32 j + l % 32
+  const int col_l = lane & 31, rowq = (lane >> 5) * 4;
+  if (splits == 1) {
+    float* C = (float*)g.C + (long long)b * g.sCb;
+    const float alpha = (float)g.alpha, beta = (float)g.beta;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        int n = n0 + wn + 32 * j + col_l;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int m = m0 + wm + 32 * i + 8 * (r >> 2) + rowq + (r & 3);
+          if (m >= g.M) continue;
+          float* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
+          float v = alpha * acc[i][j][r];
+          if (g.beta != 0.0) v += beta * (*c);
+          *c = v;
+        }
+      }
+  } else {
+    float* P = partial + ((long long)sp * g.batch + b) * (long long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        int n = n0 + wn + 32 * j + col_l;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          int m = m0 + wm + 32 * i + 8 * (r >> 2) + rowq + (r & 3);
+          if (m >= g.M) continue;
+          P[(long long)m * g.N + n] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+template <int MODE, bool AKC, bool BKC>
+hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), grid, dim3(NT), 0, s, g, splits, kchunk, partial);
+  return hipGetLastError();
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+// Returns hipErrorNotSupported when the shape/layout does not fit the MFMA
+// loaders (caller falls back to the general kernel).
+hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  if (prec != P_F32 && prec != P_BF16X3) return hipErrorNotSupported;
+  if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
+  const int BK = (prec == P_F32) ? 16 : 32;
+  const bool akc = (g.sAk == 1), bkc = (g.sBk == 1);
+  const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
+  if (!(akc || amc) || !(bkc || bmc)) return hipErrorNotSupported;
+  if (!aligned16(g.A) || !aligned16(g.B)) return hipErrorNotSupported;
+  if (g.sAb % 4 || g.sBb % 4) return hipErrorNotSupported;
+  // contiguous extents and the other strides must keep float4 alignment
+  if (akc) { if (g.K % 4 || g.sAm % 4 || (g.K2 > 0 && (g.K2 % 4 || g.sAk1 % 4))) return hipErrorNotSupported; }
+  else     { if (g.M % 4 || g.sAk % 4 || (g.K2 > 0 && g.sAk1 % 4)) return hipErrorNotSupported; }
+  if (bkc) { if (g.K % 4 || g.sBn % 4 || (g.K2 > 0 && (g.K2 % 4 || g.sBk1 % 4))) return hipErrorNotSupported; }
+  else     { if (g.N % 4 || g.sBk % 4 || (g.K2 > 0 && g.sBk1 % 4)) return hipErrorNotSupported; }
+  // split-K for deep contractions with few output tiles
+  long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
+  int splits = 1;
+  if (tiles < 1024) {
+    long long want = (2048 + tiles - 1) / tiles;
+    long long maxk = g.K / (4 * BK);
+    long long sps = want < maxk ? want : maxk;
+    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(float);
+    long long fit = (long long)(scratch_bytes / slice);
+    if (sps > fit) sps = fit;
+    if (sps > 256) sps = 256;
+    splits = sps < 1 ? 1 : (int)sps;
+  }
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  splits = (g.K + kchunk - 1) / kchunk;
+  if (splits < 1) splits = 1;
+  float* partial = (float*)scratch;
+  hipError_t e;
+  if (prec == P_F32) {
+    if (akc && bkc) e = launch<P_F32, true, true>(g, splits, kchunk, partial, s);
+    else if (akc) e = launch<P_F32, true, false>(g, splits, kchunk, partial, s);
+    else if (bkc) e = launch<P_F32, false, true>(g, splits, kchunk, partial, s);
+    else e = launch<P_F32, false, false>(g, splits, kchunk, partial, s);
+  } else {
+    if (akc && bkc) e = launch<P_BF16X3, true, true>(g, splits, kchunk, partial, s);
+    else if (akc) e = launch<P_BF16X3, true, false>(g, splits, kchunk, partial, s);
+    else if (bkc) e = launch<P_BF16X3, false, true>(g, splits, kchunk, partial, s);
+    else e = launch<P_BF16X3, false, false>(g, splits, kchunk, partial, s);
+  }
+  if (e != hipSuccess) return e;
+  if (splits > 1) return splitk_reduce_f32(g, splits, partial, s);
+  return hipSuccess;
+}
+
+}  // namespace ttn

@@ -241,8 +241,26 @@ hipError_t gemm_plain(Prec prec, const GemmDesc& g, void* scratch, size_t scratc
   return hipErrorInvalidValue;
 }
 
+hipError_t splitk_reduce_f32(const GemmDesc& g, int splits, const float* partial, hipStream_t s) {
+  long long total = (long long)g.batch * g.M * g.N;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((splitk_reduce_kernel<float>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
+  return hipGetLastError();
+}
+
 hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  if (prec != P_F64 && gemm_path_mfma_enabled()) {
+    hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s);
+    if (e != hipErrorNotSupported) return e;
+  }
   return gemm_plain(prec, g, scratch, scratch_bytes, s);
 }
+
+namespace {
+bool g_mfma_enabled = true;
+}
+bool gemm_path_mfma_enabled() { return g_mfma_enabled; }
+void gemm_set_mfma_enabled(bool on) { g_mfma_enabled = on; }
 
 }  // namespace ttn

@@ -20,4 +20,6 @@ hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, 
 hipError_t running_max(const double* x, double* run_max, hipStream_t s);
 hipError_t identity_f64(double* X, int n, hipStream_t s);
 hipError_t zero_int(int* x, int n, hipStream_t s);
+// X <- (X + sign X^T) / 2 in place (sign = +1 symmetric, -1 antisymmetric part)
+hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s);
 }  // namespace ttn

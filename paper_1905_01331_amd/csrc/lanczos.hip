@@ -182,6 +182,26 @@ __global__ void k_identity(double* __restrict__ X, int n) {
     X[i] = (i / n == i % n) ? 1.0 : 0.0;
 }
 
+// X <- 1/2 (X + sign X^T) in place (n x n); one thread per unordered pair.
+__global__ void k_symmetrize(double* __restrict__ X, int n, double sign) {
+  long long total = (long long)n * (n + 1) / 2;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    // t -> (i, j) with i <= j
+    int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+    while ((long long)(i + 1) * (i + 2) / 2 <= t) ++i;
+    while ((long long)i * (i + 1) / 2 > t) --i;
+    int j = (int)(t - (long long)i * (i + 1) / 2);  // j <= i
+    double a = X[(long long)i * n + j], b = X[(long long)j * n + i];
+    if (i == j) {
+      X[(long long)i * n + i] = (sign > 0) ? a : 0.0;
+    } else {
+      double m = 0.5 * (a + sign * b);
+      X[(long long)i * n + j] = m;
+      X[(long long)j * n + i] = sign * m;
+    }
+  }
+}
+
 __global__ void k_zero_int(int* x, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
 }
@@ -245,6 +265,10 @@ hipError_t running_max(const double* x, double* run_max, hipStream_t s) {
 }
 hipError_t identity_f64(double* X, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_identity, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, X, n);
+  return hipGetLastError();
+}
+hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(grid_for((size_t)n * (n + 1) / 2)), dim3(256), 0, s, X, n, sign);
   return hipGetLastError();
 }
 hipError_t zero_int(int* x, int n, hipStream_t s) {

@@ -95,13 +95,42 @@ constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO
 constexpr int POLAR_REFRESH = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
 
+// Per-handle event timer of contraction classes (enabled by ttn_profile).
+enum OpClass { OC_APPLY_R = 0, OC_APPLY_L, OC_CLOSE, OC_LEFT_MUL, OC_CLOSE_L, OC_CLOSE_R, OC_TOP_MM,
+               OC_POLAR_GEMM, OC_JACOBI, OC_LANCZOS_GEMM, OC_N };
+const char* const kOpNames[OC_N] = {"apply_r", "apply_l", "close", "left_mul", "close_l", "close_r",
+                                    "top_mm", "polar_gemm", "jacobi", "lanczos_gemm"};
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;      // pairs
+  std::vector<int> cls;
+  std::vector<double> flops, bytes;
+  size_t used = 0;
+  int dropped = 0;
+  ~Profiler() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+  bool begin(int c, double f, double b, hipStream_t s, size_t* slot) {
+    if (!on) return false;
+    if (used >= cls.size()) { ++dropped; return false; }
+    *slot = used++;
+    cls[*slot] = c;
+    flops[*slot] = f;
+    bytes[*slot] = b;
+    return hipEventRecord(ev[2 * *slot], s) == hipSuccess;
+  }
+  void end(size_t slot, hipStream_t s) { (void)hipEventRecord(ev[2 * slot + 1], s); }
+};
+
 struct Member {
+  Profiler* prof = nullptr;
   // configuration
   int L = 0, n = 0, d = 0, D = 0, chi = 0, ly = 1, prec = TTN_FP64;
   double c = 0.0;
   unsigned long long seed = 0;
   std::vector<int> dims;
   std::vector<double> h1, A, B;
+  std::vector<int> anti;  // product term k is antisymmetric
   const double* const* w0 = nullptr;
   const double* v0 = nullptr;
   int krylov = 40, restarts = 6;
@@ -143,6 +172,7 @@ struct Member {
 struct Ctx {
   std::vector<Member> m;
   hipStream_t s = nullptr;
+  Profiler prof;
 };
 
 // ---------------------------------------------------------------------------
@@ -197,6 +227,7 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
       }
     if (!((a_sym && b_sym) || (a_anti && b_anti)))
       return fail(TTN_EINVAL, "product term %d: A and B must be both symmetric or both antisymmetric", k);
+    M.anti.push_back(a_sym ? 0 : 1);
   }
   M.dims.resize(M.n);
   M.dims[0] = d;
@@ -311,8 +342,18 @@ void layout_member(Member& M, Arena& ar) {
 // ---------------------------------------------------------------------------
 // contraction helpers (element strides; bulk arithmetic of the member)
 // ---------------------------------------------------------------------------
-hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s) {
-  return gemm(p, g, M.splitk, M.splitk_bytes, s);
+hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls = OC_POLAR_GEMM) {
+  size_t slot = 0;
+  bool timed = false;
+  if (M.prof && M.prof->on) {
+    double es = (p == P_F64) ? 8.0 : 4.0;
+    double f = 2.0 * g.M * (double)g.N * g.K * g.batch;
+    double b = es * g.batch * ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
+    timed = M.prof->begin(cls, f, b, s, &slot);
+  }
+  hipError_t e = gemm(p, g, M.splitk, M.splitk_bytes, s);
+  if (timed) M.prof->end(slot, s);
+  return e;
 }
 
 GemmDesc desc0() {
@@ -333,7 +374,7 @@ hipError_t apply_r(const Member& M, Prec p, const void* O, const void* X, void* 
   g.B = O; g.sBk = 1; g.sBn = b;
   g.C = Y; g.sCm = b; g.sCn = 1;
   g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_APPLY_R);
 }
 // (O .l X)[a;l,r] = sum_l' O[l,l'] X[a;l',r]  -> Y   (batched over a)
 hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
@@ -345,7 +386,7 @@ hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* 
   g.B = X; g.sBk = b; g.sBn = 1; g.sBb = (long long)b * b;
   g.C = Y; g.sCm = b; g.sCn = 1; g.sCb = (long long)b * b;
   g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_APPLY_L);
 }
 // C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b)
 hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
@@ -357,7 +398,7 @@ hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void
   g.B = Qm; g.sBk = 1; g.sBn = bb;
   g.C = C; g.sCm = a; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_CLOSE);
 }
 // (X o P)[a;l,r] = sum_a' X[a,a'] P[a';l,r]
 hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void* Y, int a, int b, double alpha,
@@ -369,7 +410,7 @@ hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void*
   g.B = P; g.sBk = bb; g.sBn = 1;
   g.C = Y; g.sCm = bb; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_LEFT_MUL);
 }
 // C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']   (b x b, K = a*b)
 hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
@@ -380,7 +421,7 @@ hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void*
   g.B = Qm; g.sBk = b; g.sBn = 1;
   g.C = C; g.sCm = b; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_CLOSE_R);
 }
 // C_L(P,Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r]   (b x b, K = (a, r))
 hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
@@ -392,7 +433,7 @@ hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void*
   g.B = Qm; g.sBk = 1; g.sBk1 = bb; g.sBn = b;
   g.C = C; g.sCm = b; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, OC_CLOSE_L);
 }
 // dense square products of order x: C = alpha op(A) op(B) + beta C
 hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, bool tb, void* C, int x, double alpha,
@@ -403,7 +444,7 @@ hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, 
   g.B = Bm; g.sBk = tb ? 1 : x; g.sBn = tb ? x : 1;
   g.C = C; g.sCm = x; g.sCn = 1;
   g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s);
+  return run(M, p, g, s, p == P_F64 ? OC_TOP_MM : OC_TOP_MM);
 }
 
 // S w = h .l w + h .r w + sum_k A_k .l (B_k .r w)   (into M.Sw)
@@ -555,7 +596,12 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     g.B = Yc; g.sBk = 1; g.sBn = K;
     g.C = M.G; g.sCm = a; g.sCn = 1;
     HIPCHK(run(M, P_F64, g, s));
-    HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, 1e-15, M.jinfo + 2 * it, s));
+    {
+      size_t slot = 0;
+      bool timed = M.prof && M.prof->begin(OC_JACOBI, 0.0, 0.0, s, &slot);
+      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, 1e-15, M.jinfo + 2 * it, s));
+      if (timed) M.prof->end(slot, s);
+    }
     GemmDesc r = desc0();  // Yn = V^T Y
     r.M = a; r.N = (int)K; r.K = a;
     r.A = M.V; r.sAm = 1; r.sAk = a;
@@ -660,6 +706,13 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
       HIPCHK(convert_f32_to_f64((const float*)M.opB[n - 1], M.Bop64, D * xx, s));
     }
   }
+  // the operators are symmetric (h) or of the parity of their level-0 term
+  // in exact arithmetic; remove the rounding asymmetry so H_top is symmetric
+  HIPCHK(symmetrize_f64(M.hop64, x, 1.0, s));
+  for (int k = 0; k < D; ++k) {
+    HIPCHK(symmetrize_f64(M.Aop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
+    HIPCHK(symmetrize_f64(M.Bop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
+  }
   const int m = (int)std::min<long long>(M.krylov, (long long)xx);
   int iters = 0;
   *converged = false;
@@ -682,14 +735,14 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
         g.A = M.lzQ; g.sAm = (long long)xx; g.sAk = 1;
         g.B = M.lzW; g.sBk = 1; g.sBn = 1;
         g.C = M.coef; g.sCm = 1; g.sCn = 1;
-        HIPCHK(run(M, P_F64, g, s));
+        HIPCHK(run(M, P_F64, g, s, OC_LANCZOS_GEMM));
         GemmDesc h = desc0();  // w -= Q[0..j]^T coef
         h.M = 1; h.N = (int)xx; h.K = j + 1;
         h.A = M.coef; h.sAm = 0; h.sAk = 1;
         h.B = M.lzQ; h.sBk = (long long)xx; h.sBn = 1;
         h.C = M.lzW; h.sCm = 0; h.sCn = 1;
         h.alpha = -1.0; h.beta = 1.0;
-        HIPCHK(run(M, P_F64, h, s));
+        HIPCHK(run(M, P_F64, h, s, OC_LANCZOS_GEMM));
       }
       HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
       HIPCHK(lz_set_beta(M.scal + SCAL_TMP0, M.scal + SCAL_TMP1, M.beta, j, 1e-12, M.lzint, M.lzint + 1, s));
@@ -864,6 +917,7 @@ ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t b
     Member& M = h->c.m[i];
     setup_member(cfgs[i], M);
     layout_member(M, ar);
+    M.prof = &h->c.prof;
   }
   for (int i = 0; i < batch; ++i) {
     bool conv = false;
@@ -1106,6 +1160,51 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out) {
   out->n_levels = M.n;
   out->lanczos_iters = M.lz_iters;
   return TTN_OK;
+}
+
+ttn_status ttn_profile(ttn_handle h, int enable) {
+  if (!h) return fail(TTN_EINVAL, "null handle");
+  Profiler& P = h->c.prof;
+  if (enable) {
+    if (P.ev.empty()) {
+      const size_t cap = 1 << 15;
+      P.ev.resize(2 * cap);
+      for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
+      P.cls.resize(cap);
+      P.flops.resize(cap);
+      P.bytes.resize(cap);
+    }
+    P.used = 0;
+    P.dropped = 0;
+  }
+  P.on = enable != 0;
+  return TTN_OK;
+}
+
+ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entries, int* n_out) {
+  if (!h || !out || !n_out) return fail(TTN_EINVAL, "bad arguments");
+  Profiler& P = h->c.prof;
+  HIPCHK(hipStreamSynchronize(h->c.s));
+  std::vector<ttn_profile_entry> agg(OC_N);
+  for (int c = 0; c < OC_N; ++c) {
+    std::memset(&agg[c], 0, sizeof agg[c]);
+    std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kOpNames[c]);
+  }
+  for (size_t i = 0; i < P.used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
+    ttn_profile_entry& e = agg[P.cls[i]];
+    e.launches += 1;
+    e.ms += ms;
+    e.flops += P.flops[i];
+    e.bytes += P.bytes[i];
+  }
+  int n = 0;
+  for (int c = 0; c < OC_N && n < max_entries; ++c)
+    if (agg[c].launches) out[n++] = agg[c];
+  *n_out = n;
+  P.used = 0;
+  return P.dropped ? fail(TTN_OK, "%d launches were not timed (event pool full)", P.dropped) : TTN_OK;
 }
 
 int ttn_bond_dim(ttn_handle h, int b, int tau) {

@@ -1,0 +1,126 @@
+"""Float32 and split-bf16 bulk contractions (MFMA paths) vs the float64 CPU
+reference, stage by stage from identical states, and whole sweeps vs the
+float64 GPU path.
+
+Tolerances: the bulk stages are compared relative to the largest entry of
+the reference output.  float32 operands with float32 accumulation over
+K <= 4096 terms stay below 2e-5; split-bf16 (hi*hi + hi*lo + lo*hi, each
+operand rounded twice to bf16, relative representation error <= 2^-16)
+stays below 1e-4.  Energies after the top solve: 2e-6 (float32) and 2e-5
+(split-bf16) relative to the energy scale of the model, max(|e|, c / ly)
+with c the shift (a random initial state has e close to zero).
+"""
+import numpy as np
+import pytest
+
+from oracle import ttn_ref as T
+from paper_1905_01331_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_STAGE = {"fp32": 2e-5, "bf16x3": 1e-4}
+TOL_ENERGY = {"fp32": 2e-6, "bf16x3": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1905_01331_amd import binding
+    binding.load_library()
+    return binding
+
+
+def rel_err(x, y):
+    return float(np.abs(np.asarray(x) - np.asarray(y)).max() / max(1e-300, np.abs(np.asarray(y)).max()))
+
+
+def set_err(xs, ys):
+    """Error of a set of matrices (all product terms k of one kind) relative
+    to the largest entry of the set: the terms enter the energy summed, and a
+    term that happens to be small carries the absolute error of the others."""
+    num = max(float(np.abs(np.asarray(x) - np.asarray(y)).max()) for x, y in zip(xs, ys))
+    return num / max(1e-300, max(float(np.abs(np.asarray(y)).max()) for y in ys))
+
+
+CASES = [
+    ("tfim_L128_chi64", I.tfim_chain(1.0), 128, 64),
+    ("torus8x4_chi64", I.torus_tfim_column(4, 3.0), 8, 64),
+    ("xxx_L64_chi48", I.xxx_chain(), 64, 48),
+    ("tfim_L32_chi160", I.tfim_chain(0.8), 32, 160),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name,model,L,chi", CASES, ids=[c[0] for c in CASES])
+def test_stage_precision(B, prec, name, model, L, chi):
+    print(f"[precision] {name} {prec}", flush=True)
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 2)
+    ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
+    ref.initialise()
+    gpu = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    n = ref.n
+    worst = {}
+    for lvl in range(1, n):
+        worst["h"] = max(worst.get("h", 0), rel_err(gpu.get_operator(lvl, B.TTN_OP_H), ref.hs[lvl]))
+        ks = range(model.D)
+        worst["A"] = max(worst.get("A", 0), set_err([gpu.get_operator(lvl, B.TTN_OP_A, k) for k in ks], ref.As[lvl]))
+        worst["B"] = max(worst.get("B", 0), set_err([gpu.get_operator(lvl, B.TTN_OP_B, k) for k in ks], ref.Bs[lvl]))
+    e0 = gpu.energy()[0]
+    scale = lambda e: max(abs(e), abs(ref.c) / model.ly)
+    worst["e0"] = abs(e0 - ref.history[0]) / scale(ref.history[0])
+    gpu.set_tensor(B.TTN_TOP, ref.v)
+    gpu.descend(B.TTN_DESCEND_RHO)
+    rhos = T.descend_rho_all(ref.ws, ref.v)
+    for lvl in range(1, n):
+        worst["rho"] = max(worst.get("rho", 0), rel_err(gpu.get_operator(lvl, B.TTN_OP_RHO), rhos[lvl]))
+    for tau in range(1, n):
+        gpu.descend(B.TTN_DESCEND_DRESSED, tau)
+        h, A, Bm = ref.hs[tau - 1], ref.As[tau - 1], ref.Bs[tau - 1]
+        R, Lb = T.dressed_chain(ref.ws, ref.v, rhos, tau, A, Bm)
+        ks = range(model.D)
+        worst["Rbar"] = max(worst.get("Rbar", 0), set_err([gpu.get_operator(tau, B.TTN_OP_RBAR, k) for k in ks], R))
+        worst["Lbar"] = max(worst.get("Lbar", 0), set_err([gpu.get_operator(tau, B.TTN_OP_LBAR, k) for k in ks], Lb))
+        gpu.env(tau)
+        env = T.environment(ref.ws[tau - 1], h, A, Bm, rhos[tau], R, Lb)
+        worst["env"] = max(worst.get("env", 0), rel_err(gpu.get_operator(tau, B.TTN_OP_ENV), env))
+        gpu.update(tau)
+        w_gpu = gpu.get_tensor(tau)
+        W = w_gpu.reshape(w_gpu.shape[0], -1)
+        assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-13   # float64 polar regardless
+        w_ref, _ = T.polar_update(env)
+        ref.ws[tau - 1] = w_ref
+        gpu.set_tensor(tau, w_ref)
+        ref.hs[tau], ref.As[tau], ref.Bs[tau] = T.ascend(w_ref, h, A, Bm)
+        gpu.ascend(tau, tau)
+    gpu.update(B.TTN_TOP)
+    top = n - 1
+    lam, _ = T.top_eigen(ref.hs[top], ref.As[top], ref.Bs[top], v0=ref.v)
+    e_ref = (lam + ref.c * L) / (L * model.ly)
+    worst["e"] = abs(gpu.energy()[0] - e_ref) / scale(e_ref)
+    print("  worst relative errors:", {k: f"{v:.2e}" for k, v in worst.items()})
+    stage_keys = [k for k in worst if k not in ("e0", "e")]
+    assert max(worst[k] for k in stage_keys) < TOL_STAGE[prec]
+    assert worst["e0"] < TOL_ENERGY[prec] and worst["e"] < TOL_ENERGY[prec]
+    gpu.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_sweeps_track_fp64(B, prec):
+    model, L, chi = I.tfim_chain(1.0), 256, 32
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 4)
+    g64 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    gmx = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    e64, emx = [g64.energy()[0]], [gmx.energy()[0]]
+    for _ in range(4):
+        g64.sweep(1)
+        gmx.sweep(1)
+        e64.append(g64.energy()[0])
+        emx.append(gmx.energy()[0])
+    diff = np.abs(np.array(emx) - np.array(e64)) / np.abs(e64)
+    print(f"  {prec} vs fp64 per-sweep relative energy differences", diff)
+    assert diff.max() < 50 * TOL_ENERGY[prec]
+    assert all(b <= a + 1e-7 for a, b in zip(emx, emx[1:]))
+    g64.close()
+    gmx.close()
