@@ -191,6 +191,8 @@ def main():
         "energy_fp64_gpu": e64,
         "energy_rel_err_vs_fp64": err,
         "ortho_err_max": st.ortho_err_max,
+        "jacobi_sweeps_last": list(st.jacobi_sweeps),
+        "lanczos_iters_last": st.lanczos_iters,
         "roofline": roofline,
         "classes": classes,
         "cpu_baseline": cpu,

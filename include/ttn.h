@@ -107,8 +107,8 @@ typedef struct ttn_config {
                          at w0[tau-1] with shape (chi_tau, chi_{tau-1}^2)     */
   const double* v0;   /* optional host chi_{n-1}^2 start vector of the top
                          eigensolver (else a fixed deterministic vector)      */
-  int krylov;         /* Lanczos basis size per restart (0: 40)               */
-  int restarts;       /* Lanczos restarts per top update (0: 6)               */
+  int krylov;         /* Lanczos basis size per restart (0: 24)               */
+  int restarts;       /* Lanczos restarts per top update (0: 8)               */
   double lanczos_tol; /* target ||H v - lambda v|| / ||H||_est (0: 1e-13)     */
 } ttn_config;
 
@@ -181,6 +181,8 @@ typedef struct ttn_stats_t {
   double flops_fp64;      /* algorithmic float64 flops of one sweep           */
   int n_levels;           /* n                                                 */
   int lanczos_iters;      /* Krylov steps of the last top update              */
+  int jacobi_sweeps[4];   /* Jacobi sweeps of the last polar update's three
+                             refreshes and of the last Lanczos projection     */
 } ttn_stats_t;
 
 ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);

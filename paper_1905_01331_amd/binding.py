@@ -48,7 +48,7 @@ class TTNStats(ctypes.Structure):
         ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("lanczos_resid", ctypes.c_double),
         ("ortho_err_max", ctypes.c_double), ("sigma_ratio_min", ctypes.c_double), ("shift", ctypes.c_double),
         ("flops_bulk", ctypes.c_double), ("flops_fp64", ctypes.c_double), ("n_levels", ctypes.c_int),
-        ("lanczos_iters", ctypes.c_int),
+        ("lanczos_iters", ctypes.c_int), ("jacobi_sweeps", ctypes.c_int * 4),
     ]
 
 

@@ -41,8 +41,8 @@ hipError_t axpby_f32(const float* x, float* y, float alpha, float beta, size_t n
 hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned long long stream_id, hipStream_t s);
 
 // Jacobi eigensolver of a symmetric n x n float64 matrix G (in place; on
-// return the diagonal holds the eigenvalues), eigenvectors in the columns of
-// V (n x n).  One work-group.  `info` (device int[4]): [0] sweeps used,
+// return the diagonal holds the eigenvalues), eigenvectors in the ROWS of
+// U (n x n), G_in = U^T diag U.  One work-group.  `info` (device int[4]): [0] sweeps used,
 // [1] rotations in the first sweep.
 hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s);
 // Z[i,:] = Y[i,:] / ||Y[i,:]||  for an m x k matrix (row norms into nrm[m]); rows

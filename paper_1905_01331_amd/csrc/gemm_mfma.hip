@@ -293,6 +293,153 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// float64: v_mfma_f64_16x16x4_f64, 128 x 128 tile, BK = 16, 2 x 2 waves of
+// 64 x 64 (4 x 4 blocks of 16 x 16).  Lane l of a block holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 r][l % 16].
+// ---------------------------------------------------------------------------
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int BK64 = 16;
+
+struct OpView64 {
+  const double* base;
+  long long s_mn, s_k, s_k1;
+  int MN, K2;
+};
+__device__ __forceinline__ long long k_offset64(const OpView64& v, int k) {
+  if (v.K2 <= 0) return (long long)k * v.s_k;
+  int k1 = k / v.K2;
+  return (long long)k1 * v.s_k1 + (long long)(k - k1 * v.K2) * v.s_k;
+}
+
+template <bool KC>
+struct Stage64 {
+  static constexpr int NV = (BM * BK64) / (2 * NT);  // double2 per thread (4)
+  f64x2 r[NV];
+  __device__ __forceinline__ void load(const OpView64& v, int mn0, int k0, int kend, int tid) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int f = tid + i * NT;
+      int mn, k;
+      if constexpr (KC) { mn = f / (BK64 / 2); k = (f % (BK64 / 2)) * 2; }
+      else              { k = f / (BM / 2); mn = (f % (BM / 2)) * 2; }
+      int gm = mn0 + mn, gk = k0 + k;
+      if (gm < v.MN && gk < kend) {
+        const double* p = KC ? v.base + (long long)gm * v.s_mn + k_offset64(v, gk) : v.base + gm + k_offset64(v, gk);
+        r[i] = *reinterpret_cast<const f64x2*>(p);
+      } else {
+        r[i] = f64x2{0.0, 0.0};
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double (*pl)[BM + 2], int tid) const {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int f = tid + i * NT;
+      if constexpr (KC) {
+        int mn = f / (BK64 / 2), k = (f % (BK64 / 2)) * 2;
+        pl[k][mn] = r[i][0];
+        pl[k + 1][mn] = r[i][1];
+      } else {
+        int k = f / (BM / 2), mn = (f % (BM / 2)) * 2;
+        *reinterpret_cast<f64x2*>(&pl[k][mn]) = r[i];
+      }
+    }
+  }
+};
+
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial) {
+  __shared__ double sa_l[BK64][BM + 2];
+  __shared__ double sb_l[BK64][BN + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int bz = blockIdx.z;
+  const int b = bz / splits, sp = bz - b * splits;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+  OpView64 va{(const double*)g.A + (long long)b * g.sAb, g.sAm, g.sAk, g.sAk1, g.M, g.K2};
+  OpView64 vb{(const double*)g.B + (long long)b * g.sBb, g.sBn, g.sBk, g.sBk1, g.N, g.K2};
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  Stage64<AKC> sa;
+  Stage64<BKC> sb;
+  if (kbeg < kend) {
+    sa.load(va, m0, kbeg, kend, tid);
+    sb.load(vb, n0, kbeg, kend, tid);
+  }
+  for (int k0 = kbeg; k0 < kend; k0 += BK64) {
+    sa.store(sa_l, tid);
+    sb.store(sb_l, tid);
+    __syncthreads();
+    if (k0 + BK64 < kend) {
+      sa.load(va, m0, k0 + BK64, kend, tid);
+      sb.load(vb, n0, k0 + BK64, kend, tid);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK64; kk += 4) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sa_l[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = sb_l[kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int col_l = lane & 15, row_l = lane >> 4;
+  if (splits == 1) {
+    double* C = (double*)g.C + (long long)b * g.sCb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int n = n0 + wn + 16 * j + col_l;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int m = m0 + wm + 16 * i + row_l + 4 * r;
+          if (m >= g.M) continue;
+          double* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
+          double v = g.alpha * acc[i][j][r];
+          if (g.beta != 0.0) v += g.beta * (*c);
+          *c = v;
+        }
+      }
+  } else {
+    double* P = partial + ((long long)sp * g.batch + b) * (long long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int n = n0 + wn + 16 * j + col_l;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          int m = m0 + wm + 16 * i + row_l + 4 * r;
+          if (m >= g.M) continue;
+          P[(long long)m * g.N + n] = acc[i][j][r];
+        }
+      }
+  }
+}
+
+template <bool AKC, bool BKC>
+hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), grid, dim3(NT), 0, s, g, splits, kchunk, partial);
+  return hipGetLastError();
+}
+
 template <int MODE, bool AKC, bool BKC>
 hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
@@ -306,7 +453,46 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // Returns hipErrorNotSupported when the shape/layout does not fit the MFMA
 // loaders (caller falls back to the general kernel).
+static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
+  const bool akc = (g.sAk == 1), bkc = (g.sBk == 1);
+  const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
+  if (!(akc || amc) || !(bkc || bmc)) return hipErrorNotSupported;
+  if (!aligned16(g.A) || !aligned16(g.B)) return hipErrorNotSupported;
+  if (g.sAb % 2 || g.sBb % 2) return hipErrorNotSupported;
+  if (akc) { if (g.K % 2 || g.sAm % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sAk1 % 2))) return hipErrorNotSupported; }
+  else     { if (g.M % 2 || g.sAk % 2 || (g.K2 > 0 && g.sAk1 % 2)) return hipErrorNotSupported; }
+  if (bkc) { if (g.K % 2 || g.sBn % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sBk1 % 2))) return hipErrorNotSupported; }
+  else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
+  long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
+  int splits = 1;
+  if (tiles < 1024) {
+    long long want = (2048 + tiles - 1) / tiles;
+    long long maxk = g.K / (4 * BK64);
+    long long sps = want < maxk ? want : maxk;
+    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(double);
+    long long fit = (long long)(scratch_bytes / slice);
+    if (sps > fit) sps = fit;
+    if (sps > 256) sps = 256;
+    splits = sps < 1 ? 1 : (int)sps;
+  }
+  int kchunk = (g.K + splits - 1) / splits;
+  kchunk = ((kchunk + BK64 - 1) / BK64) * BK64;
+  splits = (g.K + kchunk - 1) / kchunk;
+  if (splits < 1) splits = 1;
+  double* partial = (double*)scratch;
+  hipError_t e;
+  if (akc && bkc) e = launch64<true, true>(g, splits, kchunk, partial, s);
+  else if (akc) e = launch64<true, false>(g, splits, kchunk, partial, s);
+  else if (bkc) e = launch64<false, true>(g, splits, kchunk, partial, s);
+  else e = launch64<false, false>(g, splits, kchunk, partial, s);
+  if (e != hipSuccess) return e;
+  if (splits > 1) return splitk_reduce_f64(g, splits, partial, s);
+  return hipSuccess;
+}
+
 hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  if (prec == P_F64) return gemm_mfma64(g, scratch, scratch_bytes, s);
   if (prec != P_F32 && prec != P_BF16X3) return hipErrorNotSupported;
   if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
   const int BK = (prec == P_F32) ? 16 : 32;

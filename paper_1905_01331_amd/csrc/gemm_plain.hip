@@ -249,8 +249,16 @@ hipError_t splitk_reduce_f32(const GemmDesc& g, int splits, const float* partial
   return hipGetLastError();
 }
 
+hipError_t splitk_reduce_f64(const GemmDesc& g, int splits, const double* partial, hipStream_t s) {
+  long long total = (long long)g.batch * g.M * g.N;
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL((splitk_reduce_kernel<double>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
+  return hipGetLastError();
+}
+
 hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
-  if (prec != P_F64 && gemm_path_mfma_enabled()) {
+  if (gemm_path_mfma_enabled()) {
     hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s);
     if (e != hipErrorNotSupported) return e;
   }

@@ -78,7 +78,7 @@ __global__ void k_build_T(const double* __restrict__ alpha, const double* __rest
 }
 
 // y = eigenvector of the smallest diagonal entry of the diagonalised T
-// (columns of V), the entry of largest magnitude made positive.
+// (rows of U).
 __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* __restrict__ V, int m,
                                 double* __restrict__ y, double* __restrict__ theta) {
   __shared__ int best;
@@ -90,7 +90,7 @@ __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* 
     theta[0] = Tdiag[(size_t)b * m + b];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += blockDim.x) y[i] = V[(size_t)i * m + best];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) y[i] = V[(size_t)best * m + i];
 }
 
 // x *= 1 / sqrt(ss[0])

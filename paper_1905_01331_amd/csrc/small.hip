@@ -150,7 +150,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __r
 // Rotation of the pair (p, q) with t = tan(phi) from
 // theta = (G_qq - G_pp) / (2 G_pq), t = sign(theta) / (|theta| + sqrt(theta^2+1)),
 // c = 1/sqrt(1+t^2), s = t c;  G <- J^T G J, V <- V J, J = [[c, s], [-s, c]] on
-// (p, q).  A pair is skipped when |G_pq| <= tol * sqrt(|G_pp G_qq|) (relative
+// (p, q); the eigenvectors are returned as the ROWS of U = V^T.  A pair is
+// skipped when |G_pq| <= tol * sqrt(|G_pp G_qq|) (relative
 // threshold: small eigenvalues of a graded matrix keep their relative
 // accuracy, Demmel and Veselic 1992).  All n/2 rotations of one round touch
 // disjoint index pairs, so the 2x2 blocks of J^T G J are independent.
@@ -158,17 +159,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __r
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAXN = 1024;
 
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, double* __restrict__ V, int n,
+// LDS: the matrix is copied into dynamic shared memory (when it fits) and
+// written back at the end; V stays in global memory.
+template <bool LDS>
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ V, int n,
                                                         int max_sweeps, double tol, int* info) {
+  extern __shared__ double dyn[];
   __shared__ double cs[JAC_MAXN / 2], sn[JAC_MAXN / 2], tn[JAC_MAXN / 2];
   __shared__ int pp[JAC_MAXN / 2], qq[JAC_MAXN / 2];
   __shared__ int rot_count;
   const int tid = threadIdx.x;
+  double* G = LDS ? dyn : Gg;
   const int N = n + (n & 1);   // even number of players; index n is a dummy when n is odd
   const int npair = N / 2;
   for (long long i = tid; i < (long long)n * n; i += blockDim.x) {
     int r = (int)(i / n), c = (int)(i - (long long)r * n);
     V[i] = (r == c) ? 1.0 : 0.0;
+    if (LDS) G[i] = Gg[i];
   }
   __syncthreads();
   int sweep = 0, first_rot = -1;
@@ -197,9 +204,10 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, 
       __syncthreads();
       for (long long idx = tid; idx < (long long)npair * npair; idx += blockDim.x) {
         int k1 = (int)(idx / npair), k2 = (int)(idx - (long long)k1 * npair);
-        int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-        double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+        double s1 = sn[k1], s2 = sn[k2];
         if (s1 == 0.0 && s2 == 0.0) continue;
+        int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        double c1 = cs[k1], c2 = cs[k2];
         bool hq1 = q1 < n, hq2 = q2 < n;
         double gpp = G[(long long)p1 * n + p2];
         double gpq = hq2 ? G[(long long)p1 * n + q2] : 0.0;
@@ -214,9 +222,8 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, 
         if (k1 == k2 && s1 != 0.0) {
           // the rotated pair itself: exact annihilation, Rutishauser's diagonal update
           double t1 = tn[k1];
-          double g_pq = G[(long long)p1 * n + q1];
-          npp = G[(long long)p1 * n + p1] - t1 * g_pq;
-          nqq = G[(long long)q1 * n + q1] + t1 * g_pq;
+          npp = gpp - t1 * gpq;
+          nqq = gqq + t1 * gpq;
           npq = 0.0;
           nqp = 0.0;
         }
@@ -225,14 +232,15 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, 
         if (hq1) G[(long long)q1 * n + p2] = nqp;
         if (hq1 && hq2) G[(long long)q1 * n + q2] = nqq;
       }
+      // rows p, q of U = V^T (eigenvectors as rows): coalesced along i
       for (long long idx = tid; idx < (long long)n * npair; idx += blockDim.x) {
-        int i = (int)(idx / npair), k = (int)(idx - (long long)i * npair);
+        int k = (int)(idx / n), i = (int)(idx - (long long)k * n);
         double c = cs[k], s = sn[k];
         if (s == 0.0) continue;
         int p = pp[k], q = qq[k];
-        double vp = V[(long long)i * n + p], vq = V[(long long)i * n + q];
-        V[(long long)i * n + p] = c * vp - s * vq;
-        V[(long long)i * n + q] = s * vp + c * vq;
+        double up = V[(long long)p * n + i], uq = V[(long long)q * n + i];
+        V[(long long)p * n + i] = c * up - s * uq;
+        V[(long long)q * n + i] = s * up + c * uq;
       }
       __syncthreads();
     }
@@ -240,6 +248,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ G, 
     if (first_rot < 0) first_rot = rc;
     __syncthreads();
     if (rc == 0) break;
+  }
+  if (LDS) {
+    for (long long i = tid; i < (long long)n * n; i += blockDim.x) Gg[i] = G[i];
   }
   if (tid == 0 && info) {
     info[0] = sweep;
@@ -319,7 +330,30 @@ hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, lon
 }
 hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s) {
   if (n > JAC_MAXN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
+  // the matrix goes to LDS when it fits next to the static rotation tables
+  static int lds_limit = -1;
+  if (lds_limit < 0) {
+    int dev = 0, v = 0;
+    lds_limit = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess) lds_limit = v;
+      int o = 0;
+      if (hipDeviceGetAttribute(&o, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && o > lds_limit)
+        lds_limit = o;
+    }
+    const int static_lds = (JAC_MAXN / 2) * (3 * 8 + 2 * 4) + 16;
+    lds_limit -= static_lds;
+    if (lds_limit > 0 &&
+        hipFuncSetAttribute((const void*)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess)
+      lds_limit = 0;
+    (void)hipGetLastError();
+  }
+  size_t bytes = (size_t)n * n * sizeof(double);
+  if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info);
+  } else {
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
+  }
   return hipGetLastError();
 }
 

@@ -133,11 +133,13 @@ struct Member {
   std::vector<int> anti;  // product term k is antisymmetric
   const double* const* w0 = nullptr;
   const double* v0 = nullptr;
-  int krylov = 40, restarts = 6;
+  int krylov = 24, restarts = 8;
   double ltol = 1e-13;
   // device
   size_t esz = 8;  // bulk element size
   std::vector<double*> w64;
+  std::vector<double*> Qw;      // per layer: left rotation of the last polar update (warm start)
+  std::vector<char> qw_valid;
   std::vector<void*> wT, opH, opA, opB, rho, Pc, At, Bt;
   void *Rb[2] = {nullptr, nullptr}, *Lb[2] = {nullptr, nullptr};
   int rb_cur = 0;
@@ -148,7 +150,7 @@ struct Member {
   double* vtop = nullptr;
   void* vT = nullptr;
   void* tmpT = nullptr;  // chi^2 bulk scratch for the top dressing
-  double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr;
+  double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr, *lzStage = nullptr;
   double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
   double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr;
   int* lzint = nullptr;
@@ -197,8 +199,8 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
   M.seed = c.seed;
   M.w0 = c.w0;
   M.v0 = c.v0;
-  M.krylov = c.krylov > 0 ? c.krylov : 40;
-  M.restarts = c.restarts > 0 ? c.restarts : 6;
+  M.krylov = c.krylov > 0 ? c.krylov : 24;
+  M.restarts = c.restarts > 0 ? c.restarts : 8;
   M.ltol = c.lanczos_tol > 0 ? c.lanczos_tol : 1e-13;
   if (M.krylov > 256) return fail(TTN_EINVAL, "krylov=%d > 256", M.krylov);
   const int d = c.d, D = c.D;
@@ -270,9 +272,12 @@ void layout_member(Member& M, Arena& ar) {
   const size_t xx = (size_t)x * x;
   M.w64.assign(n, nullptr);
   M.wT.assign(n, nullptr);
+  M.Qw.assign(n, nullptr);
+  M.qw_valid.assign(n, 0);
   for (int t = 1; t < n; ++t) {
     size_t e = (size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1];
     M.w64[t] = ar.take<double>(e);
+    M.Qw[t] = ar.take<double>((size_t)M.dims[t] * M.dims[t]);
     M.wT[t] = (M.prec == TTN_FP64) ? (void*)M.w64[t] : ar.take_bytes(M.el(e));
   }
   M.opH.assign(n, nullptr);
@@ -315,9 +320,12 @@ void layout_member(Member& M, Arena& ar) {
   M.vtop = ar.take<double>(xx);
   M.vT = (M.prec == TTN_FP64) ? (void*)M.vtop : ar.take_bytes(M.el(xx));
   M.tmpT = ar.take_bytes(M.el(xx));
-  M.hop64 = ar.take<double>(xx);
-  M.Aop64 = ar.take<double>(xx * std::max(D, 1));
-  M.Bop64 = ar.take<double>(xx * std::max(D, 1));
+  // float64 top operators, contiguous [h, A_1..A_D, B_1..B_D], and the
+  // matvec staging [y, y B_1^T .. y B_D^T, y A_1^T .. y A_D^T]
+  M.hop64 = ar.take<double>(xx * (1 + 2 * D));
+  M.Aop64 = M.hop64 + xx;
+  M.Bop64 = M.hop64 + (1 + D) * xx;
+  M.lzStage = ar.take<double>(xx * (1 + 2 * D));
   int m = std::min<long long>(M.krylov, (long long)xx);
   M.lzQ = ar.take<double>((size_t)(m + 1) * xx);
   M.lzW = ar.take<double>(xx);
@@ -582,13 +590,35 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
 // out = sign * polar(src) for src (a x K), float64: Gram -> Jacobi eigenvectors
 // -> rotate, repeated; rows of the rotated matrix end up mutually orthogonal
 // with relative accuracy, then normalised and rotated back.
-ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s) {
+// With `warm` (a rotation kept from the previous update of this layer) the
+// first Gram is taken of warm^T src, which is nearly diagonal once the sweep
+// settles, so the Jacobi sweeps of the first refresh drop; the result is the
+// same polar factor.  The final rotation is written back to `warm`.
+ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,
+                      double* warm = nullptr, bool warm_valid = false) {
+  // Invariant: Y = P src with P orthogonal (P = Q^T, rows are the current
+  // left singular vector estimates).  Each refresh diagonalises G = Y Y^T =
+  // U^T diag U (Jacobi; rows of U are eigenvectors) and sets Y <- U Y,
+  // P <- U P.  At the end the rows of Y are orthogonal to working accuracy,
+  // Y = diag(nrm) Z, and polar(src) = P^T Z.
   const size_t aK = (size_t)a * K;
-  HIPCHK(copy_bytes(M.Y, src, aK * 8, s));
   double* Yc = M.Y;
   double* Yn = M.Y2;
-  double* Qc = M.Q;
-  double* Qn = M.Q2;
+  double* Pc = M.Q;
+  double* Pn = M.Q2;
+  const bool use_warm = warm && warm_valid;
+  if (use_warm) {
+    GemmDesc r = desc0();  // Y = P_warm src
+    r.M = a; r.N = (int)K; r.K = a;
+    r.A = warm; r.sAm = a; r.sAk = 1;
+    r.B = src; r.sBk = K; r.sBn = 1;
+    r.C = Yc; r.sCm = K; r.sCn = 1;
+    HIPCHK(run(M, P_F64, r, s));
+    HIPCHK(copy_bytes(Pc, warm, (size_t)a * a * 8, s));
+  } else {
+    HIPCHK(copy_bytes(Yc, src, aK * 8, s));
+  }
+  const double jtol = std::max(1e-15, 2.2e-16 * a);
   for (int it = 0; it < POLAR_REFRESH; ++it) {
     GemmDesc g = desc0();  // G = Y Y^T
     g.M = a; g.N = a; g.K = (int)K;
@@ -599,31 +629,32 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     {
       size_t slot = 0;
       bool timed = M.prof && M.prof->begin(OC_JACOBI, 0.0, 0.0, s, &slot);
-      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, 1e-15, M.jinfo + 2 * it, s));
+      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, s));
       if (timed) M.prof->end(slot, s);
     }
-    GemmDesc r = desc0();  // Yn = V^T Y
+    GemmDesc r = desc0();  // Yn = U Y
     r.M = a; r.N = (int)K; r.K = a;
-    r.A = M.V; r.sAm = 1; r.sAk = a;
+    r.A = M.V; r.sAm = a; r.sAk = 1;
     r.B = Yc; r.sBk = K; r.sBn = 1;
     r.C = Yn; r.sCm = K; r.sCn = 1;
     HIPCHK(run(M, P_F64, r, s));
-    if (it == 0) {
-      HIPCHK(copy_bytes(Qc, M.V, (size_t)a * a * 8, s));
+    if (it == 0 && !use_warm) {
+      HIPCHK(copy_bytes(Pc, M.V, (size_t)a * a * 8, s));
     } else {
-      HIPCHK(mm(M, P_F64, Qc, false, M.V, false, Qn, a, 1.0, 0.0, s));
-      std::swap(Qc, Qn);
+      HIPCHK(mm(M, P_F64, M.V, false, Pc, false, Pn, a, 1.0, 0.0, s));  // P <- U P
+      std::swap(Pc, Pn);
     }
     std::swap(Yc, Yn);
   }
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
-  GemmDesc f = desc0();  // out = sign * Q Z
+  GemmDesc f = desc0();  // out = sign * P^T Z
   f.M = a; f.N = (int)K; f.K = a;
-  f.A = Qc; f.sAm = a; f.sAk = 1;
+  f.A = Pc; f.sAm = 1; f.sAk = a;
   f.B = Yn; f.sBk = K; f.sBn = 1;
   f.C = out; f.sCm = K; f.sCn = 1;
   f.alpha = sign;
   HIPCHK(run(M, P_F64, f, s));
+  if (warm) HIPCHK(copy_bytes(warm, Pc, (size_t)a * a * 8, s));
   return TTN_OK;
 }
 
@@ -659,8 +690,9 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
   HIPCHK(copy_bytes(M.Y2, M.env64, aK * 8, s));
   HIPCHK(axpy_dev(M.Y2, M.w64[tau], M.scal + SCAL_TMP0, -POLAR_REG, aK, s));
   // polar_core copies its source into M.Y first, so passing M.Y2 is safe
-  ttn_status st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s);
+  ttn_status st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, M.Qw[tau], M.qw_valid[tau] != 0);
   if (st) return st;
+  M.qw_valid[tau] = 1;
   HIPCHK(ratio_minmax(M.nrm, a, M.scal + SCAL_RATIO, M.scal + SCAL_RATIO_MIN, s));
   if ((st = ortho_check(M, tau, s))) return st;
   if ((st = refresh_shadow(M, tau, s))) return st;
@@ -672,22 +704,34 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
   return TTN_OK;
 }
 
-// H_top y for the two sites of level n-1 (float64 copies of the operators)
+// H_top y for the two sites of level n-1 (float64 copies of the operators):
+//   out = h y + y h^T + sum_k (A_k y B_k^T + B_k y A_k^T)
+// as  stage = [y, y B_1^T, .., y B_D^T, y A_1^T, .., y A_D^T]  (two batched
+// products), then out = [h, A_1..A_D, B_1..B_D] . stage (one product whose
+// contraction index runs over the operator blocks), then out += y h^T.
 hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s) {
-  const int x = M.dims[M.n - 1];
-  const size_t xx = (size_t)x * x;
+  const int x = M.dims[M.n - 1], D = M.D;
+  const long long xx = (long long)x * x;
   hipError_t e;
-  if ((e = mm(M, P_F64, M.hop64, false, y, false, out, x, 1.0, 0.0, s))) return e;   // h v
-  if ((e = mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s))) return e;    // v h^T
-  for (int k = 0; k < M.D; ++k) {
-    const double* Ak = M.Aop64 + k * xx;
-    const double* Bk = M.Bop64 + k * xx;
-    if ((e = mm(M, P_F64, y, false, Bk, true, M.lzT, x, 1.0, 0.0, s))) return e;    // v B^T
-    if ((e = mm(M, P_F64, Ak, false, M.lzT, false, out, x, 1.0, 1.0, s))) return e;  // A v B^T
-    if ((e = mm(M, P_F64, y, false, Ak, true, M.lzT, x, 1.0, 0.0, s))) return e;    // v A^T
-    if ((e = mm(M, P_F64, Bk, false, M.lzT, false, out, x, 1.0, 1.0, s))) return e;  // B v A^T
+  if ((e = copy_bytes(M.lzStage, y, xx * 8, s))) return e;
+  if (D > 0) {
+    for (int half = 0; half < 2; ++half) {
+      GemmDesc g = desc0();  // stage[1 + half*D + k] = y . (half ? A_k : B_k)^T
+      g.batch = D;
+      g.M = x; g.N = x; g.K = x;
+      g.A = y; g.sAm = x; g.sAk = 1; g.sAb = 0;
+      g.B = half ? M.Aop64 : M.Bop64; g.sBk = 1; g.sBn = x; g.sBb = xx;
+      g.C = M.lzStage + (1 + half * D) * xx; g.sCm = x; g.sCn = 1; g.sCb = xx;
+      if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
+    }
   }
-  return hipSuccess;
+  GemmDesc g = desc0();  // out = sum_j op_j stage_j
+  g.M = x; g.N = x; g.K = (int)((1 + 2 * D) * x); g.K2 = x;
+  g.A = M.hop64; g.sAm = x; g.sAk = 1; g.sAk1 = xx;
+  g.B = M.lzStage; g.sBk = x; g.sBn = 1; g.sBk1 = xx;
+  g.C = out; g.sCm = x; g.sCn = 1;
+  if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
+  return mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s);  // + y h^T
 }
 
 ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
@@ -750,7 +794,7 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     }
     iters += m;
     HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
-    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, 1e-15, M.jinfo + 16, s));
+    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, s));
     HIPCHK(lz_select_lowest(M.Tm, M.Vm, m, M.ycoef, M.scal + SCAL_THETA, s));
     GemmDesc g = desc0();  // v = Q[0..m-1]^T y
     g.M = 1; g.N = (int)xx; g.K = m;
@@ -1159,6 +1203,12 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out) {
   layer_flops(M, &out->flops_bulk, &out->flops_fp64);
   out->n_levels = M.n;
   out->lanczos_iters = M.lz_iters;
+  int ji[18];
+  HIPCHK(hipMemcpy(ji, M.jinfo, sizeof ji, hipMemcpyDeviceToHost));
+  out->jacobi_sweeps[0] = ji[0];
+  out->jacobi_sweeps[1] = ji[2];
+  out->jacobi_sweeps[2] = ji[4];
+  out->jacobi_sweeps[3] = ji[16];
   return TTN_OK;
 }
 

