@@ -110,6 +110,12 @@ typedef struct ttn_config {
   int krylov;         /* Lanczos basis size per restart (0: 24)               */
   int restarts;       /* Lanczos restarts per top update (0: 8)               */
   double lanczos_tol; /* target ||H v - lambda v|| / ||H||_est (0: 1e-13)     */
+  int keep_gauge;     /* 0 (default): after each update the output index of
+                         w_tau is rotated into the singular basis of its
+                         environment and the layer above (or v) absorbs the
+                         inverse rotation, which leaves the state unchanged
+                         and keeps the next environment's Gram matrix nearly
+                         diagonal; 1: store -polar(Env) as is              */
 } ttn_config;
 
 /* Bytes of device workspace needed by ttn_init for these configs. */
@@ -145,7 +151,10 @@ ttn_status ttn_env(ttn_handle h, int tau);
 
 /* tau in 1..n-1: w_tau <- -polar(Env) = -U V^T for the thin SVD
  *   Env = U S V^T (Sec. III.B, Fig. 10(a)), in float64, followed by the check
- *   ||W W^T - I||_F <= 1e-10 (TTN_EORTHO otherwise).  Does not re-ascend.
+ *   ||W W^T - I||_F <= 1e-10 (reported as TTN_EORTHO by ttn_energy).  Unless
+ *   keep_gauge is set the stored tensor is U^T w_tau = -V^T and w_{tau+1}
+ *   (or v when tau = n-1) absorbs U on its input legs (same state).  Does not
+ *   re-ascend.
  * tau == TTN_TOP: v <- lowest eigenvector of the top Hamiltonian (Lanczos,
  *   float64, warm-started from the current v) and the energy. */
 ttn_status ttn_update(ttn_handle h, int tau);

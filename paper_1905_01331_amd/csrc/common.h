@@ -44,7 +44,13 @@ hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned l
 // return the diagonal holds the eigenvalues), eigenvectors in the ROWS of
 // U (n x n), G_in = U^T diag U.  One work-group.  `info` (device int[4]): [0] sweeps used,
 // [1] rotations in the first sweep.
-hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s);
+// `scratch` (jacobi_blocked_scratch_bytes(n) bytes, may be null for n <= 128)
+// serves the blocked variant taken for n > 128.
+hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, void* scratch,
+                          hipStream_t s);
+hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, double tol, int* info, void* scratch,
+                                  hipStream_t s);
+size_t jacobi_blocked_scratch_bytes(int n);
 // Z[i,:] = Y[i,:] / ||Y[i,:]||  for an m x k matrix (row norms into nrm[m]); rows
 // with a zero norm are left zero.
 hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, long long k, hipStream_t s);

@@ -20,6 +20,12 @@ hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, 
 hipError_t running_max(const double* x, double* run_max, hipStream_t s);
 hipError_t identity_f64(double* X, int n, hipStream_t s);
 hipError_t zero_int(int* x, int n, hipStream_t s);
+// Full reorthogonalisation pass against the first nq rows of Q (row length n):
+// coef[i] = Q[i].w (i < nq), coef[nq] = w.w (before the update), then
+// w -= sum_i coef[i] Q[i].  `part` holds lz_reorth_part_doubles() doubles.
+hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s);
+size_t lz_reorth_part_doubles();
+hipError_t lz_alpha(const double* c1, const double* c2, int j, double* alpha, hipStream_t s);
 // X <- (X + sign X^T) / 2 in place (sign = +1 symmetric, -1 antisymmetric part)
 hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s);
 }  // namespace ttn

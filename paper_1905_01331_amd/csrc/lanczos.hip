@@ -202,6 +202,66 @@ __global__ void k_symmetrize(double* __restrict__ X, int n, double sign) {
   }
 }
 
+// Multi-dot for the full reorthogonalisation: part[b][i] = sum over block b's
+// slice of Q[i] . w (i < nq), part[b][nq] = w . w.  Fixed grid, deterministic.
+constexpr int MD_BLOCKS = 128, MD_THREADS = 256, MD_MAXQ = 64;
+__global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restrict__ Q, const double* __restrict__ w,
+                                                         int nq, size_t n, double* __restrict__ part) {
+  __shared__ double red[MD_THREADS / 64][MD_MAXQ + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  size_t beg = blockIdx.x * chunk, end = beg + chunk < n ? beg + chunk : n;
+  for (int i0 = 0; i0 <= nq; i0 += 16) {
+    double acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+    for (size_t e = beg + tid; e < end; e += MD_THREADS) {
+      double we = w[e];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        int i = i0 + t;
+        if (i < nq) acc[t] += Q[(size_t)i * n + e] * we;
+        else if (i == nq) acc[t] += we * we;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      double v = acc[t];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0 && i0 + t <= nq) red[wv][i0 + t] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i <= nq; i += MD_THREADS) {
+    double v = 0.0;
+    for (int k = 0; k < MD_THREADS / 64; ++k) v += red[k][i];
+    part[(size_t)blockIdx.x * (MD_MAXQ + 1) + i] = v;
+  }
+}
+__global__ void k_multidot_sum(const double* __restrict__ part, int nq, int nblocks, double* __restrict__ out) {
+  for (int i = threadIdx.x; i <= nq; i += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += part[(size_t)b * (MD_MAXQ + 1) + i];
+    out[i] = v;
+  }
+}
+// w -= sum_{i < nq} c[i] Q[i]
+__global__ void k_sub_combination(double* __restrict__ w, const double* __restrict__ Q, const double* __restrict__ c,
+                                  int nq, size_t n) {
+  __shared__ double cs[MD_MAXQ];
+  for (int i = threadIdx.x; i < nq; i += blockDim.x) cs[i] = c[i];
+  __syncthreads();
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double v = w[e];
+    for (int i = 0; i < nq; ++i) v -= cs[i] * Q[(size_t)i * n + e];
+    w[e] = v;
+  }
+}
+// alpha[j] = c1[j] + c2[j]; hss = ||H q_j||^2 before orthogonalisation
+__global__ void k_alpha(const double* __restrict__ c1, const double* __restrict__ c2, int j, double* __restrict__ alpha) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) alpha[j] = c1[j] + c2[j];
+}
+
 __global__ void k_zero_int(int* x, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
 }
@@ -269,6 +329,18 @@ hipError_t identity_f64(double* X, int n, hipStream_t s) {
 }
 hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s) {
   hipLaunchKernelGGL(k_symmetrize, dim3(grid_for((size_t)n * (n + 1) / 2)), dim3(256), 0, s, X, n, sign);
+  return hipGetLastError();
+}
+hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s) {
+  if (nq > MD_MAXQ) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS), dim3(MD_THREADS), 0, s, Q, w, nq, n, part);
+  hipLaunchKernelGGL(k_multidot_sum, dim3(1), dim3(128), 0, s, part, nq, MD_BLOCKS, coef);
+  hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n)), dim3(256), 0, s, w, Q, coef, nq, n);
+  return hipGetLastError();
+}
+size_t lz_reorth_part_doubles() { return (size_t)MD_BLOCKS * (MD_MAXQ + 1); }
+hipError_t lz_alpha(const double* c1, const double* c2, int j, double* alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, s, c1, c2, j, alpha);
   return hipGetLastError();
 }
 hipError_t zero_int(int* x, int n, hipStream_t s) {

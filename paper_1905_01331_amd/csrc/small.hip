@@ -159,12 +159,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __r
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAXN = 1024;
 
-// LDS: the matrix is copied into dynamic shared memory (when it fits) and
-// written back at the end; V stays in global memory.
-template <bool LDS>
-__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ V, int n,
+// MODE 0: G and U in global memory; 1: G copied into dynamic LDS; 2: G and U
+// both in dynamic LDS (copied back at the end).
+template <int MODE>
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ Vg, int n,
                                                         int max_sweeps, double tol, int* info) {
   extern __shared__ double dyn[];
+  constexpr bool LDS = MODE >= 1;
+  double* V = (MODE == 2) ? dyn + (long long)n * n : Vg;
   __shared__ double cs[JAC_MAXN / 2], sn[JAC_MAXN / 2], tn[JAC_MAXN / 2];
   __shared__ int pp[JAC_MAXN / 2], qq[JAC_MAXN / 2];
   __shared__ int rot_count;
@@ -252,6 +254,9 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg,
   if (LDS) {
     for (long long i = tid; i < (long long)n * n; i += blockDim.x) Gg[i] = G[i];
   }
+  if (MODE == 2) {
+    for (long long i = tid; i < (long long)n * n; i += blockDim.x) Vg[i] = V[i];
+  }
   if (tid == 0 && info) {
     info[0] = sweep;
     info[1] = first_rot;
@@ -328,8 +333,10 @@ hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, lon
   hipLaunchKernelGGL(k_row_normalize, dim3(m), dim3(RED_THREADS), 0, s, Y, Z, nrm, k);
   return hipGetLastError();
 }
-hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, hipStream_t s) {
+hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, void* scratch,
+                          hipStream_t s) {
   if (n > JAC_MAXN) return hipErrorInvalidValue;
+  if (n > 64 && scratch) return jacobi_eig_blocked_f64(G, V, n, max_sweeps, tol, info, scratch, s);
   // the matrix goes to LDS when it fits next to the static rotation tables
   static int lds_limit = -1;
   if (lds_limit < 0) {
@@ -344,15 +351,18 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
     const int static_lds = (JAC_MAXN / 2) * (3 * 8 + 2 * 4) + 16;
     lds_limit -= static_lds;
     if (lds_limit > 0 &&
-        hipFuncSetAttribute((const void*)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess)
+        (hipFuncSetAttribute((const void*)k_jacobi<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess ||
+         hipFuncSetAttribute((const void*)k_jacobi<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess))
       lds_limit = 0;
     (void)hipGetLastError();
   }
   size_t bytes = (size_t)n * n * sizeof(double);
-  if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info);
+  if (lds_limit > 0 && 2 * bytes <= (size_t)lds_limit) {
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info);
+  } else if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
+    hipLaunchKernelGGL(k_jacobi<1>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info);
   } else {
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
+    hipLaunchKernelGGL(k_jacobi<0>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
   }
   return hipGetLastError();
 }

@@ -92,7 +92,11 @@ struct Arena {
 
 constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO_MAX = 4, SCAL_RATIO = 5,
               SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10, SCAL_N = 16;
-constexpr int POLAR_REFRESH = 3;
+// Gram refreshes of the polar update: two always, a third when the second
+// Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
+// diagonal, so the rotated rows may not yet be orthogonal to working accuracy)
+constexpr int POLAR_REFRESH = 2;
+constexpr int POLAR_THIRD_IF = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
 
 // Per-handle event timer of contraction classes (enabled by ttn_profile).
@@ -135,6 +139,7 @@ struct Member {
   const double* v0 = nullptr;
   int krylov = 24, restarts = 8;
   double ltol = 1e-13;
+  bool gauge_fix = true;
   // device
   size_t esz = 8;  // bulk element size
   std::vector<double*> w64;
@@ -147,12 +152,14 @@ struct Member {
   double *env64 = nullptr, *Y = nullptr, *Y2 = nullptr, *G = nullptr, *V = nullptr, *Q = nullptr, *Q2 = nullptr,
          *nrm = nullptr;
   int* jinfo = nullptr;
+  void* jscratch = nullptr;
   double* vtop = nullptr;
   void* vT = nullptr;
   void* tmpT = nullptr;  // chi^2 bulk scratch for the top dressing
   double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr, *lzStage = nullptr;
   double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
-  double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr;
+  double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr,
+         *lzpart = nullptr;
   int* lzint = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
@@ -202,7 +209,8 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
   M.krylov = c.krylov > 0 ? c.krylov : 24;
   M.restarts = c.restarts > 0 ? c.restarts : 8;
   M.ltol = c.lanczos_tol > 0 ? c.lanczos_tol : 1e-13;
-  if (M.krylov > 256) return fail(TTN_EINVAL, "krylov=%d > 256", M.krylov);
+  M.gauge_fix = (c.keep_gauge == 0);
+  if (M.krylov > 63) return fail(TTN_EINVAL, "krylov=%d > 63", M.krylov);
   const int d = c.d, D = c.D;
   M.h1.assign(c.h1, c.h1 + d * d);
   M.A.assign(D ? c.A : nullptr, D ? c.A + (size_t)D * d * d : nullptr);
@@ -317,6 +325,7 @@ void layout_member(Member& M, Arena& ar) {
   M.Q2 = ar.take<double>(c2);
   M.nrm = ar.take<double>(cmax);
   M.jinfo = ar.take<int>(64);
+  M.jscratch = ar.take_bytes(jacobi_blocked_scratch_bytes(std::max(cmax, M.krylov)));
   M.vtop = ar.take<double>(xx);
   M.vT = (M.prec == TTN_FP64) ? (void*)M.vtop : ar.take_bytes(M.el(xx));
   M.tmpT = ar.take_bytes(M.el(xx));
@@ -337,7 +346,8 @@ void layout_member(Member& M, Arena& ar) {
   M.Tm = ar.take<double>((size_t)m * m);
   M.Vm = ar.take<double>((size_t)m * m);
   M.ycoef = ar.take<double>(m + 1);
-  M.coef = ar.take<double>(m + 1);
+  M.coef = ar.take<double>(2 * (m + 2));
+  M.lzpart = ar.take<double>(lz_reorth_part_doubles());
   M.lzint = ar.take<int>(16);
   M.scal = ar.take<double>(SCAL_N);
   M.part = ar.take<double>(256);
@@ -595,7 +605,7 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
 // settles, so the Jacobi sweeps of the first refresh drop; the result is the
 // same polar factor.  The final rotation is written back to `warm`.
 ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,
-                      double* warm = nullptr, bool warm_valid = false) {
+                      double* warm = nullptr, bool warm_valid = false, double** p_out = nullptr) {
   // Invariant: Y = P src with P orthogonal (P = Q^T, rows are the current
   // left singular vector estimates).  Each refresh diagonalises G = Y Y^T =
   // U^T diag U (Jacobi; rows of U are eigenvectors) and sets Y <- U Y,
@@ -619,7 +629,8 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     HIPCHK(copy_bytes(Yc, src, aK * 8, s));
   }
   const double jtol = std::max(1e-15, 2.2e-16 * a);
-  for (int it = 0; it < POLAR_REFRESH; ++it) {
+  int refreshes = POLAR_REFRESH;
+  for (int it = 0; it < refreshes; ++it) {
     GemmDesc g = desc0();  // G = Y Y^T
     g.M = a; g.N = a; g.K = (int)K;
     g.A = Yc; g.sAm = K; g.sAk = 1;
@@ -629,7 +640,7 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     {
       size_t slot = 0;
       bool timed = M.prof && M.prof->begin(OC_JACOBI, 0.0, 0.0, s, &slot);
-      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, s));
+      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, s));
       if (timed) M.prof->end(slot, s);
     }
     GemmDesc r = desc0();  // Yn = U Y
@@ -645,8 +656,20 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
       std::swap(Pc, Pn);
     }
     std::swap(Yc, Yn);
+    if (it == POLAR_REFRESH - 1 && refreshes == POLAR_REFRESH) {
+      int info[2] = {0, 0};
+      HIPCHK(hipMemcpyAsync(info, M.jinfo + 2 * it, sizeof info, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (info[0] > POLAR_THIRD_IF) refreshes = POLAR_REFRESH + 1;
+    }
   }
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
+  if (p_out) {
+    // gauge-fixed result: out = sign * Z, the rotation P is handed back
+    HIPCHK(axpby_f64(Yn, out, sign, 0.0, aK, s));
+    *p_out = Pc;
+    return TTN_OK;
+  }
   GemmDesc f = desc0();  // out = sign * P^T Z
   f.M = a; f.N = (int)K; f.K = a;
   f.A = Pc; f.sAm = 1; f.sAk = a;
@@ -689,10 +712,31 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
   HIPCHK(sqrt_inplace(M.scal + SCAL_TMP0, s));
   HIPCHK(copy_bytes(M.Y2, M.env64, aK * 8, s));
   HIPCHK(axpy_dev(M.Y2, M.w64[tau], M.scal + SCAL_TMP0, -POLAR_REG, aK, s));
-  // polar_core copies its source into M.Y first, so passing M.Y2 is safe
-  ttn_status st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, M.Qw[tau], M.qw_valid[tau] != 0);
-  if (st) return st;
-  M.qw_valid[tau] = 1;
+  // polar_core consumes its source before it reuses M.Y2
+  ttn_status st;
+  if (M.gauge_fix) {
+    double* P = nullptr;
+    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, nullptr, false, &P);
+    if (st) return st;
+    // absorb P^T on the input legs of the layer above: w' = P .l (P .r w),
+    // or v' = P v P^T at the top
+    if (tau < M.n - 1) {
+      const int c2 = M.dims[tau + 1];
+      HIPCHK(apply_r(M, P_F64, P, M.w64[tau + 1], M.Y2, c2, a, 0.0, s));
+      HIPCHK(apply_l(M, P_F64, P, M.Y2, M.w64[tau + 1], c2, a, 0.0, s));
+      if ((st = refresh_shadow(M, tau + 1, s))) return st;
+      M.pc_from = std::max(M.pc_from, tau + 2);
+    } else {
+      HIPCHK(mm(M, P_F64, P, false, M.vtop, false, M.G, a, 1.0, 0.0, s));
+      HIPCHK(mm(M, P_F64, M.G, false, P, true, M.vtop, a, 1.0, 0.0, s));
+      if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, (size_t)a * a, s));
+      M.rho_from = M.pc_from = 1 << 20;
+    }
+  } else {
+    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, M.Qw[tau], M.qw_valid[tau] != 0);
+    if (st) return st;
+    M.qw_valid[tau] = 1;
+  }
   HIPCHK(ratio_minmax(M.nrm, a, M.scal + SCAL_RATIO, M.scal + SCAL_RATIO_MIN, s));
   if ((st = ortho_check(M, tau, s))) return st;
   if ((st = refresh_shadow(M, tau, s))) return st;
@@ -768,33 +812,21 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     HIPCHK(zero_int(M.lzint, 16, s));
     for (int j = 0; j < m; ++j) {
       double* qj = M.lzQ + (size_t)j * xx;
-      const double* qjm1 = j ? M.lzQ + (size_t)(j - 1) * xx : qj;
       HIPCHK(top_matvec(M, qj, M.lzW, s));
-      HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP1, M.part, s));
-      HIPCHK(pair_f64(qj, M.lzW, (long long)xx, M.alpha + j, M.part, s));
-      HIPCHK(lz_three_term(M.lzW, qj, qjm1, M.alpha, M.beta, j, xx, M.lzint, s));
-      for (int pass = 0; pass < 2; ++pass) {  // full reorthogonalisation
-        GemmDesc g = desc0();  // coef = Q[0..j] w
-        g.M = j + 1; g.N = 1; g.K = (int)xx;
-        g.A = M.lzQ; g.sAm = (long long)xx; g.sAk = 1;
-        g.B = M.lzW; g.sBk = 1; g.sBn = 1;
-        g.C = M.coef; g.sCm = 1; g.sCn = 1;
-        HIPCHK(run(M, P_F64, g, s, OC_LANCZOS_GEMM));
-        GemmDesc h = desc0();  // w -= Q[0..j]^T coef
-        h.M = 1; h.N = (int)xx; h.K = j + 1;
-        h.A = M.coef; h.sAm = 0; h.sAk = 1;
-        h.B = M.lzQ; h.sBk = (long long)xx; h.sBn = 1;
-        h.C = M.lzW; h.sCm = 0; h.sCn = 1;
-        h.alpha = -1.0; h.beta = 1.0;
-        HIPCHK(run(M, P_F64, h, s, OC_LANCZOS_GEMM));
-      }
+      // two passes of classical Gram-Schmidt against q_0..q_j: the first
+      // also yields alpha_j and ||H q_j||^2, the second repairs round-off
+      double* c1 = M.coef;
+      double* c2 = M.coef + (m + 2);
+      HIPCHK(lz_reorth(M.lzW, M.lzQ, j + 1, xx, c1, M.lzpart, s));
+      HIPCHK(lz_reorth(M.lzW, M.lzQ, j + 1, xx, c2, M.lzpart, s));
+      HIPCHK(lz_alpha(c1, c2, j, M.alpha, s));
       HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
-      HIPCHK(lz_set_beta(M.scal + SCAL_TMP0, M.scal + SCAL_TMP1, M.beta, j, 1e-12, M.lzint, M.lzint + 1, s));
+      HIPCHK(lz_set_beta(M.scal + SCAL_TMP0, c1 + (j + 1), M.beta, j, 1e-12, M.lzint, M.lzint + 1, s));
       HIPCHK(lz_next_q(M.lzW, M.lzQ + (size_t)(j + 1) * xx, M.beta, j, xx, M.lzint, s));
     }
     iters += m;
     HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
-    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, s));
+    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, M.jscratch, s));
     HIPCHK(lz_select_lowest(M.Tm, M.Vm, m, M.ycoef, M.scal + SCAL_THETA, s));
     GemmDesc g = desc0();  // v = Q[0..m-1]^T y
     g.M = 1; g.N = (int)xx; g.K = m;
@@ -907,7 +939,8 @@ void layer_flops(const Member& M, double* bulk, double* f64) {
       desc += D * (12 * aa * bb * bb * bb + 4 * aa * aa * bb * bb);
     }
     F += env + reasc + chain + desc;
-    // float64: polar (POLAR_REFRESH Gram + rotate, final product) + orthonormality Gram
+    // float64: polar (POLAR_REFRESH Gram + rotate, gauge compensation or
+    // final product) + orthonormality Gram
     G += (POLAR_REFRESH * 4.0 + 2.0 + 2.0) * a * a * b * b;
   }
   for (int sg = 2; sg < n; ++sg) {

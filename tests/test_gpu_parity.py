@@ -40,6 +40,9 @@ CASES = [
     ("tfim_L64_chi24", I.tfim_chain(0.9), 64, 24),
     ("torus8x3_chi20", I.torus_tfim_column(3, 3.0), 8, 20),
     ("tfim_L128_chi70", I.tfim_chain(1.1), 128, 70),
+    # environments with more than 128 rows take the blocked Jacobi path
+    ("tfim_L32_chi160", I.tfim_chain(0.8), 32, 160),
+    ("xxx_L32_chi256", I.xxx_chain(), 32, 256),
 ]
 
 
@@ -49,7 +52,7 @@ def test_stage_parity_fp64(B, name, model, L, chi):
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 5)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
     ref.initialise()
-    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, keep_gauge=True))
     n = ref.n
     e = gpu.energy()[0]
     assert abs(e - ref.history[0]) <= 1e-12 * abs(ref.history[0]) + 1e-14
@@ -88,7 +91,7 @@ def test_stage_parity_fp64(B, name, model, L, chi):
         a = w_gpu.shape[0]
         W = w_gpu.reshape(a, -1)
         E = env.reshape(a, -1)
-        assert np.abs(W @ W.T - np.eye(a)).max() < 1e-13
+        assert np.abs(W @ W.T - np.eye(a)).max() < 2e-15 * max(a, 50)
         Mx = -E @ W.T
         scale = float(s[0])
         assert np.abs(Mx - Mx.T).max() <= 1e-12 * scale
@@ -112,23 +115,28 @@ def test_stage_parity_fp64(B, name, model, L, chi):
 
 # Sweeps from identical states: (name, model, L, chi, sweeps, tolerance).
 # Well-conditioned environments (sigma_min/sigma_max > 1e-9) are held to
-# 1e-10; the cfg-1 chain has environments with sigma_min/sigma_max ~ 1e-11,
-# where two LAPACK SVD drivers already disagree by ~5e-8 after 30 sweeps,
-# so each sweep is compared from the reference's state (re-anchored).
+# 1e-10.  The L = 16, chi = 8 chain has environments with sigma_min/sigma_max
+# ~ 1e-11: the polar factor is determined there only to ~1e-16/1e-11 in the
+# weakest directions, and two LAPACK SVD drivers (gesdd, gesvd) run on the
+# same sweeps already disagree by 4.9e-8 in the energy; each sweep is
+# compared from the reference's state (re-anchored) and held to 5e-8.
 SWEEPS = [
     ("tfim_L64_chi3", I.tfim_chain(1.0), 64, 3, 6, 1e-10),
     ("xxx_L64_chi3", I.xxx_chain(), 64, 3, 6, 1e-10),
-    ("tfim_L16_chi8_cfg1", I.tfim_chain(1.0), 16, 8, 6, 1e-8),
+    ("tfim_L16_chi8_cfg1", I.tfim_chain(1.0), 16, 8, 6, 5e-8),
 ]
 
 
+@pytest.mark.parametrize("keep_gauge", [True, False], ids=["plain", "gauge_fixed"])
 @pytest.mark.parametrize("name,model,L,chi,sweeps,tol", SWEEPS, ids=[c[0] for c in SWEEPS])
-def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol):
-    print(f"[sweep parity] {name}", flush=True)
+def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol, keep_gauge):
+    # the basis rotation of the gauge-fixed mode leaves the state, hence every
+    # energy, unchanged
+    print(f"[sweep parity] {name} keep_gauge={keep_gauge}", flush=True)
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 0)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
     ref.initialise()
-    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, keep_gauge=keep_gauge))
     worst = 0.0
     for s in range(sweeps):
         for tau in range(1, ref.n):
@@ -144,12 +152,13 @@ def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol):
     gpu.close()
 
 
-def test_unanchored_sweeps_well_conditioned(B):
+@pytest.mark.parametrize("keep_gauge", [True, False], ids=["plain", "gauge_fixed"])
+def test_unanchored_sweeps_well_conditioned(B, keep_gauge):
     model, L, chi = I.xxx_chain(), 64, 3
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 1)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ws=ws)
     hist = ref.run(8)
-    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, keep_gauge=keep_gauge))
     e = [gpu.energy()[0]]
     for _ in range(8):
         gpu.sweep(1)

@@ -64,7 +64,7 @@ def test_stage_precision(B, prec, name, model, L, chi):
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 2)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
     ref.initialise()
-    gpu = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    gpu = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws, keep_gauge=True))
     n = ref.n
     worst = {}
     for lvl in range(1, n):
