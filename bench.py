@@ -193,6 +193,7 @@ def main():
         "ortho_err_max": st.ortho_err_max,
         "jacobi_sweeps_last": list(st.jacobi_sweeps),
         "lanczos_iters_last": st.lanczos_iters,
+        "lanczos_resid_last": st.lanczos_resid,
         "roofline": roofline,
         "classes": classes,
         "cpu_baseline": cpu,

@@ -109,7 +109,7 @@ typedef struct ttn_config {
                          eigensolver (else a fixed deterministic vector)      */
   int krylov;         /* Lanczos basis size per restart (0: 24)               */
   int restarts;       /* Lanczos restarts per top update (0: 8)               */
-  double lanczos_tol; /* target ||H v - lambda v|| / ||H||_est (0: 1e-13)     */
+  double lanczos_tol; /* target ||H v - lambda v|| / max(1, |lambda|) (0: 1e-12) */
   int keep_gauge;     /* 0 (default): after each update the output index of
                          w_tau is rotated into the singular basis of its
                          environment and the layer above (or v) absorbs the

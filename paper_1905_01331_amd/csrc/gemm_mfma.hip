@@ -467,13 +467,13 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
   int splits = 1;
   if (tiles < 1024) {
-    long long want = (2048 + tiles - 1) / tiles;
+    long long want = (1024 + tiles - 1) / tiles;
     long long maxk = g.K / (4 * BK64);
     long long sps = want < maxk ? want : maxk;
     size_t slice = (size_t)g.batch * g.M * g.N * sizeof(double);
     long long fit = (long long)(scratch_bytes / slice);
     if (sps > fit) sps = fit;
-    if (sps > 256) sps = 256;
+    if (sps > 128) sps = 128;
     splits = sps < 1 ? 1 : (int)sps;
   }
   int kchunk = (g.K + splits - 1) / splits;
@@ -510,13 +510,13 @@ hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch
   long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
   int splits = 1;
   if (tiles < 1024) {
-    long long want = (2048 + tiles - 1) / tiles;
+    long long want = (1024 + tiles - 1) / tiles;
     long long maxk = g.K / (4 * BK);
     long long sps = want < maxk ? want : maxk;
     size_t slice = (size_t)g.batch * g.M * g.N * sizeof(float);
     long long fit = (long long)(scratch_bytes / slice);
     if (sps > fit) sps = fit;
-    if (sps > 256) sps = 256;
+    if (sps > 128) sps = 128;
     splits = sps < 1 ? 1 : (int)sps;
   }
   int kchunk = (g.K + splits - 1) / splits;

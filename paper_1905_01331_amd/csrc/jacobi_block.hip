@@ -6,11 +6,10 @@
 // each block pair (I, J) the 64 x 64 sub-matrix G[I u J, I u J] is loaded
 // into LDS and given one cyclic sweep of 2 x 2 Jacobi rotations (relative
 // threshold, Rutishauser updates), which yields an orthogonal R (rows) and
-// the rotated sub-matrix S' = R G_sub R^T.  Then rows I u J of G and of the
-// eigenvector matrix U are replaced by R times themselves, and columns
-// I u J of G by themselves times R^T (the diagonal block takes S' directly).
-// Every product is spread over many work-groups; the three steps of a round
-// are three launches.  A sweep with no rotation anywhere ends the iteration:
+// the rotated sub-matrix S' = R G_sub R^T; the same work-group then replaces
+// rows I u J of G and of the eigenvector matrix U by R times themselves.  A
+// second launch replaces columns I u J of G by themselves times R^T (the
+// diagonal block takes S' directly), spread over row chunks.  A sweep with no rotation anywhere ends the iteration:
 // every later launch returns at once.
 #include "common.h"
 #include <math.h>
@@ -18,7 +17,7 @@
 namespace ttn {
 namespace {
 
-constexpr int BJ_K = 32, BJ_S = 64, BJ_T = 256;
+constexpr int BJ_K = 32, BJ_S = 64, BJ_T = 1024, BJ_U = 256;
 
 __device__ __forceinline__ void bj_pair(int nb, int r, int j, int& I, int& J) {
   if (j == 0) { I = r; J = nb - 1; }
@@ -32,12 +31,15 @@ __device__ __forceinline__ int bj_gidx(int I, int J, int i, int n) {
 // sweep s is skipped once some earlier sweep made no rotation
 __device__ __forceinline__ bool bj_done(const int* cnt, int sweep) { return sweep > 0 && cnt[sweep - 1] == 0; }
 
-__global__ __launch_bounds__(BJ_T) void k_bj_solve(const double* __restrict__ G, int n, int nb, int sweep, int r,
-                                                  double tol, int inner, int* __restrict__ cnt,
+// Solves the sub-problem of pair j (one sweep of 2 x 2 rotations), writes R
+// and S', then replaces rows I u J of G and U by R times themselves.
+__global__ __launch_bounds__(BJ_T) void k_bj_solve(double* __restrict__ G, double* __restrict__ U, int n, int nb,
+                                                  int sweep, int r, double tol, int* __restrict__ cnt,
                                                   double* __restrict__ Rbuf, double* __restrict__ Sbuf) {
   if (bj_done(cnt, sweep)) return;
   __shared__ double S[BJ_S][BJ_S + 1];
   __shared__ double R[BJ_S][BJ_S + 1];
+  __shared__ double T[BJ_S][BJ_S + 1];
   __shared__ double cs[BJ_S / 2], sn[BJ_S / 2], tn[BJ_S / 2];
   __shared__ int pp[BJ_S / 2], qq[BJ_S / 2], gid[BJ_S];
   __shared__ int rc;
@@ -54,34 +56,30 @@ __global__ __launch_bounds__(BJ_T) void k_bj_solve(const double* __restrict__ G,
     R[i][k] = (i == k) ? 1.0 : 0.0;
   }
   __syncthreads();
-  int total = 0;
-  for (int sw = 0; sw < inner; ++sw) {
-    int before = rc;
-    __syncthreads();
-    for (int rr = 0; rr < BJ_S - 1; ++rr) {
-      if (tid < BJ_S / 2) {
-        int k = tid, p, q;
-        if (k == 0) { p = rr; q = BJ_S - 1; }
-        else { p = (rr + k) % (BJ_S - 1); q = (rr - k + (BJ_S - 1)) % (BJ_S - 1); }
-        if (p > q) { int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (gid[p] >= 0 && gid[q] >= 0) {
-          double gpp = S[p][p], gqq = S[q][q], gpq = S[p][q];
-          if (gpq != 0.0 && fabs(gpq) > tol * sqrt(fabs(gpp * gqq))) {
-            double theta = (gqq - gpp) / (2.0 * gpq);
-            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            atomicAdd(&rc, 1);
-          }
+  for (int rr = 0; rr < BJ_S - 1; ++rr) {
+    if (tid < BJ_S / 2) {
+      int k = tid, p, q;
+      if (k == 0) { p = rr; q = BJ_S - 1; }
+      else { p = (rr + k) % (BJ_S - 1); q = (rr - k + (BJ_S - 1)) % (BJ_S - 1); }
+      if (p > q) { int t = p; p = q; q = t; }
+      double c = 1.0, s = 0.0, t = 0.0;
+      if (gid[p] >= 0 && gid[q] >= 0) {
+        double gpp = S[p][p], gqq = S[q][q], gpq = S[p][q];
+        if (gpq != 0.0 && fabs(gpq) > tol * sqrt(fabs(gpp * gqq))) {
+          double theta = (gqq - gpp) / (2.0 * gpq);
+          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          atomicAdd(&rc, 1);
         }
-        pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t;
       }
-      __syncthreads();
-      for (int e = tid; e < (BJ_S / 2) * (BJ_S / 2); e += BJ_T) {
-        int k1 = e / (BJ_S / 2), k2 = e % (BJ_S / 2);
-        double s1 = sn[k1], s2 = sn[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
+      pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t;
+    }
+    __syncthreads();
+    {  // one 2x2 block of S per thread
+      const int k1 = tid >> 5, k2 = tid & 31;
+      double s1 = sn[k1], s2 = sn[k2];
+      if (s1 != 0.0 || s2 != 0.0) {
         int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
         double c1 = cs[k1], c2 = cs[k2];
         double gpp = S[p1][p2], gpq = S[p1][q2], gqp = S[q1][p2], gqq = S[q1][q2];
@@ -98,23 +96,23 @@ __global__ __launch_bounds__(BJ_T) void k_bj_solve(const double* __restrict__ G,
         }
         S[p1][p2] = npp; S[p1][q2] = npq; S[q1][p2] = nqp; S[q1][q2] = nqq;
       }
-      for (int e = tid; e < (BJ_S / 2) * BJ_S; e += BJ_T) {
-        int k = e / BJ_S, i = e % BJ_S;
-        double s = sn[k];
-        if (s == 0.0) continue;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // two entries of a rotated pair of R rows per thread
+      int e = tid + h * BJ_T;
+      int k = e / BJ_S, i = e % BJ_S;
+      double s = sn[k];
+      if (s != 0.0) {
         double c = cs[k];
         int p = pp[k], q = qq[k];
         double up = R[p][i], uq = R[q][i];
         R[p][i] = c * up - s * uq;
         R[q][i] = s * up + c * uq;
       }
-      __syncthreads();
     }
-    total = rc;
     __syncthreads();
-    if (rc == before) break;
   }
-  if (tid == 0 && total) atomicAdd(&cnt[sweep], total);
+  if (tid == 0 && rc) atomicAdd(&cnt[sweep], rc);
   double* Ro = Rbuf + (long long)j * BJ_S * BJ_S;
   double* So = Sbuf + (long long)j * BJ_S * BJ_S;
   for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
@@ -122,52 +120,52 @@ __global__ __launch_bounds__(BJ_T) void k_bj_solve(const double* __restrict__ G,
     Ro[e] = R[i][k];
     So[e] = S[i][k];
   }
-}
-
-// rows I u J of G and U <- R (rows), one 64-column chunk per work-group
-__global__ __launch_bounds__(BJ_T) void k_bj_rows(double* __restrict__ G, double* __restrict__ U, int n, int nb,
-                                                 int sweep, int r, const int* __restrict__ cnt,
-                                                 const double* __restrict__ Rbuf) {
-  if (bj_done(cnt, sweep)) return;
-  __shared__ double Rl[BJ_S][BJ_S + 1];
-  __shared__ double T[BJ_S][BJ_S + 1];
-  __shared__ int gid[BJ_S];
-  const int tid = threadIdx.x, j = blockIdx.x, c0 = blockIdx.y * BJ_S;
-  int I, J;
-  bj_pair(nb, r, j, I, J);
-  if (tid < BJ_S) gid[tid] = bj_gidx(I, J, tid, n);
-  const double* Rj = Rbuf + (long long)j * BJ_S * BJ_S;
-  for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) Rl[e / BJ_S][e % BJ_S] = Rj[e];
-  __syncthreads();
+  // rows I u J of G and U <- R times themselves, one 64-column chunk at a
+  // time; quarter q of the work-group computes rows 16q .. 16q+15
+  const int qtr = tid >> 8, t = tid & 255;
+  const int nchunks = (n + BJ_S - 1) / BJ_S;
   for (int which = 0; which < 2; ++which) {
     double* X = which ? U : G;
-    for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
-      int i = e / BJ_S, col = e % BJ_S;
-      int gi = gid[i], gc = c0 + col;
-      T[i][col] = (gi >= 0 && gc < n) ? X[(long long)gi * n + gc] : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
-      int i = e / BJ_S, col = e % BJ_S;
-      int gi = gid[i], gc = c0 + col;
-      if (gi < 0 || gc >= n) continue;
-      double acc = 0.0;
+    // chunk by chunk, all 1024 threads: load, then 4 quarters compute 16 rows each
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int c0 = ch * BJ_S;
+      __syncthreads();
+      for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
+        int i = e / BJ_S, col = e % BJ_S;
+        int gi = gid[i], gc = c0 + col;
+        T[i][col] = (gi >= 0 && gc < n) ? X[(long long)gi * n + gc] : 0.0;
+      }
+      __syncthreads();
+      // quarter q computes output rows 16q .. 16q+15, thread t: row 16q + t/16, 4 columns
+      const int row = 16 * qtr + (t >> 4), cg = (t & 15);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-      for (int m = 0; m < BJ_S; ++m) acc = fma(Rl[i][m], T[m][col], acc);
-      X[(long long)gi * n + gc] = acc;
+      for (int m = 0; m < BJ_S; ++m) {
+        double rv = R[row][m];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(rv, T[m][cg + 16 * u], acc[u]);
+      }
+      const int gi = gid[row];
+      if (gi >= 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int gc = c0 + cg + 16 * u;
+          if (gc < n) X[(long long)gi * n + gc] = acc[u];
+        }
+      }
     }
-    __syncthreads();
   }
 }
 
 // columns I u J of G <- themselves times R^T, one 64-row chunk per
-// work-group; the diagonal block (rows in I u J) takes S' directly
-__global__ __launch_bounds__(BJ_T) void k_bj_cols(double* __restrict__ G, int n, int nb, int sweep, int r,
+// work-group (256 threads, 4 x 4 register tiles); the diagonal block (rows in
+// I u J) takes S' directly
+__global__ __launch_bounds__(BJ_U) void k_bj_cols(double* __restrict__ G, int n, int nb, int sweep, int r,
                                                  const int* __restrict__ cnt, const double* __restrict__ Rbuf,
                                                  const double* __restrict__ Sbuf) {
   if (bj_done(cnt, sweep)) return;
-  __shared__ double Rl[BJ_S][BJ_S + 1];
-  __shared__ double T[BJ_S][BJ_S + 1];
+  __shared__ double Rt[BJ_S][BJ_S + 1];  // Rt[m][i] = R[i][m]
+  __shared__ double T[BJ_S][BJ_S + 1];   // T[row][m]
   __shared__ int gid[BJ_S];
   const int tid = threadIdx.x, j = blockIdx.x, r0 = blockIdx.y * BJ_S;
   int I, J;
@@ -175,30 +173,46 @@ __global__ __launch_bounds__(BJ_T) void k_bj_cols(double* __restrict__ G, int n,
   if (tid < BJ_S) gid[tid] = bj_gidx(I, J, tid, n);
   const double* Rj = Rbuf + (long long)j * BJ_S * BJ_S;
   const double* Sj = Sbuf + (long long)j * BJ_S * BJ_S;
-  for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) Rl[e / BJ_S][e % BJ_S] = Rj[e];
+  for (int e = tid; e < BJ_S * BJ_S; e += BJ_U) Rt[e % BJ_S][e / BJ_S] = Rj[e];
   __syncthreads();
-  for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
+  for (int e = tid; e < BJ_S * BJ_S; e += BJ_U) {
     int row = e / BJ_S, i = e % BJ_S;
     int gr = r0 + row, gi = gid[i];
     T[row][i] = (gr < n && gi >= 0) ? G[(long long)gr * n + gi] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < BJ_S * BJ_S; e += BJ_T) {
-    int row = e / BJ_S, i = e % BJ_S;
-    int gr = r0 + row, gi = gid[i];
-    if (gr >= n || gi < 0) continue;
+  // out[row][i] = sum_m T[row][m] Rt[m][i]
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+  for (int m = 0; m < BJ_S; ++m) {
+    double x[4], y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = T[ty + 16 * a][m];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[b] = Rt[m][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(x[a], y[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    int row = ty + 16 * a, gr = r0 + row;
+    if (gr >= n) continue;
     int blk = gr / BJ_K;
-    double v;
-    if (blk == I || blk == J) {
-      int loc = (blk == I ? 0 : BJ_K) + (gr & (BJ_K - 1));
-      v = Sj[loc * BJ_S + i];
-    } else {
-      double acc = 0.0;
-#pragma unroll 8
-      for (int m = 0; m < BJ_S; ++m) acc = fma(T[row][m], Rl[i][m], acc);
-      v = acc;
+    bool diag = (blk == I || blk == J);
+    int loc = (blk == I ? 0 : BJ_K) + (gr & (BJ_K - 1));
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int i = tx + 16 * b, gi = gid[i];
+      if (gi < 0) continue;
+      G[(long long)gr * n + gi] = diag ? Sj[loc * BJ_S + i] : acc[a][b];
     }
-    G[(long long)gr * n + gi] = v;
   }
 }
 
@@ -240,9 +254,8 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
   const int chunks = (n + BJ_S - 1) / BJ_S;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r) {
-      hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(BJ_T), 0, s, G, n, nb, sw, r, tol, 1, cnt, Rbuf, Sbuf);
-      hipLaunchKernelGGL(k_bj_rows, dim3(npairs, chunks), dim3(BJ_T), 0, s, G, U, n, nb, sw, r, cnt, Rbuf);
-      hipLaunchKernelGGL(k_bj_cols, dim3(npairs, chunks), dim3(BJ_T), 0, s, G, n, nb, sw, r, cnt, Rbuf, Sbuf);
+      hipLaunchKernelGGL(k_bj_solve, dim3(npairs), dim3(BJ_T), 0, s, G, U, n, nb, sw, r, tol, cnt, Rbuf, Sbuf);
+      hipLaunchKernelGGL(k_bj_cols, dim3(npairs, chunks), dim3(BJ_U), 0, s, G, n, nb, sw, r, cnt, Rbuf, Sbuf);
     }
     // every few sweeps ask whether the last sweep made any rotation
     if (sw % 3 == 2 && sw + 1 < max_sweeps) {

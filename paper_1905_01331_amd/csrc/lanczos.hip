@@ -238,12 +238,18 @@ __global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restric
     part[(size_t)blockIdx.x * (MD_MAXQ + 1) + i] = v;
   }
 }
-__global__ void k_multidot_sum(const double* __restrict__ part, int nq, int nblocks, double* __restrict__ out) {
-  for (int i = threadIdx.x; i <= nq; i += blockDim.x) {
-    double v = 0.0;
-    for (int b = 0; b < nblocks; ++b) v += part[(size_t)b * (MD_MAXQ + 1) + i];
-    out[i] = v;
+// one block per output: fixed-shape tree over the per-block partials
+__global__ __launch_bounds__(MD_BLOCKS) void k_multidot_sum(const double* __restrict__ part, int nq, int nblocks,
+                                                            double* __restrict__ out) {
+  __shared__ double sh[MD_BLOCKS];
+  const int i = blockIdx.x;
+  sh[threadIdx.x] = threadIdx.x < nblocks ? part[(size_t)threadIdx.x * (MD_MAXQ + 1) + i] : 0.0;
+  __syncthreads();
+  for (int st = MD_BLOCKS / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[i] = sh[0];
 }
 // w -= sum_{i < nq} c[i] Q[i]
 __global__ void k_sub_combination(double* __restrict__ w, const double* __restrict__ Q, const double* __restrict__ c,
@@ -334,7 +340,7 @@ hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s) {
 hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s) {
   if (nq > MD_MAXQ) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS), dim3(MD_THREADS), 0, s, Q, w, nq, n, part);
-  hipLaunchKernelGGL(k_multidot_sum, dim3(1), dim3(128), 0, s, part, nq, MD_BLOCKS, coef);
+  hipLaunchKernelGGL(k_multidot_sum, dim3(nq + 1), dim3(MD_BLOCKS), 0, s, part, nq, MD_BLOCKS, coef);
   hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n)), dim3(256), 0, s, w, Q, coef, nq, n);
   return hipGetLastError();
 }
