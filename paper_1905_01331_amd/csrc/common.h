@@ -40,6 +40,30 @@ hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size
 hipError_t axpby_f32(const float* x, float* y, float alpha, float beta, size_t n, hipStream_t s);
 hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned long long stream_id, hipStream_t s);
 
+// One 2 x 2 Jacobi rotation of the pair (p, q) of a symmetric matrix with
+// diagonal gpp, gqq and off-diagonal gpq.  t = tan(phi) is the root of
+// t^2 + 2 theta t - 1 = 0 of smaller magnitude, theta = (gqq - gpp) / (2 gpq),
+// computed without forming theta:  t = sgn(x) y / (|x| + sqrt(x^2 + y^2)),
+// x = gqq - gpp, y = 2 gpq;  c = 1/sqrt(1 + t^2) (hardware reciprocal square
+// root plus two Newton steps), s = t c.  The pair is skipped (returns false,
+// c = 1, s = t = 0) when |gpq| <= tol sqrt(|gpp gqq|): a relative threshold,
+// so that small eigenvalues of a graded matrix keep their relative accuracy
+// (Demmel and Veselic 1992).
+__device__ __forceinline__ bool jacobi_rotation(double gpp, double gqq, double gpq, double tol, double& c, double& s,
+                                                double& t) {
+  c = 1.0; s = 0.0; t = 0.0;
+  if (gpq == 0.0 || gpq * gpq <= tol * tol * fabs(gpp * gqq)) return false;
+  const double x = gqq - gpp, y = 2.0 * gpq;
+  t = (x >= 0.0 ? y : -y) / (fabs(x) + sqrt(x * x + y * y));
+  const double z = 1.0 + t * t;
+  double r = __builtin_amdgcn_rsq(z);
+  r = r * (1.5 - 0.5 * z * r * r);
+  r = r * (1.5 - 0.5 * z * r * r);
+  c = r;
+  s = t * r;
+  return true;
+}
+
 // Jacobi eigensolver of a symmetric n x n float64 matrix G (in place; on
 // return the diagonal holds the eigenvalues), eigenvectors in the ROWS of
 // U (n x n), G_in = U^T diag U.  One work-group.  `info` (device int[4]): [0] sweeps used,

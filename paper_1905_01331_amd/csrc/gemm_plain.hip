@@ -174,20 +174,30 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
 
 }  // namespace
 
-// Deterministic split-K reduction: C = alpha * sum_s P[s] + beta * C, the
-// partial slices summed in increasing split order.
+// Deterministic split-K reduction: C = alpha * sum_s P[s] + beta * C.  Eight
+// independent partial sums over the splits s = 8q + u (u = 0..7) keep eight
+// loads in flight per thread; they are combined in a fixed tree, so the
+// result does not depend on timing.
 template <typename T>
 __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict__ partial) {
   long long total = (long long)g.batch * g.M * g.N;
   long long MN = (long long)g.M * g.N;
+  long long stride = (long long)g.batch * MN;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     int b = (int)(i / MN);
     long long r = i - (long long)b * MN;
     int m = (int)(r / g.N);
     int n = (int)(r - (long long)m * g.N);
-    T s = T(0);
-    for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * g.batch + b) * MN + r];
+    const T* p = partial + (long long)b * MN + r;
+    T s8[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+    int sp = 0;
+    for (; sp + 8 <= splits; sp += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s8[u] += p[(long long)(sp + u) * stride];
+    }
+    for (int u = 0; sp + u < splits; ++u) s8[u] += p[(long long)(sp + u) * stride];
+    T s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     T* c = (T*)g.C + (long long)b * g.sCb + (long long)m * g.sCm + (long long)n * g.sCn;
     T out = (T)g.alpha * s;
     if (g.beta != 0.0) out += (T)g.beta * (*c);

@@ -147,14 +147,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __r
 
 // ---------------------------------------------------------------------------
 // Cyclic Jacobi eigensolver (parallel round-robin ordering), float64.
-// Rotation of the pair (p, q) with t = tan(phi) from
-// theta = (G_qq - G_pp) / (2 G_pq), t = sign(theta) / (|theta| + sqrt(theta^2+1)),
-// c = 1/sqrt(1+t^2), s = t c;  G <- J^T G J, V <- V J, J = [[c, s], [-s, c]] on
-// (p, q); the eigenvectors are returned as the ROWS of U = V^T.  A pair is
-// skipped when |G_pq| <= tol * sqrt(|G_pp G_qq|) (relative
-// threshold: small eigenvalues of a graded matrix keep their relative
-// accuracy, Demmel and Veselic 1992).  All n/2 rotations of one round touch
-// disjoint index pairs, so the 2x2 blocks of J^T G J are independent.
+// Rotations from jacobi_rotation (common.h): G <- J^T G J, V <- V J,
+// J = [[c, s], [-s, c]] on (p, q); the eigenvectors are returned as the ROWS
+// of U = V^T.  All n/2 rotations of one round touch disjoint index pairs, so
+// the 2x2 blocks of J^T G J are independent.
 // ---------------------------------------------------------------------------
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAXN = 1024;
@@ -193,13 +189,7 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg,
         double c = 1.0, s = 0.0, t = 0.0;
         if (q < n) {
           double gpp = G[(long long)p * n + p], gqq = G[(long long)q * n + q], gpq = G[(long long)p * n + q];
-          if (gpq != 0.0 && fabs(gpq) > tol * sqrt(fabs(gpp * gqq))) {
-            double theta = (gqq - gpp) / (2.0 * gpq);
-            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            atomicAdd(&rot_count, 1);
-          }
+          if (jacobi_rotation(gpp, gqq, gpq, tol, c, s, t)) atomicAdd(&rot_count, 1);
         }
         pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = t;
       }

@@ -657,10 +657,12 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     }
     std::swap(Yc, Yn);
     if (it == POLAR_REFRESH - 1 && refreshes == POLAR_REFRESH) {
-      int info[2] = {0, 0};
-      HIPCHK(hipMemcpyAsync(info, M.jinfo + 2 * it, sizeof info, hipMemcpyDeviceToHost, s));
+      int info[2 * POLAR_REFRESH];
+      HIPCHK(hipMemcpyAsync(info, M.jinfo, sizeof info, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      if (info[0] > POLAR_THIRD_IF) refreshes = POLAR_REFRESH + 1;
+      for (int q = 0; q < POLAR_REFRESH; ++q)
+        if (info[2 * q] < 0) return fail(TTN_EHIP, "Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
+      if (info[2 * it] > POLAR_THIRD_IF) refreshes = POLAR_REFRESH + 1;
     }
   }
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));

@@ -93,7 +93,10 @@ def test_stage_precision(B, prec, name, model, L, chi):
         gpu.update(tau)
         w_gpu = gpu.get_tensor(tau)
         W = w_gpu.reshape(w_gpu.shape[0], -1)
-        assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-13   # float64 polar regardless
+        # float64 polar regardless of the bulk precision: the same bound as
+        # the float64 parity tests (Jacobi rotations accumulate ~eps per
+        # index and sweep)
+        assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 2e-15 * max(W.shape[0], 50)
         w_ref, _ = T.polar_update(env)
         ref.ws[tau - 1] = w_ref
         gpu.set_tensor(tau, w_ref)
