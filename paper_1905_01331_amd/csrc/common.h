@@ -44,24 +44,42 @@ hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned l
 // diagonal gpp, gqq and off-diagonal gpq.  t = tan(phi) is the root of
 // t^2 + 2 theta t - 1 = 0 of smaller magnitude, theta = (gqq - gpp) / (2 gpq),
 // computed without forming theta:  t = sgn(x) y / (|x| + sqrt(x^2 + y^2)),
-// x = gqq - gpp, y = 2 gpq;  c = 1/sqrt(1 + t^2) (hardware reciprocal square
-// root plus two Newton steps), s = t c.  The pair is skipped (returns false,
-// c = 1, s = t = 0) when |gpq| <= tol sqrt(|gpp gqq|): a relative threshold,
-// so that small eigenvalues of a graded matrix keep their relative accuracy
-// (Demmel and Veselic 1992).
+// x = gqq - gpp, y = 2 gpq;  c = 1/sqrt(1 + t^2), s = t c.  The square root,
+// the reciprocal and c come from the hardware reciprocal (square root)
+// estimates refined by two Newton steps each (a few ulps; c^2 + s^2 = 1 to
+// working precision, which is what keeps the accumulated rotations
+// orthogonal); x^2 + y^2 outside [1e-280, 1e280] takes hypot().  The pair is
+// skipped (returns false, c = 1, s = t = 0) when |gpq| <= tol sqrt(|gpp gqq|):
+// a relative threshold, so that small eigenvalues of a graded matrix keep
+// their relative accuracy (Demmel and Veselic 1992).  Written without
+// branches on the data so that a wave evaluates it in one pass.
 __device__ __forceinline__ bool jacobi_rotation(double gpp, double gqq, double gpq, double tol, double& c, double& s,
                                                 double& t) {
-  c = 1.0; s = 0.0; t = 0.0;
-  if (gpq == 0.0 || gpq * gpq <= tol * tol * fabs(gpp * gqq)) return false;
+  const bool rotate = gpq != 0.0 && gpq * gpq > tol * tol * fabs(gpp * gqq);
   const double x = gqq - gpp, y = 2.0 * gpq;
-  t = (x >= 0.0 ? y : -y) / (fabs(x) + sqrt(x * x + y * y));
-  const double z = 1.0 + t * t;
-  double r = __builtin_amdgcn_rsq(z);
-  r = r * (1.5 - 0.5 * z * r * r);
-  r = r * (1.5 - 0.5 * z * r * r);
-  c = r;
-  s = t * r;
-  return true;
+  const double z = x * x + y * y;
+  double h;
+  if (z > 1e-280 && z < 1e280) {
+    double r = __builtin_amdgcn_rsq(z);
+    r = r * (1.5 - 0.5 * z * r * r);
+    r = r * (1.5 - 0.5 * z * r * r);
+    h = z * r;
+  } else {
+    h = hypot(x, y);
+  }
+  const double d = fabs(x) + h;
+  double inv = __builtin_amdgcn_rcp(d);
+  inv = inv * (2.0 - d * inv);
+  inv = inv * (2.0 - d * inv);
+  const double tt = (x >= 0.0 ? y : -y) * inv;
+  const double w = 1.0 + tt * tt;
+  double r = __builtin_amdgcn_rsq(w);
+  r = r * (1.5 - 0.5 * w * r * r);
+  r = r * (1.5 - 0.5 * w * r * r);
+  t = rotate ? tt : 0.0;
+  c = rotate ? r : 1.0;
+  s = rotate ? tt * r : 0.0;
+  return rotate;
 }
 
 // Jacobi eigensolver of a symmetric n x n float64 matrix G (in place; on

@@ -1,16 +1,20 @@
 // Blocked two-sided Jacobi eigensolver for the float64 Gram matrices of the
 // polar update when they are too large for one work-group's LDS (n > 64).
 //
-// The n indices are cut into blocks of BK = BS/2 (the last one ragged; a
-// dummy block makes the count even).  A round pairs the blocks by the circle
-// method; for each block pair (I, J) the BS x BS sub-matrix G[I u J, I u J]
-// gets one cyclic sweep of 2 x 2 Jacobi rotations (relative threshold,
+// The n indices are cut into nb blocks of BK = 16 (the last one ragged; a
+// dummy block makes nb even).  A sweep is nb rounds.  In the first nb - 1
+// rounds the blocks are paired by the circle method and each block pair
+// (I, J) rotates exactly its cross pairs (i in I, j in J): 16 steps, step s
+// rotating (I_i, J_(i+s) mod 16) for all i at once.  The last round pairs
+// blocks (2j, 2j+1) and rotates the pairs inside each block (a 16-index
+// circle method, 15 steps).  Every index pair is thus rotated once per
+// sweep, as in the cyclic method.  A round (phase A) works on the 32 x 32
+// sub-matrix G[I u J, I u J] with 2 x 2 rotations (relative threshold,
 // Rutishauser diagonal updates), which yields an orthogonal R and the
-// rotated sub-matrix S' = R G_sub R^T (phase A).  Then every block of G
-// between two index sets X, Y of the round is replaced by R_X G[X,Y] R_Y^T
-// (S' on the diagonal) and the rows X of the eigenvector matrix U by
-// R_X U[X,:] (phase B).  A sweep is nb - 1 rounds; a sweep with no rotation
-// ends the iteration.
+// rotated sub-matrix S' = R G_sub R^T; phase B replaces every block of G
+// between two index sets X, Y of the round by R_X G[X,Y] R_Y^T (S' on the
+// diagonal) and the rows X of the eigenvector matrix U by R_X U[X,:].  A
+// sweep with no rotation ends the iteration.
 //
 // The whole iteration is ONE launch of a persistent grid: its work-groups
 // share phase A (one block pair each) and phase B (one block of G or one
@@ -38,18 +42,26 @@ struct JcCtl {
   int rnd[64];     // rotations per round index, summed over sweeps
 };
 
+// Block pair j of round r (rounds 0 .. nb-2: circle method; round nb-1:
+// neighbouring blocks, for the pairs inside each block).
 __device__ __forceinline__ void jc_pair(int nb, int r, int j, int& I, int& J) {
-  if (j == 0) { I = r; J = nb - 1; }
+  if (r == nb - 1) { I = 2 * j; J = 2 * j + 1; }
+  else if (j == 0) { I = r; J = nb - 1; }
   else { I = (r + j) % (nb - 1); J = (r - j + (nb - 1)) % (nb - 1); }
 }
 
-// Grid barrier: every thread publishes its stores at device scope, thread 0
-// of each work-group counts in and polls; returns false after an abort.
+// Grid barrier.  Every thread waits until its own global stores have been
+// acknowledged (vmcnt(0)), the work-group meets, and thread 0 alone
+// publishes at device scope (the agent-scope fence writes this compute
+// unit's side of the L2 back for the other XCDs), counts in, polls, and
+// acquires (the fence invalidates the stale lines of this compute unit)
+// before the work-group meets again.  Returns false after an abort.
 __device__ bool jc_grid_sync(JcCtl* ctl, unsigned& target, int* ok_lds) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
   target += gridDim.x;
   if (threadIdx.x == 0) {
+    __threadfence();
     int ok = 1;
     atomicAdd(&ctl->bar, 1u);
     long long spins = 0;
@@ -62,11 +74,139 @@ __device__ bool jc_grid_sync(JcCtl* ctl, unsigned& target, int* ok_lds) {
       }
       __builtin_amdgcn_s_sleep(4);
     }
+    __threadfence();
     *ok_lds = ok;
   }
   __syncthreads();
-  __threadfence();
   return *ok_lds != 0;
+}
+
+// Local index pair (p, q), p < q, of rotation k (0..15) at step st of a
+// round on a 32-index sub-problem.  Cross round: p = k, q = 16 + (k + st) mod
+// 16.  Intra round: rotations 0..7 run the circle method on indices 0..15
+// (index 15 fixed), rotations 8..15 the same on indices 16..31.  Plain
+// arithmetic (no tables), so that everything stays in registers.
+template <bool CROSS>
+__device__ __forceinline__ void jc_pq(int st, int k, int& p, int& q) {
+  if constexpr (CROSS) {
+    p = k;
+    q = 16 + ((k + st) & 15);
+  } else {
+    const int kk = k & 7, off = k & 8 ? 16 : 0;
+    int a, b;
+    if (kk == 0) { a = st; b = 15; }
+    else {
+      a = st + kk; a = a >= 15 ? a - 15 : a;
+      b = st - kk; b = b < 0 ? b + 15 : b;
+    }
+    p = off + (a < b ? a : b);
+    q = off + (a < b ? b : a);
+  }
+}
+
+constexpr int JC_BS = 32, JC_BK = 16, JC_LD = JC_BS + 1;
+
+// Wave 0 of phase A: the sequential steps of one round on the 32 x 32
+// sub-problem in Sc (double buffered with Sn).  Lane l computes rotation
+// l % 16, the others read it by lane shuffles; each lane updates four 2 x 2
+// blocks.  The rotations of step st go to rc[st][k], rs[st][k], and step_lds
+// is raised to st once they are written.  Returns the lane's count of
+// rotations made.
+template <bool CROSS>
+__device__ int jc_wave0(double* Sc, double* Sn, unsigned long long vmask, double tol, double (*rc)[JC_BK],
+                        double (*rs)[JC_BK], int* step_lds, int lane) {
+  constexpr int BK = JC_BK, LD = JC_LD, NB = BK * BK / 64, NS = CROSS ? BK : BK - 1;
+  const int kr = lane % BK;         // rotation computed by this lane
+  const int k1 = lane / (64 / BK);  // row pair of this lane's blocks
+  const int k2b = lane % (64 / BK); // first column pair; then + 64/BK ...
+  int rot = 0;
+  for (int rr = 0; rr < NS; ++rr) {
+    int pr, qr, p1, q1, p2[NB], q2[NB];
+    jc_pq<CROSS>(rr, kr, pr, qr);
+    jc_pq<CROSS>(rr, k1, p1, q1);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) jc_pq<CROSS>(rr, k2b + u * (64 / BK), p2[u], q2[u]);
+    // every LDS read of the step first, then the arithmetic
+    const double app = Sc[pr * LD + pr], aqq = Sc[qr * LD + qr], apq = Sc[pr * LD + qr];
+    double bpp[NB], bpq[NB], bqp[NB], bqq[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      bpp[u] = Sc[p1 * LD + p2[u]]; bpq[u] = Sc[p1 * LD + q2[u]];
+      bqp[u] = Sc[q1 * LD + p2[u]]; bqq[u] = Sc[q1 * LD + q2[u]];
+    }
+    const bool real = (vmask >> pr) & (vmask >> qr) & 1ull;
+    double c, sn, t;
+    const bool did = jacobi_rotation(app, aqq, real ? apq : 0.0, tol, c, sn, t);
+    if (lane < BK) {
+      rc[rr][lane] = c;
+      rs[rr][lane] = sn;
+      rot += did ? 1 : 0;
+    }
+    const double c1 = __shfl(c, k1), s1 = __shfl(sn, k1), t1 = __shfl(t, k1);
+    double c2[NB], s2[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      c2[u] = __shfl(c, k2b + u * (64 / BK));
+      s2[u] = __shfl(sn, k2b + u * (64 / BK));
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const double gpp = bpp[u], gpq = bpq[u], gqp = bqp[u], gqq = bqq[u];
+      double npp, npq, nqp, nqq;
+      if (k1 == k2b + u * (64 / BK) && s1 != 0.0) {
+        npp = gpp - t1 * gpq;
+        nqq = gqq + t1 * gpq;
+        npq = 0.0;
+        nqp = 0.0;
+      } else {
+        double rp_p = c1 * gpp - s1 * gqp, rp_q = c1 * gpq - s1 * gqq;
+        double rq_p = s1 * gpp + c1 * gqp, rq_q = s1 * gpq + c1 * gqq;
+        npp = c2[u] * rp_p - s2[u] * rp_q; npq = s2[u] * rp_p + c2[u] * rp_q;
+        nqp = c2[u] * rq_p - s2[u] * rq_q; nqq = s2[u] * rq_p + c2[u] * rq_q;
+      }
+      Sn[p1 * LD + p2[u]] = npp; Sn[p1 * LD + q2[u]] = npq;
+      Sn[q1 * LD + p2[u]] = nqp; Sn[q1 * LD + q2[u]] = nqq;
+    }
+    // publish the record of step rr to the waves that accumulate R
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(step_lds, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    // one wave: LDS operations complete in order; keep the compiler from
+    // moving the next step's reads above these writes
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double* tp = Sc; Sc = Sn; Sn = tp;
+  }
+  return rot;
+}
+
+// Waves 1 and 2 of phase A: R = J_last ... J_0 (rows rotated), one step
+// behind wave 0.  Wave w owns columns 16 (w - 1) .. 16 w - 1; lane l works on
+// column 16 (w - 1) + l % 16 with rotations l / 16 + 4 u, u = 0..3 (the
+// rotations of one step touch disjoint rows, and a column is one wave's).
+template <bool CROSS>
+__device__ void jc_build_r(double* R, const double (*rc)[JC_BK], const double (*rs)[JC_BK], const int* step_lds,
+                           int wave, int lane) {
+  constexpr int LD = JC_LD, NS = CROSS ? JC_BK : JC_BK - 1;
+  const int col = (wave - 1) * 16 + (lane & 15);
+  const int kb = lane >> 4;
+  for (int rr = 0; rr < NS; ++rr) {
+    // wave 0 always completes its steps, so this wait ends
+    while (__hip_atomic_load(step_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < rr)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = kb + 4 * u;
+      int p, q;
+      jc_pq<CROSS>(rr, k, p, q);
+      const double c = rc[rr][k], sn = rs[rr][k];
+      const double up = R[p * LD + col], uq = R[q * LD + col];
+      R[p * LD + col] = c * up - sn * uq;
+      R[q * LD + col] = sn * up + c * uq;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
 }
 
 template <int BS>
@@ -82,6 +222,9 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   __shared__ int gx[BS], gy[BS];
   __shared__ int ok_lds, rot_lds;
   __shared__ int seen[64];  // rnd[] as read at the previous visit of each round
+  __shared__ double rc_lds[BK][BK], rs_lds[BK][BK];  // rotations of one round, [step][rotation]
+  __shared__ int step_lds;  // last step whose rotations wave 0 has recorded
+  static_assert(BS == 32, "the wave split of phase A is written for 32 x 32 sub-problems (four waves)");
   if (threadIdx.x < 64) seen[threadIdx.x] = 0;
   const int tid = threadIdx.x;
   const int npairs = nb / 2;
@@ -98,14 +241,18 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   };
 
   for (int sw = 0; sw < max_sweeps && alive; ++sw) {
-    for (int r = 0; r < nb - 1; ++r) {
+    for (int r = 0; r < nb; ++r) {
+      const bool cross = r < nb - 1;
+      const int nsteps = cross ? BK : BK - 1;
       // ---------------- phase A: one block pair per work-group ----------------
+      // wave 0 runs the round's steps (jc_wave0) while waves 1 and 2 build R
+      // one step behind (jc_build_r): no work-group barrier inside a round
       for (int j = blockIdx.x; j < npairs; j += gridDim.x) {
         int I, J;
         jc_pair(nb, r, j, I, J);
         __syncthreads();
         if (tid < BS) gx[tid] = gidx(I, J, tid);
-        if (tid == 0) rot_lds = 0;
+        if (tid == 0) { rot_lds = 0; step_lds = -1; }
         __syncthreads();
         double* Sc = L0;
         double* Sn = L1;
@@ -117,58 +264,20 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
           R[i * LD + k] = (i == k) ? 1.0 : 0.0;
         }
         __syncthreads();
-        const int k1 = tid / BK, k2 = tid - (tid / BK) * BK;
-        int rot = 0;
-        for (int rr = 0; rr < BS - 1; ++rr) {
-          // rotation k of this step acts on the index pair (p, q), circle method
-          int p1, q1, p2, q2;
-          if (k1 == 0) { p1 = rr; q1 = BS - 1; }
-          else { p1 = (rr + k1) % (BS - 1); q1 = (rr - k1 + (BS - 1)) % (BS - 1); }
-          if (k2 == 0) { p2 = rr; q2 = BS - 1; }
-          else { p2 = (rr + k2) % (BS - 1); q2 = (rr - k2 + (BS - 1)) % (BS - 1); }
-          if (p1 > q1) { int t = p1; p1 = q1; q1 = t; }
-          if (p2 > q2) { int t = p2; p2 = q2; q2 = t; }
-          // both rotations, computed (identically) by every thread that needs them
-          double c1, s1, t1, c2, s2, t2;
-          c1 = 1.0; s1 = 0.0; t1 = 0.0;
-          if (gx[p1] >= 0 && gx[q1] >= 0) jacobi_rotation(Sc[p1 * LD + p1], Sc[q1 * LD + q1], Sc[p1 * LD + q1], tol, c1, s1, t1);
-          if (k2 == k1) {
-            c2 = c1; s2 = s1; t2 = t1;
-          } else {
-            c2 = 1.0; s2 = 0.0; t2 = 0.0;
-            if (gx[p2] >= 0 && gx[q2] >= 0) jacobi_rotation(Sc[p2 * LD + p2], Sc[q2 * LD + q2], Sc[p2 * LD + q2], tol, c2, s2, t2);
-          }
-          {  // the 2 x 2 block (rows p1, q1; columns p2, q2) of S' = R S R^T
-            double gpp = Sc[p1 * LD + p2], gpq = Sc[p1 * LD + q2], gqp = Sc[q1 * LD + p2], gqq = Sc[q1 * LD + q2];
-            double npp, npq, nqp, nqq;
-            if (k1 == k2 && s1 != 0.0) {
-              npp = gpp - t1 * gpq;
-              nqq = gqq + t1 * gpq;
-              npq = 0.0;
-              nqp = 0.0;
-              ++rot;
-            } else {
-              double rp_p = c1 * gpp - s1 * gqp, rp_q = c1 * gpq - s1 * gqq;
-              double rq_p = s1 * gpp + c1 * gqp, rq_q = s1 * gpq + c1 * gqq;
-              npp = c2 * rp_p - s2 * rp_q; npq = s2 * rp_p + c2 * rp_q;
-              nqp = c2 * rq_p - s2 * rq_q; nqq = s2 * rq_p + c2 * rq_q;
-            }
-            Sn[p1 * LD + p2] = npp; Sn[p1 * LD + q2] = npq; Sn[q1 * LD + p2] = nqp; Sn[q1 * LD + q2] = nqq;
-          }
-          if (s1 != 0.0) {  // rows p1, q1 of R, columns 2 k2 and 2 k2 + 1
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              int c = 2 * k2 + h;
-              double up = R[p1 * LD + c], uq = R[q1 * LD + c];
-              R[p1 * LD + c] = c1 * up - s1 * uq;
-              R[q1 * LD + c] = s1 * up + c1 * uq;
-            }
-          }
-          __syncthreads();
-          double* t = Sc; Sc = Sn; Sn = t;
+        const int wave = tid >> 6, lane = tid & 63;
+        if (wave == 0) {
+          unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
+          for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gx[i] >= 0) << i;
+          const int rot = cross ? jc_wave0<true>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane)
+                                : jc_wave0<false>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane);
+          if (rot) atomicAdd(&rot_lds, rot);
+        } else if (wave <= 2) {
+          if (cross) jc_build_r<true>(R, rc_lds, rs_lds, &step_lds, wave, lane);
+          else jc_build_r<false>(R, rc_lds, rs_lds, &step_lds, wave, lane);
         }
-        if (rot) atomicAdd(&rot_lds, rot);
         __syncthreads();
+        // the final S is in the buffer written by the last step
+        const double* Sf = (nsteps & 1) ? L1 : L0;
         if (tid == 0 && rot_lds) {
           atomicAdd(&ctl->cnt[sw], rot_lds);
           atomicAdd(&ctl->rnd[r], rot_lds);
@@ -178,7 +287,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
         for (int e = tid; e < BS * BS; e += NT) {
           int i = e / BS, k = e - i * BS;
           Ro[e] = R[i * LD + k];
-          So[e] = Sc[i * LD + k];
+          So[e] = Sf[i * LD + k];
         }
       }
       if (!jc_grid_sync(ctl, target, &ok_lds)) { alive = false; break; }
@@ -305,7 +414,6 @@ __global__ void k_jc_init(double* __restrict__ U, int n, JcCtl* __restrict__ ctl
   }
 }
 
-constexpr int JC_BS = 32;
 
 int jc_compute_units() {
   static int cus = -1;

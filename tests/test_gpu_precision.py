@@ -115,20 +115,41 @@ def test_stage_precision(B, prec, name, model, L, chi):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_sweeps_track_fp64(B, prec):
+def test_mixed_sweeps_energy_of_the_same_state(B, prec):
+    """Sweeps in the bulk precision, each state re-evaluated in float64.
+
+    The mixed-precision run reports the lowest eigenvalue of its own top
+    Hamiltonian, ascended in the bulk precision.  The float64 re-evaluation
+    loads the same isometries and top tensor into a float64 handle (its
+    initialisation ascends every layer and solves the top problem in float64)
+    and must agree to TOL_ENERGY: that is the energy error of the
+    mixed-precision contractions for a given state.  The two trajectories
+    (mixed and float64 from the same start) are compared only loosely: the
+    updates are sensitive to rounding in the weak directions of the
+    environments, so the paths separate while both keep lowering the
+    energy."""
     model, L, chi = I.tfim_chain(1.0), 256, 32
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 4)
     g64 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
     gmx = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
-    e64, emx = [g64.energy()[0]], [gmx.energy()[0]]
+    n = gmx.n_levels()
+    c = gmx.stats().shift
+    e64, emx, ere = [g64.energy()[0]], [gmx.energy()[0]], []
     for _ in range(4):
         g64.sweep(1)
         gmx.sweep(1)
         e64.append(g64.energy()[0])
         emx.append(gmx.energy()[0])
-    diff = np.abs(np.array(emx) - np.array(e64)) / np.abs(e64)
-    print(f"  {prec} vs fp64 per-sweep relative energy differences", diff)
-    assert diff.max() < 50 * TOL_ENERGY[prec]
+        state = [gmx.get_tensor(tau) for tau in range(1, n)]
+        r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=gmx.get_tensor(B.TTN_TOP)))
+        ere.append(r.energy()[0])
+        r.close()
+    scale = np.maximum(np.abs(ere), abs(c) / model.ly)
+    err = np.abs(np.array(emx[1:]) - np.array(ere)) / scale
+    drift = np.abs(np.array(emx) - np.array(e64)) / np.abs(e64)
+    print(f"  {prec}: energy error of the same state {err}, trajectory drift {drift}")
+    assert err.max() < TOL_ENERGY[prec]
     assert all(b <= a + 1e-7 for a, b in zip(emx, emx[1:]))
+    assert drift.max() < 1e-3
     g64.close()
     gmx.close()
