@@ -50,6 +50,36 @@ __device__ __forceinline__ long long k_offset(const OpView& v, int k) {
   return (long long)k1 * v.s_k1 + (long long)(k - k1 * v.K2) * v.s_k;
 }
 
+// XCD-aware tile order.  Work-groups are handed to the 8 XCDs in turn
+// (work-group id mod 8), and each XCD has its own L2.  The grid is launched
+// 1-D with 8 * per work-groups; XCD c takes the contiguous range
+// [c * per, (c + 1) * per) of a logical tile order in which the output-tile
+// dimension with fewer tiles runs fastest, so that the tiles sharing an
+// operand panel (the same rows of A, or the same columns of B, and the same
+// K range) run at about the same time on one XCD and read that panel from
+// HBM once.
+struct TileMap {
+  int gx, gy, gz, per, yfast;
+};
+constexpr int N_XCD = 8;
+__device__ __forceinline__ bool map_tile(const TileMap& t, int& tx, int& ty, int& tz) {
+  const int id = blockIdx.x;
+  const long long L = (long long)(id % N_XCD) * t.per + id / N_XCD;
+  if (L >= (long long)t.gx * t.gy * t.gz) return false;
+  const int l = (int)L;
+  if (t.yfast) { ty = l % t.gy; const int r = l / t.gy; tx = r % t.gx; tz = r / t.gx; }
+  else { tx = l % t.gx; const int r = l / t.gx; ty = r % t.gy; tz = r / t.gy; }
+  return true;
+}
+TileMap make_map(int gx, int gy, int gz) {
+  TileMap t;
+  t.gx = gx; t.gy = gy; t.gz = gz;
+  const long long total = (long long)gx * gy * gz;
+  t.per = (int)((total + N_XCD - 1) / N_XCD);
+  t.yfast = gy < gx;
+  return t;
+}
+
 __device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
 
 // Per-thread register staging of one operand tile (BMN x BK floats).
@@ -105,6 +135,16 @@ template <> struct Smem<P_BF16X3> {
   __bf16 bhi[4][BN][8], blo[4][BN][8];
 };
 
+// Row of the bf16 planes where operand row `row` of plane `plane` is kept:
+// an XOR of the low three row bits with (row / 4) and (2 plane) that spreads
+// the writes of one wave over the LDS banks (the planes are a multiple of
+// the bank period apart, and an output-contiguous operand is written four
+// rows per lane) while any 32 consecutive rows of one plane stay a
+// permutation of one contiguous block for the MFMA operand reads.
+__device__ __forceinline__ int swz(int row, int plane) {
+  return row ^ (((row >> 2) ^ (plane << 1)) & 7);
+}
+
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -150,8 +190,8 @@ __device__ __forceinline__ void store_bf16(const Stage<P_BF16X3, KC>& st, __bf16
         h[e] = a;
         l[e] = b;
       }
-      *reinterpret_cast<bf16x4*>(&hi[k >> 3][mn][k & 7]) = h;
-      *reinterpret_cast<bf16x4*>(&lo[k >> 3][mn][k & 7]) = l;
+      *reinterpret_cast<bf16x4*>(&hi[k >> 3][swz(mn, k >> 3)][k & 7]) = h;
+      *reinterpret_cast<bf16x4*>(&lo[k >> 3][swz(mn, k >> 3)][k & 7]) = l;
     }
   } else {
     int mn = (tid % 32) * 4, kb = (tid / 32) * 4;
@@ -165,24 +205,26 @@ __device__ __forceinline__ void store_bf16(const Stage<P_BF16X3, KC>& st, __bf16
         h[i] = a;
         l[i] = b;
       }
-      *reinterpret_cast<bf16x4*>(&hi[kb >> 3][mn + e][kb & 7]) = h;
-      *reinterpret_cast<bf16x4*>(&lo[kb >> 3][mn + e][kb & 7]) = l;
+      *reinterpret_cast<bf16x4*>(&hi[kb >> 3][swz(mn + e, kb >> 3)][kb & 7]) = h;
+      *reinterpret_cast<bf16x4*>(&lo[kb >> 3][swz(mn + e, kb >> 3)][kb & 7]) = l;
     }
   }
 }
 
 template <int MODE, bool AKC, bool BKC>
-__global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, int kchunk, float* __restrict__ partial) {
+__global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, int kchunk, float* __restrict__ partial,
+                                                      TileMap tm) {
   constexpr int BK = Cfg<MODE>::BK;
   __shared__ Smem<MODE> sm;
 
+  int tx, ty, bz;
+  if (!map_tile(tm, tx, ty, bz)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  const int bz = blockIdx.z;
   const int b = bz / splits, sp = bz - b * splits;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = ty * BM, n0 = tx * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
@@ -235,10 +277,10 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
         bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          ah[i] = *reinterpret_cast<const bf16x8*>(&sm.ahi[c][wm + 32 * i + (lane & 31)][0]);
-          al[i] = *reinterpret_cast<const bf16x8*>(&sm.alo[c][wm + 32 * i + (lane & 31)][0]);
-          bh[i] = *reinterpret_cast<const bf16x8*>(&sm.bhi[c][wn + 32 * i + (lane & 31)][0]);
-          bl[i] = *reinterpret_cast<const bf16x8*>(&sm.blo[c][wn + 32 * i + (lane & 31)][0]);
+          ah[i] = *reinterpret_cast<const bf16x8*>(&sm.ahi[c][swz(wm + 32 * i + (lane & 31), c)][0]);
+          al[i] = *reinterpret_cast<const bf16x8*>(&sm.alo[c][swz(wm + 32 * i + (lane & 31), c)][0]);
+          bh[i] = *reinterpret_cast<const bf16x8*>(&sm.bhi[c][swz(wn + 32 * i + (lane & 31), c)][0]);
+          bl[i] = *reinterpret_cast<const bf16x8*>(&sm.blo[c][swz(wn + 32 * i + (lane & 31), c)][0]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -351,14 +393,16 @@ struct Stage64 {
 };
 
 template <bool AKC, bool BKC>
-__global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial) {
+__global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial,
+                                                        TileMap tm) {
   __shared__ double sa_l[BK64][BM + 2];
   __shared__ double sb_l[BK64][BN + 2];
+  int tx, ty, bz;
+  if (!map_tile(tm, tx, ty, bz)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  const int bz = blockIdx.z;
   const int b = bz / splits, sp = bz - b * splits;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int m0 = ty * BM, n0 = tx * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
   OpView64 va{(const double*)g.A + (long long)b * g.sAb, g.sAm, g.sAk, g.sAk1, g.M, g.K2};
@@ -435,15 +479,17 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
 
 template <bool AKC, bool BKC>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
-  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), grid, dim3(NT), 0, s, g, splits, kchunk, partial);
+  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk, partial,
+                     tm);
   return hipGetLastError();
 }
 
 template <int MODE, bool AKC, bool BKC>
 hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
-  hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), grid, dim3(NT), 0, s, g, splits, kchunk, partial);
+  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
+                     partial, tm);
   return hipGetLastError();
 }
 
