@@ -163,9 +163,19 @@ ttn_status ttn_update(ttn_handle h, int tau);
  * (E + c L) / (L ly) of each batch member to e_per_site[batch] (host). */
 ttn_status ttn_energy(ttn_handle h, double* e_per_site);
 
-/* nsweeps full sweeps: descend(RHO); for tau = 1..n-1 { descend(DRESSED,
- * tau); env(tau); update(tau); ascend(tau, tau) }; update(TOP). */
-ttn_status ttn_sweep(ttn_handle h, int nsweeps);
+/* nsweeps full sweeps (Secs. IV-V): descend(RHO); for tau = 1..n-1 {
+ * descend(DRESSED, tau); env(tau); update(tau); ascend(tau, tau) };
+ * update(TOP).  The members of a batch run their layer steps side by side on
+ * internal streams forked from and joined back into the handle's stream.
+ * use_graph != 0: the layer part (everything but update(TOP)) is captured
+ * into a HIP graph on the first such call and replayed on every later one
+ * (it holds no host synchronisation; the polar update's optional extra
+ * refresh is decided on the device); update(TOP) then runs eagerly, as its
+ * restarts are decided on the host.  The graph refers to the handle's
+ * workspace only, so ttn_set_tensor between sweeps is honoured.  Ignored
+ * while profiling is on.  Results are identical with and without the
+ * graph. */
+ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
 
 /* Checkpoint / parity access to the float64 master tensors of member b:
  * tau in 1..n-1 selects w_tau (chi_tau*chi_{tau-1}^2 doubles), tau == TTN_TOP

@@ -79,7 +79,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_env": ([P, I], I),
         "ttn_update": ([P, I], I),
         "ttn_energy": ([P, DP], I),
-        "ttn_sweep": ([P, I], I),
+        "ttn_sweep": ([P, I, I], I),
         "ttn_get_tensor": ([P, I, I, DP], I),
         "ttn_set_tensor": ([P, I, I, DP], I),
         "ttn_get_operator": ([P, I, I, I, I, DP], I),
@@ -195,8 +195,8 @@ class TTN:
         _check(self.lib.ttn_energy(self.h, _dptr(out)))
         return out
 
-    def sweep(self, nsweeps=1):
-        return _check(self.lib.ttn_sweep(self.h, nsweeps))
+    def sweep(self, nsweeps=1, graph=False):
+        return _check(self.lib.ttn_sweep(self.h, nsweeps, 1 if graph else 0))
 
     # access -----------------------------------------------------------------
     def bond_dim(self, tau, b=0):

@@ -17,6 +17,10 @@ struct GemmDesc {
   const void* B; long long sBk, sBn, sBk1, sBb;
   void* C;       long long sCm, sCn, sCb;
   double alpha, beta;
+  // optional device flag: when non-null and nonzero at run time, every
+  // kernel of the product returns at once (C untouched), so that a captured
+  // graph can carry a product whose need is decided on the device
+  const int* skip;
 };
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
@@ -34,6 +38,12 @@ hipError_t convert_f32_to_f64(const float* x, double* y, size_t n, hipStream_t s
 hipError_t fill_f64(double* x, double v, size_t n, hipStream_t s);
 hipError_t fill_f32(float* x, float v, size_t n, hipStream_t s);
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+// copies when *flag == want (device flag read at run time)
+hipError_t copy_bytes_if(void* dst, const void* src, size_t bytes, const int* flag, int want, hipStream_t s);
+// flag[0] = (info[0] <= limit) ? 1 : 0; err[0] (a double) is set to 1 when
+// any of info[0], info[2], .., info[2 (nq - 1)] is negative
+hipError_t set_flag_le(int* flag, const int* info, int limit, hipStream_t s);
+hipError_t note_negative_info(const int* info, int nq, double* err, hipStream_t s);
 hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s);
 // y = alpha*x + beta*y over n elements (float or double)
 hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size_t n, hipStream_t s);
@@ -88,10 +98,12 @@ __device__ __forceinline__ bool jacobi_rotation(double gpp, double gqq, double g
 // [1] rotations in the first sweep.
 // `scratch` (jacobi_blocked_scratch_bytes(n) bytes, may be null for n <= 128)
 // serves the blocked variant taken for n > 128.
+// `skip` (device flag, may be null): when nonzero at run time the kernels
+// return at once and G, V and info are left untouched.
 hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, void* scratch,
-                          hipStream_t s);
+                          hipStream_t s, const int* skip = nullptr);
 hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, double tol, int* info, void* scratch,
-                                  hipStream_t s);
+                                  hipStream_t s, const int* skip = nullptr);
 size_t jacobi_blocked_scratch_bytes(int n);
 // Z[i,:] = Y[i,:] / ||Y[i,:]||  for an m x k matrix (row norms into nrm[m]); rows
 // with a zero norm are left zero.

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
 
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
+  if (g.skip && *g.skip) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -399,6 +400,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   __shared__ double sb_l[BK64][BN + 2];
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
+  if (g.skip && *g.skip) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
   const int b = bz / splits, sp = bz - b * splits;

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
   __shared__ T Bs[PT_K][PT_N + 1];
   __shared__ T Al[MODE ? PT_K : 1][MODE ? PT_M + 1 : 1];
   __shared__ T Bl[MODE ? PT_K : 1][MODE ? PT_N + 1 : 1];
+  if (g.skip && *g.skip) return;
 
   const int bz = blockIdx.z;
   const int b = bz / splits;
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
 // result does not depend on timing.
 template <typename T>
 __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict__ partial) {
+  if (g.skip && *g.skip) return;
   long long total = (long long)g.batch * g.M * g.N;
   long long MN = (long long)g.M * g.N;
   long long stride = (long long)g.batch * MN;

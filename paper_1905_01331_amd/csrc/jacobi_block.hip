@@ -213,7 +213,12 @@ template <int BS>
 __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __restrict__ G, double* __restrict__ U,
                                                                    int n, int nb, int max_sweeps, double tol,
                                                                    JcCtl* __restrict__ ctl, double* __restrict__ Rbuf,
-                                                                   double* __restrict__ Sbuf, int* __restrict__ info) {
+                                                                   double* __restrict__ Sbuf, int* __restrict__ info,
+                                                                   const int* __restrict__ skip) {
+  if (skip && *skip) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { info[0] = 0; info[1] = 0; }
+    return;
+  }
   constexpr int BK = BS / 2;   // block width
   constexpr int NT = BK * BK;  // threads: one 2 x 2 block of S each
   constexpr int LD = BS + 1;
@@ -404,7 +409,8 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   }
 }
 
-__global__ void k_jc_init(double* __restrict__ U, int n, JcCtl* __restrict__ ctl) {
+__global__ void k_jc_init(double* __restrict__ U, int n, JcCtl* __restrict__ ctl, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)n * n;
        e += (long long)gridDim.x * blockDim.x)
     U[e] = (e / n == e % n) ? 1.0 : 0.0;
@@ -436,7 +442,7 @@ size_t jacobi_blocked_scratch_bytes(int n) {
 }
 
 hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, double tol, int* info, void* scratch,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int* skip) {
   constexpr int BS = JC_BS, BK = BS / 2;
   if (!info || !scratch || n < 1) return hipErrorInvalidValue;
   int nb = (n + BK - 1) / BK;
@@ -451,9 +457,9 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
   const int cus = jc_compute_units();
   if (cus <= 0) return hipErrorInvalidDevice;
   const int grid = std::max(1, std::min({std::max(npairs, nitems), JC_MAX_WG, cus}));
-  hipLaunchKernelGGL(k_jc_init, dim3(64), dim3(256), 0, s, U, n, ctl);
+  hipLaunchKernelGGL(k_jc_init, dim3(64), dim3(256), 0, s, U, n, ctl, skip);
   hipLaunchKernelGGL(k_jacobi_coop<BS>, dim3(grid), dim3(BK * BK), 0, s, G, U, n, nb, max_sweeps, tol, ctl, Rbuf,
-                     Sbuf, info);
+                     Sbuf, info, skip);
   return hipGetLastError();
 }
 

@@ -35,6 +35,19 @@ __global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
+__global__ void k_copy8_if(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n, const int* flag,
+                           int want) {
+  if (*flag != want) return;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+__global__ void k_set_flag_le(int* flag, const int* info, int limit) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = info[0] <= limit ? 1 : 0;
+}
+__global__ void k_note_negative_info(const int* info, int nq, double* err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int q = 0; q < nq; ++q)
+    if (info[2 * q] < 0) err[0] = 1.0;
+}
 __global__ void k_add_diag(double* X, int n, double v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) X[(size_t)i * n + i] += v;
 }
@@ -159,7 +172,11 @@ constexpr int JAC_MAXN = 1024;
 // both in dynamic LDS (copied back at the end).
 template <int MODE>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ Vg, int n,
-                                                        int max_sweeps, double tol, int* info) {
+                                                        int max_sweeps, double tol, int* info, const int* skip) {
+  if (skip && *skip) {
+    if (threadIdx.x == 0 && info) { info[0] = 0; info[1] = 0; }
+    return;
+  }
   extern __shared__ double dyn[];
   constexpr bool LDS = MODE >= 1;
   double* V = (MODE == 2) ? dyn + (long long)n * n : Vg;
@@ -285,6 +302,22 @@ hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   }
   return hipGetLastError();
 }
+hipError_t copy_bytes_if(void* dst, const void* src, size_t bytes, const int* flag, int want, hipStream_t s) {
+  if (!bytes) return hipSuccess;
+  if ((bytes % 8) || ((uintptr_t)dst % 8) || ((uintptr_t)src % 8)) return hipErrorInvalidValue;
+  const size_t n = bytes / 8;
+  hipLaunchKernelGGL(k_copy8_if, dim3(grid_for(n)), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, flag,
+                     want);
+  return hipGetLastError();
+}
+hipError_t set_flag_le(int* flag, const int* info, int limit, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_flag_le, dim3(1), dim3(64), 0, s, flag, info, limit);
+  return hipGetLastError();
+}
+hipError_t note_negative_info(const int* info, int nq, double* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_note_negative_info, dim3(1), dim3(64), 0, s, info, nq, err);
+  return hipGetLastError();
+}
 hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_add_diag, dim3(grid_for(n)), dim3(256), 0, s, X, n, v);
   return hipGetLastError();
@@ -324,9 +357,9 @@ hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, lon
   return hipGetLastError();
 }
 hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, void* scratch,
-                          hipStream_t s) {
+                          hipStream_t s, const int* skip) {
   if (n > JAC_MAXN) return hipErrorInvalidValue;
-  if (n > 64 && scratch) return jacobi_eig_blocked_f64(G, V, n, max_sweeps, tol, info, scratch, s);
+  if (n > 64 && scratch) return jacobi_eig_blocked_f64(G, V, n, max_sweeps, tol, info, scratch, s, skip);
   // the matrix goes to LDS when it fits next to the static rotation tables
   static int lds_limit = -1;
   if (lds_limit < 0) {
@@ -348,11 +381,11 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
   }
   size_t bytes = (size_t)n * n * sizeof(double);
   if (lds_limit > 0 && 2 * bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info);
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info, skip);
   } else if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<1>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info);
+    hipLaunchKernelGGL(k_jacobi<1>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info, skip);
   } else {
-    hipLaunchKernelGGL(k_jacobi<0>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info);
+    hipLaunchKernelGGL(k_jacobi<0>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info, skip);
   }
   return hipGetLastError();
 }

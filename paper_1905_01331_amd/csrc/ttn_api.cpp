@@ -91,7 +91,9 @@ struct Arena {
 };
 
 constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO_MAX = 4, SCAL_RATIO = 5,
-              SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10, SCAL_N = 16;
+              SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10,
+              SCAL_ERR = 11,  // 1.0 once a Jacobi solve reported an abort
+              SCAL_N = 16;
 // Gram refreshes of the polar update: two always, a third when the second
 // Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
 // diagonal, so the rotated rows may not yet be orthogonal to working accuracy)
@@ -140,6 +142,12 @@ struct Member {
   int krylov = 24, restarts = 8;
   double ltol = 1e-12;
   bool gauge_fix = true;
+  // batch members run side by side: a Jacobi solve that needs its grid
+  // co-resident (the persistent blocked solver) goes through one shared
+  // stream, one at a time, and the smaller ones use the one-work-group solver
+  bool solo = true;
+  hipStream_t grid_s = nullptr;
+  hipEvent_t grid_in = nullptr, grid_out = nullptr;
   // device
   size_t esz = 8;  // bulk element size
   std::vector<double*> w64;
@@ -152,6 +160,7 @@ struct Member {
   double *env64 = nullptr, *Y = nullptr, *Y2 = nullptr, *G = nullptr, *V = nullptr, *Q = nullptr, *Q2 = nullptr,
          *nrm = nullptr;
   int* jinfo = nullptr;
+  int* skip3 = nullptr;  // device flag: skip the extra polar refresh
   void* jscratch = nullptr;
   double* vtop = nullptr;
   void* vT = nullptr;
@@ -178,10 +187,35 @@ struct Member {
   const void* at(const void* base, size_t elems) const { return (const char*)base + elems * esz; }
 };
 
+// Streams over which the members of a batch run side by side in the layer
+// part of a sweep (forked from and joined back into the caller's stream with
+// events, so the fork is captured into the sweep graph as well).
+constexpr int POOL_STREAMS = 8;
+
 struct Ctx {
   std::vector<Member> m;
   hipStream_t s = nullptr;
   Profiler prof;
+  // captured layer part of a sweep (descend(RHO) and every layer step of
+  // every member), replayed by ttn_sweep(.., use_graph = 1)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<hipStream_t> pool;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  hipStream_t grid_s = nullptr;          // serialises the persistent Jacobi solves of a batch
+  hipStream_t cap_s = nullptr;           // stream the sweep graph is captured on
+  std::vector<hipEvent_t> member_events;  // two per member, for grid_s
+  ~Ctx() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    for (auto e : join) hipEventDestroy(e);
+    if (fork) hipEventDestroy(fork);
+    for (auto e : member_events) hipEventDestroy(e);
+    for (auto q : pool) hipStreamDestroy(q);
+    if (grid_s) hipStreamDestroy(grid_s);
+    if (cap_s) hipStreamDestroy(cap_s);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -325,6 +359,7 @@ void layout_member(Member& M, Arena& ar) {
   M.Q2 = ar.take<double>(c2);
   M.nrm = ar.take<double>(cmax);
   M.jinfo = ar.take<int>(64);
+  M.skip3 = ar.take<int>(64);
   M.jscratch = ar.take_bytes(jacobi_blocked_scratch_bytes(std::max(cmax, M.krylov)));
   M.vtop = ar.take<double>(xx);
   M.vT = (M.prec == TTN_FP64) ? (void*)M.vtop : ar.take_bytes(M.el(xx));
@@ -629,18 +664,34 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     HIPCHK(copy_bytes(Yc, src, aK * 8, s));
   }
   const double jtol = std::max(1e-15, 2.2e-16 * a);
-  int refreshes = POLAR_REFRESH;
-  for (int it = 0; it < refreshes; ++it) {
+  // POLAR_REFRESH refreshes, then one more whose need is decided on the
+  // device (the previous Jacobi needed more than POLAR_THIRD_IF sweeps): its
+  // kernels read the flag M.skip3 and return at once when it is set, so the
+  // whole update has no host synchronisation and can be captured in a graph.
+  for (int it = 0; it <= POLAR_REFRESH; ++it) {
+    const bool extra = it == POLAR_REFRESH;
+    const int* skip = extra ? M.skip3 : nullptr;
     GemmDesc g = desc0();  // G = Y Y^T
     g.M = a; g.N = a; g.K = (int)K;
     g.A = Yc; g.sAm = K; g.sAk = 1;
     g.B = Yc; g.sBk = 1; g.sBn = K;
     g.C = M.G; g.sCm = a; g.sCn = 1;
+    g.skip = skip;
     HIPCHK(run(M, P_F64, g, s));
     {
       size_t slot = 0;
       bool timed = M.prof && M.prof->begin(OC_JACOBI, 0.0, 0.0, s, &slot);
-      HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, s));
+      if (M.solo) {
+        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, s, skip));
+      } else if (a <= 128) {
+        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, nullptr, s, skip));
+      } else {
+        HIPCHK(hipEventRecord(M.grid_in, s));
+        HIPCHK(hipStreamWaitEvent(M.grid_s, M.grid_in, 0));
+        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, M.grid_s, skip));
+        HIPCHK(hipEventRecord(M.grid_out, M.grid_s));
+        HIPCHK(hipStreamWaitEvent(s, M.grid_out, 0));
+      }
       if (timed) M.prof->end(slot, s);
     }
     GemmDesc r = desc0();  // Yn = U Y
@@ -648,23 +699,30 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     r.A = M.V; r.sAm = a; r.sAk = 1;
     r.B = Yc; r.sBk = K; r.sBn = 1;
     r.C = Yn; r.sCm = K; r.sCn = 1;
+    r.skip = skip;
     HIPCHK(run(M, P_F64, r, s));
     if (it == 0 && !use_warm) {
       HIPCHK(copy_bytes(Pc, M.V, (size_t)a * a * 8, s));
     } else {
-      HIPCHK(mm(M, P_F64, M.V, false, Pc, false, Pn, a, 1.0, 0.0, s));  // P <- U P
-      std::swap(Pc, Pn);
+      GemmDesc q = desc0();  // Pn = U P
+      q.M = a; q.N = a; q.K = a;
+      q.A = M.V; q.sAm = a; q.sAk = 1;
+      q.B = Pc; q.sBk = a; q.sBn = 1;
+      q.C = Pn; q.sCm = a; q.sCn = 1;
+      q.skip = skip;
+      HIPCHK(run(M, P_F64, q, s, OC_TOP_MM));
+      if (!extra) std::swap(Pc, Pn);
     }
-    std::swap(Yc, Yn);
-    if (it == POLAR_REFRESH - 1 && refreshes == POLAR_REFRESH) {
-      int info[2 * POLAR_REFRESH];
-      HIPCHK(hipMemcpyAsync(info, M.jinfo, sizeof info, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      for (int q = 0; q < POLAR_REFRESH; ++q)
-        if (info[2 * q] < 0) return fail(TTN_EHIP, "Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
-      if (info[2 * it] > POLAR_THIRD_IF) refreshes = POLAR_REFRESH + 1;
+    if (extra) {
+      // the extra refresh wrote Yn, Pn; bring them back only if it ran
+      HIPCHK(copy_bytes_if(Yc, Yn, aK * 8, M.skip3, 0, s));
+      HIPCHK(copy_bytes_if(Pc, Pn, (size_t)a * a * 8, M.skip3, 0, s));
+    } else {
+      std::swap(Yc, Yn);
     }
+    if (it == POLAR_REFRESH - 1) HIPCHK(set_flag_le(M.skip3, M.jinfo + 2 * it, POLAR_THIRD_IF, s));
   }
+  HIPCHK(note_negative_info(M.jinfo, POLAR_REFRESH + 1, M.scal + SCAL_ERR, s));
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
   if (p_out) {
     // gauge-fixed result: out = sign * Z, the rotation P is handed back
@@ -845,9 +903,10 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     HIPCHK(residual_vec(M.lzHv, M.vtop, M.scal + SCAL_LAM, M.lzR, xx, s));
     HIPCHK(pair_f64(M.lzR, M.lzR, (long long)xx, M.scal + SCAL_RES, M.part, s));
     HIPCHK(sqrt_inplace(M.scal + SCAL_RES, s));
-    double hs[3];
-    HIPCHK(hipMemcpyAsync(hs, M.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    double hs[SCAL_ERR + 1];
+    HIPCHK(hipMemcpyAsync(hs, M.scal, sizeof hs, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (hs[SCAL_ERR] != 0.0) return fail(TTN_EHIP, "a Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
     if (hs[SCAL_RES] <= M.ltol * std::max(1.0, std::fabs(hs[SCAL_LAM]))) {
       *converged = true;
       break;
@@ -1000,6 +1059,24 @@ ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t b
     layout_member(M, ar);
     M.prof = &h->c.prof;
   }
+  if (batch > 1) {
+    Ctx& c = h->c;
+    hipError_t e = hipStreamCreateWithFlags(&c.grid_s, hipStreamNonBlocking);
+    c.member_events.resize(2 * batch, nullptr);
+    for (int i = 0; i < 2 * batch && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&c.member_events[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(TTN_EHIP, "stream/event creation failed: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < batch; ++i) {
+      Member& M = c.m[i];
+      M.solo = false;
+      M.grid_s = c.grid_s;
+      M.grid_in = c.member_events[2 * i];
+      M.grid_out = c.member_events[2 * i + 1];
+    }
+  }
   for (int i = 0; i < batch; ++i) {
     bool conv = false;
     st = init_member(h->c.m[i], h->c.s, &conv);
@@ -1106,30 +1183,90 @@ ttn_status ttn_energy(ttn_handle h, double* e) {
     double sc[SCAL_N];
     HIPCHK(hipMemcpy(sc, h->c.m[i].scal, sizeof sc, hipMemcpyDeviceToHost));
     e[i] = sc[SCAL_E];
+    if (sc[SCAL_ERR] != 0.0) return fail(TTN_EHIP, "a Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
     if (!(sc[SCAL_ORTHO_MAX] <= 1e-10)) bad = true;
   }
   if (bad) return fail(TTN_EORTHO, "an updated isometry failed the orthonormality check");
   return TTN_OK;
 }
 
-ttn_status ttn_sweep(ttn_handle h, int nsweeps) {
+// The layer part of one sweep for one member on stream s.
+ttn_status sweep_layers(Member& M, hipStream_t s) {
+  ttn_status st;
+  if ((st = stage_descend_rho(M, s))) return st;
+  for (int t = 1; t < M.n; ++t) {
+    if ((st = stage_descend_dressed(M, t, s))) return st;
+    if ((st = stage_env(M, t, s))) return st;
+    if ((st = stage_update_layer(M, t, s))) return st;
+    if ((st = stage_ascend(M, t, s))) return st;
+    M.ops_upto = std::max(M.ops_upto, t);
+  }
+  return TTN_OK;
+}
+
+// The layer part for the whole batch: one member runs on the caller's
+// stream; a batch forks to the pool streams (member i on stream i mod P) and
+// joins back.  No host synchronisation inside: capturable.
+ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
+  if (c.m.size() == 1) return sweep_layers(c.m[0], s);
+  if (c.pool.empty()) {
+    const int P = (int)std::min<size_t>(POOL_STREAMS, c.m.size());
+    c.pool.resize(P, nullptr);
+    c.join.resize(P, nullptr);
+    for (int i = 0; i < P; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&c.pool[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+  }
+  const int P = (int)c.pool.size();
+  HIPCHK(hipEventRecord(c.fork, s));
+  for (int i = 0; i < P; ++i) HIPCHK(hipStreamWaitEvent(c.pool[i], c.fork, 0));
+  for (size_t i = 0; i < c.m.size(); ++i) {
+    ttn_status st = sweep_layers(c.m[i], c.pool[i % P]);
+    if (st) return st;
+  }
+  for (int i = 0; i < P; ++i) {
+    HIPCHK(hipEventRecord(c.join[i], c.pool[i]));
+    HIPCHK(hipStreamWaitEvent(s, c.join[i], 0));
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
   if (!h || nsweeps < 0) return fail(TTN_EINVAL, "bad arguments");
+  Ctx& c = h->c;
   ttn_status warn = TTN_OK;
   for (int sw = 0; sw < nsweeps; ++sw) {
-    for (auto& M : h->c.m) {
-      hipStream_t s = h->c.s;
-      ttn_status st;
+    for (auto& M : c.m)
       if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "sweep needs every layer ascended");
-      if ((st = stage_descend_rho(M, s))) return st;
-      for (int t = 1; t < M.n; ++t) {
-        if ((st = stage_descend_dressed(M, t, s))) return st;
-        if ((st = stage_env(M, t, s))) return st;
-        if ((st = stage_update_layer(M, t, s))) return st;
-        if ((st = stage_ascend(M, t, s))) return st;
-        M.ops_upto = std::max(M.ops_upto, t);
+    ttn_status st;
+    if (use_graph && !c.prof.on) {
+      if (!c.gexec) {
+        // captured on an internal stream (the caller's may be the legacy
+        // default stream, which cannot capture); the host bookkeeping of the
+        // stages runs once here, as in an eager sweep, and the graph holds
+        // only device work, identical every sweep
+        if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
+        st = sweep_layers_all(c, c.cap_s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c.cap_s, &g);
+        if (st) {
+          if (g) hipGraphDestroy(g);
+          return st;
+        }
+        HIPCHK(e);
+        c.graph = g;
+        HIPCHK(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
       }
+      HIPCHK(hipGraphLaunch(c.gexec, c.s));
+    } else {
+      if ((st = sweep_layers_all(c, c.s))) return st;
+    }
+    for (auto& M : c.m) {
       bool conv = false;
-      if ((st = stage_update_top(M, s, &conv))) return st;
+      if ((st = stage_update_top(M, c.s, &conv))) return st;
       if (!conv) warn = TTN_WNOCONV;
     }
   }

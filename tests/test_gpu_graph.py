@@ -1,0 +1,122 @@
+"""Graph replay and batches of chains.
+
+The layer part of a sweep is captured into a HIP graph on the first
+ttn_sweep(.., use_graph=1) and replayed afterwards; every replay must give
+the energies of the eager path exactly (same kernels, same order), with the
+eager top update, synchronisations and energy reads between replays.  A
+batch runs its members side by side on internal streams; each member must
+follow the path it follows alone.
+"""
+import numpy as np
+import pytest
+
+from oracle import ttn_ref as T
+from paper_1905_01331_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1905_01331_amd import binding
+    binding.load_library()
+    return binding
+
+
+# (name, model, L, chi, precision): the one-work-group Jacobi (a <= 64), the
+# persistent blocked Jacobi (a = 160), a mixed-precision bulk
+GRAPH_CASES = [
+    ("tfim_L64_chi24_fp64", I.tfim_chain(1.0), 64, 24, "fp64"),
+    ("xxx_L32_chi160_fp64", I.xxx_chain(), 32, 160, "fp64"),
+    ("torus8x4_chi64_bf16x3", I.torus_tfim_column(4, 3.0), 8, 64, "bf16x3"),
+]
+
+
+@pytest.mark.parametrize("name,model,L,chi,prec", GRAPH_CASES, ids=[c[0] for c in GRAPH_CASES])
+def test_graph_replays_match_eager(B, name, model, L, chi, prec):
+    print(f"[graph] {name}", flush=True)
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 7)
+    eager = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    graph = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    for s in range(5):
+        eager.sweep(1)
+        graph.sweep(1, graph=True)
+        e0, e1 = eager.energy()[0], graph.energy()[0]
+        assert e0 == e1, f"sweep {s}: eager {e0!r} graph {e1!r}"
+    # the graph reads the workspace at replay time: a state loaded between
+    # sweeps is honoured
+    n = eager.n_levels()
+    state = [eager.get_tensor(tau) for tau in range(1, n)]
+    v = eager.get_tensor(B.TTN_TOP)
+    for h in (eager, graph):
+        for tau in range(1, n):
+            h.set_tensor(tau, state[tau - 1])
+        h.set_tensor(B.TTN_TOP, v)
+        h.ascend(1, n - 1)
+    eager.sweep(1)
+    graph.sweep(1, graph=True)
+    assert eager.energy()[0] == graph.energy()[0]
+    w_e = eager.get_tensor(1)
+    w_g = graph.get_tensor(1)
+    assert np.array_equal(w_e, w_g)
+    eager.close()
+    graph.close()
+
+
+def test_batch_members_follow_their_solo_paths(B):
+    # uneven L, chi and couplings; a <= 64 everywhere, so a member runs the
+    # same kernels in the batch as alone
+    draws = [(I.tfim_chain(0.7), 64, 32), (I.tfim_chain(1.3), 128, 48), (I.xxx_chain(), 32, 16),
+             (I.tfim_chain(1.0), 256, 64)]
+    inputs = [B.ChainInput(m, L, chi, "fp32", seed=100 + i) for i, (m, L, chi) in enumerate(draws)]
+    batch = B.TTN(inputs)
+    solo = [B.TTN(B.ChainInput(m, L, chi, "fp32", seed=100 + i)) for i, (m, L, chi) in enumerate(draws)]
+    e_b0 = batch.energy()
+    e_s0 = np.array([t.energy()[0] for t in solo])
+    assert np.array_equal(e_b0, e_s0)
+    for s in range(3):
+        batch.sweep(1, graph=(s > 0))
+        for t in solo:
+            t.sweep(1)
+        e_b = batch.energy()
+        e_s = np.array([t.energy()[0] for t in solo])
+        print(f"  sweep {s}: batch {e_b} solo {e_s}")
+        assert np.array_equal(e_b, e_s)
+    for t in solo:
+        t.close()
+    batch.close()
+
+
+def test_batch_with_larger_bond_dimension(B):
+    # a member with 64 < a <= 128 uses the one-work-group Jacobi in a batch
+    # and the persistent blocked solver when alone: both give the polar
+    # factor to working accuracy, but from a random start the environments
+    # have near-null directions (tiny eigenvalues of the descended density
+    # matrices) where the polar factor is fixed only by rounding, so the
+    # paths may differ there.  Checked: the member in the batch lowers the
+    # energy, stays above the free-fermion ground energy, and its isometries
+    # are orthonormal; the other member (a <= 64) matches its solo run exactly.
+    from oracle import physics_ref as P
+    draws = [(1.0, 64, 96), (1.1, 128, 32)]
+    ws = [I.random_isometries(T.layer_shapes(L, 2, chi), 20 + i) for i, (h, L, chi) in enumerate(draws)]
+    batch = B.TTN([B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w) for (h, L, chi), w in zip(draws, ws)])
+    solo = B.TTN(B.ChainInput(I.tfim_chain(draws[1][0]), draws[1][1], draws[1][2], "fp64", w0=ws[1]))
+    e0 = batch.energy()
+    for s in range(2):
+        batch.sweep(1, graph=True)
+        solo.sweep(1)
+        e = batch.energy()
+        assert e[1] == solo.energy()[0]
+        assert e[0] <= e0[0] + 1e-12
+        e0 = e
+    h, L, chi = draws[0]
+    assert e[0] >= P.tfim_free_fermion_energy(L, h) / L - 1e-12
+    for tau in range(1, batch.n_levels(0)):
+        w = batch.get_tensor(tau, 0)
+        W = w.reshape(w.shape[0], -1)
+        assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-13
+    solo.close()
+    batch.close()
