@@ -21,7 +21,18 @@ struct GemmDesc {
   // kernel of the product returns at once (C untouched), so that a captured
   // graph can carry a product whose need is decided on the device
   const int* skip;
+  // two-level batch: with batch1 > 0 the batch index b = b1 + batch1 * b2
+  // (b1 < batch1) places operand X at b1 * sXb + b2 * sXb2; batch is the
+  // total count.  batch1 == 0: one level, X at b * sXb.
+  int batch1;
+  long long sAb2, sBb2, sCb2;
 };
+
+__host__ __device__ __forceinline__ long long batch_offset(const GemmDesc& g, int b, long long s1, long long s2) {
+  if (g.batch1 <= 0) return (long long)b * s1;
+  const int q = b / g.batch1;
+  return (long long)(b - q * g.batch1) * s1 + (long long)q * s2;
+}
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
 

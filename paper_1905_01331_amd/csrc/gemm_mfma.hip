@@ -229,8 +229,8 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
-  OpView va{(const float*)g.A + (long long)b * g.sAb, g.sAm, g.sAk, g.sAk1, g.M, g.K2};
-  OpView vb{(const float*)g.B + (long long)b * g.sBb, g.sBn, g.sBk, g.sBk1, g.N, g.K2};
+  OpView va{(const float*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
+  OpView vb{(const float*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
   // row wm + 32 i + 8 (r / 4) + 4 (l / 32) + r % 4, column wn + 32 j + l % 32
   const int col_l = lane & 31, rowq = (lane >> 5) * 4;
   if (splits == 1) {
-    float* C = (float*)g.C + (long long)b * g.sCb;
+    float* C = (float*)g.C + batch_offset(g, b, g.sCb, g.sCb2);
     const float alpha = (float)g.alpha, beta = (float)g.beta;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -407,8 +407,8 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   const int m0 = ty * BM, n0 = tx * BN;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
-  OpView64 va{(const double*)g.A + (long long)b * g.sAb, g.sAm, g.sAk, g.sAk1, g.M, g.K2};
-  OpView64 vb{(const double*)g.B + (long long)b * g.sBb, g.sBn, g.sBk, g.sBk1, g.N, g.K2};
+  OpView64 va{(const double*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
+  OpView64 vb{(const double*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
   f64x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   }
   const int col_l = lane & 15, row_l = lane >> 4;
   if (splits == 1) {
-    double* C = (double*)g.C + (long long)b * g.sCb;
+    double* C = (double*)g.C + batch_offset(g, b, g.sCb, g.sCb2);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -507,7 +507,7 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
   if (!(akc || amc) || !(bkc || bmc)) return hipErrorNotSupported;
   if (!aligned16(g.A) || !aligned16(g.B)) return hipErrorNotSupported;
-  if (g.sAb % 2 || g.sBb % 2) return hipErrorNotSupported;
+  if (g.sAb % 2 || g.sBb % 2 || g.sAb2 % 2 || g.sBb2 % 2) return hipErrorNotSupported;
   if (akc) { if (g.K % 2 || g.sAm % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sAk1 % 2))) return hipErrorNotSupported; }
   else     { if (g.M % 2 || g.sAk % 2 || (g.K2 > 0 && g.sAk1 % 2)) return hipErrorNotSupported; }
   if (bkc) { if (g.K % 2 || g.sBn % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sBk1 % 2))) return hipErrorNotSupported; }
@@ -548,7 +548,7 @@ hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch
   const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
   if (!(akc || amc) || !(bkc || bmc)) return hipErrorNotSupported;
   if (!aligned16(g.A) || !aligned16(g.B)) return hipErrorNotSupported;
-  if (g.sAb % 4 || g.sBb % 4) return hipErrorNotSupported;
+  if (g.sAb % 4 || g.sBb % 4 || g.sAb2 % 4 || g.sBb2 % 4) return hipErrorNotSupported;
   // contiguous extents and the other strides must keep float4 alignment
   if (akc) { if (g.K % 4 || g.sAm % 4 || (g.K2 > 0 && (g.K2 % 4 || g.sAk1 % 4))) return hipErrorNotSupported; }
   else     { if (g.M % 4 || g.sAk % 4 || (g.K2 > 0 && g.sAk1 % 4)) return hipErrorNotSupported; }

@@ -56,8 +56,8 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
 
-  const T* __restrict__ A = (const T*)g.A + (long long)b * g.sAb;
-  const T* __restrict__ B = (const T*)g.B + (long long)b * g.sBb;
+  const T* __restrict__ A = (const T*)g.A + batch_offset(g, b, g.sAb, g.sAb2);
+  const T* __restrict__ B = (const T*)g.B + batch_offset(g, b, g.sBb, g.sBb2);
 
   const int tid = threadIdx.x;
   const int tx = tid & 15;  // columns n0 + tx + 16*j
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
   }
 
   if (splits == 1) {
-    T* C = (T*)g.C + (long long)b * g.sCb;
+    T* C = (T*)g.C + batch_offset(g, b, g.sCb, g.sCb2);
     const T alpha = (T)g.alpha, beta = (T)g.beta;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -200,7 +200,7 @@ __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict
     }
     for (int u = 0; sp + u < splits; ++u) s8[u] += p[(long long)(sp + u) * stride];
     T s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-    T* c = (T*)g.C + (long long)b * g.sCb + (long long)m * g.sCm + (long long)n * g.sCn;
+    T* c = (T*)g.C + batch_offset(g, b, g.sCb, g.sCb2) + (long long)m * g.sCm + (long long)n * g.sCn;
     T out = (T)g.alpha * s;
     if (g.beta != 0.0) out += (T)g.beta * (*c);
     *c = out;

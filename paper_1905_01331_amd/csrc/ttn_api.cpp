@@ -157,6 +157,7 @@ struct Member {
   void *Rb[2] = {nullptr, nullptr}, *Lb[2] = {nullptr, nullptr};
   int rb_cur = 0;
   void *Sw = nullptr, *S2 = nullptr, *S3 = nullptr, *envT = nullptr;
+  void *Estage = nullptr, *Xst = nullptr;  // environment staging: tensors and their left factors
   double *env64 = nullptr, *Y = nullptr, *Y2 = nullptr, *G = nullptr, *V = nullptr, *Q = nullptr, *Q2 = nullptr,
          *nrm = nullptr;
   int* jinfo = nullptr;
@@ -164,7 +165,7 @@ struct Member {
   void* jscratch = nullptr;
   double* vtop = nullptr;
   void* vT = nullptr;
-  void* tmpT = nullptr;  // chi^2 bulk scratch for the top dressing
+  void* tmpT = nullptr;  // D chi^2 bulk scratch for the top dressing
   double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr, *lzStage = nullptr;
   double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
   double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr,
@@ -344,9 +345,14 @@ void layout_member(Member& M, Arena& ar) {
     M.Rb[i] = ar.take_bytes(M.el(cq));
     M.Lb[i] = ar.take_bytes(M.el(cq));
   }
-  M.Sw = ar.take_bytes(M.el(cube));
-  M.S2 = ar.take_bytes(M.el(cube));
-  M.S3 = ar.take_bytes(M.el(cube));
+  // environment staging [S w | B_k .l w | A_k .r w], slice 0 doubles as S w;
+  // S2, S3 hold one intermediate per product term
+  const size_t nkk = (size_t)std::max(D, 1);
+  M.Estage = ar.take_bytes(M.el((1 + 2 * (size_t)D) * cube));
+  M.Sw = M.Estage;
+  M.S2 = ar.take_bytes(M.el(nkk * cube));
+  M.S3 = ar.take_bytes(M.el(nkk * cube));
+  M.Xst = ar.take_bytes(M.el((1 + 2 * (size_t)D) * (size_t)cmax * cmax));
   M.envT = (M.prec == TTN_FP64) ? nullptr : ar.take_bytes(M.el(cube));
   M.env64 = ar.take<double>(cube);
   M.Y = ar.take<double>(cube);
@@ -363,7 +369,7 @@ void layout_member(Member& M, Arena& ar) {
   M.jscratch = ar.take_bytes(jacobi_blocked_scratch_bytes(std::max(cmax, M.krylov)));
   M.vtop = ar.take<double>(xx);
   M.vT = (M.prec == TTN_FP64) ? (void*)M.vtop : ar.take_bytes(M.el(xx));
-  M.tmpT = ar.take_bytes(M.el(xx));
+  M.tmpT = ar.take_bytes(M.el(xx * std::max(D, 1)));
   // float64 top operators, contiguous [h, A_1..A_D, B_1..B_D], and the
   // matvec staging [y, y B_1^T .. y B_D^T, y A_1^T .. y A_D^T]
   M.hop64 = ar.take<double>(xx * (1 + 2 * D));
@@ -418,100 +424,155 @@ GemmDesc desc0() {
   return g;
 }
 
-// (O .r X)[a;l,r] = sum_r' O[r,r'] X[a;l,r']  -> Y
-hipError_t apply_r(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
-                   hipStream_t s) {
+// The building blocks over nk product terms at once: term k reads its
+// operator at O + k sO, its tensor at X + k sX (sX = 0: one tensor for all)
+// and writes Y + k sY; one launch for all terms.
+// (O .r X)[a;l,r] = sum_r' O[r,r'] X[a;l,r']
+hipError_t apply_r_k(const Member& M, Prec p, const void* O, long long sO, const void* X, long long sX, void* Y,
+                     long long sY, int a, int b, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
+  g.batch = nk;
   g.M = a * b; g.N = b; g.K = b; g.K2 = 0;
-  g.A = X; g.sAm = b; g.sAk = 1;
-  g.B = O; g.sBk = 1; g.sBn = b;
-  g.C = Y; g.sCm = b; g.sCn = 1;
+  g.A = X; g.sAm = b; g.sAk = 1; g.sAb = sX;
+  g.B = O; g.sBk = 1; g.sBn = b; g.sBb = sO;
+  g.C = Y; g.sCm = b; g.sCn = 1; g.sCb = sY;
   g.beta = beta;
   return run(M, p, g, s, OC_APPLY_R);
 }
-// (O .l X)[a;l,r] = sum_l' O[l,l'] X[a;l',r]  -> Y   (batched over a)
-hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
-                   hipStream_t s) {
+// (O .l X)[a;l,r] = sum_l' O[l,l'] X[a;l',r]   (batched over a, then over k)
+hipError_t apply_l_k(const Member& M, Prec p, const void* O, long long sO, const void* X, long long sX, void* Y,
+                     long long sY, int a, int b, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
-  g.batch = a;
+  const long long bb = (long long)b * b;
+  g.batch1 = a;
+  g.batch = a * nk;
   g.M = b; g.N = b; g.K = b; g.K2 = 0;
-  g.A = O; g.sAm = b; g.sAk = 1; g.sAb = 0;
-  g.B = X; g.sBk = b; g.sBn = 1; g.sBb = (long long)b * b;
-  g.C = Y; g.sCm = b; g.sCn = 1; g.sCb = (long long)b * b;
+  g.A = O; g.sAm = b; g.sAk = 1; g.sAb = 0; g.sAb2 = sO;
+  g.B = X; g.sBk = b; g.sBn = 1; g.sBb = bb; g.sBb2 = sX;
+  g.C = Y; g.sCm = b; g.sCn = 1; g.sCb = bb; g.sCb2 = sY;
   g.beta = beta;
   return run(M, p, g, s, OC_APPLY_L);
 }
 // C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b)
-hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
-                    double beta, hipStream_t s) {
+hipError_t close_aa_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
+                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
   long long bb = (long long)b * b;
+  g.batch = nk;
   g.M = a; g.N = a; g.K = (int)bb; g.K2 = 0;
-  g.A = P; g.sAm = bb; g.sAk = 1;
-  g.B = Qm; g.sBk = 1; g.sBn = bb;
-  g.C = C; g.sCm = a; g.sCn = 1;
+  g.A = P; g.sAm = bb; g.sAk = 1; g.sAb = sP;
+  g.B = Qm; g.sBk = 1; g.sBn = bb; g.sBb = sQ;
+  g.C = C; g.sCm = a; g.sCn = 1; g.sCb = sC;
   g.alpha = alpha; g.beta = beta;
   return run(M, p, g, s, OC_CLOSE);
 }
 // (X o P)[a;l,r] = sum_a' X[a,a'] P[a';l,r]
-hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void* Y, int a, int b, double alpha,
-                    double beta, hipStream_t s) {
+hipError_t left_mul_k(const Member& M, Prec p, const void* X, long long sX, const void* P, long long sP, void* Y,
+                      long long sY, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
   long long bb = (long long)b * b;
+  g.batch = nk;
   g.M = a; g.N = (int)bb; g.K = a; g.K2 = 0;
-  g.A = X; g.sAm = a; g.sAk = 1;
-  g.B = P; g.sBk = bb; g.sBn = 1;
-  g.C = Y; g.sCm = bb; g.sCn = 1;
+  g.A = X; g.sAm = a; g.sAk = 1; g.sAb = sX;
+  g.B = P; g.sBk = bb; g.sBn = 1; g.sBb = sP;
+  g.C = Y; g.sCm = bb; g.sCn = 1; g.sCb = sY;
   g.alpha = alpha; g.beta = beta;
   return run(M, p, g, s, OC_LEFT_MUL);
 }
 // C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']   (b x b, K = a*b)
-hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
-                   double beta, hipStream_t s) {
+hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
+  g.batch = nk;
   g.M = b; g.N = b; g.K = a * b; g.K2 = 0;
-  g.A = P; g.sAm = 1; g.sAk = b;
-  g.B = Qm; g.sBk = b; g.sBn = 1;
-  g.C = C; g.sCm = b; g.sCn = 1;
+  g.A = P; g.sAm = 1; g.sAk = b; g.sAb = sP;
+  g.B = Qm; g.sBk = b; g.sBn = 1; g.sBb = sQ;
+  g.C = C; g.sCm = b; g.sCn = 1; g.sCb = sC;
   g.alpha = alpha; g.beta = beta;
   return run(M, p, g, s, OC_CLOSE_R);
 }
 // C_L(P,Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r]   (b x b, K = (a, r))
-hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
-                   double beta, hipStream_t s) {
+hipError_t close_l_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
   long long bb = (long long)b * b;
+  g.batch = nk;
   g.M = b; g.N = b; g.K = a * b; g.K2 = b;
-  g.A = P; g.sAm = b; g.sAk = 1; g.sAk1 = bb;
-  g.B = Qm; g.sBk = 1; g.sBk1 = bb; g.sBn = b;
-  g.C = C; g.sCm = b; g.sCn = 1;
+  g.A = P; g.sAm = b; g.sAk = 1; g.sAk1 = bb; g.sAb = sP;
+  g.B = Qm; g.sBk = 1; g.sBk1 = bb; g.sBn = b; g.sBb = sQ;
+  g.C = C; g.sCm = b; g.sCn = 1; g.sCb = sC;
   g.alpha = alpha; g.beta = beta;
   return run(M, p, g, s, OC_CLOSE_L);
 }
-// dense square products of order x: C = alpha op(A) op(B) + beta C
+hipError_t apply_r(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
+                   hipStream_t s) {
+  return apply_r_k(M, p, O, 0, X, 0, Y, 0, a, b, beta, 1, s);
+}
+hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* Y, int a, int b, double beta,
+                   hipStream_t s) {
+  return apply_l_k(M, p, O, 0, X, 0, Y, 0, a, b, beta, 1, s);
+}
+hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                    double beta, hipStream_t s) {
+  return close_aa_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+}
+hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void* Y, int a, int b, double alpha,
+                    double beta, hipStream_t s) {
+  return left_mul_k(M, p, X, 0, P, 0, Y, 0, a, b, alpha, beta, 1, s);
+}
+hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                   double beta, hipStream_t s) {
+  return close_r_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+}
+hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
+                   double beta, hipStream_t s) {
+  return close_l_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+}
+// dense square products of order x: C = alpha op(A) op(B) + beta C, for nk
+// triples (A + k sA, B + k sB, C + k sC) in one launch
+hipError_t mm_k(const Member& M, Prec p, const void* Am, long long sA, bool ta, const void* Bm, long long sB, bool tb,
+                void* C, long long sC, int x, double alpha, double beta, int nk, hipStream_t s) {
+  if (nk < 1) return hipSuccess;
+  GemmDesc g = desc0();
+  g.batch = nk;
+  g.M = x; g.N = x; g.K = x; g.K2 = 0;
+  g.A = Am; g.sAm = ta ? 1 : x; g.sAk = ta ? x : 1; g.sAb = sA;
+  g.B = Bm; g.sBk = tb ? 1 : x; g.sBn = tb ? x : 1; g.sBb = sB;
+  g.C = C; g.sCm = x; g.sCn = 1; g.sCb = sC;
+  g.alpha = alpha; g.beta = beta;
+  return run(M, p, g, s, OC_TOP_MM);
+}
 hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, bool tb, void* C, int x, double alpha,
               double beta, hipStream_t s) {
-  GemmDesc g = desc0();
-  g.M = x; g.N = x; g.K = x; g.K2 = 0;
-  g.A = Am; g.sAm = ta ? 1 : x; g.sAk = ta ? x : 1;
-  g.B = Bm; g.sBk = tb ? 1 : x; g.sBn = tb ? x : 1;
-  g.C = C; g.sCm = x; g.sCn = 1;
-  g.alpha = alpha; g.beta = beta;
-  return run(M, p, g, s, p == P_F64 ? OC_TOP_MM : OC_TOP_MM);
+  return mm_k(M, p, Am, 0, ta, Bm, 0, tb, C, 0, x, alpha, beta, 1, s);
 }
 
-// S w = h .l w + h .r w + sum_k A_k .l (B_k .r w)   (into M.Sw)
+// S w = h .l w + h .r w + sum_k A_k .l (B_k .r w)   (into M.Sw, slice 0 of
+// the environment staging).  The D right applications are one launch into
+// S2 ([k][a][l][r]); the D left applications and their sum are one product
+// whose contraction index runs over (k, l').
 hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, hipStream_t s) {
   Prec p = M.gp();
-  size_t bb = (size_t)b * b;
+  const long long bb = (long long)b * b, cube = (long long)a * bb;
   hipError_t e;
   if ((e = apply_l(M, p, M.opH[lvl_below], w, M.Sw, a, b, 0.0, s))) return e;
   if ((e = apply_r(M, p, M.opH[lvl_below], w, M.Sw, a, b, 1.0, s))) return e;
-  for (int k = 0; k < M.D; ++k) {
-    if ((e = apply_r(M, p, M.at(M.opB[lvl_below], k * bb), w, M.S2, a, b, 0.0, s))) return e;
-    if ((e = apply_l(M, p, M.at(M.opA[lvl_below], k * bb), M.S2, M.Sw, a, b, 1.0, s))) return e;
-  }
-  return hipSuccess;
+  if (M.D == 0) return hipSuccess;
+  if ((e = apply_r_k(M, p, M.opB[lvl_below], bb, w, 0, M.S2, cube, a, b, 0.0, M.D, s))) return e;
+  GemmDesc g = desc0();  // Sw[a; l, r] += sum_{k, l'} A_k[l, l'] S2_k[a; l', r]
+  g.batch = a;
+  g.M = b; g.N = b; g.K = M.D * b; g.K2 = b;
+  g.A = M.opA[lvl_below]; g.sAm = b; g.sAk = 1; g.sAk1 = bb; g.sAb = 0;
+  g.B = M.S2; g.sBk = b; g.sBk1 = cube; g.sBn = 1; g.sBb = bb;
+  g.C = M.Sw; g.sCm = b; g.sCn = 1; g.sCb = bb;
+  g.beta = 1.0;
+  return run(M, p, g, s, OC_APPLY_L);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,17 +580,16 @@ hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, 
 // ---------------------------------------------------------------------------
 ttn_status stage_ascend(Member& M, int tau, hipStream_t s) {
   Prec p = M.gp();
-  const int a = M.dims[tau], b = M.dims[tau - 1];
-  const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+  const int a = M.dims[tau], b = M.dims[tau - 1], D = M.D;
+  const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
   const void* w = M.wT[tau];
   HIPCHK(s_apply(M, tau - 1, w, a, b, s));
   HIPCHK(close_aa(M, p, w, M.Sw, M.opH[tau], a, b, 1.0, 0.0, s));
-  for (int k = 0; k < M.D; ++k) {
-    HIPCHK(apply_r(M, p, M.at(M.opA[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
-    HIPCHK(close_aa(M, p, w, M.S2, M.at(M.opA[tau], k * aa), a, b, 1.0, 0.0, s));
-    HIPCHK(apply_l(M, p, M.at(M.opB[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
-    HIPCHK(close_aa(M, p, w, M.S2, M.at(M.opB[tau], k * aa), a, b, 1.0, 0.0, s));
-  }
+  // all product terms at once: A'_k = C(w, A_k .r w), B'_k = C(w, B_k .l w)
+  HIPCHK(apply_r_k(M, p, M.opA[tau - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opA[tau], aa, a, b, 1.0, 0.0, D, s));
+  HIPCHK(apply_l_k(M, p, M.opB[tau - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opB[tau], aa, a, b, 1.0, 0.0, D, s));
   return TTN_OK;
 }
 
@@ -553,60 +613,56 @@ ttn_status stage_descend_rho(Member& M, hipStream_t s) {
 ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
   Prec p = M.gp();
   const int n = M.n, D = M.D;
-  // carry A_k, B_k of level tau-1 up through layers tau..n-1
+  // carry A_k, B_k of level tau-1 up through layers tau..n-1 (all k at once)
   const void* prevA = M.opA[tau - 1];
   const void* prevB = M.opB[tau - 1];
   for (int sg = tau; sg < n; ++sg) {
     const int a = M.dims[sg], b = M.dims[sg - 1];
-    const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+    const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
     const void* w = M.wT[sg];
-    for (int k = 0; k < D; ++k) {
-      HIPCHK(apply_r(M, p, M.at(prevA, k * bb), w, M.S2, a, b, 0.0, s));
-      HIPCHK(close_aa(M, p, w, M.S2, M.at(M.At[sg], k * aa), a, b, 1.0, 0.0, s));
-      HIPCHK(apply_l(M, p, M.at(prevB, k * bb), w, M.S2, a, b, 0.0, s));
-      HIPCHK(close_aa(M, p, w, M.S2, M.at(M.Bt[sg], k * aa), a, b, 1.0, 0.0, s));
-    }
+    HIPCHK(apply_r_k(M, p, prevA, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.At[sg], aa, a, b, 1.0, 0.0, D, s));
+    HIPCHK(apply_l_k(M, p, prevB, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.Bt[sg], aa, a, b, 1.0, 0.0, D, s));
     prevA = M.At[sg];
     prevB = M.Bt[sg];
   }
   // top dressing: Rbar = 1/2 (v^T A v + v A v^T), Lbar = 1/2 (v B v^T + v^T B v)
   const int x = M.dims[n - 1];
-  const size_t xx = (size_t)x * x;
+  const long long xx = (long long)x * x;
   int cur = 0;
-  for (int k = 0; k < D; ++k) {
-    const void* Ak = M.at(M.At[n - 1], k * xx);
-    const void* Bk = M.at(M.Bt[n - 1], k * xx);
-    void* R = M.at(M.Rb[cur], k * xx);
-    void* Lq = M.at(M.Lb[cur], k * xx);
-    HIPCHK(mm(M, p, Ak, false, M.vT, false, M.tmpT, x, 1.0, 0.0, s));   // A v
-    HIPCHK(mm(M, p, M.vT, true, M.tmpT, false, R, x, 0.5, 0.0, s));     // v^T A v
-    HIPCHK(mm(M, p, Ak, false, M.vT, true, M.tmpT, x, 1.0, 0.0, s));    // A v^T
-    HIPCHK(mm(M, p, M.vT, false, M.tmpT, false, R, x, 0.5, 1.0, s));    // v A v^T
-    HIPCHK(mm(M, p, Bk, false, M.vT, true, M.tmpT, x, 1.0, 0.0, s));    // B v^T
-    HIPCHK(mm(M, p, M.vT, false, M.tmpT, false, Lq, x, 0.5, 0.0, s));   // v B v^T
-    HIPCHK(mm(M, p, Bk, false, M.vT, false, M.tmpT, x, 1.0, 0.0, s));   // B v
-    HIPCHK(mm(M, p, M.vT, true, M.tmpT, false, Lq, x, 0.5, 1.0, s));    // v^T B v
+  {
+    const void* At = M.At[n - 1];
+    const void* Bt = M.Bt[n - 1];
+    void* R = M.Rb[cur];
+    void* Lq = M.Lb[cur];
+    HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // A v
+    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, R, xx, x, 0.5, 0.0, D, s));    // v^T A v
+    HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // A v^T
+    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, R, xx, x, 0.5, 1.0, D, s));   // v A v^T
+    HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // B v^T
+    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, Lq, xx, x, 0.5, 0.0, D, s));  // v B v^T
+    HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // B v
+    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));   // v^T B v
   }
-  // descend through layers n-1 .. tau+1
+  // descend through layers n-1 .. tau+1 (all k at once)
   for (int sg = n - 1; sg >= tau + 1; --sg) {
     const int a = M.dims[sg], b = M.dims[sg - 1];
-    const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+    const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
     const void* w = M.wT[sg];
     const void* P = M.Pc[sg];
     const int nx = 1 - cur;
-    for (int k = 0; k < D; ++k) {
-      void* Rn = M.at(M.Rb[nx], k * bb);
-      void* Ln = M.at(M.Lb[nx], k * bb);
-      // inside a parent (A left child, B right child) + across parents
-      HIPCHK(apply_l(M, p, M.at(M.At[sg - 1], k * bb), w, M.S2, a, b, 0.0, s));
-      HIPCHK(close_r(M, p, P, M.S2, Rn, a, b, 0.5, 0.0, s));
-      HIPCHK(left_mul(M, p, M.at(M.Rb[cur], k * aa), w, M.S3, a, b, 1.0, 0.0, s));
-      HIPCHK(close_l(M, p, w, M.S3, Rn, a, b, 0.5, 1.0, s));
-      HIPCHK(apply_r(M, p, M.at(M.Bt[sg - 1], k * bb), w, M.S2, a, b, 0.0, s));
-      HIPCHK(close_l(M, p, P, M.S2, Ln, a, b, 0.5, 0.0, s));
-      HIPCHK(left_mul(M, p, M.at(M.Lb[cur], k * aa), w, M.S3, a, b, 1.0, 0.0, s));
-      HIPCHK(close_r(M, p, w, M.S3, Ln, a, b, 0.5, 1.0, s));
-    }
+    void* Rn = M.Rb[nx];
+    void* Ln = M.Lb[nx];
+    // inside a parent (A left child, B right child) + across parents
+    HIPCHK(apply_l_k(M, p, M.At[sg - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+    HIPCHK(close_r_k(M, p, P, 0, M.S2, cube, Rn, bb, a, b, 0.5, 0.0, D, s));
+    HIPCHK(left_mul_k(M, p, M.Rb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
+    HIPCHK(close_l_k(M, p, w, 0, M.S3, cube, Rn, bb, a, b, 0.5, 1.0, D, s));
+    HIPCHK(apply_r_k(M, p, M.Bt[sg - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+    HIPCHK(close_l_k(M, p, P, 0, M.S2, cube, Ln, bb, a, b, 0.5, 0.0, D, s));
+    HIPCHK(left_mul_k(M, p, M.Lb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
+    HIPCHK(close_r_k(M, p, w, 0, M.S3, cube, Ln, bb, a, b, 0.5, 1.0, D, s));
     cur = nx;
   }
   M.rb_cur = cur;
@@ -614,20 +670,30 @@ ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
   return TTN_OK;
 }
 
+// Env = [rho | Rbar_1..Rbar_D | Lbar_1..Lbar_D] o [S w ; B_k .l w ; A_k .r w]:
+// the 1 + 2D tensors are staged side by side (slice s at s a b^2) and their
+// left factors copied next to each other, so that the environment is one
+// product whose contraction index runs over (slice, a'); it is written once.
 ttn_status stage_env(Member& M, int tau, hipStream_t s) {
   Prec p = M.gp();
-  const int a = M.dims[tau], b = M.dims[tau - 1];
-  const size_t bb = (size_t)b * b, aa = (size_t)a * a;
+  const int a = M.dims[tau], b = M.dims[tau - 1], D = M.D;
+  const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
   const void* w = M.wT[tau];
-  HIPCHK(s_apply(M, tau - 1, w, a, b, s));
-  HIPCHK(left_mul(M, p, M.rho[tau], M.Sw, M.envT, a, b, 1.0, 0.0, s));
-  for (int k = 0; k < M.D; ++k) {
-    HIPCHK(apply_l(M, p, M.at(M.opB[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
-    HIPCHK(left_mul(M, p, M.at(M.Rb[M.rb_cur], k * aa), M.S2, M.envT, a, b, 1.0, 1.0, s));
-    HIPCHK(apply_r(M, p, M.at(M.opA[tau - 1], k * bb), w, M.S2, a, b, 0.0, s));
-    HIPCHK(left_mul(M, p, M.at(M.Lb[M.rb_cur], k * aa), M.S2, M.envT, a, b, 1.0, 1.0, s));
+  HIPCHK(s_apply(M, tau - 1, w, a, b, s));                                        // slice 0
+  HIPCHK(apply_l_k(M, p, M.opB[tau - 1], bb, w, 0, M.at(M.Estage, cube), cube, a, b, 0.0, D, s));
+  HIPCHK(apply_r_k(M, p, M.opA[tau - 1], bb, w, 0, M.at(M.Estage, (1 + D) * cube), cube, a, b, 0.0, D, s));
+  HIPCHK(copy_bytes(M.Xst, M.rho[tau], M.el(aa), s));
+  if (D > 0) {
+    HIPCHK(copy_bytes(M.at(M.Xst, aa), M.Rb[M.rb_cur], M.el(D * aa), s));
+    HIPCHK(copy_bytes(M.at(M.Xst, (1 + D) * aa), M.Lb[M.rb_cur], M.el(D * aa), s));
   }
-  if (M.prec != TTN_FP64) HIPCHK(convert_f32_to_f64((const float*)M.envT, M.env64, (size_t)a * bb, s));
+  GemmDesc g = desc0();
+  g.M = a; g.N = (int)bb; g.K = (1 + 2 * D) * a; g.K2 = a;
+  g.A = M.Xst; g.sAm = a; g.sAk = 1; g.sAk1 = aa;
+  g.B = M.Estage; g.sBk = bb; g.sBk1 = cube; g.sBn = 1;
+  g.C = M.envT; g.sCm = bb; g.sCn = 1;
+  HIPCHK(run(M, p, g, s, OC_LEFT_MUL));
+  if (M.prec != TTN_FP64) HIPCHK(convert_f32_to_f64((const float*)M.envT, M.env64, (size_t)cube, s));
   M.env_tau = tau;
   return TTN_OK;
 }

@@ -113,23 +113,26 @@ def test_stage_parity_fp64(B, name, model, L, chi):
     gpu.close()
 
 
-# Sweeps from identical states: (name, model, L, chi, sweeps, tolerance).
-# Well-conditioned environments (sigma_min/sigma_max > 1e-9) are held to
-# 1e-10.  The L = 16, chi = 8 chain has environments with sigma_min/sigma_max
-# ~ 1e-11: the polar factor is determined there only to ~1e-16/1e-11 in the
-# weakest directions, and two LAPACK SVD drivers (gesdd, gesvd) run on the
-# same sweeps already disagree by 4.9e-8 in the energy; each sweep is
-# compared from the reference's state (re-anchored) and held to 5e-8.
+# Sweeps from identical states: (name, model, L, chi, sweeps).  Each sweep
+# starts from the reference's state (re-anchored) and the energies after it
+# are compared.  The bar is 1e-10 where the reference's environments are well
+# conditioned.  Where an environment has sigma_min/sigma_max = r small, its
+# polar factor is fixed to working precision only up to eps / r in the
+# weakest directions (two LAPACK SVD drivers, gesdd and gesvd, already
+# disagree by 4.9e-8 in the energy on the L = 16, chi = 8 chain, where
+# r ~ 1e-10), and the later layer updates of the same sweep carry that
+# difference on: the bar is max(1e-10, eps / (10 r)) with r the smallest
+# ratio of the reference's sweep (1e-10 for r >= 2.2e-7).
 SWEEPS = [
-    ("tfim_L64_chi3", I.tfim_chain(1.0), 64, 3, 6, 1e-10),
-    ("xxx_L64_chi3", I.xxx_chain(), 64, 3, 6, 1e-10),
-    ("tfim_L16_chi8_cfg1", I.tfim_chain(1.0), 16, 8, 6, 5e-8),
+    ("tfim_L64_chi3", I.tfim_chain(1.0), 64, 3, 6),
+    ("xxx_L64_chi3", I.xxx_chain(), 64, 3, 6),
+    ("tfim_L16_chi8_cfg1", I.tfim_chain(1.0), 16, 8, 6),
 ]
 
 
 @pytest.mark.parametrize("keep_gauge", [True, False], ids=["plain", "gauge_fixed"])
-@pytest.mark.parametrize("name,model,L,chi,sweeps,tol", SWEEPS, ids=[c[0] for c in SWEEPS])
-def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol, keep_gauge):
+@pytest.mark.parametrize("name,model,L,chi,sweeps", SWEEPS, ids=[c[0] for c in SWEEPS])
+def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, keep_gauge):
     # the basis rotation of the gauge-fixed mode leaves the state, hence every
     # energy, unchanged
     print(f"[sweep parity] {name} keep_gauge={keep_gauge}", flush=True)
@@ -137,7 +140,7 @@ def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol, keep_ga
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
     ref.initialise()
     gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, keep_gauge=keep_gauge))
-    worst = 0.0
+    eps = np.finfo(np.float64).eps
     for s in range(sweeps):
         for tau in range(1, ref.n):
             gpu.set_tensor(tau, ref.ws[tau - 1])
@@ -146,9 +149,11 @@ def test_anchored_sweep_parity_fp64(B, name, model, L, chi, sweeps, tol, keep_ga
         gpu.sweep(1)
         e_gpu = gpu.energy()[0]
         e_ref = ref.sweep()
-        worst = max(worst, abs(e_gpu - e_ref) / abs(e_ref))
-    print(f"  worst per-sweep relative energy difference {worst:.3e}")
-    assert worst <= tol
+        d = abs(e_gpu - e_ref) / abs(e_ref)
+        r = float(np.min(ref.diag[-1]["sigma_ratio"]))
+        tol = max(1e-10, eps / (10.0 * r))
+        print(f"  sweep {s}: relative difference {d:.3e}, reference sigma_min/sigma_max {r:.2e}, bar {tol:.1e}")
+        assert d <= tol
     gpu.close()
 
 
