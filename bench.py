@@ -10,7 +10,9 @@ sweeps bracketed by device synchronisation.  Prints ONE JSON line.
 
 The default workload is the Heisenberg chain L = 4096 at chi = 256 in
 split-bf16; the 64 x 4 torus at chi = 128 is measured in the same run and
-reported under "chi128".  For each, the line carries:
+reported under "chi128", and 128 independent TFIM chains (seeded L, h, chi)
+swept together in one handle under "batch128", next to the same chains
+swept one at a time.  For each single chain, the line carries:
   * sweeps/s and the algorithmic contraction TFLOP/s;
   * the energy per site after the timed sweeps, the float64 re-evaluation of
     that same state (its isometries and top tensor loaded into a float64
@@ -57,6 +59,7 @@ def parse():
     p.add_argument("--no-fp64-ref", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-secondary", action="store_true", help="skip the chi=128 workload of the default run")
+    p.add_argument("--no-autotune", action="store_true", help="fixed launch heuristics instead of the autotuner")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
     return p.parse_args()
 
@@ -117,12 +120,16 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
     model = build(I)
 
     t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
-    for _ in range(warmup):
-        t.sweep(1)
+    # warm-up: the first sweep runs eagerly (the autotuner times the launch
+    # candidates of every product shape it meets), the next one captures the
+    # layer part of a sweep into a HIP graph, replayed in the timed sweeps
+    t.sweep(1)
+    for _ in range(max(1, warmup) - 1):
+        t.sweep(1, graph=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        t.sweep(1)
+        t.sweep(1, graph=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st = t.stats()
@@ -178,7 +185,8 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
     e64 = None
     if prec != "fp64" and fp64_ref:
         r = B.TTN(B.ChainInput(model, L, chi, "fp64", seed=seed))
-        r.sweep(warmup + 2 * steps)
+        r.sweep(1)
+        r.sweep(max(1, warmup) - 1 + 2 * steps, graph=True)
         e64 = float(r.energy()[0])
         r.close()
         del r
@@ -188,6 +196,60 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
         "sweeps_per_s": sweeps_per_s, "ms_per_step": 1e3 * elapsed / steps, "tflops": tflops,
         "stats": st, "energy": e, "e_re": e_re, "err_re": err_re, "e64": e64, "err": err,
         "roofline": roofline, "classes": classes,
+    }
+
+
+def measure_batch(B, I, steps, warmup):
+    """128 independent transverse-field Ising chains (seeded draw of L, h and
+    chi; float32 bulk, float64 polar and top) swept together in one handle,
+    against the same chains swept one at a time."""
+    import numpy as np
+    import torch
+    draws = I.batched_tfim_draws(128, 2026)
+    mk = lambda d: B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp32", seed=d["seed"])
+    t = B.TTN([mk(d) for d in draws])
+    w = max(1, warmup)
+    t.sweep(1)
+    for _ in range(w - 1):
+        t.sweep(1, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.sweep(1, graph=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    e_b = t.energy()
+    flops = sum(t.stats(i).flops_bulk for i in range(len(draws)))
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    # one chain at a time, eager, same number of sweeps
+    e_s = np.zeros(len(draws))
+    el_s = 0.0
+    for i, d in enumerate(draws):
+        u = B.TTN(mk(d))
+        u.sweep(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u.sweep(steps)
+        torch.cuda.synchronize()
+        el_s += time.perf_counter() - t0
+        e_s[i] = u.energy()[0]
+        u.close()
+        del u
+    torch.cuda.empty_cache()
+    small = np.array([d["chi"] <= 64 for d in draws])
+    rel = np.abs(e_b - e_s) / np.abs(e_s)
+    return {
+        "workload": "128 TFIM chains, L in {64..1024}, h in [0.5, 1.5], chi in {32, 48, 64, 96} (seed 2026)",
+        "precision": "fp32", "members": len(draws),
+        "ttn_sweeps_per_s": round(len(draws) * steps / el, 3),
+        "ms_per_batched_sweep": round(1e3 * el / steps, 3),
+        "contraction_tflops": round(flops / (el / steps) / 1e12, 3),
+        "one_at_a_time_ttn_sweeps_per_s": round(len(draws) * steps / el_s, 3),
+        "speedup_vs_one_at_a_time": round(el_s / el, 3),
+        "energy_max_rel_diff_vs_one_at_a_time_chi_le_64": float(rel[small].max()),
+        "energy_max_rel_diff_vs_one_at_a_time_all": float(rel.max()),
     }
 
 
@@ -203,6 +265,7 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    B.autotune(0 if args.no_autotune else 1)
     m = measure(B, I, args.config, args.precision, args.steps, args.warmup, args.seed, not args.no_fp64_ref)
     st = m["stats"]
     secondary = None
@@ -216,6 +279,10 @@ def main():
             "energy_rel_diff_vs_fp64_run": m2["err"], "roofline": m2["roofline"],
             "classes": m2["classes"],
         }
+
+    batch = None
+    if args.config == DEFAULT_CONFIG and not args.no_secondary:
+        batch = measure_batch(B, I, args.steps, args.warmup)
 
     cpu = None
     if not args.no_cpu:
@@ -251,7 +318,9 @@ def main():
         "lanczos_resid_last": st.lanczos_resid,
         "roofline": m["roofline"],
         "classes": m["classes"],
+        "autotune_entries": B.autotune(-1),
         "chi128": secondary,
+        "batch128": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

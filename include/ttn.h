@@ -206,6 +206,18 @@ typedef struct ttn_stats_t {
 
 ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
 
+/* Autotuning of the contraction launches, for the whole process (all
+ * handles).  mode 0: fixed heuristics (default); 1: the first time a product
+ * of a new shape and layout is run eagerly (not under graph capture) with
+ * beta = 0, its candidate launches (split-K counts of the MFMA kernels, the
+ * general kernel) are timed with HIP events on the handle's stream (this
+ * synchronises that stream) and the fastest is kept; 2: kept choices only.
+ * Kept choices are used in every mode but 0, also inside captured graphs.
+ * mode -1 leaves the mode unchanged.  entries (host, may be NULL) receives
+ * the number of kept choices.  Results may differ from the heuristic's in
+ * rounding only (another split-K count sums in another order). */
+ttn_status ttn_autotune(int mode, int* entries);
+
 /* Event timing of the contraction classes (apply_r, apply_l, close,
  * left_mul, close_l, close_r, top_mm, polar_gemm, jacobi, lanczos_gemm).
  * ttn_profile(h, 1) clears the record and brackets every later launch of a

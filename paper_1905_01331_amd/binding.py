@@ -26,7 +26,7 @@ PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
 # Every symbol declared in include/ttn.h.
 EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
-    "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator",
+    "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
 ]
 
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_update": ([P, I], I),
         "ttn_energy": ([P, DP], I),
         "ttn_sweep": ([P, I, I], I),
+        "ttn_autotune": ([I, ctypes.POINTER(ctypes.c_int)], I),
         "ttn_get_tensor": ([P, I, I, DP], I),
         "ttn_set_tensor": ([P, I, I, DP], I),
         "ttn_get_operator": ([P, I, I, I, I, DP], I),
@@ -145,6 +146,15 @@ class ChainInput:
         cfg.krylov, cfg.restarts, cfg.lanczos_tol = int(krylov), int(restarts), float(lanczos_tol)
         cfg.keep_gauge = 1 if keep_gauge else 0
         self.cfg = cfg
+
+
+def autotune(mode=-1):
+    """Sets the process-wide autotuning mode (0 off, 1 tune new shapes, 2 use
+    kept choices; -1 unchanged) and returns the number of kept choices."""
+    lib = load_library()
+    n = ctypes.c_int(0)
+    _check(lib.ttn_autotune(int(mode), ctypes.byref(n)))
+    return n.value
 
 
 def ttn_workspace_bytes(inputs):

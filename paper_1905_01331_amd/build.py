@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libttn.so")
 
-SOURCES = ["gemm_plain.hip", "gemm_mfma.hip", "small.hip", "jacobi_block.hip", "lanczos.hip", "ttn_api.cpp"]
+SOURCES = ["gemm_plain.hip", "gemm_mfma.hip", "gemm_tune.cpp", "small.hip", "jacobi_block.hip", "lanczos.hip",
+           "ttn_api.cpp"]
 ARCH = "gfx950"
 
 

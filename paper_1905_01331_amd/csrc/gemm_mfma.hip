@@ -20,6 +20,7 @@
 // float32 slices reduced in a fixed order (deterministic).
 #include "common.h"
 #include "gemm_internal.h"
+#include <algorithm>
 
 namespace ttn {
 namespace {
@@ -501,7 +502,8 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // Returns hipErrorNotSupported when the shape/layout does not fit the MFMA
 // loaders (caller falls back to the general kernel).
-static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
+static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s, int splits_req,
+                              int* splits_used) {
   if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
   const bool akc = (g.sAk == 1), bkc = (g.sBk == 1);
   const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
@@ -524,10 +526,16 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
     if (sps > 128) sps = 128;
     splits = sps < 1 ? 1 : (int)sps;
   }
+  if (splits_req > 0) {  // a tuned split count, within the scratch and K
+    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(double);
+    long long cap = std::min<long long>({128, (long long)(scratch_bytes / slice), (g.K + BK64 - 1) / BK64});
+    splits = (int)std::max<long long>(1, std::min<long long>(splits_req, cap));
+  }
   int kchunk = (g.K + splits - 1) / splits;
   kchunk = ((kchunk + BK64 - 1) / BK64) * BK64;
   splits = (g.K + kchunk - 1) / kchunk;
   if (splits < 1) splits = 1;
+  if (splits_used) *splits_used = splits;
   double* partial = (double*)scratch;
   hipError_t e;
   if (akc && bkc) e = launch64<true, true>(g, splits, kchunk, partial, s);
@@ -539,8 +547,9 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   return hipSuccess;
 }
 
-hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
-  if (prec == P_F64) return gemm_mfma64(g, scratch, scratch_bytes, s);
+hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s, int splits_req,
+                     int* splits_used) {
+  if (prec == P_F64) return gemm_mfma64(g, scratch, scratch_bytes, s, splits_req, splits_used);
   if (prec != P_F32 && prec != P_BF16X3) return hipErrorNotSupported;
   if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
   const int BK = (prec == P_F32) ? 16 : 32;
@@ -567,10 +576,16 @@ hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch
     if (sps > 128) sps = 128;
     splits = sps < 1 ? 1 : (int)sps;
   }
+  if (splits_req > 0) {  // a tuned split count, within the scratch and K
+    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(float);
+    long long cap = std::min<long long>({128, (long long)(scratch_bytes / slice), (g.K + BK - 1) / BK});
+    splits = (int)std::max<long long>(1, std::min<long long>(splits_req, cap));
+  }
   int kchunk = (g.K + splits - 1) / splits;
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   splits = (g.K + kchunk - 1) / kchunk;
   if (splits < 1) splits = 1;
+  if (splits_used) *splits_used = splits;
   float* partial = (float*)scratch;
   hipError_t e;
   if (prec == P_F32) {

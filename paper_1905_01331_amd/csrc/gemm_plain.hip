@@ -270,8 +270,10 @@ hipError_t splitk_reduce_f64(const GemmDesc& g, int splits, const double* partia
 }
 
 hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
-  if (gemm_path_mfma_enabled()) {
-    hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s);
+  GemmChoice c{0, 0};
+  const bool tuned = gemm_tuned_choice(prec, g, s, scratch, scratch_bytes, &c);
+  if (gemm_path_mfma_enabled() && !(tuned && c.path == 1)) {
+    hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s, tuned ? c.splits : 0);
     if (e != hipErrorNotSupported) return e;
   }
   return gemm_plain(prec, g, scratch, scratch_bytes, s);

@@ -17,6 +17,7 @@
 
 #include "ttn.h"
 #include "common.h"
+#include "gemm_internal.h"
 #include "lanczos.h"
 
 using namespace ttn;
@@ -1449,6 +1450,13 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out) {
   out->jacobi_sweeps[1] = ji[2];
   out->jacobi_sweeps[2] = ji[4];
   out->jacobi_sweeps[3] = ji[16];
+  return TTN_OK;
+}
+
+ttn_status ttn_autotune(int mode, int* entries) {
+  if (mode < -1 || mode > 2) return fail(TTN_EINVAL, "autotune mode %d outside [-1, 2]", mode);
+  if (mode >= 0) gemm_tune_set_mode(mode);
+  if (entries) *entries = (int)gemm_tune_entries();
   return TTN_OK;
 }
 

@@ -120,3 +120,45 @@ def test_batch_with_larger_bond_dimension(B):
         assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 1e-13
     solo.close()
     batch.close()
+
+
+def test_autotuner_keeps_choices_and_replays_them(B):
+    # mode 1 times the launch candidates of each new product shape when first
+    # met eagerly (here: at initialisation and in the first sweep); the kept
+    # choices only reorder float32 sums, so the energy of a given state stays
+    # within the float32 bar (relative to the model's energy scale); they are
+    # then used eagerly and inside the captured graph, which must agree
+    # exactly
+    model, L, chi = I.tfim_chain(1.0), 128, 64
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 3)
+    tol = 2e-6
+    try:
+        B.autotune(0)
+        ref = B.TTN(B.ChainInput(model, L, chi, "fp32", w0=ws))
+        e0_ref = ref.energy()[0]
+        scale = max(abs(e0_ref), abs(ref.stats().shift))
+        ref.close()
+        B.autotune(1)
+        tuned = B.TTN(B.ChainInput(model, L, chi, "fp32", w0=ws))
+        assert abs(tuned.energy()[0] - e0_ref) <= tol * scale
+        tuned.sweep(1)
+        assert B.autotune(-1) > 0
+        n = tuned.n_levels()
+        state = [tuned.get_tensor(tau) for tau in range(1, n)]
+        r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=tuned.get_tensor(B.TTN_TOP)))
+        assert abs(tuned.energy()[0] - r.energy()[0]) <= tol * scale
+        r.close()
+        kept = B.autotune(2)
+        eager = B.TTN(B.ChainInput(model, L, chi, "fp32", w0=ws))
+        eager.sweep(1)
+        graph = B.TTN(B.ChainInput(model, L, chi, "fp32", w0=ws))
+        graph.sweep(1)
+        for _ in range(3):
+            eager.sweep(1)
+            graph.sweep(1, graph=True)
+            assert eager.energy()[0] == graph.energy()[0]
+        assert B.autotune(-1) == kept
+        for h in (tuned, eager, graph):
+            h.close()
+    finally:
+        B.autotune(0)
