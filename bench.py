@@ -202,11 +202,19 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
 def measure_batch(B, I, steps, warmup):
     """128 independent transverse-field Ising chains (seeded draw of L, h and
     chi; float32 bulk, float64 polar and top) swept together in one handle,
-    against the same chains swept one at a time."""
+    against the same chains swept one at a time.  Chains of equal L and chi
+    form launch groups (one launch per kernel for the whole group).  The
+    energy error is each chain's energy against the float64 re-evaluation of
+    its final state; the one-at-a-time runs follow their own trajectories
+    (the group shares the top eigensolver's restarts, the autotuner may pick
+    other split-K counts for group launches, and rounding differences grow
+    along the early, ill-conditioned sweeps), so their difference is
+    reported as a drift, not as an error."""
     import numpy as np
     import torch
     draws = I.batched_tfim_draws(128, 2026)
     mk = lambda d: B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp32", seed=d["seed"])
+    n_groups = len({(d["L"], d["chi"]) for d in draws})
     t = B.TTN([mk(d) for d in draws])
     w = max(1, warmup)
     t.sweep(1)
@@ -220,8 +228,20 @@ def measure_batch(B, I, steps, warmup):
     el = time.perf_counter() - t0
     e_b = t.energy()
     flops = sum(t.stats(i).flops_bulk for i in range(len(draws)))
+    # float64 re-evaluation of every member's final state in one batch handle
+    states = []
+    for i in range(len(draws)):
+        n_i = t.n_levels(i)
+        states.append(([t.get_tensor(tau, i) for tau in range(1, n_i)], t.get_tensor(B.TTN_TOP, i)))
+    shifts = np.array([t.stats(i).shift for i in range(len(draws))])
     t.close()
     del t
+    torch.cuda.empty_cache()
+    r = B.TTN([B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp64", w0=w, v0=v)
+               for d, (w, v) in zip(draws, states)])
+    e_re = r.energy()
+    r.close()
+    del r, states
     torch.cuda.empty_cache()
     # one chain at a time, eager, same number of sweeps
     e_s = np.zeros(len(draws))
@@ -238,8 +258,8 @@ def measure_batch(B, I, steps, warmup):
         u.close()
         del u
     torch.cuda.empty_cache()
-    small = np.array([d["chi"] <= 64 for d in draws])
     rel = np.abs(e_b - e_s) / np.abs(e_s)
+    err = np.abs(e_b - e_re) / np.maximum(np.abs(e_re), shifts)
     return {
         "workload": "128 TFIM chains, L in {64..1024}, h in [0.5, 1.5], chi in {32, 48, 64, 96} (seed 2026)",
         "precision": "fp32", "members": len(draws),
@@ -248,8 +268,9 @@ def measure_batch(B, I, steps, warmup):
         "contraction_tflops": round(flops / (el / steps) / 1e12, 3),
         "one_at_a_time_ttn_sweeps_per_s": round(len(draws) * steps / el_s, 3),
         "speedup_vs_one_at_a_time": round(el_s / el, 3),
-        "energy_max_rel_diff_vs_one_at_a_time_chi_le_64": float(rel[small].max()),
-        "energy_max_rel_diff_vs_one_at_a_time_all": float(rel.max()),
+        "launch_groups": n_groups,
+        "energy_max_rel_err_vs_fp64_reeval": float(err.max()),
+        "trajectory_max_rel_diff_vs_one_at_a_time": float(rel.max()),
     }
 
 

@@ -26,7 +26,18 @@ struct GemmDesc {
   // total count.  batch1 == 0: one level, X at b * sXb.
   int batch1;
   long long sAb2, sBb2, sCb2;
+  // launch group (see GroupCtx): mcount > 1 products of the same shape whose
+  // operands, result, split-K scratch and skip flag all lie mstride bytes
+  // apart, run as one launch (member index outermost)
+  int mcount;
+  long long mstride;
 };
+
+__host__ __device__ __forceinline__ int gemm_members(const GemmDesc& g) { return g.mcount > 1 ? g.mcount : 1; }
+template <class T>
+__host__ __device__ __forceinline__ T* member_ptr(T* p, const GemmDesc& g, int m) {
+  return p ? (T*)((uintptr_t)p + (long long)m * g.mstride) : p;
+}
 
 __host__ __device__ __forceinline__ long long batch_offset(const GemmDesc& g, int b, long long s1, long long s2) {
   if (g.batch1 <= 0) return (long long)b * s1;
@@ -35,6 +46,27 @@ __host__ __device__ __forceinline__ long long batch_offset(const GemmDesc& g, in
 }
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
+
+// Launch group: identical-layout batch members placed `stride` bytes apart in
+// the workspace run as one launch per kernel; the member index is
+// blockIdx.y (small kernels) or the outermost grid index (products), and
+// every pointer argument (all of them point into a member's part of the
+// workspace) moves by stride bytes per member.  count = 1: one member.
+struct GroupCtx {
+  int count = 1;
+  long long stride = 0;
+};
+GroupCtx& grp();  // the calling thread's current launch group
+// scoped setting of the launch group
+struct GroupScope {
+  GroupCtx saved;
+  GroupScope(int count, long long stride) : saved(grp()) { grp().count = count; grp().stride = stride; }
+  ~GroupScope() { grp() = saved; }
+};
+template <class T>
+__device__ __forceinline__ T* mshift(T* p, long long ms) {
+  return p ? (T*)((uintptr_t)p + (long long)blockIdx.y * ms) : p;
+}
 
 // Launches one product in the given arithmetic.  F64: double operands and
 // result.  F32 / BF16X3: float operands and result (BF16X3 splits every

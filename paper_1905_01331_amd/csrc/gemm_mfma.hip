@@ -220,6 +220,13 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
 
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
+  {  // launch-group member: outermost index
+    const int per = g.batch * splits, mem = bz / per;
+    bz -= mem * per;
+    g.A = member_ptr(g.A, g, mem); g.B = member_ptr(g.B, g, mem); g.C = member_ptr(g.C, g, mem);
+    g.skip = member_ptr(g.skip, g, mem);
+    partial = member_ptr(partial, g, mem);
+  }
   if (g.skip && *g.skip) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -401,6 +408,13 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   __shared__ double sb_l[BK64][BN + 2];
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
+  {  // launch-group member: outermost index
+    const int per = g.batch * splits, mem = bz / per;
+    bz -= mem * per;
+    g.A = member_ptr(g.A, g, mem); g.B = member_ptr(g.B, g, mem); g.C = member_ptr(g.C, g, mem);
+    g.skip = member_ptr(g.skip, g, mem);
+    partial = member_ptr(partial, g, mem);
+  }
   if (g.skip && *g.skip) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
@@ -482,7 +496,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
 
 template <bool AKC, bool BKC>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
-  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
   hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk, partial,
                      tm);
   return hipGetLastError();
@@ -490,7 +504,7 @@ hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, 
 
 template <int MODE, bool AKC, bool BKC>
 hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
-  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits);
+  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
   hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
                      partial, tm);
   return hipGetLastError();

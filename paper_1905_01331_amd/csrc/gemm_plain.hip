@@ -46,9 +46,16 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
   __shared__ T Bs[PT_K][PT_N + 1];
   __shared__ T Al[MODE ? PT_K : 1][MODE ? PT_M + 1 : 1];
   __shared__ T Bl[MODE ? PT_K : 1][MODE ? PT_N + 1 : 1];
+  int bz = blockIdx.z;
+  {  // launch-group member: outermost index
+    const int per = g.batch * splits, mem = bz / per;
+    bz -= mem * per;
+    g.A = member_ptr(g.A, g, mem); g.B = member_ptr(g.B, g, mem); g.C = member_ptr(g.C, g, mem);
+    g.skip = member_ptr(g.skip, g, mem);
+    partial = member_ptr(partial, g, mem);
+  }
   if (g.skip && *g.skip) return;
 
-  const int bz = blockIdx.z;
   const int b = bz / splits;
   const int sp = bz - b * splits;
   const int m0 = blockIdx.y * PT_M;
@@ -181,17 +188,20 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
 // result does not depend on timing.
 template <typename T>
 __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict__ partial) {
-  if (g.skip && *g.skip) return;
-  long long total = (long long)g.batch * g.M * g.N;
-  long long MN = (long long)g.M * g.N;
-  long long stride = (long long)g.batch * MN;
+  const long long MN = (long long)g.M * g.N;
+  const long long stride = (long long)g.batch * MN;
+  const long long total = stride * gemm_members(g);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
-    int b = (int)(i / MN);
-    long long r = i - (long long)b * MN;
+    const int mem = (int)(i / stride);  // launch-group member
+    const int* skip = member_ptr(g.skip, g, mem);
+    if (skip && *skip) continue;
+    const long long im = i - (long long)mem * stride;
+    int b = (int)(im / MN);
+    long long r = im - (long long)b * MN;
     int m = (int)(r / g.N);
     int n = (int)(r - (long long)m * g.N);
-    const T* p = partial + (long long)b * MN + r;
+    const T* p = member_ptr(partial, g, mem) + (long long)b * MN + r;
     T s8[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
     int sp = 0;
     for (; sp + 8 <= splits; sp += 8) {
@@ -200,7 +210,8 @@ __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict
     }
     for (int u = 0; sp + u < splits; ++u) s8[u] += p[(long long)(sp + u) * stride];
     T s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
-    T* c = (T*)g.C + batch_offset(g, b, g.sCb, g.sCb2) + (long long)m * g.sCm + (long long)n * g.sCn;
+    T* c = (T*)member_ptr(g.C, g, mem) + batch_offset(g, b, g.sCb, g.sCb2) + (long long)m * g.sCm +
+           (long long)n * g.sCn;
     T out = (T)g.alpha * s;
     if (g.beta != 0.0) out += (T)g.beta * (*c);
     *c = out;
@@ -231,11 +242,11 @@ static hipError_t launch_plain(const GemmDesc& g, void* scratch, size_t scratch_
   if (kchunk == 0) kchunk = PT_K;
   splits = (g.K + kchunk - 1) / kchunk;
   if (splits < 1) splits = 1;
-  dim3 grid((g.N + PT_N - 1) / PT_N, (g.M + PT_M - 1) / PT_M, g.batch * splits);
+  dim3 grid((g.N + PT_N - 1) / PT_N, (g.M + PT_M - 1) / PT_M, g.batch * splits * gemm_members(g));
   hipLaunchKernelGGL((gemm_plain_kernel<T, MODE>), grid, dim3(PT_THREADS), 0, s, g, splits, kchunk,
                      (T*)scratch);
   if (splits > 1) {
-    long long total = (long long)g.batch * g.M * g.N;
+    long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
     int blocks = (int)((total + 255) / 256);
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(blocks), dim3(256), 0, s, g, splits,
@@ -254,7 +265,7 @@ hipError_t gemm_plain(Prec prec, const GemmDesc& g, void* scratch, size_t scratc
 }
 
 hipError_t splitk_reduce_f32(const GemmDesc& g, int splits, const float* partial, hipStream_t s) {
-  long long total = (long long)g.batch * g.M * g.N;
+  long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((splitk_reduce_kernel<float>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
@@ -262,7 +273,7 @@ hipError_t splitk_reduce_f32(const GemmDesc& g, int splits, const float* partial
 }
 
 hipError_t splitk_reduce_f64(const GemmDesc& g, int splits, const double* partial, hipStream_t s) {
-  long long total = (long long)g.batch * g.M * g.N;
+  long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
   int blocks = (int)((total + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL((splitk_reduce_kernel<double>), dim3(blocks), dim3(256), 0, s, g, splits, partial);

@@ -22,7 +22,7 @@
 namespace ttn {
 namespace {
 
-using Key = std::tuple<int, int, int, int, int, int, int, int, int, int, long long, long long>;
+using Key = std::tuple<int, int, int, int, int, int, int, int, int, int, long long, long long, int>;
 
 std::mutex g_mu;
 std::map<Key, GemmChoice> g_table;
@@ -30,7 +30,7 @@ int g_mode = 0;  // 0: heuristic only, 1: tune new keys, 2: stored choices only
 
 Key key_of(Prec p, const GemmDesc& g) {
   return Key{(int)p, g.M, g.N, g.K, g.K2, g.batch, g.batch1, (int)(g.sAk == 1), (int)(g.sBk == 1),
-             (int)(g.beta != 0.0), g.sAm, g.sBn};
+             (int)(g.beta != 0.0), g.sAm, g.sBn, gemm_members(g)};
 }
 
 bool overlaps(const GemmDesc& g) { return g.C == g.A || g.C == g.B; }

@@ -445,6 +445,7 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
                                   hipStream_t s, const int* skip) {
   constexpr int BS = JC_BS, BK = BS / 2;
   if (!info || !scratch || n < 1) return hipErrorInvalidValue;
+  if (grp().count != 1) return hipErrorInvalidValue;  // the grid barrier needs one problem per launch
   int nb = (n + BK - 1) / BK;
   nb += nb & 1;
   const int npairs = nb / 2;

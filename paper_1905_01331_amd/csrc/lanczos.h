@@ -15,7 +15,8 @@ hipError_t residual_vec(const double* Hv, const double* v, const double* lam, do
 hipError_t sign_fix(double* v, size_t n, hipStream_t s);
 hipError_t axpy_dev(double* y, const double* x, const double* scale, double factor, size_t n, hipStream_t s);
 hipError_t sqrt_inplace(double* x, hipStream_t s);
-hipError_t energy_store(const double* lam, double c, double L, double ly, double* out, hipStream_t s);
+// out[0] = lam[0], out[1] = (lam[0] + c[0] L) / (L ly)  (c: the shift, on the device)
+hipError_t energy_store(const double* lam, const double* c, double L, double ly, double* out, hipStream_t s);
 hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, hipStream_t s);
 hipError_t running_max(const double* x, double* run_max, hipStream_t s);
 hipError_t identity_f64(double* X, int n, hipStream_t s);

@@ -18,7 +18,8 @@ inline int grid_for(size_t n, int threads = 256, int cap = 4096) {
 // w <- w - alpha[j] q_j - beta[j-1] q_{j-1}
 __global__ void k_three_term(double* __restrict__ w, const double* __restrict__ qj, const double* __restrict__ qjm1,
                              const double* __restrict__ alpha, const double* __restrict__ beta, int j, size_t n,
-                             const int* __restrict__ stop) {
+                             const int* __restrict__ stop, long long ms_) {
+  w = mshift(w, ms_); qj = mshift(qj, ms_); qjm1 = mshift(qjm1, ms_); alpha = mshift(alpha, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_);
   if (*stop) return;
   double a = alpha[j];
   double b = (j > 0) ? beta[j - 1] : 0.0;
@@ -31,7 +32,8 @@ __global__ void k_three_term(double* __restrict__ w, const double* __restrict__ 
 
 // beta[j] = sqrt(ss); stop when beta[j] <= tol * hnorm (invariant subspace).
 __global__ void k_set_beta(const double* __restrict__ ss, const double* __restrict__ hss, double* __restrict__ beta,
-                           int j, double tol, int* __restrict__ stop, int* __restrict__ m_eff) {
+                           int j, double tol, int* __restrict__ stop, int* __restrict__ m_eff, long long ms_) {
+  ss = mshift(ss, ms_); hss = mshift(hss, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_); m_eff = mshift(m_eff, ms_);
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   if (*stop) { beta[j] = 0.0; return; }
   double b = sqrt(fmax(ss[0], 0.0));
@@ -47,7 +49,8 @@ __global__ void k_set_beta(const double* __restrict__ ss, const double* __restri
 
 // q_{j+1} = w / beta[j] (left at zero after a stop)
 __global__ void k_next_q(const double* __restrict__ w, double* __restrict__ qn, const double* __restrict__ beta, int j,
-                         size_t n, const int* __restrict__ stop) {
+                         size_t n, const int* __restrict__ stop, long long ms_) {
+  w = mshift(w, ms_); qn = mshift(qn, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_);
   double b = beta[j];
   bool st = *stop;
   double inv = (!st && b > 0.0) ? 1.0 / b : 0.0;
@@ -58,7 +61,8 @@ __global__ void k_next_q(const double* __restrict__ w, double* __restrict__ qn, 
 // Dense tridiagonal T (m x m) from alpha/beta; rows past m_eff are decoupled
 // with a diagonal above every Ritz value so they never become the lowest.
 __global__ void k_build_T(const double* __restrict__ alpha, const double* __restrict__ beta, int m,
-                          const int* __restrict__ stop, const int* __restrict__ m_eff, double* __restrict__ T) {
+                          const int* __restrict__ stop, const int* __restrict__ m_eff, double* __restrict__ T, long long ms_) {
+  alpha = mshift(alpha, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_); m_eff = mshift(m_eff, ms_); T = mshift(T, ms_);
   int me = (*stop) ? *m_eff : m;
   double big = 0.0;
   for (int i = 0; i < me; ++i) big = fmax(big, fabs(alpha[i]) + 2.0 * fabs(beta[i]));
@@ -80,7 +84,8 @@ __global__ void k_build_T(const double* __restrict__ alpha, const double* __rest
 // y = eigenvector of the smallest diagonal entry of the diagonalised T
 // (rows of U).
 __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* __restrict__ V, int m,
-                                double* __restrict__ y, double* __restrict__ theta) {
+                                double* __restrict__ y, double* __restrict__ theta, long long ms_) {
+  Tdiag = mshift(Tdiag, ms_); V = mshift(V, ms_); y = mshift(y, ms_); theta = mshift(theta, ms_);
   __shared__ int best;
   if (threadIdx.x == 0) {
     int b = 0;
@@ -94,7 +99,8 @@ __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* 
 }
 
 // x *= 1 / sqrt(ss[0])
-__global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__ ss, size_t n) {
+__global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__ ss, size_t n, long long ms_) {
+  x = mshift(x, ms_); ss = mshift(ss, ms_);
   double s = ss[0];
   double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -103,14 +109,16 @@ __global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__
 
 // r = Hv - lam v, lam = lamv[0]
 __global__ void k_residual(const double* __restrict__ Hv, const double* __restrict__ v, const double* __restrict__ lamv,
-                           double* __restrict__ r, size_t n) {
+                           double* __restrict__ r, size_t n, long long ms_) {
+  Hv = mshift(Hv, ms_); v = mshift(v, ms_); lamv = mshift(lamv, ms_); r = mshift(r, ms_);
   double lam = lamv[0];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     r[i] = Hv[i] - lam * v[i];
 }
 
 // Sign convention: the entry of largest magnitude (first on ties) positive.
-__global__ void k_sign_fix(double* __restrict__ v, size_t n) {
+__global__ void k_sign_fix(double* __restrict__ v, size_t n, long long ms_) {
+  v = mshift(v, ms_);
   __shared__ double bv[256];
   __shared__ long long bi[256];
   double best = -1.0;
@@ -144,26 +152,31 @@ __global__ void k_sign_fix(double* __restrict__ v, size_t n) {
 
 // out = a*x + b*y with a, b read from device scalars (sa, sb may be null for 1)
 __global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x, const double* __restrict__ scale,
-                           double factor, size_t n) {
+                           double factor, size_t n, long long ms_) {
+  y = mshift(y, ms_); x = mshift(x, ms_); scale = mshift(scale, ms_);
   double s = factor * (scale ? scale[0] : 1.0);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] += s * x[i];
 }
 
-__global__ void k_sqrt_inplace(double* x) {
+__global__ void k_sqrt_inplace(double* x, long long ms_) {
+  x = mshift(x, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = sqrt(fmax(x[0], 0.0));
 }
 
 // energy bookkeeping: out[0] = lam, out[1] = (lam + c L) / (L ly)
-__global__ void k_energy(const double* __restrict__ lam, double c, double L, double ly, double* __restrict__ out) {
+__global__ void k_energy(const double* __restrict__ lam, const double* __restrict__ c, double L, double ly,
+                         double* __restrict__ out, long long ms_) {
+  lam = mshift(lam, ms_); c = mshift(c, ms_); out = mshift(out, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     out[0] = lam[0];
-    out[1] = (lam[0] + c * L) / (L * ly);
+    out[1] = (lam[0] + c[0] * L) / (L * ly);
   }
 }
 
 // min/max of nrm[0..m) -> out[0] = min/max ratio (0 if max == 0)
-__global__ void k_ratio(const double* __restrict__ nrm, int m, double* __restrict__ out, double* __restrict__ run_min) {
+__global__ void k_ratio(const double* __restrict__ nrm, int m, double* __restrict__ out, double* __restrict__ run_min, long long ms_) {
+  nrm = mshift(nrm, ms_); out = mshift(out, ms_); run_min = mshift(run_min, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     double mn = nrm[0], mx = nrm[0];
     for (int i = 1; i < m; ++i) { mn = fmin(mn, nrm[i]); mx = fmax(mx, nrm[i]); }
@@ -173,17 +186,20 @@ __global__ void k_ratio(const double* __restrict__ nrm, int m, double* __restric
   }
 }
 
-__global__ void k_running_max(const double* __restrict__ x, double* __restrict__ run_max) {
+__global__ void k_running_max(const double* __restrict__ x, double* __restrict__ run_max, long long ms_) {
+  x = mshift(x, ms_); run_max = mshift(run_max, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) run_max[0] = fmax(run_max[0], x[0]);
 }
 
-__global__ void k_identity(double* __restrict__ X, int n) {
+__global__ void k_identity(double* __restrict__ X, int n, long long ms_) {
+  X = mshift(X, ms_);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n * n; i += gridDim.x * blockDim.x)
     X[i] = (i / n == i % n) ? 1.0 : 0.0;
 }
 
 // X <- 1/2 (X + sign X^T) in place (n x n); one thread per unordered pair.
-__global__ void k_symmetrize(double* __restrict__ X, int n, double sign) {
+__global__ void k_symmetrize(double* __restrict__ X, int n, double sign, long long ms_) {
+  X = mshift(X, ms_);
   long long total = (long long)n * (n + 1) / 2;
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
     // t -> (i, j) with i <= j
@@ -206,7 +222,8 @@ __global__ void k_symmetrize(double* __restrict__ X, int n, double sign) {
 // slice of Q[i] . w (i < nq), part[b][nq] = w . w.  Fixed grid, deterministic.
 constexpr int MD_BLOCKS = 128, MD_THREADS = 256, MD_MAXQ = 64;
 __global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restrict__ Q, const double* __restrict__ w,
-                                                         int nq, size_t n, double* __restrict__ part) {
+                                                         int nq, size_t n, double* __restrict__ part, long long ms_) {
+  Q = mshift(Q, ms_); w = mshift(w, ms_); part = mshift(part, ms_);
   __shared__ double red[MD_THREADS / 64][MD_MAXQ + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   size_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -240,7 +257,8 @@ __global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restric
 }
 // one block per output: fixed-shape tree over the per-block partials
 __global__ __launch_bounds__(MD_BLOCKS) void k_multidot_sum(const double* __restrict__ part, int nq, int nblocks,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out, long long ms_) {
+  part = mshift(part, ms_); out = mshift(out, ms_);
   __shared__ double sh[MD_BLOCKS];
   const int i = blockIdx.x;
   sh[threadIdx.x] = threadIdx.x < nblocks ? part[(size_t)threadIdx.x * (MD_MAXQ + 1) + i] : 0.0;
@@ -253,7 +271,8 @@ __global__ __launch_bounds__(MD_BLOCKS) void k_multidot_sum(const double* __rest
 }
 // w -= sum_{i < nq} c[i] Q[i]
 __global__ void k_sub_combination(double* __restrict__ w, const double* __restrict__ Q, const double* __restrict__ c,
-                                  int nq, size_t n) {
+                                  int nq, size_t n, long long ms_) {
+  w = mshift(w, ms_); Q = mshift(Q, ms_); c = mshift(c, ms_);
   __shared__ double cs[MD_MAXQ];
   for (int i = threadIdx.x; i < nq; i += blockDim.x) cs[i] = c[i];
   __syncthreads();
@@ -264,11 +283,13 @@ __global__ void k_sub_combination(double* __restrict__ w, const double* __restri
   }
 }
 // alpha[j] = c1[j] + c2[j]; hss = ||H q_j||^2 before orthogonalisation
-__global__ void k_alpha(const double* __restrict__ c1, const double* __restrict__ c2, int j, double* __restrict__ alpha) {
+__global__ void k_alpha(const double* __restrict__ c1, const double* __restrict__ c2, int j, double* __restrict__ alpha, long long ms_) {
+  c1 = mshift(c1, ms_); c2 = mshift(c2, ms_); alpha = mshift(alpha, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) alpha[j] = c1[j] + c2[j];
 }
 
-__global__ void k_zero_int(int* x, int n) {
+__global__ void k_zero_int(int* x, int n, long long ms_) {
+  x = mshift(x, ms_);
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
 }
 
@@ -276,81 +297,81 @@ __global__ void k_zero_int(int* x, int n) {
 
 hipError_t lz_three_term(double* w, const double* qj, const double* qjm1, const double* alpha, const double* beta, int j,
                          size_t n, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_three_term, dim3(grid_for(n)), dim3(256), 0, s, w, qj, qjm1, alpha, beta, j, n, stop);
+  hipLaunchKernelGGL(k_three_term, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, qj, qjm1, alpha, beta, j, n, stop, grp().stride);
   return hipGetLastError();
 }
 hipError_t lz_set_beta(const double* ss, const double* hss, double* beta, int j, double tol, int* stop, int* m_eff,
                        hipStream_t s) {
-  hipLaunchKernelGGL(k_set_beta, dim3(1), dim3(64), 0, s, ss, hss, beta, j, tol, stop, m_eff);
+  hipLaunchKernelGGL(k_set_beta, dim3(1, grp().count), dim3(64), 0, s, ss, hss, beta, j, tol, stop, m_eff, grp().stride);
   return hipGetLastError();
 }
 hipError_t lz_next_q(const double* w, double* qn, const double* beta, int j, size_t n, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_next_q, dim3(grid_for(n)), dim3(256), 0, s, w, qn, beta, j, n, stop);
+  hipLaunchKernelGGL(k_next_q, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, qn, beta, j, n, stop, grp().stride);
   return hipGetLastError();
 }
 hipError_t lz_build_T(const double* alpha, const double* beta, int m, const int* stop, const int* m_eff, double* T,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_build_T, dim3(1), dim3(256), 0, s, alpha, beta, m, stop, m_eff, T);
+  hipLaunchKernelGGL(k_build_T, dim3(1, grp().count), dim3(256), 0, s, alpha, beta, m, stop, m_eff, T, grp().stride);
   return hipGetLastError();
 }
 hipError_t lz_select_lowest(const double* T, const double* V, int m, double* y, double* theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_lowest, dim3(1), dim3(64), 0, s, T, V, m, y, theta);
+  hipLaunchKernelGGL(k_select_lowest, dim3(1, grp().count), dim3(64), 0, s, T, V, m, y, theta, grp().stride);
   return hipGetLastError();
 }
 hipError_t scale_rsqrt(double* x, const double* ss, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n)), dim3(256), 0, s, x, ss, n);
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, ss, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t residual_vec(const double* Hv, const double* v, const double* lam, double* r, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n)), dim3(256), 0, s, Hv, v, lam, r, n);
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n), grp().count), dim3(256), 0, s, Hv, v, lam, r, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t sign_fix(double* v, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_sign_fix, dim3(1), dim3(256), 0, s, v, n);
+  hipLaunchKernelGGL(k_sign_fix, dim3(1, grp().count), dim3(256), 0, s, v, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t axpy_dev(double* y, const double* x, const double* scale, double factor, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(n)), dim3(256), 0, s, y, x, scale, factor, n);
+  hipLaunchKernelGGL(k_axpy_dev, dim3(grid_for(n), grp().count), dim3(256), 0, s, y, x, scale, factor, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t sqrt_inplace(double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_sqrt_inplace, dim3(1), dim3(64), 0, s, x);
+  hipLaunchKernelGGL(k_sqrt_inplace, dim3(1, grp().count), dim3(64), 0, s, x, grp().stride);
   return hipGetLastError();
 }
-hipError_t energy_store(const double* lam, double c, double L, double ly, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3(1), dim3(64), 0, s, lam, c, L, ly, out);
+hipError_t energy_store(const double* lam, const double* c, double L, double ly, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1, grp().count), dim3(64), 0, s, lam, c, L, ly, out, grp().stride);
   return hipGetLastError();
 }
 hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, hipStream_t s) {
-  hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, s, nrm, m, out, run_min);
+  hipLaunchKernelGGL(k_ratio, dim3(1, grp().count), dim3(64), 0, s, nrm, m, out, run_min, grp().stride);
   return hipGetLastError();
 }
 hipError_t running_max(const double* x, double* run_max, hipStream_t s) {
-  hipLaunchKernelGGL(k_running_max, dim3(1), dim3(64), 0, s, x, run_max);
+  hipLaunchKernelGGL(k_running_max, dim3(1, grp().count), dim3(64), 0, s, x, run_max, grp().stride);
   return hipGetLastError();
 }
 hipError_t identity_f64(double* X, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_identity, dim3(grid_for((size_t)n * n)), dim3(256), 0, s, X, n);
+  hipLaunchKernelGGL(k_identity, dim3(grid_for((size_t)n * n), grp().count), dim3(256), 0, s, X, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s) {
-  hipLaunchKernelGGL(k_symmetrize, dim3(grid_for((size_t)n * (n + 1) / 2)), dim3(256), 0, s, X, n, sign);
+  hipLaunchKernelGGL(k_symmetrize, dim3(grid_for((size_t)n * (n + 1) / 2), grp().count), dim3(256), 0, s, X, n, sign, grp().stride);
   return hipGetLastError();
 }
 hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s) {
   if (nq > MD_MAXQ) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS), dim3(MD_THREADS), 0, s, Q, w, nq, n, part);
-  hipLaunchKernelGGL(k_multidot_sum, dim3(nq + 1), dim3(MD_BLOCKS), 0, s, part, nq, MD_BLOCKS, coef);
-  hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n)), dim3(256), 0, s, w, Q, coef, nq, n);
+  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS, grp().count), dim3(MD_THREADS), 0, s, Q, w, nq, n, part, grp().stride);
+  hipLaunchKernelGGL(k_multidot_sum, dim3(nq + 1, grp().count), dim3(MD_BLOCKS), 0, s, part, nq, MD_BLOCKS, coef, grp().stride);
+  hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, Q, coef, nq, n, grp().stride);
   return hipGetLastError();
 }
 size_t lz_reorth_part_doubles() { return (size_t)MD_BLOCKS * (MD_MAXQ + 1); }
 hipError_t lz_alpha(const double* c1, const double* c2, int j, double* alpha, hipStream_t s) {
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(64), 0, s, c1, c2, j, alpha);
+  hipLaunchKernelGGL(k_alpha, dim3(1, grp().count), dim3(64), 0, s, c1, c2, j, alpha, grp().stride);
   return hipGetLastError();
 }
 hipError_t zero_int(int* x, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, x, n);
+  hipLaunchKernelGGL(k_zero_int, dim3(1, grp().count), dim3(64), 0, s, x, n, grp().stride);
   return hipGetLastError();
 }
 

@@ -5,6 +5,11 @@
 
 namespace ttn {
 
+GroupCtx& grp() {
+  static thread_local GroupCtx g;
+  return g;
+}
+
 namespace {
 
 inline int grid_for(size_t n, int threads = 256, int cap = 8192) {
@@ -14,45 +19,55 @@ inline int grid_for(size_t n, int threads = 256, int cap = 8192) {
   return (int)b;
 }
 
-__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, size_t n) {
+__global__ void k_f64_to_f32(const double* __restrict__ x, float* __restrict__ y, size_t n, long long ms_) {
+  x = mshift(x, ms_); y = mshift(y, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
 }
-__global__ void k_f32_to_f64(const float* __restrict__ x, double* __restrict__ y, size_t n) {
+__global__ void k_f32_to_f64(const float* __restrict__ x, double* __restrict__ y, size_t n, long long ms_) {
+  x = mshift(x, ms_); y = mshift(y, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = (double)x[i];
 }
 template <typename T>
-__global__ void k_fill(T* __restrict__ x, T v, size_t n) {
+__global__ void k_fill(T* __restrict__ x, T v, size_t n, long long ms_) {
+  x = mshift(x, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     x[i] = v;
 }
-__global__ void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, size_t n) {
+__global__ void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, size_t n, long long ms_) {
+  src = mshift(src, ms_); dst = mshift(dst, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
-__global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n) {
+__global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n, long long ms_) {
+  src = mshift(src, ms_); dst = mshift(dst, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
 __global__ void k_copy8_if(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n, const int* flag,
-                           int want) {
+                           int want, long long ms_) {
+  src = mshift(src, ms_); dst = mshift(dst, ms_); flag = mshift(flag, ms_);
   if (*flag != want) return;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
 }
-__global__ void k_set_flag_le(int* flag, const int* info, int limit) {
+__global__ void k_set_flag_le(int* flag, const int* info, int limit, long long ms_) {
+  flag = mshift(flag, ms_); info = mshift(info, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = info[0] <= limit ? 1 : 0;
 }
-__global__ void k_note_negative_info(const int* info, int nq, double* err) {
+__global__ void k_note_negative_info(const int* info, int nq, double* err, long long ms_) {
+  info = mshift(info, ms_); err = mshift(err, ms_);
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int q = 0; q < nq; ++q)
     if (info[2 * q] < 0) err[0] = 1.0;
 }
-__global__ void k_add_diag(double* X, int n, double v) {
+__global__ void k_add_diag(double* X, int n, double v, long long ms_) {
+  X = mshift(X, ms_);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) X[(size_t)i * n + i] += v;
 }
 template <typename T>
-__global__ void k_axpby(const T* __restrict__ x, T* __restrict__ y, T alpha, T beta, size_t n) {
+__global__ void k_axpby(const T* __restrict__ x, T* __restrict__ y, T alpha, T beta, size_t n, long long ms_) {
+  x = mshift(x, ms_); y = mshift(y, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     y[i] = alpha * x[i] + (beta == T(0) ? T(0) : beta * y[i]);
 }
@@ -64,7 +79,8 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
   return z ^ (z >> 31);
 }
-__global__ void k_gaussian(double* __restrict__ x, size_t n, uint64_t seed, uint64_t stream_id) {
+__global__ void k_gaussian(double* __restrict__ x, size_t n, uint64_t seed, uint64_t stream_id, long long ms_) {
+  x = mshift(x, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     uint64_t base = splitmix64(seed ^ splitmix64(stream_id + 0x632be59bd9b4e019ull));
     uint64_t r1 = splitmix64(base + 2 * (uint64_t)i);
@@ -97,7 +113,8 @@ __device__ double block_sum(double v, double* sh) {
 
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_pair_partial(const T* __restrict__ X, const T* __restrict__ Y,
-                                                              long long n, double* __restrict__ part) {
+                                                              long long n, double* __restrict__ part, long long ms_) {
+  X = mshift(X, ms_); Y = mshift(Y, ms_); part = mshift(part, ms_);
   __shared__ double sh[RED_THREADS];
   double acc = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -106,7 +123,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_pair_partial(const T* __restric
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 __global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __restrict__ part, int np,
-                                                              double* __restrict__ out) {
+                                                              double* __restrict__ out, long long ms_) {
+  part = mshift(part, ms_); out = mshift(out, ms_);
   __shared__ double sh[RED_THREADS];
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += blockDim.x) acc += part[i];
@@ -114,7 +132,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __re
   if (threadIdx.x == 0) out[0] = s;
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_ortho_err(const double* __restrict__ G, int n, double* out) {
+__global__ __launch_bounds__(RED_THREADS) void k_ortho_err(const double* __restrict__ G, int n, double* out, long long ms_) {
+  G = mshift(G, ms_); out = mshift(out, ms_);
   __shared__ double sh[RED_THREADS];
   double acc = 0.0;
   long long nn = (long long)n * n;
@@ -128,7 +147,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_ortho_err(const double* __restr
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_row_normalize(const double* __restrict__ Y, double* __restrict__ Z,
-                                                               double* __restrict__ nrm, long long k) {
+                                                               double* __restrict__ nrm, long long k, long long ms_) {
+  Y = mshift(Y, ms_); Z = mshift(Z, ms_); nrm = mshift(nrm, ms_);
   __shared__ double sh[RED_THREADS];
   const double* y = Y + (long long)blockIdx.x * k;
   double* z = Z + (long long)blockIdx.x * k;
@@ -172,7 +192,8 @@ constexpr int JAC_MAXN = 1024;
 // both in dynamic LDS (copied back at the end).
 template <int MODE>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ Vg, int n,
-                                                        int max_sweeps, double tol, int* info, const int* skip) {
+                                                        int max_sweeps, double tol, int* info, const int* skip, long long ms_) {
+  Gg = mshift(Gg, ms_); Vg = mshift(Vg, ms_); info = mshift(info, ms_); skip = mshift(skip, ms_);
   if (skip && *skip) {
     if (threadIdx.x == 0 && info) { info[0] = 0; info[1] = 0; }
     return;
@@ -274,31 +295,31 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg,
 
 hipError_t convert_f64_to_f32(const double* x, float* y, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, y, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t convert_f32_to_f64(const float* x, double* y, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n)), dim3(256), 0, s, x, y, n);
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, y, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t fill_f64(double* x, double v, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, v, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t fill_f32(float* x, float v, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+  hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, v, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return hipSuccess;
   if ((bytes % 8 == 0) && ((uintptr_t)dst % 8 == 0) && ((uintptr_t)src % 8 == 0)) {
     size_t n = bytes / 8;
-    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n)), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n);
+    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n), grp().count), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, grp().stride);
   } else {
-    hipLaunchKernelGGL(k_copy, dim3(grid_for(bytes)), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(bytes), grp().count), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes, grp().stride);
   }
   return hipGetLastError();
 }
@@ -306,54 +327,54 @@ hipError_t copy_bytes_if(void* dst, const void* src, size_t bytes, const int* fl
   if (!bytes) return hipSuccess;
   if ((bytes % 8) || ((uintptr_t)dst % 8) || ((uintptr_t)src % 8)) return hipErrorInvalidValue;
   const size_t n = bytes / 8;
-  hipLaunchKernelGGL(k_copy8_if, dim3(grid_for(n)), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, flag,
-                     want);
+  hipLaunchKernelGGL(k_copy8_if, dim3(grid_for(n), grp().count), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, flag,
+                     want, grp().stride);
   return hipGetLastError();
 }
 hipError_t set_flag_le(int* flag, const int* info, int limit, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_flag_le, dim3(1), dim3(64), 0, s, flag, info, limit);
+  hipLaunchKernelGGL(k_set_flag_le, dim3(1, grp().count), dim3(64), 0, s, flag, info, limit, grp().stride);
   return hipGetLastError();
 }
 hipError_t note_negative_info(const int* info, int nq, double* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_note_negative_info, dim3(1), dim3(64), 0, s, info, nq, err);
+  hipLaunchKernelGGL(k_note_negative_info, dim3(1, grp().count), dim3(64), 0, s, info, nq, err, grp().stride);
   return hipGetLastError();
 }
 hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_diag, dim3(grid_for(n)), dim3(256), 0, s, X, n, v);
+  hipLaunchKernelGGL(k_add_diag, dim3(grid_for(n), grp().count), dim3(256), 0, s, X, n, v, grp().stride);
   return hipGetLastError();
 }
 hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_axpby<double>, dim3(grid_for(n)), dim3(256), 0, s, x, y, alpha, beta, n);
+  hipLaunchKernelGGL(k_axpby<double>, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, y, alpha, beta, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t axpby_f32(const float* x, float* y, float alpha, float beta, size_t n, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_axpby<float>, dim3(grid_for(n)), dim3(256), 0, s, x, y, alpha, beta, n);
+  hipLaunchKernelGGL(k_axpby<float>, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, y, alpha, beta, n, grp().stride);
   return hipGetLastError();
 }
 hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned long long stream_id, hipStream_t s) {
   if (!n) return hipSuccess;
-  hipLaunchKernelGGL(k_gaussian, dim3(grid_for(n)), dim3(256), 0, s, x, n, (uint64_t)seed, (uint64_t)stream_id);
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, n, (uint64_t)seed, (uint64_t)stream_id, grp().stride);
   return hipGetLastError();
 }
 hipError_t pair_f64(const double* X, const double* Y, long long n, double* out, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_partial<double>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, Y, n, part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out);
+  hipLaunchKernelGGL(k_pair_partial<double>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride);
   return hipGetLastError();
 }
 hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_partial<float>, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, X, Y, n, part);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out);
+  hipLaunchKernelGGL(k_pair_partial<float>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride);
   return hipGetLastError();
 }
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_ortho_err, dim3(1), dim3(RED_THREADS), 0, s, G, n, out);
+  hipLaunchKernelGGL(k_ortho_err, dim3(1, grp().count), dim3(RED_THREADS), 0, s, G, n, out, grp().stride);
   return hipGetLastError();
 }
 hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, long long k, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_row_normalize, dim3(m), dim3(RED_THREADS), 0, s, Y, Z, nrm, k);
+  hipLaunchKernelGGL(k_row_normalize, dim3(m, grp().count), dim3(RED_THREADS), 0, s, Y, Z, nrm, k, grp().stride);
   return hipGetLastError();
 }
 hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double tol, int* info, void* scratch,
@@ -381,11 +402,11 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
   }
   size_t bytes = (size_t)n * n * sizeof(double);
   if (lds_limit > 0 && 2 * bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<2>, dim3(1), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info, skip);
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1, grp().count), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
   } else if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<1>, dim3(1), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info, skip);
+    hipLaunchKernelGGL(k_jacobi<1>, dim3(1, grp().count), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
   } else {
-    hipLaunchKernelGGL(k_jacobi<0>, dim3(1), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info, skip);
+    hipLaunchKernelGGL(k_jacobi<0>, dim3(1, grp().count), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
   }
   return hipGetLastError();
 }

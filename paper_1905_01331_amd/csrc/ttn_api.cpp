@@ -94,6 +94,7 @@ struct Arena {
 constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO_MAX = 4, SCAL_RATIO = 5,
               SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10,
               SCAL_ERR = 11,  // 1.0 once a Jacobi solve reported an abort
+              SCAL_SHIFT = 12,  // the shift c (per member, read by the energy kernel)
               SCAL_N = 16;
 // Gram refreshes of the polar update: two always, a third when the second
 // Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
@@ -205,6 +206,14 @@ struct Ctx {
   std::vector<hipStream_t> pool;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  // launch groups: members of identical configuration (all but the
+  // Hamiltonian's values) laid out side by side at a uniform stride run
+  // every kernel of a stage as one launch; members[0] is the lowest address
+  struct Group {
+    std::vector<int> members;
+    long long stride = 0;
+  };
+  std::vector<Group> groups;
   hipStream_t grid_s = nullptr;          // serialises the persistent Jacobi solves of a batch
   hipStream_t cap_s = nullptr;           // stream the sweep graph is captured on
   std::vector<hipEvent_t> member_events;  // two per member, for grid_s
@@ -405,13 +414,17 @@ void layout_member(Member& M, Arena& ar) {
 hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls = OC_POLAR_GEMM) {
   size_t slot = 0;
   bool timed = false;
+  GemmDesc gg = g;
+  gg.mcount = grp().count;
+  gg.mstride = grp().stride;
   if (M.prof && M.prof->on) {
     double es = (p == P_F64) ? 8.0 : 4.0;
-    double f = 2.0 * g.M * (double)g.N * g.K * g.batch;
-    double b = es * g.batch * ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
+    double f = 2.0 * g.M * (double)g.N * g.K * g.batch * gg.mcount;
+    double b = es * g.batch * gg.mcount *
+               ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
     timed = M.prof->begin(cls, f, b, s, &slot);
   }
-  hipError_t e = gemm(p, g, M.splitk, M.splitk_bytes, s);
+  hipError_t e = gemm(p, gg, M.splitk, M.splitk_bytes, s);
   if (timed) M.prof->end(slot, s);
   return e;
 }
@@ -970,17 +983,28 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     HIPCHK(residual_vec(M.lzHv, M.vtop, M.scal + SCAL_LAM, M.lzR, xx, s));
     HIPCHK(pair_f64(M.lzR, M.lzR, (long long)xx, M.scal + SCAL_RES, M.part, s));
     HIPCHK(sqrt_inplace(M.scal + SCAL_RES, s));
-    double hs[SCAL_ERR + 1];
-    HIPCHK(hipMemcpyAsync(hs, M.scal, sizeof hs, hipMemcpyDeviceToHost, s));
+    // every member of the launch group (they share the restarts)
+    const int gc = grp().count;
+    std::vector<double> hs((size_t)gc * (SCAL_ERR + 1));
+    if (gc > 1)
+      HIPCHK(hipMemcpy2DAsync(hs.data(), (SCAL_ERR + 1) * sizeof(double), M.scal, (size_t)grp().stride,
+                              (SCAL_ERR + 1) * sizeof(double), gc, hipMemcpyDeviceToHost, s));
+    else
+      HIPCHK(hipMemcpyAsync(hs.data(), M.scal, (SCAL_ERR + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (hs[SCAL_ERR] != 0.0) return fail(TTN_EHIP, "a Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
-    if (hs[SCAL_RES] <= M.ltol * std::max(1.0, std::fabs(hs[SCAL_LAM]))) {
+    bool all_conv = true;
+    for (int q = 0; q < gc; ++q) {
+      const double* h = hs.data() + (size_t)q * (SCAL_ERR + 1);
+      if (h[SCAL_ERR] != 0.0) return fail(TTN_EHIP, "a Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
+      if (!(h[SCAL_RES] <= M.ltol * std::max(1.0, std::fabs(h[SCAL_LAM])))) all_conv = false;
+    }
+    if (all_conv) {
       *converged = true;
       break;
     }
   }
   HIPCHK(sign_fix(M.vtop, xx, s));
-  HIPCHK(energy_store(M.scal + SCAL_LAM, M.c, (double)M.L, (double)M.ly, M.scal + SCAL_LAM, s));
+  HIPCHK(energy_store(M.scal + SCAL_LAM, M.scal + SCAL_SHIFT, (double)M.L, (double)M.ly, M.scal + SCAL_LAM, s));
   if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, xx, s));
   M.lz_iters = iters;
   M.rho_from = M.pc_from = 1 << 20;
@@ -1032,6 +1056,7 @@ ttn_status init_member(Member& M, hipStream_t s, bool* conv) {
   // scalars
   double init_scal[SCAL_N] = {0};
   init_scal[SCAL_RATIO_MIN] = 1.0;
+  init_scal[SCAL_SHIFT] = M.c;
   HIPCHK(hipMemcpyAsync(M.scal, init_scal, sizeof init_scal, hipMemcpyHostToDevice, s));
   // top start vector
   const int x = M.dims[n - 1];
@@ -1081,6 +1106,91 @@ void layer_flops(const Member& M, double* bulk, double* f64) {
   *f64 = G;
 }
 
+// Everything of a member's configuration that decides its layout and the
+// host-side parameters of its launches (the Hamiltonian's values live on the
+// device and may differ inside a group).
+std::vector<double> group_key(const Member& M) {
+  std::vector<double> k = {(double)M.L, (double)M.d, (double)M.D, (double)M.chi, (double)M.prec, (double)M.ly,
+                           (double)M.krylov, (double)M.restarts, M.ltol, (double)M.gauge_fix};
+  for (int a : M.anti) k.push_back((double)a);
+  return k;
+}
+
+// Host-side stage state of the leader, copied to the other members of its
+// group after every group-wide call (they took the same path).
+void sync_group_state(Ctx& c, const Ctx::Group& G) {
+  const Member& L = c.m[G.members[0]];
+  for (size_t i = 1; i < G.members.size(); ++i) {
+    Member& M = c.m[G.members[i]];
+    M.rho_from = L.rho_from; M.pc_from = L.pc_from; M.dressed_tau = L.dressed_tau; M.env_tau = L.env_tau;
+    M.ops_upto = L.ops_upto; M.rb_cur = L.rb_cur; M.lz_iters = L.lz_iters; M.qw_valid = L.qw_valid;
+  }
+}
+
+// f(leader, group) for every group, with the launch group set.
+template <class F>
+ttn_status for_groups(Ctx& c, F f) {
+  for (auto& G : c.groups) {
+    GroupScope gs((int)G.members.size(), G.stride);
+    ttn_status st = f(c.m[G.members[0]], G);
+    if (st) return st;
+    sync_group_state(c, G);
+  }
+  return TTN_OK;
+}
+
+// The layer part of one sweep for one member on stream s.
+ttn_status sweep_layers(Member& M, hipStream_t s) {
+  ttn_status st;
+  if ((st = stage_descend_rho(M, s))) return st;
+  for (int t = 1; t < M.n; ++t) {
+    if ((st = stage_descend_dressed(M, t, s))) return st;
+    if ((st = stage_env(M, t, s))) return st;
+    if ((st = stage_update_layer(M, t, s))) return st;
+    if ((st = stage_ascend(M, t, s))) return st;
+    M.ops_upto = std::max(M.ops_upto, t);
+  }
+  return TTN_OK;
+}
+
+// The layer part for the whole batch: one member runs on the caller's
+// stream; a batch forks to the pool streams (member i on stream i mod P) and
+// joins back.  No host synchronisation inside: capturable.
+ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
+  if (c.groups.size() == 1) {
+    const Ctx::Group& G = c.groups[0];
+    GroupScope gs((int)G.members.size(), G.stride);
+    ttn_status st = sweep_layers(c.m[G.members[0]], s);
+    if (!st) sync_group_state(c, G);
+    return st;
+  }
+  if (c.pool.empty()) {
+    const int P = (int)std::min<size_t>(POOL_STREAMS, c.groups.size());
+    c.pool.resize(P, nullptr);
+    c.join.resize(P, nullptr);
+    for (int i = 0; i < P; ++i) {
+      HIPCHK(hipStreamCreateWithFlags(&c.pool[i], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+  }
+  const int P = (int)c.pool.size();
+  HIPCHK(hipEventRecord(c.fork, s));
+  for (int i = 0; i < P; ++i) HIPCHK(hipStreamWaitEvent(c.pool[i], c.fork, 0));
+  for (size_t gi = 0; gi < c.groups.size(); ++gi) {
+    const Ctx::Group& G = c.groups[gi];
+    GroupScope gs((int)G.members.size(), G.stride);
+    ttn_status st = sweep_layers(c.m[G.members[0]], c.pool[gi % P]);
+    if (st) return st;
+    sync_group_state(c, G);
+  }
+  for (int i = 0; i < P; ++i) {
+    HIPCHK(hipEventRecord(c.join[i], c.pool[i]));
+    HIPCHK(hipStreamWaitEvent(s, c.join[i], 0));
+  }
+  return TTN_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1121,10 +1231,43 @@ ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t b
   ar.base = (char*)workspace;
   bool any_noconv = false;
   for (int i = 0; i < batch; ++i) {
-    Member& M = h->c.m[i];
-    setup_member(cfgs[i], M);
-    layout_member(M, ar);
-    M.prof = &h->c.prof;
+    setup_member(cfgs[i], h->c.m[i]);
+    h->c.m[i].prof = &h->c.prof;
+  }
+  // members of equal configuration are laid out next to each other, so that
+  // they sit at a uniform stride and form one launch group; a group's bond
+  // dimensions stay <= 128 (the larger polar solves need the whole GPU)
+  {
+    Ctx& c = h->c;
+    std::vector<int> order(batch);
+    for (int i = 0; i < batch; ++i) order[i] = i;
+    std::vector<std::vector<double>> keys(batch);
+    for (int i = 0; i < batch; ++i) keys[i] = group_key(c.m[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return keys[x] < keys[y]; });
+    for (int i : order) layout_member(c.m[i], ar);
+    for (size_t k = 0; k < order.size();) {
+      Ctx::Group G;
+      G.members.push_back(order[k]);
+      size_t j = k + 1;
+      const Member& M0 = c.m[order[k]];
+      int cmax = 0;
+      for (int t = 0; t < M0.n; ++t) cmax = std::max(cmax, M0.dims[t]);
+      if (cmax <= 128) {
+        for (; j < order.size() && keys[order[j]] == keys[order[k]]; ++j) {
+          const Member& A = c.m[order[j - 1]];
+          const Member& B2 = c.m[order[j]];
+          const long long st = (long long)((char*)B2.scal - (char*)A.scal);
+          // the whole layout moves by one stride (same sizes, same alignment)
+          if (st <= 0 || (char*)B2.w64[1] - (char*)A.w64[1] != st || (char*)B2.jinfo - (char*)A.jinfo != st ||
+              (G.members.size() > 1 && st != G.stride))
+            break;
+          G.stride = st;
+          G.members.push_back(order[j]);
+        }
+      }
+      c.groups.push_back(G);
+      k = j;
+    }
   }
   if (batch > 1) {
     Ctx& c = h->c;
@@ -1171,25 +1314,22 @@ ttn_status ttn_ascend(ttn_handle h, int tau_from, int tau_to) {
       return fail(TTN_EINVAL, "ascend range [%d, %d] outside [1, %d]", tau_from, tau_to, M.n - 1);
     if (M.ops_upto < tau_from - 1) return fail(TTN_ESTATE, "level %d operators are stale; ascend from a lower layer", tau_from - 1);
   }
-  for (auto& M : h->c.m) {
+  ttn_status st0 = for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status {
     for (int t = tau_from; t <= tau_to; ++t) {
       ttn_status st = stage_ascend(M, t, h->c.s);
       if (st) return st;
     }
     M.ops_upto = std::max(M.ops_upto, tau_to);
-  }
+    return TTN_OK;
+  });
+  if (st0) return st0;
   return TTN_OK;
 }
 
 ttn_status ttn_descend(ttn_handle h, int what, int tau) {
   if (!h) return fail(TTN_EINVAL, "null handle");
-  if (what == TTN_DESCEND_RHO) {
-    for (auto& M : h->c.m) {
-      ttn_status st = stage_descend_rho(M, h->c.s);
-      if (st) return st;
-    }
-    return TTN_OK;
-  }
+  if (what == TTN_DESCEND_RHO)
+    return for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status { return stage_descend_rho(M, h->c.s); });
   if (what != TTN_DESCEND_DRESSED) return fail(TTN_EINVAL, "unknown descend kind %d", what);
   for (auto& M : h->c.m) {
     if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
@@ -1197,11 +1337,7 @@ ttn_status ttn_descend(ttn_handle h, int what, int tau) {
       return fail(TTN_ESTATE, "descend(DRESSED, %d) needs descend(RHO) after the last change of v or of a layer above %d", tau, tau);
     if (M.ops_upto < tau - 1) return fail(TTN_ESTATE, "level %d operators are stale", tau - 1);
   }
-  for (auto& M : h->c.m) {
-    ttn_status st = stage_descend_dressed(M, tau, h->c.s);
-    if (st) return st;
-  }
-  return TTN_OK;
+  return for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status { return stage_descend_dressed(M, tau, h->c.s); });
 }
 
 ttn_status ttn_env(ttn_handle h, int tau) {
@@ -1210,11 +1346,7 @@ ttn_status ttn_env(ttn_handle h, int tau) {
     if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
     if (M.dressed_tau != tau) return fail(TTN_ESTATE, "env(%d) needs descend(DRESSED, %d) first", tau, tau);
   }
-  for (auto& M : h->c.m) {
-    ttn_status st = stage_env(M, tau, h->c.s);
-    if (st) return st;
-  }
-  return TTN_OK;
+  return for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status { return stage_env(M, tau, h->c.s); });
 }
 
 ttn_status ttn_update(ttn_handle h, int tau) {
@@ -1223,23 +1355,20 @@ ttn_status ttn_update(ttn_handle h, int tau) {
     for (auto& M : h->c.m)
       if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "top update needs every layer ascended (ops up to %d of %d)", M.ops_upto, M.n - 1);
     bool all = true;
-    for (auto& M : h->c.m) {
+    ttn_status st = for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status {
       bool conv = false;
-      ttn_status st = stage_update_top(M, h->c.s, &conv);
-      if (st) return st;
+      ttn_status r = stage_update_top(M, h->c.s, &conv);
       all &= conv;
-    }
+      return r;
+    });
+    if (st) return st;
     return all ? TTN_OK : TTN_WNOCONV;
   }
   for (auto& M : h->c.m) {
     if (tau < 1 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [1, %d]", tau, M.n - 1);
     if (M.env_tau != tau) return fail(TTN_ESTATE, "update(%d) needs env(%d) first", tau, tau);
   }
-  for (auto& M : h->c.m) {
-    ttn_status st = stage_update_layer(M, tau, h->c.s);
-    if (st) return st;
-  }
-  return TTN_OK;
+  return for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status { return stage_update_layer(M, tau, h->c.s); });
 }
 
 ttn_status ttn_energy(ttn_handle h, double* e) {
@@ -1254,49 +1383,6 @@ ttn_status ttn_energy(ttn_handle h, double* e) {
     if (!(sc[SCAL_ORTHO_MAX] <= 1e-10)) bad = true;
   }
   if (bad) return fail(TTN_EORTHO, "an updated isometry failed the orthonormality check");
-  return TTN_OK;
-}
-
-// The layer part of one sweep for one member on stream s.
-ttn_status sweep_layers(Member& M, hipStream_t s) {
-  ttn_status st;
-  if ((st = stage_descend_rho(M, s))) return st;
-  for (int t = 1; t < M.n; ++t) {
-    if ((st = stage_descend_dressed(M, t, s))) return st;
-    if ((st = stage_env(M, t, s))) return st;
-    if ((st = stage_update_layer(M, t, s))) return st;
-    if ((st = stage_ascend(M, t, s))) return st;
-    M.ops_upto = std::max(M.ops_upto, t);
-  }
-  return TTN_OK;
-}
-
-// The layer part for the whole batch: one member runs on the caller's
-// stream; a batch forks to the pool streams (member i on stream i mod P) and
-// joins back.  No host synchronisation inside: capturable.
-ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
-  if (c.m.size() == 1) return sweep_layers(c.m[0], s);
-  if (c.pool.empty()) {
-    const int P = (int)std::min<size_t>(POOL_STREAMS, c.m.size());
-    c.pool.resize(P, nullptr);
-    c.join.resize(P, nullptr);
-    for (int i = 0; i < P; ++i) {
-      HIPCHK(hipStreamCreateWithFlags(&c.pool[i], hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
-    }
-    HIPCHK(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
-  }
-  const int P = (int)c.pool.size();
-  HIPCHK(hipEventRecord(c.fork, s));
-  for (int i = 0; i < P; ++i) HIPCHK(hipStreamWaitEvent(c.pool[i], c.fork, 0));
-  for (size_t i = 0; i < c.m.size(); ++i) {
-    ttn_status st = sweep_layers(c.m[i], c.pool[i % P]);
-    if (st) return st;
-  }
-  for (int i = 0; i < P; ++i) {
-    HIPCHK(hipEventRecord(c.join[i], c.pool[i]));
-    HIPCHK(hipStreamWaitEvent(s, c.join[i], 0));
-  }
   return TTN_OK;
 }
 
@@ -1331,11 +1417,13 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
     } else {
       if ((st = sweep_layers_all(c, c.s))) return st;
     }
-    for (auto& M : c.m) {
+    st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
       bool conv = false;
-      if ((st = stage_update_top(M, c.s, &conv))) return st;
-      if (!conv) warn = TTN_WNOCONV;
-    }
+      ttn_status r = stage_update_top(M, c.s, &conv);
+      if (!r && !conv) warn = TTN_WNOCONV;
+      return r;
+    });
+    if (st) return st;
   }
   return warn;
 }
