@@ -20,8 +20,10 @@ swept one at a time.  For each single chain, the line carries:
   * the energy of the float64 GPU path run from the same initial isometries
     for the same number of sweeps (a separate trajectory: it drifts apart
     from the mixed one through the rounding of the updates);
-  * a roofline entry for the dominant contraction class (its average launch
-    time measured with HIP events over a second pass of K sweeps).
+  * a roofline entry for the dominant product kernel instantiation (its
+    average launch time measured with HIP events around that kernel alone,
+    over a second pass of K eager sweeps), with the per-class and per-kernel
+    times of that pass.
 The CPU reference is timed on a bounded sample of the default workload.
 """
 import argparse
@@ -48,6 +50,71 @@ DEFAULT_CONFIG = "xxx4096"
 SECONDARY_CONFIG = "torus64x4"
 
 
+def kernel_peak(name):
+    """Published MI355X peak (TFLOP/s, in the kernel's own arithmetic) of a
+    product kernel: float32 MFMA, split-bf16 MFMA (three bf16 products per
+    float32 product, so a third of the bf16 peak in float32 flops), float64
+    MFMA; the general kernels run on the vector units."""
+    if name.startswith("gemm_mfma_kernel<1"):
+        return PEAK["fp32"]
+    if name.startswith("gemm_mfma_kernel<2"):
+        return PEAK["bf16"] / 3
+    if name.startswith("gemm_mfma64_kernel") or name.startswith("gemm_plain_kernel<double"):
+        return PEAK["fp64"]
+    return PEAK["fp32"]
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of the kernel from the committed PMC record
+    (FETCH_SIZE + WRITE_SIZE over the profiled pass, scaled by a plain copy),
+    or None when there is none for this kernel or its sources changed since."""
+    from paper_1905_01331_amd import rocprof_summary as R
+    path = os.path.join(ROOT, "profiles", "gemm_traffic_xxx4096.json")
+    if not os.path.exists(path):
+        return None, "no counter record"
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel") != kernel:
+        return None, f"counter record is for {rec.get('kernel')}"
+    if rec.get("sources_sha256") != R.sources_sha256():
+        return None, "kernel sources changed since the counters were taken"
+    return round(rec["traffic_bytes_per_launch"]), (
+        f"HBM bytes per launch (FETCH_SIZE x {rec['fetch_scale']:.3f} + WRITE_SIZE x {rec['write_scale']:.3f}, "
+        f"scales from a plain copy); algorithmic {rec['algorithmic_bytes_per_launch']:.4g}")
+
+
+def kernel_roofline(prof):
+    """Roofline entry of the product kernel instantiation with the largest
+    summed time: achieved = algorithmic flops (2 M N K per product) or bytes
+    (operands read once, result written once) per launch / average launch
+    duration (HIP events around that kernel alone).  The bound is the one its
+    arithmetic intensity puts it under: flops/byte above the ridge
+    (peak flops / 8 TB/s) is compute bound, below it memory bound."""
+    kern = {k: v for k, v in prof.items() if "kernel" in k and v["launches"]}
+    name, d = max(kern.items(), key=lambda kv: kv[1]["ms"])
+    n = d["launches"]
+    avg_s = d["ms"] / n / 1e3
+    flops, byts = d["flops"] / n, d["bytes"] / n
+    peak_f = kernel_peak(name)
+    ridge = peak_f * 1e12 / (PEAK["hbm_GBs"] * 1e9)
+    if flops > 0 and flops / byts >= ridge:
+        ach, peak, unit, bound = flops / avg_s / 1e12, peak_f, "TFLOP/s", "mfma"
+    else:
+        ach, peak, unit, bound = byts / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s", "hbm"
+    share = d["ms"] / sum(v["ms"] for v in kern.values())
+    traffic, note = measured_traffic(name)
+    return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+            "frac": round(ach / peak, 4), "traffic": traffic, "traffic_note": note,
+            "kernel": name, "launches": n, "avg_launch_us": round(avg_s * 1e6, 2),
+            "flops_per_launch": flops, "bytes_per_launch": byts,
+            "arith_intensity": round(flops / byts, 2), "ridge": round(ridge, 2),
+            "share_of_product_kernel_time": round(share, 3)}
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -61,6 +128,9 @@ def parse():
     p.add_argument("--no-secondary", action="store_true", help="skip the chi=128 workload of the default run")
     p.add_argument("--no-autotune", action="store_true", help="fixed launch heuristics instead of the autotuner")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
+    p.add_argument("--eager", action="store_true", help="no graph replay (every sweep launched eagerly)")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB elementwise copy (y = -x), the reference of the traffic counters")
     return p.parse_args()
 
 
@@ -111,7 +181,7 @@ def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
                        f"{gpu_sweep_flops / 1e12:.2f} TFLOP by the flop model")}
 
 
-def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
+def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True):
     """Times K sweeps of one workload after W warm-up sweeps; returns the
     measured fields (and the final energy) as a dict."""
     import torch
@@ -125,13 +195,15 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
     # layer part of a sweep into a HIP graph, replayed in the timed sweeps
     t.sweep(1)
     for _ in range(max(1, warmup) - 1):
-        t.sweep(1, graph=True)
+        t.sweep(1, graph=graph)
     torch.cuda.synchronize()
+    progress(f"{name}: warm-up done")
     t0 = time.perf_counter()
     for _ in range(steps):
-        t.sweep(1, graph=True)
+        t.sweep(1, graph=graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    progress(f"{name}: timed sweeps done ({1e3 * elapsed / steps:.2f} ms per sweep)")
     st = t.stats()
     sweeps_per_s = steps / elapsed
     tflops = st.flops_bulk / (elapsed / steps) / 1e12
@@ -142,22 +214,15 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
         t.sweep(1)
     prof = t.profile_read()
     t.profile(False)
+    progress(f"{name}: profiled pass done")
     e = float(t.energy()[0])  # after warmup + 2 K sweeps
     st = t.stats()
-    bulk_classes = {k: v for k, v in prof.items() if k in
-                    ("apply_r", "apply_l", "close", "left_mul", "close_l", "close_r")}
-    dom_name, dom = max(bulk_classes.items(), key=lambda kv: kv[1]["ms"])
-    avg_s = dom["ms"] / dom["launches"] / 1e3
-    ach = dom["flops"] / dom["launches"] / avg_s / 1e12
-    peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"] / 3}[prec]
-    roofline = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": None,
-                "kernel": dom_name, "launches": dom["launches"],
-                "avg_launch_us": round(avg_s * 1e6, 2),
-                "flops_per_launch": dom["flops"] / dom["launches"]}
+    roofline = kernel_roofline(prof)
     classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / steps, 3),
                    "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None}
-               for k, v in prof.items()}
+               for k, v in prof.items() if "kernel" not in k}
+    kernels = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / steps, 3)}
+               for k, v in prof.items() if "kernel" in k}
 
     # float64 re-evaluation of the same final state: the isometries and the
     # top tensor go into a float64 handle, whose initialisation ascends every
@@ -195,7 +260,7 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref):
         "name": name, "model": model, "L": L, "chi": chi, "prec": prec, "desc": desc,
         "sweeps_per_s": sweeps_per_s, "ms_per_step": 1e3 * elapsed / steps, "tflops": tflops,
         "stats": st, "energy": e, "e_re": e_re, "err_re": err_re, "e64": e64, "err": err,
-        "roofline": roofline, "classes": classes,
+        "roofline": roofline, "classes": classes, "kernels": kernels,
     }
 
 
@@ -226,6 +291,7 @@ def measure_batch(B, I, steps, warmup):
         t.sweep(1, graph=True)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    progress(f"batch of {len(draws)}: timed sweeps done ({1e3 * el / steps:.2f} ms per batched sweep)")
     e_b = t.energy()
     flops = sum(t.stats(i).flops_bulk for i in range(len(draws)))
     # float64 re-evaluation of every member's final state in one batch handle
@@ -243,6 +309,7 @@ def measure_batch(B, I, steps, warmup):
     r.close()
     del r, states
     torch.cuda.empty_cache()
+    progress("batch: float64 re-evaluation done")
     # one chain at a time, eager, same number of sweeps
     e_s = np.zeros(len(draws))
     el_s = 0.0
@@ -286,8 +353,19 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = 1 << 28
+        x = torch.ones(n, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"kernel": "neg_kernel", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                                               "launches": 3}}))
+        return
     B.autotune(0 if args.no_autotune else 1)
-    m = measure(B, I, args.config, args.precision, args.steps, args.warmup, args.seed, not args.no_fp64_ref)
+    m = measure(B, I, args.config, args.precision, args.steps, args.warmup, args.seed, not args.no_fp64_ref,
+                not args.eager)
     st = m["stats"]
     secondary = None
     if args.config == DEFAULT_CONFIG and not args.no_secondary:
@@ -339,6 +417,7 @@ def main():
         "lanczos_resid_last": st.lanczos_resid,
         "roofline": m["roofline"],
         "classes": m["classes"],
+        "kernels": m["kernels"],
         "autotune_entries": B.autotune(-1),
         "chi128": secondary,
         "batch128": batch,

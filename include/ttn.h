@@ -219,14 +219,22 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
 ttn_status ttn_autotune(int mode, int* entries);
 
 /* Event timing of the contraction classes (apply_r, apply_l, close,
- * left_mul, close_l, close_r, top_mm, polar_gemm, jacobi, lanczos_gemm).
+ * left_mul, close_l, close_r, top_mm, polar_gemm, jacobi, lanczos_gemm) and
+ * of the product kernels one by one.
  * ttn_profile(h, 1) clears the record and brackets every later launch of a
- * class with hipEventRecord on the handle's stream; ttn_profile(h, 0) stops.
- * ttn_profile_read synchronises the stream and returns one entry per class
- * with its launch count, summed elapsed milliseconds and algorithmic flops
- * (2 M N K per product) and bytes (operands read once, result written). */
+ * class with hipEventRecord on the stream it runs on; ttn_profile(h, 0)
+ * stops.  While it is on, every launch of a product kernel (by any handle of
+ * the process; the last handle to turn profiling on receives them) is also
+ * bracketed alone, without its split-K reduction, under the kernel's
+ * instantiation name (e.g. "gemm_mfma_kernel<2, true, false>", the name a
+ * kernel trace shows).  Graph sweeps are not timed (a profiled sweep runs
+ * eagerly).  ttn_profile_read synchronises and returns one entry per class
+ * and then per kernel, with its launch count, summed elapsed milliseconds and
+ * algorithmic flops (2 M N K per product) and bytes (operands read once,
+ * result written once, in the precision the kernel reads and writes).
+ * Classes come first, in the order above. */
 typedef struct ttn_profile_entry {
-  char name[24];
+  char name[48];
   int launches;
   double ms;
   double flops;

@@ -53,7 +53,7 @@ class TTNStats(ctypes.Structure):
 
 
 class TTNProfileEntry(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int), ("ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
@@ -249,9 +249,9 @@ class TTN:
         return _check(self.lib.ttn_profile(self.h, 1 if enable else 0))
 
     def profile_read(self):
-        arr = (TTNProfileEntry * 32)()
+        arr = (TTNProfileEntry * 64)()
         n = ctypes.c_int(0)
-        _check(self.lib.ttn_profile_read(self.h, arr, 32, ctypes.byref(n)))
+        _check(self.lib.ttn_profile_read(self.h, arr, 64, ctypes.byref(n)))
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
                                            bytes=arr[i].bytes) for i in range(n.value)}
 

@@ -68,6 +68,22 @@ __device__ __forceinline__ T* mshift(T* p, long long ms) {
   return p ? (T*)((uintptr_t)p + (long long)blockIdx.y * ms) : p;
 }
 
+// Optional per-kernel timing of the product kernels (set while a handle's
+// profiling is on): begin/end bracket one kernel launch with HIP events;
+// kernel ids name the instantiations (see kernel_name()).
+struct KernelTimer {
+  virtual bool begin(int kernel_id, double flops, double bytes, hipStream_t s, size_t* slot) = 0;
+  virtual void end(size_t slot, hipStream_t s) = 0;
+  virtual ~KernelTimer() {}
+};
+KernelTimer*& kernel_timer();
+enum { KID_MFMA = 0,     // + 4 * (mode - 1) + 2 * akc + bkc  (mode 1: float32, 2: split-bf16)
+       KID_MFMA64 = 8,   // + 2 * akc + bkc
+       KID_PLAIN = 12,   // + precision
+       KID_REDUCE = 15,  // split-K reductions: + 0 float, + 1 double
+       KID_N = 17 };
+const char* kernel_name(int kid);
+
 // Launches one product in the given arithmetic.  F64: double operands and
 // result.  F32 / BF16X3: float operands and result (BF16X3 splits every
 // float operand into bf16 hi + lo on load).  `scratch` (float/double,

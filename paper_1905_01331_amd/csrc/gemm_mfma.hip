@@ -497,16 +497,28 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
 template <bool AKC, bool BKC>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
   const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
+  size_t slot = 0;
+  KernelTimer* kt = kernel_timer();
+  const double work = (double)g.batch * gemm_members(g);
+  const bool timed = kt && kt->begin(KID_MFMA64 + 2 * AKC + BKC, 2.0 * g.M * (double)g.N * g.K * work,
+                                     8.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
   hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk, partial,
                      tm);
+  if (timed) kt->end(slot, s);
   return hipGetLastError();
 }
 
 template <int MODE, bool AKC, bool BKC>
 hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
   const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
+  size_t slot = 0;
+  KernelTimer* kt = kernel_timer();
+  const double work = (double)g.batch * gemm_members(g);
+  const bool timed = kt && kt->begin(KID_MFMA + 4 * (MODE - 1) + 2 * AKC + BKC, 2.0 * g.M * (double)g.N * g.K * work,
+                                     4.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
   hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
                      partial, tm);
+  if (timed) kt->end(slot, s);
   return hipGetLastError();
 }
 

@@ -219,6 +219,20 @@ __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict
 }
 
 template <typename T>
+static hipError_t splitk_reduce(const GemmDesc& g, int splits, const T* partial, hipStream_t s) {
+  const long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
+  int blocks = (int)((total + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  size_t slot = 0;
+  KernelTimer* kt = kernel_timer();
+  const bool timed =
+      kt && kt->begin(KID_REDUCE + (sizeof(T) == 8 ? 1 : 0), 0.0, sizeof(T) * (double)total * (splits + 1), s, &slot);
+  hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
+  if (timed) kt->end(slot, s);
+  return hipGetLastError();
+}
+
+template <typename T>
 static int choose_splits(const GemmDesc& g, size_t scratch_bytes) {
   long long tiles = (long long)((g.M + PT_M - 1) / PT_M) * ((g.N + PT_N - 1) / PT_N) * g.batch;
   if (tiles >= 512 || g.K < 8 * PT_K) return 1;
@@ -243,15 +257,16 @@ static hipError_t launch_plain(const GemmDesc& g, void* scratch, size_t scratch_
   splits = (g.K + kchunk - 1) / kchunk;
   if (splits < 1) splits = 1;
   dim3 grid((g.N + PT_N - 1) / PT_N, (g.M + PT_M - 1) / PT_M, g.batch * splits * gemm_members(g));
+  size_t slot = 0;
+  KernelTimer* kt = kernel_timer();
+  const double work = (double)g.batch * gemm_members(g);
+  const bool timed = kt && kt->begin(KID_PLAIN + (sizeof(T) == 8 ? 0 : 1 + MODE), 2.0 * g.M * (double)g.N * g.K * work,
+                                     sizeof(T) * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s,
+                                     &slot);
   hipLaunchKernelGGL((gemm_plain_kernel<T, MODE>), grid, dim3(PT_THREADS), 0, s, g, splits, kchunk,
                      (T*)scratch);
-  if (splits > 1) {
-    long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
-    int blocks = (int)((total + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3(blocks), dim3(256), 0, s, g, splits,
-                       (const T*)scratch);
-  }
+  if (timed) kt->end(slot, s);
+  if (splits > 1) return splitk_reduce<T>(g, splits, (const T*)scratch, s);
   return hipGetLastError();
 }
 
@@ -265,19 +280,27 @@ hipError_t gemm_plain(Prec prec, const GemmDesc& g, void* scratch, size_t scratc
 }
 
 hipError_t splitk_reduce_f32(const GemmDesc& g, int splits, const float* partial, hipStream_t s) {
-  long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((splitk_reduce_kernel<float>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
-  return hipGetLastError();
+  return splitk_reduce<float>(g, splits, partial, s);
 }
 
 hipError_t splitk_reduce_f64(const GemmDesc& g, int splits, const double* partial, hipStream_t s) {
-  long long total = (long long)g.batch * g.M * g.N * gemm_members(g);
-  int blocks = (int)((total + 255) / 256);
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL((splitk_reduce_kernel<double>), dim3(blocks), dim3(256), 0, s, g, splits, partial);
-  return hipGetLastError();
+  return splitk_reduce<double>(g, splits, partial, s);
+}
+
+KernelTimer*& kernel_timer() {
+  static KernelTimer* t = nullptr;
+  return t;
+}
+
+const char* kernel_name(int kid) {
+  static const char* const names[KID_N] = {
+      "gemm_mfma_kernel<1, false, false>", "gemm_mfma_kernel<1, false, true>", "gemm_mfma_kernel<1, true, false>",
+      "gemm_mfma_kernel<1, true, true>",   "gemm_mfma_kernel<2, false, false>", "gemm_mfma_kernel<2, false, true>",
+      "gemm_mfma_kernel<2, true, false>",  "gemm_mfma_kernel<2, true, true>",  "gemm_mfma64_kernel<false, false>",
+      "gemm_mfma64_kernel<false, true>",   "gemm_mfma64_kernel<true, false>",  "gemm_mfma64_kernel<true, true>",
+      "gemm_plain_kernel<double, 0>",      "gemm_plain_kernel<float, 0>",      "gemm_plain_kernel<float, 1>",
+      "splitk_reduce_kernel<float>", "splitk_reduce_kernel<double>"};
+  return (kid >= 0 && kid < KID_N) ? names[kid] : "?";
 }
 
 hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {

@@ -49,7 +49,15 @@ float time_once(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStrea
   return ms;
 }
 
+// the timing runs are not the product's own launches: kept out of a kernel timer
+struct TimerOff {
+  KernelTimer* saved;
+  TimerOff() : saved(kernel_timer()) { kernel_timer() = nullptr; }
+  ~TimerOff() { kernel_timer() = saved; }
+};
+
 bool tune(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s, GemmChoice* out) {
+  TimerOff off;
   std::vector<GemmChoice> cand;
   int dflt = 0;
   if (gemm_path_mfma_enabled()) {

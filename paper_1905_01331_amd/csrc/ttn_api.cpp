@@ -130,6 +130,16 @@ struct Profiler {
   void end(size_t slot, hipStream_t s) { (void)hipEventRecord(ev[2 * slot + 1], s); }
 };
 
+// Per-kernel records of the product kernels go into the same event pool,
+// under class ids OC_N + kernel id.
+struct KernelRecorder : KernelTimer {
+  Profiler* P = nullptr;
+  bool begin(int kid, double f, double b, hipStream_t s, size_t* slot) override {
+    return P && P->begin(OC_N + kid, f, b, s, slot);
+  }
+  void end(size_t slot, hipStream_t s) override { P->end(slot, s); }
+};
+
 struct Member {
   Profiler* prof = nullptr;
   // configuration
@@ -199,6 +209,7 @@ struct Ctx {
   std::vector<Member> m;
   hipStream_t s = nullptr;
   Profiler prof;
+  KernelRecorder krec;
   // captured layer part of a sweep (descend(RHO) and every layer step of
   // every member), replayed by ttn_sweep(.., use_graph = 1)
   hipGraph_t graph = nullptr;
@@ -218,6 +229,7 @@ struct Ctx {
   hipStream_t cap_s = nullptr;           // stream the sweep graph is captured on
   std::vector<hipEvent_t> member_events;  // two per member, for grid_s
   ~Ctx() {
+    if (kernel_timer() == &krec) kernel_timer() = nullptr;
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
     for (auto e : join) hipEventDestroy(e);
@@ -1564,6 +1576,9 @@ ttn_status ttn_profile(ttn_handle h, int enable) {
     P.dropped = 0;
   }
   P.on = enable != 0;
+  h->c.krec.P = &P;
+  if (enable) kernel_timer() = &h->c.krec;
+  else if (kernel_timer() == &h->c.krec) kernel_timer() = nullptr;
   return TTN_OK;
 }
 
@@ -1571,10 +1586,11 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
   if (!h || !out || !n_out) return fail(TTN_EINVAL, "bad arguments");
   Profiler& P = h->c.prof;
   HIPCHK(hipStreamSynchronize(h->c.s));
-  std::vector<ttn_profile_entry> agg(OC_N);
-  for (int c = 0; c < OC_N; ++c) {
+  std::vector<ttn_profile_entry> agg(OC_N + KID_N);
+  for (int c = 0; c < OC_N + KID_N; ++c) {
     std::memset(&agg[c], 0, sizeof agg[c]);
-    std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kOpNames[c]);
+    if (c < OC_N) std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kOpNames[c]);
+    else std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kernel_name(c - OC_N));
   }
   for (size_t i = 0; i < P.used; ++i) {
     float ms = 0.f;
@@ -1586,7 +1602,7 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
     e.bytes += P.bytes[i];
   }
   int n = 0;
-  for (int c = 0; c < OC_N && n < max_entries; ++c)
+  for (int c = 0; c < OC_N + KID_N && n < max_entries; ++c)
     if (agg[c].launches) out[n++] = agg[c];
   *n_out = n;
   P.used = 0;
