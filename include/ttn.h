@@ -57,7 +57,7 @@ enum {
   TTN_EHIP = -3,        /* a HIP runtime call failed                          */
   TTN_ENONFINITE = -4,  /* NaN or Inf in a host input                         */
   TTN_ENOCONV = -5,     /* reserved                                            */
-  TTN_EORTHO = -6,      /* an updated isometry failed ||W W^T - I||_F <= 1e-10 */
+  TTN_EORTHO = -6,      /* an updated isometry failed the orthonormality check */
   TTN_ESTATE = -7       /* stage called out of the order of the sweep         */
 };
 
@@ -151,7 +151,8 @@ ttn_status ttn_env(ttn_handle h, int tau);
 
 /* tau in 1..n-1: w_tau <- -polar(Env) = -U V^T for the thin SVD
  *   Env = U S V^T (Sec. III.B, Fig. 10(a)), in float64, followed by the check
- *   ||W W^T - I||_F <= 1e-10 (reported as TTN_EORTHO by ttn_energy).  Unless
+ *   ||W W^T - I||_F <= max(1e-10, 64 eps a^(3/2)), a the largest bond
+ *   dimension (reported as TTN_EORTHO by ttn_energy).  Unless
  *   keep_gauge is set the stored tensor is U^T w_tau = -V^T and w_{tau+1}
  *   (or v when tau = n-1) absorbs U on its input legs (same state).  Does not
  *   re-ascend.

@@ -448,6 +448,7 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
   if (grp().count != 1) return hipErrorInvalidValue;  // the grid barrier needs one problem per launch
   int nb = (n + BK - 1) / BK;
   nb += nb & 1;
+  if (nb > 64) return hipErrorInvalidValue;  // per-round counters hold 64 rounds (n <= 1024)
   const int npairs = nb / 2;
   max_sweeps = std::min(std::max(max_sweeps, 1), 256);
   double* Rbuf = (double*)scratch;

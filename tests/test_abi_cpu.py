@@ -81,3 +81,24 @@ def test_rejects_bad_precision_and_chi(lib):
         _bytes(inputs.tfim_chain(1.0), 16, 8, precision=7)
     with pytest.raises(binding.TTNError):
         _bytes(inputs.tfim_chain(1.0), 16, 0)
+    with pytest.raises(binding.TTNError):
+        _bytes(inputs.tfim_chain(1.0), 16, 1025)
+
+
+def test_rejects_empty_batch_and_bad_solver_settings(lib):
+    out = ctypes.c_size_t(0)
+    arr = (binding.TTNConfig * 1)(binding.ChainInput(inputs.tfim_chain(1.0), 16, 8).cfg)
+    assert lib.ttn_workspace_bytes(arr, 0, ctypes.byref(out)) == binding.TTN_EINVAL
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(inputs.tfim_chain(1.0), 16, 8, krylov=64)
+    assert e.value.status == binding.TTN_EINVAL
+    with pytest.raises(binding.TTNError) as e:
+        _bytes(inputs.tfim_chain(1.0), 16, 8, shift=math.inf)
+    assert e.value.status in (binding.TTN_EINVAL, binding.TTN_ENONFINITE)
+
+
+def test_zero_hamiltonian_and_unit_bond_dimension_are_accepted(lib):
+    zero = inputs.ChainModel("zero", np.zeros((2, 2)), [], [])
+    assert _bytes(zero, 32, 3, shift=1.0) > 0
+    assert _bytes(inputs.tfim_chain(1.3), 8, 1) > 0
+    assert _bytes(inputs.tfim_chain(1.0), 4, 2) > 0

@@ -1,0 +1,182 @@
+"""The benchmarked workloads at their full sizes, in the launch configuration
+the benchmark times (autotuned launches, graph-replayed sweeps), checked on
+outputs the CPU reference can compute one at a time and on properties that
+hold at any size.
+
+* XXX chain L = 4096 at chi = 256 and the 64 x 4 torus (d = 16, D = 4) at
+  chi = 128, split-bf16 bulk: after an eager and a graph sweep, one sweep is
+  run stage by stage; at the top layer the reference recomputes the
+  one-site RDM, the dressed two-site RDMs and the environment from the GPU's
+  own state (isometries, top tensor and the operators of the level below),
+  and the polar update is checked against the GPU's environment
+  (orthonormal rows, -Env W^T symmetric positive semidefinite, the maximised
+  pairing equal to the sum of singular values); the re-ascended top
+  operators are recomputed from the new isometry.  The energy of the final
+  state is re-evaluated in float64, and bounded below by the exact
+  infinite-chain energy where one is known.
+* 128 transverse-field Ising chains (seeded L, h, chi; float32 bulk) swept
+  together: every member's energy stays above its free-fermion ground
+  energy, agrees with its float64 re-evaluation, and its isometries are
+  orthonormal.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import physics_ref as P
+from oracle import ttn_ref as T
+from paper_1905_01331_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_STAGE = {"fp32": 2e-5, "bf16x3": 1e-4}
+TOL_CANCEL = {"fp32": 2e-5, "bf16x3": 3e-3}
+TOL_ENERGY = {"fp32": 2e-6, "bf16x3": 2e-5}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1905_01331_amd import binding
+    binding.load_library()
+    return binding
+
+
+@pytest.fixture
+def tuned(B):
+    B.autotune(1)
+    yield
+    B.autotune(0)
+
+
+def rel_err(x, y):
+    return float(np.abs(np.asarray(x) - np.asarray(y)).max() / max(1e-300, np.abs(np.asarray(y)).max()))
+
+
+def set_err(xs, ys):
+    num = max(float(np.abs(np.asarray(x) - np.asarray(y)).max()) for x, y in zip(xs, ys))
+    return num / max(1e-300, max(float(np.abs(np.asarray(y)).max()) for y in ys))
+
+
+# (name, model, L, chi, precision, lower bound on e per site or None)
+FULL = [
+    ("xxx_L4096_chi256_bf16x3", I.xxx_chain(), 4096, 256, "bf16x3", 0.25 - math.log(2.0) - 1e-6),
+    ("torus64x4_chi128_bf16x3", I.torus_tfim_column(4, 3.0), 64, 128, "bf16x3", None),
+]
+
+
+@pytest.mark.parametrize("name,model,L,chi,prec,bound", FULL, ids=[c[0] for c in FULL])
+def test_full_size_top_layer_sampled(B, tuned, name, model, L, chi, prec, bound):
+    print(f"[full size] {name}", flush=True)
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=0, keep_gauge=True))
+    n = t.n_levels()
+    c = t.stats().shift
+    t.sweep(1)
+    t.sweep(1, graph=True)
+    e1 = t.energy()[0]
+    print(f"  after two sweeps e = {e1:.10f}", flush=True)
+    # one sweep stage by stage; the top layer is sampled
+    top = n - 1
+    t.descend(B.TTN_DESCEND_RHO)
+    for tau in range(1, top):
+        t.descend(B.TTN_DESCEND_DRESSED, tau)
+        t.env(tau)
+        t.update(tau)
+        t.ascend(tau, tau)
+    t.descend(B.TTN_DESCEND_DRESSED, top)
+    t.env(top)
+    w = t.get_tensor(top)
+    v = t.get_tensor(B.TTN_TOP)
+    h = t.get_operator(top - 1, B.TTN_OP_H)
+    A = [t.get_operator(top - 1, B.TTN_OP_A, k) for k in range(model.D)]
+    Bm = [t.get_operator(top - 1, B.TTN_OP_B, k) for k in range(model.D)]
+    rho = T.rho_top(v)
+    At = [T.close(w, T.apply_r(a, w)) for a in A]
+    Bt = [T.close(w, T.apply_l(b, w)) for b in Bm]
+    R, Lb = T.dressed_top(v, At, Bt)
+    env = T.environment(w, h, A, Bm, rho, R, Lb)
+    ks = range(model.D)
+    errs = {
+        "rho": rel_err(t.get_operator(top, B.TTN_OP_RHO), rho),
+        "Rbar": set_err([t.get_operator(top, B.TTN_OP_RBAR, k) for k in ks], R),
+        "Lbar": set_err([t.get_operator(top, B.TTN_OP_LBAR, k) for k in ks], Lb),
+    }
+    env_gpu = t.get_operator(top, B.TTN_OP_ENV)
+    errs["env"] = rel_err(env_gpu, env)
+    print("  top-layer relative errors:", {k: f"{x:.2e}" for k, x in errs.items()}, flush=True)
+    assert errs["rho"] < TOL_STAGE[prec] and errs["env"] < TOL_STAGE[prec]
+    assert errs["Rbar"] < TOL_CANCEL[prec] and errs["Lbar"] < TOL_CANCEL[prec]
+    # float64 polar of the GPU's own environment
+    t.update(top)
+    w_new = t.get_tensor(top)
+    a = w_new.shape[0]
+    W = w_new.reshape(a, -1)
+    E = env_gpu.reshape(a, -1)
+    s = np.linalg.svd(E, compute_uv=False)
+    assert np.abs(W @ W.T - np.eye(a)).max() < 2e-15 * max(a, 50)
+    Mx = -E @ W.T
+    assert np.abs(Mx - Mx.T).max() <= 1e-12 * s[0]
+    assert np.linalg.eigvalsh(0.5 * (Mx + Mx.T)).min() >= -1e-12 * s[0]
+    assert -float(np.sum(W * E)) == pytest.approx(float(np.sum(s)), rel=1e-12)
+    # the re-ascended top operators
+    t.ascend(top, top)
+    h2, A2, B2 = T.ascend(w_new, h, A, Bm)
+    assert rel_err(t.get_operator(top, B.TTN_OP_H), h2) < TOL_STAGE[prec]
+    assert set_err([t.get_operator(top, B.TTN_OP_A, k) for k in ks], A2) < TOL_CANCEL[prec]
+    assert set_err([t.get_operator(top, B.TTN_OP_B, k) for k in ks], B2) < TOL_CANCEL[prec]
+    t.update(B.TTN_TOP)
+    e2 = t.energy()[0]
+    st = t.stats()
+    assert st.ortho_err_max < 64 * np.finfo(np.float64).eps * chi ** 1.5
+    scale = max(abs(e2), abs(c) / model.ly)
+    assert e2 <= e1 + TOL_ENERGY[prec] * scale
+    # float64 re-evaluation of the final state
+    state = [t.get_tensor(tau) for tau in range(1, n)]
+    v_top = t.get_tensor(B.TTN_TOP)
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=v_top))
+    e_re = r.energy()[0]
+    r.close()
+    print(f"  e = {e2:.10f}, float64 re-evaluation {e_re:.10f}", flush=True)
+    assert abs(e2 - e_re) <= TOL_ENERGY[prec] * scale
+    if bound is not None:
+        assert e_re >= bound
+
+
+def test_full_size_batch_of_128_chains(B, tuned):
+    draws = I.batched_tfim_draws()
+    print(f"[full size] batch of {len(draws)} chains", flush=True)
+    mk = lambda d: B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp32", seed=d["seed"])
+    t = B.TTN([mk(d) for d in draws])
+    e0 = t.energy()
+    t.sweep(1)
+    t.sweep(1, graph=True)
+    e = t.energy()
+    shifts = np.array([t.stats(i).shift for i in range(len(draws))])
+    scale = np.maximum(np.abs(e), shifts)
+    assert np.all(e <= e0 + TOL_ENERGY["fp32"] * scale)
+    states = []
+    for i in range(len(draws)):
+        n_i = t.n_levels(i)
+        states.append(([t.get_tensor(tau, i) for tau in range(1, n_i)], t.get_tensor(B.TTN_TOP, i)))
+        if i % 16 == 0:
+            for w in states[-1][0]:
+                W = w.reshape(w.shape[0], -1)
+                assert np.abs(W @ W.T - np.eye(W.shape[0])).max() < 2e-15 * max(W.shape[0], 50)
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    r = B.TTN([B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp64", w0=w, v0=v)
+               for d, (w, v) in zip(draws, states)])
+    e_re = r.energy()
+    r.close()
+    err = np.abs(e - e_re) / scale
+    print(f"  worst energy error vs float64 re-evaluation {err.max():.2e}", flush=True)
+    assert err.max() < TOL_ENERGY["fp32"]
+    floor = np.array([P.tfim_free_fermion_energy(d["L"], d["h"]) / d["L"] for d in draws])
+    assert np.all(e_re >= floor - 1e-12)

@@ -43,6 +43,8 @@ CASES = [
     # environments with more than 128 rows take the blocked Jacobi path
     ("tfim_L32_chi160", I.tfim_chain(0.8), 32, 160),
     ("xxx_L32_chi256", I.xxx_chain(), 32, 256),
+    # the critical TFIM chain workload at its full size (L = 1024, chi = 64)
+    ("tfim_L1024_chi64_full", I.tfim_chain(1.0), 1024, 64),
 ]
 
 
