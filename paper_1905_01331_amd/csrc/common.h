@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP sources of libttn (gfx950 only).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -63,9 +64,26 @@ struct GroupScope {
   GroupScope(int count, long long stride) : saved(grp()) { grp().count = count; grp().stride = stride; }
   ~GroupScope() { grp() = saved; }
 };
+// Global-memory access through an address-space-qualified pointer.  Device
+// pointers carried in structures are generic to the compiler, and generic
+// (flat) accesses count against the LDS counter as well as the vector-memory
+// counter, so a wait for LDS reads would also wait for every global load in
+// flight; these helpers make the access a global one.
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
+// (byte arithmetic on the pointer itself, not through an integer, so that the
+// compiler keeps knowing a kernel argument points to global memory)
 template <class T>
 __device__ __forceinline__ T* mshift(T* p, long long ms) {
-  return p ? (T*)((uintptr_t)p + (long long)blockIdx.y * ms) : p;
+  typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long long)blockIdx.y * ms) : p;
 }
 
 // Optional per-kernel timing of the product kernels (set while a handle's

@@ -81,7 +81,7 @@ TileMap make_map(int gx, int gy, int gz) {
   return t;
 }
 
-__device__ __forceinline__ f32x4 ld4(const float* p) { return *reinterpret_cast<const f32x4*>(p); }
+__device__ __forceinline__ f32x4 ld4(const float* p) { return gload(reinterpret_cast<const f32x4*>(p)); }
 
 // Per-thread register staging of one operand tile (BMN x BK floats).
 template <int MODE, bool KC>
@@ -123,6 +123,25 @@ struct Stage {
       }
     }
   }
+
+  // Whole tile in range and every BK chunk inside one block of the
+  // two-level contraction index: the same elements as load(), addressed as
+  // a work-group-uniform base (tile origin, k offset, load index) plus a
+  // per-thread offset, with no range tests.
+  __device__ __forceinline__ static long long fast_stride(const OpView& v) {
+    if constexpr (KC) return (long long)(NT / (BK / 4)) * v.s_mn;
+    else if constexpr (MODE == P_F32) return (long long)(NT / (BM / 4)) * v.s_k;
+    else return v.s_k;
+  }
+  __device__ __forceinline__ static long long fast_voff(const OpView& v, int tid) {
+    if constexpr (KC) return (long long)(tid / (BK / 4)) * v.s_mn + (tid % (BK / 4)) * 4;
+    else if constexpr (MODE == P_F32) return (tid % (BM / 4)) * 4 + (long long)(tid / (BM / 4)) * v.s_k;
+    else return (tid % 32) * 4 + (long long)(tid / 32) * 4 * v.s_k;
+  }
+  __device__ __forceinline__ void load_fast(const float* tile_base, long long s_i, long long voff) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) r[i] = ld4(tile_base + i * s_i + voff);
+  }
 };
 
 // LDS planes
@@ -146,9 +165,25 @@ __device__ __forceinline__ int swz(int row, int plane) {
   return row ^ (((row >> 2) ^ (plane << 1)) & 7);
 }
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+// Two floats at once: hi = bf16(x), lo = bf16(x - hi), both rounded to
+// nearest even (one packed conversion each); the float value of each hi is
+// rebuilt from the packed pair by moving its 16 bits into place.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void split2_bf16(float x0, float x1, bf16x2& hi, bf16x2& lo) {
+  hi = __builtin_convertvector(f32x2{x0, x1}, bf16x2);
+  const unsigned u = __builtin_bit_cast(unsigned, hi);
+  const float h0 = __builtin_bit_cast(float, u << 16);
+  const float h1 = __builtin_bit_cast(float, u & 0xffff0000u);
+  const float l0 = x0 - h0, l1 = x1 - h1;
+  lo = __builtin_convertvector(f32x2{l0, l1}, bf16x2);
+}
+__device__ __forceinline__ void split4_bf16(float x0, float x1, float x2, float x3, bf16x4& hi, bf16x4& lo) {
+  bf16x2 h01, l01, h23, l23;
+  split2_bf16(x0, x1, h01, l01);
+  split2_bf16(x2, x3, h23, l23);
+  hi = __builtin_shufflevector(h01, h23, 0, 1, 2, 3);
+  lo = __builtin_shufflevector(l01, l23, 0, 1, 2, 3);
 }
 
 template <bool KC>
@@ -184,13 +219,7 @@ __device__ __forceinline__ void store_bf16(const Stage<P_BF16X3, KC>& st, __bf16
       int f = tid + i * NT;
       int mn = f / (BK / 4), k = (f % (BK / 4)) * 4;
       bf16x4 h, l;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        __bf16 a, b;
-        split_bf16(st.r[i][e], a, b);
-        h[e] = a;
-        l[e] = b;
-      }
+      split4_bf16(st.r[i][0], st.r[i][1], st.r[i][2], st.r[i][3], h, l);
       *reinterpret_cast<bf16x4*>(&hi[k >> 3][swz(mn, k >> 3)][k & 7]) = h;
       *reinterpret_cast<bf16x4*>(&lo[k >> 3][swz(mn, k >> 3)][k & 7]) = l;
     }
@@ -199,61 +228,40 @@ __device__ __forceinline__ void store_bf16(const Stage<P_BF16X3, KC>& st, __bf16
 #pragma unroll
     for (int e = 0; e < 4; ++e) {  // row mn + e, k = kb .. kb+3
       bf16x4 h, l;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        __bf16 a, b;
-        split_bf16(st.r[i][e], a, b);
-        h[i] = a;
-        l[i] = b;
-      }
+      split4_bf16(st.r[0][e], st.r[1][e], st.r[2][e], st.r[3][e], h, l);
       *reinterpret_cast<bf16x4*>(&hi[kb >> 3][swz(mn + e, kb >> 3)][kb & 7]) = h;
       *reinterpret_cast<bf16x4*>(&lo[kb >> 3][swz(mn + e, kb >> 3)][kb & 7]) = l;
     }
   }
 }
 
+// The contraction loop of one output tile: the next chunk of BK contraction
+// indices of both operands is loaded into registers while the MFMAs consume
+// the current one from LDS.
 template <int MODE, bool AKC, bool BKC>
-__global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, int kchunk, float* __restrict__ partial,
-                                                      TileMap tm) {
+__device__ __forceinline__ void kloop(Smem<MODE>& sm, const OpView& va, const OpView& vb, int m0, int n0, int kbeg,
+                                      int kend, f32x16 (&acc)[2][2], int tid, bool fast) {
   constexpr int BK = Cfg<MODE>::BK;
-  __shared__ Smem<MODE> sm;
-
-  int tx, ty, bz;
-  if (!map_tile(tm, tx, ty, bz)) return;
-  {  // launch-group member: outermost index
-    const int per = g.batch * splits, mem = bz / per;
-    bz -= mem * per;
-    g.A = member_ptr(g.A, g, mem); g.B = member_ptr(g.B, g, mem); g.C = member_ptr(g.C, g, mem);
-    g.skip = member_ptr(g.skip, g, mem);
-    partial = member_ptr(partial, g, mem);
-  }
-  if (g.skip && *g.skip) return;
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
-  const int b = bz / splits, sp = bz - b * splits;
-  const int m0 = ty * BM, n0 = tx * BN;
-  const int kbeg = sp * kchunk;
-  const int kend = min(g.K, kbeg + kchunk);
-
-  OpView va{(const float*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
-  OpView vb{(const float*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
   Stage<MODE, AKC> sa;
   Stage<MODE, BKC> sb;
-  if (kbeg < kend) {
-    sa.load(va, m0, kbeg, kend, tid);
-    sb.load(vb, n0, kbeg, kend, tid);
-  }
+  const float* abase = va.base + (long long)m0 * (AKC ? va.s_mn : 1);
+  const float* bbase = vb.base + (long long)n0 * (BKC ? vb.s_mn : 1);
+  const long long as_i = Stage<MODE, AKC>::fast_stride(va), bs_i = Stage<MODE, BKC>::fast_stride(vb);
+  const long long avo = Stage<MODE, AKC>::fast_voff(va, tid);
+  const long long bvo = Stage<MODE, BKC>::fast_voff(vb, tid);
+  auto load = [&](Stage<MODE, AKC>& xa, Stage<MODE, BKC>& xb, int k) {
+    if (fast) {  // uniform over the work-group
+      xa.load_fast(abase + k_offset(va, k), as_i, avo);
+      xb.load_fast(bbase + k_offset(vb, k), bs_i, bvo);
+    } else {
+      xa.load(va, m0, k, kend, tid);
+      xb.load(vb, n0, k, kend, tid);
+    }
+  };
+  if (kbeg < kend) load(sa, sb, kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     if constexpr (MODE == P_F32) {
       store_f32<AKC>(sa, sm.a, tid);
@@ -263,10 +271,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
       store_bf16<BKC>(sb, sm.bhi, sm.blo, tid);
     }
     __syncthreads();
-    if (k0 + BK < kend) {
-      sa.load(va, m0, k0 + BK, kend, tid);
-      sb.load(vb, n0, k0 + BK, kend, tid);
-    }
+    if (k0 + BK < kend) load(sa, sb, k0 + BK);
     if constexpr (MODE == P_F32) {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 2) {
@@ -303,6 +308,45 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
     }
     __syncthreads();
   }
+}
+
+template <int MODE, bool AKC, bool BKC>
+__global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, int kchunk, float* __restrict__ partial,
+                                                      TileMap tm, int fast_ok) {
+  __shared__ Smem<MODE> sm;
+
+  int tx, ty, bz;
+  if (!map_tile(tm, tx, ty, bz)) return;
+  {  // launch-group member: outermost index
+    const int per = g.batch * splits, mem = bz / per;
+    bz -= mem * per;
+    g.A = member_ptr(g.A, g, mem); g.B = member_ptr(g.B, g, mem); g.C = member_ptr(g.C, g, mem);
+    g.skip = member_ptr(g.skip, g, mem);
+    partial = member_ptr(partial, g, mem);
+  }
+  if (g.skip && gload(g.skip)) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int b = bz / splits, sp = bz - b * splits;
+  const int m0 = ty * BM, n0 = tx * BN;
+  const int kbeg = sp * kchunk;
+  const int kend = min(g.K, kbeg + kchunk);
+
+  OpView va{(const float*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
+  OpView vb{(const float*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const bool fast = fast_ok && m0 + BM <= g.M && n0 + BN <= g.N;
+  kloop<MODE, AKC, BKC>(sm, va, vb, m0, n0, kbeg, kend, acc, tid, fast);
 
   // epilogue: lane l, register r of block (i, j) holds
   // row wm + 32 i + 8 (r / 4) + 4 (l / 32) + r % 4, column wn + 32 j + l % 32
@@ -322,8 +366,8 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
           if (m >= g.M) continue;
           float* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
           float v = alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += beta * (*c);
-          *c = v;
+          if (g.beta != 0.0) v += beta * gload(c);
+          gstore(c, v);
         }
       }
   } else {
@@ -338,7 +382,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
         for (int r = 0; r < 16; ++r) {
           int m = m0 + wm + 32 * i + 8 * (r >> 2) + rowq + (r & 3);
           if (m >= g.M) continue;
-          P[(long long)m * g.N + n] = acc[i][j][r];
+          gstore(P + (long long)m * g.N + n, acc[i][j][r]);
         }
       }
   }
@@ -379,7 +423,7 @@ struct Stage64 {
       int gm = mn0 + mn, gk = k0 + k;
       if (gm < v.MN && gk < kend) {
         const double* p = KC ? v.base + (long long)gm * v.s_mn + k_offset64(v, gk) : v.base + gm + k_offset64(v, gk);
-        r[i] = *reinterpret_cast<const f64x2*>(p);
+        r[i] = gload(reinterpret_cast<const f64x2*>(p));
       } else {
         r[i] = f64x2{0.0, 0.0};
       }
@@ -415,7 +459,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
     g.skip = member_ptr(g.skip, g, mem);
     partial = member_ptr(partial, g, mem);
   }
-  if (g.skip && *g.skip) return;
+  if (g.skip && gload(g.skip)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
   const int b = bz / splits, sp = bz - b * splits;
@@ -472,8 +516,8 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
           if (m >= g.M) continue;
           double* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
           double v = g.alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += g.beta * (*c);
-          *c = v;
+          if (g.beta != 0.0) v += g.beta * gload(c);
+          gstore(c, v);
         }
       }
   } else {
@@ -488,7 +532,7 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
         for (int r = 0; r < 4; ++r) {
           int m = m0 + wm + 16 * i + row_l + 4 * r;
           if (m >= g.M) continue;
-          P[(long long)m * g.N + n] = acc[i][j][r];
+          gstore(P + (long long)m * g.N + n, acc[i][j][r]);
         }
       }
   }
@@ -516,8 +560,12 @@ hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hip
   const double work = (double)g.batch * gemm_members(g);
   const bool timed = kt && kt->begin(KID_MFMA + 4 * (MODE - 1) + 2 * AKC + BKC, 2.0 * g.M * (double)g.N * g.K * work,
                                      4.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
+  constexpr int BK = Cfg<MODE>::BK;
+  // every chunk of BK contraction indices lies inside one block of the
+  // two-level index (kchunk is a multiple of BK)
+  const int fast_ok = (g.K % BK == 0) && (g.K2 <= 0 || g.K2 % BK == 0);
   hipLaunchKernelGGL((gemm_mfma_kernel<MODE, AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
-                     partial, tm);
+                     partial, tm, fast_ok);
   if (timed) kt->end(slot, s);
   return hipGetLastError();
 }

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
     g.skip = member_ptr(g.skip, g, mem);
     partial = member_ptr(partial, g, mem);
   }
-  if (g.skip && *g.skip) return;
+  if (g.skip && gload(g.skip)) return;
 
   const int b = bz / splits;
   const int sp = bz - b * splits;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
       else           { kk = idx / PT_M; mm = idx - kk * PT_M; }
       int m = m0 + mm, k = k0 + kk;
       T v = T(0);
-      if (m < g.M && k < kend) v = A[(long long)m * g.sAm + koff(k, g.K2, g.sAk, g.sAk1)];
+      if (m < g.M && k < kend) v = gload(A + (long long)m * g.sAm + koff(k, g.K2, g.sAk, g.sAk1));
       if constexpr (MODE == 1) {
         float hi = bf16_round((float)v);
         As[kk][mm] = hi;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
       else           { nn = idx / PT_K; kk = idx - nn * PT_K; }
       int n = n0 + nn, k = k0 + kk;
       T v = T(0);
-      if (n < g.N && k < kend) v = B[(long long)n * g.sBn + koff(k, g.K2, g.sBk, g.sBk1)];
+      if (n < g.N && k < kend) v = gload(B + (long long)n * g.sBn + koff(k, g.K2, g.sBk, g.sBk1));
       if constexpr (MODE == 1) {
         float hi = bf16_round((float)v);
         Bs[kk][nn] = hi;
@@ -159,8 +159,8 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
         if (n >= g.N) continue;
         T* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
         T r = alpha * acc[i][j];
-        if (g.beta != 0.0) r += beta * (*c);
-        *c = r;
+        if (g.beta != 0.0) r += beta * gload(c);
+        gstore(c, r);
       }
     }
   } else {
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(PT_THREADS) void gemm_plain_kernel(GemmDesc g, int 
       for (int j = 0; j < 4; ++j) {
         int n = n0 + tx + 16 * j;
         if (n >= g.N) continue;
-        P[(long long)m * g.N + n] = acc[i][j];
+        gstore(P + (long long)m * g.N + n, acc[i][j]);
       }
     }
   }
@@ -206,15 +206,15 @@ __global__ void splitk_reduce_kernel(GemmDesc g, int splits, const T* __restrict
     int sp = 0;
     for (; sp + 8 <= splits; sp += 8) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s8[u] += p[(long long)(sp + u) * stride];
+      for (int u = 0; u < 8; ++u) s8[u] += gload(p + (long long)(sp + u) * stride);
     }
-    for (int u = 0; sp + u < splits; ++u) s8[u] += p[(long long)(sp + u) * stride];
+    for (int u = 0; sp + u < splits; ++u) s8[u] += gload(p + (long long)(sp + u) * stride);
     T s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     T* c = (T*)member_ptr(g.C, g, mem) + batch_offset(g, b, g.sCb, g.sCb2) + (long long)m * g.sCm +
            (long long)n * g.sCn;
     T out = (T)g.alpha * s;
-    if (g.beta != 0.0) out += (T)g.beta * (*c);
-    *c = out;
+    if (g.beta != 0.0) out += (T)g.beta * gload(c);
+    gstore(c, out);
   }
 }
 
