@@ -351,6 +351,42 @@ def ortho_error(w):
 
 
 # --------------------------------------------------------------------------
+# entanglement of a block of sites (Sec. V, "Ground state entanglement")
+# --------------------------------------------------------------------------
+def rho_leftmost(ws, v, tau):
+    """Reduced density matrix on the upper bond index of the leftmost
+    isometry of layer tau (the block of the first 2**tau sites; tau = 0: the
+    first site).  At level n-1 the left site of v: v v^T; one level down the
+    leftmost block is the left child of the leftmost block above, so the
+    right child is traced out: C_L(w, rho o w)."""
+    n = len(ws) + 1
+    rho = v @ v.T
+    for sigma in range(n - 1, tau, -1):
+        w = ws[sigma - 1]
+        rho = close_l(w, left_mul(rho, w))
+    return rho
+
+
+def rho_average(ws, v, tau):
+    """Position average of the reduced density matrices on the upper bond
+    indices of layer tau (the same as descend_rho_all)."""
+    return descend_rho_all(ws, v)[tau]
+
+
+def entanglement(rho):
+    """Spectrum p (descending) of a reduced density matrix, the entanglement
+    spectrum lambda = -log2 p and the entanglement entropy
+    S = -sum p log2 p (Sec. V), terms with p <= 0 counted as zero (inf in
+    lambda)."""
+    p = np.sort(np.linalg.eigvalsh(0.5 * (rho + rho.T)))[::-1]
+    pos = p > 0
+    lam = np.full(p.shape, np.inf)
+    lam[pos] = -np.log2(p[pos])
+    S = float(-np.sum(p[pos] * np.log2(p[pos])))
+    return p, lam, S
+
+
+# --------------------------------------------------------------------------
 # the sweep
 # --------------------------------------------------------------------------
 class TTNRef:

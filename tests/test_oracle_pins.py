@@ -288,3 +288,61 @@ def test_sweep_xxx_bethe_bound():
     assert hist[-1] > P.BETHE_XXX_ENERGY_DENSITY - 0.01
     assert hist[-1] > e_ed16 - 0.01
     assert all(b <= a + 1e-12 for a, b in zip(hist, hist[1:]))
+
+
+# ------------------------------------------- entanglement of a block ----------
+def _block_rdm(psi, n_sites, d, start, size):
+    """Reduced density matrix of sites [start, start + size) of a state given
+    as one flat vector over n_sites sites of dimension d."""
+    t = psi.reshape([d] * n_sites)
+    keep = list(range(start, start + size))
+    rest = [i for i in range(n_sites) if i not in keep]
+    m = np.transpose(t, keep + rest).reshape(d ** size, -1)
+    return m @ m.T
+
+
+@pytest.mark.parametrize("L,chi,seed", [(8, 4, 3), (8, 3, 5), (16, 5, 7)])
+def test_entanglement_bruteforce(L, chi, seed):
+    # the block of 2**tau sites under one isometry of layer tau is reached
+    # through an isometric map from that isometry's upper bond, so the
+    # nonzero spectrum of the block's reduced density matrix is the spectrum
+    # of the bond's; the subtree below every block of a uniform TTN is the
+    # same map, so the average over blocks matches the averaged bond matrix
+    ws = I.random_isometries(T.layer_shapes(L, 2, chi), seed)
+    v = I.random_top(ws[-1].shape[0], seed)
+    n = len(ws) + 1
+    psi = P.full_state(ws, v)
+    assert np.linalg.norm(psi) == pytest.approx(1.0, abs=1e-13)
+    for tau in range(n):
+        size = 2 ** tau
+        p, lam, S = T.entanglement(T.rho_leftmost(ws, v, tau))
+        full = np.sort(np.linalg.eigvalsh(_block_rdm(psi, L, 2, 0, size)))[::-1]
+        assert np.abs(full[:len(p)] - p).max() < 1e-12
+        assert np.abs(full[len(p):]).max(initial=0.0) < 1e-12
+        pos = full > 1e-15
+        assert S == pytest.approx(float(-np.sum(full[pos] * np.log2(full[pos]))), abs=1e-10)
+        avg = sum(_block_rdm(psi, L, 2, j * size, size) for j in range(L // size)) / (L // size)
+        pa, _, Sa = T.entanglement(T.rho_average(ws, v, tau))
+        fa = np.sort(np.linalg.eigvalsh(avg))[::-1]
+        assert np.abs(fa[:len(pa)] - pa).max() < 1e-12
+        assert np.abs(fa[len(pa):]).max(initial=0.0) < 1e-12
+        assert abs(np.sum(pa) - 1.0) < 1e-12 and abs(np.sum(p) - 1.0) < 1e-12
+    # the two halves of a pure state share their spectrum
+    pl = T.entanglement(v @ v.T)[0]
+    pr = T.entanglement(v.T @ v)[0]
+    assert np.abs(pl - pr).max() < 1e-13
+
+
+def test_entanglement_closed_forms():
+    # a maximally entangled top tensor: uniform spectrum, S = log2(chi)
+    x = 8
+    p, lam, S = T.entanglement(np.eye(x) / x)
+    assert np.allclose(p, 1.0 / x) and np.allclose(lam, np.log2(x))
+    assert S == pytest.approx(np.log2(x), abs=1e-14)
+    # bond dimension one: a product of the two-site states of layer 1, so no
+    # block of 2**tau >= 2 aligned sites is entangled with the rest
+    ws = I.random_isometries(T.layer_shapes(8, 2, 1), 2)
+    v = np.ones((1, 1))
+    for tau in range(1, len(ws) + 1):
+        p, lam, S = T.entanglement(T.rho_leftmost(ws, v, tau))
+        assert p[0] == pytest.approx(1.0, abs=1e-14) and S == pytest.approx(0.0, abs=1e-14)
