@@ -56,6 +56,9 @@ enum Prec { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2 };
 struct GroupCtx {
   int count = 1;
   long long stride = 0;
+  // optional device flag (per member, shifted like every member pointer):
+  // the kernels of the helpers that honour it return at once while it is set
+  const int* skip = nullptr;
 };
 GroupCtx& grp();  // the calling thread's current launch group
 // scoped setting of the launch group
@@ -64,6 +67,12 @@ struct GroupScope {
   GroupScope(int count, long long stride) : saved(grp()) { grp().count = count; grp().stride = stride; }
   ~GroupScope() { grp() = saved; }
 };
+struct SkipScope {
+  const int* saved;
+  explicit SkipScope(const int* flag) : saved(grp().skip) { grp().skip = flag; }
+  ~SkipScope() { grp().skip = saved; }
+};
+
 // Global-memory access through an address-space-qualified pointer.  Device
 // pointers carried in structures are generic to the compiler, and generic
 // (flat) accesses count against the LDS counter as well as the vector-memory
@@ -84,6 +93,10 @@ template <class T>
 __device__ __forceinline__ T* mshift(T* p, long long ms) {
   typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
   return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (long long)blockIdx.y * ms) : p;
+}
+// true when the member's skip flag is set (uniform over the work-group)
+__device__ __forceinline__ bool member_skipped(const int* sk, long long ms) {
+  return sk && *mshift(sk, ms);
 }
 
 // Optional per-kernel timing of the product kernels (set while a handle's

@@ -2,11 +2,6 @@
 #include "common.h"
 
 namespace ttn {
-hipError_t lz_three_term(double* w, const double* qj, const double* qjm1, const double* alpha, const double* beta, int j,
-                         size_t n, const int* stop, hipStream_t s);
-hipError_t lz_set_beta(const double* ss, const double* hss, double* beta, int j, double tol, int* stop, int* m_eff,
-                       hipStream_t s);
-hipError_t lz_next_q(const double* w, double* qn, const double* beta, int j, size_t n, const int* stop, hipStream_t s);
 hipError_t lz_build_T(const double* alpha, const double* beta, int m, const int* stop, const int* m_eff, double* T,
                       hipStream_t s);
 hipError_t lz_select_lowest(const double* T, const double* V, int m, double* y, double* theta, hipStream_t s);
@@ -21,12 +16,21 @@ hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, 
 hipError_t running_max(const double* x, double* run_max, hipStream_t s);
 hipError_t identity_f64(double* X, int n, hipStream_t s);
 hipError_t zero_int(int* x, int n, hipStream_t s);
-// Full reorthogonalisation pass against the first nq rows of Q (row length n):
-// coef[i] = Q[i].w (i < nq), coef[nq] = w.w (before the update), then
-// w -= sum_i coef[i] Q[i].  `part` holds lz_reorth_part_doubles() doubles.
-hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s);
+// *done = 1 when res[0] <= tol max(1, |lam[0]|)
+hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, hipStream_t s);
+// Full reorthogonalisation against the first nq rows of Q (row length n), in
+// two passes of classical Gram-Schmidt; `part` holds lz_reorth_part_doubles()
+// doubles, `nrm` lz_norm_doubles().  For recurrence step j (nq = j + 1):
+// first:  c1 = Q^T w (c1[nq] = ||w||^2 before), w -= Q c1;
+// final:  c2 = Q^T w, w -= Q c2, alpha[j] = c1[j] + c2[j], beta[j] = ||w||
+//         (zero, and stop / m_eff set, when beta[j] <= tol ||H q_j||),
+//         q_{j+1} = w / beta[j] into qn, and also into stage when not null.
 size_t lz_reorth_part_doubles();
-hipError_t lz_alpha(const double* c1, const double* c2, int j, double* alpha, hipStream_t s);
+size_t lz_norm_doubles();
+hipError_t lz_reorth_first(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s);
+hipError_t lz_reorth_final(double* w, const double* Q, int nq, size_t n, const double* c1, double* c2, double* part,
+                           double* nrm, double* alpha, double* beta, double tol, int* stop, int* m_eff, double* qn,
+                           double* stage, hipStream_t s);
 // X <- (X + sign X^T) / 2 in place (sign = +1 symmetric, -1 antisymmetric part)
 hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s);
 }  // namespace ttn

@@ -4,6 +4,7 @@
 #include "common.h"
 #include "lanczos.h"
 #include <math.h>
+#include <algorithm>
 
 namespace ttn {
 namespace {
@@ -15,53 +16,11 @@ inline int grid_for(size_t n, int threads = 256, int cap = 4096) {
   return (int)b;
 }
 
-// w <- w - alpha[j] q_j - beta[j-1] q_{j-1}
-__global__ void k_three_term(double* __restrict__ w, const double* __restrict__ qj, const double* __restrict__ qjm1,
-                             const double* __restrict__ alpha, const double* __restrict__ beta, int j, size_t n,
-                             const int* __restrict__ stop, long long ms_) {
-  w = mshift(w, ms_); qj = mshift(qj, ms_); qjm1 = mshift(qjm1, ms_); alpha = mshift(alpha, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_);
-  if (*stop) return;
-  double a = alpha[j];
-  double b = (j > 0) ? beta[j - 1] : 0.0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double v = w[i] - a * qj[i];
-    if (j > 0) v -= b * qjm1[i];
-    w[i] = v;
-  }
-}
-
-// beta[j] = sqrt(ss); stop when beta[j] <= tol * hnorm (invariant subspace).
-__global__ void k_set_beta(const double* __restrict__ ss, const double* __restrict__ hss, double* __restrict__ beta,
-                           int j, double tol, int* __restrict__ stop, int* __restrict__ m_eff, long long ms_) {
-  ss = mshift(ss, ms_); hss = mshift(hss, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_); m_eff = mshift(m_eff, ms_);
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (*stop) { beta[j] = 0.0; return; }
-  double b = sqrt(fmax(ss[0], 0.0));
-  double hn = sqrt(fmax(hss[0], 0.0));
-  if (!(b > tol * hn) || b == 0.0) {
-    beta[j] = 0.0;
-    *stop = 1;
-    *m_eff = j + 1;
-  } else {
-    beta[j] = b;
-  }
-}
-
-// q_{j+1} = w / beta[j] (left at zero after a stop)
-__global__ void k_next_q(const double* __restrict__ w, double* __restrict__ qn, const double* __restrict__ beta, int j,
-                         size_t n, const int* __restrict__ stop, long long ms_) {
-  w = mshift(w, ms_); qn = mshift(qn, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_);
-  double b = beta[j];
-  bool st = *stop;
-  double inv = (!st && b > 0.0) ? 1.0 / b : 0.0;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    qn[i] = st ? 0.0 : w[i] * inv;
-}
-
 // Dense tridiagonal T (m x m) from alpha/beta; rows past m_eff are decoupled
 // with a diagonal above every Ritz value so they never become the lowest.
 __global__ void k_build_T(const double* __restrict__ alpha, const double* __restrict__ beta, int m,
-                          const int* __restrict__ stop, const int* __restrict__ m_eff, double* __restrict__ T, long long ms_) {
+                          const int* __restrict__ stop, const int* __restrict__ m_eff, double* __restrict__ T, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   alpha = mshift(alpha, ms_); beta = mshift(beta, ms_); stop = mshift(stop, ms_); m_eff = mshift(m_eff, ms_); T = mshift(T, ms_);
   int me = (*stop) ? *m_eff : m;
   double big = 0.0;
@@ -84,7 +43,8 @@ __global__ void k_build_T(const double* __restrict__ alpha, const double* __rest
 // y = eigenvector of the smallest diagonal entry of the diagonalised T
 // (rows of U).
 __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* __restrict__ V, int m,
-                                double* __restrict__ y, double* __restrict__ theta, long long ms_) {
+                                double* __restrict__ y, double* __restrict__ theta, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   Tdiag = mshift(Tdiag, ms_); V = mshift(V, ms_); y = mshift(y, ms_); theta = mshift(theta, ms_);
   __shared__ int best;
   if (threadIdx.x == 0) {
@@ -99,7 +59,8 @@ __global__ void k_select_lowest(const double* __restrict__ Tdiag, const double* 
 }
 
 // x *= 1 / sqrt(ss[0])
-__global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__ ss, size_t n, long long ms_) {
+__global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__ ss, size_t n, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   x = mshift(x, ms_); ss = mshift(ss, ms_);
   double s = ss[0];
   double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
@@ -109,7 +70,8 @@ __global__ void k_scale_rsqrt(double* __restrict__ x, const double* __restrict__
 
 // r = Hv - lam v, lam = lamv[0]
 __global__ void k_residual(const double* __restrict__ Hv, const double* __restrict__ v, const double* __restrict__ lamv,
-                           double* __restrict__ r, size_t n, long long ms_) {
+                           double* __restrict__ r, size_t n, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   Hv = mshift(Hv, ms_); v = mshift(v, ms_); lamv = mshift(lamv, ms_); r = mshift(r, ms_);
   double lam = lamv[0];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -159,7 +121,8 @@ __global__ void k_axpy_dev(double* __restrict__ y, const double* __restrict__ x,
     y[i] += s * x[i];
 }
 
-__global__ void k_sqrt_inplace(double* x, long long ms_) {
+__global__ void k_sqrt_inplace(double* x, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   x = mshift(x, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) x[0] = sqrt(fmax(x[0], 0.0));
 }
@@ -222,7 +185,8 @@ __global__ void k_symmetrize(double* __restrict__ X, int n, double sign, long lo
 // slice of Q[i] . w (i < nq), part[b][nq] = w . w.  Fixed grid, deterministic.
 constexpr int MD_BLOCKS = 128, MD_THREADS = 256, MD_MAXQ = 64;
 __global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restrict__ Q, const double* __restrict__ w,
-                                                         int nq, size_t n, double* __restrict__ part, long long ms_) {
+                                                         int nq, size_t n, double* __restrict__ part, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   Q = mshift(Q, ms_); w = mshift(w, ms_); part = mshift(part, ms_);
   __shared__ double red[MD_THREADS / 64][MD_MAXQ + 1];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -255,39 +219,115 @@ __global__ __launch_bounds__(MD_THREADS) void k_multidot(const double* __restric
     part[(size_t)blockIdx.x * (MD_MAXQ + 1) + i] = v;
   }
 }
-// one block per output: fixed-shape tree over the per-block partials
-__global__ __launch_bounds__(MD_BLOCKS) void k_multidot_sum(const double* __restrict__ part, int nq, int nblocks,
-                                                            double* __restrict__ out, long long ms_) {
-  part = mshift(part, ms_); out = mshift(out, ms_);
-  __shared__ double sh[MD_BLOCKS];
-  const int i = blockIdx.x;
-  sh[threadIdx.x] = threadIdx.x < nblocks ? part[(size_t)threadIdx.x * (MD_MAXQ + 1) + i] : 0.0;
-  __syncthreads();
-  for (int st = MD_BLOCKS / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
+// The coefficients of a reorthogonalisation pass, summed from the per-block
+// partials of k_multidot in a fixed order (wave i % 4 sums coefficient i:
+// each lane two partials, then a fixed shuffle tree), so every work-group
+// that calls this holds bitwise the same values.
+__device__ void md_coefficients(const double* __restrict__ part, int nq, double* cs) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i <= nq; i += (int)(blockDim.x >> 6)) {
+    double v = 0.0;
+    for (int b = lane; b < MD_BLOCKS; b += 64) v += part[(size_t)b * (MD_MAXQ + 1) + i];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) cs[i] = v;
   }
-  if (threadIdx.x == 0) out[i] = sh[0];
-}
-// w -= sum_{i < nq} c[i] Q[i]
-__global__ void k_sub_combination(double* __restrict__ w, const double* __restrict__ Q, const double* __restrict__ c,
-                                  int nq, size_t n, long long ms_) {
-  w = mshift(w, ms_); Q = mshift(Q, ms_); c = mshift(c, ms_);
-  __shared__ double cs[MD_MAXQ];
-  for (int i = threadIdx.x; i < nq; i += blockDim.x) cs[i] = c[i];
   __syncthreads();
+}
+// First pass: w -= sum_{i < nq} c[i] Q[i]; coef[0..nq] = c (coef[nq] = w.w
+// before the pass).
+__global__ __launch_bounds__(256) void k_reorth_apply(double* __restrict__ w, const double* __restrict__ Q,
+                                                      const double* __restrict__ part, int nq, size_t n,
+                                                      double* __restrict__ coef, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
+  w = mshift(w, ms_); Q = mshift(Q, ms_); part = mshift(part, ms_); coef = mshift(coef, ms_);
+  __shared__ double cs[MD_MAXQ + 1];
+  md_coefficients(part, nq, cs);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i <= nq; i += blockDim.x) coef[i] = cs[i];
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
     double v = w[e];
     for (int i = 0; i < nq; ++i) v -= cs[i] * Q[(size_t)i * n + e];
     w[e] = v;
   }
 }
-// alpha[j] = c1[j] + c2[j]; hss = ||H q_j||^2 before orthogonalisation
-__global__ void k_alpha(const double* __restrict__ c1, const double* __restrict__ c2, int j, double* __restrict__ alpha, long long ms_) {
-  c1 = mshift(c1, ms_); c2 = mshift(c2, ms_); alpha = mshift(alpha, ms_);
-  if (threadIdx.x == 0 && blockIdx.x == 0) alpha[j] = c1[j] + c2[j];
+// Second pass of step j (nq = j + 1): c2 from the partials, w -= sum c2[i]
+// Q[i], the squares of the new w summed per work-group into nrm[blockIdx.x]
+// (fixed order); work-group 0 stores c2 and alpha[j] = c1[j] + c2[j].
+__global__ __launch_bounds__(256) void k_reorth_second(double* __restrict__ w, const double* __restrict__ Q,
+                                                       const double* __restrict__ part, int nq, size_t n,
+                                                       const double* __restrict__ c1, double* __restrict__ c2,
+                                                       double* __restrict__ alpha, double* __restrict__ nrm,
+                                                       long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
+  w = mshift(w, ms_); Q = mshift(Q, ms_); part = mshift(part, ms_); c1 = mshift(c1, ms_); c2 = mshift(c2, ms_);
+  alpha = mshift(alpha, ms_); nrm = mshift(nrm, ms_);
+  __shared__ double cs[MD_MAXQ + 1];
+  __shared__ double red[4];
+  md_coefficients(part, nq, cs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int i = 0; i <= nq; ++i) c2[i] = cs[i];
+    alpha[nq - 1] = c1[nq - 1] + cs[nq - 1];
+  }
+  double ss = 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    double v = w[e];
+    for (int i = 0; i < nq; ++i) v -= cs[i] * Q[(size_t)i * n + e];
+    w[e] = v;
+    ss += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) ss += __shfl_down(ss, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+// The recurrence step j: beta[j] = ||w|| from the nb per-work-group sums
+// (each work-group adds them in the same fixed order), with the
+// invariant-subspace test against ||H q_j|| = sqrt(c1[j + 1]) (stop and m_eff
+// set, beta[j] = 0); q_{j+1} = w / beta[j] (zero after a stop), also into
+// `stage` when given.  Work-group 0 stores the scalars.
+__global__ __launch_bounds__(256) void k_lz_normalize(const double* __restrict__ w, const double* __restrict__ nrm,
+                                                      int nb, int j, size_t n, const double* __restrict__ c1,
+                                                      double* __restrict__ beta, double tol, int* __restrict__ stop,
+                                                      int* __restrict__ m_eff, double* __restrict__ qn,
+                                                      double* __restrict__ stage, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
+  w = mshift(w, ms_); nrm = mshift(nrm, ms_); c1 = mshift(c1, ms_); beta = mshift(beta, ms_);
+  stop = mshift(stop, ms_); m_eff = mshift(m_eff, ms_); qn = mshift(qn, ms_); stage = mshift(stage, ms_);
+  __shared__ double sh[256];
+  const bool stopped = *stop != 0;  // read before work-group 0 may set it
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v += nrm[b];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double b = sqrt(fmax(sh[0], 0.0));
+  const double hn = sqrt(fmax(c1[j + 1], 0.0));
+  const bool now_stop = !stopped && (!(b > tol * hn) || b == 0.0);
+  const double bj = (stopped || now_stop) ? 0.0 : b;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    beta[j] = bj;
+    if (now_stop) {
+      *stop = 1;
+      *m_eff = j + 1;
+    }
+  }
+  const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const double q = w[e] * inv;
+    qn[e] = q;
+    if (stage) stage[e] = q;
+  }
 }
 
+// *done = 1 once ||r|| <= tol max(1, |lambda|) (never cleared here)
+__global__ void k_lz_mark_done(const double* __restrict__ res, const double* __restrict__ lam, double tol,
+                               int* __restrict__ done, long long ms_) {
+  res = mshift(res, ms_); lam = mshift(lam, ms_); done = mshift(done, ms_);
+  if (threadIdx.x == 0 && blockIdx.x == 0 && res[0] <= tol * fmax(1.0, fabs(lam[0]))) *done = 1;
+}
 __global__ void k_zero_int(int* x, int n, long long ms_) {
   x = mshift(x, ms_);
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
@@ -295,35 +335,21 @@ __global__ void k_zero_int(int* x, int n, long long ms_) {
 
 }  // namespace
 
-hipError_t lz_three_term(double* w, const double* qj, const double* qjm1, const double* alpha, const double* beta, int j,
-                         size_t n, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_three_term, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, qj, qjm1, alpha, beta, j, n, stop, grp().stride);
-  return hipGetLastError();
-}
-hipError_t lz_set_beta(const double* ss, const double* hss, double* beta, int j, double tol, int* stop, int* m_eff,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_set_beta, dim3(1, grp().count), dim3(64), 0, s, ss, hss, beta, j, tol, stop, m_eff, grp().stride);
-  return hipGetLastError();
-}
-hipError_t lz_next_q(const double* w, double* qn, const double* beta, int j, size_t n, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(k_next_q, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, qn, beta, j, n, stop, grp().stride);
-  return hipGetLastError();
-}
 hipError_t lz_build_T(const double* alpha, const double* beta, int m, const int* stop, const int* m_eff, double* T,
                       hipStream_t s) {
-  hipLaunchKernelGGL(k_build_T, dim3(1, grp().count), dim3(256), 0, s, alpha, beta, m, stop, m_eff, T, grp().stride);
+  hipLaunchKernelGGL(k_build_T, dim3(1, grp().count), dim3(256), 0, s, alpha, beta, m, stop, m_eff, T, grp().stride, grp().skip);
   return hipGetLastError();
 }
 hipError_t lz_select_lowest(const double* T, const double* V, int m, double* y, double* theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_lowest, dim3(1, grp().count), dim3(64), 0, s, T, V, m, y, theta, grp().stride);
+  hipLaunchKernelGGL(k_select_lowest, dim3(1, grp().count), dim3(64), 0, s, T, V, m, y, theta, grp().stride, grp().skip);
   return hipGetLastError();
 }
 hipError_t scale_rsqrt(double* x, const double* ss, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, ss, n, grp().stride);
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(grid_for(n), grp().count), dim3(256), 0, s, x, ss, n, grp().stride, grp().skip);
   return hipGetLastError();
 }
 hipError_t residual_vec(const double* Hv, const double* v, const double* lam, double* r, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(grid_for(n), grp().count), dim3(256), 0, s, Hv, v, lam, r, n, grp().stride);
+  hipLaunchKernelGGL(k_residual, dim3(grid_for(n), grp().count), dim3(256), 0, s, Hv, v, lam, r, n, grp().stride, grp().skip);
   return hipGetLastError();
 }
 hipError_t sign_fix(double* v, size_t n, hipStream_t s) {
@@ -335,7 +361,7 @@ hipError_t axpy_dev(double* y, const double* x, const double* scale, double fact
   return hipGetLastError();
 }
 hipError_t sqrt_inplace(double* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_sqrt_inplace, dim3(1, grp().count), dim3(64), 0, s, x, grp().stride);
+  hipLaunchKernelGGL(k_sqrt_inplace, dim3(1, grp().count), dim3(64), 0, s, x, grp().stride, grp().skip);
   return hipGetLastError();
 }
 hipError_t energy_store(const double* lam, const double* c, double L, double ly, double* out, hipStream_t s) {
@@ -358,16 +384,31 @@ hipError_t symmetrize_f64(double* X, int n, double sign, hipStream_t s) {
   hipLaunchKernelGGL(k_symmetrize, dim3(grid_for((size_t)n * (n + 1) / 2), grp().count), dim3(256), 0, s, X, n, sign, grp().stride);
   return hipGetLastError();
 }
-hipError_t lz_reorth(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s) {
+size_t lz_reorth_part_doubles() { return (size_t)MD_BLOCKS * (MD_MAXQ + 1); }
+hipError_t lz_reorth_first(double* w, const double* Q, int nq, size_t n, double* coef, double* part, hipStream_t s) {
   if (nq > MD_MAXQ) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS, grp().count), dim3(MD_THREADS), 0, s, Q, w, nq, n, part, grp().stride);
-  hipLaunchKernelGGL(k_multidot_sum, dim3(nq + 1, grp().count), dim3(MD_BLOCKS), 0, s, part, nq, MD_BLOCKS, coef, grp().stride);
-  hipLaunchKernelGGL(k_sub_combination, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, Q, coef, nq, n, grp().stride);
+  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS, grp().count), dim3(MD_THREADS), 0, s, Q, w, nq, n, part, grp().stride, grp().skip);
+  hipLaunchKernelGGL(k_reorth_apply, dim3(grid_for(n), grp().count), dim3(256), 0, s, w, Q, part, nq, n, coef,
+                     grp().stride, grp().skip);
   return hipGetLastError();
 }
-size_t lz_reorth_part_doubles() { return (size_t)MD_BLOCKS * (MD_MAXQ + 1); }
-hipError_t lz_alpha(const double* c1, const double* c2, int j, double* alpha, hipStream_t s) {
-  hipLaunchKernelGGL(k_alpha, dim3(1, grp().count), dim3(64), 0, s, c1, c2, j, alpha, grp().stride);
+// work-groups of the fused passes: a fixed count for a given n
+static int lz_groups(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 1024); }
+size_t lz_norm_doubles() { return 1024; }
+hipError_t lz_reorth_final(double* w, const double* Q, int nq, size_t n, const double* c1, double* c2, double* part,
+                           double* nrm, double* alpha, double* beta, double tol, int* stop, int* m_eff, double* qn,
+                           double* stage, hipStream_t s) {
+  if (nq > MD_MAXQ) return hipErrorInvalidValue;
+  const int nb = lz_groups(n);
+  hipLaunchKernelGGL(k_multidot, dim3(MD_BLOCKS, grp().count), dim3(MD_THREADS), 0, s, Q, w, nq, n, part, grp().stride, grp().skip);
+  hipLaunchKernelGGL(k_reorth_second, dim3(nb, grp().count), dim3(256), 0, s, w, Q, part, nq, n, c1, c2, alpha, nrm,
+                     grp().stride, grp().skip);
+  hipLaunchKernelGGL(k_lz_normalize, dim3(nb, grp().count), dim3(256), 0, s, w, nrm, nb, nq - 1, n, c1, beta, tol, stop,
+                     m_eff, qn, stage, grp().stride, grp().skip);
+  return hipGetLastError();
+}
+hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_mark_done, dim3(1, grp().count), dim3(64), 0, s, res, lam, tol, done, grp().stride);
   return hipGetLastError();
 }
 hipError_t zero_int(int* x, int n, hipStream_t s) {

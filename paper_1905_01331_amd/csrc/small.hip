@@ -40,7 +40,9 @@ __global__ void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ ds
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
-__global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n, long long ms_) {
+__global__ void k_copy8(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst, size_t n, long long ms_,
+                        const int* sk = nullptr) {
+  if (member_skipped(sk, ms_)) return;
   src = mshift(src, ms_); dst = mshift(dst, ms_);
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -113,7 +115,9 @@ __device__ double block_sum(double v, double* sh) {
 
 template <typename T>
 __global__ __launch_bounds__(RED_THREADS) void k_pair_partial(const T* __restrict__ X, const T* __restrict__ Y,
-                                                              long long n, double* __restrict__ part, long long ms_) {
+                                                              long long n, double* __restrict__ part, long long ms_,
+                                                              const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   X = mshift(X, ms_); Y = mshift(Y, ms_); part = mshift(part, ms_);
   __shared__ double sh[RED_THREADS];
   double acc = 0.0;
@@ -123,7 +127,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_pair_partial(const T* __restric
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 __global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __restrict__ part, int np,
-                                                              double* __restrict__ out, long long ms_) {
+                                                              double* __restrict__ out, long long ms_, const int* sk) {
+  if (member_skipped(sk, ms_)) return;
   part = mshift(part, ms_); out = mshift(out, ms_);
   __shared__ double sh[RED_THREADS];
   double acc = 0.0;
@@ -317,7 +322,8 @@ hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return hipSuccess;
   if ((bytes % 8 == 0) && ((uintptr_t)dst % 8 == 0) && ((uintptr_t)src % 8 == 0)) {
     size_t n = bytes / 8;
-    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n), grp().count), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, grp().stride);
+    hipLaunchKernelGGL(k_copy8, dim3(grid_for(n), grp().count), dim3(256), 0, s, (const uint64_t*)src, (uint64_t*)dst, n, grp().stride,
+                       grp().skip);
   } else {
     hipLaunchKernelGGL(k_copy, dim3(grid_for(bytes), grp().count), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes, grp().stride);
   }
@@ -359,13 +365,17 @@ hipError_t gaussian_f64(double* x, size_t n, unsigned long long seed, unsigned l
   return hipGetLastError();
 }
 hipError_t pair_f64(const double* X, const double* Y, long long n, double* out, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_partial<double>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride);
+  hipLaunchKernelGGL(k_pair_partial<double>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride,
+                     grp().skip);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride,
+                     grp().skip);
   return hipGetLastError();
 }
 hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pair_partial<float>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride);
+  hipLaunchKernelGGL(k_pair_partial<float>, dim3(RED_BLOCKS, grp().count), dim3(RED_THREADS), 0, s, X, Y, n, part, grp().stride,
+                     grp().skip);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride,
+                     grp().skip);
   return hipGetLastError();
 }
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s) {

@@ -99,6 +99,7 @@ constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO
 // Gram refreshes of the polar update: two always, a third when the second
 // Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
 // diagonal, so the rotated rows may not yet be orthogonal to working accuracy)
+constexpr int LZ_DONE = 8;  // lzint slot of the top solver's per-member convergence flag
 constexpr int POLAR_REFRESH = 2;
 constexpr int POLAR_THIRD_IF = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
@@ -181,7 +182,7 @@ struct Member {
   double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr, *lzStage = nullptr;
   double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
   double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr,
-         *lzpart = nullptr;
+         *lzpart = nullptr, *lznrm = nullptr;
   int* lzint = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
@@ -411,6 +412,7 @@ void layout_member(Member& M, Arena& ar) {
   M.ycoef = ar.take<double>(m + 1);
   M.coef = ar.take<double>(2 * (m + 2));
   M.lzpart = ar.take<double>(lz_reorth_part_doubles());
+  M.lznrm = ar.take<double>(lz_norm_doubles());
   M.lzint = ar.take<int>(16);
   M.scal = ar.take<double>(SCAL_N);
   M.part = ar.take<double>(256);
@@ -429,6 +431,7 @@ hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cl
   GemmDesc gg = g;
   gg.mcount = grp().count;
   gg.mstride = grp().stride;
+  if (!gg.skip) gg.skip = grp().skip;
   if (M.prof && M.prof->on) {
     double es = (p == P_F64) ? 8.0 : 4.0;
     double f = 2.0 * g.M * (double)g.N * g.K * g.batch * gg.mcount;
@@ -905,11 +908,12 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
 // as  stage = [y, y B_1^T, .., y B_D^T, y A_1^T, .., y A_D^T]  (two batched
 // products), then out = [h, A_1..A_D, B_1..B_D] . stage (one product whose
 // contraction index runs over the operator blocks), then out += y h^T.
-hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s) {
+// (staged: y is already in stage[0])
+hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged = false) {
   const int x = M.dims[M.n - 1], D = M.D;
   const long long xx = (long long)x * x;
   hipError_t e;
-  if ((e = copy_bytes(M.lzStage, y, xx * 8, s))) return e;
+  if (!staged && (e = copy_bytes(M.lzStage, y, xx * 8, s))) return e;
   if (D > 0) {
     for (int half = 0; half < 2; ++half) {
       GemmDesc g = desc0();  // stage[1 + half*D + k] = y . (half ? A_k : B_k)^T
@@ -956,31 +960,39 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
   const int m = (int)std::min<long long>(M.krylov, (long long)xx);
   int iters = 0;
   *converged = false;
+  // members of a launch group share the restart loop; a member whose
+  // residual met the target sets its flag and every kernel of its later
+  // restarts returns at once, so it ends with the vector it has alone
+  // (a member alone leaves the loop when it converges: no flag needed)
+  int* done = M.lzint + LZ_DONE;
+  const int* skip = grp().count > 1 ? done : nullptr;
+  HIPCHK(zero_int(done, 1, s));
   for (int rs = 0; rs < M.restarts; ++rs) {
+    SkipScope skip_done(skip);
     // q_0 = v / ||v||
     HIPCHK(pair_f64(M.vtop, M.vtop, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
     HIPCHK(scale_rsqrt(M.vtop, M.scal + SCAL_TMP0, xx, s));
     HIPCHK(copy_bytes(M.lzQ, M.vtop, xx * 8, s));
-    HIPCHK(zero_int(M.lzint, 16, s));
+    HIPCHK(zero_int(M.lzint, 2, s));  // stop, m_eff
     for (int j = 0; j < m; ++j) {
       double* qj = M.lzQ + (size_t)j * xx;
-      HIPCHK(top_matvec(M, qj, M.lzW, s));
+      // q_j is in stage[0] already from the previous step (j > 0)
+      HIPCHK(top_matvec(M, qj, M.lzW, s, j > 0));
       // two passes of classical Gram-Schmidt against q_0..q_j: the first
-      // also yields alpha_j and ||H q_j||^2, the second repairs round-off
+      // also yields alpha_j and ||H q_j||^2, the second repairs round-off;
+      // the second is fused with the recurrence step (alpha_j, beta_j, with
+      // an invariant-subspace test well below the residual target so that a
+      // start vector close to convergence still spans a useful Krylov space,
+      // and q_{j+1}, also staged for the next product)
       double* c1 = M.coef;
       double* c2 = M.coef + (m + 2);
-      HIPCHK(lz_reorth(M.lzW, M.lzQ, j + 1, xx, c1, M.lzpart, s));
-      HIPCHK(lz_reorth(M.lzW, M.lzQ, j + 1, xx, c2, M.lzpart, s));
-      HIPCHK(lz_alpha(c1, c2, j, M.alpha, s));
-      HIPCHK(pair_f64(M.lzW, M.lzW, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
-      // invariant-subspace test well below the residual target, so a start
-      // vector close to convergence still spans a useful Krylov space
-      HIPCHK(lz_set_beta(M.scal + SCAL_TMP0, c1 + (j + 1), M.beta, j, 1e-14, M.lzint, M.lzint + 1, s));
-      HIPCHK(lz_next_q(M.lzW, M.lzQ + (size_t)(j + 1) * xx, M.beta, j, xx, M.lzint, s));
+      HIPCHK(lz_reorth_first(M.lzW, M.lzQ, j + 1, xx, c1, M.lzpart, s));
+      HIPCHK(lz_reorth_final(M.lzW, M.lzQ, j + 1, xx, c1, c2, M.lzpart, M.lznrm, M.alpha, M.beta, 1e-14, M.lzint,
+                             M.lzint + 1, M.lzQ + (size_t)(j + 1) * xx, j + 1 < m ? M.lzStage : nullptr, s));
     }
     iters += m;
     HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
-    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, M.jscratch, s));
+    HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, M.jscratch, s, skip));
     HIPCHK(lz_select_lowest(M.Tm, M.Vm, m, M.ycoef, M.scal + SCAL_THETA, s));
     GemmDesc g = desc0();  // v = Q[0..m-1]^T y
     g.M = 1; g.N = (int)xx; g.K = m;
@@ -995,6 +1007,7 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     HIPCHK(residual_vec(M.lzHv, M.vtop, M.scal + SCAL_LAM, M.lzR, xx, s));
     HIPCHK(pair_f64(M.lzR, M.lzR, (long long)xx, M.scal + SCAL_RES, M.part, s));
     HIPCHK(sqrt_inplace(M.scal + SCAL_RES, s));
+    HIPCHK(lz_mark_done(M.scal + SCAL_RES, M.scal + SCAL_LAM, M.ltol, done, s));
     // every member of the launch group (they share the restarts)
     const int gc = grp().count;
     std::vector<double> hs((size_t)gc * (SCAL_ERR + 1));

@@ -167,10 +167,9 @@ def test_autotuner_keeps_choices_and_replays_them(B):
 def test_launch_groups_match_solo_runs(B):
     # members of equal configuration (L, chi, precision; only h differs) are
     # laid out side by side and run every kernel of a stage as one launch; a
-    # member's arithmetic is the same as alone except that a group shares the
-    # restarts of the top eigensolver (a member that converged earlier runs
-    # extra restarts from its converged vector), so energies agree to the
-    # eigensolver's residual target rather than bit for bit
+    # group shares the restart loop of the top eigensolver, but a member that
+    # has converged sets a device flag and its kernels skip every later
+    # restart, so each member does the arithmetic it does alone
     draws = [(0.8, 128, 48), (1.2, 64, 32), (1.0, 128, 48), (0.6, 128, 48), (1.4, 64, 32)]
     ws = [I.random_isometries(T.layer_shapes(L, 2, chi), 40 + i) for i, (h, L, chi) in enumerate(draws)]
     batch = B.TTN([B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w) for (h, L, chi), w in zip(draws, ws)])
@@ -178,14 +177,14 @@ def test_launch_groups_match_solo_runs(B):
     e_b = batch.energy()
     e_s = np.array([t.energy()[0] for t in solo])
     assert np.abs(e_b - e_s).max() <= 1e-11 * np.abs(e_s).max()
-    for s in range(2):
+    for s in range(3):
         batch.sweep(1, graph=(s > 0))
         for t in solo:
             t.sweep(1)
         e_b = batch.energy()
         e_s = np.array([t.energy()[0] for t in solo])
         print(f"  sweep {s}: max relative difference {np.abs(e_b - e_s).max() / np.abs(e_s).max():.2e}")
-        assert np.abs(e_b - e_s).max() <= 1e-9 * np.abs(e_s).max()
+        assert np.abs(e_b - e_s).max() <= 1e-13 * np.abs(e_s).max()
     for i in range(len(draws)):
         for tau in range(1, batch.n_levels(i)):
             w = batch.get_tensor(tau, i)
