@@ -244,6 +244,27 @@ typedef struct ttn_profile_entry {
 ttn_status ttn_profile(ttn_handle h, int enable);
 ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entries, int* n_out);
 
+/* Entanglement of a block of sites (Sec. V, the entanglement spectrum and
+ * entropy equations): the eigenvalues p_alpha of the reduced density matrix
+ * on the upper bond index of an isometry of layer tau, i.e. of a block of
+ * 2^tau effective sites (tau = 0: one site; tau = n-1: half of the chain),
+ * and S = -sum_alpha p_alpha log2 p_alpha.  The entanglement spectrum is
+ * lambda_alpha = -log2 p_alpha.
+ *   which = TTN_ENT_AVERAGE: the density matrix averaged over the positions
+ *     of layer tau (what the sweep descends; every block of a uniform tree
+ *     hangs from the same map, so this is also the spectrum of the average
+ *     of the blocks' density matrices);
+ *   which = TTN_ENT_LEFTMOST: the block of the first 2^tau sites (at the top
+ *     v v^T, then one level down the left child of the block above, the
+ *     right child traced out).
+ * Computed in float64 from the current isometries and top tensor of member
+ * b (descents, then a Jacobi eigensolver and a sort on the device).
+ * p (host, chi_tau doubles) receives the spectrum in descending order (tiny
+ * negative values are rounding), entropy (host) S.  Synchronises the stream;
+ * does not change the sweep's state. */
+enum { TTN_ENT_AVERAGE = 0, TTN_ENT_LEFTMOST = 1 };
+ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy);
+
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);
 

@@ -19,6 +19,7 @@ TTN_OK, TTN_WRANK, TTN_WNOCONV = 0, 1, 2
 TTN_EINVAL, TTN_ENOMEM, TTN_EHIP, TTN_ENONFINITE, TTN_ENOCONV, TTN_EORTHO, TTN_ESTATE = -1, -2, -3, -4, -5, -6, -7
 TTN_FP64, TTN_FP32, TTN_SPLIT_BF16 = 0, 1, 2
 TTN_DESCEND_RHO, TTN_DESCEND_DRESSED = 0, 1
+TTN_ENT_AVERAGE, TTN_ENT_LEFTMOST = 0, 1
 TTN_TOP = -1
 TTN_OP_H, TTN_OP_A, TTN_OP_B, TTN_OP_RHO, TTN_OP_RBAR, TTN_OP_LBAR, TTN_OP_ENV = range(7)
 PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
@@ -27,7 +28,7 @@ PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
 EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
     "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
-    "ttn_stats", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
+    "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
 ]
 
 
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_last_error": ([], ctypes.c_char_p),
         "ttn_free": ([P], I),
         "ttn_profile": ([P, I], I),
+        "ttn_entanglement": ([P, I, I, I, DP, DP], I),
         "ttn_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
@@ -254,6 +256,14 @@ class TTN:
         _check(self.lib.ttn_profile_read(self.h, arr, 64, ctypes.byref(n)))
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
                                            bytes=arr[i].bytes) for i in range(n.value)}
+
+    def entanglement(self, tau, which=TTN_ENT_AVERAGE, b=0):
+        """(p, S): the spectrum (descending) of the reduced density matrix on
+        an upper bond index of layer tau, and the entropy in bits."""
+        p = np.zeros(max(self.bond_dim(tau, b), 1))  # the library rejects a bad tau
+        S = ctypes.c_double(0.0)
+        _check(self.lib.ttn_entanglement(self.h, b, tau, which, _dptr(p), ctypes.byref(S)))
+        return p, S.value
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -16,6 +16,8 @@ hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, 
 hipError_t running_max(const double* x, double* run_max, hipStream_t s);
 hipError_t identity_f64(double* X, int n, hipStream_t s);
 hipError_t zero_int(int* x, int n, hipStream_t s);
+// p[0..n) = diagonal of G (n x n) in descending order, S[0] = -sum_{p>0} p log2 p
+hipError_t spectrum_sorted(const double* G, int n, double* p, double* S, hipStream_t s);
 // *done = 1 when res[0] <= tol max(1, |lam[0]|)
 hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, hipStream_t s);
 // Full reorthogonalisation against the first nq rows of Q (row length n), in

@@ -322,6 +322,47 @@ __global__ __launch_bounds__(256) void k_lz_normalize(const double* __restrict__
   }
 }
 
+// Spectrum of a density matrix from the diagonal of its Jacobi-diagonalised
+// form (n <= 1024): sorted (bitonic network over 1024 slots, the unused ones
+// holding -inf), written in descending order, and the entropy
+// S = -sum_{p > 0} p log2 p summed in a fixed order.
+__global__ __launch_bounds__(512) void k_spectrum(const double* __restrict__ G, int n, double* __restrict__ p,
+                                                  double* __restrict__ S) {
+  constexpr int N = 1024;
+  __shared__ double v[N];
+  __shared__ double red[512];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += 512) v[i] = i < n ? G[(size_t)i * n + i] : -INFINITY;
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < N; i += 512) {
+        const int l = i ^ j;
+        if (l > i) {
+          const double a = v[i], b = v[l];
+          if (((i & k) == 0) ? (a > b) : (a < b)) {
+            v[i] = b;
+            v[l] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  double acc = 0.0;
+  for (int i = tid; i < n; i += 512) {
+    const double q = v[N - 1 - i];
+    p[i] = q;
+    if (q > 0.0) acc -= q * log2(q);
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int st = 256; st > 0; st >>= 1) {
+    if (tid < st) red[tid] += red[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) S[0] = red[0];
+}
+
 // *done = 1 once ||r|| <= tol max(1, |lambda|) (never cleared here)
 __global__ void k_lz_mark_done(const double* __restrict__ res, const double* __restrict__ lam, double tol,
                                int* __restrict__ done, long long ms_) {
@@ -409,6 +450,11 @@ hipError_t lz_reorth_final(double* w, const double* Q, int nq, size_t n, const d
 }
 hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_lz_mark_done, dim3(1, grp().count), dim3(64), 0, s, res, lam, tol, done, grp().stride);
+  return hipGetLastError();
+}
+hipError_t spectrum_sorted(const double* G, int n, double* p, double* S, hipStream_t s) {
+  if (n < 1 || n > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_spectrum, dim3(1), dim3(512), 0, s, G, n, p, S);
   return hipGetLastError();
 }
 hipError_t zero_int(int* x, int n, hipStream_t s) {

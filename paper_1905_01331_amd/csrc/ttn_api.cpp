@@ -1626,6 +1626,44 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
   return P.dropped ? fail(TTN_OK, "%d launches were not timed (event pool full)", P.dropped) : TTN_OK;
 }
 
+ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy) {
+  if (!h || !p || !entropy || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  if (which != TTN_ENT_AVERAGE && which != TTN_ENT_LEFTMOST) return fail(TTN_EINVAL, "which=%d unknown", which);
+  Member& M = h->c.m[b];
+  const int n = M.n;
+  if (tau < 0 || tau > n - 1) return fail(TTN_EINVAL, "tau=%d outside [0, %d]", tau, n - 1);
+  hipStream_t s = h->c.s;
+  GroupScope one(1, 0);
+  const bool avg = which == TTN_ENT_AVERAGE;
+  const int x = M.dims[n - 1];
+  // float64 throughout (the master isometries), in scratch of the polar
+  // update: rho in G / V in turn, rho o w in Y
+  double* cur = M.G;
+  double* nxt = M.V;
+  HIPCHK(mm(M, P_F64, M.vtop, false, M.vtop, true, cur, x, avg ? 0.5 : 1.0, 0.0, s));  // v v^T
+  if (avg) HIPCHK(mm(M, P_F64, M.vtop, true, M.vtop, false, cur, x, 0.5, 1.0, s));      // + v^T v
+  for (int lv = n - 1; lv > tau; --lv) {
+    const int a = M.dims[lv], bd = M.dims[lv - 1];
+    HIPCHK(left_mul(M, P_F64, cur, M.w64[lv], M.Y, a, bd, 1.0, 0.0, s));
+    HIPCHK(close_l(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, avg ? 0.5 : 1.0, 0.0, s));
+    if (avg) HIPCHK(close_r(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, 0.5, 1.0, s));
+    std::swap(cur, nxt);
+  }
+  const int m = M.dims[tau];
+  HIPCHK(symmetrize_f64(cur, m, 1.0, s));
+  HIPCHK(jacobi_eig_f64(cur, nxt, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 20, m > 64 ? M.jscratch : nullptr, s));
+  HIPCHK(spectrum_sorted(cur, m, M.Y, M.scal + SCAL_TMP2, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(p, M.Y, (size_t)m * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(entropy, M.scal + SCAL_TMP2, sizeof(double), hipMemcpyDeviceToHost));
+  int info[2] = {0, 0};
+  HIPCHK(hipMemcpy(info, M.jinfo + 20, sizeof info, hipMemcpyDeviceToHost));
+  if (info[0] < 0) return fail(TTN_EHIP, "the Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
+  // the scratch held the polar update's temporaries only; the environment
+  // (kept in its own buffers) stays valid
+  return TTN_OK;
+}
+
 int ttn_bond_dim(ttn_handle h, int b, int tau) {
   if (!h || b < 0 || b >= (int)h->c.m.size()) return -1;
   Member& M = h->c.m[b];
