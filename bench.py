@@ -129,6 +129,13 @@ def parse():
     p.add_argument("--no-autotune", action="store_true", help="fixed launch heuristics instead of the autotuner")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
     p.add_argument("--eager", action="store_true", help="no graph replay (every sweep launched eagerly)")
+    p.add_argument("--converge", action="store_true",
+                   help="the paper's 128 x 5 torus (h = 2.9) converged over a ladder of bond dimensions")
+    p.add_argument("--chis", default="32,64,128,256", help="bond dimensions of the --converge ladder")
+    p.add_argument("--tol", type=float, default=1e-10, help="--converge: stop when |delta e| per sweep is below")
+    p.add_argument("--budget", type=float, default=900.0, help="--converge: seconds of sweeps in all")
+    p.add_argument("--polish", type=float, default=0.0,
+                   help="--converge: seconds of float64 sweeps after the last rung (when the ladder ran in another precision)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB elementwise copy (y = -x), the reference of the traffic counters")
     return p.parse_args()
@@ -341,6 +348,115 @@ def measure_batch(B, I, steps, warmup):
     }
 
 
+def converge(B, I, args):
+    """The paper's workload (Sec. V): the 2D transverse-field Ising model on a
+    128 x 5 torus at h = 2.9, one column of 5 spins per effective site
+    (d = 32, D = 5 product terms), swept until the energy per spin changes by
+    less than tol over a sweep, for a ladder of bond dimensions.  Each rung
+    starts from the previous rung's state embedded in the larger bonds (the
+    same state, the added directions at zero weight); the first from seeded
+    random isometries.  Each rung gets a share of the time budget growing
+    with chi.  Reports e(chi), the sweeps and time spent, the last change,
+    and at the largest chi the entanglement entropy S(tau) of the averaged
+    blocks and the first 30 values of the entanglement spectrum of the
+    half-chain block (tau = 6, 64 columns)."""
+    import numpy as np
+    model = I.torus_tfim_column(5, 2.9)
+    L = 128
+    prec = args.precision or "fp64"
+    chis = [int(c) for c in args.chis.split(",")]
+    weights = np.array([float(c) ** 2 for c in chis])
+    shares = args.budget * weights / weights.sum()
+    rungs = []
+    polish = None
+    ws = v = None
+    t_start = time.perf_counter()
+    last = None
+    for chi, share in zip(chis, shares):
+        shapes = I.layer_shapes(L, model.d, chi)
+        if ws is None:
+            w0, v0 = I.random_isometries(shapes, args.seed), None
+        else:
+            w0 = I.embed_isometries(ws, shapes, args.seed + chi)
+            v0 = I.embed_top(v, shapes[-1][0])
+        t = B.TTN(B.ChainInput(model, L, chi, prec, w0=w0, v0=v0))
+        e_prev = float(t.energy()[0])
+        progress(f"chi {chi}: initialised, e {e_prev:.12f}")
+        t0 = time.perf_counter()
+        t_note = t0
+        sweeps, delta, conv = 0, None, False
+        while time.perf_counter() - t0 < share:
+            t.sweep(1, graph=True)
+            sweeps += 1
+            e = float(t.energy()[0])
+            delta = e - e_prev
+            e_prev = e
+            if time.perf_counter() - t_note > 15.0:
+                t_note = time.perf_counter()
+                progress(f"chi {chi}: sweep {sweeps} e {e:.12f} delta {delta:.2e}")
+            if abs(delta) < args.tol:
+                conv = True
+                break
+        el = time.perf_counter() - t0
+        rung = {"chi": chi, "energy_per_spin": e_prev, "sweeps": sweeps, "last_delta": delta,
+                "converged": conv, "seconds": round(el, 2), "ms_per_sweep": round(1e3 * el / max(1, sweeps), 2)}
+        progress(f"chi {chi}: e {e_prev:.12f} after {sweeps} sweeps ({el:.1f} s), converged {conv}")
+        n = t.n_levels()
+        ws = [t.get_tensor(tau) for tau in range(1, n)]
+        v = t.get_tensor(B.TTN_TOP)
+        if prec != "fp64":
+            # the energy of this state in float64 (every layer ascended and the
+            # top problem solved again in float64)
+            r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, v0=v))
+            rung["energy_per_spin_fp64_reeval"] = float(r.energy()[0])
+            r.close()
+        rungs.append(rung)
+        if chi == chis[-1] and args.polish > 0 and prec != "fp64":
+            t.close()
+            del t
+            t = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, v0=v))
+            e_prev = float(t.energy()[0])
+            t0 = t_note = time.perf_counter()
+            sweeps, delta, conv = 0, None, False
+            while time.perf_counter() - t0 < args.polish:
+                t.sweep(1, graph=True)
+                sweeps += 1
+                e = float(t.energy()[0])
+                delta = e - e_prev
+                e_prev = e
+                if time.perf_counter() - t_note > 15.0:
+                    t_note = time.perf_counter()
+                    progress(f"chi {chi} float64: sweep {sweeps} e {e:.12f} delta {delta:.2e}")
+                if abs(delta) < args.tol:
+                    conv = True
+                    break
+            el = time.perf_counter() - t0
+            polish = {"chi": chi, "precision": "fp64", "energy_per_spin": e_prev, "sweeps": sweeps,
+                      "last_delta": delta, "converged": conv, "seconds": round(el, 2)}
+            progress(f"chi {chi} float64: e {e_prev:.12f} after {sweeps} sweeps ({el:.1f} s), converged {conv}")
+            ws = [t.get_tensor(tau) for tau in range(1, n)]
+            v = t.get_tensor(B.TTN_TOP)
+        if chi == chis[-1]:
+            S = [t.entanglement(tau, B.TTN_ENT_AVERAGE)[1] for tau in range(n)]
+            p_half, S_half = t.entanglement(n - 1, B.TTN_ENT_LEFTMOST)
+            pos = p_half[p_half > 0]
+            last = {"entropy_by_tau_average": [round(x, 6) for x in S],
+                    "half_chain_entropy_leftmost": S_half,
+                    "half_chain_spectrum_first30": [round(float(-np.log2(q)), 6) for q in pos[:30]]}
+        t.close()
+        del t
+    print(json.dumps({
+        "metric": "converged energy per spin, 2D TFIM 128 x 5 torus h = 2.9",
+        "value": (polish or rungs[-1])["energy_per_spin"], "unit": "energy per spin", "higher_is_better": False,
+        "n_gpus": 1, "dtype": prec, "data": "synthetic", "tol": args.tol,
+        "seconds_total": round(time.perf_counter() - t_start, 1),
+        "config": {"workload": "2D TFIM torus 128 x 5, h = 2.9 (d = 32 column sites, D = 5)", "L": L,
+                   "chis": chis, "precision": prec, "seed": args.seed},
+        "paper_extrapolated_e_inf": -3.11229,
+        "rungs": rungs, "float64_polish": polish, "entanglement": last,
+    }))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -353,6 +469,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.converge:
+        progress("device ready")
+        B.autotune(0 if args.no_autotune else 1)
+        converge(B, I, args)
+        return
     if args.copy_calibration:
         n = 1 << 28
         x = torch.ones(n, device=dev)

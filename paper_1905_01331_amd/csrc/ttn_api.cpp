@@ -75,6 +75,107 @@ double host_lambda_max(std::vector<double> a, int n) {
   return mx;
 }
 
+// Largest eigenvalue of a larger symmetric matrix (n > 64, e.g. the bond
+// term of a column of 4 to 6 spins): restarted Lanczos with full
+// reorthogonalisation (two Gram-Schmidt passes) from a fixed start vector,
+// the tridiagonal matrix diagonalised by host_lambda_max's Jacobi method
+// through its eigenvectors, until the Ritz residual is below 1e-14 of the
+// matrix scale; returns the Rayleigh quotient of the Ritz vector.
+double host_lambda_max_lanczos(const std::vector<double>& a, int n) {
+  auto matvec = [&](const std::vector<double>& x, std::vector<double>& y) {
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+      const double* row = a.data() + (size_t)i * n;
+      for (int k = 0; k < n; ++k) acc += row[k] * x[k];
+      y[i] = acc;
+    }
+  };
+  auto dot = [&](const std::vector<double>& x, const std::vector<double>& y) {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += x[i] * y[i];
+    return acc;
+  };
+  double scale = 0.0;
+  for (double v : a) scale += v * v;
+  scale = std::sqrt(scale);
+  const int m = std::min(n, 96);
+  std::vector<double> x(n), w(n), r(n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.5 * std::sin(1.0 + i);  // fixed, generic start
+  double theta = 0.0;
+  for (int rs = 0; rs < 40; ++rs) {
+    double nx = std::sqrt(dot(x, x));
+    for (double& v : x) v /= nx;
+    std::vector<std::vector<double>> Q{x};
+    std::vector<double> al, be;
+    for (int j = 0; j < m; ++j) {
+      matvec(Q[j], w);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i <= j; ++i) {
+          const double c = dot(Q[i], w);
+          if (pass == 0 && i == j) al.push_back(c);
+          if (pass == 1 && i == j) al.back() += c;
+          for (int k = 0; k < n; ++k) w[k] -= c * Q[i][k];
+        }
+      const double b = std::sqrt(dot(w, w));
+      if (j + 1 == m || b <= 1e-14 * scale) break;
+      be.push_back(b);
+      for (double& v : w) v /= b;
+      Q.push_back(w);
+    }
+    const int k = (int)al.size();
+    // eigenpairs of the k x k tridiagonal matrix: Jacobi on a copy that also
+    // carries the eigenvectors (rows of the identity rotated alongside)
+    std::vector<double> T((size_t)k * k, 0.0), V((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) {
+      T[(size_t)i * k + i] = al[i];
+      V[(size_t)i * k + i] = 1.0;
+      if (i + 1 < k) T[(size_t)i * k + i + 1] = T[(size_t)(i + 1) * k + i] = be[i];
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+      double off = 0.0, diag = 0.0;
+      for (int p = 0; p < k; ++p)
+        for (int q = 0; q < k; ++q) (p == q ? diag : off) += T[(size_t)p * k + q] * T[(size_t)p * k + q];
+      if (off <= 1e-32 * (diag + off) || off == 0.0) break;
+      for (int p = 0; p < k - 1; ++p)
+        for (int q = p + 1; q < k; ++q) {
+          const double apq = T[(size_t)p * k + q];
+          if (apq == 0.0) continue;
+          const double th = (T[(size_t)q * k + q] - T[(size_t)p * k + p]) / (2.0 * apq);
+          const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+          const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+          for (int u = 0; u < k; ++u) {
+            const double xp = T[(size_t)p * k + u], xq = T[(size_t)q * k + u];
+            T[(size_t)p * k + u] = c * xp - s * xq;
+            T[(size_t)q * k + u] = s * xp + c * xq;
+          }
+          for (int u = 0; u < k; ++u) {
+            const double xp = T[(size_t)u * k + p], xq = T[(size_t)u * k + q];
+            T[(size_t)u * k + p] = c * xp - s * xq;
+            T[(size_t)u * k + q] = s * xp + c * xq;
+          }
+          for (int u = 0; u < k; ++u) {  // eigenvectors as rows of V
+            const double xp = V[(size_t)p * k + u], xq = V[(size_t)q * k + u];
+            V[(size_t)p * k + u] = c * xp - s * xq;
+            V[(size_t)q * k + u] = s * xp + c * xq;
+          }
+        }
+    }
+    int best = 0;
+    for (int i = 1; i < k; ++i)
+      if (T[(size_t)i * k + i] > T[(size_t)best * k + best]) best = i;
+    std::fill(x.begin(), x.end(), 0.0);
+    for (int i = 0; i < k; ++i)
+      for (int u = 0; u < n; ++u) x[u] += V[(size_t)best * k + i] * Q[i][u];
+    nx = std::sqrt(dot(x, x));
+    for (double& v : x) v /= nx;
+    matvec(x, w);
+    theta = dot(x, w);
+    for (int u = 0; u < n; ++u) r[u] = w[u] - theta * x[u];
+    if (std::sqrt(dot(r, r)) <= 1e-14 * std::max(1.0, scale)) break;
+  }
+  return theta;
+}
+
 // ---------------------------------------------------------------------------
 // workspace arena
 // ---------------------------------------------------------------------------
@@ -314,7 +415,7 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
             for (int k = 0; k < D; ++k) v += M.A[(size_t)k * d * d + i1 * d + j1] * M.B[(size_t)k * d * d + i2 * d + j2];
             b[(size_t)(i1 * d + i2) * dd + (j1 * d + j2)] = v;
           }
-    M.c = host_lambda_max(b, dd);
+    M.c = dd <= 64 ? host_lambda_max(b, dd) : host_lambda_max_lanczos(b, dd);
   } else {
     if (!std::isfinite(c.shift)) return fail(TTN_ENONFINITE, "shift is not finite");
     M.c = c.shift;

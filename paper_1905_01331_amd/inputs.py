@@ -125,6 +125,49 @@ def random_isometries(shapes, seed: int):
     return out
 
 
+def layer_shapes(L: int, d: int, chi: int):
+    """[(a, b), ...] of layers 1..n-1 (L = 2**n): bond dimensions chi_0 = d,
+    chi_tau = min(chi_{tau-1}**2, chi)."""
+    n = L.bit_length() - 1
+    dims = [d]
+    for _ in range(1, n):
+        dims.append(min(dims[-1] ** 2, chi))
+    return [(dims[t], dims[t - 1]) for t in range(1, n)]
+
+
+def embed_isometries(ws, shapes, seed: int):
+    """Isometries of larger bond dimensions that represent the same state:
+    each old w (a, b, b) sits in the corner of the new (a', b', b') (zero
+    weight on the added child directions), and the a' - a added rows are a
+    seeded orthonormal complement of the old rows.  With the top tensor
+    embedded the same way (embed_top) the network is the same state and the
+    added directions start with zero weight."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for w, (a2, b2) in zip(ws, shapes):
+        a, b = w.shape[0], w.shape[1]
+        W = np.zeros((a2, b2, b2))
+        W[:a, :b, :b] = w
+        if a2 > a:
+            M = W[:a].reshape(a, -1)
+            g = rng.standard_normal((a2 - a, b2 * b2))
+            g -= (g @ M.T) @ M
+            g -= (g @ M.T) @ M
+            q, r = np.linalg.qr(g.T)
+            s = np.sign(np.diag(r))
+            s[s == 0] = 1.0
+            W[a:] = (q * s[None, :]).T.reshape(a2 - a, b2, b2)
+        out.append(W)
+    return out
+
+
+def embed_top(v, x: int):
+    """The top tensor in the corner of a larger (x, x) one (same state)."""
+    V = np.zeros((x, x))
+    V[:v.shape[0], :v.shape[1]] = v
+    return V
+
+
 def random_top(chi: int, seed: int):
     """Seeded random normalised top tensor (chi x chi)."""
     rng = np.random.default_rng(seed)
