@@ -129,6 +129,8 @@ def parse():
     p.add_argument("--no-autotune", action="store_true", help="fixed launch heuristics instead of the autotuner")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
     p.add_argument("--eager", action="store_true", help="no graph replay (every sweep launched eagerly)")
+    p.add_argument("--evd", action="store_true",
+                   help="the eigenvalue-decomposition variant of the isometry update (one Gram refresh)")
     p.add_argument("--converge", action="store_true",
                    help="the paper's 128 x 5 torus (h = 2.9) converged over a ladder of bond dimensions")
     p.add_argument("--chis", default="32,64,128,256", help="bond dimensions of the --converge ladder")
@@ -188,7 +190,7 @@ def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
                        f"{gpu_sweep_flops / 1e12:.2f} TFLOP by the flop model")}
 
 
-def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True):
+def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True, evd=False):
     """Times K sweeps of one workload after W warm-up sweeps; returns the
     measured fields (and the final energy) as a dict."""
     import torch
@@ -196,7 +198,7 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True
     prec = prec_override or prec_default
     model = build(I)
 
-    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed, evd_update=evd))
     # warm-up: the first sweep runs eagerly (the autotuner times the launch
     # candidates of every product shape it meets), the next one captures the
     # layer part of a sweep into a HIP graph, replayed in the timed sweeps
@@ -486,7 +488,7 @@ def main():
         return
     B.autotune(0 if args.no_autotune else 1)
     m = measure(B, I, args.config, args.precision, args.steps, args.warmup, args.seed, not args.no_fp64_ref,
-                not args.eager)
+                not args.eager, args.evd)
     st = m["stats"]
     secondary = None
     if args.config == DEFAULT_CONFIG and not args.no_secondary:
@@ -523,6 +525,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": m["desc"], "L": m["L"], "chi": m["chi"], "d": m["model"].d, "D": m["model"].D,
                    "levels": int(st.n_levels), "precision": m["prec"], "seed": args.seed,
+                   "update": "evd" if args.evd else "polar",
                    "parallelism": "single GPU"},
         "contraction_tflops": round(m["tflops"], 3),
         "flops_bulk_per_sweep": st.flops_bulk,

@@ -49,7 +49,10 @@ enum {
   TTN_OK = 0,
   TTN_WRANK = 1,        /* an environment was numerically rank deficient
                            (sigma_min/sigma_max < 1e-14): the polar factor is
-                           not unique there and was completed deterministically */
+                           not unique there and was completed
+                           deterministically; or (ttn_energy, evd_update = 1)
+                           an isometry is orthonormal only to the precision
+                           of the squared environment                         */
   TTN_WNOCONV = 2,      /* the top eigensolver stopped at its iteration budget
                            above its residual target                          */
   TTN_EINVAL = -1,      /* invalid argument or configuration                  */
@@ -116,6 +119,13 @@ typedef struct ttn_config {
                          inverse rotation, which leaves the state unchanged
                          and keeps the next environment's Gram matrix nearly
                          diagonal; 1: store -polar(Env) as is              */
+  int evd_update;     /* 0 (default): the polar factor to working accuracy
+                         (Gram refreshes until the rows are orthogonal);
+                         1: the eigenvalue-decomposition variant of the
+                         appendix (Fig. 10(b)): one Gram matrix Env Env^T =
+                         U S^2 U^T and w = -U S^-1 U^T Env, cheaper but with
+                         the precision of the squared environment (relative
+                         errors of order eps (s_max / s_min)^2)              */
 } ttn_config;
 
 /* Bytes of device workspace needed by ttn_init for these configs. */

@@ -338,6 +338,20 @@ def polar_update(env):
     return -(U @ Vt).reshape(env.shape), s
 
 
+def polar_update_evd(env):
+    """The eigenvalue-decomposition variant of the update (appendix,
+    Fig. 10(b)), in w's index shape: G = Env Env^T = U S^2 U^T (a x a,
+    LAPACK syevd) and w = -U S^-1 U^T Env.  The same factor as polar_update
+    in exact arithmetic; squaring Env costs half of the precision (relative
+    errors of order eps (s_max / s_min)^2)."""
+    a = env.shape[0]
+    E = env.reshape(a, -1)
+    s2, U = np.linalg.eigh(E @ E.T)
+    s = np.sqrt(s2)
+    w = -(U @ np.diag(1.0 / s) @ U.T @ E)
+    return w.reshape(env.shape), s[::-1]
+
+
 def level_energy(L, tau, h, B, rho, R, c):
     """E = L_tau [<rho, h> + sum_k <Rbar_k, B_k>] + c L at level tau."""
     L_tau = L >> tau

@@ -40,7 +40,7 @@ class TTNConfig(ctypes.Structure):
         ("precision", ctypes.c_int), ("seed", ctypes.c_ulonglong),
         ("w0", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
         ("v0", ctypes.POINTER(ctypes.c_double)), ("krylov", ctypes.c_int), ("restarts", ctypes.c_int),
-        ("lanczos_tol", ctypes.c_double), ("keep_gauge", ctypes.c_int),
+        ("lanczos_tol", ctypes.c_double), ("keep_gauge", ctypes.c_int), ("evd_update", ctypes.c_int),
     ]
 
 
@@ -121,7 +121,7 @@ class ChainInput:
     """Host-side arrays of one batch member, kept alive for the ctypes config."""
 
     def __init__(self, model, L, chi, precision="fp64", seed=0, w0=None, v0=None, shift=None,
-                 krylov=0, restarts=0, lanczos_tol=0.0, keep_gauge=False):
+                 krylov=0, restarts=0, lanczos_tol=0.0, keep_gauge=False, evd_update=False):
         h1, A, B = model.packed()
         self.h1 = np.ascontiguousarray(h1, dtype=np.float64)
         self.A = np.ascontiguousarray(A, dtype=np.float64)
@@ -147,6 +147,7 @@ class ChainInput:
         cfg.v0 = _dptr(self.v0) if self.v0 is not None else None
         cfg.krylov, cfg.restarts, cfg.lanczos_tol = int(krylov), int(restarts), float(lanczos_tol)
         cfg.keep_gauge = 1 if keep_gauge else 0
+        cfg.evd_update = 1 if evd_update else 0
         self.cfg = cfg
 
 

@@ -256,6 +256,7 @@ struct Member {
   int krylov = 24, restarts = 8;
   double ltol = 1e-12;
   bool gauge_fix = true;
+  bool evd = false;  // one Gram refresh only (the eigenvalue-decomposition variant)
   // batch members run side by side: a Jacobi solve that needs its grid
   // co-resident (the persistent blocked solver) goes through one shared
   // stream, one at a time, and the smaller ones use the one-work-group solver
@@ -369,6 +370,8 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
   M.restarts = c.restarts > 0 ? c.restarts : 8;
   M.ltol = c.lanczos_tol > 0 ? c.lanczos_tol : 1e-12;
   M.gauge_fix = (c.keep_gauge == 0);
+  if (c.evd_update != 0 && c.evd_update != 1) return fail(TTN_EINVAL, "evd_update=%d is neither 0 nor 1", c.evd_update);
+  M.evd = (c.evd_update == 1);
   if (M.krylov > 63) return fail(TTN_EINVAL, "krylov=%d > 63", M.krylov);
   const int d = c.d, D = c.D;
   M.h1.assign(c.h1, c.h1 + d * d);
@@ -864,8 +867,12 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
   // device (the previous Jacobi needed more than POLAR_THIRD_IF sweeps): its
   // kernels read the flag M.skip3 and return at once when it is set, so the
   // whole update has no host synchronisation and can be captured in a graph.
-  for (int it = 0; it <= POLAR_REFRESH; ++it) {
-    const bool extra = it == POLAR_REFRESH;
+  // The eigenvalue-decomposition variant stops after the first refresh:
+  // then P = U, Y = U src and polar(src) = U^T diag(1/|y_i|) U src.
+  const int nref = M.evd ? 1 : POLAR_REFRESH;
+  for (int it = 0; it <= nref; ++it) {
+    const bool extra = it == nref;
+    if (extra && M.evd) break;
     const int* skip = extra ? M.skip3 : nullptr;
     GemmDesc g = desc0();  // G = Y Y^T
     g.M = a; g.N = a; g.K = (int)K;
@@ -916,9 +923,9 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     } else {
       std::swap(Yc, Yn);
     }
-    if (it == POLAR_REFRESH - 1) HIPCHK(set_flag_le(M.skip3, M.jinfo + 2 * it, POLAR_THIRD_IF, s));
+    if (it == nref - 1 && !M.evd) HIPCHK(set_flag_le(M.skip3, M.jinfo + 2 * it, POLAR_THIRD_IF, s));
   }
-  HIPCHK(note_negative_info(M.jinfo, POLAR_REFRESH + 1, M.scal + SCAL_ERR, s));
+  HIPCHK(note_negative_info(M.jinfo, M.evd ? 1 : POLAR_REFRESH + 1, M.scal + SCAL_ERR, s));
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
   if (p_out) {
     // gauge-fixed result: out = sign * Z, the rotation P is handed back
@@ -1139,6 +1146,7 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
 
 ttn_status init_member(Member& M, hipStream_t s, bool* conv) {
   const int n = M.n, d = M.d, D = M.D;
+  HIPCHK(zero_int(M.jinfo, 64, s));  // solver reports read by ttn_stats
   const size_t dd = (size_t)d * d;
   // level-0 operators (host -> device through a float64 staging area)
   std::vector<double> h0 = M.h1;
@@ -1237,7 +1245,7 @@ void layer_flops(const Member& M, double* bulk, double* f64) {
 // device and may differ inside a group).
 std::vector<double> group_key(const Member& M) {
   std::vector<double> k = {(double)M.L, (double)M.d, (double)M.D, (double)M.chi, (double)M.prec, (double)M.ly,
-                           (double)M.krylov, (double)M.restarts, M.ltol, (double)M.gauge_fix};
+                           (double)M.krylov, (double)M.restarts, M.ltol, (double)M.gauge_fix, (double)M.evd};
   for (int a : M.anti) k.push_back((double)a);
   return k;
 }
@@ -1500,7 +1508,7 @@ ttn_status ttn_update(ttn_handle h, int tau) {
 ttn_status ttn_energy(ttn_handle h, double* e) {
   if (!h || !e) return fail(TTN_EINVAL, "bad arguments");
   HIPCHK(hipStreamSynchronize(h->c.s));
-  bool bad = false;
+  bool bad = false, evd_loss = false;
   for (size_t i = 0; i < h->c.m.size(); ++i) {
     double sc[SCAL_N];
     HIPCHK(hipMemcpy(sc, h->c.m[i].scal, sizeof sc, hipMemcpyDeviceToHost));
@@ -1510,9 +1518,13 @@ ttn_status ttn_energy(ttn_handle h, double* e) {
     const Member& M = h->c.m[i];
     const double amax = (double)*std::max_element(M.dims.begin(), M.dims.end());
     const double bound = std::max(1e-10, 64.0 * 2.220446049250313e-16 * amax * std::sqrt(amax));
-    if (!(sc[SCAL_ORTHO_MAX] <= bound)) bad = true;
+    if (!(sc[SCAL_ORTHO_MAX] <= bound)) (M.evd ? evd_loss : bad) = true;
   }
   if (bad) return fail(TTN_EORTHO, "an updated isometry failed the orthonormality check");
+  // the eigenvalue-decomposition update loses orthonormality on purpose where
+  // the environment is ill conditioned: a warning, not an error
+  if (evd_loss) return fail(TTN_WRANK, "an isometry from the eigenvalue-decomposition update is orthonormal only to "
+                                       "the precision of the squared environment");
   return TTN_OK;
 }
 

@@ -346,3 +346,27 @@ def test_entanglement_closed_forms():
     for tau in range(1, len(ws) + 1):
         p, lam, S = T.entanglement(T.rho_leftmost(ws, v, tau))
         assert p[0] == pytest.approx(1.0, abs=1e-14) and S == pytest.approx(0.0, abs=1e-14)
+
+
+# ------------------------------------------- the EVD variant of the update ---
+@pytest.mark.parametrize("cond", [1e1, 1e3, 1e5])
+def test_evd_update_equals_polar_up_to_squared_condition(cond):
+    # an environment with a chosen condition number: the two constructions
+    # give the same factor to about eps cond^2 (the squared environment), and
+    # the SVD route stays at working precision
+    rng = np.random.default_rng(int(cond))
+    a, b = 6, 4
+    U, _ = np.linalg.qr(rng.standard_normal((a, a)))
+    V, _ = np.linalg.qr(rng.standard_normal((b * b, a)))
+    s = np.geomspace(1.0, 1.0 / cond, a)
+    env = (U @ np.diag(s) @ V.T).reshape(a, b, b)
+    w_svd, sv = T.polar_update(env)
+    w_evd, se = T.polar_update_evd(env)
+    exact = -(U @ V.T)
+    eps = np.finfo(np.float64).eps
+    assert np.abs(w_svd.reshape(a, -1) - exact).max() < 100 * eps * cond
+    err = np.abs(w_evd.reshape(a, -1) - exact).max()
+    assert err < 100 * eps * cond ** 2
+    assert np.allclose(se, sv, rtol=1e-6)
+    if cond >= 1e5:  # the loss is visible: far above the SVD route's error
+        assert err > 10 * np.abs(w_svd.reshape(a, -1) - exact).max()
