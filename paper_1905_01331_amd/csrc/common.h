@@ -112,7 +112,8 @@ enum { KID_MFMA = 0,     // + 4 * (mode - 1) + 2 * akc + bkc  (mode 1: float32, 
        KID_MFMA64 = 8,   // + 2 * akc + bkc
        KID_PLAIN = 12,   // + precision
        KID_REDUCE = 15,  // split-K reductions: + 0 float, + 1 double
-       KID_N = 17 };
+       KID_MFMA64S = 17, // + 2 * akc + bkc: the 64 x 64 tile float64 kernel
+       KID_N = 21 };
 const char* kernel_name(int kid);
 
 // Launches one product in the given arithmetic.  F64: double operands and

@@ -409,9 +409,9 @@ __device__ __forceinline__ long long k_offset64(const OpView64& v, int k) {
   return (long long)k1 * v.s_k1 + (long long)(k - k1 * v.K2) * v.s_k;
 }
 
-template <bool KC>
+template <bool KC, int T>
 struct Stage64 {
-  static constexpr int NV = (BM * BK64) / (2 * NT);  // double2 per thread (4)
+  static constexpr int NV = (T * BK64) / (2 * NT);  // double2 per thread (4 at T = 128, 2 at T = 64)
   f64x2 r[NV];
   __device__ __forceinline__ void load(const OpView64& v, int mn0, int k0, int kend, int tid) {
 #pragma unroll
@@ -419,7 +419,7 @@ struct Stage64 {
       int f = tid + i * NT;
       int mn, k;
       if constexpr (KC) { mn = f / (BK64 / 2); k = (f % (BK64 / 2)) * 2; }
-      else              { k = f / (BM / 2); mn = (f % (BM / 2)) * 2; }
+      else              { k = f / (T / 2); mn = (f % (T / 2)) * 2; }
       int gm = mn0 + mn, gk = k0 + k;
       if (gm < v.MN && gk < kend) {
         const double* p = KC ? v.base + (long long)gm * v.s_mn + k_offset64(v, gk) : v.base + gm + k_offset64(v, gk);
@@ -429,7 +429,7 @@ struct Stage64 {
       }
     }
   }
-  __device__ __forceinline__ void store(double (*pl)[BM + 2], int tid) const {
+  __device__ __forceinline__ void store(double (*pl)[T + 2], int tid) const {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int f = tid + i * NT;
@@ -438,18 +438,23 @@ struct Stage64 {
         pl[k][mn] = r[i][0];
         pl[k + 1][mn] = r[i][1];
       } else {
-        int k = f / (BM / 2), mn = (f % (BM / 2)) * 2;
+        int k = f / (T / 2), mn = (f % (T / 2)) * 2;
         *reinterpret_cast<f64x2*>(&pl[k][mn]) = r[i];
       }
     }
   }
 };
 
-template <bool AKC, bool BKC>
+// T x T output tile per 256-thread work-group, 2 x 2 waves of T/2 x T/2 as
+// (T/32) x (T/32) blocks of 16 x 16.  T = 128 for large products; T = 64
+// gives small products four times the work-groups at a quarter of the
+// registers per wave.
+template <bool AKC, bool BKC, int T>
 __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial,
                                                         TileMap tm) {
-  __shared__ double sa_l[BK64][BM + 2];
-  __shared__ double sb_l[BK64][BN + 2];
+  constexpr int NBK = T / 32;  // 16 x 16 blocks per wave and dimension
+  __shared__ double sa_l[BK64][T + 2];
+  __shared__ double sb_l[BK64][T + 2];
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
   {  // launch-group member: outermost index
@@ -461,20 +466,20 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   }
   if (g.skip && gload(g.skip)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+  const int wm = (wave & 1) * (T / 2), wn = (wave >> 1) * (T / 2);
   const int b = bz / splits, sp = bz - b * splits;
-  const int m0 = ty * BM, n0 = tx * BN;
+  const int m0 = ty * T, n0 = tx * T;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
   OpView64 va{(const double*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
   OpView64 vb{(const double*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
-  f64x4 acc[4][4];
+  f64x4 acc[NBK][NBK];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < NBK; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  Stage64<AKC> sa;
-  Stage64<BKC> sb;
+    for (int j = 0; j < NBK; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  Stage64<AKC, T> sa;
+  Stage64<BKC, T> sb;
   if (kbeg < kend) {
     sa.load(va, m0, kbeg, kend, tid);
     sb.load(vb, n0, kbeg, kend, tid);
@@ -489,15 +494,15 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
     }
 #pragma unroll
     for (int kk = 0; kk < BK64; kk += 4) {
-      double a[4], bv[4];
+      double a[NBK], bv[NBK];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sa_l[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < NBK; ++i) a[i] = sa_l[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = sb_l[kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < NBK; ++j) bv[j] = sb_l[kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < NBK; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NBK; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -505,9 +510,9 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   if (splits == 1) {
     double* C = (double*)g.C + batch_offset(g, b, g.sCb, g.sCb2);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NBK; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NBK; ++j) {
         int n = n0 + wn + 16 * j + col_l;
         if (n >= g.N) continue;
 #pragma unroll
@@ -523,9 +528,9 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   } else {
     double* P = partial + ((long long)sp * g.batch + b) * (long long)g.M * g.N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < NBK; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NBK; ++j) {
         int n = n0 + wn + 16 * j + col_l;
         if (n >= g.N) continue;
 #pragma unroll
@@ -538,16 +543,17 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   }
 }
 
-template <bool AKC, bool BKC>
+template <bool AKC, bool BKC, int T>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
-  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
+  const TileMap tm = make_map((g.N + T - 1) / T, (g.M + T - 1) / T, g.batch * splits * gemm_members(g));
   size_t slot = 0;
   KernelTimer* kt = kernel_timer();
   const double work = (double)g.batch * gemm_members(g);
-  const bool timed = kt && kt->begin(KID_MFMA64 + 2 * AKC + BKC, 2.0 * g.M * (double)g.N * g.K * work,
+  const int kid = (T == 128 ? KID_MFMA64 : KID_MFMA64S) + 2 * AKC + BKC;
+  const bool timed = kt && kt->begin(kid, 2.0 * g.M * (double)g.N * g.K * work,
                                      8.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
-  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk, partial,
-                     tm);
+  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC, T>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
+                     partial, tm);
   if (timed) kt->end(slot, s);
   return hipGetLastError();
 }
@@ -588,7 +594,9 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   else     { if (g.M % 2 || g.sAk % 2 || (g.K2 > 0 && g.sAk1 % 2)) return hipErrorNotSupported; }
   if (bkc) { if (g.K % 2 || g.sBn % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sBk1 % 2))) return hipErrorNotSupported; }
   else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
-  long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
+  // small products (few 128 x 128 tiles) take 64 x 64 tiles
+  const int T = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64) ? 64 : 128;
+  long long tiles = (long long)((g.M + T - 1) / T) * ((g.N + T - 1) / T) * g.batch;
   int splits = 1;
   if (tiles < 1024) {
     long long want = (1024 + tiles - 1) / tiles;
@@ -612,10 +620,17 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   if (splits_used) *splits_used = splits;
   double* partial = (double*)scratch;
   hipError_t e;
-  if (akc && bkc) e = launch64<true, true>(g, splits, kchunk, partial, s);
-  else if (akc) e = launch64<true, false>(g, splits, kchunk, partial, s);
-  else if (bkc) e = launch64<false, true>(g, splits, kchunk, partial, s);
-  else e = launch64<false, false>(g, splits, kchunk, partial, s);
+  if (T == 64) {
+    if (akc && bkc) e = launch64<true, true, 64>(g, splits, kchunk, partial, s);
+    else if (akc) e = launch64<true, false, 64>(g, splits, kchunk, partial, s);
+    else if (bkc) e = launch64<false, true, 64>(g, splits, kchunk, partial, s);
+    else e = launch64<false, false, 64>(g, splits, kchunk, partial, s);
+  } else {
+    if (akc && bkc) e = launch64<true, true, 128>(g, splits, kchunk, partial, s);
+    else if (akc) e = launch64<true, false, 128>(g, splits, kchunk, partial, s);
+    else if (bkc) e = launch64<false, true, 128>(g, splits, kchunk, partial, s);
+    else e = launch64<false, false, 128>(g, splits, kchunk, partial, s);
+  }
   if (e != hipSuccess) return e;
   if (splits > 1) return splitk_reduce_f64(g, splits, partial, s);
   return hipSuccess;
