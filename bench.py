@@ -462,8 +462,8 @@ def converge(B, I, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is a design note only)"}))
+        print(json.dumps({"error": "the sweep runs on one GPU; --gpus must be 1 "
+                                   "(sharding over several GPUs is described, not built)"}))
         sys.exit(2)
     import torch
     from paper_1905_01331_amd import binding as B
