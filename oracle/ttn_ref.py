@@ -53,7 +53,11 @@ Pins (tests/test_oracle_*.py): full-chi equality with exact diagonalisation
 (dressed chains), finite differences of a brute-force quartic energy and the
 Euler identity (environment), the polar characterisation (update), residual
 and dense eigensolver agreement (top), closed-form shifts, free-fermion and
-Bethe energies (whole sweep).
+Bethe energies (whole sweep).  The grouped sweep (a schedule of our own, see
+TTNRef.sweep_grouped): brute-force bond energies of every level of the
+one-pass chains, finite differences of every environment taken from them,
+full-chi equality with exact diagonalisation, the fixed point of a converged
+state and the variational bound.
 """
 from __future__ import annotations
 
@@ -316,6 +320,40 @@ def dressed_chain(ws, v, rhos, tau, A_low, B_low):
     return R, Lb
 
 
+def dressed_all(ws, v, rhos, As, Bs):
+    """Rbar^(tau), Lbar^(tau) for every level tau = 1..n-1 in one pass.
+
+    For a state whose operators As, Bs (levels 0..n-1) are all ascended with
+    the current isometries.  The chain of dressed_chain for level tau carries
+    A^(tau-1), B^(tau-1) up through the layers above; when no layer changes
+    in between, the carried operators are the ascended ones, As[sigma] and
+    Bs[sigma], so the descents for all levels are one recursion from the top
+    and a single pass yields every level.  Returns two lists indexed by level
+    (entry 0 unused).
+    """
+    n = len(ws) + 1
+    Rs, Ls = [None] * n, [None] * n
+    R, Lb = dressed_top(v, As[n - 1], Bs[n - 1])
+    Rs[n - 1], Ls[n - 1] = R, Lb
+    for sigma in range(n - 1, 1, -1):
+        R, Lb = descend_dressed(ws[sigma - 1], rhos[sigma], R, Lb, As[sigma - 1], Bs[sigma - 1])
+        Rs[sigma - 1], Ls[sigma - 1] = R, Lb
+    return Rs, Ls
+
+
+def layer_groups(n, groups):
+    """Layers 1..n-1 in the groups of the grouped sweep: one group of every
+    layer (groups = 1), or the odd layers and then the even ones (groups = 2,
+    so that no two neighbouring layers take their environments from the same
+    state)."""
+    layers = list(range(1, n))
+    if groups == 1:
+        return [layers]
+    if groups == 2:
+        return [[t for t in layers if t % 2 == 1], [t for t in layers if t % 2 == 0]]
+    raise ValueError("groups must be 1 or 2")
+
+
 # --------------------------------------------------------------------------
 # environment, update, energy
 # --------------------------------------------------------------------------
@@ -459,6 +497,37 @@ class TTNRef:
             info["ortho"].append(ortho_error(w_new))
             info["sigma_ratio"].append(float(s[-1] / s[0]) if s[0] > 0 else 0.0)
             self.hs[tau], self.As[tau], self.Bs[tau] = ascend(w_new, h, A, B)
+        top = n - 1
+        self.lam, self.v = top_eigen(self.hs[top], self.As[top], self.Bs[top], v0=self.v)
+        self.history.append(self.energy_per_site())
+        self.diag.append(info)
+        return self.energy_per_site()
+
+    def sweep_grouped(self, groups):
+        """One sweep in which every layer of a group takes its environment
+        from the same state (a schedule of our own, not the paper's: the
+        dressed chains of a group come from one pass, dressed_all, instead of
+        one chain per layer).  Per group: descend rho, one pass of the dressed
+        chains, the environment and the polar update of every layer of the
+        group, then ascend every layer; after the last group the top tensor.
+        Returns the energy per site after it."""
+        n = self.n
+        info = {"ortho": [], "sigma_ratio": []}
+        for members in layer_groups(n, groups):
+            if not members:
+                continue
+            rhos = descend_rho_all(self.ws, self.v)
+            Rs, Ls = dressed_all(self.ws, self.v, rhos, self.As, self.Bs)
+            new = list(self.ws)
+            for tau in members:
+                w = self.ws[tau - 1]
+                env = environment(w, self.hs[tau - 1], self.As[tau - 1], self.Bs[tau - 1], rhos[tau],
+                                  Rs[tau], Ls[tau])
+                new[tau - 1], s = polar_update(env)
+                info["ortho"].append(ortho_error(new[tau - 1]))
+                info["sigma_ratio"].append(float(s[-1] / s[0]) if s[0] > 0 else 0.0)
+            self.ws = new
+            self.hs, self.As, self.Bs = ascend_all(self.ws, self.h0, self.A0, self.B0)
         top = n - 1
         self.lam, self.v = top_eigen(self.hs[top], self.As[top], self.Bs[top], v0=self.v)
         self.history.append(self.energy_per_site())

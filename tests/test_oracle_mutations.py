@@ -41,6 +41,13 @@ def _pins_hold():
                     return False
                 if abs((L >> tau) * T.pair(Lb[k], r.As[tau][k]) - bf) > 1e-10:
                     return False
+            Rs, Ls = T.dressed_all(r.ws, v, rhos, r.As, r.Bs)
+            for k in range(model.D):
+                bf = P.bond_expectation_sum(psi_t, r.As[tau][k], r.Bs[tau][k])
+                if abs((L >> tau) * T.pair(Rs[tau][k], r.Bs[tau][k]) - bf) > 1e-10:
+                    return False
+                if abs((L >> tau) * T.pair(Ls[tau][k], r.As[tau][k]) - bf) > 1e-10:
+                    return False
             w = r.ws[tau - 1]
             env = T.environment(w, r.hs[tau - 1], r.As[tau - 1], r.Bs[tau - 1], rhos[tau], R, Lb)
             e_bond = (L >> tau) * sum(T.pair(x, y) for x, y in zip(R, r.Bs[tau]))
@@ -75,9 +82,21 @@ MUTATIONS = {
     "environment drops Lbar term": ("environment", lambda w, h, A, B, rho, R, Lb: T.left_mul(rho, T.s_apply(w, h, A, B)) + sum((T.left_mul(r, T.apply_l(b, w)) for b, r in zip(B, R)), np.zeros_like(w))),
     "update keeps the singular values": ("polar_update", lambda env: _svd_variant(env, keep_s=True)),
     "update drops the left factor": ("polar_update", lambda env: _svd_variant(env, drop_u=True)),
+    "one-pass chain carries Lbar as Rbar": ("dressed_all", lambda ws, v, rhos, As, Bs: _dressed_all_swapped(ws, v, rhos, As, Bs)),
     "s_apply B on the left child": ("s_apply", lambda w, h, A, B: T.apply_l(h, w) + T.apply_r(h, w) + sum((T.apply_r(a, T.apply_l(b, w)) for a, b in zip(A, B)), np.zeros_like(w))),
 }
 _ORIG = {}
+
+
+def _dressed_all_swapped(ws, v, rhos, As, Bs):
+    n = len(ws) + 1
+    Rs, Ls = [None] * n, [None] * n
+    R, Lb = T.dressed_top(v, As[n - 1], Bs[n - 1])
+    Rs[n - 1], Ls[n - 1] = R, Lb
+    for sigma in range(n - 1, 1, -1):
+        R, Lb = T.descend_dressed(ws[sigma - 1], rhos[sigma], Lb, R, As[sigma - 1], Bs[sigma - 1])
+        Rs[sigma - 1], Ls[sigma - 1] = R, Lb
+    return Rs, Ls
 
 
 def _svd_variant(env, keep_s=False, drop_u=False):

@@ -209,6 +209,94 @@ def test_environment_finite_differences_and_euler(model):
         assert L_tau * T.pair(w, env) == pytest.approx(e_shift + e_bond, abs=1e-11)
 
 
+# ------------------------------------------------ grouped-sweep chains ----
+@pytest.mark.parametrize("model", [I.tfim_chain(0.8), I.xxx_chain(), I.torus_tfim_column(3, 2.0)])
+def test_dressed_all_bruteforce(model):
+    """One top-down pass of the dressed chains for a fully ascended state:
+    every level's Rbar and Lbar give the brute-force bond energies of that
+    level's state vector."""
+    L = 16 if model.d == 2 else 8
+    chi = 6 if model.d == 2 else 10
+    r = make(model, L, chi, seed=4)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 3)
+    rhos = T.descend_rho_all(r.ws, v)
+    Rs, Ls = T.dressed_all(r.ws, v, rhos, r.As, r.Bs)
+    for tau in range(1, r.n):
+        psi = P.level_state(r.ws, v, tau)
+        L_tau = L >> tau
+        for k in range(model.D):
+            bf = P.bond_expectation_sum(psi, r.As[tau][k], r.Bs[tau][k])
+            assert L_tau * T.pair(Rs[tau][k], r.Bs[tau][k]) == pytest.approx(bf, abs=1e-12)
+            assert L_tau * T.pair(Ls[tau][k], r.As[tau][k]) == pytest.approx(bf, abs=1e-12)
+
+
+@pytest.mark.parametrize("model", [I.tfim_chain(0.7), I.xxx_chain()])
+def test_grouped_environments_finite_differences(model):
+    """The environments of every layer, all from the one-pass chains, are the
+    derivatives of the brute-force level energy (finite differences) and
+    satisfy the Euler identity."""
+    L, chi = 16, 6
+    r = make(model, L, chi, seed=6)
+    r.initialise()
+    v = I.random_top(r.dims[-1], 8)
+    rhos = T.descend_rho_all(r.ws, v)
+    Rs, Ls = T.dressed_all(r.ws, v, rhos, r.As, r.Bs)
+    rng = np.random.default_rng(1)
+    for tau in range(1, r.n):
+        w = r.ws[tau - 1]
+        h, A, B = r.hs[tau - 1], r.As[tau - 1], r.Bs[tau - 1]
+        env = T.environment(w, h, A, B, rhos[tau], Rs[tau], Ls[tau])
+        psi_tau = P.level_state(r.ws, v, tau)
+        L_tau = L >> tau
+        Dw = rng.standard_normal(w.shape)
+        eps = 1e-4
+        fd = (_quartic_energy(w + eps * Dw, psi_tau, h, A, B)
+              - _quartic_energy(w - eps * Dw, psi_tau, h, A, B)) / (2 * eps)
+        assert 2 * L_tau * T.pair(env, Dw) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+        e_shift = _quartic_energy(w, psi_tau, h, A, B)
+        e_bond = L_tau * sum(T.pair(x, y) for x, y in zip(Rs[tau], r.Bs[tau]))
+        assert L_tau * T.pair(w, env) == pytest.approx(e_shift + e_bond, abs=1e-11)
+
+
+@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("name,model,L,chi,key", [
+    ("tfim8", I.tfim_chain(1.0), 8, 16, "tfim_chain_L8_h1"),
+    ("xxx16", I.xxx_chain(), 16, 256, "xxx_chain_L16"),
+])
+def test_grouped_sweep_full_chi_equals_ed(name, model, L, chi, key, groups):
+    r = make(model, L, chi, seed=1)
+    r.initialise()
+    exact = GOLD[key] / L
+    for _ in range(2):
+        assert r.sweep_grouped(groups) == pytest.approx(exact, abs=1e-10)
+
+
+def test_grouped_sweep_fixed_point_and_variational():
+    """A state converged by the paper's sweep is a fixed point of the grouped
+    sweeps (every layer already equals minus the polar factor of its own
+    environment); from a random start the grouped sweeps stay above the
+    exact ground energy."""
+    model, L, chi = I.tfim_chain(1.0), 16, 4
+    r = make(model, L, chi, seed=2)
+    r.run(400, tol=1e-14)
+    e_conv = r.history[-1]
+    for groups in (1, 2):
+        q = make(model, L, chi, seed=2)
+        q.ws = [w.copy() for w in r.ws]
+        q.initialise()
+        assert q.history[0] == pytest.approx(e_conv, abs=1e-12)
+        for _ in range(3):
+            assert abs(q.sweep_grouped(groups) - e_conv) < 1e-9
+    exact = GOLD["tfim_chain_L16_h1"] / L
+    for groups in (1, 2):
+        q = make(model, L, 8, seed=5)
+        q.initialise()
+        hist = [q.sweep_grouped(groups) for _ in range(6)]
+        assert min(hist) >= exact - 1e-12
+        assert hist[-1] < q.history[0]
+
+
 # --------------------------------------------------------------- update ----
 def test_polar_update_characterisation():
     rng = np.random.default_rng(3)
