@@ -188,6 +188,24 @@ ttn_status ttn_energy(ttn_handle h, double* e_per_site);
  * graph. */
 ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
 
+/* nsweeps grouped sweeps: a schedule of our own beside the paper's (the
+ * update of Sec. III.B, the sweep of Sec. IV).  The layers are split into
+ * groups (groups = 1: every layer; groups = 2: the odd layers, then the even
+ * ones); every layer of a group takes its environment from the same state.
+ * With nothing changed in between, the operators that a layer's dressed chain
+ * carries up are the ascended operators themselves, so one top-down pass
+ * yields the two-site information of every level: per group, descend(RHO),
+ * one pass of the chains with env and update of the group's layers on the
+ * way down, then every layer is ascended again; after the last group,
+ * update(TOP).  The dressed chains take one pass per group, against one
+ * chain per layer in ttn_sweep.  groups = 1 updates neighbouring
+ * layers from the same state and may raise the energy of strongly coupled
+ * models; groups = 2 keeps neighbours apart.  Batches run member groups one
+ * after another on the handle's stream (no graph).  TTN_EINVAL for groups
+ * outside {1, 2}; TTN_ESTATE when a level's operators are stale; otherwise as
+ * ttn_sweep. */
+ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups);
+
 /* Checkpoint / parity access to the float64 master tensors of member b:
  * tau in 1..n-1 selects w_tau (chi_tau*chi_{tau-1}^2 doubles), tau == TTN_TOP
  * selects v (chi_{n-1}^2 doubles).  set_tensor invalidates every cached

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": TTN_FP64, "fp32": TTN_FP32, "bf16x3": TTN_SPLIT_BF16}
 # Every symbol declared in include/ttn.h.
 EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
-    "ttn_energy", "ttn_sweep", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
+    "ttn_energy", "ttn_sweep", "ttn_sweep_grouped", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
 ]
 
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_update": ([P, I], I),
         "ttn_energy": ([P, DP], I),
         "ttn_sweep": ([P, I, I], I),
+        "ttn_sweep_grouped": ([P, I, I], I),
         "ttn_autotune": ([I, ctypes.POINTER(ctypes.c_int)], I),
         "ttn_get_tensor": ([P, I, I, DP], I),
         "ttn_set_tensor": ([P, I, I, DP], I),
@@ -210,6 +211,9 @@ class TTN:
 
     def sweep(self, nsweeps=1, graph=False):
         return _check(self.lib.ttn_sweep(self.h, nsweeps, 1 if graph else 0))
+
+    def sweep_grouped(self, nsweeps=1, groups=2):
+        return _check(self.lib.ttn_sweep_grouped(self.h, nsweeps, groups))
 
     # access -----------------------------------------------------------------
     def bond_dim(self, tau, b=0):

@@ -743,6 +743,54 @@ ttn_status stage_descend_rho(Member& M, hipStream_t s) {
   return TTN_OK;
 }
 
+// Two-site information at the top from the carried operators At, Bt of level
+// n-1: Rbar = 1/2 (v^T A v + v A v^T), Lbar = 1/2 (v B v^T + v^T B v), into
+// slot 0 of the double buffer.
+ttn_status dressed_top(Member& M, const void* At, const void* Bt, hipStream_t s) {
+  Prec p = M.gp();
+  const int n = M.n, D = M.D;
+  const int x = M.dims[n - 1];
+  const long long xx = (long long)x * x;
+  void* R = M.Rb[0];
+  void* Lq = M.Lb[0];
+  HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // A v
+  HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, R, xx, x, 0.5, 0.0, D, s));    // v^T A v
+  HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // A v^T
+  HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, R, xx, x, 0.5, 1.0, D, s));   // v A v^T
+  HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // B v^T
+  HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, Lq, xx, x, 0.5, 0.0, D, s));  // v B v^T
+  HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // B v
+  HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));   // v^T B v
+  M.rb_cur = 0;
+  return TTN_OK;
+}
+
+// Rbar, Lbar one level down through layer sg (level sg -> sg-1), all k at
+// once; Alow, Blow are the carried operators of level sg-1.  Needs the cached
+// P = rho^(sg) o w_sg.
+ttn_status dressed_down(Member& M, int sg, const void* Alow, const void* Blow, hipStream_t s) {
+  Prec p = M.gp();
+  const int D = M.D;
+  const int a = M.dims[sg], b = M.dims[sg - 1];
+  const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
+  const void* w = M.wT[sg];
+  const void* P = M.Pc[sg];
+  const int cur = M.rb_cur, nx = 1 - cur;
+  void* Rn = M.Rb[nx];
+  void* Ln = M.Lb[nx];
+  // inside a parent (A left child, B right child) + across parents
+  HIPCHK(apply_l_k(M, p, Alow, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+  HIPCHK(close_r_k(M, p, P, 0, M.S2, cube, Rn, bb, a, b, 0.5, 0.0, D, s));
+  HIPCHK(left_mul_k(M, p, M.Rb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
+  HIPCHK(close_l_k(M, p, w, 0, M.S3, cube, Rn, bb, a, b, 0.5, 1.0, D, s));
+  HIPCHK(apply_r_k(M, p, Blow, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
+  HIPCHK(close_l_k(M, p, P, 0, M.S2, cube, Ln, bb, a, b, 0.5, 0.0, D, s));
+  HIPCHK(left_mul_k(M, p, M.Lb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
+  HIPCHK(close_r_k(M, p, w, 0, M.S3, cube, Ln, bb, a, b, 0.5, 1.0, D, s));
+  M.rb_cur = nx;
+  return TTN_OK;
+}
+
 ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
   Prec p = M.gp();
   const int n = M.n, D = M.D;
@@ -760,45 +808,11 @@ ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
     prevA = M.At[sg];
     prevB = M.Bt[sg];
   }
-  // top dressing: Rbar = 1/2 (v^T A v + v A v^T), Lbar = 1/2 (v B v^T + v^T B v)
-  const int x = M.dims[n - 1];
-  const long long xx = (long long)x * x;
-  int cur = 0;
-  {
-    const void* At = M.At[n - 1];
-    const void* Bt = M.Bt[n - 1];
-    void* R = M.Rb[cur];
-    void* Lq = M.Lb[cur];
-    HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // A v
-    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, R, xx, x, 0.5, 0.0, D, s));    // v^T A v
-    HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // A v^T
-    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, R, xx, x, 0.5, 1.0, D, s));   // v A v^T
-    HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // B v^T
-    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, Lq, xx, x, 0.5, 0.0, D, s));  // v B v^T
-    HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // B v
-    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));   // v^T B v
-  }
-  // descend through layers n-1 .. tau+1 (all k at once)
-  for (int sg = n - 1; sg >= tau + 1; --sg) {
-    const int a = M.dims[sg], b = M.dims[sg - 1];
-    const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
-    const void* w = M.wT[sg];
-    const void* P = M.Pc[sg];
-    const int nx = 1 - cur;
-    void* Rn = M.Rb[nx];
-    void* Ln = M.Lb[nx];
-    // inside a parent (A left child, B right child) + across parents
-    HIPCHK(apply_l_k(M, p, M.At[sg - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-    HIPCHK(close_r_k(M, p, P, 0, M.S2, cube, Rn, bb, a, b, 0.5, 0.0, D, s));
-    HIPCHK(left_mul_k(M, p, M.Rb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
-    HIPCHK(close_l_k(M, p, w, 0, M.S3, cube, Rn, bb, a, b, 0.5, 1.0, D, s));
-    HIPCHK(apply_r_k(M, p, M.Bt[sg - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-    HIPCHK(close_l_k(M, p, P, 0, M.S2, cube, Ln, bb, a, b, 0.5, 0.0, D, s));
-    HIPCHK(left_mul_k(M, p, M.Lb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
-    HIPCHK(close_r_k(M, p, w, 0, M.S3, cube, Ln, bb, a, b, 0.5, 1.0, D, s));
-    cur = nx;
-  }
-  M.rb_cur = cur;
+  ttn_status st;
+  if ((st = dressed_top(M, M.At[n - 1], M.Bt[n - 1], s))) return st;
+  // descend through layers n-1 .. tau+1
+  for (int sg = n - 1; sg >= tau + 1; --sg)
+    if ((st = dressed_down(M, sg, M.At[sg - 1], M.Bt[sg - 1], s))) return st;
   M.dressed_tau = tau;
   return TTN_OK;
 }
@@ -1287,6 +1301,41 @@ ttn_status sweep_layers(Member& M, hipStream_t s) {
   return TTN_OK;
 }
 
+// The layer part of one grouped sweep (a schedule of our own, not the
+// paper's): every layer of a group takes its environment from the same state,
+// so the dressed chains of all of them come from one top-down pass over the
+// ascended operators (the carried operators of a layer's own chain are those
+// when nothing changes in between).  Groups: every layer (groups = 1), or the
+// odd layers and then the even ones (groups = 2).  Per group: rho, then from
+// the top down, for each level: the environment of its layer when the layer
+// is in the group, the chains one level down (which still read the old
+// isometry), the update; then every layer is ascended again.  A gauge-fixed
+// update moves its rotation into the layer above (or v), already updated in
+// this pass: the state is the same.
+ttn_status sweep_layers_grouped(Member& M, int groups, hipStream_t s) {
+  const int n = M.n;
+  ttn_status st;
+  for (int gi = 0; gi < groups; ++gi) {
+    const int parity = gi == 0 ? 1 : 0;
+    bool any = false;
+    for (int t = 1; t < n; ++t) any |= groups == 1 || t % 2 == parity;
+    if (!any) continue;
+    if ((st = stage_descend_rho(M, s))) return st;
+    if ((st = dressed_top(M, M.opA[n - 1], M.opB[n - 1], s))) return st;
+    for (int sg = n - 1; sg >= 1; --sg) {
+      const bool upd = groups == 1 || sg % 2 == parity;
+      if (upd && (st = stage_env(M, sg, s))) return st;
+      if (sg > 1 && (st = dressed_down(M, sg, M.opA[sg - 1], M.opB[sg - 1], s))) return st;
+      if (upd && (st = stage_update_layer(M, sg, s))) return st;
+    }
+    for (int t = 1; t < n; ++t)
+      if ((st = stage_ascend(M, t, s))) return st;
+    M.ops_upto = n - 1;
+  }
+  M.dressed_tau = -1;
+  return TTN_OK;
+}
+
 // The layer part for the whole batch: one member runs on the caller's
 // stream; a batch forks to the pool streams (member i on stream i mod P) and
 // joins back.  No host synchronisation inside: capturable.
@@ -1559,6 +1608,29 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
     } else {
       if ((st = sweep_layers_all(c, c.s))) return st;
     }
+    st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
+      bool conv = false;
+      ttn_status r = stage_update_top(M, c.s, &conv);
+      if (!r && !conv) warn = TTN_WNOCONV;
+      return r;
+    });
+    if (st) return st;
+  }
+  return warn;
+}
+
+ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups) {
+  if (!h || nsweeps < 0) return fail(TTN_EINVAL, "bad arguments");
+  if (groups != 1 && groups != 2) return fail(TTN_EINVAL, "groups = %d, must be 1 or 2", groups);
+  Ctx& c = h->c;
+  ttn_status warn = TTN_OK;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (auto& M : c.m)
+      if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "sweep needs every layer ascended");
+    ttn_status st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
+      return sweep_layers_grouped(M, groups, c.s);
+    });
+    if (st) return st;
     st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
       bool conv = false;
       ttn_status r = stage_update_top(M, c.s, &conv);

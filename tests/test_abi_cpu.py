@@ -102,3 +102,9 @@ def test_zero_hamiltonian_and_unit_bond_dimension_are_accepted(lib):
     assert _bytes(zero, 32, 3, shift=1.0) > 0
     assert _bytes(inputs.tfim_chain(1.3), 8, 1) > 0
     assert _bytes(inputs.tfim_chain(1.0), 4, 2) > 0
+
+
+def test_grouped_sweep_rejects_a_null_handle(lib):
+    # argument checks run before any device call
+    assert lib.ttn_sweep_grouped(None, 1, 2) == binding.TTN_EINVAL
+    assert lib.ttn_sweep_grouped(None, 1, 3) == binding.TTN_EINVAL

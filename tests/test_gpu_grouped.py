@@ -1,0 +1,168 @@
+"""Grouped sweeps (ttn_sweep_grouped) on the GPU path against the CPU
+reference's TTNRef.sweep_grouped, from identical states.
+
+Anchored parity: before every sweep the reference's isometries and top tensor
+are loaded into the handle, then one grouped sweep runs on both sides and
+the energies are compared (bar eps / (10 r) with r the smallest
+sigma_min / sigma_max among the environments of the sweep, as for the
+paper's sweep); with the gauge kept, the updated isometries are compared
+element by element, each to a bar that follows its own environment's
+conditioning.  Also: exact energies at full bond dimension, launch groups
+against the same members run alone, a split-bf16 run against its float64
+re-evaluation, and argument errors.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import physics_ref as P
+from oracle import ttn_ref as T
+from paper_1905_01331_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "ed_energies.json")) as f:
+    GOLD = json.load(f)
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_1905_01331_amd import binding
+    binding.load_library()
+    return binding
+
+
+# (name, model, L, chi, sweeps): ragged chi across several tiles, the
+# antisymmetric XXX terms, a d = 8 torus column, and bonds above 64 (the
+# blocked Jacobi of the polar update)
+CASES = [
+    ("tfim_L64_chi12", I.tfim_chain(1.0), 64, 12, 3),
+    ("xxx_L32_chi20", I.xxx_chain(), 32, 20, 3),
+    ("torus8x3_chi24", I.torus_tfim_column(3, 3.0), 8, 24, 2),
+    ("xxx_L32_chi80", I.xxx_chain(), 32, 80, 2),
+]
+
+
+def _layer_order(n, groups):
+    return [t for grp in T.layer_groups(n, groups) for t in grp]
+
+
+@pytest.mark.parametrize("keep_gauge", [True, False], ids=["plain", "gauge_fixed"])
+@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("name,model,L,chi,sweeps", CASES, ids=[c[0] for c in CASES])
+def test_anchored_grouped_sweep_parity(B, name, model, L, chi, sweeps, groups, keep_gauge):
+    print(f"[grouped parity] {name} groups={groups} keep_gauge={keep_gauge}", flush=True)
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 7)
+    ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
+    ref.initialise()
+    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, keep_gauge=keep_gauge))
+    n = ref.n
+    order = _layer_order(n, groups)
+    for s in range(sweeps):
+        for tau in range(1, n):
+            gpu.set_tensor(tau, ref.ws[tau - 1])
+        gpu.set_tensor(B.TTN_TOP, ref.v)
+        gpu.ascend(1, n - 1)
+        gpu.sweep_grouped(1, groups)
+        e_gpu = gpu.energy()[0]
+        e_ref = ref.sweep_grouped(groups)
+        ratios = ref.diag[-1]["sigma_ratio"]
+        r = float(np.min(ratios))
+        d = abs(e_gpu - e_ref) / abs(e_ref)
+        tol = max(1e-10, EPS / (10.0 * r))
+        print(f"  sweep {s}: relative difference {d:.3e}, sigma_min/sigma_max {r:.2e}, bar {tol:.1e}")
+        assert d <= tol
+        if keep_gauge:
+            for tau, rt in zip(order, ratios):
+                diff = float(np.abs(gpu.get_tensor(tau) - ref.ws[tau - 1]).max())
+                bar = max(1e-10, 1e-13 / rt)
+                assert diff <= bar, f"layer {tau}: {diff:.2e} > {bar:.1e}"
+    assert gpu.stats().ortho_err_max < 1e-12
+    gpu.close()
+
+
+@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("name,model,L,chi,key", [
+    ("tfim8", I.tfim_chain(1.0), 8, 16, "tfim_chain_L8_h1"),
+    ("torus4x3", I.torus_tfim_column(3, 3.0), 4, 64, "torus_tfim_4x3_h3"),
+])
+def test_grouped_full_bond_dimension_is_exact(B, name, model, L, chi, key, groups):
+    print(f"[grouped] full chi {name} groups={groups}", flush=True)
+    t = B.TTN(B.ChainInput(model, L, chi, "fp64", seed=3, restarts=40))
+    exact = GOLD[key] / (L * model.ly)
+    scale = max(abs(exact), abs(t.stats().shift) / model.ly)
+    for _ in range(2):
+        t.sweep_grouped(1, groups)
+        assert abs(t.energy()[0] - exact) <= 1e-10 * scale
+    t.close()
+
+
+def test_grouped_launch_groups_match_members_alone(B):
+    # three members of one configuration (one launch per kernel) and one of
+    # another, against the same four run alone
+    draws = [(0.8, 128, 24), (1.2, 128, 24), (1.0, 128, 24), (0.9, 64, 16)]
+    ws = [I.random_isometries(T.layer_shapes(L, 2, chi), 60 + i) for i, (_, L, chi) in enumerate(draws)]
+    batch = B.TTN([B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w) for (h, L, chi), w in zip(draws, ws)])
+    solo = [B.TTN(B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w)) for (h, L, chi), w in zip(draws, ws)]
+    for s in range(3):
+        batch.sweep_grouped(1, 2)
+        for t in solo:
+            t.sweep_grouped(1, 2)
+        e_b = batch.energy()
+        e_s = np.array([t.energy()[0] for t in solo])
+        d = np.abs(e_b - e_s) / np.abs(e_s)
+        print(f"  sweep {s}: relative differences {d}")
+        assert d.max() <= 1e-13
+    for i, (h, L, _) in enumerate(draws):
+        assert e_b[i] >= P.tfim_free_fermion_energy(L, h) / L - 1e-12
+    batch.close()
+    for t in solo:
+        t.close()
+
+
+def test_grouped_split_bf16_against_float64_reevaluation(B):
+    # the energy that a split-bf16 handle reports for its state against the
+    # float64 evaluation of that state (its isometries and top tensor loaded
+    # into a float64 handle); the bar is the one of the paper's sweep
+    model, L, chi = I.xxx_chain(), 256, 48
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 8)
+    t = B.TTN(B.ChainInput(model, L, chi, "bf16x3", w0=ws))
+    c = t.stats().shift
+    n = t.n_levels()
+    e, err = [t.energy()[0]], []
+    for _ in range(4):
+        t.sweep_grouped(1, 2)
+        e.append(t.energy()[0])
+        state = [t.get_tensor(tau) for tau in range(1, n)]
+        f = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=t.get_tensor(B.TTN_TOP)))
+        e64 = f.energy()[0]
+        f.close()
+        err.append(abs(e[-1] - e64) / max(abs(e64), abs(c) / model.ly))
+    print(f"  energies {e}, error against the float64 evaluation {err}")
+    assert max(err) < 2e-5
+    assert e[-1] < e[0]
+    t.close()
+
+
+def test_grouped_rejects_bad_arguments(B):
+    t = B.TTN(B.ChainInput(I.tfim_chain(1.0), 16, 8, "fp64", seed=1))
+    for g in (0, 3, -1):
+        with pytest.raises(B.TTNError) as e:
+            t.sweep_grouped(1, g)
+        assert e.value.status == B.TTN_EINVAL
+    with pytest.raises(B.TTNError) as e:
+        t.sweep_grouped(-1, 2)
+    assert e.value.status == B.TTN_EINVAL
+    # a changed layer leaves the operators above it stale
+    t.set_tensor(2, t.get_tensor(2))
+    with pytest.raises(B.TTNError) as e:
+        t.sweep_grouped(1, 2)
+    assert e.value.status == B.TTN_ESTATE
+    t.close()
