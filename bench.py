@@ -138,6 +138,9 @@ def parse():
     p.add_argument("--budget", type=float, default=900.0, help="--converge: seconds of sweeps in all")
     p.add_argument("--polish", type=float, default=0.0,
                    help="--converge: seconds of float64 sweeps after the last rung (when the ladder ran in another precision)")
+    p.add_argument("--schedules", action="store_true",
+                   help="energy against time from one start: the paper's sweep and the grouped sweeps "
+                        "(--budget seconds each)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB elementwise copy (y = -x), the reference of the traffic counters")
     return p.parse_args()
@@ -459,6 +462,63 @@ def converge(B, I, args):
     }))
 
 
+def schedules(B, I, args):
+    """The paper's bottom-up sweep against the grouped sweeps (every layer of
+    a group takes its environment from one state; groups of two: odd layers,
+    then even ones), from the same seeded start on one workload, each for
+    the same wall-clock budget.  Reports the time per sweep, the energy per
+    site after every sweep (with its time), and the time each schedule needs
+    to reach the final energy of the paper's sweep."""
+    import numpy as np
+    make, L, chi, prec0, desc = CONFIGS[args.config]
+    model = make(I)
+    prec = args.precision or prec0
+    ws = I.random_isometries(I.layer_shapes(L, model.d, chi), args.seed)
+    # the launch tuner sees every product shape once before the clocks start
+    t = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    t.sweep(1)
+    t.sweep_grouped(1, 2)
+    t.close()
+    del t
+    progress("launch tuner warmed up")
+    runs = {}
+    for name, step in (("sequential", lambda t: t.sweep(1, graph=True)),
+                       ("grouped2", lambda t: t.sweep_grouped(1, 2)),
+                       ("grouped1", lambda t: t.sweep_grouped(1, 1))):
+        t = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+        e0 = float(t.energy()[0])
+        trace = [(0.0, e0)]
+        per = []
+        t0 = t_note = time.perf_counter()
+        while time.perf_counter() - t0 < args.budget:
+            a = time.perf_counter()
+            step(t)
+            e = float(t.energy()[0])
+            b = time.perf_counter()
+            per.append(b - a)
+            trace.append((round(b - t0, 4), e))
+            if b - t_note > 15.0:
+                t_note = b
+                progress(f"{name}: sweep {len(per)} e {e:.12f}")
+        progress(f"{name}: {len(per)} sweeps, e {trace[-1][1]:.12f}")
+        runs[name] = {"sweeps": len(per), "ms_per_sweep_median": round(1e3 * float(np.median(per)), 2),
+                      "ms_per_sweep_first": round(1e3 * per[0], 2), "energy_final": trace[-1][1],
+                      "trace": trace}
+        t.close()
+        del t
+    target = runs["sequential"]["energy_final"]
+    for r in runs.values():
+        hit = [tt for tt, e in r["trace"] if e <= target]
+        r["seconds_to_sequential_final"] = hit[0] if hit else None
+    print(json.dumps({
+        "metric": "energy per site against wall time, paper's sweep vs grouped sweeps",
+        "unit": "energy per site", "higher_is_better": False, "n_gpus": 1, "dtype": prec, "data": "synthetic",
+        "budget_seconds_each": args.budget,
+        "config": {"workload": desc, "L": L, "chi": chi, "precision": prec, "seed": args.seed},
+        "runs": runs,
+    }))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -475,6 +535,11 @@ def main():
         progress("device ready")
         B.autotune(0 if args.no_autotune else 1)
         converge(B, I, args)
+        return
+    if args.schedules:
+        progress("device ready")
+        B.autotune(0 if args.no_autotune else 1)
+        schedules(B, I, args)
         return
     if args.copy_calibration:
         n = 1 << 28
