@@ -166,3 +166,29 @@ def test_grouped_rejects_bad_arguments(B):
         t.sweep_grouped(1, 2)
     assert e.value.status == B.TTN_ESTATE
     t.close()
+
+
+def test_grouped_sweep_at_full_size(B):
+    # the XXX chain at L = 4096, chi = 256 in split-bf16, the workload of the
+    # speed measurements: two red-black sweeps from a seeded start lower the
+    # energy, keep the isometries orthonormal, and report the energy of their
+    # state to the split-bf16 bar of its float64 evaluation
+    model, L, chi = I.xxx_chain(), 4096, 256
+    print("[grouped] full size", flush=True)
+    t = B.TTN(B.ChainInput(model, L, chi, "bf16x3", seed=0))
+    c = t.stats().shift
+    e0 = t.energy()[0]
+    t.sweep_grouped(2, 2)
+    e2 = t.energy()[0]
+    n = t.n_levels()
+    assert e2 < e0
+    assert t.stats().ortho_err_max < 64 * EPS * 256 ** 1.5
+    state = [t.get_tensor(tau) for tau in range(1, n)]
+    v = t.get_tensor(B.TTN_TOP)
+    t.close()
+    f = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=v))
+    e64 = f.energy()[0]
+    f.close()
+    err = abs(e2 - e64) / max(abs(e64), abs(c))
+    print(f"  e {e0:.10f} -> {e2:.10f}, float64 evaluation {e64:.10f}, error {err:.2e}")
+    assert err < 2e-5
