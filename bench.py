@@ -483,8 +483,8 @@ def schedules(B, I, args):
     progress("launch tuner warmed up")
     runs = {}
     for name, step in (("sequential", lambda t: t.sweep(1, graph=True)),
-                       ("grouped2", lambda t: t.sweep_grouped(1, 2)),
-                       ("grouped1", lambda t: t.sweep_grouped(1, 1))):
+                       ("grouped2", lambda t: t.sweep_grouped(1, 2, graph=True)),
+                       ("grouped1", lambda t: t.sweep_grouped(1, 1, graph=True))):
         t = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
         e0 = float(t.energy()[0])
         trace = [(0.0, e0)]

@@ -200,11 +200,13 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
  * update(TOP).  The dressed chains take one pass per group, against one
  * chain per layer in ttn_sweep.  groups = 1 updates neighbouring
  * layers from the same state and may raise the energy of strongly coupled
- * models; groups = 2 keeps neighbours apart.  Batches run member groups one
- * after another on the handle's stream (no graph).  TTN_EINVAL for groups
- * outside {1, 2}; TTN_ESTATE when a level's operators are stale; otherwise as
- * ttn_sweep. */
-ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups);
+ * models; groups = 2 keeps neighbours apart.  Batches run their launch groups
+ * one after another on the handle's stream.  use_graph != 0: the layer part
+ * is captured into a HIP graph (one per grouping) on the first such call and
+ * replayed, as in ttn_sweep; results are identical with and without it.
+ * TTN_EINVAL for groups outside {1, 2}; TTN_ESTATE when a level's operators
+ * are stale; otherwise as ttn_sweep. */
+ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_graph);
 
 /* Checkpoint / parity access to the float64 master tensors of member b:
  * tau in 1..n-1 selects w_tau (chi_tau*chi_{tau-1}^2 doubles), tau == TTN_TOP

@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_update": ([P, I], I),
         "ttn_energy": ([P, DP], I),
         "ttn_sweep": ([P, I, I], I),
-        "ttn_sweep_grouped": ([P, I, I], I),
+        "ttn_sweep_grouped": ([P, I, I, I], I),
         "ttn_autotune": ([I, ctypes.POINTER(ctypes.c_int)], I),
         "ttn_get_tensor": ([P, I, I, DP], I),
         "ttn_set_tensor": ([P, I, I, DP], I),
@@ -212,8 +212,8 @@ class TTN:
     def sweep(self, nsweeps=1, graph=False):
         return _check(self.lib.ttn_sweep(self.h, nsweeps, 1 if graph else 0))
 
-    def sweep_grouped(self, nsweeps=1, groups=2):
-        return _check(self.lib.ttn_sweep_grouped(self.h, nsweeps, groups))
+    def sweep_grouped(self, nsweeps=1, groups=2, graph=False):
+        return _check(self.lib.ttn_sweep_grouped(self.h, nsweeps, groups, 1 if graph else 0))
 
     # access -----------------------------------------------------------------
     def bond_dim(self, tau, b=0):

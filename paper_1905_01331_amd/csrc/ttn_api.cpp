@@ -317,6 +317,9 @@ struct Ctx {
   // every member), replayed by ttn_sweep(.., use_graph = 1)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // captured layer part of a grouped sweep, one per grouping (1 or 2 groups)
+  hipGraph_t ggraph[2] = {nullptr, nullptr};
+  hipGraphExec_t ggexec[2] = {nullptr, nullptr};
   std::vector<hipStream_t> pool;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -335,6 +338,10 @@ struct Ctx {
     if (kernel_timer() == &krec) kernel_timer() = nullptr;
     if (gexec) hipGraphExecDestroy(gexec);
     if (graph) hipGraphDestroy(graph);
+    for (int i = 0; i < 2; ++i) {
+      if (ggexec[i]) hipGraphExecDestroy(ggexec[i]);
+      if (ggraph[i]) hipGraphDestroy(ggraph[i]);
+    }
     for (auto e : join) hipEventDestroy(e);
     if (fork) hipEventDestroy(fork);
     for (auto e : member_events) hipEventDestroy(e);
@@ -1619,7 +1626,19 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
   return warn;
 }
 
-ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups) {
+// The layer part of a grouped sweep for the whole batch: launch groups one
+// after another on stream s (no host synchronisation: capturable).
+ttn_status grouped_layers_all(Ctx& c, int groups, hipStream_t s) {
+  for (auto& G : c.groups) {
+    GroupScope gs((int)G.members.size(), G.stride);
+    ttn_status st = sweep_layers_grouped(c.m[G.members[0]], groups, s);
+    if (st) return st;
+    sync_group_state(c, G);
+  }
+  return TTN_OK;
+}
+
+ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_graph) {
   if (!h || nsweeps < 0) return fail(TTN_EINVAL, "bad arguments");
   if (groups != 1 && groups != 2) return fail(TTN_EINVAL, "groups = %d, must be 1 or 2", groups);
   Ctx& c = h->c;
@@ -1627,10 +1646,29 @@ ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups) {
   for (int sw = 0; sw < nsweeps; ++sw) {
     for (auto& M : c.m)
       if (M.ops_upto < M.n - 1) return fail(TTN_ESTATE, "sweep needs every layer ascended");
-    ttn_status st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
-      return sweep_layers_grouped(M, groups, c.s);
-    });
-    if (st) return st;
+    ttn_status st;
+    if (use_graph && !c.prof.on) {
+      hipGraphExec_t& ge = c.ggexec[groups - 1];
+      if (!ge) {
+        // captured as for ttn_sweep: the host bookkeeping runs once here, the
+        // graph holds only device work, identical every sweep
+        if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
+        st = grouped_layers_all(c, groups, c.cap_s);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c.cap_s, &g);
+        if (st) {
+          if (g) hipGraphDestroy(g);
+          return st;
+        }
+        HIPCHK(e);
+        c.ggraph[groups - 1] = g;
+        HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+      }
+      HIPCHK(hipGraphLaunch(ge, c.s));
+    } else {
+      if ((st = grouped_layers_all(c, groups, c.s))) return st;
+    }
     st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
       bool conv = false;
       ttn_status r = stage_update_top(M, c.s, &conv);

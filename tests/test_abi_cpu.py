@@ -106,5 +106,5 @@ def test_zero_hamiltonian_and_unit_bond_dimension_are_accepted(lib):
 
 def test_grouped_sweep_rejects_a_null_handle(lib):
     # argument checks run before any device call
-    assert lib.ttn_sweep_grouped(None, 1, 2) == binding.TTN_EINVAL
-    assert lib.ttn_sweep_grouped(None, 1, 3) == binding.TTN_EINVAL
+    assert lib.ttn_sweep_grouped(None, 1, 2, 0) == binding.TTN_EINVAL
+    assert lib.ttn_sweep_grouped(None, 1, 3, 1) == binding.TTN_EINVAL

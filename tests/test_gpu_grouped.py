@@ -151,6 +151,40 @@ def test_grouped_split_bf16_against_float64_reevaluation(B):
     t.close()
 
 
+@pytest.mark.parametrize("groups", [1, 2])
+def test_grouped_graph_replays_match_eager(B, groups):
+    # the captured layer part of a grouped sweep replays the eager sweep bit
+    # for bit, with eager work between replays, and reads the workspace at
+    # replay time (a state loaded between sweeps is honoured)
+    model, L, chi = I.xxx_chain(), 64, 24
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 13)
+    eager = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    graph = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    for s in range(4):
+        eager.sweep_grouped(1, groups)
+        graph.sweep_grouped(1, groups, graph=True)
+        e0, e1 = eager.energy()[0], graph.energy()[0]
+        assert e0 == e1, f"sweep {s}: eager {e0!r} graph {e1!r}"
+    n = eager.n_levels()
+    state = [eager.get_tensor(tau) for tau in range(1, n)]
+    v = eager.get_tensor(B.TTN_TOP)
+    for h in (eager, graph):
+        for tau in range(1, n):
+            h.set_tensor(tau, state[tau - 1])
+        h.set_tensor(B.TTN_TOP, v)
+        h.ascend(1, n - 1)
+    eager.sweep_grouped(1, groups)
+    graph.sweep_grouped(1, groups, graph=True)
+    assert eager.energy()[0] == graph.energy()[0]
+    assert np.array_equal(eager.get_tensor(n - 1), graph.get_tensor(n - 1))
+    # the paper's sweep and the grouped sweep keep separate graphs
+    graph.sweep(1, graph=True)
+    eager.sweep(1)
+    assert eager.energy()[0] == graph.energy()[0]
+    eager.close()
+    graph.close()
+
+
 def test_grouped_rejects_bad_arguments(B):
     t = B.TTN(B.ChainInput(I.tfim_chain(1.0), 16, 8, "fp64", seed=1))
     for g in (0, 3, -1):
