@@ -10,9 +10,12 @@ sweeps bracketed by device synchronisation.  Prints ONE JSON line.
 
 The default workload is the Heisenberg chain L = 4096 at chi = 256 in
 split-bf16; the 64 x 4 torus at chi = 128 is measured in the same run and
-reported under "chi128", and 128 independent TFIM chains (seeded L, h, chi)
+reported under "chi128", 128 independent TFIM chains (seeded L, h, chi)
 swept together in one handle under "batch128", next to the same chains
-swept one at a time.  For each single chain, the line carries:
+swept one at a time, and the grouped sweep (odd layers, then even layers,
+each group's environments from one state; not the paper's schedule) of the
+default workload from the same start under "grouped_schedule".  For each
+single chain, the line carries:
   * sweeps/s and the algorithmic contraction TFLOP/s;
   * the energy per site after the timed sweeps, the float64 re-evaluation of
     that same state (its isometries and top tensor loaded into a float64
@@ -274,6 +277,35 @@ def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True
         "stats": st, "energy": e, "e_re": e_re, "err_re": err_re, "e64": e64, "err": err,
         "roofline": roofline, "classes": classes, "kernels": kernels,
     }
+
+
+def measure_grouped(B, I, name, steps, warmup, seed, e_paper):
+    """The grouped sweep (odd layers, then even layers, each group's
+    environments from one state) on the same workload from the same seeded
+    start: K timed sweeps after W warm-up sweeps, then K more, so that the
+    energy is read after as many sweeps as the paper's schedule had."""
+    import torch
+    build, L, chi, prec, desc = CONFIGS[name]
+    model = build(I)
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
+    t.sweep_grouped(1, 2)
+    for _ in range(max(1, warmup) - 1):
+        t.sweep_grouped(1, 2, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.sweep_grouped(1, 2, graph=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t.sweep_grouped(steps, 2, graph=True)
+    e = float(t.energy()[0])
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    progress(f"{name}: grouped sweeps done ({1e3 * elapsed / steps:.2f} ms per sweep)")
+    return {"schedule": "grouped sweep, odd layers then even layers (ttn_sweep_grouped, groups = 2)",
+            "sweeps_per_s": round(steps / elapsed, 4), "ms_per_step": round(1e3 * elapsed / steps, 3),
+            "energy_per_site_after_same_sweeps": e, "paper_schedule_energy_after_same_sweeps": e_paper}
 
 
 def measure_batch(B, I, steps, warmup):
@@ -568,8 +600,11 @@ def main():
         }
 
     batch = None
+    grouped = None
     if args.config == DEFAULT_CONFIG and not args.no_secondary:
         batch = measure_batch(B, I, args.steps, args.warmup)
+        if not args.evd and args.precision is None:
+            grouped = measure_grouped(B, I, args.config, args.steps, args.warmup, args.seed, m["energy"])
 
     cpu = None
     if not args.no_cpu:
@@ -610,6 +645,7 @@ def main():
         "autotune_entries": B.autotune(-1),
         "chi128": secondary,
         "batch128": batch,
+        "grouped_schedule": grouped,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
