@@ -48,6 +48,9 @@ CONFIGS = {
     "torus64x4": (lambda I: I.torus_tfim_column(4, 3.0), 64, 128, "bf16x3",
                   "2D TFIM 64x4 torus h=3 (d=16 column sites) chi=128"),
     "xxx4096": (lambda I: I.xxx_chain(), 4096, 256, "bf16x3", "Heisenberg XXX chain L=4096 chi=256"),
+    # the paper's workload (Sec. V) at one rung of its bond-dimension ladder
+    "torus128x5": (lambda I: I.torus_tfim_column(5, 2.9), 128, 64, "fp32",
+                   "2D TFIM 128x5 torus h=2.9 (d=32 column sites) chi=64"),
 }
 DEFAULT_CONFIG = "xxx4096"
 SECONDARY_CONFIG = "torus64x4"
