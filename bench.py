@@ -140,6 +140,9 @@ def parse():
     p.add_argument("--converge", action="store_true",
                    help="the paper's 128 x 5 torus (h = 2.9) converged over a ladder of bond dimensions")
     p.add_argument("--chis", default="32,64,128,256", help="bond dimensions of the --converge ladder")
+    p.add_argument("--schedule", default="sequential", choices=["sequential", "grouped1", "grouped2"],
+                   help="--converge: the paper's sweep, or the grouped sweep with all layers (grouped1) or odd "
+                        "then even layers (grouped2) as its groups")
     p.add_argument("--tol", type=float, default=1e-10, help="--converge: stop when |delta e| per sweep is below")
     p.add_argument("--budget", type=float, default=900.0, help="--converge: seconds of sweeps in all")
     p.add_argument("--polish", type=float, default=0.0,
@@ -407,6 +410,12 @@ def converge(B, I, args):
     chis = [int(c) for c in args.chis.split(",")]
     weights = np.array([float(c) ** 2 for c in chis])
     shares = args.budget * weights / weights.sum()
+    def step(t):
+        if args.schedule == "sequential":
+            t.sweep(1, graph=True)
+        else:
+            t.sweep_grouped(1, 1 if args.schedule == "grouped1" else 2, graph=True)
+
     rungs = []
     polish = None
     ws = v = None
@@ -426,7 +435,7 @@ def converge(B, I, args):
         t_note = t0
         sweeps, delta, conv = 0, None, False
         while time.perf_counter() - t0 < share:
-            t.sweep(1, graph=True)
+            step(t)
             sweeps += 1
             e = float(t.energy()[0])
             delta = e - e_prev
@@ -459,7 +468,7 @@ def converge(B, I, args):
             t0 = t_note = time.perf_counter()
             sweeps, delta, conv = 0, None, False
             while time.perf_counter() - t0 < args.polish:
-                t.sweep(1, graph=True)
+                step(t)
                 sweeps += 1
                 e = float(t.energy()[0])
                 delta = e - e_prev
@@ -491,7 +500,7 @@ def converge(B, I, args):
         "n_gpus": 1, "dtype": prec, "data": "synthetic", "tol": args.tol,
         "seconds_total": round(time.perf_counter() - t_start, 1),
         "config": {"workload": "2D TFIM torus 128 x 5, h = 2.9 (d = 32 column sites, D = 5)", "L": L,
-                   "chis": chis, "precision": prec, "seed": args.seed},
+                   "chis": chis, "precision": prec, "seed": args.seed, "schedule": args.schedule},
         "paper_extrapolated_e_inf": -3.11229,
         "rungs": rungs, "float64_polish": polish, "entanglement": last,
     }))
