@@ -40,6 +40,7 @@ struct JcCtl {
   int pad[2];
   int cnt[256];    // rotations per sweep
   int rnd[64];     // rotations per round index, summed over sweeps
+  int need[256];   // set when some pair met the rotation test before a sweep
 };
 
 // Block pair j of round r (rounds 0 .. nb-2: circle method; round nb-1:
@@ -246,6 +247,30 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   };
 
   for (int sw = 0; sw < max_sweeps && alive; ++sw) {
+    // A sweep rotates nothing exactly when no pair meets the rotation test
+    // on the current matrix (which then stays as it is), so test every pair
+    // first: the sweep that would only confirm convergence is not run, and
+    // G, U and the sweep count come out as they would after it.  Both
+    // triangles are tested, as a sub-problem may read either copy of an
+    // off-diagonal entry (the two can differ by rounding).
+    {
+      int need = 0;
+      const long long nn = (long long)n * n;
+      for (long long e = (long long)blockIdx.x * NT + tid; e < nn; e += (long long)gridDim.x * NT) {
+        const int i = (int)(e / n), j = (int)(e - (long long)i * n);
+        if (j == i) continue;
+        const double gpq = G[e];
+        const double gpp = G[(long long)i * n + i], gqq = G[(long long)j * n + j];
+        if (gpq != 0.0 && gpq * gpq > tol * tol * fabs(gpp * gqq)) need = 1;
+      }
+      need = __syncthreads_or(need);
+      if (tid == 0 && need) atomicOr(&ctl->need[sw], 1);
+    }
+    if (!jc_grid_sync(ctl, target, &ok_lds)) { alive = false; break; }
+    if (__hip_atomic_load(&ctl->need[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      sweeps = sw;
+      break;
+    }
     for (int r = 0; r < nb; ++r) {
       const bool cross = r < nb - 1;
       const int nsteps = cross ? BK : BK - 1;
