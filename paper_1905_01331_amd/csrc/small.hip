@@ -194,7 +194,9 @@ constexpr int JAC_THREADS = 1024;
 constexpr int JAC_MAXN = 1024;
 
 // MODE 0: G and U in global memory; 1: G copied into dynamic LDS; 2: G and U
-// both in dynamic LDS (copied back at the end).
+// both in dynamic LDS (copied back at the end).  The rotations of a round
+// (c, s, t and the index pair, n/2 of each) follow the matrices in the
+// dynamic LDS, sized for n.
 template <int MODE>
 __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg, double* __restrict__ Vg, int n,
                                                         int max_sweeps, double tol, int* info, const int* skip, long long ms_) {
@@ -205,14 +207,18 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(double* __restrict__ Gg,
   }
   extern __shared__ double dyn[];
   constexpr bool LDS = MODE >= 1;
+  const int N = n + (n & 1);   // even number of players; index n is a dummy when n is odd
+  const int npair = N / 2;
+  const long long mats = (long long)MODE * n * n;  // doubles of matrices in LDS
   double* V = (MODE == 2) ? dyn + (long long)n * n : Vg;
-  __shared__ double cs[JAC_MAXN / 2], sn[JAC_MAXN / 2], tn[JAC_MAXN / 2];
-  __shared__ int pp[JAC_MAXN / 2], qq[JAC_MAXN / 2];
+  double* cs = dyn + mats;
+  double* sn = cs + npair;
+  double* tn = sn + npair;
+  int* pp = reinterpret_cast<int*>(tn + npair);
+  int* qq = pp + npair;
   __shared__ int rot_count;
   const int tid = threadIdx.x;
   double* G = LDS ? dyn : Gg;
-  const int N = n + (n & 1);   // even number of players; index n is a dummy when n is odd
-  const int npair = N / 2;
   for (long long i = tid; i < (long long)n * n; i += blockDim.x) {
     int r = (int)(i / n), c = (int)(i - (long long)r * n);
     V[i] = (r == c) ? 1.0 : 0.0;
@@ -391,7 +397,7 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
                           hipStream_t s, const int* skip) {
   if (n > JAC_MAXN) return hipErrorInvalidValue;
   if (n > 64 && scratch) return jacobi_eig_blocked_f64(G, V, n, max_sweeps, tol, info, scratch, s, skip);
-  // the matrix goes to LDS when it fits next to the static rotation tables
+  // the matrices go to LDS when they fit there with a round's rotations
   static int lds_limit = -1;
   if (lds_limit < 0) {
     int dev = 0, v = 0;
@@ -402,21 +408,21 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
       if (hipDeviceGetAttribute(&o, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess && o > lds_limit)
         lds_limit = o;
     }
-    const int static_lds = (JAC_MAXN / 2) * (3 * 8 + 2 * 4) + 16;
-    lds_limit -= static_lds;
+    lds_limit -= 16;  // static: the rotation counter
     if (lds_limit > 0 &&
         (hipFuncSetAttribute((const void*)k_jacobi<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess ||
          hipFuncSetAttribute((const void*)k_jacobi<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_limit) != hipSuccess))
       lds_limit = 0;
     (void)hipGetLastError();
   }
-  size_t bytes = (size_t)n * n * sizeof(double);
-  if (lds_limit > 0 && 2 * bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<2>, dim3(1, grp().count), dim3(JAC_THREADS), 2 * bytes, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
-  } else if (lds_limit > 0 && bytes <= (size_t)lds_limit) {
-    hipLaunchKernelGGL(k_jacobi<1>, dim3(1, grp().count), dim3(JAC_THREADS), bytes, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  const size_t rot = (size_t)((n + 1) / 2) * (3 * sizeof(double) + 2 * sizeof(int));  // a round's rotations
+  if (lds_limit > 0 && 2 * bytes + rot <= (size_t)lds_limit) {
+    hipLaunchKernelGGL(k_jacobi<2>, dim3(1, grp().count), dim3(JAC_THREADS), 2 * bytes + rot, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
+  } else if (lds_limit > 0 && bytes + rot <= (size_t)lds_limit) {
+    hipLaunchKernelGGL(k_jacobi<1>, dim3(1, grp().count), dim3(JAC_THREADS), bytes + rot, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
   } else {
-    hipLaunchKernelGGL(k_jacobi<0>, dim3(1, grp().count), dim3(JAC_THREADS), 0, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
+    hipLaunchKernelGGL(k_jacobi<0>, dim3(1, grp().count), dim3(JAC_THREADS), rot, s, G, V, n, max_sweeps, tol, info, skip, grp().stride);
   }
   return hipGetLastError();
 }
