@@ -5,8 +5,9 @@
   any sweep) is the exact ground energy (values from exact
   diagonalisation, tests/golden).
 * The shortest chain (L = 4: one isometry layer and the top), bond
-  dimension one (a product state) and a bond dimension below the site
-  dimension, against the reference, sweep by sweep from identical states.
+  dimension one (a product state), a bond dimension below the site
+  dimension and deep trees (18 and 20 levels), against the reference, sweep
+  by sweep from identical states.
 * The zero Hamiltonian with an explicit shift: every site term is -c, the
   environment is -2 rho w, and with full-rank rho the polar update returns
   the isometry unchanged; the energy is exactly zero.
@@ -79,6 +80,10 @@ SMALL = [
     ("xxx_L4_chi3", I.xxx_chain(), 4, 3, 3),
     ("tfim_L8_chi1", I.tfim_chain(1.3), 8, 1, 3),
     ("torus8x3_chi4", I.torus_tfim_column(3, 3.0), 8, 4, 3),
+    # deep trees: 18 and 20 levels (2^18 and 2^20 sites; the energy scale
+    # grows with L, the bar is relative)
+    ("tfim_L262144_chi6_deep", I.tfim_chain(1.0), 1 << 18, 6, 2),
+    ("xxx_L1048576_chi4_deep", I.xxx_chain(), 1 << 20, 4, 2),
 ]
 
 
