@@ -13,8 +13,9 @@
 // Rutishauser diagonal updates), which yields an orthogonal R and the
 // rotated sub-matrix S' = R G_sub R^T; phase B replaces every block of G
 // between two index sets X, Y of the round by R_X G[X,Y] R_Y^T (S' on the
-// diagonal) and the rows X of the eigenvector matrix U by R_X U[X,:].  A
-// sweep with no rotation ends the iteration.
+// diagonal) and the rows X of the eigenvector matrix U by R_X U[X,:].  The
+// iteration ends when no pair meets the rotation test: every pair is tested
+// before a sweep, so the sweep that would rotate nothing is not run.
 //
 // The whole iteration is ONE launch of a persistent grid: its work-groups
 // share phase A (one block pair each) and phase B (one block of G or one
