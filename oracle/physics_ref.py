@@ -162,3 +162,32 @@ def chain_operator_expectation(psi_sites, h, A, B):
     for a_k, b_k in zip(A, B):
         total += bond_expectation_sum(psi_sites, a_k, b_k)
     return total
+
+
+def site_expectations(psi_sites, h):
+    """<h_j> for every site j, brute force."""
+    out = []
+    for j in range(psi_sites.ndim):
+        phi = np.moveaxis(np.tensordot(h, psi_sites, axes=([1], [j])), 0, j)
+        out.append(float(np.sum(psi_sites * phi)))
+    return np.array(out)
+
+
+def bond_expectations(psi_sites, A, B):
+    """sum_k <A_{k,j} B_{k,j+1}> for every j (periodic), brute force."""
+    k = psi_sites.ndim
+    out = np.zeros(k)
+    for a_k, b_k in zip(A, B):
+        for j in range(k):
+            jn = (j + 1) % k
+            phi = np.moveaxis(np.tensordot(a_k, psi_sites, axes=([1], [j])), 0, j)
+            phi = np.moveaxis(np.tensordot(b_k, phi, axes=([1], [jn])), 0, jn)
+            out[j] += float(np.sum(psi_sites * phi))
+    return out
+
+
+def one_site_rdm(psi_sites, j):
+    """Reduced density matrix of site j, brute force."""
+    other = [i for i in range(psi_sites.ndim) if i != j]
+    return np.tensordot(psi_sites, psi_sites, axes=(other, other))
+

@@ -57,7 +57,10 @@ Bethe energies (whole sweep).  The grouped sweep (a schedule of our own, see
 TTNRef.sweep_grouped): brute-force bond energies of every level of the
 one-pass chains, finite differences of every environment taken from them,
 full-chi equality with exact diagonalisation, the fixed point of a converged
-state and the variational bound.
+state and the variational bound.  Position-resolved matrices and local
+energies (rho_positions, local_energies): brute-force one-site matrices,
+one-site and bond expectations and block spectra of every node, the averaged
+descent, the energy of the state, and a product state in closed form.
 """
 from __future__ import annotations
 
@@ -436,6 +439,73 @@ def entanglement(rho):
     lam[pos] = -np.log2(p[pos])
     S = float(-np.sum(p[pos] * np.log2(p[pos])))
     return p, lam, S
+
+
+# --------------------------------------------------------------------------
+# position-resolved reduced density matrices and local energies (the same
+# state read node by node instead of averaged over positions)
+# --------------------------------------------------------------------------
+def rho_positions(ws, v):
+    """Reduced density matrix on the upper bond of every node of every level.
+
+    rhos[tau][m] belongs to node m of level tau: the block of sites
+    m 2**tau .. (m+1) 2**tau - 1 (tau = 0: site m).  Level n-1 holds the two
+    halves of v: v v^T (left) and v^T v (right).  One level down node 2m is
+    the left child of node m (its right sibling traced out,
+    C_L(w, rho o w)) and node 2m+1 the right child (C_R(w, rho o w)).  The
+    position average of rhos[tau] is the averaged matrix of descend_rho_all.
+    """
+    n = len(ws) + 1
+    rhos = [None] * n
+    rhos[n - 1] = np.stack([v @ v.T, v.T @ v])
+    for tau in range(n - 1, 0, -1):
+        w = ws[tau - 1]
+        b = w.shape[1]
+        out = np.empty((2 * rhos[tau].shape[0], b, b))
+        for m in range(rhos[tau].shape[0]):
+            P = left_mul(rhos[tau][m], w)
+            out[2 * m] = close_l(w, P)
+            out[2 * m + 1] = close_r(w, P)
+        rhos[tau - 1] = out
+    return rhos
+
+
+def bond_site(tau, m):
+    """Left site j of the bond (j, j+1) whose two sites first meet under node m
+    of level tau >= 1: the last site of its left child."""
+    return m * (1 << tau) + (1 << (tau - 1)) - 1
+
+
+def local_energies(ws, v, h1, A, B):
+    """Expectation of every one-site term and of every bond of the chain.
+
+    site[j] = <h1_j>, bond[j] = sum_k <A_{k,j} B_{k,j+1}> (site L is site 0),
+    for the unshifted Hamiltonian.  Sites: <rho^(0,j), h1>.  A bond whose two
+    sites meet under node m of level tau (bond_site): with A^(tau-1) and
+    B^(tau-1) the operators that A on the last site and B on the first site of
+    a level tau-1 block become (ascend_all), its expectation is
+    <rho^(tau,m), w (A^(tau-1) x B^(tau-1)) w^T>.  The two bonds between the
+    halves of v: the middle one <v, A v B^T> and the periodic one
+    <v, B v A^T>, with the level n-1 operators.  sum(site) + sum(bond) is the
+    energy of the state.
+    """
+    n = len(ws) + 1
+    L = 1 << n
+    h1 = np.asarray(h1, dtype=np.float64)
+    _, As, Bs = ascend_all(ws, h1, list(A), list(B))
+    rhos = rho_positions(ws, v)
+    site = np.array([pair(r, h1) for r in rhos[0]])
+    bond = np.full(L, np.nan)
+    for tau in range(1, n):
+        w = ws[tau - 1]
+        op = sum((close(w, apply_l(a_k, apply_r(b_k, w))) for a_k, b_k in zip(As[tau - 1], Bs[tau - 1])),
+                 np.zeros((w.shape[0], w.shape[0])))
+        for m in range(L >> tau):
+            bond[bond_site(tau, m)] = pair(rhos[tau][m], op)
+    top = n - 1
+    bond[L // 2 - 1] = sum((pair(v, a_k @ v @ b_k.T) for a_k, b_k in zip(As[top], Bs[top])), 0.0)
+    bond[L - 1] = sum((pair(v, b_k @ v @ a_k.T) for a_k, b_k in zip(As[top], Bs[top])), 0.0)
+    return site, bond, rhos
 
 
 # --------------------------------------------------------------------------
