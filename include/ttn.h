@@ -295,6 +295,36 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
 enum { TTN_ENT_AVERAGE = 0, TTN_ENT_LEFTMOST = 1 };
 ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy);
 
+/* Position-resolved reading of the state of member b (the same uniform tree,
+ * its nodes read one by one instead of averaged over positions; the energy
+ * as a sum of local terms, Eqs. (H1D) and (1)-(5), its two-site terms met at
+ * the node where their sites first share a causal cone, Fig. 3).
+ *
+ * ttn_local_energies fills, on the host,
+ *   site[j] = <h1_j>                          (j = 0..L-1)
+ *   bond[j] = sum_k <A_{k,j} B_{k,j+1}>       (site L is site 0)
+ * for the Hamiltonian as given (no shift), so sum(site) + sum(bond) is the
+ * energy of the state (the per-site energy of ttn_energy times L * ly).  It
+ * also leaves in `work` the reduced density matrix on the upper bond of every
+ * node: level tau has L >> tau nodes, node m covering the sites
+ * m 2^tau .. (m+1) 2^tau - 1 (tau = 0: site m), each a chi_tau x chi_tau
+ * row-major float64 matrix, node m at byte offset
+ * ttn_positions_offset(h, b, tau) + 8 m chi_tau^2.  Level n-1 holds v v^T
+ * and v^T v; node 2m (2m+1) of level tau-1 is the left (right) child of
+ * node m of level tau, the other child traced out.
+ *
+ * Computed in float64 from the master isometries and top tensor, whatever
+ * the bulk precision.  The handle's state is not changed (no stage order
+ * applies).  work: device memory of the caller, 256-byte aligned, at least
+ * ttn_positions_bytes(h, b) bytes (the matrices of every level plus scratch
+ * of two chi^3 slices); a larger buffer lets more parents share each launch
+ * of the descent.  Synchronises the stream.
+ * TTN_EINVAL for a bad handle, member or pointer, or an unaligned work;
+ * TTN_ENOMEM when bytes is below the minimum; TTN_EHIP from the runtime. */
+ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes);
+ttn_status ttn_positions_offset(ttn_handle h, int b, int tau, size_t* offset);
+ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, double* site, double* bond);
+
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);
 

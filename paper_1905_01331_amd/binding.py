@@ -29,6 +29,7 @@ EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
     "ttn_energy", "ttn_sweep", "ttn_sweep_grouped", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
+    "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies",
 ]
 
 
@@ -92,6 +93,9 @@ def load_library(path: str = LIB_PATH):
         "ttn_free": ([P], I),
         "ttn_profile": ([P, I], I),
         "ttn_entanglement": ([P, I, I, I, DP, DP], I),
+        "ttn_positions_bytes": ([P, I, ctypes.POINTER(ctypes.c_size_t)], I),
+        "ttn_positions_offset": ([P, I, I, ctypes.POINTER(ctypes.c_size_t)], I),
+        "ttn_local_energies": ([P, I, P, ctypes.c_size_t, DP, DP], I),
         "ttn_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
@@ -269,6 +273,38 @@ class TTN:
         S = ctypes.c_double(0.0)
         _check(self.lib.ttn_entanglement(self.h, b, tau, which, _dptr(p), ctypes.byref(S)))
         return p, S.value
+
+    def positions_bytes(self, b=0):
+        need = ctypes.c_size_t(0)
+        _check(self.lib.ttn_positions_bytes(self.h, b, ctypes.byref(need)))
+        return need.value
+
+    def local_energies(self, b=0, levels=(), work=None):
+        """(site, bond, rhos): the expectation of every one-site term and of
+        every bond (j, j+1) of member b, and the reduced density matrices of
+        the nodes of the requested levels ({tau: array (L >> tau, chi, chi)}).
+        work: a CUDA uint8 tensor to compute in (at least positions_bytes()
+        + 256 bytes); by default one of that size is taken for the call."""
+        import torch
+        need = self.positions_bytes(b)
+        if work is None:
+            work = torch.empty(need + 256, dtype=torch.uint8, device=self.workspace.device)
+        base = work.data_ptr()
+        skip = ((base + 255) & ~255) - base
+        nbytes = work.numel() - skip
+        n = self.n_levels(b)
+        L = 1 << n
+        site, bond = np.zeros(L), np.zeros(L)
+        _check(self.lib.ttn_local_energies(self.h, b, ctypes.c_void_p(base + skip), nbytes, _dptr(site), _dptr(bond)))
+        rhos = {}
+        for tau in levels:
+            off = ctypes.c_size_t(0)
+            _check(self.lib.ttn_positions_offset(self.h, b, tau, ctypes.byref(off)))
+            c = self.bond_dim(tau, b)
+            cnt = (L >> tau) * c * c
+            raw = work[skip + off.value: skip + off.value + 8 * cnt].cpu().numpy()
+            rhos[tau] = raw.view(np.float64).reshape(L >> tau, c, c).copy()
+        return site, bond, rhos
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

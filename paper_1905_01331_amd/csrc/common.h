@@ -203,6 +203,10 @@ hipError_t row_normalize_f64(const double* Y, double* Z, double* nrm, int m, lon
 // `part` is device scratch of at least 256 doubles.
 hipError_t pair_f64(const double* X, const double* Y, long long n, double* out, double* part, hipStream_t s);
 hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, double* part, hipStream_t s);
+// Row-wise pairings: out[r os + oo] = beta out[r os + oo] + sum_{i < len}
+// X[r sX + i] Y[r sY + i] for r < rows (sY = 0: one Y for every row).
+hipError_t pair_rows_f64(const double* X, long long sX, const double* Y, long long sY, long long len, int rows,
+                         double* out, long long os, long long oo, double beta, hipStream_t s);
 // ||W W^T - I||_F from the Gram G (n x n): out[0] = sqrt(sum (G - I)^2)
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s);
 

@@ -137,6 +137,25 @@ __global__ __launch_bounds__(RED_THREADS) void k_sum_partials(const double* __re
   if (threadIdx.x == 0) out[0] = s;
 }
 
+// out[r os + oo] = beta out[r os + oo] + sum_i X[r sX + i] Y[r sY + i]: one
+// work-group per row, a fixed summation order (no atomics)
+__global__ __launch_bounds__(RED_THREADS) void k_pair_rows(const double* __restrict__ X, long long sX,
+                                                           const double* __restrict__ Y, long long sY, long long len,
+                                                           double* __restrict__ out, long long os, long long oo,
+                                                           double beta) {
+  const long long r = blockIdx.x;
+  __shared__ double sh[RED_THREADS];
+  const double* x = X + r * sX;
+  const double* y = Y + r * sY;
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < len; i += blockDim.x) acc += x[i] * y[i];
+  double s = block_sum<double>(acc, sh);
+  if (threadIdx.x == 0) {
+    double* o = out + r * os + oo;
+    *o = (beta == 0.0) ? s : beta * *o + s;
+  }
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_ortho_err(const double* __restrict__ G, int n, double* out, long long ms_) {
   G = mshift(G, ms_); out = mshift(out, ms_);
   __shared__ double sh[RED_THREADS];
@@ -382,6 +401,12 @@ hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, do
                      grp().skip);
   hipLaunchKernelGGL(k_sum_partials, dim3(1, grp().count), dim3(RED_THREADS), 0, s, part, RED_BLOCKS, out, grp().stride,
                      grp().skip);
+  return hipGetLastError();
+}
+hipError_t pair_rows_f64(const double* X, long long sX, const double* Y, long long sY, long long len, int rows,
+                         double* out, long long os, long long oo, double beta, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pair_rows, dim3(rows), dim3(RED_THREADS), 0, s, X, sX, Y, sY, len, out, os, oo, beta);
   return hipGetLastError();
 }
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s) {

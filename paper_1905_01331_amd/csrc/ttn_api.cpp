@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -713,6 +714,123 @@ hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, 
   g.C = M.Sw; g.sCm = b; g.sCn = 1; g.sCb = bb;
   g.beta = 1.0;
   return run(M, p, g, s, OC_APPLY_L);
+}
+
+// ---------------------------------------------------------------------------
+// position-resolved density matrices and local energies (float64, from the
+// master isometries and top tensor; the sweep's state is not touched)
+// ---------------------------------------------------------------------------
+// The caller's work buffer in doubles, every region on a 256-byte boundary:
+// site and bond energies (L each), h1, the product operators of two adjacent
+// levels ([A_1..A_D], [B_1..B_D], twice), the bond operator of every layer,
+// the matrices of every level (level tau: L >> tau nodes of chi_tau^2), and
+// scratch for the rest (at least two a*b*b slices; more lets more parents
+// share one launch of the descent).
+struct PosLayout {
+  long long site = 0, bond = 0, h1 = 0, ops = 0, slot = 0, scratch = 0, scratch_min = 0, min_total = 0;
+  std::vector<long long> bop, rho;
+};
+PosLayout pos_layout(const Member& M) {
+  PosLayout P;
+  const int n = M.n;
+  long long o = 0, cmax = 0;
+  for (int t = 0; t < n; ++t) cmax = std::max<long long>(cmax, M.dims[t]);
+  auto take = [&](long long k) {
+    long long r = o;
+    o = (o + k + 31) & ~31LL;
+    return r;
+  };
+  P.site = take(M.L);
+  P.bond = take(M.L);
+  P.h1 = take((long long)M.d * M.d);
+  P.slot = (long long)std::max(M.D, 1) * cmax * cmax;
+  P.ops = take(4 * P.slot);
+  P.bop.assign(n, 0);
+  for (int t = 1; t < n; ++t) P.bop[t] = take((long long)M.dims[t] * M.dims[t]);
+  P.rho.assign(n, 0);
+  for (int t = 0; t < n; ++t) P.rho[t] = take((long long)(M.L >> t) * M.dims[t] * M.dims[t]);
+  long long sc = 2LL * M.dims[n - 1] * M.dims[n - 1];
+  for (int t = 1; t < n; ++t) sc = std::max(sc, 2LL * M.dims[t] * M.dims[t - 1] * M.dims[t - 1]);
+  P.scratch = o;
+  P.scratch_min = sc;
+  P.min_total = o + sc;
+  return P;
+}
+
+// Bottom-up: the operators that A on the last and B on the first site of a
+// block of each level become, and each layer's bond operator
+// w (A x B) w^T summed over k.  Top: the two bonds between the halves of v.
+// Top-down: the matrix of every node, node 2m (2m+1) of level tau-1 the left
+// (right) child of node m of level tau, in batches of parents; each level's
+// bonds pair its nodes with its layer's bond operator, level 0 its sites with
+// h1.
+ttn_status local_energies(Member& M, double* W, long long total, const PosLayout& P, hipStream_t s) {
+  const int n = M.n, d = M.d, D = M.D, x = M.dims[n - 1];
+  const long long L = M.L, dd = (long long)d * d, xx = (long long)x * x;
+  double* S = W + P.scratch;
+  const long long sc_len = total - P.scratch;
+  double* site = W + P.site;
+  double* bond = W + P.bond;
+  HIPCHK(hipMemcpyAsync(W + P.h1, M.h1.data(), dd * 8, hipMemcpyHostToDevice, s));
+  double* opA[2] = {W + P.ops, W + P.ops + 2 * P.slot};
+  double* opB[2] = {W + P.ops + P.slot, W + P.ops + 3 * P.slot};
+  int cur = 0;
+  if (D) {
+    HIPCHK(hipMemcpyAsync(opA[0], M.A.data(), D * dd * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(opB[0], M.B.data(), D * dd * 8, hipMemcpyHostToDevice, s));
+    for (int t = 1; t < n; ++t) {
+      const int a = M.dims[t], b = M.dims[t - 1];
+      const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
+      const double* w = M.w64[t];
+      double* T1 = S;
+      double* T2 = S + cube;
+      for (int k = 0; k < D; ++k) {
+        HIPCHK(apply_r(M, P_F64, opB[cur] + k * bb, w, T1, a, b, 0.0, s));
+        HIPCHK(apply_l(M, P_F64, opA[cur] + k * bb, T1, T2, a, b, k ? 1.0 : 0.0, s));
+      }
+      HIPCHK(close_aa(M, P_F64, w, T2, W + P.bop[t], a, b, 1.0, 0.0, s));
+      for (int k = 0; k < D; ++k) {
+        HIPCHK(apply_r(M, P_F64, opA[cur] + k * bb, w, T1, a, b, 0.0, s));
+        HIPCHK(close_aa(M, P_F64, w, T1, opA[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s));
+        HIPCHK(apply_l(M, P_F64, opB[cur] + k * bb, w, T1, a, b, 0.0, s));
+        HIPCHK(close_aa(M, P_F64, w, T1, opB[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s));
+      }
+      cur ^= 1;
+    }
+    double* X = S;
+    double* Y = S + xx;
+    for (int k = 0; k < D; ++k) {  // middle bond <v, A v B^T>, periodic bond <v, B v A^T>
+      HIPCHK(mm(M, P_F64, opA[cur] + k * xx, false, M.vtop, false, X, x, 1.0, 0.0, s));
+      HIPCHK(mm(M, P_F64, X, false, opB[cur] + k * xx, true, Y, x, 1.0, 0.0, s));
+      HIPCHK(pair_rows_f64(M.vtop, 0, Y, 0, xx, 1, bond, 0, L / 2 - 1, k ? 1.0 : 0.0, s));
+      HIPCHK(mm(M, P_F64, opB[cur] + k * xx, false, M.vtop, false, X, x, 1.0, 0.0, s));
+      HIPCHK(mm(M, P_F64, X, false, opA[cur] + k * xx, true, Y, x, 1.0, 0.0, s));
+      HIPCHK(pair_rows_f64(M.vtop, 0, Y, 0, xx, 1, bond, 0, L - 1, k ? 1.0 : 0.0, s));
+    }
+  } else {
+    HIPCHK(fill_f64(bond, 0.0, (size_t)L, s));
+  }
+  double* rt = W + P.rho[n - 1];
+  HIPCHK(mm(M, P_F64, M.vtop, false, M.vtop, true, rt, x, 1.0, 0.0, s));       // v v^T
+  HIPCHK(mm(M, P_F64, M.vtop, true, M.vtop, false, rt + xx, x, 1.0, 0.0, s));  // v^T v
+  for (int t = n - 1; t >= 1; --t) {
+    const int a = M.dims[t], b = M.dims[t - 1];
+    const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
+    const long long parents = L >> t;
+    double* up = W + P.rho[t];
+    double* lo = W + P.rho[t - 1];
+    const double* w = M.w64[t];
+    if (D) HIPCHK(pair_rows_f64(up, aa, W + P.bop[t], 0, aa, (int)parents, bond, 1LL << t, (1LL << (t - 1)) - 1, 0.0, s));
+    const long long chunk = std::max<long long>(1, std::min<long long>(parents, sc_len / cube));
+    for (long long m0 = 0; m0 < parents; m0 += chunk) {
+      const int c = (int)std::min<long long>(chunk, parents - m0);
+      HIPCHK(left_mul_k(M, P_F64, up + m0 * aa, aa, w, 0, S, cube, a, b, 1.0, 0.0, c, s));
+      HIPCHK(close_l_k(M, P_F64, w, 0, S, cube, lo + 2 * m0 * bb, 2 * bb, a, b, 1.0, 0.0, c, s));
+      HIPCHK(close_r_k(M, P_F64, w, 0, S, cube, lo + (2 * m0 + 1) * bb, 2 * bb, a, b, 1.0, 0.0, c, s));
+    }
+  }
+  HIPCHK(pair_rows_f64(W + P.rho[0], dd, W + P.h1, 0, dd, (int)L, site, 1, 0, 0.0, s));
+  return TTN_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1884,6 +2002,37 @@ ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, 
   if (info[0] < 0) return fail(TTN_EHIP, "the Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
   // the scratch held the polar update's temporaries only; the environment
   // (kept in its own buffers) stays valid
+  return TTN_OK;
+}
+
+ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes) {
+  if (!h || !bytes || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  *bytes = (size_t)pos_layout(h->c.m[b]).min_total * 8;
+  return TTN_OK;
+}
+
+ttn_status ttn_positions_offset(ttn_handle h, int b, int tau, size_t* offset) {
+  if (!h || !offset || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  const Member& M = h->c.m[b];
+  if (tau < 0 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [0, %d]", tau, M.n - 1);
+  *offset = (size_t)pos_layout(M).rho[tau] * 8;
+  return TTN_OK;
+}
+
+ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, double* site, double* bond) {
+  if (!h || !work || !site || !bond || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  if ((uintptr_t)work % 256) return fail(TTN_EINVAL, "work is not 256-byte aligned");
+  Member& M = h->c.m[b];
+  const PosLayout P = pos_layout(M);
+  if ((long long)(bytes / 8) < P.min_total)
+    return fail(TTN_ENOMEM, "work of %zu bytes is smaller than %lld", bytes, P.min_total * 8);
+  hipStream_t s = h->c.s;
+  GroupScope one(1, 0);
+  ttn_status st = local_energies(M, (double*)work, (long long)(bytes / 8), P, s);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(site, (double*)work + P.site, (size_t)M.L * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bond, (double*)work + P.bond, (size_t)M.L * 8, hipMemcpyDeviceToHost));
   return TTN_OK;
 }
 

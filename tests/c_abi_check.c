@@ -55,6 +55,9 @@ static int cpu_checks(void) {
   if ((st = ttn_sweep_grouped(NULL, 1, 2, 0)) != TTN_EINVAL) return fail("null handle grouped sweep", st);
   double e;
   if ((st = ttn_energy(NULL, &e)) != TTN_EINVAL) return fail("null handle energy", st);
+  double site[32], bond[32];
+  if ((st = ttn_positions_bytes(NULL, 0, &bytes)) != TTN_EINVAL) return fail("null handle positions bytes", st);
+  if ((st = ttn_local_energies(NULL, 0, NULL, 0, site, bond)) != TTN_EINVAL) return fail("null handle local energies", st);
   printf("cpu checks passed\n");
   return 0;
 }

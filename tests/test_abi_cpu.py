@@ -108,3 +108,15 @@ def test_grouped_sweep_rejects_a_null_handle(lib):
     # argument checks run before any device call
     assert lib.ttn_sweep_grouped(None, 1, 2, 0) == binding.TTN_EINVAL
     assert lib.ttn_sweep_grouped(None, 1, 3, 1) == binding.TTN_EINVAL
+
+
+def test_position_resolved_calls_reject_bad_arguments(lib):
+    # every check happens before any device call
+    import ctypes
+    n = ctypes.c_size_t(0)
+    site = (ctypes.c_double * 4)()
+    bond = (ctypes.c_double * 4)()
+    assert lib.ttn_positions_bytes(None, 0, ctypes.byref(n)) == binding.TTN_EINVAL
+    assert lib.ttn_positions_offset(None, 0, 0, ctypes.byref(n)) == binding.TTN_EINVAL
+    assert lib.ttn_local_energies(None, 0, None, 0, site, bond) == binding.TTN_EINVAL
+    assert b"bad arguments" in lib.ttn_last_error()
