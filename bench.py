@@ -147,6 +147,8 @@ def parse():
     p.add_argument("--budget", type=float, default=900.0, help="--converge: seconds of sweeps in all")
     p.add_argument("--polish", type=float, default=0.0,
                    help="--converge: seconds of float64 sweeps after the last rung (when the ladder ran in another precision)")
+    p.add_argument("--positions", action="store_true",
+                   help="time the position-resolved density matrices and local energies of the workload's state")
     p.add_argument("--schedules", action="store_true",
                    help="energy against time from one start: the paper's sweep and the grouped sweeps "
                         "(--budget seconds each)")
@@ -563,6 +565,61 @@ def schedules(B, I, args):
     }))
 
 
+def positions(B, I, args):
+    """Position-resolved reading of one workload's state (ttn_local_energies):
+    W sweeps from the seeded start, then K timed calls that compute the
+    density matrix of every node in float64 and the L site and bond energies,
+    in a work buffer of the minimum size and in one eight times larger (more
+    parents per launch where the bond dimension is small).  Reports ms per call and the float64 contraction
+    rate of the call against the float64 MFMA peak (flops counted from the
+    products' shapes: the descents, the bond operators and the ascent of the
+    product operators), and the spread of the bond energies."""
+    import numpy as np
+    import torch
+    make, L, chi, prec0, desc = CONFIGS[args.config]
+    model = make(I)
+    prec = args.precision or prec0
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=args.seed))
+    for _ in range(args.warmup):
+        t.sweep(1)
+    n = t.n_levels()
+    dims = [t.bond_dim(tau) for tau in range(n)]
+    D = len(model.A)
+    flops = 0.0
+    for tau in range(1, n):
+        a, b = dims[tau], dims[tau - 1]
+        flops += (L >> tau) * (2.0 * a * a * b * b + 4.0 * a * b ** 3)  # left_mul, close_l, close_r
+        flops += D * (4.0 * a * b ** 3) + 2.0 * a * a * b * b            # bond operator
+        flops += D * 2 * (2.0 * a * b ** 3 + 2.0 * a * a * b * b)         # ascent of A and B
+    need = t.positions_bytes()
+    out = {}
+    for label, mult in (("min_work", 1), ("work_x8", 8)):
+        work = torch.empty(mult * need + 256, dtype=torch.uint8, device="cuda")
+        t.local_energies(work=work)  # launch choices for these shapes
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            a0 = time.perf_counter()
+            site, bond, _ = t.local_energies(work=work)
+            times.append(time.perf_counter() - a0)
+        ms = 1e3 * float(np.median(times))
+        out[label] = {"work_bytes": mult * need, "ms_per_call_median": round(ms, 2),
+                      "tflops_f64": round(flops / (ms * 1e-3) / 1e12, 2),
+                      "frac_of_f64_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK["fp64"], 3)}
+        progress(f"{label}: {ms:.1f} ms per call")
+        del work
+    e = float(t.energy()[0])
+    t.close()
+    print(json.dumps({
+        "metric": "position-resolved density matrices and local energies, ms per call",
+        "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "L": L, "chi": chi, "sweeps_before": args.warmup, "precision_of_sweeps": prec},
+        "algorithmic_tflop_per_call": round(flops / 1e12, 3), "runs": out,
+        "energy_per_site_bulk_precision": e, "sum_of_local_energies_per_site": float(site.sum() + bond.sum()) / (L * model.ly),
+        "bond_energy_min": float(bond.min()), "bond_energy_max": float(bond.max()),
+    }))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -584,6 +641,11 @@ def main():
         progress("device ready")
         B.autotune(0 if args.no_autotune else 1)
         schedules(B, I, args)
+        return
+    if args.positions:
+        progress("device ready")
+        B.autotune(0 if args.no_autotune else 1)
+        positions(B, I, args)
         return
     if args.copy_calibration:
         n = 1 << 28

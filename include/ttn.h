@@ -318,7 +318,8 @@ ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, 
  * applies).  work: device memory of the caller, 256-byte aligned, at least
  * ttn_positions_bytes(h, b) bytes (the matrices of every level plus scratch
  * of two chi^3 slices); a larger buffer lets more parents share each launch
- * of the descent.  Synchronises the stream.
+ * of the descent, up to 256 MB of intermediates per launch (at chi = 256 the
+ * minimum already reaches that).  Synchronises the stream.
  * TTN_EINVAL for a bad handle, member or pointer, or an unaligned work;
  * TTN_ENOMEM when bytes is below the minimum; TTN_EHIP from the runtime. */
 ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes);

@@ -725,7 +725,7 @@ hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, 
 // levels ([A_1..A_D], [B_1..B_D], twice), the bond operator of every layer,
 // the matrices of every level (level tau: L >> tau nodes of chi_tau^2), and
 // scratch for the rest (at least two a*b*b slices; more lets more parents
-// share one launch of the descent).
+// share one launch of the descent, up to 256 MB of them).
 struct PosLayout {
   long long site = 0, bond = 0, h1 = 0, ops = 0, slot = 0, scratch = 0, scratch_min = 0, min_total = 0;
   std::vector<long long> bop, rho;
@@ -821,7 +821,11 @@ ttn_status local_energies(Member& M, double* W, long long total, const PosLayout
     double* lo = W + P.rho[t - 1];
     const double* w = M.w64[t];
     if (D) HIPCHK(pair_rows_f64(up, aa, W + P.bop[t], 0, aa, (int)parents, bond, 1LL << t, (1LL << (t - 1)) - 1, 0.0, s));
-    const long long chunk = std::max<long long>(1, std::min<long long>(parents, sc_len / cube));
+    // parents per launch: their slabs rho o w (8 a b^2 bytes each) up to
+    // 256 MB, the size of the last-level cache (at chi = 256, two parents:
+    // measured faster than one, three or more)
+    const long long slab_cap = std::max<long long>(1, (256LL << 20) / 8 / cube);
+    const long long chunk = std::max<long long>(1, std::min<long long>({parents, sc_len / cube, slab_cap}));
     for (long long m0 = 0; m0 < parents; m0 += chunk) {
       const int c = (int)std::min<long long>(chunk, parents - m0);
       HIPCHK(left_mul_k(M, P_F64, up + m0 * aa, aa, w, 0, S, cube, a, b, 1.0, 0.0, c, s));
