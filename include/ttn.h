@@ -295,6 +295,14 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
 enum { TTN_ENT_AVERAGE = 0, TTN_ENT_LEFTMOST = 1 };
 ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy);
 
+/* The same for the block of node `node` of level tau, i.e. the 2^tau sites
+ * node 2^tau .. (node+1) 2^tau - 1 (node in 0..(L >> tau) - 1; node 0 is
+ * TTN_ENT_LEFTMOST).  Its matrix is descended along its own path: at level
+ * n-1 v v^T for the left half, v^T v for the right half; one level down the
+ * left child (C_L) or the right child (C_R) of the node above, as the bits of
+ * `node` say.  TTN_EINVAL for a node or level outside the tree. */
+ttn_status ttn_entanglement_node(ttn_handle h, int b, int tau, long long node, double* p, double* entropy);
+
 /* Position-resolved reading of the state of member b (the same uniform tree,
  * its nodes read one by one instead of averaged over positions; the energy
  * as a sum of local terms, Eqs. (H1D) and (1)-(5), its two-site terms met at

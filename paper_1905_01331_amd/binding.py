@@ -29,7 +29,7 @@ EXPORTS = [
     "ttn_workspace_bytes", "ttn_init", "ttn_ascend", "ttn_descend", "ttn_env", "ttn_update",
     "ttn_energy", "ttn_sweep", "ttn_sweep_grouped", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
-    "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies",
+    "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies", "ttn_entanglement_node",
 ]
 
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_free": ([P], I),
         "ttn_profile": ([P, I], I),
         "ttn_entanglement": ([P, I, I, I, DP, DP], I),
+        "ttn_entanglement_node": ([P, I, I, ctypes.c_longlong, DP, DP], I),
         "ttn_positions_bytes": ([P, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "ttn_positions_offset": ([P, I, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "ttn_local_energies": ([P, I, P, ctypes.c_size_t, DP, DP], I),
@@ -272,6 +273,14 @@ class TTN:
         p = np.zeros(max(self.bond_dim(tau, b), 1))  # the library rejects a bad tau
         S = ctypes.c_double(0.0)
         _check(self.lib.ttn_entanglement(self.h, b, tau, which, _dptr(p), ctypes.byref(S)))
+        return p, S.value
+
+    def entanglement_node(self, tau, node, b=0):
+        """(p, S) for the block of node `node` of level tau (sites
+        node 2**tau .. (node + 1) 2**tau - 1)."""
+        p = np.zeros(max(self.bond_dim(tau, b), 1))
+        S = ctypes.c_double(0.0)
+        _check(self.lib.ttn_entanglement_node(self.h, b, tau, node, _dptr(p), ctypes.byref(S)))
         return p, S.value
 
     def positions_bytes(self, b=0):

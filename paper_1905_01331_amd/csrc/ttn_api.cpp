@@ -1971,27 +1971,28 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
   return P.dropped ? fail(TTN_OK, "%d launches were not timed (event pool full)", P.dropped) : TTN_OK;
 }
 
-ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy) {
-  if (!h || !p || !entropy || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
-  if (which != TTN_ENT_AVERAGE && which != TTN_ENT_LEFTMOST) return fail(TTN_EINVAL, "which=%d unknown", which);
-  Member& M = h->c.m[b];
+// The spectrum and entropy of the matrix on the upper bond of a block of
+// level tau: the position average (node < 0) or node `node` (its path from
+// the top: at level sigma the node above it is node >> (sigma - tau), a left
+// child when that index is even), float64 throughout (the master isometries),
+// in scratch of the polar update: rho in G / V in turn, rho o w in Y.
+ttn_status block_entanglement(Member& M, int tau, long long node, double* p, double* entropy, hipStream_t s) {
   const int n = M.n;
-  if (tau < 0 || tau > n - 1) return fail(TTN_EINVAL, "tau=%d outside [0, %d]", tau, n - 1);
-  hipStream_t s = h->c.s;
-  GroupScope one(1, 0);
-  const bool avg = which == TTN_ENT_AVERAGE;
+  const bool avg = node < 0;
   const int x = M.dims[n - 1];
-  // float64 throughout (the master isometries), in scratch of the polar
-  // update: rho in G / V in turn, rho o w in Y
   double* cur = M.G;
   double* nxt = M.V;
-  HIPCHK(mm(M, P_F64, M.vtop, false, M.vtop, true, cur, x, avg ? 0.5 : 1.0, 0.0, s));  // v v^T
-  if (avg) HIPCHK(mm(M, P_F64, M.vtop, true, M.vtop, false, cur, x, 0.5, 1.0, s));      // + v^T v
+  const bool top_right = !avg && ((node >> (n - 1 - tau)) & 1);
+  if (avg || !top_right) HIPCHK(mm(M, P_F64, M.vtop, false, M.vtop, true, cur, x, avg ? 0.5 : 1.0, 0.0, s));  // v v^T
+  if (avg) HIPCHK(mm(M, P_F64, M.vtop, true, M.vtop, false, cur, x, 0.5, 1.0, s));                             // + v^T v
+  if (top_right) HIPCHK(mm(M, P_F64, M.vtop, true, M.vtop, false, cur, x, 1.0, 0.0, s));                       // v^T v
   for (int lv = n - 1; lv > tau; --lv) {
     const int a = M.dims[lv], bd = M.dims[lv - 1];
+    const bool right = !avg && ((node >> (lv - 1 - tau)) & 1);
     HIPCHK(left_mul(M, P_F64, cur, M.w64[lv], M.Y, a, bd, 1.0, 0.0, s));
-    HIPCHK(close_l(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, avg ? 0.5 : 1.0, 0.0, s));
+    if (avg || !right) HIPCHK(close_l(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, avg ? 0.5 : 1.0, 0.0, s));
     if (avg) HIPCHK(close_r(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, 0.5, 1.0, s));
+    if (right) HIPCHK(close_r(M, P_F64, M.w64[lv], M.Y, nxt, a, bd, 1.0, 0.0, s));
     std::swap(cur, nxt);
   }
   const int m = M.dims[tau];
@@ -2007,6 +2008,24 @@ ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, 
   // the scratch held the polar update's temporaries only; the environment
   // (kept in its own buffers) stays valid
   return TTN_OK;
+}
+
+ttn_status ttn_entanglement(ttn_handle h, int b, int tau, int which, double* p, double* entropy) {
+  if (!h || !p || !entropy || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  if (which != TTN_ENT_AVERAGE && which != TTN_ENT_LEFTMOST) return fail(TTN_EINVAL, "which=%d unknown", which);
+  Member& M = h->c.m[b];
+  if (tau < 0 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [0, %d]", tau, M.n - 1);
+  GroupScope one(1, 0);
+  return block_entanglement(M, tau, which == TTN_ENT_AVERAGE ? -1 : 0, p, entropy, h->c.s);
+}
+
+ttn_status ttn_entanglement_node(ttn_handle h, int b, int tau, long long node, double* p, double* entropy) {
+  if (!h || !p || !entropy || b < 0 || b >= (int)h->c.m.size()) return fail(TTN_EINVAL, "bad arguments");
+  Member& M = h->c.m[b];
+  if (tau < 0 || tau > M.n - 1) return fail(TTN_EINVAL, "tau=%d outside [0, %d]", tau, M.n - 1);
+  if (node < 0 || node >= (long long)(M.L >> tau)) return fail(TTN_EINVAL, "node=%lld outside [0, %d)", node, M.L >> tau);
+  GroupScope one(1, 0);
+  return block_entanglement(M, tau, node, p, entropy, h->c.s);
 }
 
 ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes) {

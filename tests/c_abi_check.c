@@ -3,7 +3,8 @@
  * device call.  "gpu": a transverse-field Ising chain (L = 32, h = 1,
  * chi = 6, float64, seeded isometries) initialised, swept twice with the
  * paper's sweep and once with the grouped sweep; prints the energies, one per
- * line, for the caller to compare.  Exit status 0 on success. */
+ * line, then the sum of the local energies of the final state, for the caller
+ * to compare.  Exit status 0 on success. */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <stdio.h>
@@ -77,7 +78,10 @@ static int gpu_run(void) {
   }
   ttn_handle h = NULL;
   int rc = 1;
-  double e0, e1, e2;
+  double e0, e1, e2, total = 0.0;
+  double site[32], bond[32];
+  size_t pbytes = 0;
+  void* work = NULL;
   if ((st = ttn_init(&c, 1, ws, bytes, NULL, &h)) != TTN_OK) { fail("init", st); goto out; }
   if ((st = ttn_energy(h, &e0)) < 0) { fail("energy", st); goto out; }
   if ((st = ttn_sweep(h, 2, 0)) < 0) { fail("sweep", st); goto out; }
@@ -85,10 +89,16 @@ static int gpu_run(void) {
   if ((st = ttn_sweep_grouped(h, 1, 2, 0)) < 0) { fail("grouped sweep", st); goto out; }
   if ((st = ttn_energy(h, &e2)) < 0) { fail("energy", st); goto out; }
   if (ttn_bond_dim(h, 0, 1) != 4) { fprintf(stderr, "bond dimension of level 1\n"); goto out; }
-  printf("%.17g\n%.17g\n%.17g\n", e0, e1, e2);
+  /* local energies in a work buffer of the minimum size */
+  if ((st = ttn_positions_bytes(h, 0, &pbytes)) != TTN_OK) { fail("positions bytes", st); goto out; }
+  if (hipMalloc(&work, pbytes) != hipSuccess) { fprintf(stderr, "hipMalloc of %zu bytes failed\n", pbytes); goto out; }
+  if ((st = ttn_local_energies(h, 0, work, pbytes, site, bond)) != TTN_OK) { fail("local energies", st); goto out; }
+  for (int j = 0; j < 32; ++j) total += site[j] + bond[j];
+  printf("%.17g\n%.17g\n%.17g\n%.17g\n", e0, e1, e2, total);
   rc = 0;
 out:
   if (h) ttn_free(h);
+  if (work) (void)hipFree(work);
   (void)hipFree(ws);
   return rc;
 }

@@ -119,4 +119,6 @@ def test_position_resolved_calls_reject_bad_arguments(lib):
     assert lib.ttn_positions_bytes(None, 0, ctypes.byref(n)) == binding.TTN_EINVAL
     assert lib.ttn_positions_offset(None, 0, 0, ctypes.byref(n)) == binding.TTN_EINVAL
     assert lib.ttn_local_energies(None, 0, None, 0, site, bond) == binding.TTN_EINVAL
+    S = ctypes.c_double(0.0)
+    assert lib.ttn_entanglement_node(None, 0, 0, 0, site, ctypes.byref(S)) == binding.TTN_EINVAL
     assert b"bad arguments" in lib.ttn_last_error()

@@ -57,7 +57,12 @@ def test_c_caller_matches_the_binding(c_prog):
     e1 = t.energy()[0]
     t.sweep_grouped(1, 2)
     e2 = t.energy()[0]
+    site, bond, _ = t.local_energies()
+    total = float(site.sum() + bond.sum())
     t.close()
-    print(f"  C {e_c}, binding {[e0, e1, e2]}")
-    assert e_c == [e0, e1, e2]
+    print(f"  C {e_c}, binding {[e0, e1, e2, total]}")
+    assert e_c[:3] == [e0, e1, e2]
     assert e2 <= e1 <= e0
+    # the same minimum-size work buffer on both sides: the same launches
+    assert abs(e_c[3] - total) <= 1e-13 * 32
+    assert abs(total / 32 - e2) <= 1e-12

@@ -99,3 +99,40 @@ def test_entanglement_rejects_bad_arguments(B):
         t.entanglement(1, 7)
     assert e.value.status == B.TTN_EINVAL
     t.close()
+
+
+@pytest.mark.parametrize("name,model,L,chi,prec", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_node_entanglement_matches_reference(B, name, model, L, chi, prec):
+    # the block of any node: its matrix descended along its own path, against
+    # the reference's matrix of that node (rho_positions); node 0 is the
+    # leftmost block, and the two halves of v share their spectrum
+    print(f"[entanglement] nodes {name}", flush=True)
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 12)
+    v = I.random_top(ws[-1].shape[0], 12)
+    t = B.TTN(B.ChainInput(model, L, chi, prec, w0=ws))
+    t.set_tensor(B.TTN_TOP, v)
+    n = len(ws) + 1
+    rhos = T.rho_positions(ws, v)
+    rng = np.random.default_rng(1)
+    worst_p, worst_s = 0.0, 0.0
+    for tau in range(n):
+        cnt = L >> tau
+        for node in sorted({0, 1, cnt - 1, int(rng.integers(cnt))}):
+            p, S = t.entanglement_node(tau, node)
+            p_ref, _, S_ref = T.entanglement(rhos[tau][node])
+            worst_p = max(worst_p, float(np.abs(p - p_ref).max()))
+            worst_s = max(worst_s, abs(S - S_ref))
+        p0, S0 = t.entanglement_node(tau, 0)
+        pl, Sl = t.entanglement(tau, B.TTN_ENT_LEFTMOST)
+        assert np.array_equal(p0, pl) and S0 == Sl
+    pa, Sa = t.entanglement_node(n - 1, 0)
+    pb, Sb = t.entanglement_node(n - 1, 1)
+    assert np.abs(pa - pb).max() < 1e-13 and abs(Sa - Sb) < 1e-12
+    print(f"  worst spectrum difference {worst_p:.2e}, entropy {worst_s:.2e}")
+    assert worst_p < 1e-12
+    assert worst_s < 1e-10
+    for tau, node in ((0, L), (1, -1), (n, 0)):
+        with pytest.raises(B.TTNError) as e:
+            t.entanglement_node(tau, node)
+        assert e.value.status == B.TTN_EINVAL
+    t.close()
