@@ -46,6 +46,8 @@ CASES = [
     ("xxx_L32_chi80", I.xxx_chain(), 32, 80, "fp64"),
     ("xxx_L128_chi48_bf16x3", I.xxx_chain(), 128, 48, "bf16x3"),
     ("tfim_L4_chi2", I.tfim_chain(1.1), 4, 2, "fp64"),
+    # the paper's column sites: d = 32, five product terms
+    ("torus8x5_chi40_fp32", I.torus_tfim_column(5, 2.9), 8, 40, "fp32"),
 ]
 
 
@@ -94,6 +96,25 @@ def test_energy_sum_after_sweeps_and_repeat_calls(B):
         print(f"  sweep {s}: e {e:.12f}, bond energies {bond.min():.6f} .. {bond.max():.6f}")
     a.close()
     b.close()
+
+
+def test_batch_members_match_solo_handles(B):
+    # members of a batch (two of one configuration, one launch group, and one
+    # of another) read one by one give what the same states give alone
+    draws = [(0.8, 64, 12), (1.2, 64, 12), (1.0, 32, 20)]
+    ws = [I.random_isometries(T.layer_shapes(L, 2, chi), 30 + i) for i, (_, L, chi) in enumerate(draws)]
+    batch = B.TTN([B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w) for (h, L, chi), w in zip(draws, ws)])
+    batch.sweep(1)
+    for i, (h, L, chi) in enumerate(draws):
+        site, bond, _ = batch.local_energies(b=i)
+        ws_h = [batch.get_tensor(tau, i) for tau in range(1, batch.n_levels(i))]
+        v_h = batch.get_tensor(B.TTN_TOP, i)
+        model = I.tfim_chain(h)
+        site_r, bond_r, _ = T.local_energies(ws_h, v_h, model.h1, model.A, model.B)
+        assert site.shape == (L,)
+        assert np.abs(site - site_r).max() <= 1e-12 and np.abs(bond - bond_r).max() <= 1e-12
+        assert abs(site.sum() + bond.sum() - batch.energy()[i] * L) <= 1e-11 * L
+    batch.close()
 
 
 def test_zero_product_terms_and_rejections(B):
