@@ -594,8 +594,10 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   else     { if (g.M % 2 || g.sAk % 2 || (g.K2 > 0 && g.sAk1 % 2)) return hipErrorNotSupported; }
   if (bkc) { if (g.K % 2 || g.sBn % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sBk1 % 2))) return hipErrorNotSupported; }
   else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
-  // small products (few 128 x 128 tiles) take 64 x 64 tiles
-  const int T = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64) ? 64 : 128;
+  // small products (few 128 x 128 tiles) and short contractions (K <= 2048:
+  // four work-groups per CU hide each tile's loads and stores, which a short
+  // k loop cannot) take 64 x 64 tiles
+  const int T = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64 || g.K <= 2048) ? 64 : 128;
   long long tiles = (long long)((g.M + T - 1) / T) * ((g.N + T - 1) / T) * g.batch;
   int splits = 1;
   if (tiles < 1024) {
