@@ -46,6 +46,7 @@ CASES = [
     ("xxx_L32_chi80", I.xxx_chain(), 32, 80, "fp64"),
     ("xxx_L128_chi48_bf16x3", I.xxx_chain(), 128, 48, "bf16x3"),
     ("tfim_L4_chi2", I.tfim_chain(1.1), 4, 2, "fp64"),
+    ("tfim_L16_chi1", I.tfim_chain(0.5), 16, 1, "fp64"),  # product states: 1 x 1 matrices above level 0
     # the paper's column sites: d = 32, five product terms
     ("torus8x5_chi40_fp32", I.torus_tfim_column(5, 2.9), 8, 40, "fp32"),
 ]
