@@ -14,7 +14,9 @@ reported under "chi128", 128 independent TFIM chains (seeded L, h, chi)
 swept together in one handle under "batch128", next to the same chains
 swept one at a time, and the grouped sweep (odd layers, then even layers,
 each group's environments from one state; not the paper's schedule) of the
-default workload from the same start under "grouped_schedule".  For each
+default workload from the same start under "grouped_schedule", and the
+position-resolved reading of that workload's state (every node's density
+matrix and every site and bond energy, float64) under "local_energies".  For each
 single chain, the line carries:
   * sweeps/s and the algorithmic contraction TFLOP/s;
   * the energy per site after the timed sweeps, the float64 re-evaluation of
@@ -565,22 +567,23 @@ def schedules(B, I, args):
     }))
 
 
-def positions(B, I, args):
+def measure_positions(B, I, name, prec, steps, warmup, seed, mults=(1, 8)):
     """Position-resolved reading of one workload's state (ttn_local_energies):
     W sweeps from the seeded start, then K timed calls that compute the
     density matrix of every node in float64 and the L site and bond energies,
-    in a work buffer of the minimum size and in one eight times larger (more
-    parents per launch where the bond dimension is small).  Reports ms per call and the float64 contraction
-    rate of the call against the float64 MFMA peak (flops counted from the
-    products' shapes: the descents, the bond operators and the ascent of the
-    product operators), and the spread of the bond energies."""
+    in a work buffer of the minimum size and (mults) in larger ones (more
+    parents per launch where the bond dimension is small).  Reports ms per
+    call and the float64 contraction rate of the call against the float64
+    MFMA peak (flops counted from the products' shapes: the descents, the bond
+    operators and the ascent of the product operators), and the spread of the
+    bond energies."""
     import numpy as np
     import torch
-    make, L, chi, prec0, desc = CONFIGS[args.config]
+    make, L, chi, prec0, desc = CONFIGS[name]
     model = make(I)
-    prec = args.precision or prec0
-    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=args.seed))
-    for _ in range(args.warmup):
+    prec = prec or prec0
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
+    for _ in range(warmup):
         t.sweep(1)
     n = t.n_levels()
     dims = [t.bond_dim(tau) for tau in range(n)]
@@ -593,12 +596,13 @@ def positions(B, I, args):
         flops += D * 2 * (2.0 * a * b ** 3 + 2.0 * a * a * b * b)         # ascent of A and B
     need = t.positions_bytes()
     out = {}
-    for label, mult in (("min_work", 1), ("work_x8", 8)):
+    for mult in mults:
+        label = "min_work" if mult == 1 else f"work_x{mult}"
         work = torch.empty(mult * need + 256, dtype=torch.uint8, device="cuda")
         t.local_energies(work=work)  # launch choices for these shapes
         torch.cuda.synchronize()
         times = []
-        for _ in range(args.steps):
+        for _ in range(steps):
             a0 = time.perf_counter()
             site, bond, _ = t.local_energies(work=work)
             times.append(time.perf_counter() - a0)
@@ -606,17 +610,28 @@ def positions(B, I, args):
         out[label] = {"work_bytes": mult * need, "ms_per_call_median": round(ms, 2),
                       "tflops_f64": round(flops / (ms * 1e-3) / 1e12, 2),
                       "frac_of_f64_peak": round(flops / (ms * 1e-3) / 1e12 / PEAK["fp64"], 3)}
-        progress(f"{label}: {ms:.1f} ms per call")
+        progress(f"{name}: local energies {label}: {ms:.1f} ms per call")
         del work
     e = float(t.energy()[0])
     t.close()
+    del t
+    torch.cuda.empty_cache()
+    return {"workload": desc, "L": L, "chi": chi, "sweeps_before": warmup, "precision_of_sweeps": prec,
+            "dtype": "f64", "algorithmic_tflop_per_call": round(flops / 1e12, 3), "runs": out,
+            "energy_per_site_bulk_precision": e,
+            "sum_of_local_energies_per_site": float(site.sum() + bond.sum()) / (L * model.ly),
+            "bond_energy_min": float(bond.min()), "bond_energy_max": float(bond.max())}
+
+
+def positions(B, I, args):
+    """The --positions mode: measure_positions on one workload, one JSON line."""
+    r = measure_positions(B, I, args.config, args.precision, args.steps, args.warmup, args.seed)
+    cfg = {"workload": r.pop("workload"), "L": r.pop("L"), "chi": r.pop("chi"),
+           "sweeps_before": r.pop("sweeps_before"), "precision_of_sweeps": r.pop("precision_of_sweeps")}
     print(json.dumps({
         "metric": "position-resolved density matrices and local energies, ms per call",
-        "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": desc, "L": L, "chi": chi, "sweeps_before": args.warmup, "precision_of_sweeps": prec},
-        "algorithmic_tflop_per_call": round(flops / 1e12, 3), "runs": out,
-        "energy_per_site_bulk_precision": e, "sum_of_local_energies_per_site": float(site.sum() + bond.sum()) / (L * model.ly),
-        "bond_energy_min": float(bond.min()), "bond_energy_max": float(bond.max()),
+        "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": r.pop("dtype"), "data": "synthetic",
+        "config": cfg, **r,
     }))
 
 
@@ -675,10 +690,12 @@ def main():
 
     batch = None
     grouped = None
+    local = None
     if args.config == DEFAULT_CONFIG and not args.no_secondary:
         batch = measure_batch(B, I, args.steps, args.warmup)
         if not args.evd and args.precision is None:
             grouped = measure_grouped(B, I, args.config, args.steps, args.warmup, args.seed, m["energy"])
+            local = measure_positions(B, I, args.config, None, 3, args.warmup, args.seed, mults=(1,))
 
     cpu = None
     if not args.no_cpu:
@@ -720,6 +737,7 @@ def main():
         "chi128": secondary,
         "batch128": batch,
         "grouped_schedule": grouped,
+        "local_energies": local,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
