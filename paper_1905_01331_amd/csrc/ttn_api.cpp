@@ -1156,8 +1156,8 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
 
 // H_top y for the two sites of level n-1 (float64 copies of the operators):
 //   out = h y + y h^T + sum_k (A_k y B_k^T + B_k y A_k^T)
-// as  stage = [y, y B_1^T, .., y B_D^T, y A_1^T, .., y A_D^T]  (two batched
-// products), then out = [h, A_1..A_D, B_1..B_D] . stage (one product whose
+// as  stage = [y, y B_1^T, .., y B_D^T, y A_1^T, .., y A_D^T]  (one batched
+// product), then out = [h, A_1..A_D, B_1..B_D] . stage (one product whose
 // contraction index runs over the operator blocks), then out += y h^T.
 // (staged: y is already in stage[0])
 hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged = false) {
@@ -1166,15 +1166,17 @@ hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bo
   hipError_t e;
   if (!staged && (e = copy_bytes(M.lzStage, y, xx * 8, s))) return e;
   if (D > 0) {
-    for (int half = 0; half < 2; ++half) {
-      GemmDesc g = desc0();  // stage[1 + half*D + k] = y . (half ? A_k : B_k)^T
-      g.batch = D;
-      g.M = x; g.N = x; g.K = x;
-      g.A = y; g.sAm = x; g.sAk = 1; g.sAb = 0;
-      g.B = half ? M.Aop64 : M.Bop64; g.sBk = 1; g.sBn = x; g.sBb = xx;
-      g.C = M.lzStage + (1 + half * D) * xx; g.sCm = x; g.sCn = 1; g.sCb = xx;
-      if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
-    }
+    // stage[1 + half*D + k] = y . (half ? A_k : B_k)^T, both halves in one
+    // launch: a two-level batch (k, half) whose outer step moves from the B
+    // block to the A block below it and from slot 1 + k to slot 1 + D + k
+    GemmDesc g = desc0();
+    g.batch1 = D;
+    g.batch = 2 * D;
+    g.M = x; g.N = x; g.K = x;
+    g.A = y; g.sAm = x; g.sAk = 1; g.sAb = 0; g.sAb2 = 0;
+    g.B = M.Bop64; g.sBk = 1; g.sBn = x; g.sBb = xx; g.sBb2 = (long long)(M.Aop64 - M.Bop64);
+    g.C = M.lzStage + xx; g.sCm = x; g.sCn = 1; g.sCb = xx; g.sCb2 = D * xx;
+    if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
   }
   GemmDesc g = desc0();  // out = sum_j op_j stage_j
   g.M = x; g.N = x; g.K = (int)((1 + 2 * D) * x); g.K2 = x;
