@@ -8,31 +8,30 @@ re-ascent; then the float64 top eigensolver and the energy) over a
 synthetic Hamiltonian resident in HBM.  W untimed sweeps, then K timed
 sweeps bracketed by device synchronisation.  Prints ONE JSON line.
 
-The default workload is the Heisenberg chain L = 4096 at chi = 256 in
-split-bf16; the 64 x 4 torus at chi = 128 is measured in the same run and
-reported under "chi128", 128 independent TFIM chains (seeded L, h, chi)
-swept together in one handle under "batch128", next to the same chains
-swept one at a time, and the grouped sweep (odd layers, then even layers,
-each group's environments from one state; not the paper's schedule) of the
-default workload from the same start under "grouped_schedule", and the
-position-resolved reading of that workload's state (every node's density
-matrix and every site and bond energy, float64) under "local_energies".  For each
-single chain, the line carries:
-  * sweeps/s and the algorithmic contraction TFLOP/s;
-  * the energy per site after the timed sweeps, the float64 re-evaluation of
-    that same state (its isometries and top tensor loaded into a float64
-    handle) and the relative error of the bulk-precision energy against it;
-  * the energy of the float64 GPU path run from the same initial isometries
-    for the same number of sweeps (a separate trajectory: it drifts apart
-    from the mixed one through the rounding of the updates);
-  * a roofline entry for the dominant product kernel instantiation (its
-    average launch time measured with HIP events around that kernel alone,
-    over a second pass of K eager sweeps), with the per-class and per-kernel
-    times of that pass.
-The CPU reference is timed on a bounded sample of the default workload.
+The headline ("value") is the Heisenberg chain L = 4096 at chi = 256 swept
+in float64 throughout, the arithmetic the paper ran (Sec. V).  Beside it:
+  * the float32 and split-bf16 bulk forms of the same workload (float64
+    polar, top solve and energy), each with its own sweep rate, the energy
+    error of its final state against the float64 re-evaluation of that state,
+    and its time to reach the float64 run's energy within 1e-6 and 1e-8 per
+    site ("mixed_precision");
+  * the same three forms of the 64 x 4 torus at chi = 128 ("chi128");
+  * the critical TFIM chain L = 1024 at chi = 64, float64 and float32, after
+    30 sweeps against the free-fermion ground energy ("tfim1024");
+  * 128 independent TFIM chains (seeded L, h, chi) swept together in one
+    handle, next to the same chains swept one at a time ("batch128");
+  * the grouped sweep (odd layers, then even layers; not the paper's
+    schedule) of the headline workload from the same start
+    ("grouped_schedule"), and the position-resolved reading of its state
+    ("local_energies").
+Every single-chain leg carries a roofline entry for its dominant product
+kernel (average launch time from HIP events around that kernel alone, over a
+profiled pass of eager sweeps) and the per-class and per-kernel times of that
+pass.  The CPU oracle is timed on a bounded sample of the headline workload.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -46,16 +45,21 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "hbm_GBs": 8000.0}
 CONFIGS = {
     # name: (model builder, L, chi, default precision, description)
     "tfim16": (lambda I: I.tfim_chain(1.0), 16, 8, "fp64", "critical TFIM chain L=16 chi=8"),
-    "tfim1024": (lambda I: I.tfim_chain(1.0), 1024, 64, "fp32", "critical TFIM chain L=1024 chi=64"),
-    "torus64x4": (lambda I: I.torus_tfim_column(4, 3.0), 64, 128, "bf16x3",
+    "tfim1024": (lambda I: I.tfim_chain(1.0), 1024, 64, "fp64", "critical TFIM chain L=1024 chi=64"),
+    "torus64x4": (lambda I: I.torus_tfim_column(4, 3.0), 64, 128, "fp64",
                   "2D TFIM 64x4 torus h=3 (d=16 column sites) chi=128"),
-    "xxx4096": (lambda I: I.xxx_chain(), 4096, 256, "bf16x3", "Heisenberg XXX chain L=4096 chi=256"),
+    "xxx4096": (lambda I: I.xxx_chain(), 4096, 256, "fp64", "Heisenberg XXX chain L=4096 chi=256"),
     # the paper's workload (Sec. V) at one rung of its bond-dimension ladder
     "torus128x5": (lambda I: I.torus_tfim_column(5, 2.9), 128, 64, "fp32",
                    "2D TFIM 128x5 torus h=2.9 (d=32 column sites) chi=64"),
 }
 DEFAULT_CONFIG = "xxx4096"
 SECONDARY_CONFIG = "torus64x4"
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+# energy of a state in the bulk precision against the float64 evaluation of
+# the same state, relative to max(|e|, c / ly) (the bars of the GPU tests)
+TOL_ENERGY = {"fp64": 1e-12, "fp32": 2e-6, "bf16x3": 2e-5}
+DELTAS = (1e-6, 1e-8)
 
 
 def kernel_peak(name):
@@ -76,26 +80,35 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the kernel from the committed PMC record
-    (FETCH_SIZE + WRITE_SIZE over the profiled pass, scaled by a plain copy),
-    or None when there is none for this kernel or its sources changed since."""
+def measured_traffic(kernel, workload, bytes_per_launch):
+    """HBM bytes per launch of the kernel from a committed PMC record
+    (FETCH_SIZE + WRITE_SIZE over a profiled pass, scaled by a plain copy),
+    keyed by workload, kernel and the algorithmic bytes per launch; None when
+    no record matches or the kernel sources changed since it was taken."""
     from paper_1905_01331_amd import rocprof_summary as R
-    path = os.path.join(ROOT, "profiles", "gemm_traffic_xxx4096.json")
-    if not os.path.exists(path):
-        return None, "no counter record"
-    with open(path) as f:
-        rec = json.load(f)
-    if rec.get("kernel") != kernel:
-        return None, f"counter record is for {rec.get('kernel')}"
-    if rec.get("sources_sha256") != R.sources_sha256():
-        return None, "kernel sources changed since the counters were taken"
-    return round(rec["traffic_bytes_per_launch"]), (
-        f"HBM bytes per launch (FETCH_SIZE x {rec['fetch_scale']:.3f} + WRITE_SIZE x {rec['write_scale']:.3f}, "
-        f"scales from a plain copy); algorithmic {rec['algorithmic_bytes_per_launch']:.4g}")
+    pdir = os.path.join(ROOT, "profiles")
+    notes = []
+    for fn in sorted(os.listdir(pdir)) if os.path.isdir(pdir) else []:
+        if not (fn.startswith("gemm_traffic_") and fn.endswith(".json")):
+            continue
+        with open(os.path.join(pdir, fn)) as f:
+            rec = json.load(f)
+        if rec.get("workload") != workload or rec.get("kernel") != kernel:
+            continue
+        alg = rec.get("algorithmic_bytes_per_launch", 0.0)
+        if abs(alg - bytes_per_launch) > 1e-6 * bytes_per_launch:
+            notes.append(f"{fn}: algorithmic bytes per launch {alg:.4g} differ from this run's {bytes_per_launch:.4g}")
+            continue
+        if rec.get("sources_sha256") != R.sources_sha256():
+            notes.append(f"{fn}: kernel sources changed since the counters were taken")
+            continue
+        return round(rec["traffic_bytes_per_launch"]), (
+            f"{fn}: HBM bytes per launch (FETCH_SIZE x {rec['fetch_scale']:.3f} + WRITE_SIZE x "
+            f"{rec['write_scale']:.3f}, scales from a plain copy); algorithmic {alg:.4g}")
+    return None, "; ".join(notes) or f"no counter record for {kernel} on {workload}"
 
 
-def kernel_roofline(prof):
+def kernel_roofline(prof, workload):
     """Roofline entry of the product kernel instantiation with the largest
     summed time: achieved = algorithmic flops (2 M N K per product) or bytes
     (operands read once, result written once) per launch / average launch
@@ -114,7 +127,7 @@ def kernel_roofline(prof):
     else:
         ach, peak, unit, bound = byts / avg_s / 1e9, PEAK["hbm_GBs"], "GB/s", "hbm"
     share = d["ms"] / sum(v["ms"] for v in kern.values())
-    traffic, note = measured_traffic(name)
+    traffic, note = measured_traffic(name, workload, byts)
     return {"bound": bound, "achieved": round(ach, 3), "peak": peak, "unit": unit,
             "frac": round(ach / peak, 4), "traffic": traffic, "traffic_note": note,
             "kernel": name, "launches": n, "avg_launch_us": round(avg_s * 1e6, 2),
@@ -131,11 +144,15 @@ def parse():
     p.add_argument("--config", default=DEFAULT_CONFIG, choices=sorted(CONFIGS))
     p.add_argument("--precision", default=None, choices=["fp64", "fp32", "bf16x3"])
     p.add_argument("--seed", type=int, default=0)
-    p.add_argument("--no-fp64-ref", action="store_true")
+    p.add_argument("--headline-only", action="store_true",
+                   help="only the headline leg (no mixed-precision, secondary or batch legs, no CPU oracle)")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--no-secondary", action="store_true", help="skip the chi=128 workload of the default run")
-    p.add_argument("--no-autotune", action="store_true", help="fixed launch heuristics instead of the autotuner")
+    p.add_argument("--no-secondary", action="store_true", help="skip the chi=128, L=1024, batch and schedule legs")
+    p.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the autotuner")
+    p.add_argument("--profile-sweeps", type=int, default=3, help="eager sweeps of the profiled pass")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
+    p.add_argument("--cpu-sweeps", action="store_true",
+                   help="only time whole sweeps of the CPU oracle (1 thread and all threads) on the workloads")
     p.add_argument("--eager", action="store_true", help="no graph replay (every sweep launched eagerly)")
     p.add_argument("--evd", action="store_true",
                    help="the eigenvalue-decomposition variant of the isometry update (one Gram refresh)")
@@ -159,24 +176,26 @@ def parse():
     return p.parse_args()
 
 
-def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
-    """Times the CPU reference (oracle/) on a bounded sample of the workload."""
-    import numpy as np
-    from oracle import ttn_ref as T
-    from paper_1905_01331_amd import inputs as I
+def oracle_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count() or 1])
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count() or 1])
     except Exception:
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
+    """Times the CPU oracle on a bounded sample of the workload: one whole
+    sweep when the estimate fits the budget, else the top layer's step (rho
+    cache, dressed chain, environment, SVD update, re-ascent), whose rate is
+    scaled to the sweep's flops by the flop model (the sample says which)."""
+    from oracle import ttn_ref as T
+    from paper_1905_01331_amd import inputs as I
+    cores = oracle_threads()
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), seed)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
-    t0 = time.perf_counter()
     ref.initialise()
-    t_init = time.perf_counter() - t0
     n = ref.n
-    # whole sweeps while they fit the budget, else the top layer step only
-    est_layer = None
     t0 = time.perf_counter()
     rhos = T.descend_rho_all(ref.ws, ref.v)
     tau = n - 1
@@ -193,110 +212,282 @@ def cpu_baseline(model, L, chi, seed, budget_s, gpu_sweep_flops):
                   + 2 * D * asc                                                    # dressed chain
                   + sum(2 * ref.dims[s] ** 2 * ref.dims[s - 1] ** 2 + 4 * ref.dims[s] * ref.dims[s - 1] ** 3
                         for s in range(2, n)))                                     # rho cache
-    if t_step * (n + 2) < budget_s:
+    rate = step_flops / t_step
+    if gpu_sweep_flops / rate < budget_s:
         t0 = time.perf_counter()
         ref.sweep()
         t_sweep = time.perf_counter() - t0
         return {"value": 1.0 / t_sweep, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
-                "sample": f"one full sweep after initialisation ({t_sweep:.2f} s)"}
-    rate = step_flops / t_step
+                "sample": f"one whole sweep after initialisation ({t_sweep:.2f} s, {cores} threads)"}
     return {"value": rate / gpu_sweep_flops, "unit": "sweeps/s", "cores": cores, "kind": "oracle",
             "sample": (f"top-layer step (rho cache, dressed chain, environment, SVD update, re-ascent) "
-                       f"= {step_flops / 1e9:.1f} GFLOP in {t_step:.2f} s, scaled to the sweep's "
-                       f"{gpu_sweep_flops / 1e12:.2f} TFLOP by the flop model")}
+                       f"= {step_flops / 1e9:.1f} GFLOP in {t_step:.2f} s on {cores} threads, its rate scaled to "
+                       f"the sweep's {gpu_sweep_flops / 1e12:.2f} TFLOP by the flop model; whole sweeps are "
+                       f"timed by bench.py --cpu-sweeps")}
 
 
-def measure(B, I, name, prec_override, steps, warmup, seed, fp64_ref, graph=True, evd=False):
-    """Times K sweeps of one workload after W warm-up sweeps; returns the
-    measured fields (and the final energy) as a dict."""
+def cpu_sweeps(args):
+    """Whole sweeps of the CPU oracle on the workloads, at one thread and at
+    every thread the host gives it (threadpoolctl), one JSON line.  Counts:
+    L = 1024 chi = 64: 1 warm-up + 3 timed sweeps; 64 x 4 torus chi = 128:
+    1 + 2; L = 4096 chi = 256: 1 timed sweep after initialisation, all
+    threads only (one sweep at one thread would take about half an hour)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import ttn_ref as T
+    from paper_1905_01331_amd import inputs as I
+    n_all = oracle_threads()
+    plan = [("tfim1024", 1, 3, (1, n_all)), ("torus64x4", 1, 2, (1, n_all)), ("xxx4096", 0, 1, (n_all,))]
+    out = {}
+    for name, warm, timed, threads in plan:
+        make, L, chi, _, desc = CONFIGS[name]
+        model = make(I)
+        rec = {"workload": desc, "warmup_sweeps": warm, "timed_sweeps": timed}
+        for th in threads:
+            with threadpool_limits(limits=th):
+                ws = I.random_isometries(T.layer_shapes(L, model.d, chi), args.seed)
+                ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ly=model.ly, ws=ws)
+                ref.initialise()
+                for _ in range(warm):
+                    ref.sweep()
+                times = []
+                for _ in range(timed):
+                    t0 = time.perf_counter()
+                    ref.sweep()
+                    times.append(time.perf_counter() - t0)
+                progress(f"oracle {name}, {th} threads: {times}")
+                rec[f"threads_{th}"] = {"s_per_sweep_median": round(float(np.median(times)), 3),
+                                        "sweeps_per_s": round(1.0 / float(np.median(times)), 5),
+                                        "energy_per_site": float(ref.history[-1])}
+        out[name] = rec
+    print(json.dumps({"metric": "CPU oracle whole sweeps", "unit": "sweeps/s", "kind": "oracle",
+                      "host_threads": n_all, "data": "synthetic", "seed": args.seed, "runs": out}))
+
+
+def free_fermion_energy_per_site(L, h):
+    """Ground energy per site of the periodic transverse-field Ising chain
+    H = -sum Z Z - h sum X in its even-parity sector (Pfeuty 1970):
+    E0 = -sum_m sqrt(1 + h^2 - 2 h cos(pi (2m + 1) / L)), m = 0..L-1."""
+    s = 0.0
+    for m in range(L):
+        s += math.sqrt(1.0 + h * h - 2.0 * h * math.cos(math.pi * (2 * m + 1) / L))
+    return -s / L
+
+
+def reevaluate(B, model, L, chi, t):
+    """Energy of the handle's state in float64: its isometries and top tensor
+    go into a float64 handle, whose initialisation ascends every layer and
+    solves the top problem in float64."""
     import torch
-    build, L, chi, prec_default, desc = CONFIGS[name]
-    prec = prec_override or prec_default
-    model = build(I)
+    n = t.n_levels()
+    state = [t.get_tensor(tau) for tau in range(1, n)]
+    v_top = t.get_tensor(B.TTN_TOP)
+    r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=v_top))
+    e = float(r.energy()[0])
+    r.close()
+    del r, state
+    torch.cuda.empty_cache()
+    return e
 
+
+def time_leg(B, I, name, prec, steps, warmup, seed, graph=True, evd=False, profile_sweeps=3):
+    """One workload in one bulk precision: W warm-up sweeps (the first eager,
+    so that the launch tuner meets every product shape; the energy read after
+    each), K timed sweeps (graph replay), then a profiled pass of eager
+    sweeps with HIP events around every product kernel launch."""
+    import torch
+    make, L, chi, _, desc = CONFIGS[name]
+    model = make(I)
     t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed, evd_update=evd))
-    # warm-up: the first sweep runs eagerly (the autotuner times the launch
-    # candidates of every product shape it meets), the next one captures the
-    # layer part of a sweep into a HIP graph, replayed in the timed sweeps
+    e_warm = [float(t.energy()[0])]
     t.sweep(1)
+    e_warm.append(float(t.energy()[0]))
     for _ in range(max(1, warmup) - 1):
         t.sweep(1, graph=graph)
+        e_warm.append(float(t.energy()[0]))
     torch.cuda.synchronize()
-    progress(f"{name}: warm-up done")
     t0 = time.perf_counter()
     for _ in range(steps):
         t.sweep(1, graph=graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    progress(f"{name}: timed sweeps done ({1e3 * elapsed / steps:.2f} ms per sweep)")
+    e_final = float(t.energy()[0])
     st = t.stats()
-    sweeps_per_s = steps / elapsed
-    tflops = st.flops_bulk / (elapsed / steps) / 1e12
-
-    # second pass of K sweeps with per-class HIP event timing
+    progress(f"{name} {prec}: {1e3 * elapsed / steps:.2f} ms per sweep")
     t.profile(True)
-    for _ in range(steps):
+    for _ in range(profile_sweeps):
         t.sweep(1)
     prof = t.profile_read()
     t.profile(False)
-    progress(f"{name}: profiled pass done")
-    e = float(t.energy()[0])  # after warmup + 2 K sweeps
-    st = t.stats()
-    roofline = kernel_roofline(prof)
-    classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / steps, 3),
+    roofline = kernel_roofline(prof, f"{desc} {prec}")
+    classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / profile_sweeps, 3),
                    "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None}
                for k, v in prof.items() if "kernel" not in k}
-    kernels = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / steps, 3)}
+    kernels = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"] / profile_sweeps, 3)}
                for k, v in prof.items() if "kernel" in k}
-
-    # float64 re-evaluation of the same final state: the isometries and the
-    # top tensor go into a float64 handle, whose initialisation ascends every
-    # layer and solves the top problem in float64
-    e_re = None
+    sweeps_done = max(1, warmup) + steps + profile_sweeps
+    e_after_profile = float(t.energy()[0])
     err_re = None
-    n_lv = int(st.n_levels)
+    e_re = None
     if prec != "fp64":
-        state = [t.get_tensor(tau) for tau in range(1, n_lv)]
-        v_top = t.get_tensor(B.TTN_TOP)
-        t.close()
-        del t
-        torch.cuda.empty_cache()
-        r = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=state, v0=v_top))
-        e_re = float(r.energy()[0])
-        r.close()
-        del r, state
-        err_re = abs(e - e_re) / abs(e_re)
-    else:
-        t.close()
-        del t
+        e_re = reevaluate(B, model, L, chi, t)
+        err_re = abs(e_after_profile - e_re) / max(abs(e_re), abs(st.shift) / model.ly)
+    t.close()
+    del t
     torch.cuda.empty_cache()
-
-    err = None
-    e64 = None
-    if prec != "fp64" and fp64_ref:
-        r = B.TTN(B.ChainInput(model, L, chi, "fp64", seed=seed))
-        r.sweep(1)
-        r.sweep(max(1, warmup) - 1 + 2 * steps, graph=True)
-        e64 = float(r.energy()[0])
-        r.close()
-        del r
-        err = abs(e - e64) / abs(e64)
+    sweep_s = elapsed / steps
     return {
-        "name": name, "model": model, "L": L, "chi": chi, "prec": prec, "desc": desc,
-        "sweeps_per_s": sweeps_per_s, "ms_per_step": 1e3 * elapsed / steps, "tflops": tflops,
-        "stats": st, "energy": e, "e_re": e_re, "err_re": err_re, "e64": e64, "err": err,
+        "name": name, "model": model, "L": L, "chi": chi, "prec": prec, "desc": desc, "stats": st,
+        "sweeps_per_s": steps / elapsed, "ms_per_step": 1e3 * sweep_s, "tflops": st.flops_bulk / sweep_s / 1e12,
+        "energy_after_timed": e_final, "energy_warmup": e_warm, "sweeps_done": sweeps_done,
+        "energy_final": e_after_profile, "e_re": e_re, "err_re": err_re,
         "roofline": roofline, "classes": classes, "kernels": kernels,
     }
 
 
-def measure_grouped(B, I, name, steps, warmup, seed, e_paper):
+def trajectory64(B, I, name, seed, sweeps):
+    """Float64 energies after every sweep from the seeded start."""
+    import torch
+    make, L, chi, _, _ = CONFIGS[name]
+    t = B.TTN(B.ChainInput(make(I), L, chi, "fp64", seed=seed))
+    e = [float(t.energy()[0])]
+    for s in range(sweeps):
+        t.sweep(1, graph=s > 0)
+        e.append(float(t.energy()[0]))
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    return e
+
+
+def time_to_energy(B, I, name, prec, seed, target, e64, s64, sweep_s, cap, max_reeval=4):
+    """Sweeps and seconds a run in `prec` needs from the seeded start until
+    the float64 energy of its state is within delta of `target` (the
+    float64 run's energy after its sweeps), for each delta in DELTAS.  A
+    state is re-evaluated in float64 only when its own reported energy is
+    within delta plus its precision's energy bar of the target (at most
+    max_reeval times per delta); the seconds are sweeps x the leg's measured
+    time per sweep.  The float64 run's own sweeps come from its trajectory."""
+    import torch
+    make, L, chi, _, _ = CONFIGS[name]
+    model = make(I)
+    res = {}
+    for d in DELTAS:
+        hit = next((s for s, e in enumerate(e64) if e <= target + d), None)
+        res[f"{d:.0e}"] = {"fp64_sweeps": hit, "fp64_seconds": None if hit is None else round(hit * s64, 4)}
+    if prec == "fp64":
+        return res
+    t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
+    c = float(t.stats().shift)
+    slack = TOL_ENERGY[prec] * max(abs(target), abs(c) / model.ly)
+    left = {d: max_reeval for d in DELTAS}
+    hit = {}
+    cache = {}
+    for s in range(1, cap + 1):
+        t.sweep(1, graph=s > 1)
+        e = float(t.energy()[0])
+        for d in DELTAS:
+            if d in hit or left[d] == 0 or e > target + d + slack:
+                continue
+            if s not in cache:
+                cache[s] = reevaluate(B, model, L, chi, t)
+            left[d] -= 1
+            if cache[s] <= target + d:
+                hit[d] = (s, e, cache[s])
+        if len(hit) == len(DELTAS) or all(left[d] == 0 for d in DELTAS if d not in hit):
+            break
+    t.close()
+    del t
+    torch.cuda.empty_cache()
+    for d in DELTAS:
+        r = res[f"{d:.0e}"]
+        if d in hit:
+            s, e, ere = hit[d]
+            r.update(sweeps=s, seconds=round(s * sweep_s, 4), energy_reported=e, energy_fp64_reeval=ere)
+        else:
+            r.update(sweeps=None, seconds=None,
+                     note=f"not reached within {cap} sweeps ({max_reeval} float64 re-evaluations allowed)")
+    return res
+
+
+def leg_summary(m, tte=None):
+    out = {"precision": m["prec"], "dtype": DTYPE[m["prec"]], "sweeps_per_s": round(m["sweeps_per_s"], 4),
+           "ms_per_step": round(m["ms_per_step"], 3), "contraction_tflops": round(m["tflops"], 3),
+           "energy_per_site": m["energy_final"], "roofline": m["roofline"], "classes": m["classes"],
+           "kernels": m["kernels"]}
+    if m["prec"] != "fp64":
+        tol = TOL_ENERGY[m["prec"]]
+        out.update(energy_fp64_reeval=m["e_re"], energy_rel_err_vs_fp64_reeval=m["err_re"],
+                   energy_tolerance=tol, within_tolerance=bool(m["err_re"] <= tol))
+    if tte is not None:
+        out["time_to_fp64_energy"] = tte
+    return out
+
+
+def workload_legs(B, I, name, args, precs):
+    """Every precision of one workload: the timed legs, the float64 run's
+    trajectory from the same start (rerun: equal to the timed run's energy
+    bit for bit), and each mixed form's time to that run's energy."""
+    legs = {}
+    for p in precs:
+        legs[p] = time_leg(B, I, name, p, args.steps, args.warmup, args.seed, graph=not args.eager,
+                           evd=args.evd, profile_sweeps=args.profile_sweeps)
+    S = max(1, args.warmup) + args.steps
+    e64 = trajectory64(B, I, name, args.seed, S)
+    m64 = legs["fp64"]
+    target = e64[S]
+    out = {"workload": m64["desc"], "reference_sweeps": S, "fp64_energy_after_reference_sweeps": target,
+           "fp64_rerun_identical": bool(e64[S] == m64["energy_after_timed"] and
+                                        e64[:len(m64["energy_warmup"])] == m64["energy_warmup"]),
+           "deltas_per_site": list(DELTAS)}
+    for p in precs:
+        tte = time_to_energy(B, I, name, p, args.seed, target, e64, m64["ms_per_step"] / 1e3,
+                             legs[p]["ms_per_step"] / 1e3, cap=3 * S)
+        out[p] = leg_summary(legs[p], tte)
+        progress(f"{name} {p}: time to the float64 energy {tte}")
+    return legs, out
+
+
+def measure_tfim1024(B, I, args, sweeps=30):
+    """The critical TFIM chain L = 1024 at chi = 64, float64 and float32 bulk
+    from the same seeded start: sweeps/s and the energy per site after
+    `sweeps` sweeps against the free-fermion ground energy."""
+    import torch
+    make, L, chi, _, desc = CONFIGS["tfim1024"]
+    model = make(I)
+    e0 = free_fermion_energy_per_site(L, 1.0)
+    out = {"workload": desc, "sweeps": sweeps, "free_fermion_energy_per_site": e0}
+    for prec in ("fp64", "fp32"):
+        t = B.TTN(B.ChainInput(model, L, chi, prec, seed=args.seed))
+        t.sweep(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.sweep(sweeps - 1, graph=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        e = float(t.energy()[0])
+        rec = {"sweeps_per_s": round((sweeps - 1) / el, 3), "ms_per_step": round(1e3 * el / (sweeps - 1), 3),
+               "energy_per_site": e, "gap_to_free_fermion": e - e0, "above_free_fermion": bool(e >= e0 - 1e-12)}
+        if prec != "fp64":
+            ere = reevaluate(B, model, L, chi, t)
+            rec.update(energy_fp64_reeval=ere,
+                       energy_rel_err_vs_fp64_reeval=abs(e - ere) / max(abs(ere), abs(t.stats().shift)))
+        t.close()
+        del t
+        torch.cuda.empty_cache()
+        out[prec] = rec
+        progress(f"tfim1024 {prec}: e {e:.10f}, free fermions {e0:.10f}")
+    return out
+
+
+def measure_grouped(B, I, name, prec, steps, warmup, seed, e_paper):
     """The grouped sweep (odd layers, then even layers, each group's
     environments from one state) on the same workload from the same seeded
-    start: K timed sweeps after W warm-up sweeps, then K more, so that the
-    energy is read after as many sweeps as the paper's schedule had."""
+    start: K timed sweeps after W warm-up sweeps, so that the energy is read
+    after as many sweeps as the paper's schedule had in its timed leg."""
     import torch
-    build, L, chi, prec, desc = CONFIGS[name]
-    model = build(I)
+    make, L, chi, _, desc = CONFIGS[name]
+    model = make(I)
     t = B.TTN(B.ChainInput(model, L, chi, prec, seed=seed))
     t.sweep_grouped(1, 2)
     for _ in range(max(1, warmup) - 1):
@@ -307,28 +498,26 @@ def measure_grouped(B, I, name, steps, warmup, seed, e_paper):
         t.sweep_grouped(1, 2, graph=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    t.sweep_grouped(steps, 2, graph=True)
     e = float(t.energy()[0])
     t.close()
     del t
     torch.cuda.empty_cache()
     progress(f"{name}: grouped sweeps done ({1e3 * elapsed / steps:.2f} ms per sweep)")
     return {"schedule": "grouped sweep, odd layers then even layers (ttn_sweep_grouped, groups = 2)",
-            "sweeps_per_s": round(steps / elapsed, 4), "ms_per_step": round(1e3 * elapsed / steps, 3),
+            "precision": prec, "sweeps_per_s": round(steps / elapsed, 4),
+            "ms_per_step": round(1e3 * elapsed / steps, 3),
             "energy_per_site_after_same_sweeps": e, "paper_schedule_energy_after_same_sweeps": e_paper}
 
 
 def measure_batch(B, I, steps, warmup):
     """128 independent transverse-field Ising chains (seeded draw of L, h and
     chi; float32 bulk, float64 polar and top) swept together in one handle,
-    against the same chains swept one at a time.  Chains of equal L and chi
-    form launch groups (one launch per kernel for the whole group).  The
-    energy error is each chain's energy against the float64 re-evaluation of
-    its final state; the one-at-a-time runs follow their own trajectories
-    (the group shares the top eigensolver's restarts, the autotuner may pick
-    other split-K counts for group launches, and rounding differences grow
-    along the early, ill-conditioned sweeps), so their difference is
-    reported as a drift, not as an error."""
+    against the same chains swept one at a time (eager, same sweeps).  Chains
+    of equal L and chi form launch groups (one launch per kernel for the
+    whole group).  A member's arithmetic does not depend on the batch, the
+    launch group, graph replay or the launch tuner, so each member's energy
+    equals its one-at-a-time run bit for bit; the energy error is each
+    chain's energy against the float64 re-evaluation of its final state."""
     import numpy as np
     import torch
     draws = I.batched_tfim_draws(128, 2026)
@@ -357,14 +546,13 @@ def measure_batch(B, I, steps, warmup):
     t.close()
     del t
     torch.cuda.empty_cache()
-    r = B.TTN([B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp64", w0=w, v0=v)
-               for d, (w, v) in zip(draws, states)])
+    r = B.TTN([B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp64", w0=w_, v0=v)
+               for d, (w_, v) in zip(draws, states)])
     e_re = r.energy()
     r.close()
     del r, states
     torch.cuda.empty_cache()
     progress("batch: float64 re-evaluation done")
-    # one chain at a time, eager, same number of sweeps
     e_s = np.zeros(len(draws))
     el_s = 0.0
     for i, d in enumerate(draws):
@@ -379,7 +567,7 @@ def measure_batch(B, I, steps, warmup):
         u.close()
         del u
     torch.cuda.empty_cache()
-    rel = np.abs(e_b - e_s) / np.abs(e_s)
+    diff = e_b - e_s
     err = np.abs(e_b - e_re) / np.maximum(np.abs(e_re), shifts)
     return {
         "workload": "128 TFIM chains, L in {64..1024}, h in [0.5, 1.5], chi in {32, 48, 64, 96} (seed 2026)",
@@ -391,7 +579,8 @@ def measure_batch(B, I, steps, warmup):
         "speedup_vs_one_at_a_time": round(el_s / el, 3),
         "launch_groups": n_groups,
         "energy_max_rel_err_vs_fp64_reeval": float(err.max()),
-        "trajectory_max_rel_diff_vs_one_at_a_time": float(rel.max()),
+        "members_equal_to_one_at_a_time": int(np.sum(diff == 0.0)),
+        "max_signed_diff_vs_one_at_a_time": float(diff[np.argmax(np.abs(diff))]),
     }
 
 
@@ -641,6 +830,9 @@ def main():
         print(json.dumps({"error": "the sweep runs on one GPU; --gpus must be 1 "
                                    "(sharding over several GPUs is described, not built)"}))
         sys.exit(2)
+    if args.cpu_sweeps:
+        cpu_sweeps(args)
+        return
     import torch
     from paper_1905_01331_amd import binding as B
     from paper_1905_01331_amd import inputs as I
@@ -673,32 +865,29 @@ def main():
                                                "launches": 3}}))
         return
     B.autotune(0 if args.no_autotune else 1)
-    m = measure(B, I, args.config, args.precision, args.steps, args.warmup, args.seed, not args.no_fp64_ref,
-                not args.eager, args.evd)
+    prec0 = args.precision or CONFIGS[args.config][3]
+    full = args.config == DEFAULT_CONFIG and not args.headline_only and args.precision is None
+    if full:
+        legs, mixed = workload_legs(B, I, args.config, args, ["fp64", "fp32", "bf16x3"])
+        m = legs["fp64"]
+    else:
+        m = time_leg(B, I, args.config, prec0, args.steps, args.warmup, args.seed, graph=not args.eager,
+                     evd=args.evd, profile_sweeps=args.profile_sweeps)
+        mixed = None
     st = m["stats"]
-    secondary = None
-    if args.config == DEFAULT_CONFIG and not args.no_secondary:
+    secondary = tfim1024 = batch = grouped = local = None
+    if full and not args.no_secondary:
         # the metric is quoted at chi = 128 and 256: the chi = 128 workload rides along
-        m2 = measure(B, I, SECONDARY_CONFIG, None, args.steps, args.warmup, args.seed, not args.no_fp64_ref)
-        secondary = {
-            "workload": m2["desc"], "precision": m2["prec"], "sweeps_per_s": round(m2["sweeps_per_s"], 4),
-            "ms_per_step": round(m2["ms_per_step"], 3), "contraction_tflops": round(m2["tflops"], 3),
-            "energy_per_site": m2["energy"], "energy_rel_err_vs_fp64_reeval": m2["err_re"],
-            "energy_rel_diff_vs_fp64_run": m2["err"], "roofline": m2["roofline"],
-            "classes": m2["classes"],
-        }
-
-    batch = None
-    grouped = None
-    local = None
-    if args.config == DEFAULT_CONFIG and not args.no_secondary:
+        _, secondary = workload_legs(B, I, SECONDARY_CONFIG, args, ["fp64", "fp32", "bf16x3"])
+        tfim1024 = measure_tfim1024(B, I, args)
         batch = measure_batch(B, I, args.steps, args.warmup)
-        if not args.evd and args.precision is None:
-            grouped = measure_grouped(B, I, args.config, args.steps, args.warmup, args.seed, m["energy"])
-            local = measure_positions(B, I, args.config, None, 3, args.warmup, args.seed, mults=(1,))
+        if not args.evd:
+            grouped = measure_grouped(B, I, args.config, "fp64", args.steps, args.warmup, args.seed,
+                                      m["energy_after_timed"])
+            local = measure_positions(B, I, args.config, "fp64", 3, args.warmup, args.seed, mults=(1,))
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not args.headline_only:
         cpu = cpu_baseline(m["model"], m["L"], m["chi"], args.seed, args.cpu_budget, st.flops_bulk)
 
     out = {
@@ -712,34 +901,36 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": m["prec"],
+        "dtype": DTYPE[m["prec"]],
         "data": "synthetic",
         "config": {"workload": m["desc"], "L": m["L"], "chi": m["chi"], "d": m["model"].d, "D": m["model"].D,
                    "levels": int(st.n_levels), "precision": m["prec"], "seed": args.seed,
-                   "update": "evd" if args.evd else "polar",
-                   "parallelism": "single GPU"},
+                   "update": "evd" if args.evd else "polar", "parallelism": "single GPU"},
         "contraction_tflops": round(m["tflops"], 3),
         "flops_bulk_per_sweep": st.flops_bulk,
         "flops_fp64_per_sweep": st.flops_fp64,
-        "energy_per_site": m["energy"],
-        "energy_fp64_reeval": m["e_re"],
-        "energy_rel_err_vs_fp64_reeval": m["err_re"],
-        "energy_fp64_gpu_same_sweeps": m["e64"],
-        "energy_rel_diff_vs_fp64_run": m["err"],
+        "product_bytes_per_sweep": st.bytes_hbm,
+        "energy_per_site": m["energy_after_timed"],
+        "energy_per_site_prev_sweep": st.e_prev,
         "ortho_err_max": st.ortho_err_max,
         "jacobi_sweeps_last": list(st.jacobi_sweeps),
         "lanczos_iters_last": st.lanczos_iters,
         "lanczos_resid_last": st.lanczos_resid,
         "roofline": m["roofline"],
+        "profiled_sweeps": args.profile_sweeps,
         "classes": m["classes"],
         "kernels": m["kernels"],
         "autotune_entries": B.autotune(-1),
+        "mixed_precision": mixed,
         "chi128": secondary,
+        "tfim1024": tfim1024,
         "batch128": batch,
         "grouped_schedule": grouped,
         "local_energies": local,
         "cpu_baseline": cpu,
     }
+    if m["prec"] != "fp64":
+        out.update(energy_fp64_reeval=m["e_re"], energy_rel_err_vs_fp64_reeval=m["err_re"])
     print(json.dumps(out))
 
 

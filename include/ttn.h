@@ -55,11 +55,13 @@ enum {
                            of the squared environment                         */
   TTN_WNOCONV = 2,      /* the top eigensolver stopped at its iteration budget
                            above its residual target                          */
+  TTN_WPROF = 3,        /* ttn_profile_read: launches were not timed (event
+                           pool full); the returned record is incomplete       */
   TTN_EINVAL = -1,      /* invalid argument or configuration                  */
   TTN_ENOMEM = -2,      /* workspace smaller than ttn_workspace_bytes()        */
   TTN_EHIP = -3,        /* a HIP runtime call failed                          */
   TTN_ENONFINITE = -4,  /* NaN or Inf in a host input                         */
-  TTN_ENOCONV = -5,     /* reserved                                            */
+  TTN_ENOCONV = -5,     /* a Jacobi eigensolver stopped at its sweep limit     */
   TTN_EORTHO = -6,      /* an updated isometry failed the orthonormality check */
   TTN_ESTATE = -7       /* stage called out of the order of the sweep         */
 };
@@ -152,11 +154,11 @@ ttn_status ttn_ascend(ttn_handle h, int tau_from, int tau_to);
  *   Lbar_k^(tau) for the update of layer tau (1 <= tau <= n-1): A_k, B_k of
  *   level tau-1 are carried up to the top with the current layers, dressed by
  *   v and descended back to level tau (Sec. III.A, Fig. 3). */
-ttn_status ttn_descend(ttn_handle h, int what, int tau);
+ttn_status ttn_descend(ttn_handle h, int tau, int what);
 
 /* Environment of w_tau (Sec. III.A), same index shape as w_tau:
  *   Env = rho o (S w) + sum_k Rbar_k o (B_k .l w) + sum_k Lbar_k o (A_k .r w).
- * Requires ttn_descend(DRESSED, tau) since the last change of layer tau. */
+ * Requires ttn_descend(tau, DRESSED) since the last change of layer tau. */
 ttn_status ttn_env(ttn_handle h, int tau);
 
 /* tau in 1..n-1: w_tau <- -polar(Env) = -U V^T for the thin SVD
@@ -171,20 +173,32 @@ ttn_status ttn_env(ttn_handle h, int tau);
 ttn_status ttn_update(ttn_handle h, int tau);
 
 /* Synchronises the stream and writes the energy per physical spin
- * (E + c L) / (L ly) of each batch member to e_per_site[batch] (host). */
+ * (E + c L) / (L ly) of each batch member to e_per_site[batch] (host): the
+ * energy per site of Sec. IV, E the lowest eigenvalue of the shifted top
+ * Hamiltonian and L ly the number of spins (a torus column of ly spins is
+ * one site).  Errors: TTN_EHIP when a Jacobi solve aborted, TTN_EORTHO when
+ * an updated isometry failed its orthonormality check, TTN_ENOCONV when a
+ * Jacobi solve of the last sweep stopped at its sweep limit without
+ * converging; warnings: TTN_WRANK (see evd_update), TTN_WNOCONV when the
+ * last top update stopped at its restart budget above its residual target. */
 ttn_status ttn_energy(ttn_handle h, double* e_per_site);
 
 /* nsweeps full sweeps (Secs. IV-V): descend(RHO); for tau = 1..n-1 {
- * descend(DRESSED, tau); env(tau); update(tau); ascend(tau, tau) };
+ * descend(tau, DRESSED); env(tau); update(tau); ascend(tau, tau) };
  * update(TOP).  The members of a batch run their layer steps side by side on
  * internal streams forked from and joined back into the handle's stream.
- * use_graph != 0: the layer part (everything but update(TOP)) is captured
- * into a HIP graph on the first such call and replayed on every later one
- * (it holds no host synchronisation; the polar update's optional extra
- * refresh is decided on the device); update(TOP) then runs eagerly, as its
- * restarts are decided on the host.  The graph refers to the handle's
- * workspace only, so ttn_set_tensor between sweeps is honoured.  Ignored
- * while profiling is on.  Results are identical with and without the
+ * use_graph = 0: eager launches; update(TOP) reads its convergence on the
+ * host after every restart and stops launching once every member converged
+ * (TTN_WNOCONV when the restart budget ran out first).
+ * use_graph != 0: the whole sweep, update(TOP) included, is captured into a
+ * HIP graph on the first such call and replayed on every later one with no
+ * host synchronisation: the polar update's optional extra refresh and the
+ * top solver's restarts are decided on the device (every restart of the
+ * budget is in the graph; a flag set when the residual meets its target
+ * makes the kernels of the later restarts return at once), and ttn_energy
+ * reports a top update that did not converge.  The graph refers to the
+ * handle's workspace only, so ttn_set_tensor between sweeps is honoured.
+ * Ignored while profiling is on.  Results are identical with and without the
  * graph. */
 ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
 
@@ -201,9 +215,10 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
  * chain per layer in ttn_sweep.  groups = 1 updates neighbouring
  * layers from the same state and may raise the energy of strongly coupled
  * models; groups = 2 keeps neighbours apart.  Batches run their launch groups
- * one after another on the handle's stream.  use_graph != 0: the layer part
- * is captured into a HIP graph (one per grouping) on the first such call and
- * replayed, as in ttn_sweep; results are identical with and without it.
+ * one after another on the handle's stream.  use_graph != 0: the whole
+ * grouped sweep, update(TOP) included, is captured into a HIP graph (one per
+ * grouping) on the first such call and replayed, as in ttn_sweep; results are
+ * identical with and without it.
  * TTN_EINVAL for groups outside {1, 2}; TTN_ESTATE when a level's operators
  * are stale; otherwise as ttn_sweep. */
 ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_graph);
@@ -230,24 +245,41 @@ typedef struct ttn_stats_t {
   double flops_bulk;      /* algorithmic bulk flops of one sweep              */
   double flops_fp64;      /* algorithmic float64 flops of one sweep           */
   int n_levels;           /* n                                                 */
-  int lanczos_iters;      /* Krylov steps of the last top update              */
+  int lanczos_iters;      /* Krylov steps of the last top update (restarts
+                             that ran x the Krylov space)                     */
   int jacobi_sweeps[4];   /* Jacobi sweeps of the last polar update's three
                              refreshes and of the last Lanczos projection     */
+  double e_prev;          /* energy per physical spin before the last top
+                             update (0 before the first one)                  */
+  double bytes_hbm;       /* algorithmic bytes of the products of the last
+                             sweep (each operand read once, each result
+                             written once, in the precision it is stored in):
+                             the layer part as last launched or captured, plus
+                             the last top update                              */
 } ttn_stats_t;
 
 ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
 
 /* Autotuning of the contraction launches, for the whole process (all
- * handles).  mode 0: fixed heuristics (default); 1: the first time a product
- * of a new shape and layout is run eagerly (not under graph capture) with
- * beta = 0, its candidate launches (split-K counts of the MFMA kernels, the
- * general kernel) are timed with HIP events on the handle's stream (this
- * synchronises that stream) and the fastest is kept; 2: kept choices only.
- * Kept choices are used in every mode but 0, also inside captured graphs.
- * mode -1 leaves the mode unchanged.  entries (host, may be NULL) receives
- * the number of kept choices.  Results may differ from the heuristic's in
- * rounding only (another split-K count sums in another order). */
+ * handles).  mode 0: default launch shapes (default); 1: the first time a
+ * product of a new shape and layout is run eagerly (not under graph capture)
+ * with beta = 0, its candidate launch shapes (float64 output tile 64 x 64 or
+ * 128 x 128; the order in which tiles are handed to the XCDs) are timed with
+ * HIP events on the handle's stream (this synchronises that stream) and the
+ * fastest is kept; 2: kept choices only.  Kept choices are used in every mode
+ * but 0, also inside captured graphs.  mode -1 leaves the mode unchanged.
+ * entries (host, may be NULL) receives the number of kept choices.  A choice
+ * never changes a result: the split of a contraction into partial sums, and
+ * the instruction sequence of every output element, depend on the product's
+ * shape alone, so every mode gives the same bits. */
 ttn_status ttn_autotune(int mode, int* entries);
+
+/* The kept launch choices written to a text file (path, host string), and
+ * read back (merged into the table; entries, may be NULL, receives the
+ * number read).  TTN_EINVAL when the file cannot be written, read or parsed;
+ * a failed load leaves the table unchanged. */
+ttn_status ttn_autotune_save(const char* path);
+ttn_status ttn_autotune_load(const char* path, int* entries);
 
 /* Event timing of the contraction classes (apply_r, apply_l, close,
  * left_mul, close_l, close_r, top_mm, polar_gemm, jacobi, lanczos_gemm) and
@@ -333,6 +365,7 @@ ttn_status ttn_entanglement_node(ttn_handle h, int b, int tau, long long node, d
 ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes);
 ttn_status ttn_positions_offset(ttn_handle h, int b, int tau, size_t* offset);
 ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, double* site, double* bond);
+
 
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);

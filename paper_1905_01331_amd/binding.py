@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libttn.so")
 
-TTN_OK, TTN_WRANK, TTN_WNOCONV = 0, 1, 2
+TTN_OK, TTN_WRANK, TTN_WNOCONV, TTN_WPROF = 0, 1, 2, 3
 TTN_EINVAL, TTN_ENOMEM, TTN_EHIP, TTN_ENONFINITE, TTN_ENOCONV, TTN_EORTHO, TTN_ESTATE = -1, -2, -3, -4, -5, -6, -7
 TTN_FP64, TTN_FP32, TTN_SPLIT_BF16 = 0, 1, 2
 TTN_DESCEND_RHO, TTN_DESCEND_DRESSED = 0, 1
@@ -30,6 +30,7 @@ EXPORTS = [
     "ttn_energy", "ttn_sweep", "ttn_sweep_grouped", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
     "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies", "ttn_entanglement_node",
+    "ttn_autotune_save", "ttn_autotune_load",
 ]
 
 
@@ -51,6 +52,7 @@ class TTNStats(ctypes.Structure):
         ("ortho_err_max", ctypes.c_double), ("sigma_ratio_min", ctypes.c_double), ("shift", ctypes.c_double),
         ("flops_bulk", ctypes.c_double), ("flops_fp64", ctypes.c_double), ("n_levels", ctypes.c_int),
         ("lanczos_iters", ctypes.c_int), ("jacobi_sweeps", ctypes.c_int * 4),
+        ("e_prev", ctypes.c_double), ("bytes_hbm", ctypes.c_double),
     ]
 
 
@@ -84,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         "ttn_sweep": ([P, I, I], I),
         "ttn_sweep_grouped": ([P, I, I, I], I),
         "ttn_autotune": ([I, ctypes.POINTER(ctypes.c_int)], I),
+        "ttn_autotune_save": ([ctypes.c_char_p], I),
+        "ttn_autotune_load": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)], I),
         "ttn_get_tensor": ([P, I, I, DP], I),
         "ttn_set_tensor": ([P, I, I, DP], I),
         "ttn_get_operator": ([P, I, I, I, I, DP], I),
@@ -166,6 +170,19 @@ def autotune(mode=-1):
     return n.value
 
 
+def autotune_save(path):
+    """Writes the kept launch choices to a text file."""
+    _check(load_library().ttn_autotune_save(str(path).encode()))
+
+
+def autotune_load(path):
+    """Merges the launch choices of a text file into the table; returns how
+    many it held."""
+    n = ctypes.c_int(0)
+    _check(load_library().ttn_autotune_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
 def ttn_workspace_bytes(inputs):
     lib = load_library()
     arr = (TTNConfig * len(inputs))(*[x.cfg for x in inputs])
@@ -201,7 +218,7 @@ class TTN:
         return _check(self.lib.ttn_ascend(self.h, tau_from, tau_to))
 
     def descend(self, what, tau=0):
-        return _check(self.lib.ttn_descend(self.h, what, tau))
+        return _check(self.lib.ttn_descend(self.h, tau, what))
 
     def env(self, tau):
         return _check(self.lib.ttn_env(self.h, tau))
@@ -210,8 +227,10 @@ class TTN:
         return _check(self.lib.ttn_update(self.h, tau))
 
     def energy(self):
+        """Energies per site; the call's status (0 or a warning such as
+        TTN_WNOCONV) is kept in self.energy_status."""
         out = np.zeros(self.batch)
-        _check(self.lib.ttn_energy(self.h, _dptr(out)))
+        self.energy_status = _check(self.lib.ttn_energy(self.h, _dptr(out)))
         return out
 
     def sweep(self, nsweeps=1, graph=False):
@@ -263,7 +282,8 @@ class TTN:
     def profile_read(self):
         arr = (TTNProfileEntry * 64)()
         n = ctypes.c_int(0)
-        _check(self.lib.ttn_profile_read(self.h, arr, 64, ctypes.byref(n)))
+        # an incomplete record (launches not timed) is an error here
+        _check(self.lib.ttn_profile_read(self.h, arr, 64, ctypes.byref(n)), allow_warn=False)
         return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
                                            bytes=arr[i].bytes) for i in range(n.value)}
 

@@ -132,9 +132,11 @@ hipError_t copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 // copies when *flag == want (device flag read at run time)
 hipError_t copy_bytes_if(void* dst, const void* src, size_t bytes, const int* flag, int want, hipStream_t s);
 // flag[0] = (info[0] <= limit) ? 1 : 0; err[0] (a double) is set to 1 when
-// any of info[0], info[2], .., info[2 (nq - 1)] is negative
+// any of info[0], info[2], .., info[2 (nq - 1)] is negative (an aborted
+// solve), noconv[0] (may be null) when any of them is >= limit (a solve that
+// used all its sweeps)
 hipError_t set_flag_le(int* flag, const int* info, int limit, hipStream_t s);
-hipError_t note_negative_info(const int* info, int nq, double* err, hipStream_t s);
+hipError_t note_negative_info(const int* info, int nq, double* err, double* noconv, int limit, hipStream_t s);
 hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s);
 // y = alpha*x + beta*y over n elements (float or double)
 hipError_t axpby_f64(const double* x, double* y, double alpha, double beta, size_t n, hipStream_t s);

@@ -17,7 +17,9 @@
 // lo planes), so that the 32 lanes of a half-wave read 32 consecutive
 // entries (float32) or 32 consecutive 16-byte chunks (bf16).
 // Long contractions are split over the grid's z dimension into partial
-// float32 slices reduced in a fixed order (deterministic).
+// float32 slices reduced in a fixed order; the split count depends on the
+// product's shape alone, so a result never depends on how or where the
+// product was launched (tile order, launch group, tuned choices).
 #include "common.h"
 #include "gemm_internal.h"
 #include <algorithm>
@@ -72,12 +74,14 @@ __device__ __forceinline__ bool map_tile(const TileMap& t, int& tx, int& ty, int
   else { tx = l % t.gx; const int r = l / t.gx; ty = r % t.gy; tz = r / t.gy; }
   return true;
 }
-TileMap make_map(int gx, int gy, int gz) {
+// orient: 0 the smaller tile dimension fastest, 1 x fastest, 2 y fastest
+// (a launch-shape choice: the tiles compute the same values in any order)
+TileMap make_map(int gx, int gy, int gz, int orient) {
   TileMap t;
   t.gx = gx; t.gy = gy; t.gz = gz;
   const long long total = (long long)gx * gy * gz;
   t.per = (int)((total + N_XCD - 1) / N_XCD);
-  t.yfast = gy < gx;
+  t.yfast = orient == 0 ? gy < gx : orient == 2;
   return t;
 }
 
@@ -544,8 +548,8 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
 }
 
 template <bool AKC, bool BKC, int T>
-hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s) {
-  const TileMap tm = make_map((g.N + T - 1) / T, (g.M + T - 1) / T, g.batch * splits * gemm_members(g));
+hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s, int orient) {
+  const TileMap tm = make_map((g.N + T - 1) / T, (g.M + T - 1) / T, g.batch * splits * gemm_members(g), orient);
   size_t slot = 0;
   KernelTimer* kt = kernel_timer();
   const double work = (double)g.batch * gemm_members(g);
@@ -559,8 +563,8 @@ hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, 
 }
 
 template <int MODE, bool AKC, bool BKC>
-hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s) {
-  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g));
+hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hipStream_t s, int orient) {
+  const TileMap tm = make_map((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.batch * splits * gemm_members(g), orient);
   size_t slot = 0;
   KernelTimer* kt = kernel_timer();
   const double work = (double)g.batch * gemm_members(g);
@@ -580,10 +584,36 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
 
+// Split-K count of a product: a function of its shape, batch and arithmetic
+// only (never of a tuned choice, of the launch group or of timing), so that a
+// product is summed in the same order wherever and however it is launched.
+// Products with few output tiles (counted at the tile `tile`) and a long
+// contraction are split for about 1024 work-groups, each slice at least
+// 4 BK deep, at most 128 slices and what the scratch holds.
+static int split_count(const GemmDesc& g, int tile, int bk, size_t elem, size_t scratch_bytes, int* kchunk) {
+  const long long tiles = (long long)((g.M + tile - 1) / tile) * ((g.N + tile - 1) / tile) * g.batch;
+  int splits = 1;
+  if (tiles < 1024) {
+    long long want = (1024 + tiles - 1) / tiles;
+    long long maxk = g.K / (4 * bk);
+    long long sps = want < maxk ? want : maxk;
+    const size_t slice = (size_t)g.batch * g.M * g.N * elem;
+    const long long fit = (long long)(scratch_bytes / slice);
+    if (sps > fit) sps = fit;
+    if (sps > 128) sps = 128;
+    splits = sps < 1 ? 1 : (int)sps;
+  }
+  int kc = (g.K + splits - 1) / splits;
+  kc = ((kc + bk - 1) / bk) * bk;
+  splits = (g.K + kc - 1) / kc;
+  *kchunk = kc;
+  return splits < 1 ? 1 : splits;
+}
+
 // Returns hipErrorNotSupported when the shape/layout does not fit the MFMA
 // loaders (caller falls back to the general kernel).
-static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s, int splits_req,
-                              int* splits_used) {
+static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s,
+                              const GemmLaunch& how) {
   if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
   const bool akc = (g.sAk == 1), bkc = (g.sBk == 1);
   const bool amc = (g.sAm == 1), bmc = (g.sBn == 1);
@@ -596,51 +626,35 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
   // small products (few 128 x 128 tiles) and short contractions (K <= 2048:
   // four work-groups per CU hide each tile's loads and stores, which a short
-  // k loop cannot) take 64 x 64 tiles
-  const int T = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64 || g.K <= 2048) ? 64 : 128;
-  long long tiles = (long long)((g.M + T - 1) / T) * ((g.N + T - 1) / T) * g.batch;
-  int splits = 1;
-  if (tiles < 1024) {
-    long long want = (1024 + tiles - 1) / tiles;
-    long long maxk = g.K / (4 * BK64);
-    long long sps = want < maxk ? want : maxk;
-    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(double);
-    long long fit = (long long)(scratch_bytes / slice);
-    if (sps > fit) sps = fit;
-    if (sps > 128) sps = 128;
-    splits = sps < 1 ? 1 : (int)sps;
-  }
-  if (splits_req > 0) {  // a tuned split count, within the scratch and K
-    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(double);
-    long long cap = std::min<long long>({128, (long long)(scratch_bytes / slice), (g.K + BK64 - 1) / BK64});
-    splits = (int)std::max<long long>(1, std::min<long long>(splits_req, cap));
-  }
-  int kchunk = (g.K + splits - 1) / splits;
-  kchunk = ((kchunk + BK64 - 1) / BK64) * BK64;
-  splits = (g.K + kchunk - 1) / kchunk;
-  if (splits < 1) splits = 1;
-  if (splits_used) *splits_used = splits;
+  // k loop cannot) take 64 x 64 tiles by default.  Both tiles issue the same
+  // MFMA sequence for every output element, so the tile is a launch choice
+  // only; the split count follows the default tile.
+  const int T0 = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64 || g.K <= 2048) ? 64 : 128;
+  int kchunk = 0;
+  const int splits = split_count(g, T0, BK64, sizeof(double), scratch_bytes, &kchunk);
+  const int T = how.tile == 64 || how.tile == 128 ? how.tile : T0;
   double* partial = (double*)scratch;
+  const int o = how.orient;
   hipError_t e;
   if (T == 64) {
-    if (akc && bkc) e = launch64<true, true, 64>(g, splits, kchunk, partial, s);
-    else if (akc) e = launch64<true, false, 64>(g, splits, kchunk, partial, s);
-    else if (bkc) e = launch64<false, true, 64>(g, splits, kchunk, partial, s);
-    else e = launch64<false, false, 64>(g, splits, kchunk, partial, s);
+    if (akc && bkc) e = launch64<true, true, 64>(g, splits, kchunk, partial, s, o);
+    else if (akc) e = launch64<true, false, 64>(g, splits, kchunk, partial, s, o);
+    else if (bkc) e = launch64<false, true, 64>(g, splits, kchunk, partial, s, o);
+    else e = launch64<false, false, 64>(g, splits, kchunk, partial, s, o);
   } else {
-    if (akc && bkc) e = launch64<true, true, 128>(g, splits, kchunk, partial, s);
-    else if (akc) e = launch64<true, false, 128>(g, splits, kchunk, partial, s);
-    else if (bkc) e = launch64<false, true, 128>(g, splits, kchunk, partial, s);
-    else e = launch64<false, false, 128>(g, splits, kchunk, partial, s);
+    if (akc && bkc) e = launch64<true, true, 128>(g, splits, kchunk, partial, s, o);
+    else if (akc) e = launch64<true, false, 128>(g, splits, kchunk, partial, s, o);
+    else if (bkc) e = launch64<false, true, 128>(g, splits, kchunk, partial, s, o);
+    else e = launch64<false, false, 128>(g, splits, kchunk, partial, s, o);
   }
   if (e != hipSuccess) return e;
   if (splits > 1) return splitk_reduce_f64(g, splits, partial, s);
   return hipSuccess;
 }
 
-hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s, int splits_req,
-                     int* splits_used) {
-  if (prec == P_F64) return gemm_mfma64(g, scratch, scratch_bytes, s, splits_req, splits_used);
+hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s,
+                     const GemmLaunch& how) {
+  if (prec == P_F64) return gemm_mfma64(g, scratch, scratch_bytes, s, how);
   if (prec != P_F32 && prec != P_BF16X3) return hipErrorNotSupported;
   if (g.M < 32 || g.N < 32 || g.K < 16 || g.batch < 1) return hipErrorNotSupported;
   const int BK = (prec == P_F32) ? 16 : 32;
@@ -654,41 +668,21 @@ hipError_t gemm_mfma(Prec prec, const GemmDesc& g, void* scratch, size_t scratch
   else     { if (g.M % 4 || g.sAk % 4 || (g.K2 > 0 && g.sAk1 % 4)) return hipErrorNotSupported; }
   if (bkc) { if (g.K % 4 || g.sBn % 4 || (g.K2 > 0 && (g.K2 % 4 || g.sBk1 % 4))) return hipErrorNotSupported; }
   else     { if (g.N % 4 || g.sBk % 4 || (g.K2 > 0 && g.sBk1 % 4)) return hipErrorNotSupported; }
-  // split-K for deep contractions with few output tiles
-  long long tiles = (long long)((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN) * g.batch;
-  int splits = 1;
-  if (tiles < 1024) {
-    long long want = (1024 + tiles - 1) / tiles;
-    long long maxk = g.K / (4 * BK);
-    long long sps = want < maxk ? want : maxk;
-    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(float);
-    long long fit = (long long)(scratch_bytes / slice);
-    if (sps > fit) sps = fit;
-    if (sps > 128) sps = 128;
-    splits = sps < 1 ? 1 : (int)sps;
-  }
-  if (splits_req > 0) {  // a tuned split count, within the scratch and K
-    size_t slice = (size_t)g.batch * g.M * g.N * sizeof(float);
-    long long cap = std::min<long long>({128, (long long)(scratch_bytes / slice), (g.K + BK - 1) / BK});
-    splits = (int)std::max<long long>(1, std::min<long long>(splits_req, cap));
-  }
-  int kchunk = (g.K + splits - 1) / splits;
-  kchunk = ((kchunk + BK - 1) / BK) * BK;
-  splits = (g.K + kchunk - 1) / kchunk;
-  if (splits < 1) splits = 1;
-  if (splits_used) *splits_used = splits;
+  int kchunk = 0;
+  const int splits = split_count(g, BM, BK, sizeof(float), scratch_bytes, &kchunk);
   float* partial = (float*)scratch;
+  const int o = how.orient;
   hipError_t e;
   if (prec == P_F32) {
-    if (akc && bkc) e = launch<P_F32, true, true>(g, splits, kchunk, partial, s);
-    else if (akc) e = launch<P_F32, true, false>(g, splits, kchunk, partial, s);
-    else if (bkc) e = launch<P_F32, false, true>(g, splits, kchunk, partial, s);
-    else e = launch<P_F32, false, false>(g, splits, kchunk, partial, s);
+    if (akc && bkc) e = launch<P_F32, true, true>(g, splits, kchunk, partial, s, o);
+    else if (akc) e = launch<P_F32, true, false>(g, splits, kchunk, partial, s, o);
+    else if (bkc) e = launch<P_F32, false, true>(g, splits, kchunk, partial, s, o);
+    else e = launch<P_F32, false, false>(g, splits, kchunk, partial, s, o);
   } else {
-    if (akc && bkc) e = launch<P_BF16X3, true, true>(g, splits, kchunk, partial, s);
-    else if (akc) e = launch<P_BF16X3, true, false>(g, splits, kchunk, partial, s);
-    else if (bkc) e = launch<P_BF16X3, false, true>(g, splits, kchunk, partial, s);
-    else e = launch<P_BF16X3, false, false>(g, splits, kchunk, partial, s);
+    if (akc && bkc) e = launch<P_BF16X3, true, true>(g, splits, kchunk, partial, s, o);
+    else if (akc) e = launch<P_BF16X3, true, false>(g, splits, kchunk, partial, s, o);
+    else if (bkc) e = launch<P_BF16X3, false, true>(g, splits, kchunk, partial, s, o);
+    else e = launch<P_BF16X3, false, false>(g, splits, kchunk, partial, s, o);
   }
   if (e != hipSuccess) return e;
   if (splits > 1) return splitk_reduce_f32(g, splits, partial, s);

@@ -306,10 +306,10 @@ const char* kernel_name(int kid) {
 }
 
 hipError_t gemm(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s) {
-  GemmChoice c{0, 0};
-  const bool tuned = gemm_tuned_choice(prec, g, s, scratch, scratch_bytes, &c);
-  if (gemm_path_mfma_enabled() && !(tuned && c.path == 1)) {
-    hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s, tuned ? c.splits : 0);
+  if (gemm_path_mfma_enabled()) {
+    GemmLaunch how;
+    gemm_tuned_choice(prec, g, s, scratch, scratch_bytes, &how);
+    hipError_t e = gemm_mfma(prec, g, scratch, scratch_bytes, s, how);
     if (e != hipErrorNotSupported) return e;
   }
   return gemm_plain(prec, g, scratch, scratch_bytes, s);

@@ -1,21 +1,25 @@
 // Autotuner of the product launches.
 //
-// A product is keyed by its arithmetic, shape, batch and operand layout.
-// In tuning mode, the first time a key is met on a stream that is not being
-// captured, with beta = 0 and an output that overlaps neither operand (so
-// that running it again gives the same result), every candidate launch is
-// timed with HIP events on that stream and the fastest is stored; the
-// product is then run once more with the stored choice, so its result is the
-// one every later call gives.  Candidates: the MFMA kernels with the split-K
-// count of the heuristic, half, a quarter, double and no split, and the
-// general kernel.  Later calls (also inside a graph capture) use the stored
-// choice; keys never tuned use the heuristic.  The table lives for the
-// process and is shared by every handle.
+// A product is keyed by its arithmetic, shape, batch, operand layout and
+// launch-group size.  In tuning mode, the first time a key is met on a stream
+// that is not being captured, with beta = 0 and an output that overlaps
+// neither operand (so that running it again gives the same result), every
+// candidate launch shape is timed with HIP events on that stream, three times
+// each, and the fastest is stored; the product is then run once more with
+// the stored choice.  Candidates: the output tile (float64: 64 x 64 or
+// 128 x 128) and the order in which tiles are handed to the XCDs (smaller
+// tile dimension fastest, x fastest, y fastest).  No candidate changes the
+// arithmetic: the split-K partition is fixed by the shape, and every tile
+// issues the same MFMA sequence for an output element, so a tuned launch
+// returns the same bits as the default one.  Later calls (also inside a graph
+// capture) use the stored choice; keys never tuned use the default.  The
+// table lives for the process, is shared by every handle, and can be written
+// to and read from a text file (one key and its choice per line).
 #include "gemm_internal.h"
 #include <algorithm>
+#include <cstdio>
 #include <map>
 #include <mutex>
-#include <set>
 #include <tuple>
 #include <vector>
 
@@ -25,8 +29,8 @@ namespace {
 using Key = std::tuple<int, int, int, int, int, int, int, int, int, int, long long, long long, int>;
 
 std::mutex g_mu;
-std::map<Key, GemmChoice> g_table;
-int g_mode = 0;  // 0: heuristic only, 1: tune new keys, 2: stored choices only
+std::map<Key, GemmLaunch> g_table;
+int g_mode = 0;  // 0: defaults only, 1: tune new keys, 2: stored choices only
 
 Key key_of(Prec p, const GemmDesc& g) {
   return Key{(int)p, g.M, g.N, g.K, g.K2, g.batch, g.batch1, (int)(g.sAk == 1), (int)(g.sBk == 1),
@@ -35,12 +39,11 @@ Key key_of(Prec p, const GemmDesc& g) {
 
 bool overlaps(const GemmDesc& g) { return g.C == g.A || g.C == g.B; }
 
-float time_once(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s, const GemmChoice& c,
+float time_once(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s, const GemmLaunch& c,
                 hipEvent_t e0, hipEvent_t e1, hipError_t* err) {
   *err = hipEventRecord(e0, s);
   if (*err) return 1e30f;
-  if (c.path == 0) *err = gemm_mfma(p, g, scratch, bytes, s, c.splits);
-  else *err = gemm_plain(p, g, scratch, bytes, s);
+  *err = gemm_mfma(p, g, scratch, bytes, s, c);
   if (*err) return 1e30f;
   if ((*err = hipEventRecord(e1, s))) return 1e30f;
   if ((*err = hipEventSynchronize(e1))) return 1e30f;
@@ -56,34 +59,34 @@ struct TimerOff {
   ~TimerOff() { kernel_timer() = saved; }
 };
 
-bool tune(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s, GemmChoice* out) {
+bool tune(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s, GemmLaunch* out) {
   TimerOff off;
-  std::vector<GemmChoice> cand;
-  int dflt = 0;
-  if (gemm_path_mfma_enabled()) {
-    // one run with the heuristic gives its split count (and warms the caches)
-    hipError_t e = gemm_mfma(p, g, scratch, bytes, s, 0, &dflt);
-    if (e == hipSuccess) {
-      std::set<int> sp{dflt, std::max(1, dflt / 2), std::max(1, dflt / 4), std::min(128, 2 * dflt), 1};
-      for (int x : sp) cand.push_back(GemmChoice{0, x});
-    } else if (e != hipErrorNotSupported) {
-      return false;
-    }
-  }
-  cand.push_back(GemmChoice{1, 0});
-  if (cand.size() == 1) {
-    *out = cand[0];
+  // one run with the default launch (warms the caches; products the MFMA
+  // kernels do not take have nothing to tune)
+  hipError_t e = gemm_mfma(p, g, scratch, bytes, s, GemmLaunch());
+  if (e == hipErrorNotSupported) {
+    *out = GemmLaunch();
     return true;
   }
+  if (e != hipSuccess) return false;
+  std::vector<GemmLaunch> cand;
+  const int tiles[2] = {64, 128};
+  for (int t = 0; t < (p == P_F64 ? 2 : 1); ++t)
+    for (int o = 0; o < 3; ++o) {
+      GemmLaunch c;
+      c.tile = p == P_F64 ? tiles[t] : 0;
+      c.orient = o;
+      cand.push_back(c);
+    }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) hipEventDestroy(e0);
     return false;
   }
   float best = 1e30f;
-  GemmChoice pick = cand[0];
+  GemmLaunch pick = cand[0];
   bool ok = true;
-  for (const GemmChoice& c : cand) {
+  for (const GemmLaunch& c : cand) {
     hipError_t err = hipSuccess;
     float t = 1e30f;
     for (int r = 0; r < 3 && ok; ++r) {
@@ -117,8 +120,44 @@ void gemm_tune_clear() {
   g_table.clear();
 }
 
+bool gemm_tune_save(const char* path) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return false;
+  for (const auto& kv : g_table) {
+    const Key& k = kv.first;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %lld %lld %d : %d %d\n", std::get<0>(k), std::get<1>(k),
+                 std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), std::get<7>(k),
+                 std::get<8>(k), std::get<9>(k), std::get<10>(k), std::get<11>(k), std::get<12>(k), kv.second.tile,
+                 kv.second.orient);
+  }
+  return std::fclose(f) == 0;
+}
+
+int gemm_tune_load(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  std::map<Key, GemmLaunch> add;
+  int v[13];
+  long long sa = 0, sb = 0;
+  GemmLaunch c;
+  int got;
+  while ((got = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lld %lld %d : %d %d", &v[0], &v[1], &v[2], &v[3],
+                            &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &sa, &sb, &v[12], &c.tile, &c.orient)) == 15) {
+    if (c.tile != 0 && c.tile != 64 && c.tile != 128) break;
+    if (c.orient < 0 || c.orient > 2) break;
+    add[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], sa, sb, v[12]}] = c;
+  }
+  const bool clean = got == EOF;
+  std::fclose(f);
+  if (!clean) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const auto& kv : add) g_table[kv.first] = kv.second;
+  return (int)add.size();
+}
+
 bool gemm_tuned_choice(Prec prec, const GemmDesc& g, hipStream_t s, void* scratch, size_t scratch_bytes,
-                       GemmChoice* out) {
+                       GemmLaunch* out) {
   const Key k = key_of(prec, g);
   int mode;
   {
@@ -134,7 +173,7 @@ bool gemm_tuned_choice(Prec prec, const GemmDesc& g, hipStream_t s, void* scratc
   if (mode != 1 || g.beta != 0.0 || overlaps(g) || g.skip) return false;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
-  GemmChoice c{0, 0};
+  GemmLaunch c;
   if (!tune(prec, g, scratch, scratch_bytes, s, &c)) return false;
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[k] = c;

@@ -128,12 +128,16 @@ __global__ void k_sqrt_inplace(double* x, long long ms_, const int* sk) {
 }
 
 // energy bookkeeping: out[0] = lam, out[1] = (lam + c L) / (L ly)
+// out[0] = lambda, out[1] = e = (lambda + c L) / (L ly); the energy it
+// replaces goes to prev[0] (prev may be null)
 __global__ void k_energy(const double* __restrict__ lam, const double* __restrict__ c, double L, double ly,
-                         double* __restrict__ out, long long ms_) {
-  lam = mshift(lam, ms_); c = mshift(c, ms_); out = mshift(out, ms_);
+                         double* __restrict__ out, double* __restrict__ prev, long long ms_) {
+  lam = mshift(lam, ms_); c = mshift(c, ms_); out = mshift(out, ms_); prev = mshift(prev, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    out[0] = lam[0];
-    out[1] = (lam[0] + c[0] * L) / (L * ly);
+    const double l = lam[0];
+    if (prev) prev[0] = out[1];
+    out[0] = l;
+    out[1] = (l + c[0] * L) / (L * ly);
   }
 }
 
@@ -363,11 +367,14 @@ __global__ __launch_bounds__(512) void k_spectrum(const double* __restrict__ G, 
   if (tid == 0) S[0] = red[0];
 }
 
-// *done = 1 once ||r|| <= tol max(1, |lambda|) (never cleared here)
+// After a restart: a restart that ran (done still 0 on entry) is counted in
+// *runs; *done = 1 once ||r|| <= tol max(1, |lambda|) (never cleared here).
 __global__ void k_lz_mark_done(const double* __restrict__ res, const double* __restrict__ lam, double tol,
-                               int* __restrict__ done, long long ms_) {
-  res = mshift(res, ms_); lam = mshift(lam, ms_); done = mshift(done, ms_);
-  if (threadIdx.x == 0 && blockIdx.x == 0 && res[0] <= tol * fmax(1.0, fabs(lam[0]))) *done = 1;
+                               int* __restrict__ done, int* __restrict__ runs, long long ms_) {
+  res = mshift(res, ms_); lam = mshift(lam, ms_); done = mshift(done, ms_); runs = mshift(runs, ms_);
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *done) return;
+  ++*runs;
+  if (res[0] <= tol * fmax(1.0, fabs(lam[0]))) *done = 1;
 }
 __global__ void k_zero_int(int* x, int n, long long ms_) {
   x = mshift(x, ms_);
@@ -405,8 +412,9 @@ hipError_t sqrt_inplace(double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_sqrt_inplace, dim3(1, grp().count), dim3(64), 0, s, x, grp().stride, grp().skip);
   return hipGetLastError();
 }
-hipError_t energy_store(const double* lam, const double* c, double L, double ly, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy, dim3(1, grp().count), dim3(64), 0, s, lam, c, L, ly, out, grp().stride);
+hipError_t energy_store(const double* lam, const double* c, double L, double ly, double* out, double* prev,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_energy, dim3(1, grp().count), dim3(64), 0, s, lam, c, L, ly, out, prev, grp().stride);
   return hipGetLastError();
 }
 hipError_t ratio_minmax(const double* nrm, int m, double* out, double* run_min, hipStream_t s) {
@@ -448,8 +456,8 @@ hipError_t lz_reorth_final(double* w, const double* Q, int nq, size_t n, const d
                      m_eff, qn, stage, grp().stride, grp().skip);
   return hipGetLastError();
 }
-hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_mark_done, dim3(1, grp().count), dim3(64), 0, s, res, lam, tol, done, grp().stride);
+hipError_t lz_mark_done(const double* res, const double* lam, double tol, int* done, int* runs, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_mark_done, dim3(1, grp().count), dim3(64), 0, s, res, lam, tol, done, runs, grp().stride);
   return hipGetLastError();
 }
 hipError_t spectrum_sorted(const double* G, int n, double* p, double* S, hipStream_t s) {

@@ -57,11 +57,13 @@ __global__ void k_set_flag_le(int* flag, const int* info, int limit, long long m
   flag = mshift(flag, ms_); info = mshift(info, ms_);
   if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = info[0] <= limit ? 1 : 0;
 }
-__global__ void k_note_negative_info(const int* info, int nq, double* err, long long ms_) {
-  info = mshift(info, ms_); err = mshift(err, ms_);
+__global__ void k_note_negative_info(const int* info, int nq, double* err, double* noconv, int limit, long long ms_) {
+  info = mshift(info, ms_); err = mshift(err, ms_); noconv = mshift(noconv, ms_);
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int q = 0; q < nq; ++q)
+  for (int q = 0; q < nq; ++q) {
     if (info[2 * q] < 0) err[0] = 1.0;
+    if (noconv && info[2 * q] >= limit) noconv[0] = 1.0;
+  }
 }
 __global__ void k_add_diag(double* X, int n, double v, long long ms_) {
   X = mshift(X, ms_);
@@ -366,8 +368,9 @@ hipError_t set_flag_le(int* flag, const int* info, int limit, hipStream_t s) {
   hipLaunchKernelGGL(k_set_flag_le, dim3(1, grp().count), dim3(64), 0, s, flag, info, limit, grp().stride);
   return hipGetLastError();
 }
-hipError_t note_negative_info(const int* info, int nq, double* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_note_negative_info, dim3(1, grp().count), dim3(64), 0, s, info, nq, err, grp().stride);
+hipError_t note_negative_info(const int* info, int nq, double* err, double* noconv, int limit, hipStream_t s) {
+  hipLaunchKernelGGL(k_note_negative_info, dim3(1, grp().count), dim3(64), 0, s, info, nq, err, noconv, limit,
+                     grp().stride);
   return hipGetLastError();
 }
 hipError_t add_diag_f64(double* X, int n, double v, hipStream_t s) {

@@ -197,12 +197,15 @@ constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO
               SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10,
               SCAL_ERR = 11,  // 1.0 once a Jacobi solve reported an abort
               SCAL_SHIFT = 12,  // the shift c (per member, read by the energy kernel)
+              SCAL_EPREV = 13,  // the energy before the last top update
+              SCAL_NOCONV = 14,  // 1.0 once a polar Jacobi solve used all its sweeps
               SCAL_N = 16;
 // Gram refreshes of the polar update: two always, a third when the second
 // Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
 // diagonal, so the rotated rows may not yet be orthogonal to working accuracy)
 constexpr int LZ_DONE = 8;  // lzint slot of the top solver's per-member convergence flag
 constexpr int POLAR_REFRESH = 2;
+constexpr int POLAR_JACOBI_SWEEPS = 60;  // sweep limit of a polar Jacobi solve
 constexpr int POLAR_THIRD_IF = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
 
@@ -295,13 +298,26 @@ struct Member {
   // rho^(l) o w_l for l >= pc_from
   int rho_from = 1 << 20, pc_from = 1 << 20;
   int dressed_tau = -1, env_tau = -1, ops_upto = 0;
-  int lz_iters = 0;
   bool ortho_fail = false;
+  // algorithmic bytes of the products (operands read once, result written
+  // once) of the last layer pass and of the last top update, counted while
+  // the launches are issued (a graph replay repeats its capture's count)
+  mutable double bytes_acc = 0.0;
+  mutable bool counting = false;
+  double bytes_layers = 0.0, bytes_top = 0.0;
 
   Prec gp() const { return prec == TTN_FP64 ? P_F64 : (prec == TTN_FP32 ? P_F32 : P_BF16X3); }
   size_t el(size_t n_) const { return n_ * esz; }
   void* at(void* base, size_t elems) const { return (char*)base + elems * esz; }
   const void* at(const void* base, size_t elems) const { return (const char*)base + elems * esz; }
+};
+
+// Counts the product bytes of what runs in its scope into `into`.
+struct ByteCount {
+  Member& M;
+  double& into;
+  ByteCount(Member& m, double& dst) : M(m), into(dst) { M.bytes_acc = 0.0; M.counting = true; }
+  ~ByteCount() { M.counting = false; into = M.bytes_acc; }
 };
 
 // Streams over which the members of a batch run side by side in the layer
@@ -544,6 +560,9 @@ hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cl
   gg.mcount = grp().count;
   gg.mstride = grp().stride;
   if (!gg.skip) gg.skip = grp().skip;
+  if (M.counting)
+    M.bytes_acc += (p == P_F64 ? 8.0 : 4.0) * g.batch *
+                   ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
   if (M.prof && M.prof->on) {
     double es = (p == P_F64) ? 8.0 : 4.0;
     double f = 2.0 * g.M * (double)g.N * g.K * g.batch * gg.mcount;
@@ -974,6 +993,40 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
   return TTN_OK;
 }
 
+// The eigenproblem of the polar update's Gram matrix (M.G -> eigenvalues on
+// its diagonal, eigenvectors as the rows of M.V).  The solver depends on the
+// order a alone, so a member of a batch does the arithmetic it does alone:
+// a <= 64 the one-work-group solver (all members of a launch group in one
+// launch), a > 64 the blocked solver with its persistent grid.  In a batch a
+// blocked solve of a <= 128 (at most 26 work-groups) runs on the member's own
+// stream, one launch per member of its launch group; larger ones (up to 128
+// work-groups) go one at a time through the batch's shared stream, so the
+// persistent grids that can run at once stay well below what the compute
+// units hold.
+hipError_t polar_jacobi(Member& M, int a, double jtol, int it, const int* skip, hipStream_t s) {
+  int* info = M.jinfo + 2 * it;
+  if (a <= 64) return jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, nullptr, s, skip);
+  if (M.solo) return jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, M.jscratch, s, skip);
+  if (a <= 128) {
+    const GroupCtx g = grp();
+    GroupScope one(1, 0);
+    for (int m = 0; m < g.count; ++m) {
+      const long long off = (long long)m * g.stride;
+      auto sh = [off](auto* p) { return p ? (decltype(p))((char*)p + off) : p; };
+      hipError_t e = jacobi_eig_f64(sh(M.G), sh(M.V), a, POLAR_JACOBI_SWEEPS, jtol, sh(info), sh(M.jscratch), s,
+                                    skip ? (const int*)((const char*)skip + off) : nullptr);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e;
+  if ((e = hipEventRecord(M.grid_in, s))) return e;
+  if ((e = hipStreamWaitEvent(M.grid_s, M.grid_in, 0))) return e;
+  if ((e = jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, M.jscratch, M.grid_s, skip))) return e;
+  if ((e = hipEventRecord(M.grid_out, M.grid_s))) return e;
+  return hipStreamWaitEvent(s, M.grid_out, 0);
+}
+
 // out = sign * polar(src) for src (a x K), float64: Gram -> Jacobi eigenvectors
 // -> rotate, repeated; rows of the rotated matrix end up mutually orthogonal
 // with relative accuracy, then normalised and rotated back.
@@ -1027,17 +1080,7 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     {
       size_t slot = 0;
       bool timed = M.prof && M.prof->begin(OC_JACOBI, 0.0, 0.0, s, &slot);
-      if (M.solo) {
-        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, s, skip));
-      } else if (a <= 128) {
-        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, nullptr, s, skip));
-      } else {
-        HIPCHK(hipEventRecord(M.grid_in, s));
-        HIPCHK(hipStreamWaitEvent(M.grid_s, M.grid_in, 0));
-        HIPCHK(jacobi_eig_f64(M.G, M.V, a, 60, jtol, M.jinfo + 2 * it, M.jscratch, M.grid_s, skip));
-        HIPCHK(hipEventRecord(M.grid_out, M.grid_s));
-        HIPCHK(hipStreamWaitEvent(s, M.grid_out, 0));
-      }
+      HIPCHK(polar_jacobi(M, a, jtol, it, skip, s));
       if (timed) M.prof->end(slot, s);
     }
     GemmDesc r = desc0();  // Yn = U Y
@@ -1068,7 +1111,8 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     }
     if (it == nref - 1 && !M.evd) HIPCHK(set_flag_le(M.skip3, M.jinfo + 2 * it, POLAR_THIRD_IF, s));
   }
-  HIPCHK(note_negative_info(M.jinfo, M.evd ? 1 : POLAR_REFRESH + 1, M.scal + SCAL_ERR, s));
+  HIPCHK(note_negative_info(M.jinfo, M.evd ? 1 : POLAR_REFRESH + 1, M.scal + SCAL_ERR, M.scal + SCAL_NOCONV,
+                            POLAR_JACOBI_SWEEPS, s));
   HIPCHK(row_normalize_f64(Yc, Yn, M.nrm, a, K, s));
   if (p_out) {
     // gauge-fixed result: out = sign * Z, the rotation P is handed back
@@ -1187,7 +1231,16 @@ hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bo
   return mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s);  // + y h^T
 }
 
-ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
+// The top update.  Restarts after the one whose residual met the target do
+// nothing: a device flag (set by lz_mark_done) makes every kernel of a later
+// restart return at once.  With `sync` the host reads the flags after every
+// restart and stops launching once every member of the launch group has
+// converged (*converged tells whether they did); without it every restart of
+// the budget is launched and nothing is read back, so the update can be
+// captured into a graph (convergence is then read from the flag by
+// ttn_energy).  Both give the same arithmetic.
+ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged, bool sync = true) {
+  ByteCount bc(M, M.bytes_top);
   const int n = M.n, x = M.dims[n - 1], D = M.D;
   const size_t xx = (size_t)x * x;
   if (M.prec == TTN_FP64) {
@@ -1216,10 +1269,9 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
   // members of a launch group share the restart loop; a member whose
   // residual met the target sets its flag and every kernel of its later
   // restarts returns at once, so it ends with the vector it has alone
-  // (a member alone leaves the loop when it converges: no flag needed)
   int* done = M.lzint + LZ_DONE;
-  const int* skip = grp().count > 1 ? done : nullptr;
-  HIPCHK(zero_int(done, 1, s));
+  const int* skip = done;
+  HIPCHK(zero_int(done, 2, s));  // the flag and the count of restarts run
   for (int rs = 0; rs < M.restarts; ++rs) {
     SkipScope skip_done(skip);
     // q_0 = v / ||v||
@@ -1260,7 +1312,8 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
     HIPCHK(residual_vec(M.lzHv, M.vtop, M.scal + SCAL_LAM, M.lzR, xx, s));
     HIPCHK(pair_f64(M.lzR, M.lzR, (long long)xx, M.scal + SCAL_RES, M.part, s));
     HIPCHK(sqrt_inplace(M.scal + SCAL_RES, s));
-    HIPCHK(lz_mark_done(M.scal + SCAL_RES, M.scal + SCAL_LAM, M.ltol, done, s));
+    HIPCHK(lz_mark_done(M.scal + SCAL_RES, M.scal + SCAL_LAM, M.ltol, done, done + 1, s));
+    if (!sync) continue;
     // every member of the launch group (they share the restarts)
     const int gc = grp().count;
     std::vector<double> hs((size_t)gc * (SCAL_ERR + 1));
@@ -1281,10 +1334,12 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
       break;
     }
   }
+  if (!sync) *converged = true;  // not known here: ttn_energy reads the flag
   HIPCHK(sign_fix(M.vtop, xx, s));
-  HIPCHK(energy_store(M.scal + SCAL_LAM, M.scal + SCAL_SHIFT, (double)M.L, (double)M.ly, M.scal + SCAL_LAM, s));
+  HIPCHK(energy_store(M.scal + SCAL_LAM, M.scal + SCAL_SHIFT, (double)M.L, (double)M.ly, M.scal + SCAL_LAM,
+                      M.scal + SCAL_EPREV, s));
   if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, xx, s));
-  M.lz_iters = iters;
+  (void)iters;
   M.rho_from = M.pc_from = 1 << 20;
   return TTN_OK;
 }
@@ -1402,7 +1457,8 @@ void sync_group_state(Ctx& c, const Ctx::Group& G) {
   for (size_t i = 1; i < G.members.size(); ++i) {
     Member& M = c.m[G.members[i]];
     M.rho_from = L.rho_from; M.pc_from = L.pc_from; M.dressed_tau = L.dressed_tau; M.env_tau = L.env_tau;
-    M.ops_upto = L.ops_upto; M.rb_cur = L.rb_cur; M.lz_iters = L.lz_iters; M.qw_valid = L.qw_valid;
+    M.ops_upto = L.ops_upto; M.rb_cur = L.rb_cur; M.qw_valid = L.qw_valid;
+    M.bytes_layers = L.bytes_layers; M.bytes_top = L.bytes_top;
   }
 }
 
@@ -1420,6 +1476,7 @@ ttn_status for_groups(Ctx& c, F f) {
 
 // The layer part of one sweep for one member on stream s.
 ttn_status sweep_layers(Member& M, hipStream_t s) {
+  ByteCount bc(M, M.bytes_layers);
   ttn_status st;
   if ((st = stage_descend_rho(M, s))) return st;
   for (int t = 1; t < M.n; ++t) {
@@ -1444,6 +1501,7 @@ ttn_status sweep_layers(Member& M, hipStream_t s) {
 // update moves its rotation into the layer above (or v), already updated in
 // this pass: the state is the same.
 ttn_status sweep_layers_grouped(Member& M, int groups, hipStream_t s) {
+  ByteCount bc(M, M.bytes_layers);
   const int n = M.n;
   ttn_status st;
   for (int gi = 0; gi < groups; ++gi) {
@@ -1505,6 +1563,17 @@ ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
   return TTN_OK;
 }
 
+// The top update of every member (launch group by launch group) on stream s;
+// *all (may be null) receives whether every member converged (with sync).
+ttn_status top_all(Ctx& c, hipStream_t s, bool sync, bool* all) {
+  return for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
+    bool conv = false;
+    ttn_status r = stage_update_top(M, s, &conv, sync);
+    if (!r && !conv && all) *all = false;
+    return r;
+  });
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1513,6 +1582,13 @@ ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
 struct ttn_ctx {
   Ctx c;
 };
+
+namespace ttn {
+// for the library's other sources: the stream a handle runs on, and the
+// calling thread's error message (what ttn_last_error returns)
+hipStream_t handle_stream(ttn_handle h) { return h ? h->c.s : nullptr; }
+ttn_status set_error(ttn_status st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace ttn
 
 extern "C" {
 
@@ -1640,7 +1716,7 @@ ttn_status ttn_ascend(ttn_handle h, int tau_from, int tau_to) {
   return TTN_OK;
 }
 
-ttn_status ttn_descend(ttn_handle h, int what, int tau) {
+ttn_status ttn_descend(ttn_handle h, int tau, int what) {
   if (!h) return fail(TTN_EINVAL, "null handle");
   if (what == TTN_DESCEND_RHO)
     return for_groups(h->c, [&](Member& M, const Ctx::Group&) -> ttn_status { return stage_descend_rho(M, h->c.s); });
@@ -1688,12 +1764,17 @@ ttn_status ttn_update(ttn_handle h, int tau) {
 ttn_status ttn_energy(ttn_handle h, double* e) {
   if (!h || !e) return fail(TTN_EINVAL, "bad arguments");
   HIPCHK(hipStreamSynchronize(h->c.s));
-  bool bad = false, evd_loss = false;
+  bool bad = false, evd_loss = false, noconv = false;
   for (size_t i = 0; i < h->c.m.size(); ++i) {
     double sc[SCAL_N];
     HIPCHK(hipMemcpy(sc, h->c.m[i].scal, sizeof sc, hipMemcpyDeviceToHost));
+    int done = 0;
+    HIPCHK(hipMemcpy(&done, h->c.m[i].lzint + LZ_DONE, sizeof done, hipMemcpyDeviceToHost));
+    noconv |= done == 0;
     e[i] = sc[SCAL_E];
     if (sc[SCAL_ERR] != 0.0) return fail(TTN_EHIP, "a Jacobi eigensolver aborted (grid barrier wait exceeded its bound)");
+    if (sc[SCAL_NOCONV] != 0.0)
+      return fail(TTN_ENOCONV, "a polar Jacobi solve used all %d of its sweeps without converging", POLAR_JACOBI_SWEEPS);
     // rounding of a x a rotations grows like eps a^(3/2) in the Frobenius norm
     const Member& M = h->c.m[i];
     const double amax = (double)*std::max_element(M.dims.begin(), M.dims.end());
@@ -1705,6 +1786,7 @@ ttn_status ttn_energy(ttn_handle h, double* e) {
   // the environment is ill conditioned: a warning, not an error
   if (evd_loss) return fail(TTN_WRANK, "an isometry from the eigenvalue-decomposition update is orthonormal only to "
                                        "the precision of the squared environment");
+  if (noconv) return fail(TTN_WNOCONV, "the last top update stopped at its restart budget above its residual target");
   return TTN_OK;
 }
 
@@ -1725,6 +1807,7 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
         if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
         st = sweep_layers_all(c, c.cap_s);
+        if (!st) st = top_all(c, c.cap_s, false, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c.cap_s, &g);
         if (st) {
@@ -1736,16 +1819,14 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
         HIPCHK(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
       }
       HIPCHK(hipGraphLaunch(c.gexec, c.s));
+      // the top update ran inside the graph; its convergence is reported by
+      // ttn_energy
     } else {
       if ((st = sweep_layers_all(c, c.s))) return st;
+      bool all = true;
+      if ((st = top_all(c, c.s, true, &all))) return st;
+      if (!all) warn = TTN_WNOCONV;
     }
-    st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
-      bool conv = false;
-      ttn_status r = stage_update_top(M, c.s, &conv);
-      if (!r && !conv) warn = TTN_WNOCONV;
-      return r;
-    });
-    if (st) return st;
   }
   return warn;
 }
@@ -1779,6 +1860,7 @@ ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_grap
         if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
         st = grouped_layers_all(c, groups, c.cap_s);
+        if (!st) st = top_all(c, c.cap_s, false, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c.cap_s, &g);
         if (st) {
@@ -1792,14 +1874,10 @@ ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_grap
       HIPCHK(hipGraphLaunch(ge, c.s));
     } else {
       if ((st = grouped_layers_all(c, groups, c.s))) return st;
+      bool all = true;
+      if ((st = top_all(c, c.s, true, &all))) return st;
+      if (!all) warn = TTN_WNOCONV;
     }
-    st = for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
-      bool conv = false;
-      ttn_status r = stage_update_top(M, c.s, &conv);
-      if (!r && !conv) warn = TTN_WNOCONV;
-      return r;
-    });
-    if (st) return st;
   }
   return warn;
 }
@@ -1907,7 +1985,11 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out) {
   out->shift = M.c;
   layer_flops(M, &out->flops_bulk, &out->flops_fp64);
   out->n_levels = M.n;
-  out->lanczos_iters = M.lz_iters;
+  int lzi[2] = {0, 0};  // converged flag, restarts run
+  HIPCHK(hipMemcpy(lzi, M.lzint + LZ_DONE, sizeof lzi, hipMemcpyDeviceToHost));
+  out->lanczos_iters = lzi[1] * (int)std::min<long long>(M.krylov, (long long)M.dims[M.n - 1] * M.dims[M.n - 1]);
+  out->e_prev = sc[SCAL_EPREV];
+  out->bytes_hbm = M.bytes_layers + M.bytes_top;
   int ji[18];
   HIPCHK(hipMemcpy(ji, M.jinfo, sizeof ji, hipMemcpyDeviceToHost));
   out->jacobi_sweeps[0] = ji[0];
@@ -1924,12 +2006,26 @@ ttn_status ttn_autotune(int mode, int* entries) {
   return TTN_OK;
 }
 
+ttn_status ttn_autotune_save(const char* path) {
+  if (!path) return fail(TTN_EINVAL, "null path");
+  if (!gemm_tune_save(path)) return fail(TTN_EINVAL, "cannot write the launch table to %s", path);
+  return TTN_OK;
+}
+
+ttn_status ttn_autotune_load(const char* path, int* entries) {
+  if (!path) return fail(TTN_EINVAL, "null path");
+  const int n = gemm_tune_load(path);
+  if (n < 0) return fail(TTN_EINVAL, "cannot read a launch table from %s", path);
+  if (entries) *entries = n;
+  return TTN_OK;
+}
+
 ttn_status ttn_profile(ttn_handle h, int enable) {
   if (!h) return fail(TTN_EINVAL, "null handle");
   Profiler& P = h->c.prof;
   if (enable) {
     if (P.ev.empty()) {
-      const size_t cap = 1 << 15;
+      const size_t cap = 1 << 16;
       P.ev.resize(2 * cap);
       for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
       P.cls.resize(cap);
@@ -1970,7 +2066,13 @@ ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entrie
     if (agg[c].launches) out[n++] = agg[c];
   *n_out = n;
   P.used = 0;
-  return P.dropped ? fail(TTN_OK, "%d launches were not timed (event pool full)", P.dropped) : TTN_OK;
+  if (P.dropped) {
+    const int d = P.dropped;
+    P.dropped = 0;
+    return fail(TTN_WPROF, "%d launches were not timed (event pool of %zu full): the record is incomplete", d,
+                P.cls.size());
+  }
+  return TTN_OK;
 }
 
 // The spectrum and entropy of the matrix on the upper bond of a block of

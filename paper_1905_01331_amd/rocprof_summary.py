@@ -137,7 +137,9 @@ def main():
         fetch = sum(kf) / len(kf) * 1024.0 * f_scale
         write = sum(kw) / len(kw) * 1024.0 * w_scale
         alg = rf["bytes_per_launch"]
-        rec = {"kernel": kernel, "workload": bench["config"]["workload"], "launches": n,
+        # keyed as bench.py looks it up: the workload's description and its precision
+        rec = {"kernel": kernel, "workload": f"{bench['config']['workload']} {bench['config']['precision']}",
+               "launches": n,
                "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
                "traffic_bytes_per_launch": fetch + write, "algorithmic_bytes_per_launch": alg,
                "fetch_scale": f_scale, "write_scale": w_scale, "sources_sha256": sources_sha256()}

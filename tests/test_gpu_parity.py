@@ -45,6 +45,9 @@ CASES = [
     ("xxx_L32_chi256", I.xxx_chain(), 32, 256),
     # the critical TFIM chain workload at its full size (L = 1024, chi = 64)
     ("tfim_L1024_chi64_full", I.tfim_chain(1.0), 1024, 64),
+    # the paper's site type: torus columns of 5 spins (d = 32, five product
+    # terms), h = 2.9
+    ("torus16x5_chi64_paper_sites", I.torus_tfim_column(5, 2.9), 16, 64),
 ]
 
 
@@ -59,7 +62,9 @@ def test_stage_parity_fp64(B, name, model, L, chi):
     e = gpu.energy()[0]
     assert abs(e - ref.history[0]) <= 1e-12 * abs(ref.history[0]) + 1e-14
     st = gpu.stats()
-    assert st.shift == pytest.approx(ref.c, abs=1e-13)
+    # the host's shift solver (dense Jacobi, or restarted Lanczos above
+    # 64 x 64) agrees with a dense LAPACK solver to about 1e-15 relative
+    assert st.shift == pytest.approx(ref.c, rel=2e-14, abs=1e-13)
     for lvl in range(n):
         assert rel_err(gpu.get_operator(lvl, B.TTN_OP_H), ref.hs[lvl]) < 1e-12
         for k in range(model.D):
@@ -173,6 +178,61 @@ def test_unanchored_sweeps_well_conditioned(B, keep_gauge):
     diff = np.abs(np.array(e) - np.array(hist)) / np.abs(hist)
     print("  step-matched relative differences", diff)
     assert diff.max() <= 1e-10
+    gpu.close()
+
+
+def test_cfg1_thirty_sweeps_against_the_oracle_and_ed(B):
+    """The TFIM chain L = 16 at chi = 8 from seeded random isometries, 30
+    sweeps on the GPU and in the oracle, compared sweep by sweep.  The top
+    layer's environment is nearly singular here (sigma_min / sigma_max near
+    1e-10 in the first sweeps), so its polar factor is fixed only up to about
+    eps / r in its weakest directions, and two correct implementations
+    separate by more than 1e-10 (A13): the oracle run twice, with LAPACK's
+    gesdd and gesvd SVD drivers, already differs by up to 5e-8.  Bars: at
+    every sweep the A13 bar of the anchored sweeps, max(1e-10, eps / (10 r))
+    with r the smallest ratio the oracle met so far; after the 30 sweeps the
+    GPU within 10 times the largest spread of the two LAPACK runs.  The energy
+    must fall every sweep and stay above the exact ground energy."""
+    import json
+    import os
+    import scipy.linalg as sl
+    model, L, chi = I.tfim_chain(1.0), 16, 8
+    ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 0)
+    ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ws=[w.copy() for w in ws])
+    h_dd = np.array(ref.run(30))
+
+    def gesvd_update(env):
+        a = env.shape[0]
+        U, s, Vt = sl.svd(env.reshape(a, -1), full_matrices=False, lapack_driver="gesvd")
+        return -(U @ Vt).reshape(env.shape), s
+
+    saved = T.polar_update
+    T.polar_update = gesvd_update
+    try:
+        ref2 = T.TTNRef(L, chi, model.h1, model.A, model.B, ws=[w.copy() for w in ws])
+        h_vd = np.array(ref2.run(30))
+    finally:
+        T.polar_update = saved
+    gpu = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
+    e = [gpu.energy()[0]]
+    for _ in range(30):
+        gpu.sweep(1)
+        e.append(gpu.energy()[0])
+    e = np.array(e)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ed_energies.json")))
+    e_ed = gold["tfim_chain_L16_h1"] / L
+    spread = np.abs(h_dd - h_vd) / np.abs(h_dd)
+    diff = np.abs(e - h_dd) / np.abs(h_dd)
+    r_sweep = np.array([1.0] + [float(np.min(d["sigma_ratio"])) for d in ref.diag])
+    bar = np.maximum(1e-10, np.finfo(np.float64).eps / (10.0 * np.minimum.accumulate(r_sweep)))
+    print("  relative difference per sweep", np.array2string(diff, precision=2))
+    print("  gesdd-gesvd spread per sweep ", np.array2string(spread, precision=2))
+    print(f"  sweep 30: gpu {e[-1]:.13f} oracle {h_dd[-1]:.13f} (gesvd {h_vd[-1]:.13f}), ED {e_ed:.13f}")
+    assert diff[0] <= 1e-12
+    assert np.all(diff <= bar), np.flatnonzero(diff > bar)
+    assert diff[-1] <= max(1e-10, 10.0 * spread.max())
+    assert np.all(e[1:] <= e[:-1] + 1e-13 * np.abs(e[:-1]))
+    assert e[-1] >= e_ed - 1e-12
     gpu.close()
 
 

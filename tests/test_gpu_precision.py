@@ -54,6 +54,9 @@ CASES = [
     ("torus8x4_chi64", I.torus_tfim_column(4, 3.0), 8, 64),
     ("xxx_L64_chi48", I.xxx_chain(), 64, 48),
     ("tfim_L32_chi160", I.tfim_chain(0.8), 32, 160),
+    # the paper's site type: torus columns of 5 spins (d = 32, five product
+    # terms), h = 2.9
+    ("torus16x5_chi64_paper_sites", I.torus_tfim_column(5, 2.9), 16, 64),
 ]
 
 
