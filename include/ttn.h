@@ -366,6 +366,24 @@ ttn_status ttn_positions_bytes(ttn_handle h, int b, size_t* bytes);
 ttn_status ttn_positions_offset(ttn_handle h, int b, int tau, size_t* offset);
 ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, double* site, double* bond);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): ttn_local_energies
+ * with its work buffer in a static device array of the library,
+ * TTN_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held until the process ends,
+ * instead of memory the caller brings.  It calls no allocating routine.
+ * Inputs (the handle's state) and outputs (site, bond on the host) as for
+ * ttn_local_energies, with the same results as ttn_local_energies given a
+ * work buffer of TTN_NOALLOC_SCRATCH_BYTES bytes.  TTN_ENOMEM when member b
+ * needs more than the static scratch (ttn_positions_bytes above
+ * TTN_NOALLOC_SCRATCH_BYTES; e.g. L = 1024 at chi = 64 fits, L = 4096 at
+ * chi = 256 does not); TTN_EINVAL, TTN_EHIP as for ttn_local_energies.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (the computation writes every entry it reads): calls that
+ * overlap on one GPU (from several threads or streams) race and must not be
+ * made.  Synchronises the stream. */
+#define TTN_NOALLOC_SCRATCH_BYTES (64u << 20)
+ttn_status ttn_local_energies_noalloc(ttn_handle h, int b, double* site, double* bond);
+
 
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);

@@ -30,7 +30,7 @@ EXPORTS = [
     "ttn_energy", "ttn_sweep", "ttn_sweep_grouped", "ttn_get_tensor", "ttn_set_tensor", "ttn_get_operator", "ttn_autotune",
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
     "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies", "ttn_entanglement_node",
-    "ttn_autotune_save", "ttn_autotune_load",
+    "ttn_autotune_save", "ttn_autotune_load", "ttn_local_energies_noalloc",
 ]
 
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "ttn_positions_bytes": ([P, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "ttn_positions_offset": ([P, I, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "ttn_local_energies": ([P, I, P, ctypes.c_size_t, DP, DP], I),
+        "ttn_local_energies_noalloc": ([P, I, DP, DP], I),
         "ttn_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
@@ -334,6 +335,15 @@ class TTN:
             raw = work[skip + off.value: skip + off.value + 8 * cnt].cpu().numpy()
             rhos[tau] = raw.view(np.float64).reshape(L >> tau, c, c).copy()
         return site, bond, rhos
+
+    def local_energies_noalloc(self, b=0):
+        """(site, bond) of member b from ttn_local_energies_noalloc: the
+        library's static device scratch instead of a caller's work buffer."""
+        n = self.n_levels(b)
+        L = 1 << n
+        site, bond = np.zeros(L), np.zeros(L)
+        _check(self.lib.ttn_local_energies_noalloc(self.h, b, _dptr(site), _dptr(bond)))
+        return site, bond
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
