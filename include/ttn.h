@@ -190,16 +190,20 @@ ttn_status ttn_energy(ttn_handle h, double* e_per_site);
  * use_graph = 0: eager launches; update(TOP) reads its convergence on the
  * host after every restart and stops launching once every member converged
  * (TTN_WNOCONV when the restart budget ran out first).
- * use_graph != 0: the whole sweep, update(TOP) included, is captured into a
- * HIP graph on the first such call and replayed on every later one with no
- * host synchronisation: the polar update's optional extra refresh and the
- * top solver's restarts are decided on the device (every restart of the
- * budget is in the graph; a flag set when the residual meets its target
- * makes the kernels of the later restarts return at once), and ttn_energy
- * reports a top update that did not converge.  The graph refers to the
- * handle's workspace only, so ttn_set_tensor between sweeps is honoured.
- * Ignored while profiling is on.  Results are identical with and without the
- * graph. */
+ * use_graph != 0: the layer part is captured into a HIP graph on the first
+ * such call and replayed on every later one; it holds no host
+ * synchronisation (the polar update's optional extra refresh is decided on
+ * the device).  The top update is replayed from a second graph that holds a
+ * planned number of Lanczos restarts: a flag set on the device when the
+ * residual meets its target makes the kernels of the later restarts return
+ * at once.  use_graph = 2: the plan is the whole restart budget, and nothing
+ * is read back (ttn_energy reports a top update that did not converge).
+ * use_graph = 1: the plan is the number of restarts the slowest member has
+ * needed so far (one graph per plan, kept); one host read after the replay
+ * runs the rest of the budget eagerly for a member that needs more, and
+ * raises the plan.  The graphs refer to the handle's workspace only, so
+ * ttn_set_tensor between sweeps is honoured.  Ignored while profiling is on.
+ * Results are identical in every mode. */
 ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
 
 /* nsweeps grouped sweeps: a schedule of our own beside the paper's (the
@@ -215,10 +219,10 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph);
  * chain per layer in ttn_sweep.  groups = 1 updates neighbouring
  * layers from the same state and may raise the energy of strongly coupled
  * models; groups = 2 keeps neighbours apart.  Batches run their launch groups
- * one after another on the handle's stream.  use_graph != 0: the whole
- * grouped sweep, update(TOP) included, is captured into a HIP graph (one per
- * grouping) on the first such call and replayed, as in ttn_sweep; results are
- * identical with and without it.
+ * one after another on the handle's stream.  use_graph != 0: the layer part
+ * is captured into a HIP graph (one per grouping) on the first such call and
+ * replayed, and update(TOP) as in ttn_sweep; results are identical in every
+ * mode.
  * TTN_EINVAL for groups outside {1, 2}; TTN_ESTATE when a level's operators
  * are stale; otherwise as ttn_sweep. */
 ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_graph);
@@ -263,8 +267,8 @@ ttn_status ttn_stats(ttn_handle h, int b, ttn_stats_t* out);
 /* Autotuning of the contraction launches, for the whole process (all
  * handles).  mode 0: default launch shapes (default); 1: the first time a
  * product of a new shape and layout is run eagerly (not under graph capture)
- * with beta = 0, its candidate launch shapes (float64 output tile 64 x 64 or
- * 128 x 128; the order in which tiles are handed to the XCDs) are timed with
+ * with beta = 0, its candidate launch shapes (float64 output tile 64 x 64,
+ * 128 x 64 or 64 x 128; the order in which tiles are handed to the XCDs) are timed with
  * HIP events on the handle's stream (this synchronises that stream) and the
  * fastest is kept; 2: kept choices only.  Kept choices are used in every mode
  * but 0, also inside captured graphs.  mode -1 leaves the mode unchanged.
@@ -383,7 +387,6 @@ ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, dou
  * made.  Synchronises the stream. */
 #define TTN_NOALLOC_SCRATCH_BYTES (64u << 20)
 ttn_status ttn_local_energies_noalloc(ttn_handle h, int b, double* site, double* bond);
-
 
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);

@@ -235,10 +235,13 @@ class TTN:
         return out
 
     def sweep(self, nsweeps=1, graph=False):
-        return _check(self.lib.ttn_sweep(self.h, nsweeps, 1 if graph else 0))
+        """graph: False eager, True (or 1) graph replay with one host read per
+        sweep for the top solver's restarts, 2 graph replay with the whole
+        restart budget in the graph and no host read."""
+        return _check(self.lib.ttn_sweep(self.h, nsweeps, int(graph)))
 
     def sweep_grouped(self, nsweeps=1, groups=2, graph=False):
-        return _check(self.lib.ttn_sweep_grouped(self.h, nsweeps, groups, 1 if graph else 0))
+        return _check(self.lib.ttn_sweep_grouped(self.h, nsweeps, groups, int(graph)))
 
     # access -----------------------------------------------------------------
     def bond_dim(self, tau, b=0):

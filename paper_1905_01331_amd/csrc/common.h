@@ -109,11 +109,10 @@ struct KernelTimer {
 };
 KernelTimer*& kernel_timer();
 enum { KID_MFMA = 0,     // + 4 * (mode - 1) + 2 * akc + bkc  (mode 1: float32, 2: split-bf16)
-       KID_MFMA64 = 8,   // + 2 * akc + bkc
-       KID_PLAIN = 12,   // + precision
-       KID_REDUCE = 15,  // split-K reductions: + 0 float, + 1 double
-       KID_MFMA64S = 17, // + 2 * akc + bkc: the 64 x 64 tile float64 kernel
-       KID_N = 21 };
+       KID_F64 = 8,      // + 4 * tile + 2 * akc + bkc  (tile 0: 64 x 64, 1: 128 x 64, 2: 64 x 128)
+       KID_PLAIN = 20,   // + precision
+       KID_REDUCE = 23,  // split-K reductions: + 0 float, + 1 double
+       KID_N = 25 };
 const char* kernel_name(int kid);
 
 // Launches one product in the given arithmetic.  F64: double operands and

@@ -3,9 +3,9 @@
 
 namespace ttn {
 hipError_t gemm_plain(Prec prec, const GemmDesc& g, void* scratch, size_t scratch_bytes, hipStream_t s);
-// Launch shape of an MFMA product: the output tile (float64: 64 or 128, 0 for
-// the default) and the order in which tiles are handed out (0 default, 1 x
-// fastest, 2 y fastest).  Every choice computes every output element with
+// Launch shape of an MFMA product: the output tile (float64: 1 64 x 64,
+// 2 128 x 64, 3 64 x 128; 0 the default, 64 x 64) and the order in which tiles
+// are handed out (0 default, 1 x fastest, 2 y fastest).  Every choice computes every output element with
 // the same instruction sequence and the same split-K partition, so results
 // are identical bit for bit; only the speed differs.
 struct GemmLaunch {

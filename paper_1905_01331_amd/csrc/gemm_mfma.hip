@@ -394,12 +394,21 @@ __global__ __launch_bounds__(NT) void gemm_mfma_kernel(GemmDesc g, int splits, i
 
 
 // ---------------------------------------------------------------------------
-// float64: v_mfma_f64_16x16x4_f64, 128 x 128 tile, BK = 16, 2 x 2 waves of
-// 64 x 64 (4 x 4 blocks of 16 x 16).  Lane l of a block holds
-// A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 r][l % 16].
+// float64: v_mfma_f64_4x4x4_4b_f64, four independent 4 x 4 x 4 products per
+// instruction.  On gfx950 this form runs at about 0.9 of the float64 peak in
+// a loop of independent products, against about 0.6 for the 16 x 16 x 4
+// form, so every float64 product uses it.  Lane layout (measured with
+// one-hot operands): lane l holds A_b[l % 4][l / 16] and B_b[l / 16][l % 4]
+// of block b = (l / 4) % 4 and receives D_b[l / 16][l % 4].  The four blocks
+// are stacked along M, so one instruction multiplies a 16 x 4 slice of A by
+// a 4 x 4 slice of B: lane l reads A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 4], and its result is C[4 ((l / 4) % 4) + l / 16][l % 4].
+// A wave owns RI x RJ such units (16 RI rows, 4 RJ columns), 2 x 2 waves a
+// work-group.  BK = 16 contraction indices per LDS chunk, two LDS buffers
+// (one barrier per chunk).  Every tile issues the same instruction sequence
+// for an output element, so the tile is a launch choice only.
 // ---------------------------------------------------------------------------
 typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int BK64 = 16;
 
 struct OpView64 {
@@ -413,9 +422,18 @@ __device__ __forceinline__ long long k_offset64(const OpView64& v, int k) {
   return (long long)k1 * v.s_k1 + (long long)(k - k1 * v.K2) * v.s_k;
 }
 
-template <bool KC, int T>
+// tile t: 0 64 x 64 (RI 2, RJ 8), 1 128 x 64 (RI 4, RJ 8), 2 64 x 128 (RI 2, RJ 16)
+template <int TILE> struct Tile64;
+template <> struct Tile64<0> { static constexpr int RI = 2, RJ = 8; };
+template <> struct Tile64<1> { static constexpr int RI = 4, RJ = 8; };
+template <> struct Tile64<2> { static constexpr int RI = 2, RJ = 16; };
+
+// Register staging of one operand tile (MN x BK64 doubles): float64 pairs
+// along k (contraction-contiguous) or along mn (output-contiguous), written
+// to LDS as [k][mn].
+template <bool KC, int MN>
 struct Stage64 {
-  static constexpr int NV = (T * BK64) / (2 * NT);  // double2 per thread (4 at T = 128, 2 at T = 64)
+  static constexpr int NV = (MN * BK64) / (2 * NT);
   f64x2 r[NV];
   __device__ __forceinline__ void load(const OpView64& v, int mn0, int k0, int kend, int tid) {
 #pragma unroll
@@ -423,7 +441,7 @@ struct Stage64 {
       int f = tid + i * NT;
       int mn, k;
       if constexpr (KC) { mn = f / (BK64 / 2); k = (f % (BK64 / 2)) * 2; }
-      else              { k = f / (T / 2); mn = (f % (T / 2)) * 2; }
+      else              { k = f / (MN / 2); mn = (f % (MN / 2)) * 2; }
       int gm = mn0 + mn, gk = k0 + k;
       if (gm < v.MN && gk < kend) {
         const double* p = KC ? v.base + (long long)gm * v.s_mn + k_offset64(v, gk) : v.base + gm + k_offset64(v, gk);
@@ -433,7 +451,7 @@ struct Stage64 {
       }
     }
   }
-  __device__ __forceinline__ void store(double (*pl)[T + 2], int tid) const {
+  __device__ __forceinline__ void store(double (*pl)[MN + 2], int tid) const {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int f = tid + i * NT;
@@ -442,23 +460,20 @@ struct Stage64 {
         pl[k][mn] = r[i][0];
         pl[k + 1][mn] = r[i][1];
       } else {
-        int k = f / (T / 2), mn = (f % (T / 2)) * 2;
+        int k = f / (MN / 2), mn = (f % (MN / 2)) * 2;
         *reinterpret_cast<f64x2*>(&pl[k][mn]) = r[i];
       }
     }
   }
 };
 
-// T x T output tile per 256-thread work-group, 2 x 2 waves of T/2 x T/2 as
-// (T/32) x (T/32) blocks of 16 x 16.  T = 128 for large products; T = 64
-// gives small products four times the work-groups at a quarter of the
-// registers per wave.
-template <bool AKC, bool BKC, int T>
-__global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial,
-                                                        TileMap tm) {
-  constexpr int NBK = T / 32;  // 16 x 16 blocks per wave and dimension
-  __shared__ double sa_l[BK64][T + 2];
-  __shared__ double sb_l[BK64][T + 2];
+template <bool AKC, bool BKC, int TILE>
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmDesc g, int splits, int kchunk, double* __restrict__ partial,
+                                                     TileMap tm) {
+  constexpr int RI = Tile64<TILE>::RI, RJ = Tile64<TILE>::RJ;
+  constexpr int WM = 16 * RI, WN = 4 * RJ, TM = 2 * WM, TN = 2 * WN;
+  __shared__ double sa_l[2][BK64][TM + 2];
+  __shared__ double sb_l[2][BK64][TN + 2];
   int tx, ty, bz;
   if (!map_tile(tm, tx, ty, bz)) return;
   {  // launch-group member: outermost index
@@ -470,96 +485,110 @@ __global__ __launch_bounds__(NT) void gemm_mfma64_kernel(GemmDesc g, int splits,
   }
   if (g.skip && gload(g.skip)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * (T / 2), wn = (wave >> 1) * (T / 2);
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
   const int b = bz / splits, sp = bz - b * splits;
-  const int m0 = ty * T, n0 = tx * T;
+  const int m0 = ty * TM, n0 = tx * TN;
   const int kbeg = sp * kchunk;
   const int kend = min(g.K, kbeg + kchunk);
   OpView64 va{(const double*)g.A + batch_offset(g, b, g.sAb, g.sAb2), g.sAm, g.sAk, g.sAk1, g.M, g.K2};
   OpView64 vb{(const double*)g.B + batch_offset(g, b, g.sBb, g.sBb2), g.sBn, g.sBk, g.sBk1, g.N, g.K2};
-  f64x4 acc[NBK][NBK];
+  double acc[RI][RJ];
 #pragma unroll
-  for (int i = 0; i < NBK; ++i)
+  for (int i = 0; i < RI; ++i)
 #pragma unroll
-    for (int j = 0; j < NBK; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  Stage64<AKC, T> sa;
-  Stage64<BKC, T> sb;
+    for (int j = 0; j < RJ; ++j) acc[i][j] = 0.0;
+  Stage64<AKC, TM> sa;
+  Stage64<BKC, TN> sb;
+  const int lk = lane >> 4, la = lane & 15, lbn = lane & 3;
   if (kbeg < kend) {
     sa.load(va, m0, kbeg, kend, tid);
     sb.load(vb, n0, kbeg, kend, tid);
+    sa.store(sa_l[0], tid);
+    sb.store(sb_l[0], tid);
   }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK64) {
-    sa.store(sa_l, tid);
-    sb.store(sb_l, tid);
-    __syncthreads();
-    if (k0 + BK64 < kend) {
+    const bool more = k0 + BK64 < kend;
+    if (more) {
       sa.load(va, m0, k0 + BK64, kend, tid);
       sb.load(vb, n0, k0 + BK64, kend, tid);
     }
 #pragma unroll
     for (int kk = 0; kk < BK64; kk += 4) {
-      double a[NBK], bv[NBK];
+      double av[RI], bv[RJ];
 #pragma unroll
-      for (int i = 0; i < NBK; ++i) a[i] = sa_l[kk + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < RI; ++i) av[i] = sa_l[buf][kk + lk][wm + 16 * i + la];
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) bv[j] = sb_l[kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < RJ; ++j) bv[j] = sb_l[buf][kk + lk][wn + 4 * j + lbn];
 #pragma unroll
-      for (int i = 0; i < NBK; ++i)
+      for (int i = 0; i < RI; ++i)
 #pragma unroll
-        for (int j = 0; j < NBK; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < RJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      sa.store(sa_l[buf ^ 1], tid);
+      sb.store(sb_l[buf ^ 1], tid);
     }
     __syncthreads();
+    buf ^= 1;
   }
-  const int col_l = lane & 15, row_l = lane >> 4;
+  // lane l's result of unit (i, j): row wm + 16 i + 4 ((l / 4) % 4) + l / 16,
+  // column wn + 4 j + l % 4
+  const int row_l = 4 * ((lane >> 2) & 3) + lk;
   if (splits == 1) {
     double* C = (double*)g.C + batch_offset(g, b, g.sCb, g.sCb2);
 #pragma unroll
-    for (int i = 0; i < NBK; ++i)
+    for (int i = 0; i < RI; ++i) {
+      const int m = m0 + wm + 16 * i + row_l;
+      if (m >= g.M) continue;
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) {
-        int n = n0 + wn + 16 * j + col_l;
+      for (int j = 0; j < RJ; ++j) {
+        const int n = n0 + wn + 4 * j + lbn;
         if (n >= g.N) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int m = m0 + wm + 16 * i + row_l + 4 * r;
-          if (m >= g.M) continue;
-          double* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
-          double v = g.alpha * acc[i][j][r];
-          if (g.beta != 0.0) v += g.beta * gload(c);
-          gstore(c, v);
-        }
+        double* c = C + (long long)m * g.sCm + (long long)n * g.sCn;
+        double v = g.alpha * acc[i][j];
+        if (g.beta != 0.0) v += g.beta * gload(c);
+        gstore(c, v);
       }
+    }
   } else {
     double* P = partial + ((long long)sp * g.batch + b) * (long long)g.M * g.N;
 #pragma unroll
-    for (int i = 0; i < NBK; ++i)
+    for (int i = 0; i < RI; ++i) {
+      const int m = m0 + wm + 16 * i + row_l;
+      if (m >= g.M) continue;
 #pragma unroll
-      for (int j = 0; j < NBK; ++j) {
-        int n = n0 + wn + 16 * j + col_l;
-        if (n >= g.N) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          int m = m0 + wm + 16 * i + row_l + 4 * r;
-          if (m >= g.M) continue;
-          gstore(P + (long long)m * g.N + n, acc[i][j][r]);
-        }
+      for (int j = 0; j < RJ; ++j) {
+        const int n = n0 + wn + 4 * j + lbn;
+        if (n < g.N) gstore(P + (long long)m * g.N + n, acc[i][j]);
       }
+    }
   }
 }
 
-template <bool AKC, bool BKC, int T>
+template <bool AKC, bool BKC, int TILE>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s, int orient) {
-  const TileMap tm = make_map((g.N + T - 1) / T, (g.M + T - 1) / T, g.batch * splits * gemm_members(g), orient);
+  constexpr int TM = 32 * Tile64<TILE>::RI, TN = 8 * Tile64<TILE>::RJ;
+  const TileMap tm = make_map((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.batch * splits * gemm_members(g), orient);
   size_t slot = 0;
   KernelTimer* kt = kernel_timer();
   const double work = (double)g.batch * gemm_members(g);
-  const int kid = (T == 128 ? KID_MFMA64 : KID_MFMA64S) + 2 * AKC + BKC;
+  const int kid = KID_F64 + 4 * TILE + 2 * AKC + BKC;
   const bool timed = kt && kt->begin(kid, 2.0 * g.M * (double)g.N * g.K * work,
                                      8.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
-  hipLaunchKernelGGL((gemm_mfma64_kernel<AKC, BKC, T>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
+  hipLaunchKernelGGL((gemm_f64_kernel<AKC, BKC, TILE>), dim3(N_XCD * tm.per), dim3(NT), 0, s, g, splits, kchunk,
                      partial, tm);
   if (timed) kt->end(slot, s);
   return hipGetLastError();
+}
+
+template <bool AKC, bool BKC>
+hipError_t launch64_tile(int tile, const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s,
+                         int orient) {
+  if (tile == 1) return launch64<AKC, BKC, 1>(g, splits, kchunk, partial, s, orient);
+  if (tile == 2) return launch64<AKC, BKC, 2>(g, splits, kchunk, partial, s, orient);
+  return launch64<AKC, BKC, 0>(g, splits, kchunk, partial, s, orient);
 }
 
 template <int MODE, bool AKC, bool BKC>
@@ -624,29 +653,18 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   else     { if (g.M % 2 || g.sAk % 2 || (g.K2 > 0 && g.sAk1 % 2)) return hipErrorNotSupported; }
   if (bkc) { if (g.K % 2 || g.sBn % 2 || (g.K2 > 0 && (g.K2 % 2 || g.sBk1 % 2))) return hipErrorNotSupported; }
   else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
-  // small products (few 128 x 128 tiles) and short contractions (K <= 2048:
-  // four work-groups per CU hide each tile's loads and stores, which a short
-  // k loop cannot) take 64 x 64 tiles by default.  Both tiles issue the same
-  // MFMA sequence for every output element, so the tile is a launch choice
-  // only; the split count follows the default tile.
-  const int T0 = ((long long)((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch < 64 || g.K <= 2048) ? 64 : 128;
+  // the split count follows the shape alone (counted at 64 x 64 tiles); the
+  // tile (64 x 64 by default) is a launch choice
   int kchunk = 0;
-  const int splits = split_count(g, T0, BK64, sizeof(double), scratch_bytes, &kchunk);
-  const int T = how.tile == 64 || how.tile == 128 ? how.tile : T0;
+  const int splits = split_count(g, 64, BK64, sizeof(double), scratch_bytes, &kchunk);
+  const int tile = how.tile >= 1 && how.tile <= 3 ? how.tile - 1 : 0;
   double* partial = (double*)scratch;
   const int o = how.orient;
   hipError_t e;
-  if (T == 64) {
-    if (akc && bkc) e = launch64<true, true, 64>(g, splits, kchunk, partial, s, o);
-    else if (akc) e = launch64<true, false, 64>(g, splits, kchunk, partial, s, o);
-    else if (bkc) e = launch64<false, true, 64>(g, splits, kchunk, partial, s, o);
-    else e = launch64<false, false, 64>(g, splits, kchunk, partial, s, o);
-  } else {
-    if (akc && bkc) e = launch64<true, true, 128>(g, splits, kchunk, partial, s, o);
-    else if (akc) e = launch64<true, false, 128>(g, splits, kchunk, partial, s, o);
-    else if (bkc) e = launch64<false, true, 128>(g, splits, kchunk, partial, s, o);
-    else e = launch64<false, false, 128>(g, splits, kchunk, partial, s, o);
-  }
+  if (akc && bkc) e = launch64_tile<true, true>(tile, g, splits, kchunk, partial, s, o);
+  else if (akc) e = launch64_tile<true, false>(tile, g, splits, kchunk, partial, s, o);
+  else if (bkc) e = launch64_tile<false, true>(tile, g, splits, kchunk, partial, s, o);
+  else e = launch64_tile<false, false>(tile, g, splits, kchunk, partial, s, o);
   if (e != hipSuccess) return e;
   if (splits > 1) return splitk_reduce_f64(g, splits, partial, s);
   return hipSuccess;

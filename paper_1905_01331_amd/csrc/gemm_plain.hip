@@ -296,12 +296,13 @@ const char* kernel_name(int kid) {
   static const char* const names[KID_N] = {
       "gemm_mfma_kernel<1, false, false>", "gemm_mfma_kernel<1, false, true>", "gemm_mfma_kernel<1, true, false>",
       "gemm_mfma_kernel<1, true, true>",   "gemm_mfma_kernel<2, false, false>", "gemm_mfma_kernel<2, false, true>",
-      "gemm_mfma_kernel<2, true, false>",  "gemm_mfma_kernel<2, true, true>",  "gemm_mfma64_kernel<false, false, 128>",
-      "gemm_mfma64_kernel<false, true, 128>", "gemm_mfma64_kernel<true, false, 128>", "gemm_mfma64_kernel<true, true, 128>",
+      "gemm_mfma_kernel<2, true, false>",  "gemm_mfma_kernel<2, true, true>",
+      "gemm_f64_kernel<false, false, 0>",  "gemm_f64_kernel<false, true, 0>",  "gemm_f64_kernel<true, false, 0>",
+      "gemm_f64_kernel<true, true, 0>",    "gemm_f64_kernel<false, false, 1>", "gemm_f64_kernel<false, true, 1>",
+      "gemm_f64_kernel<true, false, 1>",   "gemm_f64_kernel<true, true, 1>",   "gemm_f64_kernel<false, false, 2>",
+      "gemm_f64_kernel<false, true, 2>",   "gemm_f64_kernel<true, false, 2>",  "gemm_f64_kernel<true, true, 2>",
       "gemm_plain_kernel<double, 0>",      "gemm_plain_kernel<float, 0>",      "gemm_plain_kernel<float, 1>",
-      "splitk_reduce_kernel<float>", "splitk_reduce_kernel<double>",
-      "gemm_mfma64_kernel<false, false, 64>", "gemm_mfma64_kernel<false, true, 64>",
-      "gemm_mfma64_kernel<true, false, 64>", "gemm_mfma64_kernel<true, true, 64>"};
+      "splitk_reduce_kernel<float>",       "splitk_reduce_kernel<double>"};
   return (kid >= 0 && kid < KID_N) ? names[kid] : "?";
 }
 

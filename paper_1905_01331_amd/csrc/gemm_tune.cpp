@@ -6,8 +6,8 @@
 // neither operand (so that running it again gives the same result), every
 // candidate launch shape is timed with HIP events on that stream, three times
 // each, and the fastest is stored; the product is then run once more with
-// the stored choice.  Candidates: the output tile (float64: 64 x 64 or
-// 128 x 128) and the order in which tiles are handed to the XCDs (smaller
+// the stored choice.  Candidates: the output tile (float64: 64 x 64, 128 x 64
+// or 64 x 128) and the order in which tiles are handed to the XCDs (smaller
 // tile dimension fastest, x fastest, y fastest).  No candidate changes the
 // arithmetic: the split-K partition is fixed by the shape, and every tile
 // issues the same MFMA sequence for an output element, so a tuned launch
@@ -70,11 +70,10 @@ bool tune(Prec p, const GemmDesc& g, void* scratch, size_t bytes, hipStream_t s,
   }
   if (e != hipSuccess) return false;
   std::vector<GemmLaunch> cand;
-  const int tiles[2] = {64, 128};
-  for (int t = 0; t < (p == P_F64 ? 2 : 1); ++t)
+  for (int t = 0; t < (p == P_F64 ? 3 : 1); ++t)
     for (int o = 0; o < 3; ++o) {
       GemmLaunch c;
-      c.tile = p == P_F64 ? tiles[t] : 0;
+      c.tile = p == P_F64 ? t + 1 : 0;
       c.orient = o;
       cand.push_back(c);
     }
@@ -144,7 +143,7 @@ int gemm_tune_load(const char* path) {
   int got;
   while ((got = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lld %lld %d : %d %d", &v[0], &v[1], &v[2], &v[3],
                             &v[4], &v[5], &v[6], &v[7], &v[8], &v[9], &sa, &sb, &v[12], &c.tile, &c.orient)) == 15) {
-    if (c.tile != 0 && c.tile != 64 && c.tile != 128) break;
+    if (c.tile < 0 || c.tile > 3) break;
     if (c.orient < 0 || c.orient > 2) break;
     add[Key{v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], sa, sb, v[12]}] = c;
   }

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -350,10 +351,15 @@ struct Ctx {
   std::vector<Group> groups;
   hipStream_t grid_s = nullptr;          // serialises the persistent Jacobi solves of a batch
   hipStream_t cap_s = nullptr;           // stream the sweep graph is captured on
+  // graphs of the planned top update, by the number of restarts they hold,
+  // and the plan: the restarts the slowest member has needed so far
+  std::map<int, hipGraphExec_t> top_exec;
+  int top_plan = 1;
   std::vector<hipEvent_t> member_events;  // two per member, for grid_s
   ~Ctx() {
     if (kernel_timer() == &krec) kernel_timer() = nullptr;
     if (gexec) hipGraphExecDestroy(gexec);
+    for (auto& kv : top_exec) hipGraphExecDestroy(kv.second);
     if (graph) hipGraphDestroy(graph);
     for (int i = 0; i < 2; ++i) {
       if (ggexec[i]) hipGraphExecDestroy(ggexec[i]);
@@ -1231,16 +1237,17 @@ hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bo
   return mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s);  // + y h^T
 }
 
-// The top update.  Restarts after the one whose residual met the target do
-// nothing: a device flag (set by lz_mark_done) makes every kernel of a later
-// restart return at once.  With `sync` the host reads the flags after every
-// restart and stops launching once every member of the launch group has
-// converged (*converged tells whether they did); without it every restart of
-// the budget is launched and nothing is read back, so the update can be
-// captured into a graph (convergence is then read from the flag by
-// ttn_energy).  Both give the same arithmetic.
-ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged, bool sync = true) {
-  ByteCount bc(M, M.bytes_top);
+// The top update, in three parts.  top_prepare copies the top operators to
+// float64, makes them exactly symmetric (or antisymmetric) and clears the
+// convergence flag and the restart count; top_restarts runs Lanczos restarts;
+// top_finish fixes the sign of v and stores the energy.  Restarts after the
+// one whose residual met the target do nothing: a device flag (set by
+// lz_mark_done) makes every kernel of a later restart return at once.  With
+// `sync` the host reads the flags after every restart and stops launching once
+// every member of the launch group has converged (*converged tells whether
+// they did); without it `count` restarts are launched and nothing is read
+// back, so they can be captured into a graph.  Both give the same arithmetic.
+ttn_status top_prepare(Member& M, hipStream_t s) {
   const int n = M.n, x = M.dims[n - 1], D = M.D;
   const size_t xx = (size_t)x * x;
   if (M.prec == TTN_FP64) {
@@ -1263,16 +1270,21 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged, bool sync
     HIPCHK(symmetrize_f64(M.Aop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
     HIPCHK(symmetrize_f64(M.Bop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
   }
+  HIPCHK(zero_int(M.lzint + LZ_DONE, 2, s));  // the flag and the count of restarts run
+  return TTN_OK;
+}
+
+ttn_status top_restarts(Member& M, hipStream_t s, int count, bool sync, bool* converged) {
+  const int n = M.n, x = M.dims[n - 1];
+  const size_t xx = (size_t)x * x;
   const int m = (int)std::min<long long>(M.krylov, (long long)xx);
-  int iters = 0;
   *converged = false;
   // members of a launch group share the restart loop; a member whose
   // residual met the target sets its flag and every kernel of its later
   // restarts returns at once, so it ends with the vector it has alone
   int* done = M.lzint + LZ_DONE;
   const int* skip = done;
-  HIPCHK(zero_int(done, 2, s));  // the flag and the count of restarts run
-  for (int rs = 0; rs < M.restarts; ++rs) {
+  for (int rs = 0; rs < count; ++rs) {
     SkipScope skip_done(skip);
     // q_0 = v / ||v||
     HIPCHK(pair_f64(M.vtop, M.vtop, (long long)xx, M.scal + SCAL_TMP0, M.part, s));
@@ -1295,7 +1307,6 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged, bool sync
       HIPCHK(lz_reorth_final(M.lzW, M.lzQ, j + 1, xx, c1, c2, M.lzpart, M.lznrm, M.alpha, M.beta, 1e-14, M.lzint,
                              M.lzint + 1, M.lzQ + (size_t)(j + 1) * xx, j + 1 < m ? M.lzStage : nullptr, s));
     }
-    iters += m;
     HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
     HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, M.jscratch, s, skip));
     HIPCHK(lz_select_lowest(M.Tm, M.Vm, m, M.ycoef, M.scal + SCAL_THETA, s));
@@ -1334,14 +1345,31 @@ ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged, bool sync
       break;
     }
   }
-  if (!sync) *converged = true;  // not known here: ttn_energy reads the flag
+  if (!sync) *converged = true;  // not known here: read from the flag afterwards
+  return TTN_OK;
+}
+
+// keep_prev: the energy replaced is not the previous update's (a top update
+// continued after a first finish), so the stored previous energy stays
+ttn_status top_finish(Member& M, hipStream_t s, bool keep_prev = false) {
+  const int x = M.dims[M.n - 1];
+  const size_t xx = (size_t)x * x;
   HIPCHK(sign_fix(M.vtop, xx, s));
   HIPCHK(energy_store(M.scal + SCAL_LAM, M.scal + SCAL_SHIFT, (double)M.L, (double)M.ly, M.scal + SCAL_LAM,
-                      M.scal + SCAL_EPREV, s));
+                      keep_prev ? nullptr : M.scal + SCAL_EPREV, s));
   if (M.prec != TTN_FP64) HIPCHK(convert_f64_to_f32(M.vtop, (float*)M.vT, xx, s));
-  (void)iters;
   M.rho_from = M.pc_from = 1 << 20;
   return TTN_OK;
+}
+
+// The whole top update, eagerly: every restart of the budget until the
+// launch group has converged.
+ttn_status stage_update_top(Member& M, hipStream_t s, bool* converged) {
+  ByteCount bc(M, M.bytes_top);
+  ttn_status st;
+  if ((st = top_prepare(M, s))) return st;
+  if ((st = top_restarts(M, s, M.restarts, true, converged))) return st;
+  return top_finish(M, s);
 }
 
 ttn_status init_member(Member& M, hipStream_t s, bool* conv) {
@@ -1563,15 +1591,116 @@ ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
   return TTN_OK;
 }
 
-// The top update of every member (launch group by launch group) on stream s;
-// *all (may be null) receives whether every member converged (with sync).
-ttn_status top_all(Ctx& c, hipStream_t s, bool sync, bool* all) {
+// The top update of every member, eagerly (launch group by launch group);
+// *all is cleared when a member stopped at its restart budget.
+ttn_status top_all(Ctx& c, hipStream_t s, bool* all) {
   return for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
     bool conv = false;
-    ttn_status r = stage_update_top(M, s, &conv, sync);
-    if (!r && !conv && all) *all = false;
+    ttn_status r = stage_update_top(M, s, &conv);
+    if (!r && !conv) *all = false;
     return r;
   });
+}
+
+// The top update with `plan` restarts (at most each member's budget)
+// launched without host reads, so that it can be captured into a graph.
+ttn_status top_planned(Ctx& c, hipStream_t s, int plan) {
+  return for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
+    ByteCount bc(M, M.bytes_top);
+    bool conv = false;
+    ttn_status st;
+    if ((st = top_prepare(M, s))) return st;
+    if ((st = top_restarts(M, s, std::min(plan, M.restarts), false, &conv))) return st;
+    return top_finish(M, s);
+  });
+}
+
+// Restarts run by the slowest member's last top update, and whether every
+// member's flag is set (reads the device; synchronises the stream).
+ttn_status top_status(Ctx& c, hipStream_t s, int* most, bool* all) {
+  HIPCHK(hipStreamSynchronize(s));
+  *most = 0;
+  *all = true;
+  for (auto& M : c.m) {
+    int f[2] = {0, 0};
+    HIPCHK(hipMemcpy(f, M.lzint + LZ_DONE, sizeof f, hipMemcpyDeviceToHost));
+    *most = std::max(*most, f[1]);
+    if (!f[0]) *all = false;
+  }
+  return TTN_OK;
+}
+
+// After a planned top update: the launch groups with a member whose flag is
+// still clear get the rest of their restart budget eagerly (host reads after
+// each restart), and v and the energy are finished again (the same
+// arithmetic as one eager update: a finished v only had its sign fixed, and
+// a restart normalises its start vector, so the sign carries through
+// exactly).  *all is cleared when a member stopped at its budget; *most
+// receives the restarts the slowest member ran.
+ttn_status top_complete(Ctx& c, hipStream_t s, int plan, int* most, bool* all) {
+  ttn_status st;
+  if ((st = top_status(c, s, most, all))) return st;
+  if (*all) return TTN_OK;
+  for (auto& G : c.groups) {
+    bool pending = false;
+    for (int i : G.members) {
+      int f = 0;
+      HIPCHK(hipMemcpy(&f, c.m[i].lzint + LZ_DONE, sizeof f, hipMemcpyDeviceToHost));
+      if (!f) pending = true;
+    }
+    Member& L = c.m[G.members[0]];
+    const int rest = L.restarts - std::min(plan, L.restarts);
+    if (!pending || rest <= 0) continue;
+    GroupScope gs((int)G.members.size(), G.stride);
+    bool conv = false;
+    if ((st = top_restarts(L, s, rest, true, &conv))) return st;
+    if ((st = top_finish(L, s, true))) return st;
+    sync_group_state(c, G);
+  }
+  return top_status(c, s, most, all);
+}
+
+// Captures (once per restart plan) or replays the graph of a planned top update.
+ttn_status top_graph_launch(Ctx& c, int plan) {
+  auto it = c.top_exec.find(plan);
+  if (it == c.top_exec.end()) {
+    if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
+    ttn_status st = top_planned(c, c.cap_s, plan);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c.cap_s, &g);
+    if (st) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    HIPCHK(e);
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(e);
+    it = c.top_exec.emplace(plan, ge).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, c.s));
+  return TTN_OK;
+}
+
+// The top update after a replayed layer part.  use_graph == 2: every restart
+// of the budget in the graph, no host read.  Otherwise the graph holds the
+// restarts the slowest member needed so far, one host read afterwards
+// finishes any member that needs more (eagerly) and raises the plan.
+ttn_status top_after_graph(Ctx& c, int use_graph, ttn_status* warn) {
+  int budget = 1;
+  for (auto& M : c.m) budget = std::max(budget, M.restarts);
+  if (use_graph == 2) return top_graph_launch(c, budget);
+  const int plan = std::min(budget, std::max(1, c.top_plan));
+  ttn_status st = top_graph_launch(c, plan);
+  if (st) return st;
+  int most = 0;
+  bool all = true;
+  if ((st = top_complete(c, c.s, plan, &most, &all))) return st;
+  c.top_plan = std::max(c.top_plan, most);
+  if (!all) *warn = TTN_WNOCONV;
+  return TTN_OK;
 }
 
 }  // namespace
@@ -1687,6 +1816,16 @@ ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t b
     any_noconv |= !conv;
     h->c.m[i].w0 = nullptr;
     h->c.m[i].v0 = nullptr;
+  }
+  {  // the first restart plan of graph sweeps: what the initial top updates needed
+    int most = 1;
+    bool all = true;
+    st = top_status(h->c, h->c.s, &most, &all);
+    if (st) {
+      delete h;
+      return st;
+    }
+    h->c.top_plan = std::max(1, most);
   }
   *out = h;
   return any_noconv ? TTN_WNOCONV : TTN_OK;
@@ -1807,7 +1946,6 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
         if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
         st = sweep_layers_all(c, c.cap_s);
-        if (!st) st = top_all(c, c.cap_s, false, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c.cap_s, &g);
         if (st) {
@@ -1819,12 +1957,11 @@ ttn_status ttn_sweep(ttn_handle h, int nsweeps, int use_graph) {
         HIPCHK(hipGraphInstantiate(&c.gexec, c.graph, nullptr, nullptr, 0));
       }
       HIPCHK(hipGraphLaunch(c.gexec, c.s));
-      // the top update ran inside the graph; its convergence is reported by
-      // ttn_energy
+      if ((st = top_after_graph(c, use_graph, &warn))) return st;
     } else {
       if ((st = sweep_layers_all(c, c.s))) return st;
       bool all = true;
-      if ((st = top_all(c, c.s, true, &all))) return st;
+      if ((st = top_all(c, c.s, &all))) return st;
       if (!all) warn = TTN_WNOCONV;
     }
   }
@@ -1860,7 +1997,6 @@ ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_grap
         if (!c.cap_s) HIPCHK(hipStreamCreateWithFlags(&c.cap_s, hipStreamNonBlocking));
         HIPCHK(hipStreamBeginCapture(c.cap_s, hipStreamCaptureModeRelaxed));
         st = grouped_layers_all(c, groups, c.cap_s);
-        if (!st) st = top_all(c, c.cap_s, false, nullptr);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c.cap_s, &g);
         if (st) {
@@ -1872,10 +2008,11 @@ ttn_status ttn_sweep_grouped(ttn_handle h, int nsweeps, int groups, int use_grap
         HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
       }
       HIPCHK(hipGraphLaunch(ge, c.s));
+      if ((st = top_after_graph(c, use_graph, &warn))) return st;
     } else {
       if ((st = grouped_layers_all(c, groups, c.s))) return st;
       bool all = true;
-      if ((st = top_all(c, c.s, true, &all))) return st;
+      if ((st = top_all(c, c.s, &all))) return st;
       if (!all) warn = TTN_WNOCONV;
     }
   }

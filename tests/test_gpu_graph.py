@@ -66,38 +66,54 @@ def test_graph_replays_match_eager(B, name, model, L, chi, prec):
     graph.close()
 
 
-def test_top_update_inside_the_graph(B):
-    # the captured sweep holds the top update too: every restart of the
-    # budget, the ones after convergence returning at once on a device flag;
-    # the eager sweep stops launching at convergence; both end with the same
-    # vector and Krylov count.  With too small a budget (4 Krylov vectors, one
-    # restart) the eager sweep returns TTN_WNOCONV and ttn_energy reports it
-    # after a graph sweep
+def test_top_update_from_graphs(B):
+    # graph sweeps replay the top update from a graph too: mode 2 with every
+    # restart of the budget (the ones after convergence return at once on a
+    # device flag), mode 1 with the restarts needed so far and an eager
+    # completion when a member needs more; the eager sweep stops launching at
+    # convergence.  All end with the same vector, energy and Krylov count,
+    # over sweeps whose restart needs vary (a small Krylov space).  With too
+    # small a budget (4 Krylov vectors, one restart) the eager sweep returns
+    # TTN_WNOCONV, so does a mode-1 sweep, and ttn_energy reports it after
+    # either graph mode
     model, L, chi = I.tfim_chain(1.0), 64, 16
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 9)
-    eager = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
-    graph = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws))
-    for _ in range(3):
-        assert eager.sweep(1) == B.TTN_OK
-        assert graph.sweep(1, graph=True) == B.TTN_OK
-        assert eager.energy()[0] == graph.energy()[0]
-        assert graph.energy_status == B.TTN_OK
-        assert eager.stats().lanczos_iters == graph.stats().lanczos_iters > 0
-        assert np.array_equal(eager.get_tensor(B.TTN_TOP), graph.get_tensor(B.TTN_TOP))
-    eager.close()
-    graph.close()
+    small = dict(krylov=6, restarts=8)
+    eager = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **small))
+    g1 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **small))
+    g2 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **small))
+    iters = set()
+    for s in range(4):
+        st_e = eager.sweep(1)
+        assert g1.sweep(1, graph=1) == st_e
+        g2.sweep(1, graph=2)
+        e = eager.energy()[0]
+        assert g1.energy()[0] == e and g2.energy()[0] == e
+        assert g1.energy_status == eager.energy_status == g2.energy_status
+        it = eager.stats().lanczos_iters
+        assert g1.stats().lanczos_iters == it == g2.stats().lanczos_iters > 0
+        assert eager.stats().e_prev == g1.stats().e_prev == g2.stats().e_prev
+        iters.add(it)
+        v = eager.get_tensor(B.TTN_TOP)
+        assert np.array_equal(g1.get_tensor(B.TTN_TOP), v) and np.array_equal(g2.get_tensor(B.TTN_TOP), v)
+    print(f"  Krylov steps per top update: {sorted(iters)}")
+    for h in (eager, g1, g2):
+        h.close()
     tight = dict(krylov=4, restarts=1)
     eager = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **tight))
-    graph = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **tight))
+    g1 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **tight))
+    g2 = B.TTN(B.ChainInput(model, L, chi, "fp64", w0=ws, **tight))
     assert eager.sweep(1) == B.TTN_WNOCONV
-    eager.energy()
+    assert g1.sweep(1, graph=1) == B.TTN_WNOCONV
+    g2.sweep(1, graph=2)
+    e = eager.energy()[0]
     assert eager.energy_status == B.TTN_WNOCONV
-    graph.sweep(1, graph=True)
-    assert graph.energy()[0] == eager.energy()[0]
-    assert graph.energy_status == B.TTN_WNOCONV
-    assert graph.stats().lanczos_iters == 4
-    eager.close()
-    graph.close()
+    for g in (g1, g2):
+        assert g.energy()[0] == e
+        assert g.energy_status == B.TTN_WNOCONV
+        assert g.stats().lanczos_iters == 4
+    for h in (eager, g1, g2):
+        h.close()
 
 
 def test_batch_members_follow_their_solo_paths(B):
