@@ -149,6 +149,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-secondary", action="store_true", help="skip the chi=128, L=1024, batch and schedule legs")
     p.add_argument("--no-autotune", action="store_true", help="default launch shapes instead of the autotuner")
+    p.add_argument("--tune-file", default=None,
+                   help="launch choices: read from this text file when it exists (shapes it lacks keep the default "
+                        "launch), else tuned and written there at the end; profiling runs share one file so that "
+                        "each launches the same kernels")
     p.add_argument("--profile-sweeps", type=int, default=3, help="eager sweeps of the profiled pass")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of CPU reference work")
     p.add_argument("--cpu-sweeps", action="store_true",
@@ -171,6 +175,10 @@ def parse():
     p.add_argument("--schedules", action="store_true",
                    help="energy against time from one start: the paper's sweep and the grouped sweeps "
                         "(--budget seconds each)")
+    p.add_argument("--positional", action="store_true",
+                   help="position-resolved networks only (every node its own isometry), one JSON line")
+    p.add_argument("--pos-configs", default="xxx1024_chi64,xxx4096_chi128",
+                   help="--positional: workloads, comma separated, from " + ", ".join(POS_CONFIGS))
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB elementwise copy (y = -x), the reference of the traffic counters")
     return p.parse_args()
@@ -262,6 +270,74 @@ def cpu_sweeps(args):
         out[name] = rec
     print(json.dumps({"metric": "CPU oracle whole sweeps", "unit": "sweeps/s", "kind": "oracle",
                       "host_threads": n_all, "data": "synthetic", "seed": args.seed, "runs": out}))
+
+
+# position-resolved networks: every node its own isometry, float64
+POS_CONFIGS = {
+    "xxx1024_chi64": (lambda I: I.xxx_chain(), 1024, 64, "Heisenberg XXX chain L=1024 chi=64, every node its own isometry"),
+    "xxx4096_chi128": (lambda I: I.xxx_chain(), 4096, 128,
+                       "Heisenberg XXX chain L=4096 chi=128, every node its own isometry"),
+}
+
+
+def measure_positional(B, I, name, steps, warmup, seed):
+    """Sweeps of a position-resolved network (ttn_pos_*): every isometry of a
+    layer is its own tensor and each stage runs over all nodes of a layer (or
+    of one parity) per launch.  Warm-up sweeps, K timed sweeps, one profiled
+    sweep with HIP events around every product kernel."""
+    import torch
+    make, L, chi, desc = POS_CONFIGS[name]
+    model = make(I)
+    nws = I.random_node_isometries(L, model.d, chi, seed)
+    g = B.PosTTN(model, L, chi, nws)
+    del nws
+    hist = [g.energy()[1]]
+    for _ in range(max(1, warmup)):
+        g.sweep(1)
+        hist.append(g.energy()[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.sweep(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hist.append(g.energy()[1])
+    st = g.stats()
+    progress(f"positional {name}: {1e3 * el / steps:.2f} ms per sweep")
+    g.profile(True)
+    g.sweep(1)
+    prof = g.profile_read()
+    g.profile(False)
+    hist.append(g.energy()[1])
+    roofline = kernel_roofline(prof, f"{desc} fp64")
+    kernels = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"], 3)}
+               for k, v in prof.items() if "kernel" in k}
+    classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None}
+               for k, v in prof.items() if "kernel" not in k}
+    nodes = sum(L >> t for t in range(1, g.n))
+    g.close()
+    torch.cuda.empty_cache()
+    return {
+        "workload": desc, "L": L, "chi": chi, "precision": "fp64", "isometries": nodes,
+        "sweeps_per_s": round(steps / el, 4), "ms_per_sweep": round(1e3 * el / steps, 3),
+        "flops_per_sweep": st.flops_sweep, "product_bytes_per_sweep": st.bytes_sweep,
+        "contraction_tflops": round(st.flops_sweep / (el / steps) / 1e12, 3),
+        "energy_per_site_by_sweep": hist, "energy_never_rises": all(b <= a + 1e-12 for a, b in zip(hist, hist[1:])),
+        "roofline": roofline, "classes": classes, "kernels": kernels,
+    }
+
+
+def positional(B, I, args):
+    out = {}
+    for name in args.pos_configs.split(","):
+        out[name] = measure_positional(B, I, name, args.steps, args.warmup, args.seed)
+    first = out[next(iter(out))]
+    print(json.dumps({
+        "metric": "position-resolved TTN sweeps/s (every node its own isometry)", "value": first["sweeps_per_s"],
+        "unit": "sweeps/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": first["workload"]}, "runs": out,
+    }))
 
 
 def free_fermion_energy_per_site(L, h):
@@ -892,6 +968,11 @@ def main():
         B.autotune(0 if args.no_autotune else 1)
         schedules(B, I, args)
         return
+    if args.positional:
+        progress("device ready")
+        B.autotune(0 if args.no_autotune else 1)
+        positional(B, I, args)
+        return
     if args.positions:
         progress("device ready")
         B.autotune(0 if args.no_autotune else 1)
@@ -907,7 +988,13 @@ def main():
         print(json.dumps({"copy_calibration": {"kernel": "neg_kernel", "bytes_read": 4 * n, "bytes_written": 4 * n,
                                                "launches": 3}}))
         return
-    B.autotune(0 if args.no_autotune else 1)
+    tune_loaded = False
+    if args.tune_file and os.path.exists(args.tune_file) and not args.no_autotune:
+        B.autotune_load(args.tune_file)
+        B.autotune(2)
+        tune_loaded = True
+    else:
+        B.autotune(0 if args.no_autotune else 1)
     prec0 = args.precision or CONFIGS[args.config][3]
     full = args.config == DEFAULT_CONFIG and not args.headline_only and args.precision is None
     if full:
@@ -975,6 +1062,9 @@ def main():
     }
     if m["prec"] != "fp64":
         out.update(energy_fp64_reeval=m["e_re"], energy_rel_err_vs_fp64_reeval=m["err_re"])
+    if args.tune_file and not tune_loaded and not args.no_autotune:
+        B.autotune_save(args.tune_file)
+    out["launch_choices"] = "read from " + args.tune_file if tune_loaded else ("tuned" if not args.no_autotune else "default")
     print(json.dumps(out))
 
 

@@ -388,6 +388,106 @@ ttn_status ttn_local_energies(ttn_handle h, int b, void* work, size_t bytes, dou
 #define TTN_NOALLOC_SCRATCH_BYTES (64u << 20)
 ttn_status ttn_local_energies_noalloc(ttn_handle h, int b, double* site, double* bond);
 
+/* ------------------------------------------------------------------------
+ * Position-resolved network: every node (tau, m) its own isometry
+ * w^(tau, m) (Sec. II.C labels the isometries by layer and position; the
+ * translation-invariant Hamiltonians of Sec. III let the paper take them
+ * equal along a layer, which the functions above do).  Float64 throughout.
+ * Node m of level tau covers sites m 2^tau .. (m + 1) 2^tau - 1; its input
+ * legs are nodes 2m (left) and 2m + 1 (right) of level tau - 1.
+ *
+ * A sweep (Sec. IV with each layer split by parity): layers bottom-up; in a
+ * layer first the even then the odd nodes, every node of a parity group
+ * updated from one state (such nodes are never neighbours: each group is an
+ * exact block step), w <- -polar(Env) (Sec. III.B) for each; then the top
+ * tensor as the lowest eigenvector of the top Hamiltonian, whose two sites
+ * now carry different operators (Lanczos, as for ttn_update(TTN_TOP)).
+ * Energies and errors as for the uniform network; the energy is the top
+ * eigenvalue plus c L, divided by L ly.
+ * ------------------------------------------------------------------------ */
+typedef struct ttn_pos_ctx* ttn_pos_handle;
+
+typedef struct ttn_pos_config {
+  int L, d, chi, D;   /* as ttn_config                                         */
+  const double* h1;   /* host d*d; A, B: host D*d*d (as ttn_config)            */
+  const double* A;
+  const double* B;
+  double shift;       /* NaN: the largest eigenvalue of the bond term          */
+  int ly;             /* spins per effective site                             */
+  unsigned long long seed; /* start vector of the first top solve when v0 is
+                         NULL (counter-based Gaussian, as ttn_config)         */
+  const double* const* w0; /* required host array of n-1 pointers: w0[tau-1]
+                         holds the L_tau isometries of layer tau, node-major,
+                         each chi_tau x chi_{tau-1} x chi_{tau-1}
+                         (L_tau = L >> tau)                                   */
+  const double* v0;   /* optional host chi_{n-1}^2 start vector               */
+  int krylov, restarts;  /* as in ttn_config, 0: 24, 8                         */
+  double lanczos_tol;    /* as in ttn_config, 0: 1e-12                         */
+  int chunk_nodes;    /* nodes per launch chunk at most (0: as many as 1 GiB of
+                         staging holds); results do not depend on it beyond
+                         rounding                                             */
+} ttn_pos_config;
+
+/* Workspace: the per-node arrays (isometries, operators, density matrices
+ * and edge information of every node, the descent's cache: each about the
+ * size of all isometries, so about five times the isometries' bytes), the
+ * top solver's buffers, and staging of at most 1 GiB per launch chunk.
+ * Same errors as ttn_workspace_bytes; TTN_EINVAL when w0 or one of its
+ * layers is NULL. */
+ttn_status ttn_pos_workspace_bytes(const ttn_pos_config* cfg, size_t* bytes);
+/* Copies the inputs, ascends every node's operators and solves the top
+ * problem (v0 or the seeded vector as the start).  Errors as ttn_init;
+ * TTN_WNOCONV when the first top solve ended above its target. */
+ttn_status ttn_pos_init(const ttn_pos_config* cfg, void* workspace, size_t bytes, void* stream,
+                        ttn_pos_handle* out);
+/* nsweeps sweeps (above).  TTN_EHIP / TTN_ENOCONV when a polar Jacobi solve
+ * aborted / used its sweep limit; TTN_WNOCONV from the top solver. */
+ttn_status ttn_pos_sweep(ttn_pos_handle h, int nsweeps);
+/* e[0] = top eigenvalue lambda, e[1] = energy per spin of the current state. */
+ttn_status ttn_pos_energy(ttn_pos_handle h, double* e);
+/* rho, X, Y of every node of every level from the current tensors (read
+ * back with ttn_pos_get(TTN_POS_DX)).  Synchronises the stream. */
+ttn_status ttn_pos_descend(ttn_pos_handle h);
+/* The environments of the nodes parity, parity + 2, .. of level tau (1 <=
+ * tau < n) from the current tensors, into host (count x chi_tau x
+ * chi_{tau-1}^2, count = L_tau / 2); the state is not changed. */
+ttn_status ttn_pos_env(ttn_pos_handle h, int tau, int parity, double* host);
+/* Copies a block to the host:
+ *   TTN_POS_W   (level >= 1) the L_tau isometries, node-major;
+ *   TTN_POS_OPS the operators [h, A_1..A_D, B_1..B_D] of each node (chi_tau^2
+ *               each, node-major; level 0 one block: h1 - c I, A, B), h the
+ *               sum of the terms inside the node's block, A_k its last site's
+ *               and B_k its first site's edge operator;
+ *   TTN_POS_DX  [rho, X_1..X_D, Y_1..Y_D] of each node as of the last
+ *               ttn_pos_descend: X_k pairs with B_k (the bond arriving at the
+ *               block's first site), Y_k with A_k (the bond leaving its last);
+ *   TTN_POS_TOP the top tensor (level ignored). */
+enum { TTN_POS_W = 0, TTN_POS_OPS = 1, TTN_POS_DX = 2, TTN_POS_TOP = 3 };
+ttn_status ttn_pos_get(ttn_pos_handle h, int what, int level, double* host);
+/* Counters of the last sweep and the top solve. */
+typedef struct ttn_pos_stats_t {
+  double energy, lam;     /* as ttn_pos_energy                                  */
+  double flops_sweep;     /* product flops of the last ttn_pos_sweep: every node's
+                             products, the polar updates' and the top solve's    */
+  double bytes_sweep;     /* product bytes of the same (each operand read once,
+                             each result written once)                           */
+  double lanczos_resid;   /* ||H v - lambda v|| after the last top solve          */
+  int n_levels;
+  int top_converged;      /* 1 when the last top solve met its target            */
+} ttn_pos_stats_t;
+ttn_status ttn_pos_stats(ttn_pos_handle h, ttn_pos_stats_t* out);
+/* Event timing of the handle's launches by contraction class and kernel, as
+ * ttn_profile / ttn_profile_read (same entry layout and warnings). */
+ttn_status ttn_pos_profile(ttn_pos_handle h, int enable);
+ttn_status ttn_pos_profile_read(ttn_pos_handle h, ttn_profile_entry* out, int max_entries, int* n_out);
+/* Replaces a block from the host: TTN_POS_W (level >= 1) the isometries of a
+ * layer, node-major, after which every level from it up is ascended again;
+ * TTN_POS_TOP the top tensor (chi_{n-1}^2 doubles), not solved again.  The
+ * isometries are taken as given (rows are not checked for orthonormality).
+ * TTN_EINVAL for another kind or a level outside [1, n). */
+ttn_status ttn_pos_set(ttn_pos_handle h, int what, int level, const double* host);
+ttn_status ttn_pos_free(ttn_pos_handle h);
+
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);
 

@@ -54,30 +54,6 @@ from oracle import ttn_ref as T
 # --------------------------------------------------------------------------
 # the network
 # --------------------------------------------------------------------------
-def node_isometries(uniform_ws, L):
-    """Position-resolved copies of a uniform network: layer tau holds L_tau
-    copies of its isometry (the same state)."""
-    return [[w.copy() for _ in range(L >> (t + 1))] for t, w in enumerate(uniform_ws)]
-
-
-def random_node_isometries(L, d, chi, seed):
-    """Seeded random isometries for every node: for each layer in order and
-    each node in order, a Gaussian (b*b x a) matrix from default_rng(seed),
-    its reduced QR with the signs of diag(R) folded into Q, w = Q^T."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for t, (a, b) in enumerate(T.layer_shapes(L, d, chi)):
-        layer = []
-        for _ in range(L >> (t + 1)):
-            g = rng.standard_normal((b * b, a))
-            q, r = np.linalg.qr(g)
-            s = np.sign(np.diag(r))
-            s[s == 0] = 1.0
-            layer.append(np.ascontiguousarray((q * s[None, :]).T.reshape(a, b, b)))
-        out.append(layer)
-    return out
-
-
 def level_state(nws, v, level):
     """State on the sites of `level` (one index per node, left to right),
     contracted from the top through every node's own isometry."""
@@ -204,10 +180,11 @@ def environment(w, hL, hR, AL, BL, AR, BR, rho, X, Y):
 # --------------------------------------------------------------------------
 class PositionalTTN:
     """Position-resolved TTN energy minimisation, float64.  nws[tau-1][m] is
-    the isometry of node m of layer tau; v the top tensor (solved at
-    initialisation when not given)."""
+    the isometry of node m of layer tau (an input: inputs.random_node_isometries
+    draws seeded ones); v the top tensor (solved at initialisation when not
+    given)."""
 
-    def __init__(self, L, chi, h1, A, B, ly=1, nws=None, v=None, seed=0, shift=None):
+    def __init__(self, L, chi, h1, A, B, nws, ly=1, v=None, shift=None):
         self.L, self.chi, self.ly = L, chi, ly
         self.h1 = np.asarray(h1, dtype=np.float64)
         self.A = [np.asarray(a, dtype=np.float64) for a in A]
@@ -218,7 +195,7 @@ class PositionalTTN:
         self.dims = T.bond_dims(L, self.d, chi)
         self.c = T.shift_constant(self.h1, self.A, self.B) if shift is None else float(shift)
         self.h0 = self.h1 - self.c * np.eye(self.d)
-        self.nws = nws if nws is not None else random_node_isometries(L, self.d, chi, seed)
+        self.nws = [[np.array(w, dtype=np.float64) for w in layer] for layer in nws]
         self.v = v
         self.history = []
         self.diag = []

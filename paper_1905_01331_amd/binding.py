@@ -31,7 +31,10 @@ EXPORTS = [
     "ttn_stats", "ttn_entanglement", "ttn_bond_dim", "ttn_last_error", "ttn_free", "ttn_profile", "ttn_profile_read",
     "ttn_positions_bytes", "ttn_positions_offset", "ttn_local_energies", "ttn_entanglement_node",
     "ttn_autotune_save", "ttn_autotune_load", "ttn_local_energies_noalloc",
+    "ttn_pos_workspace_bytes", "ttn_pos_init", "ttn_pos_sweep", "ttn_pos_energy", "ttn_pos_descend", "ttn_pos_env",
+    "ttn_pos_get", "ttn_pos_set", "ttn_pos_free", "ttn_pos_stats", "ttn_pos_profile", "ttn_pos_profile_read",
 ]
+TTN_POS_W, TTN_POS_OPS, TTN_POS_DX, TTN_POS_TOP = range(4)
 
 
 class TTNConfig(ctypes.Structure):
@@ -46,6 +49,17 @@ class TTNConfig(ctypes.Structure):
     ]
 
 
+class TTNPosConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int), ("d", ctypes.c_int), ("chi", ctypes.c_int), ("D", ctypes.c_int),
+        ("h1", ctypes.POINTER(ctypes.c_double)), ("A", ctypes.POINTER(ctypes.c_double)),
+        ("B", ctypes.POINTER(ctypes.c_double)), ("shift", ctypes.c_double), ("ly", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong), ("w0", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+        ("v0", ctypes.POINTER(ctypes.c_double)), ("krylov", ctypes.c_int), ("restarts", ctypes.c_int),
+        ("lanczos_tol", ctypes.c_double), ("chunk_nodes", ctypes.c_int),
+    ]
+
+
 class TTNStats(ctypes.Structure):
     _fields_ = [
         ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("lanczos_resid", ctypes.c_double),
@@ -53,6 +67,14 @@ class TTNStats(ctypes.Structure):
         ("flops_bulk", ctypes.c_double), ("flops_fp64", ctypes.c_double), ("n_levels", ctypes.c_int),
         ("lanczos_iters", ctypes.c_int), ("jacobi_sweeps", ctypes.c_int * 4),
         ("e_prev", ctypes.c_double), ("bytes_hbm", ctypes.c_double),
+    ]
+
+
+class TTNPosStats(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("flops_sweep", ctypes.c_double),
+        ("bytes_sweep", ctypes.c_double), ("lanczos_resid", ctypes.c_double), ("n_levels", ctypes.c_int),
+        ("top_converged", ctypes.c_int),
     ]
 
 
@@ -103,6 +125,18 @@ def load_library(path: str = LIB_PATH):
         "ttn_local_energies": ([P, I, P, ctypes.c_size_t, DP, DP], I),
         "ttn_local_energies_noalloc": ([P, I, DP, DP], I),
         "ttn_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
+        "ttn_pos_workspace_bytes": ([ctypes.POINTER(TTNPosConfig), ctypes.POINTER(ctypes.c_size_t)], I),
+        "ttn_pos_init": ([ctypes.POINTER(TTNPosConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)], I),
+        "ttn_pos_sweep": ([P, I], I),
+        "ttn_pos_energy": ([P, DP], I),
+        "ttn_pos_descend": ([P], I),
+        "ttn_pos_env": ([P, I, I, DP], I),
+        "ttn_pos_get": ([P, I, I, DP], I),
+        "ttn_pos_set": ([P, I, I, DP], I),
+        "ttn_pos_free": ([P], I),
+        "ttn_pos_stats": ([P, ctypes.POINTER(TTNPosStats)], I),
+        "ttn_pos_profile": ([P, I], I),
+        "ttn_pos_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -352,6 +386,145 @@ class TTN:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.ttn_free(self.h)
             self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bond_dims(L, d, chi):
+    """chi_tau = min(chi_{tau-1}^2, chi), chi_0 = d, for tau < n (L = 2^n)."""
+    n = int(L).bit_length() - 1
+    dims = [int(d)]
+    for _ in range(1, n):
+        dims.append(min(dims[-1] * dims[-1], int(chi)))
+    return dims
+
+
+class PosTTN:
+    """Handle of a position-resolved network (include/ttn.h, ttn_pos_*).
+    w0: one array per layer tau = 1..n-1 of shape (L >> tau, chi_tau,
+    chi_{tau-1}, chi_{tau-1}); v0 optional."""
+
+    def __init__(self, model, L, chi, w0, v0=None, shift=None, seed=0, krylov=0, restarts=0, lanczos_tol=0.0,
+                 chunk_nodes=0, device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        h1, A, B = model.packed()
+        self.h1 = np.ascontiguousarray(h1, dtype=np.float64)
+        self.A = np.ascontiguousarray(A, dtype=np.float64)
+        self.B = np.ascontiguousarray(B, dtype=np.float64)
+        self.L, self.chi, self.d, self.D = int(L), int(chi), int(model.d), int(model.D)
+        self.dims = bond_dims(L, model.d, chi)
+        self.n = len(self.dims)
+        self.w0 = [np.ascontiguousarray(w, dtype=np.float64) for w in w0]
+        self.v0 = None if v0 is None else np.ascontiguousarray(v0, dtype=np.float64)
+        cfg = TTNPosConfig()
+        cfg.L, cfg.d, cfg.chi, cfg.D = self.L, self.d, self.chi, self.D
+        cfg.h1 = _dptr(self.h1)
+        cfg.A = _dptr(self.A) if self.D else None
+        cfg.B = _dptr(self.B) if self.D else None
+        cfg.shift = math.nan if shift is None else float(shift)
+        cfg.ly = int(model.ly)
+        cfg.seed = int(seed)
+        self._wptrs = (ctypes.POINTER(ctypes.c_double) * max(1, len(self.w0)))(*[_dptr(w) for w in self.w0])
+        cfg.w0 = ctypes.cast(self._wptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
+        cfg.v0 = _dptr(self.v0) if self.v0 is not None else None
+        cfg.krylov, cfg.restarts, cfg.lanczos_tol = int(krylov), int(restarts), float(lanczos_tol)
+        cfg.chunk_nodes = int(chunk_nodes)
+        self.cfg = cfg
+        need = ctypes.c_size_t(0)
+        _check(lib.ttn_pos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(need)))
+        self.workspace = torch.empty(need.value + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
+        h = ctypes.c_void_p(0)
+        self.init_status = _check(lib.ttn_pos_init(ctypes.byref(cfg), ctypes.c_void_p(aligned), need.value,
+                                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+
+    def sweep(self, nsweeps=1):
+        return _check(self.lib.ttn_pos_sweep(self.h, int(nsweeps)))
+
+    def energy(self):
+        """(lambda, energy per spin); the call's status in self.energy_status."""
+        out = np.zeros(2)
+        self.energy_status = _check(self.lib.ttn_pos_energy(self.h, _dptr(out)))
+        return float(out[0]), float(out[1])
+
+    def descend(self):
+        return _check(self.lib.ttn_pos_descend(self.h))
+
+    def env(self, tau, parity):
+        a, b = self.dims[tau], self.dims[tau - 1]
+        out = np.zeros(((self.L >> tau) // 2, a, b, b))
+        _check(self.lib.ttn_pos_env(self.h, int(tau), int(parity), _dptr(out)))
+        return out
+
+    def isometries(self, tau):
+        a, b = self.dims[tau], self.dims[tau - 1]
+        out = np.zeros((self.L >> tau, a, b, b))
+        _check(self.lib.ttn_pos_get(self.h, TTN_POS_W, int(tau), _dptr(out)))
+        return out
+
+    def operators(self, level):
+        """(h, A, B): per node (node-major) h (x, x), A and B (D, x, x); level 0
+        one node."""
+        x = self.dims[level]
+        nodes = 1 if level == 0 else self.L >> level
+        out = np.zeros((nodes, 1 + 2 * self.D, x, x))
+        _check(self.lib.ttn_pos_get(self.h, TTN_POS_OPS, int(level), _dptr(out)))
+        return out[:, 0], out[:, 1:1 + self.D], out[:, 1 + self.D:]
+
+    def node_matrices(self, level):
+        """(rho, X, Y) of every node of a level as of the last descend()."""
+        x = self.dims[level]
+        out = np.zeros((self.L >> level, 1 + 2 * self.D, x, x))
+        _check(self.lib.ttn_pos_get(self.h, TTN_POS_DX, int(level), _dptr(out)))
+        return out[:, 0], out[:, 1:1 + self.D], out[:, 1 + self.D:]
+
+    def top(self):
+        x = self.dims[-1]
+        out = np.zeros((x, x))
+        _check(self.lib.ttn_pos_get(self.h, TTN_POS_TOP, 0, _dptr(out)))
+        return out
+
+    def set_top(self, v):
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        _check(self.lib.ttn_pos_set(self.h, TTN_POS_TOP, 0, _dptr(v)))
+
+    def set_isometries(self, tau, ws):
+        """Layer tau's isometries (L >> tau, chi_tau, chi_{tau-1}, chi_{tau-1});
+        the levels from tau up are ascended again."""
+        ws = np.ascontiguousarray(ws, dtype=np.float64)
+        a, b = self.dims[tau], self.dims[tau - 1]
+        if ws.shape != (self.L >> tau, a, b, b):
+            raise ValueError(f"layer {tau}: shape {ws.shape}")
+        _check(self.lib.ttn_pos_set(self.h, TTN_POS_W, int(tau), _dptr(ws)))
+
+    def stats(self):
+        st = TTNPosStats()
+        _check(self.lib.ttn_pos_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def profile(self, enable=True):
+        return _check(self.lib.ttn_pos_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (TTNProfileEntry * 64)()
+        n = ctypes.c_int(0)
+        _check(self.lib.ttn_pos_profile_read(self.h, arr, 64, ctypes.byref(n)), allow_warn=False)
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                           bytes=arr[i].bytes) for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ttn_pos_free(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -208,6 +208,13 @@ hipError_t pair_f32(const float* X, const float* Y, long long n, double* out, do
 // X[r sX + i] Y[r sY + i] for r < rows (sY = 0: one Y for every row).
 hipError_t pair_rows_f64(const double* X, long long sX, const double* Y, long long sY, long long len, int rows,
                          double* out, long long os, long long oo, double beta, hipStream_t s);
+// count blocks of len doubles: dst[j ds + i] = src[j ss + i] (not a launch
+// group helper: the two strides differ)
+hipError_t copy_strided_f64(double* dst, long long ds, const double* src, long long ss, long long len, int count,
+                            hipStream_t s);
+// out[0] = 1 when out[0] != 0 or any x[j stride + i0] != 0 (j < count); out[1]
+// likewise with i1 (one work-item)
+hipError_t flags_or(const double* x, long long stride, int count, int i0, int i1, double* out, hipStream_t s);
 // ||W W^T - I||_F from the Gram G (n x n): out[0] = sqrt(sum (G - I)^2)
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s);
 

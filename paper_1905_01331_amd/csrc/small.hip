@@ -455,4 +455,38 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
   return hipGetLastError();
 }
 
+namespace {
+__global__ void k_copy_strided(const double* __restrict__ src, long long ss, double* __restrict__ dst, long long ds,
+                               long long len) {
+  const double* a = src + (long long)blockIdx.y * ss;
+  double* b = dst + (long long)blockIdx.y * ds;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < len; i += (long long)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+__global__ void k_flags_or(const double* __restrict__ x, long long stride, int count, int i0, int i1,
+                           double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double f0 = out[0], f1 = out[1];
+  for (int j = 0; j < count; ++j) {
+    if (x[(long long)j * stride + i0] != 0.0) f0 = 1.0;
+    if (x[(long long)j * stride + i1] != 0.0) f1 = 1.0;
+  }
+  out[0] = f0;
+  out[1] = f1;
+}
+}  // namespace
+
+hipError_t copy_strided_f64(double* dst, long long ds, const double* src, long long ss, long long len, int count,
+                            hipStream_t s) {
+  if (count < 1 || len < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_strided, dim3(grid_for((size_t)len), count), dim3(256), 0, s, src, ss, dst, ds, len);
+  return hipGetLastError();
+}
+
+hipError_t flags_or(const double* x, long long stride, int count, int i0, int i1, double* out, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_flags_or, dim3(1), dim3(64), 0, s, x, stride, count, i0, i1, out);
+  return hipGetLastError();
+}
+
 }  // namespace ttn

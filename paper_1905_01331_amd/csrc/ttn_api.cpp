@@ -21,10 +21,12 @@
 #include "common.h"
 #include "gemm_internal.h"
 #include "lanczos.h"
+#include "ttn_core.h"
 
 using namespace ttn;
 
-namespace {
+namespace ttn {
+namespace core {
 
 thread_local std::string g_err;
 
@@ -38,11 +40,6 @@ ttn_status fail(ttn_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIPCHK(expr)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess) return fail(TTN_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // host: largest eigenvalue of a small symmetric matrix (cyclic Jacobi)
@@ -181,146 +178,6 @@ double host_lambda_max_lanczos(const std::vector<double>& a, int n) {
 // ---------------------------------------------------------------------------
 // workspace arena
 // ---------------------------------------------------------------------------
-struct Arena {
-  char* base = nullptr;
-  size_t off = 0;
-  template <typename T>
-  T* take(size_t n) {
-    off = (off + 255) & ~size_t(255);
-    T* p = base ? reinterpret_cast<T*>(base + off) : reinterpret_cast<T*>(off + 256);
-    off += n * sizeof(T);
-    return p;
-  }
-  void* take_bytes(size_t n) { return take<char>(n); }
-};
-
-constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO_MAX = 4, SCAL_RATIO = 5,
-              SCAL_RATIO_MIN = 6, SCAL_TMP0 = 7, SCAL_TMP1 = 8, SCAL_TMP2 = 9, SCAL_THETA = 10,
-              SCAL_ERR = 11,  // 1.0 once a Jacobi solve reported an abort
-              SCAL_SHIFT = 12,  // the shift c (per member, read by the energy kernel)
-              SCAL_EPREV = 13,  // the energy before the last top update
-              SCAL_NOCONV = 14,  // 1.0 once a polar Jacobi solve used all its sweeps
-              SCAL_N = 16;
-// Gram refreshes of the polar update: two always, a third when the second
-// Jacobi needed more than POLAR_THIRD_IF sweeps (its start was not nearly
-// diagonal, so the rotated rows may not yet be orthogonal to working accuracy)
-constexpr int LZ_DONE = 8;  // lzint slot of the top solver's per-member convergence flag
-constexpr int POLAR_REFRESH = 2;
-constexpr int POLAR_JACOBI_SWEEPS = 60;  // sweep limit of a polar Jacobi solve
-constexpr int POLAR_THIRD_IF = 3;
-constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
-
-// Per-handle event timer of contraction classes (enabled by ttn_profile).
-enum OpClass { OC_APPLY_R = 0, OC_APPLY_L, OC_CLOSE, OC_LEFT_MUL, OC_CLOSE_L, OC_CLOSE_R, OC_TOP_MM,
-               OC_POLAR_GEMM, OC_JACOBI, OC_LANCZOS_GEMM, OC_N };
-const char* const kOpNames[OC_N] = {"apply_r", "apply_l", "close", "left_mul", "close_l", "close_r",
-                                    "top_mm", "polar_gemm", "jacobi", "lanczos_gemm"};
-struct Profiler {
-  bool on = false;
-  std::vector<hipEvent_t> ev;      // pairs
-  std::vector<int> cls;
-  std::vector<double> flops, bytes;
-  size_t used = 0;
-  int dropped = 0;
-  ~Profiler() {
-    for (auto e : ev) hipEventDestroy(e);
-  }
-  bool begin(int c, double f, double b, hipStream_t s, size_t* slot) {
-    if (!on) return false;
-    if (used >= cls.size()) { ++dropped; return false; }
-    *slot = used++;
-    cls[*slot] = c;
-    flops[*slot] = f;
-    bytes[*slot] = b;
-    return hipEventRecord(ev[2 * *slot], s) == hipSuccess;
-  }
-  void end(size_t slot, hipStream_t s) { (void)hipEventRecord(ev[2 * slot + 1], s); }
-};
-
-// Per-kernel records of the product kernels go into the same event pool,
-// under class ids OC_N + kernel id.
-struct KernelRecorder : KernelTimer {
-  Profiler* P = nullptr;
-  bool begin(int kid, double f, double b, hipStream_t s, size_t* slot) override {
-    return P && P->begin(OC_N + kid, f, b, s, slot);
-  }
-  void end(size_t slot, hipStream_t s) override { P->end(slot, s); }
-};
-
-struct Member {
-  Profiler* prof = nullptr;
-  // configuration
-  int L = 0, n = 0, d = 0, D = 0, chi = 0, ly = 1, prec = TTN_FP64;
-  double c = 0.0;
-  unsigned long long seed = 0;
-  std::vector<int> dims;
-  std::vector<double> h1, A, B;
-  std::vector<int> anti;  // product term k is antisymmetric
-  const double* const* w0 = nullptr;
-  const double* v0 = nullptr;
-  int krylov = 24, restarts = 8;
-  double ltol = 1e-12;
-  bool gauge_fix = true;
-  bool evd = false;  // one Gram refresh only (the eigenvalue-decomposition variant)
-  // batch members run side by side: a Jacobi solve that needs its grid
-  // co-resident (the persistent blocked solver) goes through one shared
-  // stream, one at a time, and the smaller ones use the one-work-group solver
-  bool solo = true;
-  hipStream_t grid_s = nullptr;
-  hipEvent_t grid_in = nullptr, grid_out = nullptr;
-  // device
-  size_t esz = 8;  // bulk element size
-  std::vector<double*> w64;
-  std::vector<double*> Qw;      // per layer: left rotation of the last polar update (warm start)
-  std::vector<char> qw_valid;
-  std::vector<void*> wT, opH, opA, opB, rho, Pc, At, Bt;
-  void *Rb[2] = {nullptr, nullptr}, *Lb[2] = {nullptr, nullptr};
-  int rb_cur = 0;
-  void *Sw = nullptr, *S2 = nullptr, *S3 = nullptr, *envT = nullptr;
-  void *Estage = nullptr, *Xst = nullptr;  // environment staging: tensors and their left factors
-  double *env64 = nullptr, *Y = nullptr, *Y2 = nullptr, *G = nullptr, *V = nullptr, *Q = nullptr, *Q2 = nullptr,
-         *nrm = nullptr;
-  int* jinfo = nullptr;
-  int* skip3 = nullptr;  // device flag: skip the extra polar refresh
-  void* jscratch = nullptr;
-  double* vtop = nullptr;
-  void* vT = nullptr;
-  void* tmpT = nullptr;  // D chi^2 bulk scratch for the top dressing
-  double *hop64 = nullptr, *Aop64 = nullptr, *Bop64 = nullptr, *lzStage = nullptr;
-  double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
-  double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr,
-         *lzpart = nullptr, *lznrm = nullptr;
-  int* lzint = nullptr;
-  double* scal = nullptr;
-  double* part = nullptr;
-  void* splitk = nullptr;
-  size_t splitk_bytes = 0;
-  // state of the sweep: rho^(l) is current for l >= rho_from, the cached
-  // rho^(l) o w_l for l >= pc_from
-  int rho_from = 1 << 20, pc_from = 1 << 20;
-  int dressed_tau = -1, env_tau = -1, ops_upto = 0;
-  bool ortho_fail = false;
-  // algorithmic bytes of the products (operands read once, result written
-  // once) of the last layer pass and of the last top update, counted while
-  // the launches are issued (a graph replay repeats its capture's count)
-  mutable double bytes_acc = 0.0;
-  mutable bool counting = false;
-  double bytes_layers = 0.0, bytes_top = 0.0;
-
-  Prec gp() const { return prec == TTN_FP64 ? P_F64 : (prec == TTN_FP32 ? P_F32 : P_BF16X3); }
-  size_t el(size_t n_) const { return n_ * esz; }
-  void* at(void* base, size_t elems) const { return (char*)base + elems * esz; }
-  const void* at(const void* base, size_t elems) const { return (const char*)base + elems * esz; }
-};
-
-// Counts the product bytes of what runs in its scope into `into`.
-struct ByteCount {
-  Member& M;
-  double& into;
-  ByteCount(Member& m, double& dst) : M(m), into(dst) { M.bytes_acc = 0.0; M.counting = true; }
-  ~ByteCount() { M.counting = false; into = M.bytes_acc; }
-};
-
 // Streams over which the members of a batch run side by side in the layer
 // part of a sweep (forked from and joined back into the caller's stream with
 // events, so the fork is captured into the sweep graph as well).
@@ -559,16 +416,21 @@ void layout_member(Member& M, Arena& ar) {
 // ---------------------------------------------------------------------------
 // contraction helpers (element strides; bulk arithmetic of the member)
 // ---------------------------------------------------------------------------
-hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls = OC_POLAR_GEMM) {
+hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls) {
   size_t slot = 0;
   bool timed = false;
   GemmDesc gg = g;
   gg.mcount = grp().count;
   gg.mstride = grp().stride;
   if (!gg.skip) gg.skip = grp().skip;
-  if (M.counting)
-    M.bytes_acc += (p == P_F64 ? 8.0 : 4.0) * g.batch *
-                   ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
+  if (M.counting) {
+    const double per = (p == P_F64 ? 8.0 : 4.0) * g.batch *
+                       ((double)g.M * g.K + (double)g.K * g.N + (g.beta != 0.0 ? 2.0 : 1.0) * g.M * (double)g.N);
+    const double members = gg.mcount > 1 ? gg.mcount : 1;
+    M.bytes_acc += per;
+    M.traffic_acc += per * members;
+    M.flops_acc += 2.0 * g.M * (double)g.N * g.K * g.batch * members;
+  }
   if (M.prof && M.prof->on) {
     double es = (p == P_F64) ? 8.0 : 4.0;
     double f = 2.0 * g.M * (double)g.N * g.K * g.batch * gg.mcount;
@@ -1041,7 +903,7 @@ hipError_t polar_jacobi(Member& M, int a, double jtol, int it, const int* skip, 
 // settles, so the Jacobi sweeps of the first refresh drop; the result is the
 // same polar factor.  The final rotation is written back to `warm`.
 ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,
-                      double* warm = nullptr, bool warm_valid = false, double** p_out = nullptr) {
+                      double* warm, bool warm_valid, double** p_out) {
   // Invariant: Y = P src with P orthogonal (P = Q^T, rows are the current
   // left singular vector estimates).  Each refresh diagonalises G = Y Y^T =
   // U^T diag U (Jacobi; rows of U are eigenvectors) and sets Y <- U Y,
@@ -1209,10 +1071,15 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
 // as  stage = [y, y B_1^T, .., y B_D^T, y A_1^T, .., y A_D^T]  (one batched
 // product), then out = [h, A_1..A_D, B_1..B_D] . stage (one product whose
 // contraction index runs over the operator blocks), then out += y h^T.
+// With right-site operators of their own (hopR64), the factors on the right
+// of y (B_k^T, A_k^T, h^T) are the right site's.
 // (staged: y is already in stage[0])
-hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged = false) {
+hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged) {
   const int x = M.dims[M.n - 1], D = M.D;
   const long long xx = (long long)x * x;
+  const double* hR = M.hopR64 ? M.hopR64 : M.hop64;
+  const double* AR = hR + xx;
+  const double* BR = hR + (1 + D) * xx;
   hipError_t e;
   if (!staged && (e = copy_bytes(M.lzStage, y, xx * 8, s))) return e;
   if (D > 0) {
@@ -1224,7 +1091,7 @@ hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bo
     g.batch = 2 * D;
     g.M = x; g.N = x; g.K = x;
     g.A = y; g.sAm = x; g.sAk = 1; g.sAb = 0; g.sAb2 = 0;
-    g.B = M.Bop64; g.sBk = 1; g.sBn = x; g.sBb = xx; g.sBb2 = (long long)(M.Aop64 - M.Bop64);
+    g.B = BR; g.sBk = 1; g.sBn = x; g.sBb = xx; g.sBb2 = (long long)(AR - BR);
     g.C = M.lzStage + xx; g.sCm = x; g.sCn = 1; g.sCb = xx; g.sCb2 = D * xx;
     if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
   }
@@ -1234,7 +1101,7 @@ hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bo
   g.B = M.lzStage; g.sBk = x; g.sBn = 1; g.sBk1 = xx;
   g.C = out; g.sCm = x; g.sCn = 1;
   if ((e = run(M, P_F64, g, s, OC_TOP_MM))) return e;
-  return mm(M, P_F64, y, false, M.hop64, true, out, x, 1.0, 1.0, s);  // + y h^T
+  return mm(M, P_F64, y, false, hR, true, out, x, 1.0, 1.0, s);  // + y h^T
 }
 
 // The top update, in three parts.  top_prepare copies the top operators to
@@ -1269,6 +1136,14 @@ ttn_status top_prepare(Member& M, hipStream_t s) {
   for (int k = 0; k < D; ++k) {
     HIPCHK(symmetrize_f64(M.Aop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
     HIPCHK(symmetrize_f64(M.Bop64 + k * xx, x, M.anti[k] ? -1.0 : 1.0, s));
+  }
+  if (M.hopR64) {
+    HIPCHK(copy_bytes(M.hopR64, M.topR, (1 + 2 * D) * xx * 8, s));
+    HIPCHK(symmetrize_f64(M.hopR64, x, 1.0, s));
+    for (int k = 0; k < D; ++k) {
+      HIPCHK(symmetrize_f64(M.hopR64 + (1 + k) * xx, x, M.anti[k] ? -1.0 : 1.0, s));
+      HIPCHK(symmetrize_f64(M.hopR64 + (1 + D + k) * xx, x, M.anti[k] ? -1.0 : 1.0, s));
+    }
   }
   HIPCHK(zero_int(M.lzint + LZ_DONE, 2, s));  // the flag and the count of restarts run
   return TTN_OK;
@@ -1351,7 +1226,7 @@ ttn_status top_restarts(Member& M, hipStream_t s, int count, bool sync, bool* co
 
 // keep_prev: the energy replaced is not the previous update's (a top update
 // continued after a first finish), so the stored previous energy stays
-ttn_status top_finish(Member& M, hipStream_t s, bool keep_prev = false) {
+ttn_status top_finish(Member& M, hipStream_t s, bool keep_prev) {
   const int x = M.dims[M.n - 1];
   const size_t xx = (size_t)x * x;
   HIPCHK(sign_fix(M.vtop, xx, s));
@@ -1703,7 +1578,64 @@ ttn_status top_after_graph(Ctx& c, int use_graph, ttn_status* warn) {
   return TTN_OK;
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// event timing of a handle's launches (ttn_profile, ttn_pos_profile)
+// ---------------------------------------------------------------------------
+ttn_status profile_switch(Profiler& P, KernelRecorder& krec, int enable) {
+  if (enable) {
+    if (P.ev.empty()) {
+      const size_t cap = 1 << 16;
+      P.ev.resize(2 * cap);
+      for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
+      P.cls.resize(cap);
+      P.flops.resize(cap);
+      P.bytes.resize(cap);
+    }
+    P.used = 0;
+    P.dropped = 0;
+  }
+  P.on = enable != 0;
+  krec.P = &P;
+  if (enable) kernel_timer() = &krec;
+  else if (kernel_timer() == &krec) kernel_timer() = nullptr;
+  return TTN_OK;
+}
+
+ttn_status profile_collect(Profiler& P, hipStream_t s, ttn_profile_entry* out, int max_entries, int* n_out) {
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<ttn_profile_entry> agg(OC_N + KID_N);
+  for (int c = 0; c < OC_N + KID_N; ++c) {
+    std::memset(&agg[c], 0, sizeof agg[c]);
+    if (c < OC_N) std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kOpNames[c]);
+    else std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kernel_name(c - OC_N));
+  }
+  for (size_t i = 0; i < P.used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
+    ttn_profile_entry& e = agg[P.cls[i]];
+    e.launches += 1;
+    e.ms += ms;
+    e.flops += P.flops[i];
+    e.bytes += P.bytes[i];
+  }
+  int n = 0;
+  for (int c = 0; c < OC_N + KID_N && n < max_entries; ++c)
+    if (agg[c].launches) out[n++] = agg[c];
+  *n_out = n;
+  P.used = 0;
+  if (P.dropped) {
+    const int d = P.dropped;
+    P.dropped = 0;
+    return fail(TTN_WPROF, "%d launches were not timed (event pool of %zu full): the record is incomplete", d,
+                P.cls.size());
+  }
+  return TTN_OK;
+}
+
+}  // namespace core
+}  // namespace ttn
+
+using namespace ttn::core;
 
 // ===========================================================================
 // C ABI
@@ -2159,57 +2091,12 @@ ttn_status ttn_autotune_load(const char* path, int* entries) {
 
 ttn_status ttn_profile(ttn_handle h, int enable) {
   if (!h) return fail(TTN_EINVAL, "null handle");
-  Profiler& P = h->c.prof;
-  if (enable) {
-    if (P.ev.empty()) {
-      const size_t cap = 1 << 16;
-      P.ev.resize(2 * cap);
-      for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
-      P.cls.resize(cap);
-      P.flops.resize(cap);
-      P.bytes.resize(cap);
-    }
-    P.used = 0;
-    P.dropped = 0;
-  }
-  P.on = enable != 0;
-  h->c.krec.P = &P;
-  if (enable) kernel_timer() = &h->c.krec;
-  else if (kernel_timer() == &h->c.krec) kernel_timer() = nullptr;
-  return TTN_OK;
+  return profile_switch(h->c.prof, h->c.krec, enable);
 }
 
 ttn_status ttn_profile_read(ttn_handle h, ttn_profile_entry* out, int max_entries, int* n_out) {
   if (!h || !out || !n_out) return fail(TTN_EINVAL, "bad arguments");
-  Profiler& P = h->c.prof;
-  HIPCHK(hipStreamSynchronize(h->c.s));
-  std::vector<ttn_profile_entry> agg(OC_N + KID_N);
-  for (int c = 0; c < OC_N + KID_N; ++c) {
-    std::memset(&agg[c], 0, sizeof agg[c]);
-    if (c < OC_N) std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kOpNames[c]);
-    else std::snprintf(agg[c].name, sizeof agg[c].name, "%s", kernel_name(c - OC_N));
-  }
-  for (size_t i = 0; i < P.used; ++i) {
-    float ms = 0.f;
-    HIPCHK(hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]));
-    ttn_profile_entry& e = agg[P.cls[i]];
-    e.launches += 1;
-    e.ms += ms;
-    e.flops += P.flops[i];
-    e.bytes += P.bytes[i];
-  }
-  int n = 0;
-  for (int c = 0; c < OC_N + KID_N && n < max_entries; ++c)
-    if (agg[c].launches) out[n++] = agg[c];
-  *n_out = n;
-  P.used = 0;
-  if (P.dropped) {
-    const int d = P.dropped;
-    P.dropped = 0;
-    return fail(TTN_WPROF, "%d launches were not timed (event pool of %zu full): the record is incomplete", d,
-                P.cls.size());
-  }
-  return TTN_OK;
+  return profile_collect(h->c.prof, h->c.s, out, max_entries, n_out);
 }
 
 // The spectrum and entropy of the matrix on the upper bond of a block of

@@ -125,6 +125,32 @@ def random_isometries(shapes, seed: int):
     return out
 
 
+def random_node_isometries(L: int, d: int, chi: int, seed: int):
+    """Seeded random isometries of a position-resolved network: for layer
+    tau = 1..n-1 an array (L >> tau, a, b, b), node-major.  For each layer in
+    order and each node in order, a Gaussian (b*b x a) matrix from
+    ``numpy.random.default_rng(seed)``, its reduced QR with the signs of
+    diag(R) folded into Q, w = Q^T (as random_isometries)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t, (a, b) in enumerate(layer_shapes(L, d, chi), start=1):
+        layer = np.empty((L >> t, a, b, b))
+        for m in range(L >> t):
+            g = rng.standard_normal((b * b, a))
+            q, r = np.linalg.qr(g)
+            s = np.sign(np.diag(r))
+            s[s == 0] = 1.0
+            layer[m] = (q * s[None, :]).T.reshape(a, b, b)
+        out.append(layer)
+    return out
+
+
+def uniform_node_isometries(ws, L: int):
+    """Position-resolved copies of a uniform network (layer tau of ws repeated
+    on its L >> tau nodes): the same state."""
+    return [np.repeat(np.asarray(w)[None], L >> t, axis=0) for t, w in enumerate(ws, start=1)]
+
+
 def layer_shapes(L: int, d: int, chi: int):
     """[(a, b), ...] of layers 1..n-1 (L = 2**n): bond dimensions chi_0 = d,
     chi_tau = min(chi_{tau-1}**2, chi)."""

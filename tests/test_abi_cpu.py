@@ -122,3 +122,47 @@ def test_position_resolved_calls_reject_bad_arguments(lib):
     S = ctypes.c_double(0.0)
     assert lib.ttn_entanglement_node(None, 0, 0, 0, site, ctypes.byref(S)) == binding.TTN_EINVAL
     assert b"bad arguments" in lib.ttn_last_error()
+
+
+def _pos_cfg(model, L, chi, w0, chunk=0):
+    h1, A, B = model.packed()
+    keep = [np.ascontiguousarray(x, dtype=np.float64) for x in (h1, A, B)]
+    cfg = binding.TTNPosConfig()
+    cfg.L, cfg.d, cfg.chi, cfg.D = L, model.d, chi, model.D
+    cfg.h1 = binding._dptr(keep[0])
+    cfg.A = binding._dptr(keep[1]) if model.D else None
+    cfg.B = binding._dptr(keep[2]) if model.D else None
+    cfg.shift, cfg.ly, cfg.chunk_nodes = math.nan, model.ly, chunk
+    if w0 is not None:
+        ws = [np.ascontiguousarray(w) for w in w0]
+        keep.append(ws)
+        arr = (ctypes.POINTER(ctypes.c_double) * len(ws))(*[binding._dptr(w) for w in ws])
+        keep.append(arr)
+        cfg.w0 = ctypes.cast(arr, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
+    return cfg, keep
+
+
+def test_node_resolved_workspace_and_validation(lib):
+    # host-only: sizes grow with the node count, missing isometries and a
+    # negative chunk are rejected, null handles too
+    model = inputs.xxx_chain()
+    out = ctypes.c_size_t(0)
+    sizes = []
+    for L in (16, 64):
+        w0 = inputs.random_node_isometries(L, model.d, 8, 0)
+        cfg, keep = _pos_cfg(model, L, 8, w0)
+        assert lib.ttn_pos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_OK
+        sizes.append(out.value)
+    assert 0 < sizes[0] < sizes[1]
+    cfg, keep = _pos_cfg(model, 16, 8, None)
+    assert lib.ttn_pos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    cfg, keep = _pos_cfg(model, 16, 8, inputs.random_node_isometries(16, 2, 8, 0), chunk=-1)
+    assert lib.ttn_pos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    cfg, keep = _pos_cfg(model, 12, 8, inputs.random_node_isometries(16, 2, 8, 0))
+    assert lib.ttn_pos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    e = (ctypes.c_double * 2)()
+    assert lib.ttn_pos_sweep(None, 1) == binding.TTN_EINVAL
+    assert lib.ttn_pos_energy(None, e) == binding.TTN_EINVAL
+    assert lib.ttn_pos_env(None, 1, 0, e) == binding.TTN_EINVAL
+    assert lib.ttn_pos_get(None, binding.TTN_POS_W, 1, e) == binding.TTN_EINVAL
+    assert lib.ttn_pos_free(None) == binding.TTN_OK

@@ -25,7 +25,8 @@ MODELS = [
 
 
 def make(model, L, chi, seed):
-    return Q.PositionalTTN(L, chi, model.h1, model.A, model.B, ly=model.ly, seed=seed)
+    nws = I.random_node_isometries(L, model.d, chi, seed)
+    return Q.PositionalTTN(L, chi, model.h1, model.A, model.B, nws, ly=model.ly)
 
 
 def brute_energy(r, psi_sites):
@@ -61,7 +62,7 @@ def test_uniform_copies_reproduce_the_uniform_reference():
     ws = I.random_isometries(T.layer_shapes(L, model.d, chi), 4)
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B, ws=[w.copy() for w in ws])
     e_u = ref.initialise()
-    r = Q.PositionalTTN(L, chi, model.h1, model.A, model.B, nws=Q.node_isometries(ws, L))
+    r = Q.PositionalTTN(L, chi, model.h1, model.A, model.B, I.uniform_node_isometries(ws, L))
     assert r.initialise() == pytest.approx(e_u, abs=1e-12)
     # averaged over the nodes of a level, the node matrices are the uniform
     # reference's position-averaged descent
@@ -159,7 +160,7 @@ def test_a_converged_uniform_state_is_not_raised():
     ref = T.TTNRef(L, chi, model.h1, model.A, model.B,
                    ws=I.random_isometries(T.layer_shapes(L, model.d, chi), 6))
     ref.run(12)
-    r = Q.PositionalTTN(L, chi, model.h1, model.A, model.B, nws=Q.node_isometries(ref.ws, L), v=ref.v.copy())
+    r = Q.PositionalTTN(L, chi, model.h1, model.A, model.B, I.uniform_node_isometries(ref.ws, L), v=ref.v.copy())
     e0 = r.initialise()
     assert e0 == pytest.approx(ref.history[-1], abs=1e-12)
     hist = r.run(2)
