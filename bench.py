@@ -1064,7 +1064,7 @@ def main():
         out.update(energy_fp64_reeval=m["e_re"], energy_rel_err_vs_fp64_reeval=m["err_re"])
     if args.tune_file and not tune_loaded and not args.no_autotune:
         B.autotune_save(args.tune_file)
-    out["launch_choices"] = "read from " + args.tune_file if tune_loaded else ("tuned" if not args.no_autotune else "default")
+    out["launch_choices"] = "read from " + os.path.basename(args.tune_file) if tune_loaded else ("tuned" if not args.no_autotune else "default")
     print(json.dumps(out))
 
 
