@@ -51,9 +51,11 @@ using namespace ttn::core;
 namespace {
 
 // staging of one launch chunk of nodes (bytes); a chunk holds at least one node
-constexpr size_t POS_STAGE_BYTES = 1ull << 30;
-// polar slabs of one launch group of nodes (bytes)
-constexpr size_t POS_SLAB_BYTES = 1ull << 30;
+constexpr size_t POS_STAGE_BYTES = 8ull << 30;
+// polar slabs of one launch group of nodes (bytes): a whole parity group of a
+// bulk level at chi = 128 (128 nodes of 64 MB) in one launch, so that its
+// one-work-group Jacobi solves run side by side
+constexpr size_t POS_SLAB_BYTES = 16ull << 30;
 // order above which a node's Jacobi solves take the blocked solver, one node
 // per launch (below, one work-group per node, every node of a chunk at once)
 constexpr int POS_GROUP_JACOBI_MAX = 128;
@@ -354,8 +356,8 @@ ttn_status pos_descend_xy(Pos& P, int lowest) {
 }
 
 // Environments of nodes m0, m0 + 2, .. (nn of them) of level t into the env
-// areas of the first nn polar slabs.
-ttn_status pos_env_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout& S) {
+// areas of polar slabs slab0, slab0 + 1, ..
+ttn_status pos_env_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout& S, int slab0) {
   const int a = P.dims[t], b = P.dims[t - 1], D = P.D;
   const long long bb = (long long)b * b, aa = (long long)a * a, cube = P.cube(t);
   const long long so = P.ops_stride(t - 1), sd = P.dx_stride(t);
@@ -375,7 +377,7 @@ ttn_status pos_env_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout& 
   g.M = a; g.N = (int)bb; g.K = (1 + 2 * D) * a; g.K2 = a;
   g.A = P.DX[t] + m0 * sd; g.sAm = a; g.sAk = 1; g.sAk1 = aa; g.sAb = 2 * sd;
   g.B = E; g.sBk = bb; g.sBk1 = cube; g.sBn = 1; g.sBb = es;
-  g.C = P.slabs + S.env; g.sCm = bb; g.sCn = 1; g.sCb = S.size;
+  g.C = P.slabs + slab0 * S.size + S.env; g.sCm = bb; g.sCn = 1; g.sCb = S.size;
   g.batch = nn;
   HIPCHK(run(P.M, P_F64, g, P.s, OC_LEFT_MUL));
   return TTN_OK;
@@ -433,12 +435,16 @@ ttn_status pos_group(Pos& P, int t, int p, double* host) {
   const int a = P.dims[t], b = P.dims[t - 1];
   const SlabLayout S = slab_layout(a, b);
   const long long count = P.nodes(t) / 2, cube = P.cube(t);
-  const long long ch = std::min(P.chunk[t], P.pchunk[t]);
-  for (long long j0 = 0; j0 < count; j0 += ch) {
-    const int nn = (int)std::min<long long>(ch, count - j0);
+  // a polar launch group of pchunk nodes; their environments in staging
+  // chunks of at most chunk nodes, each written into its nodes' slabs
+  for (long long j0 = 0; j0 < count; j0 += P.pchunk[t]) {
+    const int nn = (int)std::min<long long>(P.pchunk[t], count - j0);
     const long long m0 = p + 2 * j0;
-    ttn_status r = pos_env_chunk(P, t, m0, nn, S);
-    if (r) return r;
+    for (int e0 = 0; e0 < nn; e0 += (int)P.chunk[t]) {
+      const int ne = (int)std::min<long long>(P.chunk[t], nn - e0);
+      ttn_status r = pos_env_chunk(P, t, m0 + 2LL * e0, ne, S, e0);
+      if (r) return r;
+    }
     if (host) {
       for (int j = 0; j < nn; ++j)
         HIPCHK(hipMemcpyAsync(host + (j0 + j) * cube, P.slabs + j * S.size + S.env, cube * 8, hipMemcpyDeviceToHost,
@@ -446,7 +452,8 @@ ttn_status pos_group(Pos& P, int t, int p, double* host) {
       HIPCHK(hipStreamSynchronize(P.s));
       continue;
     }
-    if ((r = pos_polar_chunk(P, t, m0, nn, S))) return r;
+    ttn_status r = pos_polar_chunk(P, t, m0, nn, S);
+    if (r) return r;
   }
   return TTN_OK;
 }
@@ -527,7 +534,7 @@ PosSizes pos_sizes(const Member& M, int chunk_nodes) {
     pc = std::min<long long>(pc, std::max<long long>(1, nodes / 2));
     if (chunk_nodes > 0) pc = std::min<long long>(pc, chunk_nodes);
     z.pchunk[t] = pc;
-    z.slabs = std::max(z.slabs, std::min(z.chunk[t], pc) * sl);
+    z.slabs = std::max(z.slabs, pc * sl);
   }
   z.topR = (1 + 2LL * D) * x_top;
   return z;
