@@ -32,6 +32,13 @@ struct GemmDesc {
   // apart, run as one launch (member index outermost)
   int mcount;
   long long mstride;
+  // square outputs known to be symmetric (tri = 1) or, for the batch entries
+  // whose bit is set in anti (inner batch index), antisymmetric: a float64
+  // launch may compute the block upper triangle only and mirror the rest
+  // (beta must be 0); other launches ignore it.  The split count then follows
+  // the tiles computed.
+  int tri;
+  unsigned long long anti;
 };
 
 __host__ __device__ __forceinline__ int gemm_members(const GemmDesc& g) { return g.mcount > 1 ? g.mcount : 1; }

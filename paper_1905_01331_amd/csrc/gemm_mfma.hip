@@ -62,12 +62,24 @@ __device__ __forceinline__ long long k_offset(const OpView& v, int k) {
 // K range) run at about the same time on one XCD and read that panel from
 // HBM once.
 struct TileMap {
-  int gx, gy, gz, per, yfast;
+  int gx, gy, gz, per, yfast, tri;
 };
 constexpr int N_XCD = 8;
 __device__ __forceinline__ bool map_tile(const TileMap& t, int& tx, int& ty, int& tz) {
   const int id = blockIdx.x;
   const long long L = (long long)(id % N_XCD) * t.per + id / N_XCD;
+  if (t.tri) {
+    // the block upper triangle (ty <= tx) of a gx x gx tile grid, row by row
+    const int T = t.gx, ntri = T * (T + 1) / 2;
+    if (L >= (long long)ntri * t.gz) return false;
+    int r = (int)(L % ntri);
+    tz = (int)(L / ntri);
+    int row = 0;
+    while (r >= T - row) { r -= T - row; ++row; }
+    ty = row;
+    tx = row + r;
+    return true;
+  }
   if (L >= (long long)t.gx * t.gy * t.gz) return false;
   const int l = (int)L;
   if (t.yfast) { ty = l % t.gy; const int r = l / t.gy; tx = r % t.gx; tz = r / t.gx; }
@@ -76,10 +88,11 @@ __device__ __forceinline__ bool map_tile(const TileMap& t, int& tx, int& ty, int
 }
 // orient: 0 the smaller tile dimension fastest, 1 x fastest, 2 y fastest
 // (a launch-shape choice: the tiles compute the same values in any order)
-TileMap make_map(int gx, int gy, int gz, int orient) {
+TileMap make_map(int gx, int gy, int gz, int orient, bool tri = false) {
   TileMap t;
   t.gx = gx; t.gy = gy; t.gz = gz;
-  const long long total = (long long)gx * gy * gz;
+  t.tri = tri ? 1 : 0;
+  const long long total = tri ? (long long)gx * (gx + 1) / 2 * gz : (long long)gx * gy * gz;
   t.per = (int)((total + N_XCD - 1) / N_XCD);
   t.yfast = orient == 0 ? gy < gx : orient == 2;
   return t;
@@ -570,10 +583,14 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(GemmDesc g, int splits, in
 template <bool AKC, bool BKC, int TILE>
 hipError_t launch64(const GemmDesc& g, int splits, int kchunk, double* partial, hipStream_t s, int orient) {
   constexpr int TM = 32 * Tile64<TILE>::RI, TN = 8 * Tile64<TILE>::RJ;
-  const TileMap tm = make_map((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.batch * splits * gemm_members(g), orient);
+  const bool tri = g.tri != 0 && TM == TN && g.M == g.N;
+  const TileMap tm = make_map((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.batch * splits * gemm_members(g), orient,
+                              tri);
   size_t slot = 0;
   KernelTimer* kt = kernel_timer();
-  const double work = (double)g.batch * gemm_members(g);
+  const int T = (g.N + TN - 1) / TN;
+  // work of the tiles computed (a triangle counts its share of the square)
+  const double work = (double)g.batch * gemm_members(g) * (tri ? (double)(T + 1) / (2.0 * T) : 1.0);
   const int kid = KID_F64 + 4 * TILE + 2 * AKC + BKC;
   const bool timed = kt && kt->begin(kid, 2.0 * g.M * (double)g.N * g.K * work,
                                      8.0 * work * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N), s, &slot);
@@ -609,6 +626,32 @@ hipError_t launch(const GemmDesc& g, int splits, int kchunk, float* partial, hip
   return hipGetLastError();
 }
 
+// C[i][j] = sign C[j][i] for the strictly lower tiles (i / tile > j / tile)
+// of every batch entry and member of a product computed on its block upper
+// triangle; sign -1 for the entries whose bit is set in g.anti.
+__global__ void k_mirror_lower(GemmDesc g, int tile) {
+  const int n = g.M;
+  const long long nn = (long long)n * n;
+  const int b = blockIdx.y % g.batch, mem = blockIdx.y / g.batch;
+  if (g.skip && gload(member_ptr(g.skip, g, mem))) return;
+  double* C = (double*)member_ptr(g.C, g, mem) + batch_offset(g, b, g.sCb, g.sCb2);
+  const int bi = g.batch1 > 0 ? b % g.batch1 : b;
+  const double sign = (bi < 64 && ((g.anti >> bi) & 1ull)) ? -1.0 : 1.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < nn;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
+    if (i / tile <= j / tile) continue;
+    gstore(C + (long long)i * g.sCm + (long long)j * g.sCn, sign * gload(C + (long long)j * g.sCm + (long long)i * g.sCn));
+  }
+}
+
+hipError_t mirror_lower_f64(const GemmDesc& g, int tile, hipStream_t s) {
+  const long long nn = (long long)g.M * g.M;
+  int blocks = (int)std::min<long long>((nn + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_mirror_lower, dim3(blocks, g.batch * gemm_members(g)), dim3(256), 0, s, g, tile);
+  return hipGetLastError();
+}
+
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
@@ -619,8 +662,10 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 // Products with few output tiles (counted at the tile `tile`) and a long
 // contraction are split for about 1024 work-groups, each slice at least
 // 4 BK deep, at most 128 slices and what the scratch holds.
-static int split_count(const GemmDesc& g, int tile, int bk, size_t elem, size_t scratch_bytes, int* kchunk) {
-  const long long tiles = (long long)((g.M + tile - 1) / tile) * ((g.N + tile - 1) / tile) * g.batch;
+static int split_count(const GemmDesc& g, int tile, int bk, size_t elem, size_t scratch_bytes, int* kchunk,
+                       bool tri = false) {
+  const long long tm = (g.M + tile - 1) / tile, tn = (g.N + tile - 1) / tile;
+  const long long tiles = (tri ? tm * (tm + 1) / 2 : tm * tn) * g.batch;
   int splits = 1;
   if (tiles < 1024) {
     long long want = (1024 + tiles - 1) / tiles;
@@ -655,18 +700,24 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   else     { if (g.N % 2 || g.sBk % 2 || (g.K2 > 0 && g.sBk1 % 2)) return hipErrorNotSupported; }
   // the split count follows the shape alone (counted at 64 x 64 tiles); the
   // tile (64 x 64 by default) is a launch choice
+  // a symmetric (antisymmetric) square output: the 64 x 64 tiles of the
+  // block upper triangle, then the mirror
+  const bool tri = g.tri != 0 && g.M == g.N && g.beta == 0.0;
+  GemmDesc gt = g;
+  gt.tri = tri ? 1 : 0;
   int kchunk = 0;
-  const int splits = split_count(g, 64, BK64, sizeof(double), scratch_bytes, &kchunk);
-  const int tile = how.tile >= 1 && how.tile <= 3 ? how.tile - 1 : 0;
+  const int splits = split_count(g, 64, BK64, sizeof(double), scratch_bytes, &kchunk, tri);
+  const int tile = tri ? 0 : (how.tile >= 1 && how.tile <= 3 ? how.tile - 1 : 0);
   double* partial = (double*)scratch;
   const int o = how.orient;
   hipError_t e;
-  if (akc && bkc) e = launch64_tile<true, true>(tile, g, splits, kchunk, partial, s, o);
-  else if (akc) e = launch64_tile<true, false>(tile, g, splits, kchunk, partial, s, o);
-  else if (bkc) e = launch64_tile<false, true>(tile, g, splits, kchunk, partial, s, o);
-  else e = launch64_tile<false, false>(tile, g, splits, kchunk, partial, s, o);
+  if (akc && bkc) e = launch64_tile<true, true>(tile, gt, splits, kchunk, partial, s, o);
+  else if (akc) e = launch64_tile<true, false>(tile, gt, splits, kchunk, partial, s, o);
+  else if (bkc) e = launch64_tile<false, true>(tile, gt, splits, kchunk, partial, s, o);
+  else e = launch64_tile<false, false>(tile, gt, splits, kchunk, partial, s, o);
   if (e != hipSuccess) return e;
-  if (splits > 1) return splitk_reduce_f64(g, splits, partial, s);
+  if (splits > 1 && (e = splitk_reduce_f64(gt, splits, partial, s)) != hipSuccess) return e;
+  if (tri) return mirror_lower_f64(gt, 64, s);
   return hipSuccess;
 }
 

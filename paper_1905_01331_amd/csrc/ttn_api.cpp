@@ -483,11 +483,17 @@ hipError_t apply_l_k(const Member& M, Prec p, const void* O, long long sO, const
   g.beta = beta;
   return run(M, p, g, s, OC_APPLY_L);
 }
-// C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b)
+// C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b).  Every
+// use has Q = O w with P = w and O symmetric, or antisymmetric for the terms
+// whose bit is set in anti, so C is symmetric (antisymmetric) and a float64
+// launch computes its upper triangle only.
 hipError_t close_aa_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                      unsigned long long anti) {
   if (nk < 1) return hipSuccess;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   long long bb = (long long)b * b;
   g.batch = nk;
   g.M = a; g.N = a; g.K = (int)bb; g.K2 = 0;
@@ -547,8 +553,8 @@ hipError_t apply_l(const Member& M, Prec p, const void* O, const void* X, void* 
   return apply_l_k(M, p, O, 0, X, 0, Y, 0, a, b, beta, 1, s);
 }
 hipError_t close_aa(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
-                    double beta, hipStream_t s) {
-  return close_aa_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+                    double beta, hipStream_t s, bool anti) {
+  return close_aa_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s, anti ? 1ull : 0ull);
 }
 hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void* Y, int a, int b, double alpha,
                     double beta, hipStream_t s) {
@@ -675,12 +681,12 @@ ttn_status local_energies(Member& M, double* W, long long total, const PosLayout
         HIPCHK(apply_r(M, P_F64, opB[cur] + k * bb, w, T1, a, b, 0.0, s));
         HIPCHK(apply_l(M, P_F64, opA[cur] + k * bb, T1, T2, a, b, k ? 1.0 : 0.0, s));
       }
-      HIPCHK(close_aa(M, P_F64, w, T2, W + P.bop[t], a, b, 1.0, 0.0, s));
+      HIPCHK(close_aa(M, P_F64, w, T2, W + P.bop[t], a, b, 1.0, 0.0, s, false));
       for (int k = 0; k < D; ++k) {
         HIPCHK(apply_r(M, P_F64, opA[cur] + k * bb, w, T1, a, b, 0.0, s));
-        HIPCHK(close_aa(M, P_F64, w, T1, opA[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s));
+        HIPCHK(close_aa(M, P_F64, w, T1, opA[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s, M.anti[k] != 0));
         HIPCHK(apply_l(M, P_F64, opB[cur] + k * bb, w, T1, a, b, 0.0, s));
-        HIPCHK(close_aa(M, P_F64, w, T1, opB[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s));
+        HIPCHK(close_aa(M, P_F64, w, T1, opB[cur ^ 1] + k * aa, a, b, 1.0, 0.0, s, M.anti[k] != 0));
       }
       cur ^= 1;
     }
@@ -733,12 +739,12 @@ ttn_status stage_ascend(Member& M, int tau, hipStream_t s) {
   const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
   const void* w = M.wT[tau];
   HIPCHK(s_apply(M, tau - 1, w, a, b, s));
-  HIPCHK(close_aa(M, p, w, M.Sw, M.opH[tau], a, b, 1.0, 0.0, s));
+  HIPCHK(close_aa(M, p, w, M.Sw, M.opH[tau], a, b, 1.0, 0.0, s, false));
   // all product terms at once: A'_k = C(w, A_k .r w), B'_k = C(w, B_k .l w)
   HIPCHK(apply_r_k(M, p, M.opA[tau - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opA[tau], aa, a, b, 1.0, 0.0, D, s));
+  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opA[tau], aa, a, b, 1.0, 0.0, D, s, M.anti_bits()));
   HIPCHK(apply_l_k(M, p, M.opB[tau - 1], bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opB[tau], aa, a, b, 1.0, 0.0, D, s));
+  HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.opB[tau], aa, a, b, 1.0, 0.0, D, s, M.anti_bits()));
   return TTN_OK;
 }
 
@@ -818,9 +824,9 @@ ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
     const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
     const void* w = M.wT[sg];
     HIPCHK(apply_r_k(M, p, prevA, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.At[sg], aa, a, b, 1.0, 0.0, D, s));
+    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.At[sg], aa, a, b, 1.0, 0.0, D, s, M.anti_bits()));
     HIPCHK(apply_l_k(M, p, prevB, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.Bt[sg], aa, a, b, 1.0, 0.0, D, s));
+    HIPCHK(close_aa_k(M, p, w, 0, M.S2, cube, M.Bt[sg], aa, a, b, 1.0, 0.0, D, s, M.anti_bits()));
     prevA = M.At[sg];
     prevB = M.Bt[sg];
   }
@@ -864,8 +870,9 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
 // The eigenproblem of the polar update's Gram matrix (M.G -> eigenvalues on
 // its diagonal, eigenvectors as the rows of M.V).  The solver depends on the
 // order a alone, so a member of a batch does the arithmetic it does alone:
-// a <= 64 the one-work-group solver (all members of a launch group in one
-// launch), a > 64 the blocked solver with its persistent grid.  In a batch a
+// a <= POLAR_ONE_WG_MAX the one-work-group solver (G and its eigenvectors
+// both in LDS; all members of a launch group in one launch), larger a the
+// blocked solver with its persistent grid.  In a batch a
 // blocked solve of a <= 128 (at most 26 work-groups) runs on the member's own
 // stream, one launch per member of its launch group; larger ones (up to 128
 // work-groups) go one at a time through the batch's shared stream, so the
@@ -873,7 +880,7 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
 // units hold.
 hipError_t polar_jacobi(Member& M, int a, double jtol, int it, const int* skip, hipStream_t s) {
   int* info = M.jinfo + 2 * it;
-  if (a <= 64) return jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, nullptr, s, skip);
+  if (a <= POLAR_ONE_WG_MAX) return jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, nullptr, s, skip);
   if (M.solo) return jacobi_eig_f64(M.G, M.V, a, POLAR_JACOBI_SWEEPS, jtol, info, M.jscratch, s, skip);
   if (a <= 128) {
     const GroupCtx g = grp();
@@ -938,8 +945,9 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     const bool extra = it == nref;
     if (extra && M.evd) break;
     const int* skip = extra ? M.skip3 : nullptr;
-    GemmDesc g = desc0();  // G = Y Y^T
+    GemmDesc g = desc0();  // G = Y Y^T (symmetric: upper triangle and mirror)
     g.M = a; g.N = a; g.K = (int)K;
+    g.tri = 1;
     g.A = Yc; g.sAm = K; g.sAk = 1;
     g.B = Yc; g.sBk = 1; g.sBn = K;
     g.C = M.G; g.sCm = a; g.sCn = 1;
@@ -1011,6 +1019,7 @@ ttn_status ortho_check(Member& M, int tau, hipStream_t s) {
   const long long K = (long long)M.dims[tau - 1] * M.dims[tau - 1];
   GemmDesc g = desc0();
   g.M = a; g.N = a; g.K = (int)K;
+  g.tri = 1;
   g.A = M.w64[tau]; g.sAm = K; g.sAk = 1;
   g.B = M.w64[tau]; g.sBk = 1; g.sBn = K;
   g.C = M.G; g.sCm = a; g.sCn = 1;

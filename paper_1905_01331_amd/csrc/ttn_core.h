@@ -52,6 +52,10 @@ constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO
 constexpr int LZ_DONE = 8;  // lzint slot of the top solver's per-member convergence flag
 constexpr int POLAR_REFRESH = 2;
 constexpr int POLAR_JACOBI_SWEEPS = 60;  // sweep limit of a polar Jacobi solve
+// largest Gram order solved by the one-work-group Jacobi (G and U, 2 * 96^2
+// doubles, and a round's rotation tables fit the 160 KB of LDS); above it the
+// blocked solver
+constexpr int POLAR_ONE_WG_MAX = 96;
 constexpr int POLAR_THIRD_IF = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
 
@@ -161,6 +165,13 @@ struct Member {
   double bytes_layers = 0.0, bytes_top = 0.0;
 
   Prec gp() const { return prec == TTN_FP64 ? P_F64 : (prec == TTN_FP32 ? P_F32 : P_BF16X3); }
+  // bit k set: product term k is antisymmetric (its ascended operators are too)
+  unsigned long long anti_bits() const {
+    unsigned long long m = 0;
+    for (size_t k = 0; k < anti.size() && k < 64; ++k)
+      if (anti[k]) m |= 1ull << k;
+    return m;
+  }
   size_t el(size_t n_) const { return n_ * esz; }
   void* at(void* base, size_t elems) const { return (char*)base + elems * esz; }
   const void* at(const void* base, size_t elems) const { return (const char*)base + elems * esz; }
@@ -192,7 +203,8 @@ hipError_t apply_r_k(const Member& M, Prec p, const void* O, long long sO, const
 hipError_t apply_l_k(const Member& M, Prec p, const void* O, long long sO, const void* X, long long sX, void* Y,
                      long long sY, int a, int b, double beta, int nk, hipStream_t s);
 hipError_t close_aa_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s);
+                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                      unsigned long long anti);
 hipError_t left_mul_k(const Member& M, Prec p, const void* X, long long sX, const void* P, long long sP, void* Y,
                       long long sY, int a, int b, double alpha, double beta, int nk, hipStream_t s);
 hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,

@@ -177,12 +177,16 @@ hipError_t pos_apply_l_sum(Pos& P, const double* O, long long ok, long long on, 
   batch2(g, a, nn, 0, on, bb, xn, bb, yn);
   return run(P.M, P_F64, g, P.s, OC_APPLY_L);
 }
-// C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r] over (k, node)
+// C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r] over (k, node); every use has
+// P = w, Q = O w with O symmetric (antisymmetric for the bits of anti, by k),
+// so C is computed on its upper triangle and mirrored
 hipError_t pos_close(Pos& P, const double* Pm, long long pk, long long pn, const double* Qm, long long qk, long long qn,
-                     double* C, long long ck, long long cn, int a, int b, int nk, int nn) {
+                     double* C, long long ck, long long cn, int a, int b, int nk, int nn, unsigned long long anti) {
   if (nk < 1 || nn < 1) return hipSuccess;
   const long long bb = (long long)b * b;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   g.M = a; g.N = a; g.K = (int)bb;
   g.A = Pm; g.sAm = bb; g.sAk = 1;
   g.B = Qm; g.sBk = 1; g.sBn = bb;
@@ -265,15 +269,16 @@ ttn_status pos_ascend_nodes(Pos& P, int t, long long m0, int st, long long count
     const double* opR = opL + so;
     const long long cs = 2LL * st * so;
     double* out = P.OPS[t] + m * sp;
-    HIPCHK(pos_close(P, w, 0, st * cube, Sw, 0, sws, out, 0, st * sp, a, b, 1, nn));  // h
+    HIPCHK(pos_close(P, w, 0, st * cube, Sw, 0, sws, out, 0, st * sp, a, b, 1, nn, 0));  // h
     if (D == 0) continue;
     // A'_k = C(w, A_{R,k} .r w)
     HIPCHK(pos_apply_r(P, opR + bb, bb, cs, w, 0, st * cube, S2, cube, sws, a, b, 0.0, D, nn));
-    HIPCHK(pos_close(P, w, 0, st * cube, S2, cube, sws, out + aa, aa, st * sp, a, b, D, nn));
+    HIPCHK(pos_close(P, w, 0, st * cube, S2, cube, sws, out + aa, aa, st * sp, a, b, D, nn, P.M.anti_bits()));
     // B'_k = C(w, B_{L,k} .l w)
     for (int k = 0; k < D; ++k)
       HIPCHK(pos_apply_l(P, opL + (1 + D + k) * bb, cs, w, st * cube, S2 + k * cube, sws, a, b, 0.0, nn));
-    HIPCHK(pos_close(P, w, 0, st * cube, S2, cube, sws, out + (1 + D) * aa, aa, st * sp, a, b, D, nn));
+    HIPCHK(pos_close(P, w, 0, st * cube, S2, cube, sws, out + (1 + D) * aa, aa, st * sp, a, b, D, nn,
+                     P.M.anti_bits()));
   }
   return TTN_OK;
 }
@@ -407,9 +412,10 @@ ttn_status pos_polar_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout
   Mn.splitk_bytes = (size_t)(128LL * a * a * 8);
   Mn.solo = true;
   Mn.evd = false;
-  // one work-group per node up to POS_GROUP_JACOBI_MAX, else (one node per
-  // launch) the blocked solver with the handle's scratch
-  Mn.jscratch = (nn == 1 && a > 64) ? P.M.jscratch : nullptr;
+  // one work-group per node (up to POS_GROUP_JACOBI_MAX); a single node above
+  // POLAR_ONE_WG_MAX takes the blocked solver with the handle's scratch, as
+  // the uniform network does
+  Mn.jscratch = (nn == 1 && a > POLAR_ONE_WG_MAX) ? P.M.jscratch : nullptr;
   {
     GroupScope grp_nodes(nn, S.size * 8);
     HIPCHK(zero_int(Mn.jinfo, 64, P.s));

@@ -26,7 +26,7 @@ def B():
     return binding
 
 
-# (name, model, L, chi, precision): the one-work-group Jacobi (a <= 64), the
+# (name, model, L, chi, precision): the one-work-group Jacobi (a <= 96), the
 # persistent blocked Jacobi (a = 160), a mixed-precision bulk
 GRAPH_CASES = [
     ("tfim_L64_chi24_fp64", I.tfim_chain(1.0), 64, 24, "fp64"),
@@ -141,10 +141,11 @@ def test_batch_members_follow_their_solo_paths(B):
 
 
 def test_batch_with_larger_bond_dimension(B):
-    # a member with 64 < a <= 128 takes the blocked Jacobi solver in a batch
-    # as it does alone (the solver is chosen by the order of the Gram matrix
-    # only), so both members follow their solo runs bit for bit
-    draws = [(1.0, 64, 96), (1.1, 128, 32)]
+    # a member with 96 < a <= 128 takes the blocked Jacobi solver in a batch
+    # as it does alone, a member with a = 96 the one-work-group solver in both
+    # (the solver is chosen by the order of the Gram matrix only), so every
+    # member follows its solo run bit for bit
+    draws = [(1.0, 64, 112), (1.1, 128, 32), (0.9, 64, 96)]
     ws = [I.random_isometries(T.layer_shapes(L, 2, chi), 20 + i) for i, (h, L, chi) in enumerate(draws)]
     batch = B.TTN([B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w) for (h, L, chi), w in zip(draws, ws)])
     solo = [B.TTN(B.ChainInput(I.tfim_chain(h), L, chi, "fp64", w0=w)) for (h, L, chi), w in zip(draws, ws)]
@@ -206,7 +207,8 @@ def test_autotuner_choices_leave_results_unchanged(B):
 def test_benchmarked_batch_follows_solo_runs_with_tuner_and_graph(B):
     # the batch as the benchmark runs it: float32 bulk, launch tuner on,
     # sweeps replayed from the captured graph, members of uneven L, chi and
-    # h, two launch groups, a chi = 96 member (blocked Jacobi); every member
+    # h, two launch groups, chi = 96 members (the one-work-group Jacobi with
+    # G and its eigenvectors in LDS, one launch for their group); every member
     # equals its solo run (tuner on too, eager) bit for bit
     draws = [(0.9, 64, 96), (1.2, 128, 48), (0.7, 128, 48), (1.4, 256, 32), (1.1, 64, 96), (0.6, 512, 64)]
     mk = lambda i, d: B.ChainInput(I.tfim_chain(d[0]), d[1], d[2], "fp32", seed=1000 + i)
