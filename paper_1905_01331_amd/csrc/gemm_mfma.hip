@@ -449,6 +449,14 @@ struct Stage64 {
   static constexpr int NV = (MN * BK64) / (2 * NT);
   f64x2 r[NV];
   __device__ __forceinline__ void load(const OpView64& v, int mn0, int k0, int kend, int tid) {
+    // a two-level contraction index whose inner extent is a multiple of the
+    // chunk: the chunk lies in one outer block, whose offset is computed once
+    const bool blk = v.K2 > 0 && (v.K2 % BK64) == 0;
+    long long kbase = 0;
+    if (blk) {
+      const int k1 = k0 / v.K2;
+      kbase = (long long)k1 * v.s_k1 + (long long)(k0 - k1 * v.K2) * v.s_k;
+    }
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int f = tid + i * NT;
@@ -457,7 +465,8 @@ struct Stage64 {
       else              { k = f / (MN / 2); mn = (f % (MN / 2)) * 2; }
       int gm = mn0 + mn, gk = k0 + k;
       if (gm < v.MN && gk < kend) {
-        const double* p = KC ? v.base + (long long)gm * v.s_mn + k_offset64(v, gk) : v.base + gm + k_offset64(v, gk);
+        const long long ko = blk ? kbase + (long long)k * v.s_k : k_offset64(v, gk);
+        const double* p = KC ? v.base + (long long)gm * v.s_mn + ko : v.base + gm + ko;
         r[i] = gload(reinterpret_cast<const f64x2*>(p));
       } else {
         r[i] = f64x2{0.0, 0.0};
