@@ -222,6 +222,13 @@ hipError_t copy_strided_f64(double* dst, long long ds, const double* src, long l
 // out[0] = 1 when out[0] != 0 or any x[j stride + i0] != 0 (j < count); out[1]
 // likewise with i1 (one work-item)
 hipError_t flags_or(const double* x, long long stride, int count, int i0, int i1, double* out, hipStream_t s);
+// nrm2[i] = squared norm of row i of Y (m x k); flag[0] = 1 when every row's
+// norm is at least rel times the largest, else 0 (numerically null rows)
+hipError_t no_null_rows(const double* Y, int m, long long k, double rel, double* nrm2, int* flag, hipStream_t s);
+// unless *flag: the rows i of Y (m x k) whose squared norm nrm2[i] lies below
+// rel^2 max_j nrm2[j] become rel sqrt(max_j nrm2[j]) T[i, :]
+hipError_t fill_null_rows(double* Y, const double* T, const double* nrm2, int m, long long k, double rel,
+                          const int* flag, hipStream_t s);
 // ||W W^T - I||_F from the Gram G (n x n): out[0] = sqrt(sum (G - I)^2)
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s);
 

@@ -489,4 +489,71 @@ hipError_t flags_or(const double* x, long long stride, int count, int i0, int i1
   return hipGetLastError();
 }
 
+namespace {
+// maximum of x[0..n), by the whole block (blockDim 256)
+__device__ double block_max(const double* x, int n) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, x[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+// out[i] = sum_j Y[i, j]^2, one block per row, fixed order
+__global__ void k_row_sumsq(const double* Y, long long k, double* out, long long ms_) {
+  Y = mshift(Y, ms_); out = mshift(out, ms_);
+  __shared__ double red[256];
+  const double* y = Y + (long long)blockIdx.x * k;
+  double acc = 0.0;
+  for (long long j = threadIdx.x; j < k; j += blockDim.x) acc += y[j] * y[j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+__global__ void k_no_null_rows(const double* nrm2, int m, double rel, int* flag, long long ms_) {
+  nrm2 = mshift(nrm2, ms_); flag = mshift(flag, ms_);
+  const double floor_ = rel * rel * block_max(nrm2, m);
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x)
+    if (nrm2[i] < floor_) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) flag[0] = any ? 0 : 1;
+}
+__global__ void k_fill_null_rows(double* Y, const double* T, const double* nrm2, int m, long long k, double rel,
+                                 const int* flag, long long ms_) {
+  Y = mshift(Y, ms_); T = mshift(T, ms_); nrm2 = mshift(nrm2, ms_); flag = mshift(flag, ms_);
+  if (flag[0]) return;
+  const double nmax = block_max(nrm2, m);
+  const int i = blockIdx.x;
+  if (!(nrm2[i] < rel * rel * nmax)) return;
+  const double scale = rel * sqrt(nmax);
+  for (long long j = threadIdx.x; j < k; j += blockDim.x) Y[(long long)i * k + j] = scale * T[(long long)i * k + j];
+}
+}  // namespace
+
+hipError_t no_null_rows(const double* Y, int m, long long k, double rel, double* nrm2, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_sumsq, dim3(m, grp().count), dim3(256), 0, s, Y, k, nrm2, grp().stride);
+  hipLaunchKernelGGL(k_no_null_rows, dim3(1, grp().count), dim3(256), 0, s, nrm2, m, rel, flag, grp().stride);
+  return hipGetLastError();
+}
+
+hipError_t fill_null_rows(double* Y, const double* T, const double* nrm2, int m, long long k, double rel,
+                          const int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_null_rows, dim3(m, grp().count), dim3(256), 0, s, Y, T, nrm2, m, k, rel, flag,
+                     grp().stride);
+  return hipGetLastError();
+}
+
 }  // namespace ttn

@@ -909,8 +909,17 @@ hipError_t polar_jacobi(Member& M, int a, double jtol, int it, const int* skip, 
 // first Gram is taken of warm^T src, which is nearly diagonal once the sweep
 // settles, so the Jacobi sweeps of the first refresh drop; the result is the
 // same polar factor.  The final rotation is written back to `warm`.
+// With `fill_from` (the current isometry, a x K) and `fill_tmp` (a x K
+// scratch), rows of the first refresh's rotated matrix that are numerically
+// null (norm below 4 eps sqrt(a) times the largest: rounding noise of the
+// rotation, where the environment is rank deficient and the polar factor is
+// not fixed) are replaced by the same rotation of the current isometry's
+// rows at that scale, so that the
+// completion leans toward the current isometry and the refreshes after it
+// orthogonalise well-separated rows instead of rounding noise.  Nothing
+// changes when no row is null (a device flag skips the fill).
 ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,
-                      double* warm, bool warm_valid, double** p_out) {
+                      double* warm, bool warm_valid, double** p_out, const double* fill_from, double* fill_tmp) {
   // Invariant: Y = P src with P orthogonal (P = Q^T, rows are the current
   // left singular vector estimates).  Each refresh diagonalises G = Y Y^T =
   // U^T diag U (Jacobi; rows of U are eigenvectors) and sets Y <- U Y,
@@ -966,6 +975,21 @@ ttn_status polar_core(Member& M, const double* src, int a, long long K, double s
     r.C = Yn; r.sCm = K; r.sCn = 1;
     r.skip = skip;
     HIPCHK(run(M, P_F64, r, s));
+    if (it == 0 && !use_warm && !M.evd && fill_from && fill_tmp) {
+      // a row of U src whose norm is within a few roundings of the largest's
+      // eps sqrt(a) is rounding noise of the rotation
+      const double rel = 4.0 * 2.220446049250313e-16 * std::sqrt((double)a);
+      int* none = M.skip3 + 1;  // 1: no null row, the fill is skipped
+      HIPCHK(no_null_rows(Yn, a, K, rel, M.nrm, none, s));
+      GemmDesc t = desc0();  // T = U w_cur
+      t.M = a; t.N = (int)K; t.K = a;
+      t.A = M.V; t.sAm = a; t.sAk = 1;
+      t.B = fill_from; t.sBk = K; t.sBn = 1;
+      t.C = fill_tmp; t.sCm = K; t.sCn = 1;
+      t.skip = none;
+      HIPCHK(run(M, P_F64, t, s));
+      HIPCHK(fill_null_rows(Yn, fill_tmp, M.nrm, a, K, rel, none, s));
+    }
     if (it == 0 && !use_warm) {
       HIPCHK(copy_bytes(Pc, M.V, (size_t)a * a * 8, s));
     } else {
@@ -1043,7 +1067,7 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
   ttn_status st;
   if (M.gauge_fix) {
     double* P = nullptr;
-    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, nullptr, false, &P);
+    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, nullptr, false, &P, M.w64[tau], M.env64);
     if (st) return st;
     // absorb P^T on the input legs of the layer above: w' = P .l (P .r w),
     // or v' = P v P^T at the top
@@ -1060,7 +1084,8 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
       M.rho_from = M.pc_from = 1 << 20;
     }
   } else {
-    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, M.Qw[tau], M.qw_valid[tau] != 0);
+    st = polar_core(M, M.Y2, a, K, -1.0, M.w64[tau], s, M.Qw[tau], M.qw_valid[tau] != 0, nullptr, M.w64[tau],
+                    M.env64);
     if (st) return st;
     M.qw_valid[tau] = 1;
   }

@@ -218,7 +218,8 @@ hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, 
 // out = sign * polar(src), src a x K float64 (M.Y, M.Y2, M.G, M.V, M.Q,
 // M.Q2, M.nrm, M.jinfo, M.skip3, M.scal as scratch)
 ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,
-                      double* warm = nullptr, bool warm_valid = false, double** p_out = nullptr);
+                      double* warm = nullptr, bool warm_valid = false, double** p_out = nullptr,
+                      const double* fill_from = nullptr, double* fill_tmp = nullptr);
 // the top update: prepare (float64 operators, symmetrised), Lanczos restarts,
 // finish (sign of v, energy)
 hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged = false);

@@ -65,8 +65,8 @@ constexpr double POS_REG = 1e-30;            // tie-breaker toward the current i
 long long al32(long long x) { return (x + 31) & ~31LL; }  // doubles to a 256-byte boundary
 
 struct SlabLayout {  // offsets in doubles within one node's polar slab
-  long long env = 0, Y = 0, Y2 = 0, G = 0, V = 0, Q = 0, Q2 = 0, nrm = 0, jinfo = 0, skip3 = 0, scal = 0, part = 0,
-            splitk = 0, size = 0;
+  long long env = 0, wold = 0, Y = 0, Y2 = 0, G = 0, V = 0, Q = 0, Q2 = 0, nrm = 0, jinfo = 0, skip3 = 0, scal = 0,
+            part = 0, splitk = 0, size = 0;
 };
 SlabLayout slab_layout(int a, int b) {
   SlabLayout S;
@@ -74,6 +74,7 @@ SlabLayout slab_layout(int a, int b) {
   long long o = 0;
   auto take = [&](long long k) { long long r = o; o = al32(o + k); return r; };
   S.env = take(cube);
+  S.wold = take(cube);
   S.Y = take(cube);
   S.Y2 = take(cube);
   S.G = take(aa);
@@ -394,7 +395,7 @@ ttn_status pos_polar_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout
   const int a = P.dims[t], b = P.dims[t - 1];
   const long long K = (long long)b * b, aK = (long long)a * K, cube = P.cube(t);
   double* sl = P.slabs;
-  HIPCHK(copy_strided_f64(sl + S.Y, S.size, P.W[t] + m0 * cube, 2 * cube, cube, nn, P.s));  // w_old
+  HIPCHK(copy_strided_f64(sl + S.wold, S.size, P.W[t] + m0 * cube, 2 * cube, cube, nn, P.s));  // w_old
   Member Mn = P.M;  // the polar update's scratch: slab 0, the others S.size doubles apart
   Mn.flops_acc = Mn.traffic_acc = 0.0;
   Mn.Y = sl + S.Y;
@@ -424,8 +425,10 @@ ttn_status pos_polar_chunk(Pos& P, int t, long long m0, int nn, const SlabLayout
     HIPCHK(pair_f64(env, env, aK, Mn.scal + SCAL_TMP0, Mn.part, P.s));
     HIPCHK(sqrt_inplace(Mn.scal + SCAL_TMP0, P.s));
     HIPCHK(copy_bytes(Mn.Y2, env, (size_t)aK * 8, P.s));
-    HIPCHK(axpy_dev(Mn.Y2, Mn.Y, Mn.scal + SCAL_TMP0, -POS_REG, (size_t)aK, P.s));
-    ttn_status r = polar_core(Mn, Mn.Y2, a, K, -1.0, env, P.s);
+    HIPCHK(axpy_dev(Mn.Y2, sl + S.wold, Mn.scal + SCAL_TMP0, -POS_REG, (size_t)aK, P.s));
+    // the environment's area is free once Y2 holds it: scratch of the null-row
+    // fill, then the output
+    ttn_status r = polar_core(Mn, Mn.Y2, a, K, -1.0, env, P.s, nullptr, false, nullptr, sl + S.wold, env);
     if (r) return r;
   }
   P.M.flops_acc += Mn.flops_acc;
