@@ -36,6 +36,16 @@ TOL_CANCEL = {"fp32": 2e-5, "bf16x3": 3e-3}
 TOL_ENERGY = {"fp32": 2e-6, "bf16x3": 2e-5}
 
 
+def energy_bar(prec, levels):
+    """The mixed-precision energy bar at depth `levels`: float32 2e-6;
+    split-bf16 (levels - 1) * 2 * 2^-18 (each split operand exact to 2^-18
+    relative, a product of two to about twice that, carried through
+    levels - 1 ascents), at least 2e-5."""
+    if prec == "bf16x3":
+        return max(TOL_ENERGY[prec], (levels - 1) * 2.0 * 2.0 ** -18)
+    return TOL_ENERGY[prec]
+
+
 @pytest.fixture(scope="module")
 def B():
     if not torch.cuda.is_available():
@@ -132,7 +142,7 @@ def test_full_size_top_layer_sampled(B, tuned, name, model, L, chi, prec, bound)
     st = t.stats()
     assert st.ortho_err_max < 64 * np.finfo(np.float64).eps * chi ** 1.5
     scale = max(abs(e2), abs(c) / model.ly)
-    assert e2 <= e1 + TOL_ENERGY[prec] * scale
+    assert e2 <= e1 + energy_bar(prec, n) * scale
     # float64 re-evaluation of the final state
     state = [t.get_tensor(tau) for tau in range(1, n)]
     v_top = t.get_tensor(B.TTN_TOP)
@@ -143,7 +153,7 @@ def test_full_size_top_layer_sampled(B, tuned, name, model, L, chi, prec, bound)
     e_re = r.energy()[0]
     r.close()
     print(f"  e = {e2:.10f}, float64 re-evaluation {e_re:.10f}", flush=True)
-    assert abs(e2 - e_re) <= TOL_ENERGY[prec] * scale
+    assert abs(e2 - e_re) <= energy_bar(prec, n) * scale
     if bound is not None:
         assert e_re >= bound
 
