@@ -9,10 +9,14 @@ method's arithmetic).
 
 Modules
 -------
-ttn_ref      the sweep, written from Secs. II.C and III of the paper
-physics_ref  exact diagonalisation, closed forms and brute-force state vectors
-             used to pin ``ttn_ref`` against mathematics other than itself
+ttn_ref         the sweep, written from Secs. II.C and III of the paper
+ttn_positional  the same with an isometry of its own at every node
+ttn_complex     the same for complex tensors (Hamiltonians with complex
+                matrix elements): bra copies conjugated
+physics_ref     exact diagonalisation, closed forms and brute-force state
+                vectors used to pin the three against mathematics other than
+                themselves
 
-Every function in ``ttn_ref`` has at least one pin in ``tests/`` (see the
-module docstrings).  Nothing here is parity-unpinned.
+Every function in them has at least one pin in ``tests/`` (see the module
+docstrings).  Nothing here is parity-unpinned.
 """

@@ -20,6 +20,7 @@ import scipy.sparse.linalg as spla
 _X = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 0.0]]))
 _Z = sp.csr_matrix(np.array([[1.0, 0.0], [0.0, -1.0]]))
 _Y_IM = sp.csr_matrix(np.array([[0.0, -1.0], [1.0, 0.0]]))  # sigma^y / i
+_Y = sp.csr_matrix(np.array([[0.0, -1.0j], [1.0j, 0.0]]))  # sigma^y (complex)
 
 
 def _site_op(op, i, n_spins):
@@ -53,6 +54,35 @@ def heisenberg_chain_hamiltonian(L):
     return H.tocsr()
 
 
+def xxz_chain_hamiltonian(L, J, Delta, hz=0.0):
+    """H = sum_i [J (Sx Sx + Sy Sy) + Delta Sz Sz + hz Sz_i], S = sigma / 2,
+    periodic chain (sparse, real: Sy Sy = -(sigma^y/i)(sigma^y/i)/4)."""
+    H = sp.csr_matrix((2 ** L, 2 ** L))
+    for i in range(L):
+        j = (i + 1) % L
+        H = H + 0.25 * J * (_site_op(_X, i, L) @ _site_op(_X, j, L))
+        H = H - 0.25 * J * (_site_op(_Y_IM, i, L) @ _site_op(_Y_IM, j, L))
+        H = H + 0.25 * Delta * (_site_op(_Z, i, L) @ _site_op(_Z, j, L))
+        H = H + 0.5 * hz * _site_op(_Z, i, L)
+    return H.tocsr()
+
+
+def dm_xxz_chain_hamiltonian(L, J, Dm, Delta, hz=0.0):
+    """H = sum_i [J (Sx Sx + Sy Sy) + Delta Sz Sz + Dm (Sx_i Sy_{i+1} -
+    Sy_i Sx_{i+1}) + hz Sz_i], S = sigma / 2, periodic chain, built spin by
+    spin with the complex sigma^y (sparse, complex Hermitian)."""
+    H = sp.csr_matrix((2 ** L, 2 ** L), dtype=np.complex128)
+    for i in range(L):
+        j = (i + 1) % L
+        xi, xj = _site_op(_X, i, L), _site_op(_X, j, L)
+        yi, yj = _site_op(_Y, i, L), _site_op(_Y, j, L)
+        H = H + 0.25 * J * (xi @ xj + yi @ yj)
+        H = H + 0.25 * Delta * (_site_op(_Z, i, L) @ _site_op(_Z, j, L))
+        H = H + 0.25 * Dm * (xi @ yj - yi @ xj)
+        H = H + 0.5 * hz * _site_op(_Z, i, L)
+    return H.tocsr()
+
+
 def torus_tfim_hamiltonian(Lx, Ly, h):
     """Eq. (H2D): sum_{m,n} (-X_{m,n} X_{m+1,n} - X_{m,n} X_{m,n+1} + h Z_{m,n}).
 
@@ -72,7 +102,8 @@ def torus_tfim_hamiltonian(Lx, Ly, h):
 
 
 def ground_energy(H):
-    """Lowest eigenvalue of a sparse symmetric matrix (scipy Lanczos)."""
+    """Lowest eigenvalue of a sparse symmetric (or complex Hermitian) matrix
+    (scipy Lanczos)."""
     if H.shape[0] <= 512:
         return float(np.linalg.eigvalsh(H.toarray())[0])
     vals = spla.eigsh(H, k=1, which="SA", tol=1e-14, return_eigenvectors=False)
@@ -191,3 +222,48 @@ def one_site_rdm(psi_sites, j):
     other = [i for i in range(psi_sites.ndim) if i != j]
     return np.tensordot(psi_sites, psi_sites, axes=(other, other))
 
+
+
+# --------------------------------------------------------------------------
+# complex states (one index per site): expectations with the bra conjugated
+# --------------------------------------------------------------------------
+def complex_chain_expectation(psi_sites, h, A, B):
+    """<psi| sum_j [h_j + sum_k A_{k,j} B_{k,j+1}] |psi> (periodic), complex
+    state, brute force; the real part (the operator is Hermitian)."""
+    k = psi_sites.ndim
+    total = 0.0 + 0.0j
+    for j in range(k):
+        phi = np.moveaxis(np.tensordot(h, psi_sites, axes=([1], [j])), 0, j)
+        total += np.vdot(psi_sites, phi)
+    for a_k, b_k in zip(A, B):
+        for j in range(k):
+            jn = (j + 1) % k
+            phi = np.moveaxis(np.tensordot(a_k, psi_sites, axes=([1], [j])), 0, j)
+            phi = np.moveaxis(np.tensordot(b_k, phi, axes=([1], [jn])), 0, jn)
+            total += np.vdot(psi_sites, phi)
+    return float(total.real)
+
+
+def complex_bond_expectations(psi_sites, A, B):
+    """sum_k <A_{k,j} B_{k,j+1}> for every j (periodic), complex state."""
+    k = psi_sites.ndim
+    out = np.zeros(k, dtype=np.complex128)
+    for a_k, b_k in zip(A, B):
+        for j in range(k):
+            jn = (j + 1) % k
+            phi = np.moveaxis(np.tensordot(a_k, psi_sites, axes=([1], [j])), 0, j)
+            phi = np.moveaxis(np.tensordot(b_k, phi, axes=([1], [jn])), 0, jn)
+            out[j] += np.vdot(psi_sites, phi)
+    return out
+
+
+def pairing_matrix_average(psi_sites):
+    """Position average of M_j[x, x'] = sum conj(psi[.. x ..]) psi[.. x' ..]
+    over the other sites: the transpose of site j's density matrix, which
+    pairs with an operator element by element, <O_j> = sum M_j * O."""
+    k = psi_sites.ndim
+    acc = 0.0
+    for j in range(k):
+        other = [i for i in range(k) if i != j]
+        acc = acc + np.tensordot(psi_sites.conj(), psi_sites, axes=(other, other))
+    return acc / k

@@ -10,9 +10,12 @@ the inputs a run starts from:
   effective site, spin-1/2 Heisenberg XXX chain);
 * seeded random isometries (Gaussian draw, reduced QR, sign-fixed) for a list
   of layer shapes;
-* the seeded draw of the batched workload (many independent chains).
+* the seeded draw of the batched workload (many independent chains);
+* a chain with complex product terms (the chiral XXZ chain) and seeded
+  complex isometries and top tensors for it.
 
-All matrices are real float64, row-major, ket index first.
+All matrices are row-major, ket index first; real float64 except those of
+the complex chain (complex128).
 """
 from __future__ import annotations
 
@@ -35,20 +38,21 @@ class ChainModel:
     symmetric operator.
     """
 
-    def __init__(self, name, h1, A, B, ly=1):
+    def __init__(self, name, h1, A, B, ly=1, dtype=np.float64):
         self.name = name
-        self.h1 = np.ascontiguousarray(h1, dtype=np.float64)
-        self.A = [np.ascontiguousarray(a, dtype=np.float64) for a in A]
-        self.B = [np.ascontiguousarray(b, dtype=np.float64) for b in B]
+        self.dtype = np.dtype(dtype)
+        self.h1 = np.ascontiguousarray(h1, dtype=self.dtype)
+        self.A = [np.ascontiguousarray(a, dtype=self.dtype) for a in A]
+        self.B = [np.ascontiguousarray(b, dtype=self.dtype) for b in B]
         self.d = self.h1.shape[0]
         self.D = len(self.A)
         self.ly = ly
 
     def packed(self):
-        """(h1, A[D,d,d], B[D,d,d]) as contiguous float64 arrays."""
+        """(h1, A[D,d,d], B[D,d,d]) as contiguous arrays of the model's dtype."""
         d, D = self.d, self.D
-        A = np.stack(self.A) if D else np.zeros((0, d, d))
-        B = np.stack(self.B) if D else np.zeros((0, d, d))
+        A = np.stack(self.A) if D else np.zeros((0, d, d), dtype=self.dtype)
+        B = np.stack(self.B) if D else np.zeros((0, d, d), dtype=self.dtype)
         return self.h1, np.ascontiguousarray(A), np.ascontiguousarray(B)
 
 
@@ -103,6 +107,46 @@ def xxx_chain() -> ChainModel:
     sz = 0.5 * PAULI_Z
     isy = 0.5 * PAULI_IY
     return ChainModel("xxx", np.zeros((2, 2)), [sx, isy, sz], [sx, -isy, sz], ly=1)
+
+
+def dm_chain(J: float = 1.0, Dm: float = 1.0, Delta: float = 1.0, hz: float = 0.0) -> ChainModel:
+    """Spin-1/2 XXZ chain with a Dzyaloshinskii-Moriya term along z (complex):
+    ``H = sum_i [J (Sx_i Sx_{i+1} + Sy_i Sy_{i+1}) + Delta Sz_i Sz_{i+1}
+    + Dm (Sx_i Sy_{i+1} - Sy_i Sx_{i+1}) + hz Sz_i]`` with S = sigma/2 and
+    the complex Sy.  Written with three product terms, each A_k and B_k
+    Hermitian: A = (Sx, Sy, Sz), B = (J Sx + Dm Sy, J Sy - Dm Sx, Delta Sz).
+    The DM term makes the Hamiltonian matrix complex (Sx Sy is imaginary)."""
+    sx = 0.5 * PAULI_X.astype(np.complex128)
+    sy = 0.5 * np.array([[0.0, -1.0j], [1.0j, 0.0]])
+    sz = 0.5 * PAULI_Z.astype(np.complex128)
+    return ChainModel(f"dm_xxz(J={J},Dm={Dm},Delta={Delta},hz={hz})", hz * sz, [sx, sy, sz],
+                      [J * sx + Dm * sy, J * sy - Dm * sx, Delta * sz], ly=1, dtype=np.complex128)
+
+
+def random_complex_isometries(shapes, seed: int):
+    """Seeded complex isometries for layer shapes [(a, b), ...]: for each layer
+    in order a complex Gaussian (b*b x a) matrix G = X + iY (X drawn before Y
+    from ``numpy.random.default_rng(seed)``), its reduced QR with the phases of
+    diag(R) folded into Q, and w[a; l, r] = Q[(l, r), a]; the rows of w are
+    orthonormal in the Hermitian sense, sum_{l,r} w[a; l, r] conj(w[a'; l, r])
+    = delta."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for a, b in shapes:
+        g = rng.standard_normal((b * b, a)) + 1j * rng.standard_normal((b * b, a))
+        q, r = np.linalg.qr(g)
+        dg = np.diag(r)
+        ph = np.where(np.abs(dg) > 0, dg / np.maximum(np.abs(dg), 1e-300), 1.0)
+        q = q * ph[None, :]
+        out.append(np.ascontiguousarray(q.T.reshape(a, b, b)))
+    return out
+
+
+def random_complex_top(chi: int, seed: int):
+    """Seeded random complex top tensor of unit norm (real part drawn first)."""
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal((chi, chi)) + 1j * rng.standard_normal((chi, chi))
+    return v / np.linalg.norm(v)
 
 
 def random_isometries(shapes, seed: int):
