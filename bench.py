@@ -201,6 +201,10 @@ def parse():
                    help="position-resolved networks only (every node its own isometry), one JSON line")
     p.add_argument("--pos-configs", default="xxx1024_chi64,xxx4096_chi128",
                    help="--positional: workloads, comma separated, from " + ", ".join(POS_CONFIGS))
+    p.add_argument("--complex", action="store_true",
+                   help="complex tensors only (a chain with complex matrix elements), one JSON line")
+    p.add_argument("--cplx-configs", default="dm1024_chi64,dm4096_chi128",
+                   help="--complex: workloads, comma separated, from " + ", ".join(CPLX_CONFIGS))
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB elementwise copy (y = -x), the reference of the traffic counters")
     return p.parse_args()
@@ -359,6 +363,94 @@ def positional(B, I, args):
         "metric": "position-resolved TTN sweeps/s (every node its own isometry)", "value": first["sweeps_per_s"],
         "unit": "sweeps/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
         "config": {"workload": first["workload"]}, "runs": out,
+    }))
+
+
+# complex tensors: the chiral XXZ chain (a Dzyaloshinskii-Moriya term makes
+# its matrix elements complex), float64 complex arithmetic
+CPLX_CONFIGS = {
+    "dm1024_chi64": (1024, 64, "chiral XXZ chain (J=1, Dm=0.5, Delta=1) L=1024 chi=64, complex tensors"),
+    "dm4096_chi128": (4096, 128, "chiral XXZ chain (J=1, Dm=0.5, Delta=1) L=4096 chi=128, complex tensors"),
+    "dm4096_chi256": (4096, 256, "chiral XXZ chain (J=1, Dm=0.5, Delta=1) L=4096 chi=256, complex tensors"),
+}
+CPLX_ORACLE_SAMPLE = (1024, 32)  # whole oracle sweeps at this size (a bounded CPU sample)
+
+
+def measure_complex(B, I, name, steps, warmup, seed):
+    """Sweeps of a uniform network with complex tensors (ttn_cplx_*): each
+    complex product is four real float64 products on the MFMA kernels; warm-up
+    sweeps, K timed sweeps, one profiled sweep with HIP events around every
+    product kernel."""
+    import torch
+    L, chi, desc = CPLX_CONFIGS[name]
+    model = I.dm_chain(1.0, 0.5, 1.0, 0.0)
+    ws = I.random_complex_isometries(I.layer_shapes(L, model.d, chi), seed)
+    g = B.CplxTTN(model, L, chi, ws)
+    del ws
+    hist = [g.energy()[1]]
+    for _ in range(max(1, warmup)):
+        g.sweep(1)
+        hist.append(g.energy()[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.sweep(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hist.append(g.energy()[1])
+    st = g.stats()
+    progress(f"complex {name}: {1e3 * el / steps:.2f} ms per sweep")
+    g.profile(True)
+    g.sweep(1)
+    prof = g.profile_read()
+    g.profile(False)
+    hist.append(g.energy()[1])
+    roofline = kernel_roofline(prof, f"{desc} fp64")
+    kernels = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"], 3)}
+               for k, v in prof.items() if "kernel" in k}
+    classes = {k: {"launches": v["launches"], "ms_per_sweep": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / (v["ms"] / 1e3) / 1e12, 3) if v["ms"] > 0 and v["flops"] else None}
+               for k, v in prof.items() if "kernel" not in k}
+    g.close()
+    torch.cuda.empty_cache()
+    return {
+        "workload": desc, "L": L, "chi": chi, "precision": "complex128",
+        "sweeps_per_s": round(steps / el, 4), "ms_per_sweep": round(1e3 * el / steps, 3),
+        "flops_per_sweep": st.flops_sweep, "product_bytes_per_sweep": st.bytes_sweep,
+        "contraction_tflops": round(st.flops_sweep / (el / steps) / 1e12, 3),
+        "energy_per_site_by_sweep": hist, "energy_never_rises": all(b <= a + 1e-12 for a, b in zip(hist, hist[1:])),
+        "ortho_err_max": st.ortho_err_max, "repaired_updates": st.repairs, "sigma_ratio_min": st.sigma_ratio_min,
+        "roofline": roofline, "classes": classes, "kernels": kernels,
+    }
+
+
+def complex_oracle_baseline(I, seed):
+    """The complex oracle as it stands, whole sweeps on the host at a bounded
+    size (CPLX_ORACLE_SAMPLE), after one untimed initialisation."""
+    from oracle import ttn_complex as C
+    L, chi = CPLX_ORACLE_SAMPLE
+    model = I.dm_chain(1.0, 0.5, 1.0, 0.0)
+    ref = C.ComplexTTNRef(L, chi, model.h1, model.A, model.B,
+                          I.random_complex_isometries(I.layer_shapes(L, model.d, chi), seed))
+    ref.initialise()
+    t0 = time.perf_counter()
+    ref.sweep()
+    el = time.perf_counter() - t0
+    return {"value": round(1.0 / el, 5), "unit": "sweeps/s", "cores": oracle_threads(), "kind": "oracle",
+            "sample": f"one whole sweep of the complex oracle, chiral XXZ chain L={L} chi={chi} (dense top "
+                      f"eigensolver), {el:.1f} s"}
+
+
+def complex_leg(B, I, args):
+    out = {}
+    for name in args.cplx_configs.split(","):
+        out[name] = measure_complex(B, I, name, args.steps, args.warmup, args.seed)
+    first = out[next(iter(out))]
+    progress("complex: oracle sample")
+    print(json.dumps({
+        "metric": "complex-tensor TTN sweeps/s", "value": first["sweeps_per_s"], "unit": "sweeps/s",
+        "higher_is_better": True, "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+        "config": {"workload": first["workload"]}, "runs": out, "cpu_baseline": complex_oracle_baseline(I, args.seed),
     }))
 
 
@@ -995,6 +1087,11 @@ def main():
         progress("device ready")
         B.autotune(0 if args.no_autotune else 1)
         positional(B, I, args)
+        return
+    if args.complex:
+        progress("device ready")
+        B.autotune(0 if args.no_autotune else 1)
+        complex_leg(B, I, args)
         return
     if args.positions:
         progress("device ready")

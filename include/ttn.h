@@ -488,6 +488,115 @@ ttn_status ttn_pos_profile_read(ttn_pos_handle h, ttn_profile_entry* out, int ma
 ttn_status ttn_pos_set(ttn_pos_handle h, int what, int level, const double* host);
 ttn_status ttn_pos_free(ttn_pos_handle h);
 
+/* ------------------------------------------------------------------------
+ * Complex tensors: Hamiltonians with complex matrix elements (the paper's
+ * method for real tensors, Secs. II.C and III, with every transpose a
+ * conjugate transpose).  A uniform network (one isometry per layer, as
+ * ttn_init), float64 complex arithmetic throughout.  Conventions: a level
+ * tau basis state is |a> = sum_{l,r} w[a; l, r] |l>|r> with rows of w
+ * orthonormal in the Hermitian sense; operators ascend as
+ * O'[a, a'] = sum conj(w[a; x]) (O w)[a'; x]; the state is
+ * sum v[al, be] |al>|be>; the descended matrices pair with operators element
+ * by element, rho[a, a'] = <conj(c_a) c_a'> (the transpose of the usual
+ * density matrix).  A sweep (Sec. IV): layers bottom-up, each updated to
+ * w = -U V^H for its environment Env = U S V^H (Sec. III.B), then v as the
+ * lowest eigenvector of the Hermitian top Hamiltonian (Lanczos on its real
+ * embedding; its global phase is not fixed).
+ *
+ * Complex arrays cross this boundary interleaved: (re, im) pairs of
+ * doubles, row-major, the layout of C99 double complex and of numpy's
+ * complex128.
+ * ------------------------------------------------------------------------ */
+typedef struct ttn_cplx_ctx* ttn_cplx_handle;
+
+typedef struct ttn_cplx_config {
+  int L, d, chi, D;   /* as ttn_config                                         */
+  const double* h1;   /* host d*d complex (interleaved), Hermitian             */
+  const double* A;    /* host D*d*d complex; B likewise.  The two-site term
+                         1/2 (h1 x I + I x h1) + sum_k A_k x B_k must be
+                         Hermitian                                            */
+  const double* B;
+  double shift;       /* NaN: the largest eigenvalue of the bond term          */
+  int ly;             /* spins per effective site                             */
+  unsigned long long seed; /* start vector of the first top solve when v0 is
+                         NULL (counter-based Gaussian real and imaginary
+                         parts)                                               */
+  const double* const* w0; /* required host array of n-1 pointers: w0[tau-1]
+                         is layer tau's chi_tau x chi_{tau-1} x chi_{tau-1}
+                         complex isometry                                     */
+  const double* v0;   /* optional host chi_{n-1}^2 complex start vector       */
+  int krylov, restarts;  /* as in ttn_config, 0: 24, 8                         */
+  double lanczos_tol;    /* as in ttn_config, 0: 1e-12                         */
+} ttn_cplx_config;
+
+/* Workspace: two planes (real, imaginary) of the network's complex arrays
+ * (isometries, operators and descended matrices of every level, a
+ * contraction's intermediates, about (3 + 3D) times the largest isometry),
+ * and the polar update's buffers for the real embedding of an environment
+ * (five times four times the largest isometry).  Errors as
+ * ttn_workspace_bytes; TTN_EINVAL when w0 or one of its layers is NULL, when
+ * h1 or the bond term is not Hermitian. */
+ttn_status ttn_cplx_workspace_bytes(const ttn_cplx_config* cfg, size_t* bytes);
+/* Copies the inputs, ascends the operators and solves the top problem.
+ * Errors as ttn_init; TTN_WNOCONV when the first top solve ended above its
+ * target. */
+ttn_status ttn_cplx_init(const ttn_cplx_config* cfg, void* workspace, size_t bytes, void* stream,
+                         ttn_cplx_handle* out);
+/* nsweeps sweeps (above).  TTN_EHIP / TTN_ENOCONV when a polar Jacobi solve
+ * aborted / used its sweep limit; TTN_WNOCONV from the top solver. */
+ttn_status ttn_cplx_sweep(ttn_cplx_handle h, int nsweeps);
+/* e[0] = top eigenvalue lambda, e[1] = energy per spin of the current state. */
+ttn_status ttn_cplx_energy(ttn_cplx_handle h, double* e);
+/* rho of every level from 1 up from the current tensors (read back with
+ * ttn_cplx_get(TTN_CPLX_RHO)).  Synchronises the stream. */
+ttn_status ttn_cplx_descend(ttn_cplx_handle h);
+/* The environment of layer tau (1 <= tau < n) from the current tensors
+ * (Sec. III.A: rho of level tau and the two-site matrices Rbar, Lbar of the
+ * product terms carried up from level tau - 1 through the current layers
+ * and down again), into host (chi_tau x chi_{tau-1}^2 complex); the
+ * two-site matrices stay readable (TTN_CPLX_RBAR, TTN_CPLX_LBAR).  The state
+ * is not changed.  Synchronises the stream. */
+ttn_status ttn_cplx_env(ttn_cplx_handle h, int tau, double* host);
+/* Copies a complex block to the host (interleaved):
+ *   TTN_CPLX_W    (level >= 1) the isometry of layer tau;
+ *   TTN_CPLX_OPS  [h, A_1..A_D, B_1..B_D] of a level (chi^2 each; level 0:
+ *                 h1 - c I, A, B);
+ *   TTN_CPLX_RHO  rho of a level >= 1 as of the last ttn_cplx_descend or
+ *                 sweep;
+ *   TTN_CPLX_RBAR, TTN_CPLX_LBAR  [Rbar_1..Rbar_D] (Lbar) of the last
+ *                 ttn_cplx_env's level (level ignored);
+ *   TTN_CPLX_TOP  the top tensor (level ignored). */
+enum { TTN_CPLX_W = 0, TTN_CPLX_OPS = 1, TTN_CPLX_RHO = 2, TTN_CPLX_RBAR = 3, TTN_CPLX_LBAR = 4,
+       TTN_CPLX_TOP = 5 };
+ttn_status ttn_cplx_get(ttn_cplx_handle h, int what, int level, double* host);
+/* Replaces a block from the host: TTN_CPLX_W (level >= 1), after which
+ * every level from it up is ascended again; TTN_CPLX_TOP, not solved again.
+ * TTN_EINVAL for another kind or a level outside [1, n). */
+ttn_status ttn_cplx_set(ttn_cplx_handle h, int what, int level, const double* host);
+/* Counters of the last sweep and top solve. */
+typedef struct ttn_cplx_stats_t {
+  double energy, lam;     /* as ttn_cplx_energy                                 */
+  double flops_sweep;     /* real flops of the last sweep's products (a complex
+                             product is four real ones of its shape)            */
+  double bytes_sweep;     /* their bytes (each operand read once, each result
+                             written once)                                      */
+  double lanczos_resid;   /* ||H v - lambda v|| after the last top solve          */
+  double ortho_err_max;   /* largest ||W W^H - I||_F of an update since init      */
+  double sigma_ratio_min; /* smallest s_min / s_max of an environment since init  */
+  int n_levels;
+  int top_converged;      /* 1 when the last top solve met its target            */
+  long long repairs;      /* layer updates since init whose environment was
+                             numerically rank deficient enough that the polar
+                             factor of its real embedding, read as a complex
+                             matrix, was not an isometry (off by more than
+                             1e-10), and was replaced by its own polar factor   */
+} ttn_cplx_stats_t;
+ttn_status ttn_cplx_stats(ttn_cplx_handle h, ttn_cplx_stats_t* out);
+/* Event timing of the handle's launches, as ttn_profile / ttn_profile_read. */
+ttn_status ttn_cplx_profile(ttn_cplx_handle h, int enable);
+ttn_status ttn_cplx_profile_read(ttn_cplx_handle h, ttn_profile_entry* out, int max_entries, int* n_out);
+ttn_status ttn_cplx_free(ttn_cplx_handle h);
+
 /* Bond dimension chi_tau of member b (tau in 0..n-1), or -1. */
 int ttn_bond_dim(ttn_handle h, int b, int tau);
 

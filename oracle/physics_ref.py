@@ -128,6 +128,24 @@ def tfim_critical_energy(L):
     return -2.0 / math.sin(math.pi / (2 * L))
 
 
+def xx_chain_free_fermion_energy(L, J=1.0):
+    """Ground energy of the periodic XX chain J sum (Sx Sx + Sy Sy), S = sigma/2.
+
+    Jordan-Wigner: (J/2) sum_j (c_j^+ c_{j+1} + h.c.) with one-particle
+    energies J cos k; with N particles the boundary bond is periodic for odd N
+    (k = 2 pi m / L) and antiperiodic for even N (k = 2 pi (m + 1/2) / L).
+    The ground energy is the least over N of the N lowest energies' sum
+    (Lieb, Schultz and Mattis, Ann. Phys. 16, 407 (1961))."""
+    m = np.arange(L)
+    per = np.sort(J * np.cos(2 * np.pi * m / L))
+    anti = np.sort(J * np.cos(2 * np.pi * (m + 0.5) / L))
+    best = 0.0
+    for N in range(1, L + 1):
+        e = (per if N % 2 == 1 else anti)[:N].sum()
+        best = min(best, float(e))
+    return best
+
+
 BETHE_XXX_ENERGY_DENSITY = 0.25 - math.log(2.0)  # Hulthen: 1/4 - ln 2
 
 

@@ -33,8 +33,12 @@ EXPORTS = [
     "ttn_autotune_save", "ttn_autotune_load", "ttn_local_energies_noalloc",
     "ttn_pos_workspace_bytes", "ttn_pos_init", "ttn_pos_sweep", "ttn_pos_energy", "ttn_pos_descend", "ttn_pos_env",
     "ttn_pos_get", "ttn_pos_set", "ttn_pos_free", "ttn_pos_stats", "ttn_pos_profile", "ttn_pos_profile_read",
+    "ttn_cplx_workspace_bytes", "ttn_cplx_init", "ttn_cplx_sweep", "ttn_cplx_energy", "ttn_cplx_descend",
+    "ttn_cplx_env", "ttn_cplx_get", "ttn_cplx_set", "ttn_cplx_stats", "ttn_cplx_profile", "ttn_cplx_profile_read",
+    "ttn_cplx_free",
 ]
 TTN_POS_W, TTN_POS_OPS, TTN_POS_DX, TTN_POS_TOP = range(4)
+TTN_CPLX_W, TTN_CPLX_OPS, TTN_CPLX_RHO, TTN_CPLX_RBAR, TTN_CPLX_LBAR, TTN_CPLX_TOP = range(6)
 
 
 class TTNConfig(ctypes.Structure):
@@ -75,6 +79,26 @@ class TTNPosStats(ctypes.Structure):
         ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("flops_sweep", ctypes.c_double),
         ("bytes_sweep", ctypes.c_double), ("lanczos_resid", ctypes.c_double), ("n_levels", ctypes.c_int),
         ("top_converged", ctypes.c_int),
+    ]
+
+
+class TTNCplxConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int), ("d", ctypes.c_int), ("chi", ctypes.c_int), ("D", ctypes.c_int),
+        ("h1", ctypes.POINTER(ctypes.c_double)), ("A", ctypes.POINTER(ctypes.c_double)),
+        ("B", ctypes.POINTER(ctypes.c_double)), ("shift", ctypes.c_double), ("ly", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong), ("w0", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+        ("v0", ctypes.POINTER(ctypes.c_double)), ("krylov", ctypes.c_int), ("restarts", ctypes.c_int),
+        ("lanczos_tol", ctypes.c_double),
+    ]
+
+
+class TTNCplxStats(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double), ("lam", ctypes.c_double), ("flops_sweep", ctypes.c_double),
+        ("bytes_sweep", ctypes.c_double), ("lanczos_resid", ctypes.c_double), ("ortho_err_max", ctypes.c_double),
+        ("sigma_ratio_min", ctypes.c_double), ("n_levels", ctypes.c_int), ("top_converged", ctypes.c_int),
+        ("repairs", ctypes.c_longlong),
     ]
 
 
@@ -137,6 +161,18 @@ def load_library(path: str = LIB_PATH):
         "ttn_pos_stats": ([P, ctypes.POINTER(TTNPosStats)], I),
         "ttn_pos_profile": ([P, I], I),
         "ttn_pos_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
+        "ttn_cplx_workspace_bytes": ([ctypes.POINTER(TTNCplxConfig), ctypes.POINTER(ctypes.c_size_t)], I),
+        "ttn_cplx_init": ([ctypes.POINTER(TTNCplxConfig), P, ctypes.c_size_t, P, ctypes.POINTER(P)], I),
+        "ttn_cplx_sweep": ([P, I], I),
+        "ttn_cplx_energy": ([P, DP], I),
+        "ttn_cplx_descend": ([P], I),
+        "ttn_cplx_env": ([P, I, DP], I),
+        "ttn_cplx_get": ([P, I, I, DP], I),
+        "ttn_cplx_set": ([P, I, I, DP], I),
+        "ttn_cplx_stats": ([P, ctypes.POINTER(TTNCplxStats)], I),
+        "ttn_cplx_profile": ([P, I], I),
+        "ttn_cplx_profile_read": ([P, ctypes.POINTER(TTNProfileEntry), I, ctypes.POINTER(I)], I),
+        "ttn_cplx_free": ([P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -531,3 +567,130 @@ class PosTTN:
             self.close()
         except Exception:
             pass
+
+
+def _cptr(a: np.ndarray):
+    """Pointer to a contiguous complex128 array as interleaved doubles."""
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class CplxTTN:
+    """Handle of a uniform network with complex tensors (include/ttn.h,
+    ttn_cplx_*).  model: a ChainModel (complex or real matrices, passed as
+    complex128); w0: one complex array per layer tau = 1..n-1 of shape
+    (chi_tau, chi_{tau-1}, chi_{tau-1}); v0 optional."""
+
+    def __init__(self, model, L, chi, w0, v0=None, shift=None, seed=0, krylov=0, restarts=0, lanczos_tol=0.0,
+                 device="cuda", stream=None):
+        import torch
+        lib = load_library()
+        h1, A, B = model.packed()
+        self.h1 = np.ascontiguousarray(h1, dtype=np.complex128)
+        self.A = np.ascontiguousarray(A, dtype=np.complex128)
+        self.B = np.ascontiguousarray(B, dtype=np.complex128)
+        self.L, self.chi, self.d, self.D = int(L), int(chi), int(model.d), int(model.D)
+        self.dims = bond_dims(L, model.d, chi)
+        self.n = len(self.dims)
+        self.w0 = [np.ascontiguousarray(w, dtype=np.complex128) for w in w0]
+        self.v0 = None if v0 is None else np.ascontiguousarray(v0, dtype=np.complex128)
+        cfg = TTNCplxConfig()
+        cfg.L, cfg.d, cfg.chi, cfg.D = self.L, self.d, self.chi, self.D
+        cfg.h1 = _cptr(self.h1)
+        cfg.A = _cptr(self.A) if self.D else None
+        cfg.B = _cptr(self.B) if self.D else None
+        cfg.shift = math.nan if shift is None else float(shift)
+        cfg.ly = int(model.ly)
+        cfg.seed = int(seed)
+        self._wptrs = (ctypes.POINTER(ctypes.c_double) * max(1, len(self.w0)))(*[_cptr(w) for w in self.w0])
+        cfg.w0 = ctypes.cast(self._wptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
+        cfg.v0 = _cptr(self.v0) if self.v0 is not None else None
+        cfg.krylov, cfg.restarts, cfg.lanczos_tol = int(krylov), int(restarts), float(lanczos_tol)
+        self.cfg = cfg
+        need = ctypes.c_size_t(0)
+        _check(lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(need)))
+        self.workspace = torch.empty(need.value + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device=self.workspace.device)
+        h = ctypes.c_void_p(0)
+        self.init_status = _check(lib.ttn_cplx_init(ctypes.byref(cfg), ctypes.c_void_p(aligned), need.value,
+                                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+
+    def sweep(self, nsweeps=1):
+        return _check(self.lib.ttn_cplx_sweep(self.h, int(nsweeps)))
+
+    def energy(self):
+        """(lambda, energy per spin); the call's status in self.energy_status."""
+        out = np.zeros(2)
+        self.energy_status = _check(self.lib.ttn_cplx_energy(self.h, _dptr(out)))
+        return float(out[0]), float(out[1])
+
+    def descend(self):
+        return _check(self.lib.ttn_cplx_descend(self.h))
+
+    def env(self, tau):
+        a, b = self.dims[tau], self.dims[tau - 1]
+        out = np.zeros((a, b, b), dtype=np.complex128)
+        _check(self.lib.ttn_cplx_env(self.h, int(tau), _cptr(out)))
+        return out
+
+    def _get(self, what, level, shape):
+        out = np.zeros(shape, dtype=np.complex128)
+        _check(self.lib.ttn_cplx_get(self.h, what, int(level), _cptr(out)))
+        return out
+
+    def isometry(self, tau):
+        a, b = self.dims[tau], self.dims[tau - 1]
+        return self._get(TTN_CPLX_W, tau, (a, b, b))
+
+    def operators(self, level):
+        """(h, A, B) of a level: h (x, x), A and B (D, x, x)."""
+        x = self.dims[level]
+        out = self._get(TTN_CPLX_OPS, level, (1 + 2 * self.D, x, x))
+        return out[0], out[1:1 + self.D], out[1 + self.D:]
+
+    def rho(self, level):
+        x = self.dims[level]
+        return self._get(TTN_CPLX_RHO, level, (x, x))
+
+    def dressed(self, tau):
+        """(Rbar, Lbar) of the last env() call's level tau, (D, x, x) each."""
+        x = self.dims[tau]
+        return (self._get(TTN_CPLX_RBAR, 0, (self.D, x, x)), self._get(TTN_CPLX_LBAR, 0, (self.D, x, x)))
+
+    def top(self):
+        x = self.dims[-1]
+        return self._get(TTN_CPLX_TOP, 0, (x, x))
+
+    def set_top(self, v):
+        v = np.ascontiguousarray(v, dtype=np.complex128)
+        _check(self.lib.ttn_cplx_set(self.h, TTN_CPLX_TOP, 0, _cptr(v)))
+
+    def set_isometry(self, tau, w):
+        w = np.ascontiguousarray(w, dtype=np.complex128)
+        a, b = self.dims[tau], self.dims[tau - 1]
+        if w.shape != (a, b, b):
+            raise ValueError(f"layer {tau}: shape {w.shape}")
+        _check(self.lib.ttn_cplx_set(self.h, TTN_CPLX_W, int(tau), _cptr(w)))
+
+    def stats(self):
+        st = TTNCplxStats()
+        _check(self.lib.ttn_cplx_stats(self.h, ctypes.byref(st)))
+        return st
+
+    def profile(self, enable=True):
+        return _check(self.lib.ttn_cplx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        arr = (TTNProfileEntry * 64)()
+        n = ctypes.c_int(0)
+        _check(self.lib.ttn_cplx_profile_read(self.h, arr, 64, ctypes.byref(n)), allow_warn=False)
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].ms, flops=arr[i].flops,
+                                           bytes=arr[i].bytes) for i in range(n.value)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ttn_cplx_free(self.h)
+            self.h = None

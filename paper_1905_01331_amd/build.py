@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libttn.so")
 
 SOURCES = ["gemm_plain.hip", "gemm_mfma.hip", "gemm_tune.cpp", "small.hip", "jacobi_block.hip", "lanczos.hip",
-           "ttn_api.cpp", "ttn_positional.cpp", "noalloc.hip"]
+           "ttn_api.cpp", "ttn_positional.cpp", "ttn_complex.cpp", "complex.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

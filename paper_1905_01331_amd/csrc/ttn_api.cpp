@@ -416,7 +416,34 @@ void layout_member(Member& M, Arena& ar) {
 // ---------------------------------------------------------------------------
 // contraction helpers (element strides; bulk arithmetic of the member)
 // ---------------------------------------------------------------------------
+CplxCtx& cplx() {
+  static thread_local CplxCtx c;
+  return c;
+}
+
+hipError_t run_real(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls);
+
 hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls) {
+  const CplxCtx cx = cplx();
+  if (cx.delta == 0) return run_real(M, p, g, s, cls);
+  // complex: four real products over the planes (no symmetric shortcut: the
+  // real and imaginary parts of a Hermitian result are not each symmetric)
+  const double sa = cx.conj_a ? -1.0 : 1.0;
+  auto im = [&](const void* q) { return (const void*)((const char*)q + cx.delta); };
+  GemmDesc q = g;
+  q.tri = 0;
+  q.anti = 0;
+  hipError_t e;
+  if ((e = run_real(M, p, q, s, cls))) return e;  // Re C = alpha Re A Re B + beta Re C
+  q.A = im(g.A); q.B = im(g.B); q.alpha = -sa * g.alpha; q.beta = 1.0;
+  if ((e = run_real(M, p, q, s, cls))) return e;  //      - alpha (+-Im A) Im B
+  q.A = g.A; q.B = im(g.B); q.C = (void*)im(g.C); q.alpha = g.alpha; q.beta = g.beta;
+  if ((e = run_real(M, p, q, s, cls))) return e;  // Im C = alpha Re A Im B + beta Im C
+  q.A = im(g.A); q.B = g.B; q.alpha = sa * g.alpha; q.beta = 1.0;
+  return run_real(M, p, q, s, cls);               //      + alpha (+-Im A) Re B
+}
+
+hipError_t run_real(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls) {
   size_t slot = 0;
   bool timed = false;
   GemmDesc gg = g;
@@ -441,6 +468,14 @@ hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cl
   hipError_t e = gemm(p, gg, M.splitk, M.splitk_bytes, s);
   if (timed) M.prof->end(slot, s);
   return e;
+}
+
+// a copy of an array, and of its imaginary plane inside a CplxScope
+hipError_t copy_planes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  hipError_t e = copy_bytes(dst, src, bytes, s);
+  const long long d = cplx().delta;
+  if (e || d == 0) return e;
+  return copy_bytes((char*)dst + d, (const char*)src + d, bytes, s);
 }
 
 GemmDesc desc0() {
@@ -486,11 +521,13 @@ hipError_t apply_l_k(const Member& M, Prec p, const void* O, long long sO, const
 // C(P,Q)[a,a'] = sum_{l,r} P[a;l,r] Q[a';l,r]   (a x a, K = b*b).  Every
 // use has Q = O w with P = w and O symmetric, or antisymmetric for the terms
 // whose bit is set in anti, so C is symmetric (antisymmetric) and a float64
-// launch computes its upper triangle only.
+// launch computes its upper triangle only.  In the three closes P is the bra
+// copy of a contraction (conjugated when the products are complex).
 hipError_t close_aa_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
                       long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
                       unsigned long long anti) {
   if (nk < 1) return hipSuccess;
+  BraScope bra;
   GemmDesc g = desc0();
   g.tri = 1;
   g.anti = anti;
@@ -521,6 +558,7 @@ hipError_t left_mul_k(const Member& M, Prec p, const void* X, long long sX, cons
 hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
   if (nk < 1) return hipSuccess;
+  BraScope bra;
   GemmDesc g = desc0();
   g.batch = nk;
   g.M = b; g.N = b; g.K = a * b; g.K2 = 0;
@@ -534,6 +572,7 @@ hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const
 hipError_t close_l_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
                      long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
   if (nk < 1) return hipSuccess;
+  BraScope bra;
   GemmDesc g = desc0();
   long long bb = (long long)b * b;
   g.batch = nk;
@@ -751,9 +790,12 @@ ttn_status stage_ascend(Member& M, int tau, hipStream_t s) {
 ttn_status stage_descend_rho(Member& M, hipStream_t s) {
   Prec p = M.gp();
   const int n = M.n, x = M.dims[n - 1];
-  // rho^(n-1) = 1/2 (v v^T + v^T v)
-  HIPCHK(mm(M, p, M.vT, false, M.vT, true, M.rho[n - 1], x, 0.5, 0.0, s));
-  HIPCHK(mm(M, p, M.vT, true, M.vT, false, M.rho[n - 1], x, 0.5, 1.0, s));
+  // rho^(n-1) = 1/2 (v v^T + v^T v) (the first factor is the bra copy)
+  {
+    BraScope bra;
+    HIPCHK(mm(M, p, M.vT, false, M.vT, true, M.rho[n - 1], x, 0.5, 0.0, s));
+    HIPCHK(mm(M, p, M.vT, true, M.vT, false, M.rho[n - 1], x, 0.5, 1.0, s));
+  }
   for (int lv = n - 1; lv >= 2; --lv) {
     const int a = M.dims[lv], b = M.dims[lv - 1];
     HIPCHK(left_mul(M, p, M.rho[lv], M.wT[lv], M.Pc[lv], a, b, 1.0, 0.0, s));
@@ -775,14 +817,27 @@ ttn_status dressed_top(Member& M, const void* At, const void* Bt, hipStream_t s)
   const long long xx = (long long)x * x;
   void* R = M.Rb[0];
   void* Lq = M.Lb[0];
+  // the left factor v (v^T) of each second product is the bra copy
   HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // A v
-  HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, R, xx, x, 0.5, 0.0, D, s));    // v^T A v
+  {
+    BraScope bra;
+    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, R, xx, x, 0.5, 0.0, D, s));  // v^T A v
+  }
   HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // A v^T
-  HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, R, xx, x, 0.5, 1.0, D, s));   // v A v^T
+  {
+    BraScope bra;
+    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, R, xx, x, 0.5, 1.0, D, s));  // v A v^T
+  }
   HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, true, M.tmpT, xx, x, 1.0, 0.0, D, s));   // B v^T
-  HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, Lq, xx, x, 0.5, 0.0, D, s));  // v B v^T
+  {
+    BraScope bra;
+    HIPCHK(mm_k(M, p, M.vT, 0, false, M.tmpT, xx, false, Lq, xx, x, 0.5, 0.0, D, s));  // v B v^T
+  }
   HIPCHK(mm_k(M, p, Bt, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // B v
-  HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));   // v^T B v
+  {
+    BraScope bra;
+    HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));  // v^T B v
+  }
   M.rb_cur = 0;
   return TTN_OK;
 }
@@ -851,10 +906,10 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
   HIPCHK(s_apply(M, tau - 1, w, a, b, s));                                        // slice 0
   HIPCHK(apply_l_k(M, p, M.opB[tau - 1], bb, w, 0, M.at(M.Estage, cube), cube, a, b, 0.0, D, s));
   HIPCHK(apply_r_k(M, p, M.opA[tau - 1], bb, w, 0, M.at(M.Estage, (1 + D) * cube), cube, a, b, 0.0, D, s));
-  HIPCHK(copy_bytes(M.Xst, M.rho[tau], M.el(aa), s));
+  HIPCHK(copy_planes(M.Xst, M.rho[tau], M.el(aa), s));
   if (D > 0) {
-    HIPCHK(copy_bytes(M.at(M.Xst, aa), M.Rb[M.rb_cur], M.el(D * aa), s));
-    HIPCHK(copy_bytes(M.at(M.Xst, (1 + D) * aa), M.Lb[M.rb_cur], M.el(D * aa), s));
+    HIPCHK(copy_planes(M.at(M.Xst, aa), M.Rb[M.rb_cur], M.el(D * aa), s));
+    HIPCHK(copy_planes(M.at(M.Xst, (1 + D) * aa), M.Lb[M.rb_cur], M.el(D * aa), s));
   }
   GemmDesc g = desc0();
   g.M = a; g.N = (int)bb; g.K = (1 + 2 * D) * a; g.K2 = a;
@@ -1109,6 +1164,7 @@ ttn_status stage_update_layer(Member& M, int tau, hipStream_t s) {
 // of y (B_k^T, A_k^T, h^T) are the right site's.
 // (staged: y is already in stage[0])
 hipError_t top_matvec(Member& M, const double* y, double* out, hipStream_t s, bool staged) {
+  if (M.matvec) return M.matvec(M, y, out, s);
   const int x = M.dims[M.n - 1], D = M.D;
   const long long xx = (long long)x * x;
   const double* hR = M.hopR64 ? M.hopR64 : M.hop64;
@@ -1185,7 +1241,7 @@ ttn_status top_prepare(Member& M, hipStream_t s) {
 
 ttn_status top_restarts(Member& M, hipStream_t s, int count, bool sync, bool* converged) {
   const int n = M.n, x = M.dims[n - 1];
-  const size_t xx = (size_t)x * x;
+  const size_t xx = M.top_len ? (size_t)M.top_len : (size_t)x * x;
   const int m = (int)std::min<long long>(M.krylov, (long long)xx);
   *converged = false;
   // members of a launch group share the restart loop; a member whose
@@ -1214,7 +1270,8 @@ ttn_status top_restarts(Member& M, hipStream_t s, int count, bool sync, bool* co
       double* c2 = M.coef + (m + 2);
       HIPCHK(lz_reorth_first(M.lzW, M.lzQ, j + 1, xx, c1, M.lzpart, s));
       HIPCHK(lz_reorth_final(M.lzW, M.lzQ, j + 1, xx, c1, c2, M.lzpart, M.lznrm, M.alpha, M.beta, 1e-14, M.lzint,
-                             M.lzint + 1, M.lzQ + (size_t)(j + 1) * xx, j + 1 < m ? M.lzStage : nullptr, s));
+                             M.lzint + 1, M.lzQ + (size_t)(j + 1) * xx, j + 1 < m && !M.matvec ? M.lzStage : nullptr,
+                             s));
     }
     HIPCHK(lz_build_T(M.alpha, M.beta, m, M.lzint, M.lzint + 1, M.Tm, s));
     HIPCHK(jacobi_eig_f64(M.Tm, M.Vm, m, 80, std::max(1e-15, 2.2e-16 * m), M.jinfo + 16, M.jscratch, s, skip));
@@ -1262,7 +1319,7 @@ ttn_status top_restarts(Member& M, hipStream_t s, int count, bool sync, bool* co
 // continued after a first finish), so the stored previous energy stays
 ttn_status top_finish(Member& M, hipStream_t s, bool keep_prev) {
   const int x = M.dims[M.n - 1];
-  const size_t xx = (size_t)x * x;
+  const size_t xx = M.top_len ? (size_t)M.top_len : (size_t)x * x;
   HIPCHK(sign_fix(M.vtop, xx, s));
   HIPCHK(energy_store(M.scal + SCAL_LAM, M.scal + SCAL_SHIFT, (double)M.L, (double)M.ly, M.scal + SCAL_LAM,
                       keep_prev ? nullptr : M.scal + SCAL_EPREV, s));

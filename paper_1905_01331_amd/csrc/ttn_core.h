@@ -19,6 +19,10 @@ namespace core {
 
 // records the calling thread's error message (ttn_last_error) and returns st
 ttn_status fail(ttn_status st, const char* fmt, ...);
+// largest eigenvalue of a small symmetric matrix (n x n, row-major), host:
+// cyclic Jacobi (n <= 64) or restarted Lanczos
+double host_lambda_max(std::vector<double> a, int n);
+double host_lambda_max_lanczos(const std::vector<double>& a, int n);
 
 #define HIPCHK(expr)                                                                  \
   do {                                                                                \
@@ -96,6 +100,28 @@ struct KernelRecorder : KernelTimer {
   void end(size_t slot, hipStream_t s) override { P->end(slot, s); }
 };
 
+// Complex products over split planes: inside a CplxScope every product that
+// run() issues is complex, each operand's imaginary plane lying `delta` bytes
+// after its real plane (C = A B becomes four real products: Re C = Re A Re B
+// - Im A Im B, Im C = Re A Im B + Im A Re B); inside a BraScope as well, the
+// first operand is conjugated (the bra copy of a contraction).  delta = 0:
+// real products.
+struct CplxCtx {
+  long long delta = 0;
+  bool conj_a = false;
+};
+CplxCtx& cplx();  // the calling thread's
+struct CplxScope {
+  CplxCtx saved;
+  explicit CplxScope(long long delta) : saved(cplx()) { cplx().delta = delta; cplx().conj_a = false; }
+  ~CplxScope() { cplx() = saved; }
+};
+struct BraScope {
+  bool saved;
+  BraScope() : saved(cplx().conj_a) { cplx().conj_a = true; }
+  ~BraScope() { cplx().conj_a = saved; }
+};
+
 struct Member {
   Profiler* prof = nullptr;
   // configuration
@@ -141,6 +167,11 @@ struct Member {
   // symmetrised copy the matvec reads; null: both sites carry hop64's
   const double* topR = nullptr;
   double* hopR64 = nullptr;
+  // top problem of another form (complex tensors: a real vector of top_len
+  // doubles and its own product y -> H y); null: the real top of dims[n-1]
+  long long top_len = 0;
+  hipError_t (*matvec)(Member& M, const double* y, double* out, hipStream_t s) = nullptr;
+  void* owner = nullptr;
   double *lzQ = nullptr, *lzW = nullptr, *lzT = nullptr, *lzHv = nullptr, *lzR = nullptr;
   double *alpha = nullptr, *beta = nullptr, *Tm = nullptr, *Vm = nullptr, *ycoef = nullptr, *coef = nullptr,
          *lzpart = nullptr, *lznrm = nullptr;
@@ -215,6 +246,19 @@ hipError_t mm_k(const Member& M, Prec p, const void* Am, long long sA, bool ta, 
                 void* C, long long sC, int x, double alpha, double beta, int nk, hipStream_t s);
 hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, bool tb, void* C, int x, double alpha,
               double beta, hipStream_t s);
+// the stages of the uniform sweep over the member's arrays (the layer's S w
+// into M.Sw; operators of level tau from level tau-1; rho of every level;
+// the two-site matrices at the top, one level down, and for layer tau; the
+// environment of layer tau into M.envT)
+hipError_t s_apply(const Member& M, int lvl_below, const void* w, int a, int b, hipStream_t s);
+ttn_status stage_ascend(Member& M, int tau, hipStream_t s);
+ttn_status stage_descend_rho(Member& M, hipStream_t s);
+ttn_status dressed_top(Member& M, const void* At, const void* Bt, hipStream_t s);
+ttn_status dressed_down(Member& M, int sg, const void* Alow, const void* Blow, hipStream_t s);
+ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s);
+ttn_status stage_env(Member& M, int tau, hipStream_t s);
+// a copy of an array, and of its imaginary plane inside a CplxScope
+hipError_t copy_planes(void* dst, const void* src, size_t bytes, hipStream_t s);
 // out = sign * polar(src), src a x K float64 (M.Y, M.Y2, M.G, M.V, M.Q,
 // M.Q2, M.nrm, M.jinfo, M.skip3, M.scal as scratch)
 ttn_status polar_core(Member& M, const double* src, int a, long long K, double sign, double* out, hipStream_t s,

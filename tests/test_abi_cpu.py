@@ -166,3 +166,57 @@ def test_node_resolved_workspace_and_validation(lib):
     assert lib.ttn_pos_env(None, 1, 0, e) == binding.TTN_EINVAL
     assert lib.ttn_pos_get(None, binding.TTN_POS_W, 1, e) == binding.TTN_EINVAL
     assert lib.ttn_pos_free(None) == binding.TTN_OK
+
+
+def _cplx_cfg(model, L, chi, ws):
+    keep = []
+    cfg = binding.TTNCplxConfig()
+    h1, A, B = model.packed()
+    h1, A, B = (np.ascontiguousarray(x, dtype=np.complex128) for x in (h1, A, B))
+    keep += [h1, A, B]
+    cfg.L, cfg.d, cfg.chi, cfg.D = L, model.d, chi, model.D
+    cfg.h1, cfg.A, cfg.B = binding._cptr(h1), binding._cptr(A), binding._cptr(B)
+    cfg.shift = math.nan
+    cfg.ly = 1
+    if ws is not None:
+        ws = [np.ascontiguousarray(w, dtype=np.complex128) for w in ws]
+        keep += ws
+        arr = (ctypes.POINTER(ctypes.c_double) * len(ws))(*[binding._cptr(w) for w in ws])
+        keep.append(arr)
+        cfg.w0 = ctypes.cast(arr, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))
+    return cfg, keep
+
+
+def test_complex_workspace_and_validation(lib):
+    # host-only: the workspace grows with chi; a non-Hermitian h1, a bond term
+    # that is not Hermitian, missing isometries and a bad length are
+    # rejected; null handles too
+    model = inputs.dm_chain(1.0, 0.5, 1.0, 0.2)
+    out = ctypes.c_size_t(0)
+    sizes = []
+    for chi in (8, 32):
+        ws = inputs.random_complex_isometries(inputs.layer_shapes(64, 2, chi), 0)
+        cfg, keep = _cplx_cfg(model, 64, chi, ws)
+        assert lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_OK
+        sizes.append(out.value)
+    assert 0 < sizes[0] < sizes[1]
+    ws = inputs.random_complex_isometries(inputs.layer_shapes(16, 2, 8), 0)
+    bad = inputs.ChainModel("bad", np.array([[0, 1j], [1j, 0]]), model.A, model.B, dtype=np.complex128)
+    cfg, keep = _cplx_cfg(bad, 16, 8, ws)
+    assert lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    assert b"Hermitian" in lib.ttn_last_error()
+    # i Sx x Sy alone is anti-Hermitian: the bond term is not Hermitian
+    sx, sy = model.A[0], model.A[1]
+    bad = inputs.ChainModel("bad", np.zeros((2, 2)), [1j * sx], [sy], dtype=np.complex128)
+    cfg, keep = _cplx_cfg(bad, 16, 8, ws)
+    assert lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    cfg, keep = _cplx_cfg(model, 16, 8, None)
+    assert lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    cfg, keep = _cplx_cfg(model, 12, 8, ws)
+    assert lib.ttn_cplx_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == binding.TTN_EINVAL
+    e = (ctypes.c_double * 2)()
+    assert lib.ttn_cplx_sweep(None, 1) == binding.TTN_EINVAL
+    assert lib.ttn_cplx_energy(None, e) == binding.TTN_EINVAL
+    assert lib.ttn_cplx_env(None, 1, e) == binding.TTN_EINVAL
+    assert lib.ttn_cplx_get(None, binding.TTN_CPLX_W, 1, e) == binding.TTN_EINVAL
+    assert lib.ttn_cplx_free(None) == binding.TTN_OK

@@ -252,3 +252,14 @@ def test_planted_missing_conjugation_is_caught(monkeypatch):
     psi = P.full_state(r.ws, v)
     e_bf = np.vdot(psi, P.dm_xxz_chain_hamiltonian(L, 1.0, 0.6, 0.8, 0.3) @ psi).real
     assert abs(e_ttn - e_bf) > 1e-3
+
+
+@pytest.mark.parametrize("L", [6, 8, 12])
+def test_xx_free_fermion_closed_form_equals_ed(L):
+    # the bound the GPU tests hold long chiral chains to: at Dm = J, Delta = 0
+    # and L a multiple of 8 the chain is an XX ring with J' = sqrt(2) J
+    assert P.xx_chain_free_fermion_energy(L, 1.3) == pytest.approx(
+        P.ground_energy(P.xxz_chain_hamiltonian(L, 1.3, 0.0)), abs=1e-12)
+    if L % 8 == 0:
+        assert P.xx_chain_free_fermion_energy(L, np.sqrt(2.0)) == pytest.approx(
+            P.ground_energy(P.dm_xxz_chain_hamiltonian(L, 1.0, 1.0, 0.0)), abs=1e-12)
