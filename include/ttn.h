@@ -423,7 +423,7 @@ typedef struct ttn_pos_config {
   const double* v0;   /* optional host chi_{n-1}^2 start vector               */
   int krylov, restarts;  /* as in ttn_config, 0: 24, 8                         */
   double lanczos_tol;    /* as in ttn_config, 0: 1e-12                         */
-  int chunk_nodes;    /* nodes per launch chunk at most (0: as many as 1 GiB of
+  int chunk_nodes;    /* nodes per launch chunk at most (0: as many as 8 GiB of
                          staging holds); results do not depend on it beyond
                          rounding                                             */
 } ttn_pos_config;
@@ -431,7 +431,7 @@ typedef struct ttn_pos_config {
 /* Workspace: the per-node arrays (isometries, operators, density matrices
  * and edge information of every node, the descent's cache: each about the
  * size of all isometries, so about five times the isometries' bytes), the
- * top solver's buffers, and staging of at most 1 GiB per launch chunk.
+ * top solver's buffers, and staging of at most 8 GiB per launch chunk.
  * Same errors as ttn_workspace_bytes; TTN_EINVAL when w0 or one of its
  * layers is NULL. */
 ttn_status ttn_pos_workspace_bytes(const ttn_pos_config* cfg, size_t* bytes);
