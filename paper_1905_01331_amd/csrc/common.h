@@ -232,18 +232,4 @@ hipError_t fill_null_rows(double* Y, const double* T, const double* nrm2, int m,
 // ||W W^T - I||_F from the Gram G (n x n): out[0] = sqrt(sum (G - I)^2)
 hipError_t ortho_err_from_gram(const double* G, int n, double* out, hipStream_t s);
 
-// -------- complex layouts (complex.hip) ----------------------------------------
-// split planes from interleaved (re, im) pairs (z: 2n doubles, 16-byte
-// aligned) and back
-hipError_t deinterleave_f64(const double* z, double* re, double* im, size_t n, hipStream_t s);
-hipError_t interleave_f64(const double* re, const double* im, double* z, size_t n, hipStream_t s);
-// real embedding of the complex m x k matrix X = xr + i xi: y (2m x 2k,
-// row-major) = [[xr, -xi], [xi, xr]]; products, conjugate transposes and so
-// polar factors of complex matrices are those of their embeddings (m <= 32767)
-hipError_t embed_complex_f64(const double* xr, const double* xi, double* y, int m, long long k, hipStream_t s);
-// the complex m x k matrix whose embedding is nearest to y (2m x 2k) =
-// [[P, Q], [R, S]]: xr = (P + S) / 2, xi = (R - Q) / 2 (the projection onto
-// embeddings; exact on an embedding)
-hipError_t unembed_complex_f64(const double* y, double* xr, double* xi, int m, long long k, hipStream_t s);
-
 }  // namespace ttn

@@ -3,7 +3,7 @@
 // matrix that the polar update factors.
 #include <hip/hip_runtime.h>
 
-#include "common.h"
+#include "complex.h"
 
 namespace ttn {
 namespace {

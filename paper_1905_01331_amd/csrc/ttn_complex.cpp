@@ -28,6 +28,7 @@
 
 #include "ttn.h"
 #include "common.h"
+#include "complex.h"
 #include "lanczos.h"
 #include "ttn_core.h"
 

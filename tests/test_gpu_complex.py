@@ -251,3 +251,37 @@ def test_product_state_chain_with_rank_deficient_environments(B):
     assert hist[-1] < hist[0] - 0.1
     assert gpu.stats().ortho_err_max <= 10 * EPS * chi ** 2
     gpu.close()
+
+
+def test_round_trips_and_argument_errors(B):
+    """set/get of isometries and of the top tensor return what was set (and a
+    set isometry re-ascends the levels above: the energy of the oracle's
+    state follows); the two-site matrices need an environment first; bad
+    kinds and levels are rejected."""
+    model, L, chi = I.dm_chain(1.0, 0.6, 0.8, 0.3), 32, 6
+    ref, _, gpu = pair_up(B, model, L, chi, seed=21)
+    other = I.random_complex_isometries(C.layer_shapes(L, model.d, chi), 22)
+    for t in range(1, ref.n):
+        gpu.set_isometry(t, other[t - 1])
+        assert np.array_equal(gpu.isometry(t), other[t - 1])
+    v = I.random_complex_top(ref.dims[-1], 23)
+    gpu.set_top(v)
+    assert np.array_equal(gpu.top(), v)
+    alt = C.ComplexTTNRef(L, chi, model.h1, model.A, model.B, other)
+    alt.initialise()
+    for t in range(ref.n):
+        h, _, _ = gpu.operators(t)
+        assert np.abs(h - alt.hs[t]).max() <= 1e-13 * scale(alt.hs[t]), t
+    with pytest.raises(B.TTNError):
+        gpu.dressed(1)  # no environment since the last change of state
+    gpu.env(2)
+    Rg, _ = gpu.dressed(2)
+    assert Rg.shape == (model.D, ref.dims[2], ref.dims[2])
+    for bad in ((B.TTN_CPLX_W, 0), (B.TTN_CPLX_W, ref.n), (B.TTN_CPLX_RHO, -1), (17, 1)):
+        with pytest.raises(B.TTNError):
+            gpu._get(bad[0], bad[1], (1,))
+    with pytest.raises(B.TTNError):
+        gpu.env(0)
+    with pytest.raises(B.TTNError):
+        gpu.sweep(-1)
+    gpu.close()
