@@ -35,8 +35,9 @@ struct GemmDesc {
   // square outputs known to be symmetric (tri = 1) or, for the batch entries
   // whose bit is set in anti (inner batch index), antisymmetric: a float64
   // launch may compute the block upper triangle only and mirror the rest
-  // (beta must be 0); other launches ignore it.  The split count then follows
-  // the tiles computed.
+  // (with beta != 0 the old C must have the same parity: only its upper
+  // triangle is read); other launches ignore it.  The split count then
+  // follows the tiles computed.
   int tri;
   unsigned long long anti;
 };

@@ -710,8 +710,9 @@ static hipError_t gemm_mfma64(const GemmDesc& g, void* scratch, size_t scratch_b
   // the split count follows the shape alone (counted at 64 x 64 tiles); the
   // tile (64 x 64 by default) is a launch choice
   // a symmetric (antisymmetric) square output: the 64 x 64 tiles of the
-  // block upper triangle, then the mirror
-  const bool tri = g.tri != 0 && g.M == g.N && g.beta == 0.0;
+  // block upper triangle, then the mirror (with beta != 0 the old C is read
+  // on the upper triangle only; the caller's C has the output's parity)
+  const bool tri = g.tri != 0 && g.M == g.N;
   GemmDesc gt = g;
   gt.tri = tri ? 1 : 0;
   int kchunk = 0;

@@ -554,12 +554,21 @@ hipError_t left_mul_k(const Member& M, Prec p, const void* X, long long sX, cons
   g.alpha = alpha; g.beta = beta;
   return run(M, p, g, s, OC_LEFT_MUL);
 }
-// C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']   (b x b, K = a*b)
+// C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r']   (b x b, K = a*b).  Both
+// child closes only ever produce symmetric matrices (density matrices:
+// P = w, Q = rho o w, or Q = w and P = rho o w, with rho symmetric) or, in the
+// dressed chains, matrices of their product term's parity (bit k of anti set:
+// antisymmetric), so a float64 launch computes the block upper triangle and
+// mirrors it; a beta != 0 accumulation reads the upper triangle of a C of the
+// same parity.
 hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                     unsigned long long anti) {
   if (nk < 1) return hipSuccess;
   BraScope bra;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   g.batch = nk;
   g.M = b; g.N = b; g.K = a * b; g.K2 = 0;
   g.A = P; g.sAm = 1; g.sAk = b; g.sAb = sP;
@@ -570,10 +579,13 @@ hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const
 }
 // C_L(P,Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r]   (b x b, K = (a, r))
 hipError_t close_l_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s) {
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                     unsigned long long anti) {
   if (nk < 1) return hipSuccess;
   BraScope bra;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   long long bb = (long long)b * b;
   g.batch = nk;
   g.M = b; g.N = b; g.K = a * b; g.K2 = b;
@@ -601,11 +613,11 @@ hipError_t left_mul(const Member& M, Prec p, const void* X, const void* P, void*
 }
 hipError_t close_r(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
                    double beta, hipStream_t s) {
-  return close_r_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+  return close_r_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s, 0);
 }
 hipError_t close_l(const Member& M, Prec p, const void* P, const void* Qm, void* C, int a, int b, double alpha,
                    double beta, hipStream_t s) {
-  return close_l_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s);
+  return close_l_k(M, p, P, 0, Qm, 0, C, 0, a, b, alpha, beta, 1, s, 0);
 }
 // dense square products of order x: C = alpha op(A) op(B) + beta C, for nk
 // triples (A + k sA, B + k sB, C + k sC) in one launch
@@ -761,8 +773,8 @@ ttn_status local_energies(Member& M, double* W, long long total, const PosLayout
     for (long long m0 = 0; m0 < parents; m0 += chunk) {
       const int c = (int)std::min<long long>(chunk, parents - m0);
       HIPCHK(left_mul_k(M, P_F64, up + m0 * aa, aa, w, 0, S, cube, a, b, 1.0, 0.0, c, s));
-      HIPCHK(close_l_k(M, P_F64, w, 0, S, cube, lo + 2 * m0 * bb, 2 * bb, a, b, 1.0, 0.0, c, s));
-      HIPCHK(close_r_k(M, P_F64, w, 0, S, cube, lo + (2 * m0 + 1) * bb, 2 * bb, a, b, 1.0, 0.0, c, s));
+      HIPCHK(close_l_k(M, P_F64, w, 0, S, cube, lo + 2 * m0 * bb, 2 * bb, a, b, 1.0, 0.0, c, s, 0));
+      HIPCHK(close_r_k(M, P_F64, w, 0, S, cube, lo + (2 * m0 + 1) * bb, 2 * bb, a, b, 1.0, 0.0, c, s, 0));
     }
   }
   HIPCHK(pair_rows_f64(W + P.rho[0], dd, W + P.h1, 0, dd, (int)L, site, 1, 0, 0.0, s));
@@ -857,13 +869,13 @@ ttn_status dressed_down(Member& M, int sg, const void* Alow, const void* Blow, h
   void* Ln = M.Lb[nx];
   // inside a parent (A left child, B right child) + across parents
   HIPCHK(apply_l_k(M, p, Alow, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-  HIPCHK(close_r_k(M, p, P, 0, M.S2, cube, Rn, bb, a, b, 0.5, 0.0, D, s));
+  HIPCHK(close_r_k(M, p, P, 0, M.S2, cube, Rn, bb, a, b, 0.5, 0.0, D, s, M.anti_bits()));
   HIPCHK(left_mul_k(M, p, M.Rb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
-  HIPCHK(close_l_k(M, p, w, 0, M.S3, cube, Rn, bb, a, b, 0.5, 1.0, D, s));
+  HIPCHK(close_l_k(M, p, w, 0, M.S3, cube, Rn, bb, a, b, 0.5, 1.0, D, s, M.anti_bits()));
   HIPCHK(apply_r_k(M, p, Blow, bb, w, 0, M.S2, cube, a, b, 0.0, D, s));
-  HIPCHK(close_l_k(M, p, P, 0, M.S2, cube, Ln, bb, a, b, 0.5, 0.0, D, s));
+  HIPCHK(close_l_k(M, p, P, 0, M.S2, cube, Ln, bb, a, b, 0.5, 0.0, D, s, M.anti_bits()));
   HIPCHK(left_mul_k(M, p, M.Lb[cur], aa, w, 0, M.S3, cube, a, b, 1.0, 0.0, D, s));
-  HIPCHK(close_r_k(M, p, w, 0, M.S3, cube, Ln, bb, a, b, 0.5, 1.0, D, s));
+  HIPCHK(close_r_k(M, p, w, 0, M.S3, cube, Ln, bb, a, b, 0.5, 1.0, D, s, M.anti_bits()));
   M.rb_cur = nx;
   return TTN_OK;
 }

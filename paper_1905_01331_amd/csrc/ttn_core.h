@@ -239,9 +239,11 @@ hipError_t close_aa_k(const Member& M, Prec p, const void* P, long long sP, cons
 hipError_t left_mul_k(const Member& M, Prec p, const void* X, long long sX, const void* P, long long sP, void* Y,
                       long long sY, int a, int b, double alpha, double beta, int nk, hipStream_t s);
 hipError_t close_r_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s);
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                     unsigned long long anti);
 hipError_t close_l_k(const Member& M, Prec p, const void* P, long long sP, const void* Qm, long long sQ, void* C,
-                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s);
+                     long long sC, int a, int b, double alpha, double beta, int nk, hipStream_t s,
+                     unsigned long long anti);
 hipError_t mm_k(const Member& M, Prec p, const void* Am, long long sA, bool ta, const void* Bm, long long sB, bool tb,
                 void* C, long long sC, int x, double alpha, double beta, int nk, hipStream_t s);
 hipError_t mm(const Member& M, Prec p, const void* Am, bool ta, const void* Bm, bool tb, void* C, int x, double alpha,
