@@ -208,11 +208,17 @@ hipError_t pos_left_mul(Pos& P, const double* X, long long xk, long long xn, con
   batch2(g, nk, nn, xk, xn, qk, qn, yk, yn);
   return run(P.M, P_F64, g, P.s, OC_LEFT_MUL);
 }
-// C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r'] over (k, node)
+// C_R(P,Q)[r,r'] = sum_{a,l} P[a;l,r] Q[a;l,r'] over (k, node).  The child
+// closes produce the children's rho (symmetric) and edge information of the
+// parity of their product term (bit k of anti: antisymmetric), so a float64
+// launch computes the block upper triangle and mirrors it.
 hipError_t pos_close_r(Pos& P, const double* Pm, long long pk, long long pn, const double* Qm, long long qk,
-                       long long qn, double* C, long long ck, long long cn, int a, int b, int nk, int nn) {
+                       long long qn, double* C, long long ck, long long cn, int a, int b, int nk, int nn,
+                       unsigned long long anti) {
   if (nk < 1 || nn < 1) return hipSuccess;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   g.M = b; g.N = b; g.K = a * b;
   g.A = Pm; g.sAm = 1; g.sAk = b;
   g.B = Qm; g.sBk = b; g.sBn = 1;
@@ -222,10 +228,13 @@ hipError_t pos_close_r(Pos& P, const double* Pm, long long pk, long long pn, con
 }
 // C_L(P,Q)[l,l'] = sum_{a,r} P[a;l,r] Q[a;l',r] over (k, node)
 hipError_t pos_close_l(Pos& P, const double* Pm, long long pk, long long pn, const double* Qm, long long qk,
-                       long long qn, double* C, long long ck, long long cn, int a, int b, int nk, int nn) {
+                       long long qn, double* C, long long ck, long long cn, int a, int b, int nk, int nn,
+                       unsigned long long anti) {
   if (nk < 1 || nn < 1) return hipSuccess;
   const long long bb = (long long)b * b;
   GemmDesc g = desc0();
+  g.tri = 1;
+  g.anti = anti;
   g.M = b; g.N = b; g.K = a * b; g.K2 = b;
   g.A = Pm; g.sAm = b; g.sAk = 1; g.sAk1 = bb;
   g.B = Qm; g.sBk = 1; g.sBk1 = bb; g.sBn = b;
@@ -304,8 +313,8 @@ ttn_status pos_descend_rho(Pos& P) {
     const long long cube = P.cube(t), sd = P.dx_stride(t), sdc = P.dx_stride(t - 1);
     const int nn = (int)P.nodes(t);
     HIPCHK(pos_left_mul(P, P.DX[t], 0, sd, P.W[t], 0, cube, P.PC[t], 0, cube, a, b, 1, nn));
-    HIPCHK(pos_close_l(P, P.W[t], 0, cube, P.PC[t], 0, cube, P.DX[t - 1], 0, 2 * sdc, a, b, 1, nn));
-    HIPCHK(pos_close_r(P, P.W[t], 0, cube, P.PC[t], 0, cube, P.DX[t - 1] + sdc, 0, 2 * sdc, a, b, 1, nn));
+    HIPCHK(pos_close_l(P, P.W[t], 0, cube, P.PC[t], 0, cube, P.DX[t - 1], 0, 2 * sdc, a, b, 1, nn, 0));
+    HIPCHK(pos_close_r(P, P.W[t], 0, cube, P.PC[t], 0, cube, P.DX[t - 1] + sdc, 0, 2 * sdc, a, b, 1, nn, 0));
   }
   return TTN_OK;
 }
@@ -321,6 +330,7 @@ ttn_status pos_descend_xy(Pos& P, int lowest) {
   double* dx0 = P.DX[n - 1];
   double* dx1 = dx0 + sdt;
   double* T = P.stage;
+  const unsigned long long anti = P.M.anti_bits();
   // X^(0) = v A^(1) v^T, X^(1) = v^T A^(0) v, Y^(0) = v B^(1) v^T, Y^(1) = v^T B^(0) v
   HIPCHK(mm_k(P.M, P_F64, op1 + xx, xx, false, v, 0, true, T, xx, x, 1.0, 0.0, D, P.s));
   HIPCHK(mm_k(P.M, P_F64, v, 0, false, T, xx, false, dx0 + xx, xx, x, 1.0, 0.0, D, P.s));
@@ -346,16 +356,16 @@ ttn_status pos_descend_xy(Pos& P, int lowest) {
       const double* opr = opl + soc;
       // outer edges from the parent's: X_L = C_L(w, X o w), Y_R = C_R(w, Y o w)
       HIPCHK(pos_left_mul(P, dx + aa, aa, sd, w, 0, cube, T, cube, ts, a, b, D, nn));
-      HIPCHK(pos_close_l(P, w, 0, cube, T, cube, ts, lo_l + bb, bb, 2 * sdc, a, b, D, nn));
+      HIPCHK(pos_close_l(P, w, 0, cube, T, cube, ts, lo_l + bb, bb, 2 * sdc, a, b, D, nn, anti));
       HIPCHK(pos_left_mul(P, dx + (1 + D) * aa, aa, sd, w, 0, cube, T, cube, ts, a, b, D, nn));
-      HIPCHK(pos_close_r(P, w, 0, cube, T, cube, ts, lo_r + (1 + D) * bb, bb, 2 * sdc, a, b, D, nn));
+      HIPCHK(pos_close_r(P, w, 0, cube, T, cube, ts, lo_r + (1 + D) * bb, bb, 2 * sdc, a, b, D, nn, anti));
       // inner edges meet inside the parent: X_R = C_R(w, A_{L,k} .l (rho o w)),
       // Y_L = C_L(w, B_{R,k} .r (rho o w))
       for (int k = 0; k < D; ++k)
         HIPCHK(pos_apply_l(P, opl + (1 + k) * bb, 2 * soc, pc, cube, T + k * cube, ts, a, b, 0.0, nn));
-      HIPCHK(pos_close_r(P, w, 0, cube, T, cube, ts, lo_r + bb, bb, 2 * sdc, a, b, D, nn));
+      HIPCHK(pos_close_r(P, w, 0, cube, T, cube, ts, lo_r + bb, bb, 2 * sdc, a, b, D, nn, anti));
       HIPCHK(pos_apply_r(P, opr + (1 + D) * bb, bb, 2 * soc, pc, 0, cube, T, cube, ts, a, b, 0.0, D, nn));
-      HIPCHK(pos_close_l(P, w, 0, cube, T, cube, ts, lo_l + (1 + D) * bb, bb, 2 * sdc, a, b, D, nn));
+      HIPCHK(pos_close_l(P, w, 0, cube, T, cube, ts, lo_l + (1 + D) * bb, bb, 2 * sdc, a, b, D, nn, anti));
     }
   }
   return TTN_OK;
