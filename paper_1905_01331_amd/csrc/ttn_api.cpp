@@ -426,17 +426,22 @@ hipError_t run_real(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, i
 hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls) {
   const CplxCtx cx = cplx();
   if (cx.delta == 0) return run_real(M, p, g, s, cls);
-  // complex: four real products over the planes (no symmetric shortcut: the
-  // real and imaginary parts of a Hermitian result are not each symmetric)
+  // complex: four real products over the planes.  A result asked on its
+  // triangle is Hermitian or anti-Hermitian when the caller allows it
+  // (tri_ok): the real plane then has the parity of the anti bits and the
+  // imaginary plane the opposite one, and each plane's two products run on
+  // the triangle (the second accumulates into the first's upper triangle)
   const double sa = cx.conj_a ? -1.0 : 1.0;
   auto im = [&](const void* q) { return (const void*)((const char*)q + cx.delta); };
+  const bool tri = g.tri != 0 && cx.tri_ok;
   GemmDesc q = g;
-  q.tri = 0;
-  q.anti = 0;
+  q.tri = tri ? 1 : 0;
+  q.anti = tri ? g.anti : 0;
   hipError_t e;
   if ((e = run_real(M, p, q, s, cls))) return e;  // Re C = alpha Re A Re B + beta Re C
   q.A = im(g.A); q.B = im(g.B); q.alpha = -sa * g.alpha; q.beta = 1.0;
   if ((e = run_real(M, p, q, s, cls))) return e;  //      - alpha (+-Im A) Im B
+  q.anti = tri ? ~g.anti : 0;
   q.A = g.A; q.B = im(g.B); q.C = (void*)im(g.C); q.alpha = g.alpha; q.beta = g.beta;
   if ((e = run_real(M, p, q, s, cls))) return e;  // Im C = alpha Re A Im B + beta Im C
   q.A = im(g.A); q.B = g.B; q.alpha = sa * g.alpha; q.beta = 1.0;

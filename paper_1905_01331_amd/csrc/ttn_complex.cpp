@@ -52,6 +52,10 @@ struct ttn_cplx_ctx {
   // current isometry, the polar update's fill scratch; host transfers
   double *emb = nullptr, *emb_w = nullptr, *emb_t = nullptr, *io = nullptr;
   std::vector<int> herm;  // per product term: 1 A_k, B_k Hermitian, -1 anti-Hermitian, 0 neither
+  // every term Hermitian or anti-Hermitian: the ascended operators, the
+  // descended matrices and the two-site matrices are too, and their products
+  // run on the block upper triangle (M.anti: the anti-Hermitian terms)
+  bool tri_ok = false;
   int env_tau = -1;
   long long repairs = 0;  // updates whose result was replaced by its nearest isometry
   bool top_conv = true;
@@ -350,7 +354,7 @@ ttn_status cx_top(Cx& P) {
   const int n = P.n, x = P.dims[n - 1], D = P.D;
   const long long xx = (long long)x * x;
   {
-    CplxScope cs(P.delta);
+    CplxScope cs(P.delta, P.tri_ok);
     HIPCHK(copy_planes(P.tops, P.ops[n - 1], (1 + 2 * D) * xx * 8, P.s));
   }
   // remove the rounding asymmetry: h Hermitian, A_k, B_k of their term's kind
@@ -450,7 +454,7 @@ ttn_status cx_update(Cx& P, int tau) {
 }
 
 ttn_status cx_ascend_from(Cx& P, int from) {
-  CplxScope cs(P.delta);
+  CplxScope cs(P.delta, P.tri_ok);
   ttn_status r;
   for (int t = from; t < P.n; ++t)
     if ((r = stage_ascend(P.M, t, P.s))) return r;
@@ -461,18 +465,18 @@ ttn_status cx_sweep_body(Cx& P) {
   Member& M = P.M;
   ttn_status r;
   {
-    CplxScope cs(P.delta);
+    CplxScope cs(P.delta, P.tri_ok);
     if ((r = stage_descend_rho(M, P.s))) return r;
   }
   for (int t = 1; t < P.n; ++t) {
     {
-      CplxScope cs(P.delta);
+      CplxScope cs(P.delta, P.tri_ok);
       if ((r = stage_descend_dressed(M, t, P.s))) return r;
       if ((r = stage_env(M, t, P.s))) return r;
     }
     if ((r = cx_update(P, t))) return r;
     {
-      CplxScope cs(P.delta);
+      CplxScope cs(P.delta, P.tri_ok);
       if ((r = stage_ascend(M, t, P.s))) return r;
     }
   }
@@ -530,6 +534,11 @@ ttn_status ttn_cplx_init(const ttn_cplx_config* cfg, void* workspace, size_t byt
   P->s = (hipStream_t)stream;
   Member& M = P->M;
   if ((st = cx_member(cfg, M, &P->herm))) return bail(st);
+  P->tri_ok = true;
+  for (int hk : P->herm) {
+    P->tri_ok = P->tri_ok && hk != 0;
+    M.anti.push_back(hk < 0 ? 1 : 0);
+  }
   cx_layout(M, (char*)workspace, P);
   M.prof = &P->prof;
   M.matvec = cx_matvec;
@@ -604,7 +613,7 @@ ttn_status ttn_cplx_descend(ttn_cplx_handle h) {
   ttn_status st = cx_check(h);
   if (st) return st;
   {
-    CplxScope cs(h->delta);
+    CplxScope cs(h->delta, h->tri_ok);
     if ((st = stage_descend_rho(h->M, h->s))) return st;
   }
   HIPCHK(hipStreamSynchronize(h->s));
@@ -616,7 +625,7 @@ ttn_status ttn_cplx_env(ttn_cplx_handle h, int tau, double* host) {
   if (st) return st;
   if (tau < 1 || tau >= h->n || !host) return fail(TTN_EINVAL, "tau=%d: need 1 <= tau < %d, non-null host", tau, h->n);
   {
-    CplxScope cs(h->delta);
+    CplxScope cs(h->delta, h->tri_ok);
     if ((st = stage_descend_rho(h->M, h->s))) return st;
     if ((st = stage_descend_dressed(h->M, tau, h->s))) return st;
     if ((st = stage_env(h->M, tau, h->s))) return st;

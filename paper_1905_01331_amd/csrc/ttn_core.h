@@ -106,14 +106,24 @@ struct KernelRecorder : KernelTimer {
 // - Im A Im B, Im C = Re A Im B + Im A Re B); inside a BraScope as well, the
 // first operand is conjugated (the bra copy of a contraction).  delta = 0:
 // real products.
+// A product that asks for its block upper triangle (GemmDesc.tri: a
+// symmetric real result, antisymmetric for the anti bits) keeps it in complex
+// arithmetic when tri_ok: the caller's results are then Hermitian (anti bit
+// clear: real part symmetric, imaginary part antisymmetric) or anti-Hermitian
+// (the reverse), and each plane is computed on its triangle with its parity.
 struct CplxCtx {
   long long delta = 0;
   bool conj_a = false;
+  bool tri_ok = false;
 };
 CplxCtx& cplx();  // the calling thread's
 struct CplxScope {
   CplxCtx saved;
-  explicit CplxScope(long long delta) : saved(cplx()) { cplx().delta = delta; cplx().conj_a = false; }
+  CplxScope(long long delta, bool tri_ok) : saved(cplx()) {
+    cplx().delta = delta;
+    cplx().conj_a = false;
+    cplx().tri_ok = tri_ok;
+  }
   ~CplxScope() { cplx() = saved; }
 };
 struct BraScope {
