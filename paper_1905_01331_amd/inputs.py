@@ -109,18 +109,30 @@ def xxx_chain() -> ChainModel:
     return ChainModel("xxx", np.zeros((2, 2)), [sx, isy, sz], [sx, -isy, sz], ly=1)
 
 
-def dm_chain(J: float = 1.0, Dm: float = 1.0, Delta: float = 1.0, hz: float = 0.0) -> ChainModel:
+def dm_chain(J: float = 1.0, Dm: float = 1.0, Delta: float = 1.0, hz: float = 0.0,
+             form: str = "hermitian") -> ChainModel:
     """Spin-1/2 XXZ chain with a Dzyaloshinskii-Moriya term along z (complex):
     ``H = sum_i [J (Sx_i Sx_{i+1} + Sy_i Sy_{i+1}) + Delta Sz_i Sz_{i+1}
     + Dm (Sx_i Sy_{i+1} - Sy_i Sx_{i+1}) + hz Sz_i]`` with S = sigma/2 and
-    the complex Sy.  Written with three product terms, each A_k and B_k
-    Hermitian: A = (Sx, Sy, Sz), B = (J Sx + Dm Sy, J Sy - Dm Sx, Delta Sz).
-    The DM term makes the Hamiltonian matrix complex (Sx Sy is imaginary)."""
+    the complex Sy.  The DM term makes the Hamiltonian matrix complex (Sx Sy
+    is imaginary).  Two ways of writing it with three product terms:
+    form="hermitian": A = (Sx, Sy, Sz), B = (J Sx + Dm Sy, J Sy - Dm Sx,
+    Delta Sz), every factor Hermitian; form="ladder": with S+- = Sx +- i Sy,
+    A = ((J + i Dm)/2 S+, (J - i Dm)/2 S-, Sz), B = (S-, S+, Delta Sz), whose
+    first two terms have factors that are neither Hermitian nor
+    anti-Hermitian (their sum is Hermitian)."""
     sx = 0.5 * PAULI_X.astype(np.complex128)
     sy = 0.5 * np.array([[0.0, -1.0j], [1.0j, 0.0]])
     sz = 0.5 * PAULI_Z.astype(np.complex128)
-    return ChainModel(f"dm_xxz(J={J},Dm={Dm},Delta={Delta},hz={hz})", hz * sz, [sx, sy, sz],
-                      [J * sx + Dm * sy, J * sy - Dm * sx, Delta * sz], ly=1, dtype=np.complex128)
+    name = f"dm_xxz(J={J},Dm={Dm},Delta={Delta},hz={hz},{form})"
+    if form == "hermitian":
+        return ChainModel(name, hz * sz, [sx, sy, sz], [J * sx + Dm * sy, J * sy - Dm * sx, Delta * sz], ly=1,
+                          dtype=np.complex128)
+    if form == "ladder":
+        sp, sm = sx + 1j * sy, sx - 1j * sy
+        return ChainModel(name, hz * sz, [0.5 * (J + 1j * Dm) * sp, 0.5 * (J - 1j * Dm) * sm, sz],
+                          [sm, sp, Delta * sz], ly=1, dtype=np.complex128)
+    raise ValueError("form must be 'hermitian' or 'ladder'")
 
 
 def random_complex_isometries(shapes, seed: int):

@@ -36,11 +36,14 @@ def B():
 
 
 # (name, model, L, chi): one tile, several tiles with ragged edges (chi 40:
-# products of 1600 rows, 40-wide outputs), a real Hamiltonian (with an
+# products of 1600 rows, 40-wide outputs), the chain written with S+-
+# factors (neither Hermitian nor anti-Hermitian: every close on the full
+# square, the top operators not symmetrised), a real Hamiltonian (with an
 # anti-Hermitian product term) through the complex path
 CASES = [
     ("dm_L16_chi4", I.dm_chain(1.0, 0.6, 0.8, 0.3), 16, 4),
     ("dm_L32_chi6", I.dm_chain(1.0, 1.0, 1.0, 0.0), 32, 6),
+    ("dm_ladder_L32_chi6", I.dm_chain(1.0, 1.0, 1.0, 0.0, form="ladder"), 32, 6),
     ("dm_L64_chi40", I.dm_chain(1.0, 0.4, 0.7, 0.1), 64, 40),
     ("xxx_real_L32_chi8", I.xxx_chain(), 32, 8),
 ]
@@ -173,6 +176,7 @@ def test_sweep_comparisons_cover_well_conditioned_cases():
         covered[name] = (next((i for i, x in enumerate(r) if x < R_UNIQUE), len(r)), len(r))
     assert covered["dm_L16_chi4"][0] == covered["dm_L16_chi4"][1]
     assert covered["dm_L32_chi6"][0] == covered["dm_L32_chi6"][1]
+    assert covered["dm_ladder_L32_chi6"][0] == covered["dm_ladder_L32_chi6"][1]
     assert covered["dm_L64_chi40"][0] >= covered["dm_L64_chi40"][1] - 1
 
 
@@ -285,3 +289,36 @@ def test_round_trips_and_argument_errors(B):
     with pytest.raises(B.TTNError):
         gpu.sweep(-1)
     gpu.close()
+
+
+def test_minimal_network_is_exact(B):
+    """L = 4 (one layer and the top tensor) at full bond dimension: the state
+    space is the whole Hilbert space, so the energy is the exact ground energy
+    of the four-site chiral ring."""
+    model, L, chi = I.dm_chain(1.0, 0.6, 0.8, 0.3), 4, 4
+    ws = I.random_complex_isometries(C.layer_shapes(L, model.d, chi), 2)
+    gpu = B.CplxTTN(model, L, chi, ws, **LZ)
+    e_ed = PR.ground_energy(PR.dm_xxz_chain_hamiltonian(L, 1.0, 0.6, 0.8, 0.3)) / L
+    assert gpu.energy()[1] == pytest.approx(e_ed, abs=1e-12)
+    gpu.close()
+
+
+def test_both_forms_of_the_chain_give_one_trajectory(B):
+    """The same chain written with Hermitian factors (closes on the triangle)
+    and with S+- factors (closes on the full square), from the same
+    isometries: the same energies sweep by sweep, to the A13 bar of the
+    smallest condition ratio met."""
+    L, chi = 64, 12
+    her = I.dm_chain(1.0, 0.5, 1.0, 0.0)
+    lad = I.dm_chain(1.0, 0.5, 1.0, 0.0, form="ladder")
+    ws = I.random_complex_isometries(C.layer_shapes(L, 2, chi), 31)
+    g1 = B.CplxTTN(her, L, chi, ws, **LZ)
+    g2 = B.CplxTTN(lad, L, chi, ws, **LZ)
+    assert g1.energy()[1] == pytest.approx(g2.energy()[1], abs=1e-12)
+    for _ in range(3):
+        g1.sweep(1)
+        g2.sweep(1)
+        r_min = min(g1.stats().sigma_ratio_min, g2.stats().sigma_ratio_min)
+        assert g1.energy()[1] == pytest.approx(g2.energy()[1], abs=max(1e-12, EPS / (10 * r_min)))
+    g1.close()
+    g2.close()

@@ -52,6 +52,14 @@ def test_effective_chain_is_the_spin_chain():
     assert np.abs(ref - ref.conj().T).max() < 1e-15
 
 
+def test_ladder_form_is_the_same_chain():
+    # the chain written with S+- factors (neither Hermitian nor anti-Hermitian)
+    L = 6
+    lad = I.dm_chain(1.0, 0.6, 0.8, 0.3, form="ladder")
+    assert np.abs(chain_matrix(lad, L) - chain_matrix(DM, L)).max() < 1e-14
+    assert not np.allclose(lad.A[0], lad.A[0].conj().T)
+
+
 @pytest.mark.parametrize("L,Delta", [(8, 0.7), (16, -0.4)])
 def test_dm_chain_maps_onto_a_real_xxz_chain(L, Delta):
     # rotating spin j about z by j theta with tan(theta) = Dm / J removes the
