@@ -720,9 +720,11 @@ def measure_grouped(B, I, name, prec, steps, warmup, seed, e_paper):
 def measure_batch(B, I, steps, warmup):
     """128 independent transverse-field Ising chains (seeded draw of L, h and
     chi; float32 bulk, float64 polar and top) swept together in one handle,
-    against the same chains swept one at a time (eager, same sweeps).  Chains
-    of equal L and chi form launch groups (one launch per kernel for the
-    whole group).  A member's arithmetic does not depend on the batch, the
+    against the same chains swept one at a time (eager, same sweeps).  The
+    layer part of a sweep runs over the chains of one chi together, every
+    length in one launch per stage level by level (the four groups side by
+    side); chains of equal L and chi form the launch groups of the top
+    updates.  A member's arithmetic does not depend on the batch, the
     launch group, graph replay or the launch tuner, so each member's energy
     equals its one-at-a-time run bit for bit; the energy error is each
     chain's energy against the float64 re-evaluation of its final state."""
@@ -730,7 +732,10 @@ def measure_batch(B, I, steps, warmup):
     import torch
     draws = I.batched_tfim_draws(128, 2026)
     mk = lambda d: B.ChainInput(I.tfim_chain(d["h"]), d["L"], d["chi"], "fp32", seed=d["seed"])
+    # launch groups of identical configuration (per-stage calls, top updates)
+    # and the coarse groups of one bond dimension the layer part runs over
     n_groups = len({(d["L"], d["chi"]) for d in draws})
+    n_coarse = len({d["chi"] for d in draws})
     t = B.TTN([mk(d) for d in draws])
     w = max(1, warmup)
     t.sweep(1)
@@ -793,7 +798,7 @@ def measure_batch(B, I, steps, warmup):
         "contraction_tflops": round(flops / (el / steps) / 1e12, 3),
         "one_at_a_time_ttn_sweeps_per_s": round(len(draws) * steps / el_s, 3),
         "speedup_vs_one_at_a_time": round(el_s / el, 3),
-        "launch_groups": n_groups,
+        "launch_groups": n_groups, "layer_part_groups": n_coarse,
         "energy_max_rel_err_vs_fp64_reeval": float(err.max()),
         "members_equal_to_one_at_a_time": int(np.sum(diff == 0.0)),
         "max_signed_diff_vs_one_at_a_time": float(diff[np.argmax(np.abs(diff))]),

@@ -206,6 +206,13 @@ struct Ctx {
     long long stride = 0;
   };
   std::vector<Group> groups;
+  // the layer part of a sweep runs over coarser groups: members of one
+  // configuration but different lengths L (their per-level shapes agree),
+  // laid out longest first at a uniform stride (shorter members padded to the
+  // longest's depth), advanced level by level in lockstep; the members still
+  // at a level are a prefix of the group, those whose top is at a level a
+  // contiguous range
+  std::vector<Group> coarse;
   hipStream_t grid_s = nullptr;          // serialises the persistent Jacobi solves of a batch
   hipStream_t cap_s = nullptr;           // stream the sweep graph is captured on
   // graphs of the planned top update, by the number of restarts they hold,
@@ -318,23 +325,28 @@ ttn_status setup_member(const ttn_config& c, Member& M) {
   return TTN_OK;
 }
 
-void layout_member(Member& M, Arena& ar) {
-  const int n = M.n, D = M.D;
+void layout_member(Member& M, Arena& ar, int n_pad) {
+  // n_pad > n: the per-level arrays of levels n .. n_pad - 1 are laid out too
+  // (unused), so that members of one bond dimension and different lengths
+  // share one layout and sit at a uniform stride
+  const int n = std::max(M.n, n_pad), D = M.D;
+  std::vector<int> dims = M.dims;
+  while ((int)dims.size() < n) dims.push_back((int)std::min<long long>((long long)dims.back() * dims.back(), M.chi));
   int cmax = 0;
   size_t cube = 0;  // largest a*b*b
-  for (int t = 0; t < n; ++t) cmax = std::max(cmax, M.dims[t]);
-  for (int t = 1; t < n; ++t) cube = std::max(cube, (size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1]);
+  for (int t = 0; t < n; ++t) cmax = std::max(cmax, dims[t]);
+  for (int t = 1; t < n; ++t) cube = std::max(cube, (size_t)dims[t] * dims[t - 1] * dims[t - 1]);
   cube = std::max(cube, (size_t)(1 + 2 * D) * M.d * M.d);  // staging of the level-0 operators
-  const int x = M.dims[n - 1];
+  const int x = M.dims[M.n - 1];
   const size_t xx = (size_t)x * x;
   M.w64.assign(n, nullptr);
   M.wT.assign(n, nullptr);
   M.Qw.assign(n, nullptr);
   M.qw_valid.assign(n, 0);
   for (int t = 1; t < n; ++t) {
-    size_t e = (size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1];
+    size_t e = (size_t)dims[t] * dims[t - 1] * dims[t - 1];
     M.w64[t] = ar.take<double>(e);
-    M.Qw[t] = ar.take<double>((size_t)M.dims[t] * M.dims[t]);
+    M.Qw[t] = ar.take<double>((size_t)dims[t] * dims[t]);
     M.wT[t] = (M.prec == TTN_FP64) ? (void*)M.w64[t] : ar.take_bytes(M.el(e));
   }
   M.opH.assign(n, nullptr);
@@ -345,14 +357,14 @@ void layout_member(Member& M, Arena& ar) {
   M.At.assign(n, nullptr);
   M.Bt.assign(n, nullptr);
   for (int t = 0; t < n; ++t) {
-    size_t q = (size_t)M.dims[t] * M.dims[t];
+    size_t q = (size_t)dims[t] * dims[t];
     M.opH[t] = ar.take_bytes(M.el(q));
     M.opA[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
     M.opB[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
     M.rho[t] = ar.take_bytes(M.el(q));
     M.At[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
     M.Bt[t] = ar.take_bytes(M.el(q * std::max(D, 1)));
-    if (t >= 2) M.Pc[t] = ar.take_bytes(M.el((size_t)M.dims[t] * M.dims[t - 1] * M.dims[t - 1]));
+    if (t >= 2) M.Pc[t] = ar.take_bytes(M.el((size_t)dims[t] * dims[t - 1] * dims[t - 1]));
   }
   size_t cq = (size_t)cmax * cmax * std::max(D, 1);
   for (int i = 0; i < 2; ++i) {
@@ -826,14 +838,14 @@ ttn_status stage_descend_rho(Member& M, hipStream_t s) {
 
 // Two-site information at the top from the carried operators At, Bt of level
 // n-1: Rbar = 1/2 (v^T A v + v A v^T), Lbar = 1/2 (v B v^T + v^T B v), into
-// slot 0 of the double buffer.
+// slot rb_cur of the double buffer (set by the caller).
 ttn_status dressed_top(Member& M, const void* At, const void* Bt, hipStream_t s) {
   Prec p = M.gp();
   const int n = M.n, D = M.D;
   const int x = M.dims[n - 1];
   const long long xx = (long long)x * x;
-  void* R = M.Rb[0];
-  void* Lq = M.Lb[0];
+  void* R = M.Rb[M.rb_cur];
+  void* Lq = M.Lb[M.rb_cur];
   // the left factor v (v^T) of each second product is the bra copy
   HIPCHK(mm_k(M, p, At, xx, false, M.vT, 0, false, M.tmpT, xx, x, 1.0, 0.0, D, s));  // A v
   {
@@ -855,7 +867,6 @@ ttn_status dressed_top(Member& M, const void* At, const void* Bt, hipStream_t s)
     BraScope bra;
     HIPCHK(mm_k(M, p, M.vT, 0, true, M.tmpT, xx, false, Lq, xx, x, 0.5, 1.0, D, s));  // v^T B v
   }
-  M.rb_cur = 0;
   return TTN_OK;
 }
 
@@ -903,6 +914,7 @@ ttn_status stage_descend_dressed(Member& M, int tau, hipStream_t s) {
     prevB = M.Bt[sg];
   }
   ttn_status st;
+  M.rb_cur = 0;
   if ((st = dressed_top(M, M.At[n - 1], M.Bt[n - 1], s))) return st;
   // descend through layers n-1 .. tau+1
   for (int sg = n - 1; sg >= tau + 1; --sg)
@@ -1461,6 +1473,50 @@ std::vector<double> group_key(const Member& M) {
   return k;
 }
 
+// Members that may share a coarse group: every configuration value but L,
+// and the same top bond dimension (then their shapes agree level by level).
+std::vector<double> coarse_key(const Member& M) {
+  std::vector<double> k = group_key(M);
+  k.erase(k.begin());
+  k.push_back((double)M.dims[M.n - 1]);
+  return k;
+}
+
+int member_cmax(const Member& M) {
+  int cmax = 0;
+  for (int t = 0; t < M.n; ++t) cmax = std::max(cmax, M.dims[t]);
+  return cmax;
+}
+
+// Layout order and padded depth of a batch: sorted by coarse key, deepest
+// first, then by the full key (so that members of identical configuration
+// are adjacent); in a batch, the members of a coarse group with bond
+// dimensions <= 128 are padded to the group's largest depth.
+void plan_batch(const std::vector<Member>& ms, std::vector<int>& order, std::vector<int>& npad) {
+  const int batch = (int)ms.size();
+  order.resize(batch);
+  npad.assign(batch, 0);
+  std::vector<std::vector<double>> ck(batch), fk(batch);
+  for (int i = 0; i < batch; ++i) {
+    order[i] = i;
+    ck[i] = coarse_key(ms[i]);
+    fk[i] = group_key(ms[i]);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (ck[x] != ck[y]) return ck[x] < ck[y];
+    if (ms[x].n != ms[y].n) return ms[x].n > ms[y].n;
+    return fk[x] < fk[y];
+  });
+  if (batch < 2) return;
+  for (int k = 0; k < batch;) {
+    int j = k + 1;
+    while (j < batch && ck[order[j]] == ck[order[k]]) ++j;
+    if (member_cmax(ms[order[k]]) <= 128)
+      for (int i = k; i < j; ++i) npad[order[i]] = ms[order[k]].n;
+    k = j;
+  }
+}
+
 // Host-side stage state of the leader, copied to the other members of its
 // group after every group-wide call (they took the same path).
 void sync_group_state(Ctx& c, const Ctx::Group& G) {
@@ -1521,6 +1577,7 @@ ttn_status sweep_layers_grouped(Member& M, int groups, hipStream_t s) {
     for (int t = 1; t < n; ++t) any |= groups == 1 || t % 2 == parity;
     if (!any) continue;
     if ((st = stage_descend_rho(M, s))) return st;
+    M.rb_cur = 0;
     if ((st = dressed_top(M, M.opA[n - 1], M.opB[n - 1], s))) return st;
     for (int sg = n - 1; sg >= 1; --sg) {
       const bool upd = groups == 1 || sg % 2 == parity;
@@ -1536,10 +1593,146 @@ ttn_status sweep_layers_grouped(Member& M, int groups, hipStream_t s) {
   return TTN_OK;
 }
 
+// The layer part of one sweep for a coarse group (members sorted by depth,
+// deepest first, one layout at one stride): the stages of sweep_layers level
+// by level over the members that have the level, each launch covering a
+// contiguous range of members.  The two-site matrices sit in slot sg % 2 at
+// level sg for every member, so that members whose chains started at
+// different tops share each descent.  Every member does the arithmetic it
+// does alone.  No host synchronisation: capturable.
+ttn_status sweep_layers_coarse(Ctx& c, const Ctx::Group& G, hipStream_t s) {
+  const int cnt = (int)G.members.size();
+  auto nlev = [&](int i) { return c.m[G.members[i]].n; };
+  const int nmax = nlev(0);
+  // members [0, prefix(X)) have a level X; [first_top(X), prefix(X)) have their top there
+  auto prefix = [&](int X) { int k = 0; while (k < cnt && nlev(k) - 1 >= X) ++k; return k; };
+  auto first_top = [&](int X) { int k = 0; while (k < cnt && nlev(k) - 1 > X) ++k; return k; };
+  // f(base member) on members [first, first + count) as one launch group;
+  // the product bytes it issues are every member's
+  std::vector<double> bytes(cnt, 0.0);
+  auto on = [&](int first, int count, auto f) -> ttn_status {
+    if (count <= 0) return TTN_OK;
+    GroupScope gs(count, G.stride);
+    Member& B = c.m[G.members[first]];
+    B.bytes_acc = 0.0;
+    B.counting = true;
+    ttn_status st = f(B);
+    B.counting = false;
+    for (int i = first; i < first + count; ++i) bytes[i] += B.bytes_acc;
+    return st;
+  };
+  ttn_status st;
+  // rho of every level: top matrices where each member's top is, descents below
+  for (int lv = nmax - 1; lv >= 1; --lv) {
+    const int p = prefix(lv), f = first_top(lv);
+    if ((st = on(f, p - f, [&](Member& B) -> ttn_status {
+           const int x = B.dims[lv];
+           BraScope bra;
+           HIPCHK(mm(B, B.gp(), B.vT, false, B.vT, true, B.rho[lv], x, 0.5, 0.0, s));
+           HIPCHK(mm(B, B.gp(), B.vT, true, B.vT, false, B.rho[lv], x, 0.5, 1.0, s));
+           return TTN_OK;
+         })))
+      return st;
+    if (lv < 2) continue;
+    if ((st = on(0, p, [&](Member& B) -> ttn_status {
+           const int a = B.dims[lv], b = B.dims[lv - 1];
+           const Prec q = B.gp();
+           HIPCHK(left_mul(B, q, B.rho[lv], B.wT[lv], B.Pc[lv], a, b, 1.0, 0.0, s));
+           HIPCHK(close_l(B, q, B.wT[lv], B.Pc[lv], B.rho[lv - 1], a, b, 0.5, 0.0, s));
+           HIPCHK(close_r(B, q, B.wT[lv], B.Pc[lv], B.rho[lv - 1], a, b, 0.5, 1.0, s));
+           return TTN_OK;
+         })))
+      return st;
+  }
+  for (int t = 1; t < nmax; ++t) {
+    const int pt = prefix(t);
+    const int D = c.m[G.members[0]].D;
+    // dressed chains: A^(t-1), B^(t-1) carried up through layers t .. (own top)
+    for (int sg = t; sg < nmax; ++sg)
+      if ((st = on(0, prefix(sg), [&](Member& B) -> ttn_status {
+             const int a = B.dims[sg], b = B.dims[sg - 1];
+             const long long bb = (long long)b * b, aa = (long long)a * a, cube = (long long)a * bb;
+             const Prec q = B.gp();
+             const void* pa = sg == t ? B.opA[t - 1] : B.At[sg - 1];
+             const void* pb = sg == t ? B.opB[t - 1] : B.Bt[sg - 1];
+             HIPCHK(apply_r_k(B, q, pa, bb, B.wT[sg], 0, B.S2, cube, a, b, 0.0, D, s));
+             HIPCHK(close_aa_k(B, q, B.wT[sg], 0, B.S2, cube, B.At[sg], aa, a, b, 1.0, 0.0, D, s, B.anti_bits()));
+             HIPCHK(apply_l_k(B, q, pb, bb, B.wT[sg], 0, B.S2, cube, a, b, 0.0, D, s));
+             HIPCHK(close_aa_k(B, q, B.wT[sg], 0, B.S2, cube, B.Bt[sg], aa, a, b, 1.0, 0.0, D, s, B.anti_bits()));
+             return TTN_OK;
+           })))
+        return st;
+    // the top dressing of each member at its own top, the descents below it
+    for (int sg = nmax - 1; sg >= t; --sg) {
+      const int p = prefix(sg), f = first_top(sg);
+      if ((st = on(f, p - f, [&](Member& B) -> ttn_status {
+             B.rb_cur = sg % 2;
+             return dressed_top(B, B.At[sg], B.Bt[sg], s);
+           })))
+        return st;
+      if (sg == t) break;
+      if ((st = on(0, p, [&](Member& B) -> ttn_status {
+             B.rb_cur = sg % 2;
+             return dressed_down(B, sg, B.At[sg - 1], B.Bt[sg - 1], s);
+           })))
+        return st;
+    }
+    if ((st = on(0, pt, [&](Member& B) -> ttn_status {
+           B.rb_cur = t % 2;
+           return stage_env(B, t, s);
+         })))
+      return st;
+    // the update (its gauge rotation goes into the layer above, or into v
+    // for the members whose top layer this is), then the new operators
+    const int ft = first_top(t);
+    if ((st = on(0, ft, [&](Member& B) -> ttn_status { return stage_update_layer(B, t, s); }))) return st;
+    if ((st = on(ft, pt - ft, [&](Member& B) -> ttn_status { return stage_update_layer(B, t, s); }))) return st;
+    if ((st = on(0, pt, [&](Member& B) -> ttn_status { return stage_ascend(B, t, s); }))) return st;
+  }
+  // host state as a member's own sweep_layers leaves it
+  const Member& L0 = c.m[G.members[0]];
+  for (int i = 0; i < cnt; ++i) {
+    Member& M = c.m[G.members[i]];
+    M.bytes_layers = bytes[i];
+    M.rho_from = std::max(1, M.n - 1);
+    M.pc_from = M.n;
+    M.dressed_tau = -1;
+    M.env_tau = -1;
+    M.ops_upto = M.n - 1;
+    for (int t = 1; t < M.n; ++t) M.qw_valid[t] = L0.qw_valid[t];
+  }
+  return TTN_OK;
+}
+
 // The layer part for the whole batch: one member runs on the caller's
 // stream; a batch forks to the pool streams (member i on stream i mod P) and
 // joins back.  No host synchronisation inside: capturable.
 ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
+  if (!c.coarse.empty()) {
+    // coarse groups (one configuration, every length), side by side
+    if (c.pool.empty()) {
+      const int P = (int)std::min<size_t>(POOL_STREAMS, c.coarse.size());
+      c.pool.resize(P, nullptr);
+      c.join.resize(P, nullptr);
+      for (int i = 0; i < P; ++i) {
+        HIPCHK(hipStreamCreateWithFlags(&c.pool[i], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c.join[i], hipEventDisableTiming));
+      }
+      HIPCHK(hipEventCreateWithFlags(&c.fork, hipEventDisableTiming));
+    }
+    const int P = (int)c.pool.size();
+    HIPCHK(hipEventRecord(c.fork, s));
+    for (int i = 0; i < P; ++i) HIPCHK(hipStreamWaitEvent(c.pool[i], c.fork, 0));
+    for (size_t gi = 0; gi < c.coarse.size(); ++gi) {
+      ttn_status st = sweep_layers_coarse(c, c.coarse[gi], c.pool[gi % P]);
+      if (st) return st;
+    }
+    for (int i = 0; i < P; ++i) {
+      HIPCHK(hipEventRecord(c.join[i], c.pool[i]));
+      HIPCHK(hipStreamWaitEvent(s, c.join[i], 0));
+    }
+    return TTN_OK;
+  }
   if (c.groups.size() == 1) {
     const Ctx::Group& G = c.groups[0];
     GroupScope gs((int)G.members.size(), G.stride);
@@ -1765,13 +1958,15 @@ const char* ttn_last_error(void) { return g_err.c_str(); }
 
 ttn_status ttn_workspace_bytes(const ttn_config* cfgs, int batch, size_t* bytes) {
   if (!cfgs || batch < 1 || !bytes) return fail(TTN_EINVAL, "bad arguments");
-  Arena ar;
+  std::vector<Member> ms(batch);
   for (int i = 0; i < batch; ++i) {
-    Member M;
-    ttn_status st = setup_member(cfgs[i], M);
+    ttn_status st = setup_member(cfgs[i], ms[i]);
     if (st) return st;
-    layout_member(M, ar);
   }
+  std::vector<int> order, npad;
+  plan_batch(ms, order, npad);
+  Arena ar;
+  for (int i : order) layout_member(ms[i], ar, npad[i]);
   *bytes = ar.off + 256;
   return TTN_OK;
 }
@@ -1795,38 +1990,44 @@ ttn_status ttn_init(const ttn_config* cfgs, int batch, void* workspace, size_t b
   }
   // members of equal configuration are laid out next to each other, so that
   // they sit at a uniform stride and form one launch group; a group's bond
-  // dimensions stay <= 128 (the larger polar solves need the whole GPU)
+  // dimensions stay <= 128 (the larger polar solves need the whole GPU).
+  // Members of one configuration but different lengths follow one another,
+  // deepest first, padded to one layout: a coarse group for the layer part
+  // of a sweep.
   {
     Ctx& c = h->c;
-    std::vector<int> order(batch);
-    for (int i = 0; i < batch; ++i) order[i] = i;
-    std::vector<std::vector<double>> keys(batch);
-    for (int i = 0; i < batch; ++i) keys[i] = group_key(c.m[i]);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return keys[x] < keys[y]; });
-    for (int i : order) layout_member(c.m[i], ar);
-    for (size_t k = 0; k < order.size();) {
-      Ctx::Group G;
-      G.members.push_back(order[k]);
-      size_t j = k + 1;
-      const Member& M0 = c.m[order[k]];
-      int cmax = 0;
-      for (int t = 0; t < M0.n; ++t) cmax = std::max(cmax, M0.dims[t]);
-      if (cmax <= 128) {
-        for (; j < order.size() && keys[order[j]] == keys[order[k]]; ++j) {
-          const Member& A = c.m[order[j - 1]];
-          const Member& B2 = c.m[order[j]];
-          const long long st = (long long)((char*)B2.scal - (char*)A.scal);
-          // the whole layout moves by one stride (same sizes, same alignment)
-          if (st <= 0 || (char*)B2.w64[1] - (char*)A.w64[1] != st || (char*)B2.jinfo - (char*)A.jinfo != st ||
-              (G.members.size() > 1 && st != G.stride))
-            break;
-          G.stride = st;
-          G.members.push_back(order[j]);
+    std::vector<int> order, npad;
+    plan_batch(c.m, order, npad);
+    for (int i : order) layout_member(c.m[i], ar, npad[i]);
+    // the next member is one stride after the previous (the whole layout moves)
+    auto extends = [&](const Ctx::Group& G, int prev, int next) {
+      const Member& A = c.m[prev];
+      const Member& B2 = c.m[next];
+      const long long st = (long long)((char*)B2.scal - (char*)A.scal);
+      if (st <= 0 || (char*)B2.w64[1] - (char*)A.w64[1] != st || (char*)B2.jinfo - (char*)A.jinfo != st ||
+          (G.members.size() > 1 && st != G.stride))
+        return 0LL;
+      return st;
+    };
+    auto build = [&](auto same, std::vector<Ctx::Group>& out) {
+      for (size_t k = 0; k < order.size();) {
+        Ctx::Group G;
+        G.members.push_back(order[k]);
+        size_t j = k + 1;
+        if (member_cmax(c.m[order[k]]) <= 128) {
+          for (; j < order.size() && same(order[j], order[k]); ++j) {
+            const long long st = extends(G, order[j - 1], order[j]);
+            if (!st) break;
+            G.stride = st;
+            G.members.push_back(order[j]);
+          }
         }
+        out.push_back(G);
+        k = j;
       }
-      c.groups.push_back(G);
-      k = j;
-    }
+    };
+    build([&](int x, int y) { return group_key(c.m[x]) == group_key(c.m[y]); }, c.groups);
+    if (batch > 1) build([&](int x, int y) { return coarse_key(c.m[x]) == coarse_key(c.m[y]); }, c.coarse);
   }
   if (batch > 1) {
     Ctx& c = h->c;

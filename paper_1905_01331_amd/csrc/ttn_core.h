@@ -234,7 +234,7 @@ struct ByteCount {
 ttn_status profile_switch(Profiler& P, KernelRecorder& krec, int enable);
 ttn_status profile_collect(Profiler& P, hipStream_t s, ttn_profile_entry* out, int max_entries, int* n_out);
 ttn_status setup_member(const ttn_config& c, Member& M);
-void layout_member(Member& M, Arena& ar);
+void layout_member(Member& M, Arena& ar, int n_pad = 0);
 // one product in the member's arithmetic, timed and byte-counted
 hipError_t run(const Member& M, Prec p, const GemmDesc& g, hipStream_t s, int cls = OC_POLAR_GEMM);
 GemmDesc desc0();

@@ -234,6 +234,32 @@ def test_benchmarked_batch_follows_solo_runs_with_tuner_and_graph(B):
         B.autotune(0)
 
 
+@pytest.mark.parametrize("prec,keep_gauge", [("fp32", False), ("fp64", True)])
+def test_members_of_one_bond_dimension_and_different_lengths(B, prec, keep_gauge):
+    # chains of one chi and five lengths (depths 6 to 10) form one coarse group:
+    # the layer part of a sweep advances them level by level together, the
+    # members at a level a prefix of the group, those whose top is there a
+    # range of it (their top dressing, their gauge rotation into v); each
+    # member's arithmetic is its own, so every member equals its solo run bit
+    # for bit, eager and replayed, with the gauge fixed and kept (warm starts)
+    draws = [(0.8, 256, 32), (1.2, 64, 32), (1.0, 128, 32), (0.6, 64, 32), (1.4, 1024, 32)]
+    mk = lambda i, d: B.ChainInput(I.tfim_chain(d[0]), d[1], d[2], prec, seed=300 + i, keep_gauge=keep_gauge)
+    batch = B.TTN([mk(i, d) for i, d in enumerate(draws)])
+    solo = [B.TTN(mk(i, d)) for i, d in enumerate(draws)]
+    for s in range(4):
+        batch.sweep(1, graph=(s >= 2))
+        for t in solo:
+            t.sweep(1)
+        e_b = batch.energy()
+        e_s = np.array([t.energy()[0] for t in solo])
+        assert np.array_equal(e_b, e_s), (s, e_b, e_s)
+    for i, t in enumerate(solo):
+        for tau in range(1, t.n_levels()):
+            assert np.array_equal(batch.get_tensor(tau, i), t.get_tensor(tau)), (i, tau)
+        t.close()
+    batch.close()
+
+
 def test_launch_groups_match_solo_runs(B):
     # members of equal configuration (L, chi, precision; only h differs) are
     # laid out side by side and run every kernel of a stage as one launch; a
