@@ -1767,9 +1767,60 @@ ttn_status sweep_layers_all(Ctx& c, hipStream_t s) {
   return TTN_OK;
 }
 
-// The top update of every member, eagerly (launch group by launch group);
-// *all is cleared when a member stopped at its restart budget.
+// The top update of a coarse group: the operators prepared and the result
+// finished per length (a member's top operators sit at its own level, its
+// energy divides by its own L), the restarts over the whole group (one top
+// bond dimension, one layout): eagerly with a host check after each (all
+// non-null), or `plan` of them without host reads (capturable).
+ttn_status top_coarse(Ctx& c, const Ctx::Group& G, hipStream_t s, bool* all, int plan = 0) {
+  const int cnt = (int)G.members.size();
+  std::vector<std::pair<int, int>> runs;  // [first, end) of equal depth
+  for (int k = 0; k < cnt;) {
+    int j = k + 1;
+    while (j < cnt && c.m[G.members[j]].n == c.m[G.members[k]].n) ++j;
+    runs.push_back({k, j});
+    k = j;
+  }
+  ttn_status st;
+  for (auto& r : runs) {
+    GroupScope gs(r.second - r.first, G.stride);
+    if ((st = top_prepare(c.m[G.members[r.first]], s))) return st;
+  }
+  Member& B = c.m[G.members[0]];
+  bool conv = false;
+  {
+    GroupScope gs(cnt, G.stride);
+    B.bytes_acc = 0.0;
+    B.counting = true;
+    st = all ? top_restarts(B, s, B.restarts, true, &conv)
+             : top_restarts(B, s, std::min(plan, B.restarts), false, &conv);
+    B.counting = false;
+    if (st) return st;
+  }
+  if (all && !conv) *all = false;
+  for (auto& r : runs) {
+    GroupScope gs(r.second - r.first, G.stride);
+    if ((st = top_finish(c.m[G.members[r.first]], s))) return st;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    Member& M = c.m[G.members[i]];
+    M.bytes_top = B.bytes_acc;
+    M.rho_from = M.pc_from = 1 << 20;
+  }
+  return TTN_OK;
+}
+
+// The top update of every member, eagerly (launch group by launch group, or
+// coarse group by coarse group); *all is cleared when a member stopped at its
+// restart budget.
 ttn_status top_all(Ctx& c, hipStream_t s, bool* all) {
+  if (!c.coarse.empty()) {
+    for (auto& G : c.coarse) {
+      ttn_status st = top_coarse(c, G, s, all);
+      if (st) return st;
+    }
+    return TTN_OK;
+  }
   return for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
     bool conv = false;
     ttn_status r = stage_update_top(M, s, &conv);
@@ -1779,8 +1830,16 @@ ttn_status top_all(Ctx& c, hipStream_t s, bool* all) {
 }
 
 // The top update with `plan` restarts (at most each member's budget)
-// launched without host reads, so that it can be captured into a graph.
+// launched without host reads, so that it can be captured into a graph
+// (coarse group by coarse group when the batch has them).
 ttn_status top_planned(Ctx& c, hipStream_t s, int plan) {
+  if (!c.coarse.empty()) {
+    for (auto& G : c.coarse) {
+      ttn_status st = top_coarse(c, G, s, nullptr, plan);
+      if (st) return st;
+    }
+    return TTN_OK;
+  }
   return for_groups(c, [&](Member& M, const Ctx::Group&) -> ttn_status {
     ByteCount bc(M, M.bytes_top);
     bool conv = false;
