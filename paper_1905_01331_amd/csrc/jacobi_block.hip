@@ -33,12 +33,13 @@ namespace ttn {
 namespace {
 
 constexpr int JC_MAX_WG = 128;
-constexpr long long JC_SPIN_LIMIT = 1LL << 21;  // about a second of polling
+constexpr long long JC_SPIN_LIMIT = 1LL << 21;  // about two seconds of polling
+constexpr int JC_FLAG_STRIDE = 32;              // one 128-byte line per work-group flag
 
 struct JcCtl {
-  unsigned bar;    // barrier arrivals
+  unsigned flag[JC_MAX_WG * JC_FLAG_STRIDE];  // barrier epoch reached by each work-group
   int abort;       // set when a barrier wait exceeded its bound
-  int pad[2];
+  int pad[3];
   int cnt[256];    // rotations per sweep
   int rnd[64];     // rotations per round index, summed over sweeps
   int need[256];   // set when some pair met the rotation test before a sweep
@@ -53,29 +54,41 @@ __device__ __forceinline__ void jc_pair(int nb, int r, int j, int& I, int& J) {
 }
 
 // Grid barrier.  Every thread waits until its own global stores have been
-// acknowledged (vmcnt(0)), the work-group meets, and thread 0 alone
-// publishes at device scope (the agent-scope fence writes this compute
-// unit's side of the L2 back for the other XCDs), counts in, polls, and
-// acquires (the fence invalidates the stale lines of this compute unit)
-// before the work-group meets again.  Returns false after an abort.
-__device__ bool jc_grid_sync(JcCtl* ctl, unsigned& target, int* ok_lds) {
+// acknowledged (vmcnt(0)) and the work-group meets; thread 0 publishes at
+// device scope (the agent-scope fence writes this compute unit's side of the
+// L2 back for the other XCDs) and stores the barrier's epoch in the
+// work-group's own flag.  Each flag has a cache line of its own and is
+// written by one work-group only, so arrivals never queue on one address (a
+// shared arrival counter serialises the grid's atomics: with it a sweep of
+// order 256, 100 work-groups, took a fifth longer).  Thread i < grid then
+// polls flag i, the work-group meets, and thread 0 acquires (the fence
+// invalidates the stale lines of this compute unit) before the work-group
+// meets again.
+// Returns false after an abort.
+__device__ bool jc_grid_sync(JcCtl* ctl, unsigned& epoch, int* ok_lds) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
-  target += gridDim.x;
+  ++epoch;
   if (threadIdx.x == 0) {
     __threadfence();
-    int ok = 1;
-    atomicAdd(&ctl->bar, 1u);
+    __hip_atomic_store(&ctl->flag[blockIdx.x * JC_FLAG_STRIDE], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  int ok = 1;
+  if (threadIdx.x < gridDim.x) {
+    const unsigned* f = &ctl->flag[threadIdx.x * JC_FLAG_STRIDE];
     long long spins = 0;
-    while (__hip_atomic_load(&ctl->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
       if (__hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
       if (++spins > JC_SPIN_LIMIT) {
         atomicExch(&ctl->abort, 1);
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(4);
+      __builtin_amdgcn_s_sleep(1);
     }
+  }
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) {
     __threadfence();
     *ok_lds = ok;
   }
@@ -107,6 +120,7 @@ __device__ __forceinline__ void jc_pq(int st, int k, int& p, int& q) {
 }
 
 constexpr int JC_BS = 32, JC_BK = 16, JC_LD = JC_BS + 1;
+static_assert(JC_MAX_WG <= JC_BK * JC_BK, "every flag of the grid barrier needs a polling thread");
 
 // Wave 0 of phase A: the sequential steps of one round on the 32 x 32
 // sub-problem in Sc (double buffered with Sn).  Lane l computes rotation
@@ -238,7 +252,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   const int ng = npairs * (npairs + 1) / 2;
   const int nchunks = (n + BS - 1) / BS;
   const int nitems = ng + npairs * nchunks;
-  unsigned target = 0;
+  unsigned epoch = 0;
   int sweeps = max_sweeps;
   bool alive = true;
 
@@ -267,7 +281,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
       need = __syncthreads_or(need);
       if (tid == 0 && need) atomicOr(&ctl->need[sw], 1);
     }
-    if (!jc_grid_sync(ctl, target, &ok_lds)) { alive = false; break; }
+    if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
     if (__hip_atomic_load(&ctl->need[sw], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
       sweeps = sw;
       break;
@@ -321,7 +335,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
           So[e] = Sf[i * LD + k];
         }
       }
-      if (!jc_grid_sync(ctl, target, &ok_lds)) { alive = false; break; }
+      if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
       // a round without any rotation has R = I and S' = S: phase B would
       // rewrite G and U unchanged, so every work-group skips it (all read the
       // same count after the barrier)
@@ -420,7 +434,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
           }
         }
       }
-      if (!jc_grid_sync(ctl, target, &ok_lds)) { alive = false; break; }
+      if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
     }
     if (!alive) break;
     // every work-group reads the same final count after the barrier
