@@ -17,14 +17,17 @@
 // iteration ends when no pair meets the rotation test: every pair is tested
 // before a sweep, so the sweep that would rotate nothing is not run.
 //
-// The whole iteration is ONE launch of a persistent grid: its work-groups
-// share phase A (one block pair each) and phase B (one block of G or one
-// panel of U each) and meet at a grid barrier between phases.  The grid
-// never exceeds the number of compute units and a work-group needs far less
-// than one compute unit's resources, so every work-group of the grid is
-// resident at once.  Each barrier wait is bounded: past the bound the
-// kernel raises an abort flag, every work-group leaves at its next barrier,
-// and info[0] = -1 reports the failure to the host.
+// The whole iteration is ONE launch of a persistent grid.  Phase B of a
+// round and phase A of the next run side by side, between two grid
+// barriers: phase B writes the next matrix into a second copy while phase
+// A's work-groups (one block pair each) assemble their sub-problems from the
+// current copy and the previous round's R and S records, with the same
+// arithmetic as phase B's, so the two agree bit for bit and a round costs
+// one barrier.  The grid never exceeds the number of compute units and a
+// work-group needs far less than one compute unit's resources, so every
+// work-group of the grid is resident at once.  Each barrier wait is bounded:
+// past the bound the kernel raises an abort flag, every work-group leaves at
+// its next barrier, and info[0] = -1 reports the failure to the host.
 #include "common.h"
 #include <math.h>
 #include <algorithm>
@@ -44,6 +47,10 @@ struct JcCtl {
   int rnd[64];     // rotations per round index, summed over sweeps
   int need[256];   // set when some pair met the rotation test before a sweep
 };
+
+// Scratch layout: the control block, two slots (round parity) of R and of S
+// records (npairs 32 x 32 each), then the second copy of G.
+constexpr size_t JC_CTL_BYTES = (sizeof(JcCtl) + 255) / 256 * 256;
 
 // Block pair j of round r (rounds 0 .. nb-2: circle method; round nb-1:
 // neighbouring blocks, for the pairs inside each block).
@@ -225,11 +232,59 @@ __device__ void jc_build_r(double* R, const double (*rc)[JC_BK], const double (*
   }
 }
 
+// Phase B's block product of round r for the block pair (x, y), x < y,
+// restricted to rows r0 .. r0 + 15 of pair x and columns c0 .. c0 + 15 of
+// pair y: out = (R_x G[X, Y] R_y^T)[rows, columns], each entry the same
+// chain of fused multiply-adds as phase B's (so the same bits).  Uses L1, L2,
+// L3; the 16 x 16 result is left in L1 at [r][c].
+template <int BS>
+__device__ void jc_cross_block(const double* __restrict__ Gc, int n, const double* __restrict__ Rx,
+                               const double* __restrict__ Ry, const int* gxa, const int* gyb, int r0, int c0,
+                               double* L1, double* L2, double* L3) {
+  constexpr int BK = BS / 2, NT = BK * BK, LD = BS + 1;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < BS * BS; e += NT) {
+    const int i = e / BS, k = e - i * BS;
+    const int gi = gxa[i], gk = gyb[k];
+    L1[i * LD + k] = (gi >= 0 && gk >= 0) ? Gc[(long long)gi * n + gk] : 0.0;
+  }
+  for (int e = tid; e < BK * BS; e += NT) {
+    const int i = e / BS, k = e - i * BS;
+    L2[i * LD + k] = Ry[(c0 + i) * BS + k];  // row c of R_y restricted to the columns kept
+    L3[i * LD + k] = Rx[(r0 + i) * BS + k];  // row r of R_x restricted to the rows kept
+  }
+  __syncthreads();
+  // T[m][c] = sum_m' G[X_m, Y_m'] R_y[c0 + c][m'], m = 0..31, c = 0..15
+  double t[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * NT, m = e / BK, c = e - m * BK;
+    double acc = 0.0;
+    for (int q = 0; q < BS; ++q) acc = fma(L1[m * LD + q], L2[c * LD + q], acc);
+    t[u] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * NT, m = e / BK, c = e - m * BK;
+    L2[m * LD + c] = t[u];  // T, 32 x 16
+  }
+  __syncthreads();
+  {
+    const int r = tid / BK, c = tid - r * BK;
+    double acc = 0.0;
+    for (int m = 0; m < BS; ++m) acc = fma(L3[r * LD + m], L2[m * LD + c], acc);
+    L1[r * LD + c] = acc;
+  }
+  __syncthreads();
+}
+
 template <int BS>
 __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __restrict__ G, double* __restrict__ U,
                                                                    int n, int nb, int max_sweeps, double tol,
                                                                    JcCtl* __restrict__ ctl, double* __restrict__ Rbuf,
-                                                                   double* __restrict__ Sbuf, int* __restrict__ info,
+                                                                   double* __restrict__ Sbuf, double* __restrict__ Galt,
+                                                                   int* __restrict__ info,
                                                                    const int* __restrict__ skip) {
   if (skip && *skip) {
     if (blockIdx.x == 0 && threadIdx.x == 0) { info[0] = 0; info[1] = 0; }
@@ -239,10 +294,11 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   constexpr int NT = BK * BK;  // threads: one 2 x 2 block of S each
   constexpr int LD = BS + 1;
   constexpr int RS = NT / BS;  // row stride of the four outputs per thread in phase B
-  __shared__ double L0[BS * LD], L1[BS * LD], L2[BS * LD];
-  __shared__ int gx[BS], gy[BS];
+  __shared__ double L0[BS * LD], L1[BS * LD], L2[BS * LD], L3[BS * LD];
+  __shared__ int gx[BS], gy[BS], gz[BS];
   __shared__ int ok_lds, rot_lds;
   __shared__ int seen[64];  // rnd[] as read at the previous visit of each round
+  __shared__ int inv[64];   // 2 * pair + half of every block in the previous round
   __shared__ double rc_lds[BK][BK], rs_lds[BK][BK];  // rotations of one round, [step][rotation]
   __shared__ int step_lds;  // last step whose rotations wave 0 has recorded
   static_assert(BS == 32, "the wave split of phase A is written for 32 x 32 sub-problems (four waves)");
@@ -252,6 +308,13 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   const int ng = npairs * (npairs + 1) / 2;
   const int nchunks = (n + BS - 1) / BS;
   const int nitems = ng + npairs * nchunks;
+  const long long rec = (long long)npairs * BS * BS;  // one round's R (or S) records
+  // phase A on work-groups 0 .. npairs - 1, phase B on the others (on all of
+  // them, after phase A, when the grid has no others)
+  const int b0 = (int)gridDim.x > npairs ? npairs : 0;
+  const int bw = (int)blockIdx.x - b0, bstride = (int)gridDim.x - b0;
+  double* Gc = G;     // the matrix as the current epoch starts
+  double* Gn = Galt;  // the other copy, where phase B writes the next one
   unsigned epoch = 0;
   int sweeps = max_sweeps;
   bool alive = true;
@@ -274,8 +337,8 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
       for (long long e = (long long)blockIdx.x * NT + tid; e < nn; e += (long long)gridDim.x * NT) {
         const int i = (int)(e / n), j = (int)(e - (long long)i * n);
         if (j == i) continue;
-        const double gpq = G[e];
-        const double gpp = G[(long long)i * n + i], gqq = G[(long long)j * n + j];
+        const double gpq = Gc[e];
+        const double gpp = Gc[(long long)i * n + i], gqq = Gc[(long long)j * n + j];
         if (gpq != 0.0 && gpq * gpq > tol * tol * fabs(gpp * gqq)) need = 1;
       }
       need = __syncthreads_or(need);
@@ -286,155 +349,225 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
       sweeps = sw;
       break;
     }
-    for (int r = 0; r < nb; ++r) {
-      const bool cross = r < nb - 1;
-      const int nsteps = cross ? BK : BK - 1;
-      // ---------------- phase A: one block pair per work-group ----------------
+    // Epoch q runs phase A of round q and, beside it, phase B of round q - 1
+    // (epoch nb: phase B of the last round alone).  Phase B reads the matrix
+    // as round q - 1 found it (Gc) and writes the next one to Gn; phase A of
+    // round q takes its sub-problem from Gc and the records of round q - 1,
+    // computing exactly the entries phase B writes there, so both agree bit
+    // for bit.  R and S records alternate between two slots by round parity.
+    for (int q = 0; q <= nb; ++q) {
+      // phase B of round q - 1 runs only if that round rotated (every
+      // work-group reads the same count after the barrier)
+      bool rot_b = false;
+      if (q > 0) {
+        const int rv = __hip_atomic_load(&ctl->rnd[q - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rot_b = rv != seen[q - 1];
+        __syncthreads();
+        if (tid == 0) seen[q - 1] = rv;
+      }
+      const double* Rp = Rbuf + ((q - 1) & 1) * rec;  // records of round q - 1
+      const double* Sp = Sbuf + ((q - 1) & 1) * rec;
+      // ---------------- phase A of round q: one block pair per work-group ----------------
       // wave 0 runs the round's steps (jc_wave0) while waves 1 and 2 build R
       // one step behind (jc_build_r): no work-group barrier inside a round
-      for (int j = blockIdx.x; j < npairs; j += gridDim.x) {
-        int I, J;
-        jc_pair(nb, r, j, I, J);
-        __syncthreads();
-        if (tid < BS) gx[tid] = gidx(I, J, tid);
-        if (tid == 0) { rot_lds = 0; step_lds = -1; }
-        __syncthreads();
-        double* Sc = L0;
-        double* Sn = L1;
-        double* R = L2;
-        for (int e = tid; e < BS * BS; e += NT) {
-          int i = e / BS, k = e - i * BS;
-          int gi = gx[i], gk = gx[k];
-          Sc[i * LD + k] = (gi >= 0 && gk >= 0) ? G[(long long)gi * n + gk] : 0.0;
-          R[i * LD + k] = (i == k) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        const int wave = tid >> 6, lane = tid & 63;
-        if (wave == 0) {
-          unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
-          for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gx[i] >= 0) << i;
-          const int rot = cross ? jc_wave0<true>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane)
-                                : jc_wave0<false>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane);
-          if (rot) atomicAdd(&rot_lds, rot);
-        } else if (wave <= 2) {
-          if (cross) jc_build_r<true>(R, rc_lds, rs_lds, &step_lds, wave, lane);
-          else jc_build_r<false>(R, rc_lds, rs_lds, &step_lds, wave, lane);
-        }
-        __syncthreads();
-        // the final S is in the buffer written by the last step
-        const double* Sf = (nsteps & 1) ? L1 : L0;
-        if (tid == 0 && rot_lds) {
-          atomicAdd(&ctl->cnt[sw], rot_lds);
-          atomicAdd(&ctl->rnd[r], rot_lds);
-        }
-        double* Ro = Rbuf + (long long)j * BS * BS;
-        double* So = Sbuf + (long long)j * BS * BS;
-        for (int e = tid; e < BS * BS; e += NT) {
-          int i = e / BS, k = e - i * BS;
-          Ro[e] = R[i * LD + k];
-          So[e] = Sf[i * LD + k];
-        }
-      }
-      if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
-      // a round without any rotation has R = I and S' = S: phase B would
-      // rewrite G and U unchanged, so every work-group skips it (all read the
-      // same count after the barrier)
-      const int rv = __hip_atomic_load(&ctl->rnd[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const bool rotated = rv != seen[r];
-      __syncthreads();
-      if (tid == 0) seen[r] = rv;
-      if (!rotated) continue;
-      // ---------------- phase B: blocks of G and panels of U ----------------
-      for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-        __syncthreads();
-        const int row = tid / BS, col = tid - (tid / BS) * BS;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        if (item < ng) {
-          // (x, y) with x <= y from the packed upper-triangle index
-          int x = 0, rem = item;
-          while (rem >= npairs - x) { rem -= npairs - x; ++x; }
-          const int y = x + rem;
-          int Ix, Jx, Iy, Jy;
-          jc_pair(nb, r, x, Ix, Jx);
-          jc_pair(nb, r, y, Iy, Jy);
-          if (tid < BS) { gx[tid] = gidx(Ix, Jx, tid); gy[tid] = gidx(Iy, Jy, tid); }
+      if (q < nb) {
+        const int r = q;
+        const bool cross = r < nb - 1;
+        const int nsteps = cross ? BK : BK - 1;
+        for (int j = blockIdx.x; j < npairs; j += gridDim.x) {
+          int I, J;
+          jc_pair(nb, r, j, I, J);
           __syncthreads();
-          if (x == y) {
-            const double* Sx = Sbuf + (long long)x * BS * BS;
+          if (tid < BS) gx[tid] = gidx(I, J, tid);
+          if (tid == 0) { rot_lds = 0; step_lds = -1; }
+          if (r > 0 && tid < npairs) {
+            int Ip, Jp;
+            jc_pair(nb, r - 1, tid, Ip, Jp);
+            inv[Ip] = 2 * tid;
+            inv[Jp] = 2 * tid + 1;
+          }
+          __syncthreads();
+          double* Sc = L0;
+          double* Sn = L1;
+          double* R = L2;
+          if (r == 0) {
             for (int e = tid; e < BS * BS; e += NT) {
               int i = e / BS, k = e - i * BS;
               int gi = gx[i], gk = gx[k];
-              if (gi >= 0 && gk >= 0) G[(long long)gi * n + gk] = Sx[e];
+              Sc[i * LD + k] = (gi >= 0 && gk >= 0) ? Gc[(long long)gi * n + gk] : 0.0;
             }
-            continue;
+          } else {
+            // G[I u J, I u J] after round r - 1: the blocks inside one pair
+            // of that round from its S record, the cross block from its R
+            // records and Gc
+            const int c1 = inv[I], c2 = inv[J];
+            const int x1 = c1 >> 1, h1 = c1 & 1, x2 = c2 >> 1, h2 = c2 & 1;
+            const double* S1 = Sp + (long long)x1 * BS * BS;
+            const double* S2 = Sp + (long long)x2 * BS * BS;
+            for (int e = tid; e < BK * BK; e += NT) {
+              const int i = e / BK, k = e - i * BK;
+              Sc[i * LD + k] = S1[(h1 * BK + i) * BS + h1 * BK + k];
+              Sc[(BK + i) * LD + BK + k] = S2[(h2 * BK + i) * BS + h2 * BK + k];
+              if (x1 == x2) {
+                Sc[i * LD + BK + k] = S1[(h1 * BK + i) * BS + h2 * BK + k];
+                Sc[(BK + i) * LD + k] = S1[(h2 * BK + i) * BS + h1 * BK + k];
+              }
+            }
+            if (x1 != x2) {
+              // phase B computes the block of the pair with the lower index
+              const int xa = x1 < x2 ? x1 : x2, xb = x1 < x2 ? x2 : x1;
+              const int ha = x1 < x2 ? h1 : h2, hb = x1 < x2 ? h2 : h1;
+              int Ia, Ja, Ib, Jb;
+              jc_pair(nb, r - 1, xa, Ia, Ja);
+              jc_pair(nb, r - 1, xb, Ib, Jb);
+              if (tid < BS) { gy[tid] = gidx(Ia, Ja, tid); gz[tid] = gidx(Ib, Jb, tid); }
+              __syncthreads();
+              jc_cross_block<BS>(Gc, n, Rp + (long long)xa * BS * BS, Rp + (long long)xb * BS * BS, gy, gz,
+                                 ha * BK, hb * BK, L1, L2, L3);
+              for (int e = tid; e < BK * BK; e += NT) {
+                const int i = e / BK, k = e - i * BK;
+                const double v = L1[i * LD + k];
+                if (x1 < x2) { Sc[i * LD + BK + k] = v; Sc[(BK + k) * LD + i] = v; }
+                else { Sc[(BK + i) * LD + k] = v; Sc[k * LD + BK + i] = v; }
+              }
+            }
+            __syncthreads();
+            // entries of padding indices read as zero, as from G
+            for (int e = tid; e < BS * BS; e += NT) {
+              const int i = e / BS, k = e - i * BS;
+              if (gx[i] < 0 || gx[k] < 0) Sc[i * LD + k] = 0.0;
+            }
           }
-          const double* Rx = Rbuf + (long long)x * BS * BS;
-          const double* Ry = Rbuf + (long long)y * BS * BS;
+          __syncthreads();
           for (int e = tid; e < BS * BS; e += NT) {
             int i = e / BS, k = e - i * BS;
-            int gi = gx[i], gk = gy[k];
-            L0[i * LD + k] = (gi >= 0 && gk >= 0) ? G[(long long)gi * n + gk] : 0.0;
-            L1[i * LD + k] = Rx[e];
-            L2[k * LD + i] = Ry[e];  // transposed: L2[m][k] = R_y[k][m]
+            R[i * LD + k] = (i == k) ? 1.0 : 0.0;
           }
           __syncthreads();
-          // T = G[X,Y] R_y^T, four outputs per thread (rows row + RS u, column col)
-          for (int m = 0; m < BS; ++m) {
-            double ry = L2[m * LD + col];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma(L0[(row + u * RS) * LD + m], ry, acc[u]);
+          const int wave = tid >> 6, lane = tid & 63;
+          if (wave == 0) {
+            unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
+            for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gx[i] >= 0) << i;
+            const int rot = cross ? jc_wave0<true>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane)
+                                  : jc_wave0<false>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane);
+            if (rot) atomicAdd(&rot_lds, rot);
+          } else if (wave <= 2) {
+            if (cross) jc_build_r<true>(R, rc_lds, rs_lds, &step_lds, wave, lane);
+            else jc_build_r<false>(R, rc_lds, rs_lds, &step_lds, wave, lane);
           }
           __syncthreads();
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            L0[(row + u * RS) * LD + col] = acc[u];
-            acc[u] = 0.0;
+          // the final S is in the buffer written by the last step
+          const double* Sf = (nsteps & 1) ? L1 : L0;
+          if (tid == 0 && rot_lds) {
+            atomicAdd(&ctl->cnt[sw], rot_lds);
+            atomicAdd(&ctl->rnd[r], rot_lds);
           }
-          __syncthreads();
-          // out = R_x T
-          for (int m = 0; m < BS; ++m) {
-            double tv = L0[m * LD + col];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma(L1[(row + u * RS) * LD + m], tv, acc[u]);
-          }
-          const int gk = gy[col];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int gi = gx[row + u * RS];
-            if (gi >= 0 && gk >= 0) {
-              G[(long long)gi * n + gk] = acc[u];
-              G[(long long)gk * n + gi] = acc[u];
-            }
-          }
-        } else {
-          const int it = item - ng;
-          const int x = it / nchunks, c0 = (it - x * nchunks) * BS;
-          int Ix, Jx;
-          jc_pair(nb, r, x, Ix, Jx);
-          if (tid < BS) gx[tid] = gidx(Ix, Jx, tid);
-          __syncthreads();
-          const double* Rx = Rbuf + (long long)x * BS * BS;
+          double* Ro = Rbuf + (r & 1) * rec + (long long)j * BS * BS;
+          double* So = Sbuf + (r & 1) * rec + (long long)j * BS * BS;
           for (int e = tid; e < BS * BS; e += NT) {
             int i = e / BS, k = e - i * BS;
-            int gi = gx[i], gc = c0 + k;
-            L0[i * LD + k] = (gi >= 0 && gc < n) ? U[(long long)gi * n + gc] : 0.0;
-            L1[i * LD + k] = Rx[e];
-          }
-          __syncthreads();
-          for (int m = 0; m < BS; ++m) {
-            double uv = L0[m * LD + col];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma(L1[(row + u * RS) * LD + m], uv, acc[u]);
-          }
-          const int gc = c0 + col;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int gi = gx[row + u * RS];
-            if (gi >= 0 && gc < n) U[(long long)gi * n + gc] = acc[u];
+            Ro[e] = R[i * LD + k];
+            So[e] = Sf[i * LD + k];
           }
         }
       }
-      if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
+      // ---------------- phase B of round q - 1: blocks of G and panels of U ----------------
+      if (rot_b && bw >= 0) {
+        const int r = q - 1;
+        for (int item = bw; item < nitems; item += bstride) {
+          __syncthreads();
+          const int row = tid / BS, col = tid - (tid / BS) * BS;
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          if (item < ng) {
+            // (x, y) with x <= y from the packed upper-triangle index
+            int x = 0, rem = item;
+            while (rem >= npairs - x) { rem -= npairs - x; ++x; }
+            const int y = x + rem;
+            int Ix, Jx, Iy, Jy;
+            jc_pair(nb, r, x, Ix, Jx);
+            jc_pair(nb, r, y, Iy, Jy);
+            if (tid < BS) { gx[tid] = gidx(Ix, Jx, tid); gy[tid] = gidx(Iy, Jy, tid); }
+            __syncthreads();
+            if (x == y) {
+              const double* Sx = Sp + (long long)x * BS * BS;
+              for (int e = tid; e < BS * BS; e += NT) {
+                int i = e / BS, k = e - i * BS;
+                int gi = gx[i], gk = gx[k];
+                if (gi >= 0 && gk >= 0) Gn[(long long)gi * n + gk] = Sx[e];
+              }
+              continue;
+            }
+            const double* Rx = Rp + (long long)x * BS * BS;
+            const double* Ry = Rp + (long long)y * BS * BS;
+            for (int e = tid; e < BS * BS; e += NT) {
+              int i = e / BS, k = e - i * BS;
+              int gi = gx[i], gk = gy[k];
+              L0[i * LD + k] = (gi >= 0 && gk >= 0) ? Gc[(long long)gi * n + gk] : 0.0;
+              L1[i * LD + k] = Rx[e];
+              L2[k * LD + i] = Ry[e];  // transposed: L2[m][k] = R_y[k][m]
+            }
+            __syncthreads();
+            // T = G[X,Y] R_y^T, four outputs per thread (rows row + RS u, column col)
+            for (int m = 0; m < BS; ++m) {
+              double ry = L2[m * LD + col];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[u] = fma(L0[(row + u * RS) * LD + m], ry, acc[u]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              L0[(row + u * RS) * LD + col] = acc[u];
+              acc[u] = 0.0;
+            }
+            __syncthreads();
+            // out = R_x T
+            for (int m = 0; m < BS; ++m) {
+              double tv = L0[m * LD + col];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[u] = fma(L1[(row + u * RS) * LD + m], tv, acc[u]);
+            }
+            const int gk = gy[col];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int gi = gx[row + u * RS];
+              if (gi >= 0 && gk >= 0) {
+                Gn[(long long)gi * n + gk] = acc[u];
+                Gn[(long long)gk * n + gi] = acc[u];
+              }
+            }
+          } else {
+            const int it = item - ng;
+            const int x = it / nchunks, c0 = (it - x * nchunks) * BS;
+            int Ix, Jx;
+            jc_pair(nb, r, x, Ix, Jx);
+            if (tid < BS) gx[tid] = gidx(Ix, Jx, tid);
+            __syncthreads();
+            const double* Rx = Rp + (long long)x * BS * BS;
+            for (int e = tid; e < BS * BS; e += NT) {
+              int i = e / BS, k = e - i * BS;
+              int gi = gx[i], gc = c0 + k;
+              L0[i * LD + k] = (gi >= 0 && gc < n) ? U[(long long)gi * n + gc] : 0.0;
+              L1[i * LD + k] = Rx[e];
+            }
+            __syncthreads();
+            for (int m = 0; m < BS; ++m) {
+              double uv = L0[m * LD + col];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc[u] = fma(L1[(row + u * RS) * LD + m], uv, acc[u]);
+            }
+            const int gc = c0 + col;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int gi = gx[row + u * RS];
+              if (gi >= 0 && gc < n) U[(long long)gi * n + gc] = acc[u];
+            }
+          }
+        }
+      }
+      if (q < nb || rot_b) {
+        if (!jc_grid_sync(ctl, epoch, &ok_lds)) { alive = false; break; }
+      }
+      if (rot_b) { double* t = Gc; Gc = Gn; Gn = t; }
     }
     if (!alive) break;
     // every work-group reads the same final count after the barrier
@@ -442,6 +575,12 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
       sweeps = sw;
       break;
     }
+  }
+  // the result goes back to the caller's matrix (every write to Gc is behind
+  // the last barrier)
+  if (Gc != G) {
+    for (long long e = (long long)blockIdx.x * NT + tid; e < (long long)n * n; e += (long long)gridDim.x * NT)
+      G[e] = Gc[e];
   }
   if (blockIdx.x == 0 && tid == 0) {
     info[0] = alive ? sweeps : -1;
@@ -478,7 +617,7 @@ int jc_compute_units() {
 size_t jacobi_blocked_scratch_bytes(int n) {
   int nb = (n + JC_BS / 2 - 1) / (JC_BS / 2);
   nb += nb & 1;
-  return (size_t)2 * (nb / 2) * JC_BS * JC_BS * sizeof(double) + sizeof(JcCtl) + 256;
+  return JC_CTL_BYTES + ((size_t)4 * (nb / 2) * JC_BS * JC_BS + (size_t)n * n) * sizeof(double);
 }
 
 hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, double tol, int* info, void* scratch,
@@ -491,17 +630,19 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
   if (nb > 64) return hipErrorInvalidValue;  // per-round counters hold 64 rounds (n <= 1024)
   const int npairs = nb / 2;
   max_sweeps = std::min(std::max(max_sweeps, 1), 256);
-  double* Rbuf = (double*)scratch;
-  double* Sbuf = Rbuf + (size_t)npairs * BS * BS;
-  JcCtl* ctl = (JcCtl*)(Sbuf + (size_t)npairs * BS * BS);
+  JcCtl* ctl = (JcCtl*)scratch;
+  double* Rbuf = (double*)((char*)scratch + JC_CTL_BYTES);
+  double* Sbuf = Rbuf + (size_t)2 * npairs * BS * BS;
+  double* Galt = Sbuf + (size_t)2 * npairs * BS * BS;
   const int nchunks = (n + BS - 1) / BS;
   const int nitems = npairs * (npairs + 1) / 2 + npairs * nchunks;
   const int cus = jc_compute_units();
   if (cus <= 0) return hipErrorInvalidDevice;
-  const int grid = std::max(1, std::min({std::max(npairs, nitems), JC_MAX_WG, cus}));
+  // phase A's work-groups beside phase B's, as far as the compute units go
+  const int grid = std::max(1, std::min({npairs + nitems, JC_MAX_WG, cus}));
   hipLaunchKernelGGL(k_jc_init, dim3(64), dim3(256), 0, s, U, n, ctl, skip);
   hipLaunchKernelGGL(k_jacobi_coop<BS>, dim3(grid), dim3(BK * BK), 0, s, G, U, n, nb, max_sweeps, tol, ctl, Rbuf,
-                     Sbuf, info, skip);
+                     Sbuf, Galt, info, skip);
   return hipGetLastError();
 }
 
