@@ -129,107 +129,64 @@ __device__ __forceinline__ void jc_pq(int st, int k, int& p, int& q) {
 constexpr int JC_BS = 32, JC_BK = 16, JC_LD = JC_BS + 1;
 static_assert(JC_MAX_WG <= JC_BK * JC_BK, "every flag of the grid barrier needs a polling thread");
 
-// Wave 0 of phase A: the sequential steps of one round on the 32 x 32
-// sub-problem in Sc (double buffered with Sn).  Lane l computes rotation
-// l % 16, the others read it by lane shuffles; each lane updates four 2 x 2
-// blocks.  The rotations of step st go to rc[st][k], rs[st][k], and step_lds
-// is raised to st once they are written.  Returns the lane's count of
-// rotations made.
+// Phase A's steps of one round on the 32 x 32 sub-problem in Sc (double
+// buffered with Sn), all four waves of the work-group in lockstep, one
+// work-group barrier per step.  Every lane computes rotation lane % 16 of
+// the step (its wave reads the others by lane shuffles); thread t updates
+// the 2 x 2 block of row pair (t % 64) / 4 and column pair t % 4 + 4 (t / 64)
+// of S, and rows p, q of R (R <- J R) for rotation t % 16 in columns t / 16
+// and t / 16 + 16.  The rotations of one step touch disjoint index pairs, so
+// these updates are independent.  Returns the rotations made (counted by
+// lanes 0..15 of wave 0).
 template <bool CROSS>
-__device__ int jc_wave0(double* Sc, double* Sn, unsigned long long vmask, double tol, double (*rc)[JC_BK],
-                        double (*rs)[JC_BK], int* step_lds, int lane) {
-  constexpr int BK = JC_BK, LD = JC_LD, NB = BK * BK / 64, NS = CROSS ? BK : BK - 1;
-  const int kr = lane % BK;         // rotation computed by this lane
-  const int k1 = lane / (64 / BK);  // row pair of this lane's blocks
-  const int k2b = lane % (64 / BK); // first column pair; then + 64/BK ...
+__device__ int jc_round(double* Sc, double* Sn, double* R, unsigned long long vmask, double tol) {
+  constexpr int BK = JC_BK, LD = JC_LD, NS = CROSS ? BK : BK - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kr = lane % BK;                      // rotation computed by this lane (and this thread's R rows)
+  const int k1 = lane / (64 / BK);               // row pair of this thread's block of S
+  const int k2 = lane % (64 / BK) + 4 * wave;    // its column pair
+  const int col = tid / BK;                      // its columns of R: col, col + 16
   int rot = 0;
   for (int rr = 0; rr < NS; ++rr) {
-    int pr, qr, p1, q1, p2[NB], q2[NB];
+    int pr, qr, p1, q1, p2, q2;
     jc_pq<CROSS>(rr, kr, pr, qr);
     jc_pq<CROSS>(rr, k1, p1, q1);
-#pragma unroll
-    for (int u = 0; u < NB; ++u) jc_pq<CROSS>(rr, k2b + u * (64 / BK), p2[u], q2[u]);
+    jc_pq<CROSS>(rr, k2, p2, q2);
     // every LDS read of the step first, then the arithmetic
     const double app = Sc[pr * LD + pr], aqq = Sc[qr * LD + qr], apq = Sc[pr * LD + qr];
-    double bpp[NB], bpq[NB], bqp[NB], bqq[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      bpp[u] = Sc[p1 * LD + p2[u]]; bpq[u] = Sc[p1 * LD + q2[u]];
-      bqp[u] = Sc[q1 * LD + p2[u]]; bqq[u] = Sc[q1 * LD + q2[u]];
-    }
+    const double gpp = Sc[p1 * LD + p2], gpq = Sc[p1 * LD + q2];
+    const double gqp = Sc[q1 * LD + p2], gqq = Sc[q1 * LD + q2];
+    const double up0 = R[pr * LD + col], uq0 = R[qr * LD + col];
+    const double up1 = R[pr * LD + col + BK], uq1 = R[qr * LD + col + BK];
     const bool real = (vmask >> pr) & (vmask >> qr) & 1ull;
     double c, sn, t;
     const bool did = jacobi_rotation(app, aqq, real ? apq : 0.0, tol, c, sn, t);
-    if (lane < BK) {
-      rc[rr][lane] = c;
-      rs[rr][lane] = sn;
-      rot += did ? 1 : 0;
-    }
+    if (wave == 0 && lane < BK) rot += did ? 1 : 0;
     const double c1 = __shfl(c, k1), s1 = __shfl(sn, k1), t1 = __shfl(t, k1);
-    double c2[NB], s2[NB];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      c2[u] = __shfl(c, k2b + u * (64 / BK));
-      s2[u] = __shfl(sn, k2b + u * (64 / BK));
+    const double c2 = __shfl(c, k2), s2 = __shfl(sn, k2);
+    double npp, npq, nqp, nqq;
+    if (k1 == k2 && s1 != 0.0) {
+      // the rotated pair itself: exact annihilation, Rutishauser's diagonal update
+      npp = gpp - t1 * gpq;
+      nqq = gqq + t1 * gpq;
+      npq = 0.0;
+      nqp = 0.0;
+    } else {
+      double rp_p = c1 * gpp - s1 * gqp, rp_q = c1 * gpq - s1 * gqq;
+      double rq_p = s1 * gpp + c1 * gqp, rq_q = s1 * gpq + c1 * gqq;
+      npp = c2 * rp_p - s2 * rp_q; npq = s2 * rp_p + c2 * rp_q;
+      nqp = c2 * rq_p - s2 * rq_q; nqq = s2 * rq_p + c2 * rq_q;
     }
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const double gpp = bpp[u], gpq = bpq[u], gqp = bqp[u], gqq = bqq[u];
-      double npp, npq, nqp, nqq;
-      if (k1 == k2b + u * (64 / BK) && s1 != 0.0) {
-        npp = gpp - t1 * gpq;
-        nqq = gqq + t1 * gpq;
-        npq = 0.0;
-        nqp = 0.0;
-      } else {
-        double rp_p = c1 * gpp - s1 * gqp, rp_q = c1 * gpq - s1 * gqq;
-        double rq_p = s1 * gpp + c1 * gqp, rq_q = s1 * gpq + c1 * gqq;
-        npp = c2[u] * rp_p - s2[u] * rp_q; npq = s2[u] * rp_p + c2[u] * rp_q;
-        nqp = c2[u] * rq_p - s2[u] * rq_q; nqq = s2[u] * rq_p + c2[u] * rq_q;
-      }
-      Sn[p1 * LD + p2[u]] = npp; Sn[p1 * LD + q2[u]] = npq;
-      Sn[q1 * LD + p2[u]] = nqp; Sn[q1 * LD + q2[u]] = nqq;
-    }
-    // publish the record of step rr to the waves that accumulate R
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0) __hip_atomic_store(step_lds, rr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    // one wave: LDS operations complete in order; keep the compiler from
-    // moving the next step's reads above these writes
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    Sn[p1 * LD + p2] = npp; Sn[p1 * LD + q2] = npq;
+    Sn[q1 * LD + p2] = nqp; Sn[q1 * LD + q2] = nqq;
+    R[pr * LD + col] = c * up0 - sn * uq0;
+    R[qr * LD + col] = sn * up0 + c * uq0;
+    R[pr * LD + col + BK] = c * up1 - sn * uq1;
+    R[qr * LD + col + BK] = sn * up1 + c * uq1;
+    __syncthreads();
     double* tp = Sc; Sc = Sn; Sn = tp;
   }
   return rot;
-}
-
-// Waves 1 and 2 of phase A: R = J_last ... J_0 (rows rotated), one step
-// behind wave 0.  Wave w owns columns 16 (w - 1) .. 16 w - 1; lane l works on
-// column 16 (w - 1) + l % 16 with rotations l / 16 + 4 u, u = 0..3 (the
-// rotations of one step touch disjoint rows, and a column is one wave's).
-template <bool CROSS>
-__device__ void jc_build_r(double* R, const double (*rc)[JC_BK], const double (*rs)[JC_BK], const int* step_lds,
-                           int wave, int lane) {
-  constexpr int LD = JC_LD, NS = CROSS ? JC_BK : JC_BK - 1;
-  const int col = (wave - 1) * 16 + (lane & 15);
-  const int kb = lane >> 4;
-  for (int rr = 0; rr < NS; ++rr) {
-    // wave 0 always completes its steps, so this wait ends
-    while (__hip_atomic_load(step_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < rr)
-      __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = kb + 4 * u;
-      int p, q;
-      jc_pq<CROSS>(rr, k, p, q);
-      const double c = rc[rr][k], sn = rs[rr][k];
-      const double up = R[p * LD + col], uq = R[q * LD + col];
-      R[p * LD + col] = c * up - sn * uq;
-      R[q * LD + col] = sn * up + c * uq;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  }
 }
 
 // Phase B's block product of round r for the block pair (x, y), x < y,
@@ -299,8 +256,6 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   __shared__ int ok_lds, rot_lds;
   __shared__ int seen[64];  // rnd[] as read at the previous visit of each round
   __shared__ int inv[64];   // 2 * pair + half of every block in the previous round
-  __shared__ double rc_lds[BK][BK], rs_lds[BK][BK];  // rotations of one round, [step][rotation]
-  __shared__ int step_lds;  // last step whose rotations wave 0 has recorded
   static_assert(BS == 32, "the wave split of phase A is written for 32 x 32 sub-problems (four waves)");
   if (threadIdx.x < 64) seen[threadIdx.x] = 0;
   const int tid = threadIdx.x;
@@ -368,8 +323,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
       const double* Rp = Rbuf + ((q - 1) & 1) * rec;  // records of round q - 1
       const double* Sp = Sbuf + ((q - 1) & 1) * rec;
       // ---------------- phase A of round q: one block pair per work-group ----------------
-      // wave 0 runs the round's steps (jc_wave0) while waves 1 and 2 build R
-      // one step behind (jc_build_r): no work-group barrier inside a round
+      // the four waves run the round's steps together (jc_round)
       if (q < nb) {
         const int r = q;
         const bool cross = r < nb - 1;
@@ -379,7 +333,7 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
           jc_pair(nb, r, j, I, J);
           __syncthreads();
           if (tid < BS) gx[tid] = gidx(I, J, tid);
-          if (tid == 0) { rot_lds = 0; step_lds = -1; }
+          if (tid == 0) rot_lds = 0;
           if (r > 0 && tid < npairs) {
             int Ip, Jp;
             jc_pair(nb, r - 1, tid, Ip, Jp);
@@ -444,16 +398,11 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
             R[i * LD + k] = (i == k) ? 1.0 : 0.0;
           }
           __syncthreads();
-          const int wave = tid >> 6, lane = tid & 63;
-          if (wave == 0) {
+          {
             unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
             for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gx[i] >= 0) << i;
-            const int rot = cross ? jc_wave0<true>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane)
-                                  : jc_wave0<false>(Sc, Sn, vmask, tol, rc_lds, rs_lds, &step_lds, lane);
+            const int rot = cross ? jc_round<true>(Sc, Sn, R, vmask, tol) : jc_round<false>(Sc, Sn, R, vmask, tol);
             if (rot) atomicAdd(&rot_lds, rot);
-          } else if (wave <= 2) {
-            if (cross) jc_build_r<true>(R, rc_lds, rs_lds, &step_lds, wave, lane);
-            else jc_build_r<false>(R, rc_lds, rs_lds, &step_lds, wave, lane);
           }
           __syncthreads();
           // the final S is in the buffer written by the last step
