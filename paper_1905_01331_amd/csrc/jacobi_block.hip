@@ -29,6 +29,7 @@
 // past the bound the kernel raises an abort flag, every work-group leaves at
 // its next barrier, and info[0] = -1 reports the failure to the host.
 #include "common.h"
+#include "jacobi.h"
 #include <math.h>
 #include <algorithm>
 
@@ -138,16 +139,24 @@ static_assert(JC_MAX_WG <= JC_BK * JC_BK, "every flag of the grid barrier needs 
 // and t / 16 + 16.  The rotations of one step touch disjoint index pairs, so
 // these updates are independent.  Returns the rotations made (counted by
 // lanes 0..15 of wave 0).
+// lt: the thread's index among the 256 that share the sub-problem; threads
+// with `active` false (a work-group running fewer sub-problems than it has
+// thread groups) only meet the barriers.
 template <bool CROSS>
-__device__ int jc_round(double* Sc, double* Sn, double* R, unsigned long long vmask, double tol) {
+__device__ int jc_round(double* Sc, double* Sn, double* R, unsigned long long vmask, double tol, int lt,
+                        bool active) {
   constexpr int BK = JC_BK, LD = JC_LD, NS = CROSS ? BK : BK - 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = lt, lane = tid & 63, wave = tid >> 6;
   const int kr = lane % BK;                      // rotation computed by this lane (and this thread's R rows)
   const int k1 = lane / (64 / BK);               // row pair of this thread's block of S
   const int k2 = lane % (64 / BK) + 4 * wave;    // its column pair
   const int col = tid / BK;                      // its columns of R: col, col + 16
   int rot = 0;
   for (int rr = 0; rr < NS; ++rr) {
+    if (!active) {
+      __syncthreads();
+      continue;
+    }
     int pr, qr, p1, q1, p2, q2;
     jc_pq<CROSS>(rr, kr, pr, qr);
     jc_pq<CROSS>(rr, k1, p1, q1);
@@ -401,7 +410,8 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
           {
             unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
             for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gx[i] >= 0) << i;
-            const int rot = cross ? jc_round<true>(Sc, Sn, R, vmask, tol) : jc_round<false>(Sc, Sn, R, vmask, tol);
+            const int rot = cross ? jc_round<true>(Sc, Sn, R, vmask, tol, tid, true)
+                                  : jc_round<false>(Sc, Sn, R, vmask, tol, tid, true);
             if (rot) atomicAdd(&rot_lds, rot);
           }
           __syncthreads();
@@ -537,6 +547,209 @@ __global__ __launch_bounds__((BS / 2) * (BS / 2)) void k_jacobi_coop(double* __r
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// The same blocked method inside ONE work-group (1024 threads), for orders
+// 32 < n <= 96: G (padded to nb blocks of 16) in LDS, the eigenvector matrix
+// in global memory.  Each of the round's block pairs (at most three) is
+// rotated by a group of 256 threads (jc_round), then the whole work-group
+// updates the blocks of G between two pairs and the rows of U in 32 x 32
+// products, four at a time, with work-group barriers in place of the grid
+// barriers.  One work-group per problem, so a launch group's members run side
+// by side in one launch (blockIdx.y = member).
+// ---------------------------------------------------------------------------
+constexpr int JL_THREADS = 1024;
+constexpr int JL_MAXP = 3;  // block pairs of one round (n <= 96)
+
+__global__ __launch_bounds__(JL_THREADS) void k_jacobi_lds(double* __restrict__ Gg, double* __restrict__ Ug, int n,
+                                                          int max_sweeps, double tol, int* __restrict__ info,
+                                                          const int* __restrict__ skip, long long ms_) {
+  Gg = mshift(Gg, ms_); Ug = mshift(Ug, ms_); info = mshift(info, ms_); skip = mshift(skip, ms_);
+  if (skip && *skip) {
+    if (threadIdx.x == 0 && info) { info[0] = 0; info[1] = 0; }
+    return;
+  }
+  constexpr int BS = JC_BS, BK = JC_BK, LD = JC_LD, SUB = BS * LD, RS = 256 / BS;
+  extern __shared__ double dyn[];
+  __shared__ int gxs[4][BS], gys[4][BS];
+  __shared__ int rot_l, cnt_l;
+  int nb = (n + BK - 1) / BK;
+  nb += nb & 1;
+  const int np = nb * BK, LG = np + 1, npairs = nb / 2;
+  double* G = dyn;                       // np x np, row stride LG; padding rows and columns stay zero
+  double* P = G + (size_t)np * LG;       // pair p: S, S', R (SUB doubles each)
+  const int tid = threadIdx.x, grp = tid >> 8, lt = tid & 255;
+  for (int e = tid; e < np * np; e += JL_THREADS) {
+    const int i = e / np, k = e - i * np;
+    G[i * LG + k] = (i < n && k < n) ? Gg[(long long)i * n + k] : 0.0;
+  }
+  for (int e = tid; e < n * n; e += JL_THREADS) Ug[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  // phase B's thread groups each use a free S buffer of the pairs as scratch
+  const int slots = 2 * npairs < 4 ? 2 * npairs : 4;
+  const int ngi = npairs * (npairs - 1) / 2;  // blocks between two pairs (x < y)
+  const int nch = (n + BS - 1) / BS;
+  const int nitems = ngi + npairs * nch;
+  int sweep = 0, first_rot = -1;
+  for (; sweep < max_sweeps; ++sweep) {
+    // the sweep that would rotate nothing is not run (as in the grid solver)
+    int need = 0;
+    for (int e = tid; e < n * n; e += JL_THREADS) {
+      const int i = e / n, j = e - i * n;
+      if (j == i) continue;
+      const double gpq = G[i * LG + j], gpp = G[i * LG + i], gqq = G[j * LG + j];
+      if (gpq != 0.0 && gpq * gpq > tol * tol * fabs(gpp * gqq)) need = 1;
+    }
+    if (!__syncthreads_or(need)) break;
+    if (tid == 0) cnt_l = 0;
+    for (int r = 0; r < nb; ++r) {
+      const bool cross = r < nb - 1;
+      const int nsteps = cross ? BK : BK - 1;
+      // ---- phase A: thread group p rotates block pair p ----
+      const bool act = grp < npairs;
+      double* Sc = P + (size_t)(act ? grp : 0) * 3 * SUB;
+      double* Sn = Sc + SUB;
+      double* R = Sn + SUB;
+      if (act && lt < BS) {
+        int I, J;
+        jc_pair(nb, r, grp, I, J);
+        gxs[grp][lt] = lt < BK ? I * BK + lt : J * BK + (lt - BK);
+      }
+      if (tid == 0) rot_l = 0;
+      __syncthreads();
+      if (act) {
+        for (int e = lt; e < BS * BS; e += 256) {
+          const int i = e / BS, k = e - i * BS;
+          Sc[i * LD + k] = G[gxs[grp][i] * LG + gxs[grp][k]];
+          R[i * LD + k] = (i == k) ? 1.0 : 0.0;
+        }
+      }
+      __syncthreads();
+      unsigned long long vmask = 0;  // bit i: index i of the sub-problem is real
+      if (act)
+        for (int i = 0; i < BS; ++i) vmask |= (unsigned long long)(gxs[grp][i] < n) << i;
+      const int rot = cross ? jc_round<true>(Sc, Sn, R, vmask, tol, lt, act)
+                            : jc_round<false>(Sc, Sn, R, vmask, tol, lt, act);
+      if (rot) atomicAdd(&rot_l, rot);
+      __syncthreads();
+      if (act) {
+        // the rotated sub-problem back into its diagonal block of G
+        const double* Sf = (nsteps & 1) ? Sn : Sc;
+        for (int e = lt; e < BS * BS; e += 256) {
+          const int i = e / BS, k = e - i * BS;
+          G[gxs[grp][i] * LG + gxs[grp][k]] = Sf[i * LD + k];
+        }
+      }
+      __syncthreads();
+      const int rl = rot_l;
+      if (tid == 0) cnt_l += rl;
+      if (rl == 0) continue;  // R = I for every pair: nothing else changes
+      // ---- phase B: G blocks between two pairs, then rows of U ----
+      for (int it = 0; it * slots < nitems; ++it) {
+        const int item = it * slots + grp;
+        const bool valid = grp < slots && item < nitems;
+        const bool gitem = valid && item < ngi;
+        double* T = P + (size_t)(grp >> 1) * 3 * SUB + (grp & 1) * SUB;  // an S buffer, free now
+        int x = 0, y = 0, c0 = 0;
+        if (valid) {
+          if (gitem) {
+            int rem = item;
+            while (rem >= npairs - 1 - x) { rem -= npairs - 1 - x; ++x; }
+            y = x + 1 + rem;
+          } else {
+            x = (item - ngi) / nch;
+            c0 = ((item - ngi) % nch) * BS;
+          }
+          if (lt < BS) {
+            int I, J;
+            jc_pair(nb, r, x, I, J);
+            gxs[grp][lt] = lt < BK ? I * BK + lt : J * BK + (lt - BK);
+            if (gitem) {
+              jc_pair(nb, r, y, I, J);
+              gys[grp][lt] = lt < BK ? I * BK + lt : J * BK + (lt - BK);
+            }
+          }
+        }
+        __syncthreads();
+        const double* Rx = P + (size_t)x * 3 * SUB + 2 * SUB;
+        const double* Ry = P + (size_t)y * 3 * SUB + 2 * SUB;
+        const int row = lt / BS, col = lt - (lt / BS) * BS;
+        if (valid) {
+          for (int e = lt; e < BS * BS; e += 256) {
+            const int i = e / BS, k = e - i * BS;
+            if (gitem) {
+              T[i * LD + k] = G[gxs[grp][i] * LG + gys[grp][k]];
+            } else {
+              const int gi = gxs[grp][i], gc = c0 + k;
+              T[i * LD + k] = (gi < n && gc < n) ? Ug[(long long)gi * n + gc] : 0.0;
+            }
+          }
+        }
+        __syncthreads();
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (gitem) {
+          // G[X,Y] R_y^T
+          for (int m = 0; m < BS; ++m) {
+            const double ry = Ry[col * LD + m];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(T[(row + u * RS) * LD + m], ry, acc[u]);
+          }
+        } else if (valid) {
+          // R_x U[X, c0 ..]
+          for (int m = 0; m < BS; ++m) {
+            const double uv = T[m * LD + col];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(Rx[(row + u * RS) * LD + m], uv, acc[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int gi = gxs[grp][row + u * RS], gc = c0 + col;
+            if (gi < n && gc < n) Ug[(long long)gi * n + gc] = acc[u];
+          }
+        }
+        __syncthreads();
+        if (gitem) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            T[(row + u * RS) * LD + col] = acc[u];
+            acc[u] = 0.0;
+          }
+        }
+        __syncthreads();
+        if (gitem) {
+          // R_x (G[X,Y] R_y^T), into both triangles
+          for (int m = 0; m < BS; ++m) {
+            const double tv = T[m * LD + col];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(Rx[(row + u * RS) * LD + m], tv, acc[u]);
+          }
+          const int gk = gys[grp][col];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int gi = gxs[grp][row + u * RS];
+            G[gi * LG + gk] = acc[u];
+            G[gk * LG + gi] = acc[u];
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    const int c = cnt_l;
+    if (first_rot < 0) first_rot = c;
+    __syncthreads();
+    if (c == 0) break;
+  }
+  for (int e = tid; e < n * n; e += JL_THREADS) {
+    const int i = e / n, k = e - i * n;
+    Gg[e] = G[i * LG + k];
+  }
+  if (tid == 0 && info) {
+    info[0] = sweep;
+    info[1] = first_rot < 0 ? 0 : first_rot;
+  }
+}
+
 __global__ void k_jc_init(double* __restrict__ U, int n, JcCtl* __restrict__ ctl, const int* __restrict__ skip) {
   if (skip && *skip) return;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)n * n;
@@ -592,6 +805,29 @@ hipError_t jacobi_eig_blocked_f64(double* G, double* U, int n, int max_sweeps, d
   hipLaunchKernelGGL(k_jc_init, dim3(64), dim3(256), 0, s, U, n, ctl, skip);
   hipLaunchKernelGGL(k_jacobi_coop<BS>, dim3(grid), dim3(BK * BK), 0, s, G, U, n, nb, max_sweeps, tol, ctl, Rbuf,
                      Sbuf, Galt, info, skip);
+  return hipGetLastError();
+}
+
+size_t jacobi_lds_bytes(int n) {
+  int nb = (n + JC_BK - 1) / JC_BK;
+  nb += nb & 1;
+  const size_t np = (size_t)nb * JC_BK;
+  return (np * (np + 1) + (size_t)(nb / 2) * 3 * JC_BS * JC_LD) * sizeof(double);
+}
+
+hipError_t jacobi_eig_lds_f64(double* G, double* U, int n, int max_sweeps, double tol, int* info, hipStream_t s,
+                              const int* skip) {
+  if (n <= JC_BS || n > JC_LDS_MAXN) return hipErrorInvalidValue;
+  static int lds_ok = -1;
+  const size_t bytes = jacobi_lds_bytes(JC_LDS_MAXN);
+  if (lds_ok < 0) {
+    lds_ok = hipFuncSetAttribute((const void*)k_jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes) == hipSuccess ? 1 : 0;
+    (void)hipGetLastError();
+  }
+  if (!lds_ok) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(k_jacobi_lds, dim3(1, grp().count), dim3(JL_THREADS), jacobi_lds_bytes(n), s, G, U, n,
+                     std::min(std::max(max_sweeps, 1), 256), tol, info, skip, grp().stride);
   return hipGetLastError();
 }
 

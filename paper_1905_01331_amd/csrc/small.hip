@@ -1,6 +1,7 @@
 // Element-wise kernels, deterministic reductions, the counter-based Gaussian
 // generator and the float64 Jacobi eigensolver used by the polar update.
 #include "common.h"
+#include "jacobi.h"
 #include <math.h>
 
 namespace ttn {
@@ -425,6 +426,9 @@ hipError_t jacobi_eig_f64(double* G, double* V, int n, int max_sweeps, double to
                           hipStream_t s, const int* skip) {
   if (n > JAC_MAXN) return hipErrorInvalidValue;
   if (n > 64 && scratch) return jacobi_eig_blocked_f64(G, V, n, max_sweeps, tol, info, scratch, s, skip);
+  // orders that fill their blocks of 16 (padding to an even block count
+  // below 8): the blocked method inside one work-group
+  if (jacobi_lds_preferred(n)) return jacobi_eig_lds_f64(G, V, n, max_sweeps, tol, info, s, skip);
   // the matrices go to LDS when they fit there with a round's rotations
   static int lds_limit = -1;
   if (lds_limit < 0) {
