@@ -40,6 +40,10 @@ CASES = [
     ("tfim_L64_chi24", I.tfim_chain(0.9), 64, 24),
     ("torus8x3_chi20", I.torus_tfim_column(3, 3.0), 8, 20),
     ("tfim_L128_chi70", I.tfim_chain(1.1), 128, 70),
+    # orders the one-work-group blocked Jacobi takes, padded to whole
+    # 16-index blocks (60 -> 64, 90 -> 96)
+    ("xxx_L64_chi60", I.xxx_chain(), 64, 60),
+    ("tfim_L32_chi90", I.tfim_chain(1.2), 32, 90),
     # environments with more than 128 rows take the blocked Jacobi path
     ("tfim_L32_chi160", I.tfim_chain(0.8), 32, 160),
     ("xxx_L32_chi256", I.xxx_chain(), 32, 256),
