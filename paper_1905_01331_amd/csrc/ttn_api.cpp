@@ -1921,8 +1921,11 @@ ttn_status top_graph_launch(Ctx& c, int plan) {
 
 // The top update after a replayed layer part.  use_graph == 2: every restart
 // of the budget in the graph, no host read.  Otherwise the graph holds the
-// restarts the slowest member needed so far, one host read afterwards
-// finishes any member that needs more (eagerly) and raises the plan.
+// restarts the slowest member needed in the previous update, one host read
+// afterwards finishes any member that needs more (eagerly), and the plan
+// follows what this update needed (a plan held at the largest need so far,
+// that of the first solves from random isometries, kept launching restarts
+// that return at once in every later sweep).
 ttn_status top_after_graph(Ctx& c, int use_graph, ttn_status* warn) {
   int budget = 1;
   for (auto& M : c.m) budget = std::max(budget, M.restarts);
@@ -1933,7 +1936,7 @@ ttn_status top_after_graph(Ctx& c, int use_graph, ttn_status* warn) {
   int most = 0;
   bool all = true;
   if ((st = top_complete(c, c.s, plan, &most, &all))) return st;
-  c.top_plan = std::max(c.top_plan, most);
+  c.top_plan = std::max(1, most);
   if (!all) *warn = TTN_WNOCONV;
   return TTN_OK;
 }
