@@ -954,11 +954,12 @@ ttn_status stage_env(Member& M, int tau, hipStream_t s) {
 // The eigenproblem of the polar update's Gram matrix (M.G -> eigenvalues on
 // its diagonal, eigenvectors as the rows of M.V).  The solver depends on the
 // order a alone, so a member of a batch does the arithmetic it does alone:
-// a <= POLAR_ONE_WG_MAX the one-work-group solver (G and its eigenvectors
-// both in LDS; all members of a launch group in one launch), larger a the
-// blocked solver with its persistent grid.  In a batch a
-// blocked solve of a <= 128 (at most 26 work-groups) runs on the member's own
-// stream, one launch per member of its launch group; larger ones (up to 128
+// a <= POLAR_ONE_WG_MAX one work-group per matrix (the cyclic solver with G
+// and its eigenvectors in LDS, or for the orders that fill whole blocks the
+// blocked method with G in LDS; all members of a launch group in one
+// launch), larger a the blocked solver with its persistent grid.  In a batch
+// a blocked grid solve of a <= 128 (at most 30 work-groups) runs on the
+// member's own stream, one launch per member of its launch group; larger ones (up to 128
 // work-groups) go one at a time through the batch's shared stream, so the
 // persistent grids that can run at once stay well below what the compute
 // units hold.

@@ -56,9 +56,10 @@ constexpr int SCAL_LAM = 0, SCAL_E = 1, SCAL_RES = 2, SCAL_ORTHO = 3, SCAL_ORTHO
 constexpr int LZ_DONE = 8;  // lzint slot of the top solver's per-member convergence flag
 constexpr int POLAR_REFRESH = 2;
 constexpr int POLAR_JACOBI_SWEEPS = 60;  // sweep limit of a polar Jacobi solve
-// largest Gram order solved by the one-work-group Jacobi (G and U, 2 * 96^2
-// doubles, and a round's rotation tables fit the 160 KB of LDS); above it the
-// blocked solver
+// largest Gram order solved in one work-group (the cyclic solver's G and U,
+// 2 * 96^2 doubles, and a round's rotation tables fit the 160 KB of LDS, as
+// do the blocked one-work-group solver's padded G and sub-problems); above it
+// the blocked grid solver
 constexpr int POLAR_ONE_WG_MAX = 96;
 constexpr int POLAR_THIRD_IF = 3;
 constexpr double POLAR_REG = 1e-30;   // tie-breaker toward the current isometry in null directions
